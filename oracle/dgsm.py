@@ -1,0 +1,305 @@
+"""FP64 oracle: Deep Gaussian Shadow Map build and query.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Every quantity is
+float64; inputs given as float32 are widened exactly.  No culling, no
+tiling, no reordering: the atlas is the plain definition of Sec. 3.2,
+
+    tau(d, t) = sum_i beta_i * int_0^t exp(-1/2 (a_i s^2 + 2 b_i s + c_i)) ds   (Eq. 2)
+    T(d, t)   = exp(-tau(d, t))                                              (Eq. 4)
+
+evaluated with the erf primitive of Eq. 3 at every texel centre of the
+octahedral atlas and every radial shell.  The only shortcut is an exact skip
+of pairs whose whole-ray contribution is below 1e-15 (|erf difference| <= 2),
+which bounds the total error by N * 1e-15.
+
+Conventions (readings of the paper where it is silent):
+* texel (row i, column j) has u = -1 + (2j+1)/W, v = -1 + (2i+1)/H  (Sec. 3.2,
+  "pixel centers"); u runs along columns, v along rows.
+* sgn(0) = +1 in the octahedral fold.
+* shells: uniform centres t_k = (k + 1/2) t_max / K (Sec. 3.2) or geometric
+  radii r_k = r0 (r1/r0)^(k/(K-1)) (the workload configurations).
+* query: bilinear in texel space with the octahedral mirror wrap across the
+  outer edges, times linear in the fractional shell index, applied to T.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy import special
+
+SKIP = 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Gaussian parameters (Sec. 3.2 first paragraph, Eq. 5)
+# ---------------------------------------------------------------------------
+
+def quaternion_to_matrix(q):
+    """Rotation matrices [..., 3, 3] of quaternions (w, x, y, z), normalised first."""
+    q = np.asarray(q, dtype=np.float64)
+    q = q / np.linalg.norm(q, axis=-1, keepdims=True)
+    w, x, y, z = q[..., 0], q[..., 1], q[..., 2], q[..., 3]
+    R = np.empty(q.shape[:-1] + (3, 3))
+    R[..., 0, 0] = 1 - 2 * (y * y + z * z)
+    R[..., 0, 1] = 2 * (x * y - w * z)
+    R[..., 0, 2] = 2 * (x * z + w * y)
+    R[..., 1, 0] = 2 * (x * y + w * z)
+    R[..., 1, 1] = 1 - 2 * (x * x + z * z)
+    R[..., 1, 2] = 2 * (y * z - w * x)
+    R[..., 2, 0] = 2 * (x * z - w * y)
+    R[..., 2, 1] = 2 * (y * z + w * x)
+    R[..., 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def precision_matrix(scale, rot):
+    """A_i = Sigma_i^-1 = R diag(s^-2) R^T for Sigma_i = R diag(s^2) R^T (Sec. 3.2)."""
+    R = quaternion_to_matrix(rot)
+    s = np.asarray(scale, dtype=np.float64)
+    return np.einsum("nij,nj,nkj->nik", R, 1.0 / (s * s), R)
+
+
+def absorption_amplitude(opacity, A, kappa=1.0):
+    """Eq. 5: beta_i = kappa tau*_i sqrt(tr(A_i)/3) / sqrt(2 pi), tau* = -ln(1 - alpha)."""
+    alpha = np.asarray(opacity, dtype=np.float64)
+    tau_star = -np.log1p(-alpha)
+    tr = np.trace(A, axis1=-2, axis2=-1)
+    return kappa * tau_star * np.sqrt(tr / 3.0) / np.sqrt(2.0 * np.pi)
+
+
+def absorption(x, mean, A, beta):
+    """Eq. 1: sigma(x) = sum_i beta_i exp(-1/2 (x - mu_i)^T A_i (x - mu_i)), x [..., 3]."""
+    x = np.asarray(x, dtype=np.float64)
+    diff = x[..., None, :] - np.asarray(mean, dtype=np.float64)
+    q = np.einsum("...ni,nij,...nj->...n", diff, A, diff)
+    return np.sum(beta * np.exp(-0.5 * q), axis=-1)
+
+
+# ---------------------------------------------------------------------------
+# Closed-form line integral (Eqs. 2-3)
+# ---------------------------------------------------------------------------
+
+def ray_quadratic(d, o_L, mean, A):
+    """Eq. 2 coefficients for directions d [P,3] and Gaussians [N]: a, b [P,N], c [N].
+
+    a = d^T A d, b = d^T A (o_L - mu), c = (o_L - mu)^T A (o_L - mu).
+    """
+    d = np.asarray(d, dtype=np.float64)
+    m = np.asarray(o_L, dtype=np.float64)[None, :] - np.asarray(mean, dtype=np.float64)
+    dd = (d[:, :, None] * d[:, None, :]).reshape(d.shape[0], 9)
+    a = dd @ A.reshape(-1, 9).T
+    Am = np.einsum("nij,nj->ni", A, m)
+    b = d @ Am.T
+    c = np.einsum("ni,ni->n", m, Am)
+    return a, b, c
+
+
+def erf_difference(x1, x0):
+    """erf(x1) - erf(x0) for x1 >= x0, switching to erfc where both tails agree."""
+    x1, x0 = np.broadcast_arrays(np.atleast_1d(np.asarray(x1, dtype=np.float64)),
+                                 np.atleast_1d(np.asarray(x0, dtype=np.float64)))
+    out = np.array(special.erf(x1) - special.erf(x0))
+    pos = x0 > 0
+    out[pos] = special.erfc(x0[pos]) - special.erfc(x1[pos])
+    neg = x1 < 0
+    out[neg] = special.erfc(-x1[neg]) - special.erfc(-x0[neg])
+    return out
+
+
+def line_integral(a, b, c, t):
+    """Eq. 3: int_0^t exp(-1/2 (a s^2 + 2 b s + c)) ds, broadcasting a, b, c against t."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    pref = np.sqrt(np.pi / (2 * a)) * np.exp(-0.5 * (c - b * b / a))
+    ra = np.sqrt(a / 2)
+    return pref * erf_difference(ra * (t + b / a), ra * (b / a))
+
+
+# ---------------------------------------------------------------------------
+# Octahedral parameterisation and shells (Sec. 3.2, "Directional parameterization")
+# ---------------------------------------------------------------------------
+
+def _sgn(x):
+    return np.where(x >= 0, 1.0, -1.0)
+
+
+def octahedral_encode(d):
+    """psi: unit vectors [..., 3] -> (u, v) in [-1, 1]^2, with sgn(0) = +1."""
+    d = np.asarray(d, dtype=np.float64)
+    q = d / np.sum(np.abs(d), axis=-1, keepdims=True)
+    qx, qy, qz = q[..., 0], q[..., 1], q[..., 2]
+    u = np.where(qz >= 0, qx, _sgn(qx) * (1 - np.abs(qy)))
+    v = np.where(qz >= 0, qy, _sgn(qy) * (1 - np.abs(qx)))
+    return u, v
+
+
+def octahedral_decode(u, v):
+    """psi^-1: undo the fold, z = 1 - |u| - |v|, normalise."""
+    u = np.asarray(u, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    z = 1 - np.abs(u) - np.abs(v)
+    x = np.where(z < 0, _sgn(u) * (1 - np.abs(v)), u)
+    y = np.where(z < 0, _sgn(v) * (1 - np.abs(u)), v)
+    d = np.stack([x, y, z], axis=-1)
+    return d / np.linalg.norm(d, axis=-1, keepdims=True)
+
+
+def texel_uv(H, W):
+    """(u, v) of every texel centre, arrays [H, W]."""
+    j = np.arange(W, dtype=np.float64)
+    i = np.arange(H, dtype=np.float64)
+    u = -1 + (2 * j + 1) / W
+    v = -1 + (2 * i + 1) / H
+    return np.broadcast_to(u[None, :], (H, W)), np.broadcast_to(v[:, None], (H, W))
+
+
+def texel_directions(H, W):
+    """Unit direction of every texel centre, [H, W, 3]."""
+    u, v = texel_uv(H, W)
+    return octahedral_decode(u, v)
+
+
+def shell_radii(K, spacing="geometric", r0=0.05, r1=8.0):
+    """Radial sample distances t_k [K]."""
+    k = np.arange(K, dtype=np.float64)
+    if spacing == "geometric":
+        return r0 * (r1 / r0) ** (k / (K - 1))
+    if spacing == "uniform":
+        return (k + 0.5) * r1 / K
+    raise ValueError(spacing)
+
+
+# ---------------------------------------------------------------------------
+# Build
+# ---------------------------------------------------------------------------
+
+def gaussian_terms(g, kappa=1.0):
+    """(mean, A, beta) in float64 for a Gaussian set with .mean/.scale/.rot/.opacity."""
+    A = precision_matrix(g.scale, g.rot)
+    beta = absorption_amplitude(g.opacity, A, kappa)
+    return np.asarray(g.mean, dtype=np.float64), A, beta
+
+
+def optical_depth(dirs, t, o_L, mean, A, beta, chunk=2048):
+    """tau(d_p, t_k) [P, K] for unit directions dirs [P, 3] (Eqs. 2-3)."""
+    dirs = np.asarray(dirs, dtype=np.float64).reshape(-1, 3)
+    t = np.asarray(t, dtype=np.float64)
+    P, K = dirs.shape[0], t.shape[0]
+    tau = np.zeros((P, K))
+    for s in range(0, mean.shape[0], chunk):
+        e = slice(s, s + chunk)
+        a, b, c = ray_quadratic(dirs, o_L, mean[e], A[e])
+        pref = beta[e][None, :] * np.sqrt(np.pi / (2 * a)) * np.exp(-0.5 * (c[None, :] - b * b / a))
+        p_idx, n_idx = np.nonzero(2 * pref >= SKIP)
+        if p_idx.size == 0:
+            continue
+        aa, bb = a[p_idx, n_idx], b[p_idx, n_idx]
+        ra = np.sqrt(aa / 2)[:, None]
+        boa = (bb / aa)[:, None]
+        vals = pref[p_idx, n_idx][:, None] * erf_difference(ra * (t[None, :] + boa), ra * boa)
+        np.add.at(tau, p_idx, vals)
+    return tau
+
+
+def build(light, gaussians, H, W, K, spacing="geometric", r0=0.05, r1=8.0, kappa=1.0):
+    """Transmittance atlas T[K, H, W] for one point light (Eqs. 2-4, Sec. 3.2)."""
+    mean, A, beta = gaussian_terms(gaussians, kappa)
+    dirs = texel_directions(H, W).reshape(-1, 3)
+    t = shell_radii(K, spacing, r0, r1)
+    tau = optical_depth(dirs, t, light, mean, A, beta)
+    return np.exp(-tau).T.reshape(K, H, W)
+
+
+def build_texels(light, gaussians, rows, cols, K, spacing="geometric", r0=0.05, r1=8.0,
+                 kappa=1.0, H=None, W=None):
+    """T[len(rows), K] at the given texels of an H x W atlas (sampled parity)."""
+    mean, A, beta = gaussian_terms(gaussians, kappa)
+    u = -1 + (2 * np.asarray(cols, dtype=np.float64) + 1) / W
+    v = -1 + (2 * np.asarray(rows, dtype=np.float64) + 1) / H
+    dirs = octahedral_decode(u, v)
+    t = shell_radii(K, spacing, r0, r1)
+    return np.exp(-optical_depth(dirs, t, light, mean, A, beta))
+
+
+# ---------------------------------------------------------------------------
+# Query (Sec. 3.3)
+# ---------------------------------------------------------------------------
+
+def wrap_texel(i, j, H, W):
+    """Octahedral mirror wrap of integer texel indices (possibly one step outside).
+
+    Across the left/right edge (u = -+1) the map identifies (u, v) with (u, -v);
+    across the top/bottom edge (v = -+1) it identifies (u, v) with (-u, v).
+    """
+    i = np.asarray(i).copy()
+    j = np.asarray(j).copy()
+    out = j < 0
+    j[out], i[out] = 0, H - 1 - i[out]
+    out = j >= W
+    j[out], i[out] = W - 1, H - 1 - i[out]
+    out = i < 0
+    i[out], j[out] = 0, W - 1 - j[out]
+    out = i >= H
+    i[out], j[out] = H - 1, W - 1 - j[out]
+    return i, j
+
+
+def query_coords(light, points, H, W, K, spacing="geometric", r0=0.05, r1=8.0):
+    """Continuous texel coordinates (i_f, j_f) and fractional shell k_f of points."""
+    diff = np.asarray(points, dtype=np.float64) - np.asarray(light, dtype=np.float64)
+    r = np.linalg.norm(diff, axis=-1)
+    diff = np.where(r[:, None] > 0, diff, np.array([0.0, 0.0, 1.0]))
+    u, v = octahedral_encode(diff)
+    jf = (u + 1) * W / 2 - 0.5
+    i_f = (v + 1) * H / 2 - 0.5
+    if spacing == "geometric":
+        with np.errstate(divide="ignore"):
+            kf = (K - 1) * np.log(np.maximum(r, 1e-300) / r0) / np.log(r1 / r0)
+    else:
+        kf = r * K / r1 - 0.5
+    kf = np.clip(kf, 0.0, K - 1)
+    return i_f, jf, kf
+
+
+def _corner_weights(i_f, jf, kf, K):
+    i0 = np.floor(i_f).astype(np.int64)
+    j0 = np.floor(jf).astype(np.int64)
+    k0 = np.minimum(np.floor(kf).astype(np.int64), K - 2)
+    return i0, j0, k0, i_f - i0, jf - j0, kf - k0
+
+
+def query(table, light, points, spacing="geometric", r0=0.05, r1=8.0):
+    """Trilinear lookup of T[K, H, W] at world points [P, 3] (Sec. 3.3)."""
+    K, H, W = table.shape
+    i_f, jf, kf = query_coords(light, points, H, W, K, spacing, r0, r1)
+    i0, j0, k0, fi, fj, fk = _corner_weights(i_f, jf, kf, K)
+    out = np.zeros(i_f.shape)
+    for di, wi in ((0, 1 - fi), (1, fi)):
+        for dj, wj in ((0, 1 - fj), (1, fj)):
+            ii, jj = wrap_texel(i0 + di, j0 + dj, H, W)
+            for dk, wk in ((0, 1 - fk), (1, fk)):
+                out += wi * wj * wk * table[k0 + dk, ii, jj]
+    return out
+
+
+def query_exact(light, gaussians, points, H, W, K, spacing="geometric", r0=0.05, r1=8.0,
+                kappa=1.0):
+    """Query at points without a stored atlas: the 8 texel values each point
+    interpolates are computed from Eqs. 2-4 directly (for full-size sampling)."""
+    mean, A, beta = gaussian_terms(gaussians, kappa)
+    i_f, jf, kf = query_coords(light, points, H, W, K, spacing, r0, r1)
+    i0, j0, k0, fi, fj, fk = _corner_weights(i_f, jf, kf, K)
+    t_all = shell_radii(K, spacing, r0, r1)
+    out = np.zeros(i_f.shape)
+    for di, wi in ((0, 1 - fi), (1, fi)):
+        for dj, wj in ((0, 1 - fj), (1, fj)):
+            ii, jj = wrap_texel(i0 + di, j0 + dj, H, W)
+            u = -1 + (2 * jj + 1) / W
+            v = -1 + (2 * ii + 1) / H
+            dirs = octahedral_decode(u, v)
+            tau = optical_depth(dirs, t_all, light, mean, A, beta)
+            T = np.exp(-tau)
+            rows = np.arange(len(ii))
+            for dk, wk in ((0, 1 - fk), (1, fk)):
+                out += wi * wj * wk * T[rows, k0 + dk]
+    return out

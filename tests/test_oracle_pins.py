@@ -1,0 +1,372 @@
+"""Pins for the FP64 oracle: checks against what the paper and mathematics fix.
+
+None of these re-types an oracle formula.  They use numerical quadrature of
+the absorption field (Eq. 1), closed forms derived by hand, exact symmetries
+and invariants of Eqs. 2-5, library routines for special cases (scipy's
+rotations, complex spherical harmonics, adaptive quadrature) and brute force
+on tiny inputs.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+from scipy.spatial.transform import Rotation
+
+from oracle import dgsm as od
+from oracle import sh as osh
+import synth
+
+
+def tiny_scene(seed=0, n=3, lo=0.6, hi=1.6, median=0.15):
+    rng = np.random.default_rng(seed)
+    return synth.random_gaussians(rng, rng.uniform(lo, hi, (n, 3)), median)
+
+
+# ---------------------------------------------------------------------------
+# Gaussian parameters
+# ---------------------------------------------------------------------------
+
+def test_quaternion_matches_scipy_rotation():
+    rng = np.random.default_rng(1)
+    q = rng.standard_normal((50, 4))
+    R = od.quaternion_to_matrix(q)
+    ref = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()  # scipy is scalar-last
+    assert np.max(np.abs(R - ref)) < 1e-14
+
+
+def test_precision_eigenvalues_are_inverse_variances():
+    g = tiny_scene(2, n=20)
+    A = od.precision_matrix(g.scale, g.rot)
+    for k in range(g.n):
+        ev = np.linalg.eigvalsh(A[k])
+        ref = np.sort(1.0 / g.scale[k].astype(np.float64) ** 2)
+        assert np.allclose(ev, ref, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Eq. 3 against quadrature of Eq. 2 / Eq. 1
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(6))
+def test_closed_form_matches_quadrature_of_quadratic(seed):
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.5, 50.0)
+    tc = rng.uniform(-2, 3)                 # centre of the Gaussian along the ray
+    b = -a * tc
+    c = b * b / a + rng.uniform(0, 4)       # c - b^2/a >= 0 for a PSD form
+    for t in (0.1, 0.7, 2.5, 6.0):
+        got = od.line_integral(a, b, c, t)
+        ref, _ = integrate.quad(lambda s: math.exp(-0.5 * (a * s * s + 2 * b * s + c)), 0.0, t,
+                                epsabs=0, epsrel=1e-13, limit=200, points=[min(max(tc, 0), t)])
+        assert abs(got - ref) <= 1e-10 * max(abs(ref), 1e-300) + 1e-300
+
+
+def test_optical_depth_matches_quadrature_of_absorption_field():
+    """Chain Eq. 1 -> Eq. 2 -> Eq. 3 for anisotropic Gaussians on random rays."""
+    g = tiny_scene(3, n=6)
+    mean, A, beta = od.gaussian_terms(g)
+    o_L = np.array([0.1, -0.2, 0.05])
+    rng = np.random.default_rng(4)
+    # aim the rays at the Gaussians so that the integrals are not negligible
+    targets = mean[rng.integers(0, g.n, 5)] + 0.05 * rng.standard_normal((5, 3))
+    dirs = targets - o_L
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    t = np.array([0.3, 1.0, 1.7, 2.4, 5.0])
+    tau = od.optical_depth(dirs, t, o_L, mean, A, beta)
+    for p in range(dirs.shape[0]):
+        for k, tk in enumerate(t):
+            ref, _ = integrate.quad(lambda s: od.absorption(o_L + s * dirs[p], mean, A, beta), 0.0, tk,
+                                    epsabs=1e-14, epsrel=1e-12, limit=400)
+            assert abs(tau[p, k] - ref) <= 1e-9 * max(ref, 1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Eq. 5 calibration: isotropic, on-axis closed form
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha,s,D,kappa", [(0.7, 0.05, 2.0, 1.0), (0.3, 0.2, 1.0, 1.0),
+                                             (0.95, 0.02, 3.0, 0.5), (0.5, 0.1, 0.15, 2.0)])
+def test_isotropic_on_axis_closed_form(alpha, s, D, kappa):
+    # tau(t) = kappa tau*/2 [erf((t - D)/(s sqrt2)) + erf(D/(s sqrt2))], derived by hand
+    g = synth.Gaussians(np.array([[0.0, 0.0, D]], np.float32), np.full((1, 3), s, np.float32),
+                        np.array([[1, 0, 0, 0]], np.float32), np.array([alpha], np.float32))
+    mean, A, beta = od.gaussian_terms(g, kappa)
+    a32 = float(np.float32(alpha))
+    s = float(np.float32(s))
+    D = float(np.float32(D))
+    tau_star = -math.log1p(-a32)
+    t = np.array([0.5 * D, D, D + s, D + 10 * s, 50.0])
+    tau = od.optical_depth(np.array([[0.0, 0.0, 1.0]]), t, np.zeros(3), mean, A, beta)[0]
+    ref = kappa * tau_star / 2 * (special.erf((t - D) / (s * math.sqrt(2))) + special.erf(D / (s * math.sqrt(2))))
+    assert np.allclose(tau, ref, rtol=1e-12, atol=1e-15)
+    if D > 8 * s:   # far field: T(inf) = (1 - alpha)^kappa, the 3DGS opacity
+        assert abs(math.exp(-tau[-1]) - (1 - a32) ** kappa) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Whole-build invariants and special cases
+# ---------------------------------------------------------------------------
+
+ATL = dict(H=8, W=8, K=6, spacing="geometric", r0=0.05, r1=8.0)
+
+
+def test_empty_and_transparent_scene_is_fully_lit():
+    T = od.build(np.zeros(3), synth.Gaussians.empty(), **ATL)
+    assert T.shape == (6, 8, 8) and np.all(T == 1.0)
+    g = tiny_scene(5, n=4)
+    g.opacity[:] = 0.0
+    assert np.all(od.build(np.zeros(3), g, **ATL) == 1.0)
+
+
+def test_transmittance_monotone_in_radius():
+    g = tiny_scene(6, n=30, lo=-2, hi=2, median=0.2)
+    T = od.build(np.array([0.05, 0.02, -0.03]), g, 16, 16, 12)
+    assert np.all(np.diff(T, axis=0) <= 0)
+    assert np.all((T > 0) & (T <= 1))
+
+
+def test_additivity_over_gaussian_sets():
+    g = tiny_scene(7, n=12, lo=-2, hi=2, median=0.2)
+    light = np.array([0.1, 0.0, 0.0])
+    T = od.build(light, g, **ATL)
+    T1 = od.build(light, g.subset(np.arange(0, 5)), **ATL)
+    T2 = od.build(light, g.subset(np.arange(5, 12)), **ATL)
+    assert np.allclose(T, T1 * T2, rtol=1e-12, atol=1e-15)
+
+
+def test_kappa_power_law():
+    g = tiny_scene(8, n=10, lo=-2, hi=2, median=0.2)
+    light = np.array([0.0, 0.1, 0.0])
+    T1 = od.build(light, g, **ATL)
+    T3 = od.build(light, g, **ATL, kappa=2.5)
+    assert np.allclose(T3, T1 ** 2.5, rtol=1e-11, atol=1e-15)
+
+
+def test_length_scale_invariance():
+    g = tiny_scene(9, n=10, lo=-2, hi=2, median=0.2)
+    light = np.array([0.05, 0.0, 0.1])
+    lam = 4.0   # a power of two keeps the float32 inputs exact
+    g2 = synth.Gaussians(g.mean * lam, g.scale * lam, g.rot, g.opacity)
+    T1 = od.build(light, g, 8, 8, 6, r0=0.05, r1=8.0)
+    T2 = od.build(light * lam, g2, 8, 8, 6, r0=0.05 * lam, r1=8.0 * lam)
+    assert np.allclose(T1, T2, rtol=1e-12, atol=1e-14)
+
+
+def test_brute_force_quadrature_on_tiny_atlas():
+    g = tiny_scene(10, n=3, lo=-1.2, hi=1.2, median=0.25)
+    light = np.zeros(3)
+    H = W = 4
+    K = 4
+    T = od.build(light, g, H, W, K, r0=0.3, r1=3.0)
+    mean, A, beta = od.gaussian_terms(g)
+    t = 0.3 * (10.0 ** (np.arange(K) / (K - 1)))
+    for i in range(H):
+        for j in range(W):
+            u = -1 + (2 * j + 1) / W
+            v = -1 + (2 * i + 1) / H
+            z = 1 - abs(u) - abs(v)
+            x, y = (u, v) if z >= 0 else (math.copysign(1 - abs(v), u), math.copysign(1 - abs(u), v))
+            d = np.array([x, y, z]) / math.sqrt(x * x + y * y + z * z)
+            for k in range(K):
+                tau, _ = integrate.quad(lambda s: od.absorption(s * d, mean, A, beta), 0, t[k],
+                                        epsabs=1e-13, epsrel=1e-11, limit=400)
+                assert abs(T[k, i, j] - math.exp(-tau)) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Octahedral map: round trip and exact symmetries of the atlas
+# ---------------------------------------------------------------------------
+
+def test_octahedral_round_trip_at_texel_centres():
+    for H, W in ((8, 8), (6, 10), (32, 32)):
+        u, v = od.texel_uv(H, W)
+        uu, vv = od.octahedral_encode(od.octahedral_decode(u, v))
+        assert np.max(np.abs(uu - u)) < 1e-14 and np.max(np.abs(vv - v)) < 1e-14
+
+
+def test_octahedral_encode_is_onto_the_square_and_folds_lower_hemisphere():
+    rng = np.random.default_rng(11)
+    d = rng.standard_normal((2000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    u, v = od.octahedral_encode(d)
+    assert np.all(np.abs(u) <= 1) and np.all(np.abs(v) <= 1)
+    up = d[:, 2] >= 0
+    assert np.all(np.abs(u[up]) + np.abs(v[up]) <= 1 + 1e-15)
+    assert np.all(np.abs(u[~up]) + np.abs(v[~up]) >= 1 - 1e-15)
+
+
+def _rotated_scene(g, rot: Rotation):
+    mean = rot.apply(g.mean.astype(np.float64)).astype(np.float32)
+    q = (rot * Rotation.from_quat(g.rot[:, [1, 2, 3, 0]].astype(np.float64))).as_quat()
+    return synth.Gaussians(mean, g.scale, q[:, [3, 0, 1, 2]].astype(np.float32), g.opacity)
+
+
+def test_atlas_symmetry_mirror_x_is_column_flip():
+    g = tiny_scene(12, n=15, lo=-2, hi=2, median=0.2)
+    gm = synth.Gaussians(g.mean * np.array([-1, 1, 1], np.float32), g.scale,
+                         g.rot * np.array([1, 1, -1, -1], np.float32), g.opacity)  # reflect x
+    T = od.build(np.zeros(3), g, 8, 8, 5)
+    Tm = od.build(np.zeros(3), gm, 8, 8, 5)
+    assert np.allclose(Tm, T[:, :, ::-1], rtol=1e-9, atol=1e-12)
+
+
+def test_atlas_symmetry_quarter_turn_about_z():
+    g = tiny_scene(13, n=15, lo=-2, hi=2, median=0.2)
+    # exact float32 quarter turn: (x, y, z) -> (-y, x, z)
+    rot = Rotation.from_euler("z", 90, degrees=True)
+    gr = _rotated_scene(g, rot)
+    gr.mean[:] = np.stack([-g.mean[:, 1], g.mean[:, 0], g.mean[:, 2]], 1)
+    T = od.build(np.zeros(3), g, 8, 8, 5)
+    Tr = od.build(np.zeros(3), gr, 8, 8, 5)
+    # (u, v) -> (-v, u): texel (i, j) -> (j, W-1-i)
+    W = 8
+    ref = np.empty_like(T)
+    for i in range(8):
+        for j in range(8):
+            ref[:, j, W - 1 - i] = T[:, i, j]
+    assert np.allclose(Tr, ref, rtol=1e-6, atol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# Query
+# ---------------------------------------------------------------------------
+
+def _random_table(K, H, W, seed=14):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0, 1, (K, H, W))
+
+
+def test_query_reproduces_texel_values_at_centres_and_shells():
+    K, H, W = 5, 8, 8
+    table = _random_table(K, H, W)
+    t = od.shell_radii(K, "geometric", 0.05, 8.0)
+    d = od.texel_directions(H, W)
+    light = np.array([0.3, -0.2, 0.1])
+    for k in range(K):
+        pts = light + t[k] * d.reshape(-1, 3)
+        got = od.query(table, light, pts)
+        assert np.allclose(got, table[k].reshape(-1), atol=1e-10)
+
+
+def test_query_partition_of_unity_and_bounds():
+    K, H, W = 6, 8, 8
+    rng = np.random.default_rng(15)
+    pts = rng.uniform(-6, 6, (4000, 3))
+    assert np.allclose(od.query(np.full((K, H, W), 0.37), np.zeros(3), pts), 0.37, atol=1e-14)
+    table = _random_table(K, H, W)
+    got = od.query(table, np.zeros(3), pts)
+    assert np.all(got >= table.min() - 1e-12) and np.all(got <= table.max() + 1e-12)
+
+
+def test_query_is_continuous_across_the_octahedral_seams():
+    K, H, W = 4, 8, 8
+    table = _random_table(K, H, W, seed=16)
+    rng = np.random.default_rng(17)
+    for _ in range(200):
+        # a direction on the lower-hemisphere seam y = 0 (the u = +-1 edge) or x = 0
+        a = rng.uniform(0.05, 0.95)
+        sx = rng.choice([-1, 1])
+        if rng.uniform() < 0.5:
+            base = np.array([sx * a, 0.0, -(1 - a)])
+            eps = np.array([0.0, 1e-9, 0.0])
+        else:
+            base = np.array([0.0, sx * a, -(1 - a)])
+            eps = np.array([1e-9, 0.0, 0.0])
+        r = rng.uniform(0.1, 7.0)
+        p1 = r * (base + eps) / np.linalg.norm(base + eps)
+        p2 = r * (base - eps) / np.linalg.norm(base - eps)
+        v1, v2 = od.query(table, np.zeros(3), np.stack([p1, p2]))
+        assert abs(v1 - v2) < 1e-6
+
+
+def test_wrap_maps_corners_to_the_opposite_corner():
+    i, j = od.wrap_texel(np.array([-1, 8, -1, 8]), np.array([-1, 8, 8, -1]), 8, 8)
+    assert list(zip(i, j)) == [(7, 7), (0, 0), (7, 0), (0, 7)]
+
+
+# ---------------------------------------------------------------------------
+# SH basis and radiance transfer
+# ---------------------------------------------------------------------------
+
+def test_real_sh_matches_scipy_complex_harmonics():
+    rng = np.random.default_rng(18)
+    d = rng.standard_normal((300, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    th = np.arccos(np.clip(d[:, 2], -1, 1))
+    ph = np.arctan2(d[:, 1], d[:, 0])
+    B = osh.real_sh(4, d)
+    for l in range(5):
+        for m in range(-l, l + 1):
+            Y = special.sph_harm_y(l, abs(m), th, ph)   # includes the Condon-Shortley phase
+            if m > 0:
+                ref = math.sqrt(2) * (-1) ** m * Y.real
+            elif m < 0:
+                ref = math.sqrt(2) * (-1) ** abs(m) * Y.imag
+            else:
+                ref = Y.real
+            assert np.max(np.abs(B[:, l * l + l + m] - ref)) < 1e-12
+
+
+def test_real_sh_orthonormal_by_quadrature():
+    x, wx = np.polynomial.legendre.leggauss(40)
+    nph = 80
+    ph = (np.arange(nph) + 0.5) * 2 * math.pi / nph
+    X, P = np.meshgrid(x, ph, indexing="ij")
+    st = np.sqrt(1 - X * X)
+    d = np.stack([st * np.cos(P), st * np.sin(P), X], -1).reshape(-1, 3)
+    w = (wx[:, None] * np.full(nph, 2 * math.pi / nph)[None, :]).reshape(-1)
+    B = osh.real_sh(3, d)
+    G = (B * w[:, None]).T @ B
+    assert np.max(np.abs(G - np.eye(16))) < 1e-12
+
+
+def test_transfer_constant_probe_special_case():
+    rng = np.random.default_rng(19)
+    probe = np.zeros((16, 3))
+    probe[0] = [0.9, 1.3, 0.4]
+    n = rng.standard_normal((50, 3))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    eps = 1e-3
+    s = osh.transfer_scale(probe, n, 16, 32, q=1.0, clip_max=10.0, eps=eps)
+    L = probe[0] * osh.C0                     # Y_00 = 1/(2 sqrt(pi))
+    dirs, w = osh.latlong_grid(16, 32)
+    S = np.maximum(0, n @ dirs.T)
+    den = (S * w).sum(1)
+    assert np.allclose(s, L[None, :] * (den / (den + eps))[:, None], rtol=1e-13)
+
+
+def test_transfer_lambertian_limit_matches_irradiance_convolution():
+    """q = 1 and a fine grid: s_c(n) -> E_c(n) / pi with the clamped-cosine SH
+    convolution A_0 = pi, A_1 = 2 pi / 3, A_2 = pi / 4, A_3 = 0."""
+    rng = np.random.default_rng(20)
+    probe = rng.normal(0, 0.3, (16, 3))
+    probe[0] = rng.uniform(2.0, 3.0, 3)          # keep E > 0 so no clip engages
+    n = rng.standard_normal((20, 3))
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    s = osh.transfer_scale(probe, n, 400, 800, q=1.0, clip_max=100.0, eps=0.0)
+    Ahat = np.array([math.pi] + [2 * math.pi / 3] * 3 + [math.pi / 4] * 5 + [0.0] * 7)
+    E = osh.real_sh(3, n) @ (Ahat[:, None] * probe)
+    assert np.max(np.abs(s - E / math.pi)) < 2e-4
+
+
+def test_transfer_glossy_denominator_funk_hecke():
+    # sum_j w_j max(0, <w_j, n>)^q -> 2 pi / (q + 1) (times the grid cell area)
+    for q in (1.0, 4.0, 16.0):
+        dirs, w = osh.latlong_grid(400, 800)
+        cell = (math.pi / 400) * (2 * math.pi / 800)
+        n = np.array([0.3, -0.5, 0.81])
+        n /= np.linalg.norm(n)
+        den = (np.maximum(0, dirs @ n) ** q * w).sum() * cell
+        assert abs(den - 2 * math.pi / (q + 1)) < 2e-4
+
+
+def test_normals_are_smallest_axis_and_face_outward():
+    g = tiny_scene(21, n=40, lo=-1, hi=1)
+    c = osh.alpha_centroid(g.mean, g.opacity)
+    n = osh.normals(g.rot, g.scale, g.mean, c)
+    R = Rotation.from_quat(g.rot[:, [1, 2, 3, 0]].astype(np.float64)).as_matrix()
+    for k in range(g.n):
+        ax = int(np.argmin(g.scale[k]))
+        assert abs(abs(n[k] @ R[k][:, ax]) - 1) < 1e-12
+        assert n[k] @ (g.mean[k] - c) >= 0
