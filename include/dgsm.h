@@ -1,0 +1,173 @@
+/*
+ * dgsm.h - C ABI of the MI355X (gfx950) Deep Gaussian Shadow Map library.
+ *
+ * Method: "Animated 3DGS Avatars in Diverse Scenes with Consistent Lighting
+ * and Shadows" (arXiv 2601.01660), Sec. 3.2 (build), Sec. 3.3 (sampling) and
+ * Sec. 3.5 (SH radiance transfer).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array pointers are DEVICE pointers owned by the caller, unless the
+ *    comment says "host".  Arrays are dense, C order, float32 unless stated.
+ *  - The library performs no device allocation inside dgsm_build, dgsm_query,
+ *    sh_transfer or dgsm_alpha_centroid; scratch memory comes from a caller
+ *    workspace sized by the matching *_workspace_size function.
+ *  - Every call is asynchronous and stream ordered on `stream` (a hipStream_t;
+ *    NULL is the legacy default stream).  Outputs are valid once the stream
+ *    reaches the call.
+ *  - Arguments are validated on the host before anything is enqueued.  A
+ *    non-zero dgsm_status means nothing was enqueued (DGSM_EHIP: a HIP launch
+ *    failed; earlier kernels of the same call may have run).
+ *  - Calls on distinct output and workspace buffers may run concurrently on
+ *    different streams.  The library holds no global mutable state.
+ *
+ * Gaussian records (Sec. 3.2, first paragraph): mean mu, covariance
+ * Sigma = R diag(s^2) R^T with R from a quaternion (w, x, y, z) that the
+ * library normalises, precision A = Sigma^-1, opacity alpha in [0, 1).
+ *
+ * Atlas layout (Sec. 3.2 "Directional parameterization ... and storage"):
+ * T[l][k][i][j], shell-major, light l, shell k, texel row i, column j.  Texel
+ * (i, j) stores T at direction psi^-1(u, v) with u = -1 + (2j+1)/W and
+ * v = -1 + (2i+1)/H (texel centres; sgn(0) = +1 in the octahedral fold) and at
+ * radius t_k:
+ *    uniform   t_k = (k + 1/2) * r1 / K                  (r0 unused)
+ *    geometric t_k = r0 * (r1/r0)^(k/(K-1))
+ */
+#ifndef DGSM_H
+#define DGSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DGSM_OK = 0,
+    DGSM_EINVAL = 1,       /* invalid argument (null pointer, bad size, bad enum) */
+    DGSM_EWORKSPACE = 2,   /* workspace pointer null or smaller than required */
+    DGSM_EHIP = 3,         /* a HIP runtime call or kernel launch failed */
+    DGSM_EUNSUPPORTED = 4  /* valid request this build does not implement */
+} dgsm_status;
+
+typedef enum { DGSM_SHELLS_UNIFORM = 0, DGSM_SHELLS_GEOMETRIC = 1 } dgsm_spacing;
+typedef enum { DGSM_F32 = 0, DGSM_F16 = 1 } dgsm_dtype;
+
+/* Gaussian set, structure of arrays, device memory.  n may be 0. */
+typedef struct {
+    const float* mean;     /* [n][3] metres */
+    const float* scale;    /* [n][3] standard deviations s > 0 in metres */
+    const float* rot;      /* [n][4] quaternion (w, x, y, z), any non-zero norm */
+    const float* opacity;  /* [n]    alpha in [0, 1) */
+    int64_t n;
+} dgsm_gaussians_t;
+
+/* Point lights.  pos is a DEVICE pointer [n][3].  kappa is the global
+ * strength knob of Eq. 5 (1 reproduces the 3DGS opacity in the far field). */
+typedef struct {
+    const float* pos;
+    int32_t n;
+    float kappa;
+} dgsm_lights_t;
+
+/* Atlas description.  H and W even, >= 2; K >= 2; r1 > 0, and 0 < r0 < r1
+ * for geometric spacing.  cull_eps is the per-Gaussian contribution bound of
+ * the light-space culling (Sec. 3.2 "Occluder culling"): a Gaussian is left
+ * out of a tile only where its optical depth along every texel ray of the
+ * tile is provably below cull_eps.  cull_eps = 0 disables culling (every
+ * Gaussian is evaluated for every texel; the result then equals the plain
+ * definition up to FP32 rounding).  Typical value 1e-8. */
+typedef struct {
+    int32_t H, W, K;
+    int32_t spacing;       /* dgsm_spacing */
+    float r0, r1;
+    int32_t dtype;         /* dgsm_dtype of the stored T: FP32, or FP16 (RNE of the FP32 value) */
+    float cull_eps;
+} dgsm_atlas_desc_t;
+
+/* Human-readable text for a status code (static storage). */
+const char* dgsm_status_string(dgsm_status s);
+
+/* Bytes of workspace dgsm_build needs for this atlas, n_gauss Gaussians and
+ * n_lights lights.  Returns 0 if desc is invalid. */
+size_t dgsm_build_workspace_size(const dgsm_atlas_desc_t* desc, int64_t n_gauss, int32_t n_lights);
+
+/*
+ * dgsm_build - tabulate T(d, t) = exp(-tau(d, t)) for every light (Sec. 3.2).
+ *   tau(d, t) = sum_i beta_i int_0^t exp(-1/2 (x(s)-mu_i)^T A_i (x(s)-mu_i)) ds,
+ *   x(s) = o_L + s d (Eqs. 1-2), each term in the erf closed form of Eq. 3,
+ *   T by Eq. 4, beta_i = kappa (-ln(1-alpha_i)) sqrt(tr(A_i)/3) / sqrt(2 pi) (Eq. 5).
+ * Every Gaussian passed is an occluder.  Computed in FP32 with the
+ * cancellation-prone geometry (light-to-mean offsets, ray cross products and
+ * the distance along the ray) in FP64.
+ *   lights   : n >= 1 lights
+ *   gaussians: any n >= 0 (n = 0 gives T = 1 everywhere)
+ *   atlas    : device output [lights.n][K][H][W] of desc->dtype
+ *   ws       : device workspace of >= dgsm_build_workspace_size(...) bytes; its
+ *              contents on entry are ignored and on exit undefined
+ * T is non-increasing in k at every texel and lies in [0, 1].
+ */
+dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
+                       const dgsm_atlas_desc_t* desc, void* atlas, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/*
+ * dgsm_query - sample the atlas at world points (Sec. 3.3): for each light l
+ * and point x, r = |x - o_L|, d = (x - o_L)/r (d = +z when r = 0), continuous
+ * texel coordinates j_f = (u+1) W/2 - 1/2, i_f = (v+1) H/2 - 1/2 of (u, v) =
+ * psi(d), fractional shell k_f = (K-1) ln(r/r0)/ln(r1/r0) (geometric) or
+ * r K / r1 - 1/2 (uniform) clamped to [0, K-1]; trilinear interpolation of T.
+ * Texel neighbours outside the grid follow the octahedral mirror wrap: a
+ * column beyond the left/right edge maps to column 0 / W-1 at row H-1-i, then
+ * a row beyond the top/bottom edge maps to row 0 / H-1 at column W-1-j.
+ *   atlas : device [lights.n][K][H][W] of desc->dtype (as written by dgsm_build)
+ *   points: device [P][3];  T: device output [lights.n][P] float32.  P may be 0.
+ */
+dgsm_status dgsm_query(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc, const void* atlas,
+                       const float* points, int64_t P, float* T, void* stream);
+
+/* Parameters of the SH radiance transfer (Sec. 3.5).  The lat-long grid has
+ * cell centres theta_a = (a + 1/2) pi / n_theta, phi_b = (b + 1/2) 2 pi / n_phi,
+ * direction (sin th cos ph, sin th sin ph, cos th) and weight sin(theta).
+ * Defaults used by the workloads: 32 x 64, q = 1, clip_max = 4, eps = 1e-6,
+ * gamma = 1. */
+typedef struct {
+    int32_t n_theta, n_phi;   /* >= 1 each */
+    float q;                  /* lobe exponent, > 0 (1 = Lambertian) */
+    float clip_max;           /* t_max of the clip, > 0 */
+    float eps;                /* denominator epsilon, >= 0 */
+    float gamma;              /* global intensity */
+    const float* centroid;    /* device [3]: point the normals face away from */
+} dgsm_sh_params_t;
+
+/*
+ * sh_transfer - per-Gaussian radiance transfer (Sec. 3.4 evaluation and 3.5).
+ *   L(w) = B(w) A with the probe A = probe_sh [Kp][3] (Kp in {1, 4, 9, 16});
+ *   B is the real orthonormal SH basis, index k = l^2 + l + m, WITHOUT the
+ *   Condon-Shortley phase (Y_1,-1 ~ +y, Y_1,0 ~ +z, Y_1,1 ~ +x).
+ *   n = column of R for the smallest scale (ties: lowest axis), negated when
+ *   n . (mu - centroid) < 0.  S_j = max(0, <w_j, n>)^q.
+ *   s_c = clip_[0, clip_max]( sum_j w_j L_c(w_j) S_j / (sum_j w_j S_j + eps) ).
+ *   scale_out     : device [n][3] = s
+ *   colour_sh     : device [n][16][3] SH colour coefficients, or NULL
+ *   colour_sh_out : device [n][16][3] = gamma s_c f (no clamp), or NULL
+ *   rgb_out       : device [n][3] = max(0, gamma (0.5 + C0 f_0) s) with
+ *                   C0 = 1/(2 sqrt(pi)) (the DC colour), or NULL
+ *   colour_sh_out and rgb_out require colour_sh.
+ */
+dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_t* gaussians,
+                        const float* colour_sh, const dgsm_sh_params_t* params, float* scale_out,
+                        float* colour_sh_out, float* rgb_out, void* stream);
+
+/* dgsm_alpha_centroid - c = sum_i alpha_i mu_i / sum_i alpha_i (Sec. 3.2
+ * "Receiver-driven region", the alpha-weighted avatar centroid), accumulated
+ * in FP64 in a fixed order (bitwise reproducible).  centroid: device [3].
+ * n >= 1 and sum alpha > 0 required for a finite result. */
+dgsm_status dgsm_alpha_centroid(const dgsm_gaussians_t* gaussians, float* centroid, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGSM_H */

@@ -1,0 +1,220 @@
+"""Python binding of the MI355X DGSM library (``libdgsm.so``, C ABI in include/dgsm.h).
+
+Argument marshalling only: every step of the build, query and transfer runs
+in the library's HIP kernels.  Tensors must be contiguous float32 CUDA (ROCm)
+tensors; calls are enqueued on ``torch.cuda.current_stream()``.  There is no
+CPU fallback: if the library is missing, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgsm.so")
+
+DGSM_SHELLS_UNIFORM, DGSM_SHELLS_GEOMETRIC = 0, 1
+DGSM_F32, DGSM_F16 = 0, 1
+
+
+class _Gaussians(ctypes.Structure):
+    _fields_ = [("mean", ctypes.c_void_p), ("scale", ctypes.c_void_p), ("rot", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class _Lights(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_void_p), ("n", ctypes.c_int32), ("kappa", ctypes.c_float)]
+
+
+class _AtlasDesc(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("spacing", ctypes.c_int32), ("r0", ctypes.c_float), ("r1", ctypes.c_float),
+                ("dtype", ctypes.c_int32), ("cull_eps", ctypes.c_float)]
+
+
+class _ShParams(ctypes.Structure):
+    _fields_ = [("n_theta", ctypes.c_int32), ("n_phi", ctypes.c_int32), ("q", ctypes.c_float),
+                ("clip_max", ctypes.c_float), ("eps", ctypes.c_float), ("gamma", ctypes.c_float),
+                ("centroid", ctypes.c_void_p)]
+
+
+_LIB = None
+
+# exported symbol -> (restype, argtypes)
+SIGNATURES = {
+    "dgsm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "dgsm_build_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(_AtlasDesc), ctypes.c_int64, ctypes.c_int32]),
+    "dgsm_build": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_Gaussians), ctypes.POINTER(_AtlasDesc),
+                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dgsm_query": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_AtlasDesc), ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "sh_transfer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_Gaussians), ctypes.c_void_p,
+                                   ctypes.POINTER(_ShParams), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p]),
+    "dgsm_alpha_centroid": (ctypes.c_int, [ctypes.POINTER(_Gaussians), ctypes.c_void_p, ctypes.c_void_p]),
+}
+
+
+def lib():
+    """The loaded ``libdgsm.so``; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"DGSM HIP library not built: {LIB_PATH} is missing "
+                               "(run `python -m paper_2601_01660_amd.build`)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+class DGSMError(RuntimeError):
+    pass
+
+
+def _check(status: int):
+    if status != 0:
+        raise DGSMError(f"dgsm status {status}: {lib().dgsm_status_string(status).decode()}")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dev(t, dtype=torch.float32):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    if not t.is_cuda:
+        t = t.cuda()
+    if t.dtype != dtype:
+        t = t.to(dtype)
+    return t.contiguous()
+
+
+@dataclass
+class GaussianSet:
+    """Device-resident Gaussian set (structure of arrays, float32)."""
+
+    mean: torch.Tensor     # [N, 3]
+    scale: torch.Tensor    # [N, 3]
+    rot: torch.Tensor      # [N, 4] (w, x, y, z)
+    opacity: torch.Tensor  # [N]
+
+    @property
+    def n(self) -> int:
+        return int(self.mean.shape[0])
+
+    @staticmethod
+    def from_host(g) -> "GaussianSet":
+        """From any object with numpy .mean/.scale/.rot/.opacity (e.g. synth.Gaussians)."""
+        return GaussianSet(_dev(g.mean), _dev(g.scale), _dev(g.rot), _dev(g.opacity))
+
+    def struct(self) -> _Gaussians:
+        return _Gaussians(self.mean.data_ptr(), self.scale.data_ptr(), self.rot.data_ptr(),
+                          self.opacity.data_ptr(), self.n)
+
+
+@dataclass
+class Atlas:
+    """Atlas description (mirrors dgsm_atlas_desc_t)."""
+
+    H: int
+    W: int
+    K: int
+    spacing: str = "geometric"
+    r0: float = 0.05
+    r1: float = 8.0
+    dtype: str = "f32"
+    cull_eps: float = 1e-8
+
+    def struct(self) -> _AtlasDesc:
+        sp = {"uniform": DGSM_SHELLS_UNIFORM, "geometric": DGSM_SHELLS_GEOMETRIC}[self.spacing]
+        dt = {"f32": DGSM_F32, "f16": DGSM_F16}[self.dtype]
+        return _AtlasDesc(self.H, self.W, self.K, sp, self.r0, self.r1, dt, self.cull_eps)
+
+    @property
+    def torch_dtype(self):
+        return torch.float16 if self.dtype == "f16" else torch.float32
+
+    @staticmethod
+    def from_spec(spec, **kw) -> "Atlas":
+        """From an object with H, W, K, spacing, r0, r1 (e.g. synth.AtlasSpec)."""
+        return Atlas(spec.H, spec.W, spec.K, spec.spacing, spec.r0, spec.r1, **kw)
+
+
+def dgsm_build_workspace_size(atlas: Atlas, n_gauss: int, n_lights: int) -> int:
+    d = atlas.struct()
+    return int(lib().dgsm_build_workspace_size(ctypes.byref(d), n_gauss, n_lights))
+
+
+def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0, out=None, workspace=None):
+    """Build T[L, K, H, W] (see dgsm_build in include/dgsm.h)."""
+    lights = _dev(lights)
+    L = int(lights.shape[0])
+    d = atlas.struct()
+    ws_bytes = dgsm_build_workspace_size(atlas, gaussians.n, L)
+    if ws_bytes == 0:
+        raise DGSMError("invalid atlas description")
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=lights.device)
+    if out is None:
+        out = torch.empty((L, atlas.K, atlas.H, atlas.W), dtype=atlas.torch_dtype, device=lights.device)
+    lt = _Lights(lights.data_ptr(), L, kappa)
+    gs = gaussians.struct()
+    _check(lib().dgsm_build(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), _ptr(out), _ptr(workspace),
+                            workspace.numel(), _stream()))
+    return out
+
+
+def dgsm_query(lights, atlas: Atlas, table, points, out=None):
+    """Trilinear lookup T[L, P] of the atlas at points [P, 3]."""
+    lights = _dev(lights)
+    points = _dev(points)
+    L = int(lights.shape[0])
+    P = int(points.shape[0])
+    if out is None:
+        out = torch.empty((L, P), dtype=torch.float32, device=points.device)
+    d = atlas.struct()
+    lt = _Lights(lights.data_ptr(), L, 1.0)
+    _check(lib().dgsm_query(ctypes.byref(lt), ctypes.byref(d), _ptr(table), _ptr(points), P, _ptr(out), _stream()))
+    return out
+
+
+def dgsm_alpha_centroid(gaussians: GaussianSet, out=None):
+    if out is None:
+        out = torch.empty(3, dtype=torch.float32, device=gaussians.mean.device)
+    gs = gaussians.struct()
+    _check(lib().dgsm_alpha_centroid(ctypes.byref(gs), _ptr(out), _stream()))
+    return out
+
+
+def sh_transfer(probe_sh, gaussians: GaussianSet, colour_sh=None, centroid=None, n_theta=32, n_phi=64,
+                q=1.0, clip_max=4.0, eps=1e-6, gamma=1.0):
+    """Per-Gaussian lighting scale [N,3], relit SH [N,16,3] and RGB [N,3] (Sec. 3.5)."""
+    probe_sh = _dev(probe_sh)
+    colour_sh = _dev(colour_sh)
+    if centroid is None:
+        centroid = dgsm_alpha_centroid(gaussians)
+    centroid = _dev(centroid)
+    N = gaussians.n
+    dev = gaussians.mean.device
+    s = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    f_out = torch.empty((N, 16, 3), dtype=torch.float32, device=dev) if colour_sh is not None else None
+    rgb = torch.empty((N, 3), dtype=torch.float32, device=dev) if colour_sh is not None else None
+    prm = _ShParams(n_theta, n_phi, q, clip_max, eps, gamma, centroid.data_ptr())
+    gs = gaussians.struct()
+    _check(lib().sh_transfer(_ptr(probe_sh), int(probe_sh.shape[0]), ctypes.byref(gs), _ptr(colour_sh),
+                             ctypes.byref(prm), _ptr(s), _ptr(f_out), _ptr(rgb), _stream()))
+    return s, f_out, rgb

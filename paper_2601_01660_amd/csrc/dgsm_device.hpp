@@ -1,0 +1,136 @@
+// Device-side building blocks shared by the DGSM kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "dgsm.h"
+
+namespace dgsm {
+
+constexpr int kWave = 64;
+constexpr int kTile = 8;          // atlas tile side in texels (Sec. 3.2 buckets 8x8 tiles)
+constexpr int kMaxSuper = 64;     // supertiles per light (one 64-bit mask per Gaussian)
+constexpr int kPrepThreads = 256;
+constexpr float kZc = 4.5f;       // erf is saturated beyond |x| > 4.5 (erfc(4.5) < 2e-10)
+
+// Tiling of one atlas: tiles of kTile x kTile texels, grouped into at most
+// 8 x 8 supertiles (the coarse level of the two-level light-space binning).
+struct Geom {
+    int H, W, K, spacing, dtype;
+    float r0, r1;
+    int TH, TW;      // tiles per column / row
+    int SGH, SGW;    // supertile grid
+    int STH, STW;    // tiles per supertile side
+    int S;           // SGH * SGW
+    int ntiles;
+};
+
+inline Geom make_geom(const dgsm_atlas_desc_t& d) {
+    Geom g{};
+    g.H = d.H; g.W = d.W; g.K = d.K; g.spacing = d.spacing; g.dtype = d.dtype;
+    g.r0 = d.r0; g.r1 = d.r1;
+    g.TH = (d.H + kTile - 1) / kTile;
+    g.TW = (d.W + kTile - 1) / kTile;
+    g.SGH = g.TH < 8 ? g.TH : 8;
+    g.SGW = g.TW < 8 ? g.TW : 8;
+    g.STH = (g.TH + g.SGH - 1) / g.SGH;
+    g.STW = (g.TW + g.SGW - 1) / g.SGW;
+    g.SGH = (g.TH + g.STH - 1) / g.STH;   // drop empty supertile rows/cols
+    g.SGW = (g.TW + g.STW - 1) / g.STW;
+    g.S = g.SGH * g.SGW;
+    g.ntiles = g.TH * g.TW;
+    return g;
+}
+
+// Per-(light, Gaussian) record read by the tile build with wave-uniform
+// (scalar) loads.  w_j = R e_j / s_j are the rows of the whitening W with
+// A = W^T W; c_j = R e_j / (s_k s_l) are the rows of adj(A)^(1/2).
+struct __attribute__((aligned(16))) GRec {
+    double mx, my, mz;   // o_L - mu, exact in FP64
+    float w[9];
+    float c[9];
+    float bp;            // beta * sqrt(pi / 2)
+    float pad[3];
+};
+static_assert(sizeof(GRec) == 112, "GRec layout");
+
+// Octahedral decode of the texel centre (i, j) of an H x W atlas (Sec. 3.2).
+__device__ inline void texel_dir(int i, int j, int H, int W, double& x, double& y, double& z) {
+    const double u = -1.0 + (2.0 * j + 1.0) / W;
+    const double v = -1.0 + (2.0 * i + 1.0) / H;
+    const double au = fabs(u), av = fabs(v);
+    z = 1.0 - au - av;
+    if (z < 0.0) {
+        x = (u >= 0.0 ? 1.0 : -1.0) * (1.0 - av);
+        y = (v >= 0.0 ? 1.0 : -1.0) * (1.0 - au);
+    } else {
+        x = u;
+        y = v;
+    }
+    const double inv = 1.0 / sqrt(x * x + y * y + z * z);
+    x *= inv; y *= inv; z *= inv;
+}
+
+// Two cones (unit axis, sin of half the half-angle) can share a direction iff
+// the angle between the axes is at most the sum of the half-angles.  Tested
+// with the chord |a - b| = 2 sin(angle / 2), which stays accurate for small
+// angles.  sh < 0 marks an empty cone.
+__device__ inline bool cones_touch(float4 a, float4 b) {
+    if (a.w < 0.f || b.w < 0.f) return false;
+    const float ca = sqrtf(fmaxf(0.f, 1.f - a.w * a.w));
+    const float cb = sqrtf(fmaxf(0.f, 1.f - b.w * b.w));
+    const float sh = a.w * cb + ca * b.w;        // sin((ta + tb) / 2)
+    const float chh = ca * cb - a.w * b.w;       // cos((ta + tb) / 2)
+    if (chh <= 0.f) return true;                 // half-angles sum to >= pi
+    const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    return dx * dx + dy * dy + dz * dz <= 4.f * sh * sh;
+}
+
+// Shell radius t_k in FP64.
+__device__ inline double shell_radius(int k, int K, int spacing, float r0, float r1) {
+    if (spacing == DGSM_SHELLS_GEOMETRIC)
+        return (double)r0 * pow((double)r1 / (double)r0, (double)k / (double)(K - 1));
+    return ((double)k + 0.5) * (double)r1 / (double)K;
+}
+
+template <typename T>
+__device__ inline T wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, kWave);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ inline T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, kWave);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// Rank of this lane among the lanes set in a wave ballot.
+__device__ inline int ballot_rank(uint64_t bal) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+}
+
+template <typename T> struct Store;
+template <> struct Store<float> {
+    __device__ static inline void put(float* p, float v) { *p = v; }
+    __device__ static inline float get(const float* p) { return *p; }
+};
+template <> struct Store<__half> {
+    __device__ static inline void put(__half* p, float v) { *p = __float2half_rn(v); }
+    __device__ static inline float get(const __half* p) { return __half2float(*p); }
+};
+
+}  // namespace dgsm

@@ -1,0 +1,120 @@
+// DGSM sampling on gfx950 (Sec. 3.3): trilinear lookup of the octahedral x
+// radial atlas at world points, one thread per point, all lights per thread
+// (the point is read once; each light adds 8 texel gathers and one store).
+
+#include "dgsm_device.hpp"
+#include "dgsm_host.hpp"
+
+namespace dgsm {
+
+// Octahedral mirror wrap of a texel one step outside the grid: across the
+// left/right edge (u = -1/+1) the map identifies (u, v) with (u, -v), across
+// the top/bottom edge (v = -1/+1) it identifies (u, v) with (-u, v).
+__device__ inline int wrap_offset(int i, int j, int H, int W) {
+    if (j < 0) { j = 0; i = H - 1 - i; }
+    else if (j >= W) { j = W - 1; i = H - 1 - i; }
+    if (i < 0) { i = 0; j = W - 1 - j; }
+    else if (i >= H) { i = H - 1; j = W - 1 - j; }
+    return i * W + j;
+}
+
+struct QueryArgs {
+    Geom g;
+    const float* lights;   // [L][3]
+    int L;
+    const void* atlas;     // [L][K][H][W]
+    const float* points;   // [P][3]
+    int64_t P;
+    float* T;              // [L][P]
+    float lr0, kscale;     // shell coordinate: geometric (log2 r - lr0) * kscale, uniform r * kscale - 1/2
+};
+
+template <typename InT>
+__global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.P) return;
+    const Geom& g = a.g;
+    const float x = a.points[3 * p], y = a.points[3 * p + 1], z = a.points[3 * p + 2];
+    const size_t plane = (size_t)g.H * g.W;
+    const InT* atlas = reinterpret_cast<const InT*>(a.atlas);
+    for (int l = 0; l < a.L; ++l) {
+        const float dx = x - a.lights[3 * l], dy = y - a.lights[3 * l + 1], dz = z - a.lights[3 * l + 2];
+        const float l1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
+        float qx = 0.f, qy = 0.f, qz = 1.f;
+        if (l1 > 0.f) {
+            const float il = 1.f / l1;
+            qx = dx * il; qy = dy * il; qz = dz * il;
+        }
+        float u = qx, v = qy;
+        if (qz < 0.f) {
+            u = copysignf(1.f - fabsf(qy), qx >= 0.f ? 1.f : -1.f);
+            v = copysignf(1.f - fabsf(qx), qy >= 0.f ? 1.f : -1.f);
+        }
+        // clamped (NaN-safe) so that every gathered texel index stays in the atlas
+        const float jf = fminf(fmaxf((u + 1.f) * (0.5f * (float)g.W) - 0.5f, -0.5f), (float)g.W - 0.5f);
+        const float fi_ = fminf(fmaxf((v + 1.f) * (0.5f * (float)g.H) - 0.5f, -0.5f), (float)g.H - 0.5f);
+        const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+        float kf = g.spacing == DGSM_SHELLS_GEOMETRIC ? (__log2f(r) - a.lr0) * a.kscale : r * a.kscale - 0.5f;
+        kf = fminf(fmaxf(kf, 0.f), (float)(g.K - 1));   // log2(0) = -inf clamps to shell 0
+        const float j0f = floorf(jf), i0f = floorf(fi_);
+        const int j0 = (int)j0f, i0 = (int)i0f;
+        const float fj = jf - j0f, fi = fi_ - i0f;
+        const int k0 = min((int)kf, g.K - 2);
+        const float fk = kf - (float)k0;
+        const int o00 = wrap_offset(i0, j0, g.H, g.W), o01 = wrap_offset(i0, j0 + 1, g.H, g.W);
+        const int o10 = wrap_offset(i0 + 1, j0, g.H, g.W), o11 = wrap_offset(i0 + 1, j0 + 1, g.H, g.W);
+        const InT* s0 = atlas + ((size_t)l * g.K + k0) * plane;
+        const InT* s1 = s0 + plane;
+        const float a0 = (1.f - fj) * Store<InT>::get(s0 + o00) + fj * Store<InT>::get(s0 + o01);
+        const float b0 = (1.f - fj) * Store<InT>::get(s0 + o10) + fj * Store<InT>::get(s0 + o11);
+        const float a1 = (1.f - fj) * Store<InT>::get(s1 + o00) + fj * Store<InT>::get(s1 + o01);
+        const float b1 = (1.f - fj) * Store<InT>::get(s1 + o10) + fj * Store<InT>::get(s1 + o11);
+        const float t0 = (1.f - fi) * a0 + fi * b0;
+        const float t1 = (1.f - fi) * a1 + fi * b1;
+        a.T[(size_t)l * a.P + p] = (1.f - fk) * t0 + fk * t1;
+    }
+}
+
+hipError_t launch_query(const Geom& g, const float* lights, int L, const void* atlas, const float* points,
+                        int64_t P, float* T, hipStream_t st) {
+    if (P == 0) return hipSuccess;
+    QueryArgs a{g, lights, L, atlas, points, P, T, 0.f, 0.f};
+    if (g.spacing == DGSM_SHELLS_GEOMETRIC) {
+        a.lr0 = log2f(g.r0);
+        a.kscale = (float)(g.K - 1) / log2f(g.r1 / g.r0);
+    } else {
+        a.kscale = (float)g.K / g.r1;
+    }
+    const unsigned blocks = (unsigned)((P + 255) / 256);
+    if (g.dtype == DGSM_F16)
+        query_kernel<__half><<<blocks, 256, 0, st>>>(a);
+    else
+        query_kernel<float><<<blocks, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace dgsm
+
+using namespace dgsm;
+
+extern "C" dgsm_status dgsm_query(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc, const void* atlas,
+                                  const float* points, int64_t P, float* T, void* stream) {
+    dgsm_status st = validate_desc(desc);
+    if (st != DGSM_OK) return st;
+    if ((st = validate_lights(lights)) != DGSM_OK) return st;
+    if (P < 0 || (P > 0 && (!atlas || !points || !T))) return DGSM_EINVAL;
+    const Geom g = make_geom(*desc);
+    return launch_query(g, lights->pos, lights->n, atlas, points, P, T,
+                        reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? DGSM_OK : DGSM_EHIP;
+}
+
+extern "C" const char* dgsm_status_string(dgsm_status s) {
+    switch (s) {
+        case DGSM_OK: return "ok";
+        case DGSM_EINVAL: return "invalid argument";
+        case DGSM_EWORKSPACE: return "workspace missing or too small";
+        case DGSM_EHIP: return "HIP runtime or kernel launch error";
+        case DGSM_EUNSUPPORTED: return "unsupported by this build";
+    }
+    return "unknown status";
+}

@@ -1,0 +1,102 @@
+"""CPU checks of the C ABI: the header compiles as C, the library loads and
+exports every declared entry point, and host-side validation rejects bad
+arguments before anything touches a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dgsm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "defined")))
+
+
+def test_header_compiles_as_c_and_cpp():
+    for std, lang in (("c11", "c"), ("c++17", "c++")):
+        r = subprocess.run(["gcc", "-x", lang, f"-std={std}", "-fsyntax-only", "-Wall", "-Werror", HEADER],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("dgsm_build", "dgsm_query", "sh_transfer", "dgsm_build_workspace_size",
+              "dgsm_status_string", "dgsm_alpha_centroid"):
+        assert n in names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2601_01660_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.skip("libdgsm.so not built")
+    return P.lib()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    r = subprocess.run(["nm", "-D", "--defined-only", lib._name], capture_output=True, text=True)
+    exported = set(line.split()[-1] for line in r.stdout.splitlines() if line.strip())
+    for n in declared_functions():
+        assert n in exported, n
+        assert hasattr(lib, n)
+
+
+def test_status_strings(lib):
+    import paper_2601_01660_amd as P
+    for s in range(5):
+        assert isinstance(lib.dgsm_status_string(s), bytes)
+    assert P.lib().dgsm_status_string(0) == b"ok"
+
+
+def _desc(**kw):
+    import paper_2601_01660_amd as P
+    base = dict(H=32, W=32, K=16, spacing="geometric", r0=0.05, r1=8.0, dtype="f32", cull_eps=1e-8)
+    base.update(kw)
+    return P.Atlas(**base)
+
+
+def test_workspace_size_is_host_only_and_grows_with_n(lib):
+    import paper_2601_01660_amd as P
+    a = P.dgsm_build_workspace_size(_desc(), 0, 1)
+    b = P.dgsm_build_workspace_size(_desc(), 5000, 1)
+    c = P.dgsm_build_workspace_size(_desc(H=512, W=512, K=64), 2_150_000, 4)
+    assert 0 < a < b < c
+
+
+@pytest.mark.parametrize("bad", [dict(H=31), dict(W=0), dict(K=1), dict(K=513), dict(r0=0.0),
+                                 dict(r0=9.0), dict(r1=-1.0), dict(cull_eps=-1.0)])
+def test_invalid_descriptions_are_rejected(lib, bad):
+    import paper_2601_01660_amd as P
+    assert P.dgsm_build_workspace_size(_desc(**bad), 10, 1) == 0
+    d = _desc(**bad).struct()
+    lt = P._Lights(1, 1, 1.0)          # never dereferenced: validation comes first
+    gs = P._Gaussians(0, 0, 0, 0, 0)
+    st = lib.dgsm_build(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), 1, 1, 1 << 40, None)
+    assert st == 1
+
+
+def test_null_pointers_and_small_workspace_are_rejected(lib):
+    import paper_2601_01660_amd as P
+    d = _desc().struct()
+    gs = P._Gaussians(0, 0, 0, 0, 5)          # n > 0 with null arrays
+    lt = P._Lights(1, 1, 1.0)
+    assert lib.dgsm_build(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), 1, 1, 1 << 40, None) == 1
+    gs = P._Gaussians(1, 1, 1, 1, 5)
+    assert lib.dgsm_build(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), 1, 1, 16, None) == 2
+    assert lib.dgsm_build(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), 1, None, 1 << 40, None) == 2
+    lt0 = P._Lights(0, 1, 1.0)
+    assert lib.dgsm_build(ctypes.byref(lt0), ctypes.byref(gs), ctypes.byref(d), 1, 1, 1 << 40, None) == 1
+    assert lib.dgsm_query(ctypes.byref(lt), ctypes.byref(d), None, 1, 10, 1, None) == 1
+    prm = P._ShParams(32, 64, 1.0, 4.0, 1e-6, 1.0, 0)
+    assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, None, None) == 1
+    prm = P._ShParams(32, 64, 1.0, 4.0, 1e-6, 1.0, 1)
+    assert lib.sh_transfer(1, 5, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, None, None) == 1
+    assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, 1, None) == 1

@@ -1,0 +1,265 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: FP32 transmittance within 1e-4 absolute of the oracle (table and
+queries); FP16 storage within 1e-2; SH transfer within 1e-4 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import dgsm as od
+from oracle import sh as osh
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_01660_amd as P
+    P.lib()   # raises if the HIP library is missing
+
+
+def _util():
+    import gpu_util
+    return gpu_util
+
+
+def _report(name, err):
+    print(f"[parity] {name}: max|dT| = {err:.3e}", flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Plain build + query at the 5k-Gaussian workload (32 x 32 x 16)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cfg1():
+    c = synth.cfg1()
+    a = c["atlas"]
+    c["oracle_T"] = od.build(c["lights"][0], c["gaussians"], a.H, a.W, a.K, a.spacing, a.r0, a.r1)
+    return c
+
+
+def test_cfg1_build_matches_oracle(cfg1):
+    U = _util()
+    T, _ = U.gpu_build(cfg1["gaussians"], cfg1["lights"], cfg1["atlas"])
+    got = T[0].cpu().numpy().astype(np.float64)
+    err = np.abs(got - cfg1["oracle_T"]).max()
+    _report("cfg1 build", err)
+    assert err <= TOL
+
+
+def test_cfg1_query_matches_oracle(cfg1):
+    U = _util()
+    T, atlas = U.gpu_build(cfg1["gaussians"], cfg1["lights"], cfg1["atlas"])
+    got = U.gpu_query(cfg1["lights"], atlas, T, cfg1["points"])[0]
+    ref = od.query(cfg1["oracle_T"], cfg1["lights"][0], cfg1["points"])
+    err = np.abs(got - ref).max()
+    _report("cfg1 query", err)
+    assert err <= TOL
+    # the query kernel alone: FP64 trilinear of the GPU's own table
+    own = od.query(T[0].cpu().numpy().astype(np.float64), cfg1["lights"][0], cfg1["points"])
+    assert np.abs(got - own).max() <= 2e-5
+
+
+def test_cfg1_denser_ragged_two_lights():
+    """The 5k scene at 36 x 36 (ragged 8x8 tiles) x 24 shells, two lights, one inside the cloud."""
+    U = _util()
+    c = synth.cfg1()
+    g = c["gaussians"]
+    lights = np.array([[0.0, 0.0, 0.0], [2.5, 2.5, 2.5]], np.float32)
+    spec = synth.AtlasSpec(36, 36, 24)
+    T, atlas = U.gpu_build(g, lights, spec)
+    got = T.cpu().numpy().astype(np.float64)
+    for l in range(2):
+        ref = od.build(lights[l], g, spec.H, spec.W, spec.K)
+        err = np.abs(got[l] - ref).max()
+        _report(f"36x36x24 light {l}", err)
+        assert err <= TOL
+        pts = g.mean[::7]
+        q = U.gpu_query(lights, atlas, T, pts)[l]
+        assert np.abs(q - od.query(ref, lights[l], pts)).max() <= TOL
+
+
+def test_uniform_shells_and_kappa():
+    U = _util()
+    c = synth.cfg1(1500)
+    g = c["gaussians"]
+    spec = synth.AtlasSpec(16, 24, 10, spacing="uniform", r0=0.05, r1=8.0)
+    T, atlas = U.gpu_build(g, c["lights"], spec, kappa=1.7)
+    ref = od.build(c["lights"][0], g, spec.H, spec.W, spec.K, "uniform", spec.r0, spec.r1, kappa=1.7)
+    err = np.abs(T[0].cpu().numpy() - ref).max()
+    _report("uniform shells kappa 1.7", err)
+    assert err <= TOL
+    q = U.gpu_query(c["lights"], atlas, T, g.mean)[0]
+    assert np.abs(q - od.query(ref, c["lights"][0], g.mean, "uniform", spec.r0, spec.r1)).max() <= TOL
+
+
+def test_light_inside_gaussians_and_large_scales():
+    """Gaussians that contain the light (global culling cones) and wide ramps."""
+    U = _util()
+    rng = np.random.default_rng(5)
+    g = synth.random_gaussians(rng, rng.uniform(-0.6, 0.6, (300, 3)), 0.25)
+    lights = np.array([[0.01, -0.02, 0.03]], np.float32)
+    spec = synth.AtlasSpec(24, 24, 20, r0=0.02, r1=3.0)
+    T, _ = U.gpu_build(g, lights, spec)
+    ref = od.build(lights[0], g, spec.H, spec.W, spec.K, spec.spacing, spec.r0, spec.r1)
+    err = np.abs(T[0].cpu().numpy() - ref).max()
+    _report("light inside", err)
+    assert err <= TOL
+
+
+# ---------------------------------------------------------------------------
+# Special cases and invariants on the GPU
+# ---------------------------------------------------------------------------
+
+def test_empty_and_transparent_scene():
+    U = _util()
+    spec = synth.AtlasSpec(16, 16, 8)
+    lights = np.zeros((1, 3), np.float32)
+    T, atlas = U.gpu_build(synth.Gaussians.empty(), lights, spec)
+    assert torch.all(T == 1.0)
+    g = synth.cfg1(200)["gaussians"]
+    g.opacity[:] = 0.0
+    T, _ = U.gpu_build(g, lights, spec)
+    assert torch.all(T == 1.0)
+    q = U.gpu_query(lights, atlas, T, np.random.default_rng(1).uniform(-5, 5, (1000, 3)))
+    assert np.all(q == 1.0)
+
+
+def test_monotone_bounded_and_deterministic(cfg1):
+    U = _util()
+    spec = synth.AtlasSpec(64, 64, 32)
+    T1, _ = U.gpu_build(cfg1["gaussians"], cfg1["lights"], spec)
+    T2, _ = U.gpu_build(cfg1["gaussians"], cfg1["lights"], spec)
+    assert torch.equal(T1, T2)
+    assert torch.all(T1[:, 1:] <= T1[:, :-1])
+    assert torch.all((T1 >= 0) & (T1 <= 1))
+
+
+def test_culling_matches_unculled(cfg1):
+    U = _util()
+    spec = synth.AtlasSpec(64, 64, 16)
+    Tc, _ = U.gpu_build(cfg1["gaussians"], cfg1["lights"], spec, cull_eps=1e-8)
+    Tn, _ = U.gpu_build(cfg1["gaussians"], cfg1["lights"], spec, cull_eps=0.0)
+    err = (Tc - Tn).abs().max().item()
+    _report("culled vs unculled", err)
+    assert err <= 1e-6
+
+
+def test_additivity_on_gpu(cfg1):
+    U = _util()
+    g = cfg1["gaussians"]
+    spec = synth.AtlasSpec(32, 32, 16)
+    T, _ = U.gpu_build(g, cfg1["lights"], spec)
+    T1, _ = U.gpu_build(g.subset(np.arange(0, 2000)), cfg1["lights"], spec)
+    T2, _ = U.gpu_build(g.subset(np.arange(2000, g.n)), cfg1["lights"], spec)
+    assert (T - T1 * T2).abs().max().item() <= 1e-5
+
+
+def test_fp16_storage_within_bar(cfg1):
+    U = _util()
+    spec = synth.AtlasSpec(64, 64, 16)
+    T32, a32 = U.gpu_build(cfg1["gaussians"], cfg1["lights"], spec, dtype="f32")
+    T16, a16 = U.gpu_build(cfg1["gaussians"], cfg1["lights"], spec, dtype="f16")
+    assert T16.dtype == torch.float16
+    assert (T16.float() - T32).abs().max().item() <= 1e-2
+    assert torch.equal(T16, T32.half())       # RNE of the FP32 value
+    q32 = U.gpu_query(cfg1["lights"], a32, T32, cfg1["points"])
+    q16 = U.gpu_query(cfg1["lights"], a16, T16, cfg1["points"])
+    assert np.abs(q32 - q16).max() <= 1e-2
+
+
+def test_minimal_atlas():
+    U = _util()
+    c = synth.cfg1(300)
+    spec = synth.AtlasSpec(2, 2, 2)
+    T, atlas = U.gpu_build(c["gaussians"], c["lights"], spec)
+    ref = od.build(c["lights"][0], c["gaussians"], 2, 2, 2)
+    assert np.abs(T[0].cpu().numpy() - ref).max() <= TOL
+    q = U.gpu_query(c["lights"], atlas, T, c["points"])[0]
+    assert np.abs(q - od.query(ref, c["lights"][0], c["points"])).max() <= TOL
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads, sampled against the oracle
+# ---------------------------------------------------------------------------
+
+def test_cfg2_full_size_sampled():
+    U = _util()
+    c = synth.cfg2()
+    g, spec, light = c["gaussians"], c["atlas"], c["lights"][0]
+    T, atlas = U.gpu_build(g, c["lights"], spec)
+    i, j = U.sample_texels(g, light, spec.H, spec.W, 64, seed=21)
+    ref = od.build_texels(light, g, i, j, spec.K, spec.spacing, spec.r0, spec.r1, H=spec.H, W=spec.W)
+    got = T[0].cpu().numpy()[:, i, j].T
+    err = np.abs(got - ref).max()
+    _report("cfg2 sampled texels", err)
+    assert err <= TOL
+    pts = g.mean[np.random.default_rng(22).choice(g.n, 12, replace=False)]
+    q = U.gpu_query(c["lights"], atlas, T, pts)[0]
+    qref = od.query_exact(light, g, pts, spec.H, spec.W, spec.K, spec.spacing, spec.r0, spec.r1)
+    err = np.abs(q - qref).max()
+    _report("cfg2 sampled queries", err)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", TOL), ("f16", 1e-2)])
+def test_cfg3_frame0_full_size_sampled(dtype, tol):
+    """2M scene + 150k avatar Gaussians, 4 lights, 512 x 512 x 64 (the timed workload)."""
+    U = _util()
+    c = synth.cfg3(frames=1)
+    g = synth.Gaussians.concat([c["scene"], c["avatar"]])
+    spec = c["atlas"]
+    T, atlas = U.gpu_build(g, c["lights"], spec, dtype=dtype)
+    host = T.float().cpu().numpy()
+    for l in range(4):
+        light = c["lights"][l]
+        i, j = U.sample_texels(g, light, spec.H, spec.W, 16, seed=30 + l)
+        ref = od.build_texels(light, g, i, j, spec.K, spec.spacing, spec.r0, spec.r1, H=spec.H, W=spec.W)
+        err = np.abs(host[l][:, i, j].T - ref).max()
+        _report(f"cfg3 {dtype} light {l} sampled texels", err)
+        assert err <= tol
+
+
+# ---------------------------------------------------------------------------
+# SH radiance transfer
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kp,q", [(16, 1.0), (9, 1.0), (4, 3.5), (1, 1.0), (16, 8.0)])
+def test_sh_transfer_matches_oracle(kp, q):
+    import paper_2601_01660_amd as P
+    c = synth.cfg2(n_scene=10, n_avatar=3000)
+    av = c["avatar"]
+    rng = np.random.default_rng(40 + kp)
+    probe = synth.sh_probe(rng, kp)
+    f = c["colour_sh"]
+    gs = P.GaussianSet.from_host(av)
+    cen_gpu = P.dgsm_alpha_centroid(gs)
+    cen = osh.alpha_centroid(av.mean, av.opacity)
+    assert np.abs(cen_gpu.cpu().numpy() - cen).max() <= 1e-6
+    s, fo, rgb = P.sh_transfer(torch.from_numpy(probe), gs, torch.from_numpy(f), cen_gpu, q=q)
+    torch.cuda.synchronize()
+    s_ref, f_ref, rgb_ref = osh.relight(probe, av, f, centroid=cen_gpu.cpu().numpy().astype(np.float64), q=q)
+    s = s.cpu().numpy()
+    # normals that sit on the centroid plane may legitimately flip: accept either side there
+    n = osh.normals(av.rot, av.scale, av.mean, cen_gpu.cpu().numpy().astype(np.float64))
+    side = np.abs(np.einsum("ni,ni->n", n, av.mean - cen_gpu.cpu().numpy()))
+    amb = side < 1e-5
+    s_flip = osh.transfer_scale(probe, -n[amb], q=q) if amb.any() else None
+    rel = np.abs(s - s_ref) / np.maximum(np.abs(s_ref), 1e-3)
+    if amb.any():
+        rel_f = np.abs(s[amb] - s_flip) / np.maximum(np.abs(s_flip), 1e-3)
+        rel[amb] = np.minimum(rel[amb], rel_f)
+    print(f"[parity] sh kp={kp} q={q}: max rel = {rel.max():.3e}", flush=True)
+    assert rel.max() <= 1e-4
+    ok = ~amb
+    assert np.abs(fo.cpu().numpy()[ok] - f_ref[ok]).max() <= 1e-4 * max(1.0, np.abs(f_ref).max())
+    assert np.abs(rgb.cpu().numpy()[ok] - rgb_ref[ok]).max() <= 1e-4 * max(1.0, np.abs(rgb_ref).max())
