@@ -1,0 +1,197 @@
+"""DGSM build + query benchmark on one MI355X.
+
+Workload (the metric's configuration): a room of 2,000,000 static scene
+Gaussians plus a 150,000-Gaussian avatar translated rigidly along a seeded
+random walk for 60 frames, 4 point lights, 512 x 512 octahedral atlas x 64
+geometric shells (0.05-8 m) per light, FP32 arithmetic, FP16 atlas storage.
+Every frame builds the 4 atlases from all 2.15M Gaussians and queries the 4
+lights at all 2.15M Gaussian centres.  One step = all 60 frames; inputs are
+resident in HBM before timing starts.
+
+Prints ONE JSON line (rank 0).  ``value`` is ms per frame (lower is better).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DGSM build+query ms/frame (2M Gaussians, 4 lights); surrogate vs atlas at ΔT"
+
+# Algorithmic FP32-equivalent flops of the per-tile accumulation, per counted unit
+# (FMA = 2; transcendental = 1): see the roofline section of the design notes.
+FLOPS_PER_TILE_PAIR = 62      # ray geometry, a, e0, prefactor: every binned (texel, Gaussian) pair
+FLOPS_PER_ACTIVE_PAIR = 45    # closest-approach distance, erf scale, shell range: pairs above cull_eps
+FLOPS_PER_RAMP_EVAL = 27      # one shell of the erf ramp: argument, erf, increment
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--frames", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-texels", type=int, default=40)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(scene, avatar, lights, spec, n_texels):
+    """Time the FP64 oracle on a bounded sample and extrapolate to one frame."""
+    import numpy as np
+    import synth
+    from oracle import dgsm as od
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    g = synth.Gaussians.concat([scene, avatar])
+    rng = np.random.default_rng(7)
+    i = rng.integers(0, spec.H, n_texels)
+    j = rng.integers(0, spec.W, n_texels)
+    t0 = time.perf_counter()
+    od.build_texels(lights[0], g, i, j, spec.K, spec.spacing, spec.r0, spec.r1, H=spec.H, W=spec.W)
+    t_texel = (time.perf_counter() - t0) / n_texels
+    table = rng.uniform(0, 1, (spec.K, spec.H, spec.W))
+    pts = g.mean[:200_000]
+    t0 = time.perf_counter()
+    od.query(table, lights[0], pts, spec.spacing, spec.r0, spec.r1)
+    t_point = (time.perf_counter() - t0) / pts.shape[0]
+    L = lights.shape[0]
+    ms = 1e3 * (t_texel * spec.H * spec.W * L + t_point * g.n * L)
+    if limiter is not None:
+        limiter.unregister()
+    return {"value": ms, "unit": "ms/frame", "cores": 1, "kind": "oracle",
+            "sample": (f"{n_texels} texels x {spec.K} shells of light 0 over all {g.n} Gaussians "
+                       f"({t_texel:.3f} s/texel) + FP64 trilinear query of 200000 points; "
+                       f"extrapolated linearly to {L} lights x {spec.H}x{spec.W} texels + {L} x {g.n} queries")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(lights, frames or atlas tiles would shard without exchange; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2601_01660_amd as P
+    import synth
+
+    P.lib()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    F = args.frames
+    c = synth.cfg3(frames=F)
+    scene, avatar, lights_h, traj, spec = c["scene"], c["avatar"], c["lights"], c["trajectory"], c["atlas"]
+    N = scene.n + avatar.n
+    L = lights_h.shape[0]
+    log(f"workload: {scene.n} scene + {avatar.n} avatar Gaussians, {L} lights, "
+        f"{spec.H}x{spec.W}x{spec.K} fp16, {F} frames")
+
+    # ---- device-resident inputs (untimed) --------------------------------------------------
+    g0 = synth.Gaussians.concat([scene, avatar])
+    scale = torch.from_numpy(g0.scale).to(dev)
+    rot = torch.from_numpy(g0.rot).to(dev)
+    opac = torch.from_numpy(g0.opacity).to(dev)
+    means = torch.empty((F, N, 3), dtype=torch.float32, device=dev)
+    means[:, :scene.n] = torch.from_numpy(scene.mean).to(dev)
+    av = torch.from_numpy(avatar.mean).to(dev)
+    tr = torch.from_numpy(traj).to(dev)
+    for f in range(F):
+        means[f, scene.n:] = av + tr[f]          # FP32 add, same bits as synth's translate
+    sets = [P.GaussianSet(means[f], scale, rot, opac) for f in range(F)]
+    lights = torch.from_numpy(lights_h).to(dev)
+    atlas = P.Atlas.from_spec(spec, dtype="f16", cull_eps=1e-8)
+    ws = torch.empty(P.dgsm_build_workspace_size(atlas, N, L), dtype=torch.uint8, device=dev)
+    table = torch.empty((L, spec.K, spec.H, spec.W), dtype=torch.float16, device=dev)
+    Tq = torch.empty((L, N), dtype=torch.float32, device=dev)
+    log(f"workspace {ws.numel() / 2**30:.2f} GiB, atlas {table.numel() * 2 / 2**20:.0f} MiB")
+
+    acc_ev = []
+
+    def step(record=False):
+        for f in range(F):
+            P.dgsm_bin(lights, sets[f], atlas, ws)
+            if record:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+            P.dgsm_accumulate(lights, atlas, N, table, ws)
+            if record:
+                e1.record()
+                acc_ev.append((e0, e1))
+            P.dgsm_query(lights, atlas, table, sets[f].mean, out=Tq)
+
+    # ---- pair counters for the roofline (untimed) -------------------------------------------
+    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    for f in range(F):
+        P.dgsm_bin(lights, sets[f], atlas, ws)
+        P.dgsm_accumulate(lights, atlas, N, table, ws, stats=stats)
+    torch.cuda.synchronize()
+    st = stats.cpu().numpy().astype(np.float64) / F
+    flops = (FLOPS_PER_TILE_PAIR * st[0] + FLOPS_PER_ACTIVE_PAIR * st[1] + FLOPS_PER_RAMP_EVAL * st[2])
+    log(f"per frame: tile pairs {st[0]:.3e}, active pairs {st[1]:.3e}, ramp evals {st[2]:.3e}, "
+        f"list entries {st[3]:.3e}")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record()
+    for _ in range(args.steps):
+        step(record=True)
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    ms_frame = ms_step / F
+    acc_ms = float(np.mean([a.elapsed_time(b) for a, b in acc_ev]))
+    log(f"timed {args.steps} steps: {ms_total:.1f} ms (wall {wall:.2f} s); accumulate {acc_ms:.3f} ms/launch")
+
+    achieved = flops / (acc_ms * 1e-3) / 1e12
+    roofline = {"kernel": "tile_build_kernel (dgsm_accumulate, 4 lights per launch)", "bound": "alu",
+                "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "launch_ms": round(acc_ms, 4),
+                "units_per_launch": {"tile_pairs": st[0], "active_pairs": st[1], "ramp_evals": st[2]}}
+
+    out = {"metric": METRIC, "value": round(ms_frame, 4), "unit": "ms/frame", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": (f"room {scene.n} static + avatar {avatar.n} rigid-walk Gaussians, "
+                                   f"{L} point lights, {spec.H}x{spec.W}x{spec.K} geometric shells "
+                                   f"0.05-8 m, fp16 atlas, build+query every frame"),
+                      "frames_per_step": F, "gaussians": N, "lights": L,
+                      "mode": "plain per-frame dgsm_bin + dgsm_accumulate + dgsm_query"},
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(scene, avatar, lights_h, spec, args.cpu_texels)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

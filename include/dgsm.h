@@ -113,6 +113,32 @@ dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaus
                        void* stream);
 
 /*
+ * dgsm_build in two phases, for callers that schedule or time them apart.
+ * dgsm_build(...) is exactly dgsm_bin(...) followed by dgsm_accumulate(...) on
+ * the same workspace.
+ *
+ * dgsm_bin - light-space culling and bucketing of the occluders (Sec. 3.2
+ * "Occluder culling via light-space footprints"): per light and Gaussian a
+ * record of the Eq. 2-3 quantities and a conservative cone of directions
+ * outside which its optical depth stays below desc->cull_eps; Gaussian ids are
+ * bucketed, in ascending order, into lists of atlas supertiles (groups of 8x8
+ * texel tiles) whose texel-centre directions the cone can reach.
+ *
+ * dgsm_accumulate - per 8x8 atlas tile, the Gaussians of its supertile list
+ * whose cone reaches the tile are evaluated at every texel (Eq. 3), summed
+ * over Gaussians in list order (Eq. 2; bitwise reproducible) and stored as T
+ * (Eq. 4) in atlas.  n_gauss must equal the count passed to dgsm_bin.
+ *   stats: optional device array [4] of counters the call ADDS to (zero it
+ *   first): texel-Gaussian pairs evaluated at tile granularity, pairs whose
+ *   prefactor exceeded cull_eps, erf-ramp evaluations, supertile list entries
+ *   scanned.  NULL disables counting (the timed configuration).
+ */
+dgsm_status dgsm_bin(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
+                     const dgsm_atlas_desc_t* desc, void* ws, size_t ws_bytes, void* stream);
+dgsm_status dgsm_accumulate(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc, int64_t n_gauss,
+                            void* atlas, void* ws, size_t ws_bytes, unsigned long long* stats, void* stream);
+
+/*
  * dgsm_query - sample the atlas at world points (Sec. 3.3): for each light l
  * and point x, r = |x - o_L|, d = (x - o_L)/r (d = +z when r = 0), continuous
  * texel coordinates j_f = (u+1) W/2 - 1/2, i_f = (v+1) H/2 - 1/2 of (u, v) =

