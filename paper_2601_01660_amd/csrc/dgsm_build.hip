@@ -1,18 +1,21 @@
 // DGSM build on gfx950: light-space binning + per-tile closed-form optical depth.
 //
-// Pipeline for one light (Sec. 3.2):
+// Pipeline (all lights in every launch, blockIdx.y = light), Sec. 3.2:
 //   tile_cone_kernel / super_cone_kernel  bounding cones of the texel-centre
-//        directions of every 8x8 atlas tile and of every supertile
+//        directions of every 8x8 atlas tile and of every supertile (8x8 tiles)
 //   preprocess_kernel  per Gaussian: whitening rows, beta (Eq. 5), light-to-mean
-//        offset in FP64, a rigorous culling cone, the 64-bit supertile mask,
+//        offset in FP64, a rigorous culling cone, the supertile mask and
 //        per-block supertile counts
 //   scan_kernel        exclusive scan of those counts per supertile
+//   bases_kernel       supertile list bases, padded to 64-entry chunks
 //   scatter_kernel     stable compaction of Gaussian ids into supertile lists
 //                      (ascending id within a list: the summation order is fixed)
-//   tile_build_kernel  one wave per tile: filter the supertile list against the
-//        tile cone, then for every (texel, Gaussian) pair evaluate Eq. 3 on the
-//        shells where the erf ramps, add the per-shell increments in LDS,
-//        prefix over shells, T = exp(-tau) (Eq. 4), shell-major store.
+//   tile_mask_kernel   each list entry against the <= 64 tiles of its supertile,
+//                      transposed into one 64-bit hit word per (tile, chunk)
+//   tile_build_kernel  one wave per tile: walk its hit words; for every
+//        (texel, Gaussian) pair evaluate Eq. 3 on the shells where the erf
+//        ramps and add the per-shell increments in LDS; prefix over shells,
+//        T = exp(-tau) (Eq. 4), shell-major store.
 
 #include "dgsm_device.hpp"
 #include "dgsm_host.hpp"
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(64) void tile_cone_kernel(Geom g, float4* __restric
 // of (angle to the tile axis + tile half-angle).
 __global__ __launch_bounds__(64) void super_cone_kernel(Geom g, const float4* __restrict__ tcone,
                                                         float4* __restrict__ scone) {
-    const int s = threadIdx.x;
+    const int s = blockIdx.x * 64 + threadIdx.x;
     if (s >= g.S) return;
     const int sy = s / g.SGW, sx = s - sy * g.SGW;
     const int ty0 = sy * g.STH, ty1 = min(ty0 + g.STH, g.TH);
@@ -85,25 +88,47 @@ __global__ __launch_bounds__(64) void super_cone_kernel(Geom g, const float4* __
 }
 
 // ---------------------------------------------------------------------------
-// Per-Gaussian preprocess + supertile mask + per-block counts
+// Workspace slices
 // ---------------------------------------------------------------------------
 
 // Pointers into one light's slice of the workspace.
 struct LightWs {
-    int* totals;       // [64] list length per supertile
+    int* totals;       // [kMaxSuper] list length per supertile
+    int* lbase;        // [kMaxSuper + 1] list base per supertile, multiples of 64
     GRec* rec;         // [n]
     float4* cone;      // [n]
-    uint64_t* mask;    // [n]
+    uint64_t* mask;    // [n][kMaskWords] supertile masks
     int* counts;       // [S][nb] per-block counts, scanned in place
-    int* lists;        // [n * S] supertile lists, concatenated in supertile order
+    int* lists;        // [cap] supertile lists, 64-entry chunks
+    uint64_t* bits;    // [cap] per supertile: [tile][chunk] hit words
 };
 
 __host__ __device__ inline LightWs light_ws(unsigned char* ws, const BuildLayout& L, int l) {
     unsigned char* b = ws + L.light0 + (size_t)l * L.light_stride;
-    return LightWs{reinterpret_cast<int*>(b + L.totals), reinterpret_cast<GRec*>(b + L.rec),
-                   reinterpret_cast<float4*>(b + L.cone), reinterpret_cast<uint64_t*>(b + L.mask),
-                   reinterpret_cast<int*>(b + L.counts), reinterpret_cast<int*>(b + L.lists)};
+    return LightWs{reinterpret_cast<int*>(b + L.totals), reinterpret_cast<int*>(b + L.lbase),
+                   reinterpret_cast<GRec*>(b + L.rec), reinterpret_cast<float4*>(b + L.cone),
+                   reinterpret_cast<uint64_t*>(b + L.mask), reinterpret_cast<int*>(b + L.counts),
+                   reinterpret_cast<int*>(b + L.lists), reinterpret_cast<uint64_t*>(b + L.bits)};
 }
+
+// Tiles of supertile s: origin, extent and local index t = (ty-ty0)*ntx + (tx-tx0).
+struct SuperSpan {
+    int ty0, tx0, nty, ntx;
+};
+
+__host__ __device__ inline SuperSpan super_span(const Geom& g, int s) {
+    const int sy = s / g.SGW, sx = s - sy * g.SGW;
+    SuperSpan r;
+    r.ty0 = sy * g.STH;
+    r.tx0 = sx * g.STW;
+    r.nty = min(g.STH, g.TH - r.ty0);
+    r.ntx = min(g.STW, g.TW - r.tx0);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Per-Gaussian preprocess + supertile mask + per-block counts
+// ---------------------------------------------------------------------------
 
 struct PrepArgs {
     const float* mean;
@@ -181,19 +206,20 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
         }
         W.cone[i] = cone;
     }
-    uint64_t m = 0;
+    uint64_t m[kMaskWords] = {0, 0, 0, 0};
     for (int s = 0; s < a.S; ++s) {
         const bool b = in && cones_touch(cone, scone[s]);
-        m |= (uint64_t)b << s;
+        m[s >> 6] |= (uint64_t)b << (s & 63);
         const uint64_t bal = __ballot(b);
         if (lane == 0) wcnt[w][s] = __popcll(bal);
     }
-    if (in) W.mask[i] = m;
+    if (in)
+        for (int q = 0; q < kMaskWords; ++q) W.mask[(size_t)i * kMaskWords + q] = m[q];
     __syncthreads();
-    if (tid < a.S) {
+    for (int s = tid; s < a.S; s += kPrepThreads) {
         int c = 0;
-        for (int ww = 0; ww < kPrepThreads / kWave; ++ww) c += wcnt[ww][tid];
-        W.counts[(size_t)tid * a.lay.nb + blockIdx.x] = c;
+        for (int ww = 0; ww < kPrepThreads / kWave; ++ww) c += wcnt[ww][s];
+        W.counts[(size_t)s * a.lay.nb + blockIdx.x] = c;
     }
 }
 
@@ -201,31 +227,48 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
 // Exclusive scan of the per-block counts, one workgroup per (supertile, light)
 // ---------------------------------------------------------------------------
 
+// Inclusive scan of one value per thread over a 256-thread block.
+__device__ inline int block_scan_incl(int v, int* wsum) {
+    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(x, o, kWave);
+        if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wsum[w] = x;
+    __syncthreads();
+    for (int ww = 0; ww < w; ++ww) x += wsum[ww];
+    return x;
+}
+
 __global__ __launch_bounds__(256) void scan_kernel(unsigned char* ws, BuildLayout lay) {
     __shared__ int wsum[4];
     const LightWs W = light_ws(ws, lay, blockIdx.y);
-    const int s = blockIdx.x, tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    const int s = blockIdx.x, tid = threadIdx.x;
     const int nb = lay.nb;
     int* c = W.counts + (size_t)s * nb;
     int carry = 0;
     for (int base = 0; base < nb; base += 256) {
         const int idx = base + tid;
         const int v = idx < nb ? c[idx] : 0;
-        int x = v;   // inclusive wave scan
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const int y = __shfl_up(x, o, kWave);
-            if (lane >= o) x += y;
-        }
-        if (lane == kWave - 1) wsum[w] = x;
-        __syncthreads();
-        int pre = carry;
-        for (int ww = 0; ww < w; ++ww) pre += wsum[ww];
-        if (idx < nb) c[idx] = pre + x - v;
+        const int x = block_scan_incl(v, wsum);
+        if (idx < nb) c[idx] = carry + x - v;
         carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
         __syncthreads();
     }
     if (tid == 0) W.totals[s] = carry;
+}
+
+// List base of every supertile, each list padded to a multiple of 64 entries.
+__global__ __launch_bounds__(256) void bases_kernel(unsigned char* ws, BuildLayout lay, int S) {
+    __shared__ int wsum[4];
+    const LightWs W = light_ws(ws, lay, blockIdx.x);
+    const int s = threadIdx.x;
+    const int v = s < S ? (W.totals[s] + 63) & ~63 : 0;
+    const int x = block_scan_incl(v, wsum);
+    if (s < S) W.lbase[s] = x - v;
+    if (s == S - 1) W.lbase[S] = x;
 }
 
 // ---------------------------------------------------------------------------
@@ -238,26 +281,65 @@ __global__ __launch_bounds__(kPrepThreads) void scatter_kernel(unsigned char* ws
     __shared__ int wcnt[kPrepThreads / kWave][kMaxSuper];
     const LightWs W = light_ws(ws, lay, blockIdx.y);
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
-    if (tid < S) {
-        int b = 0;
-        for (int q = 0; q < tid; ++q) b += W.totals[q];
-        base_s[tid] = b + W.counts[(size_t)tid * lay.nb + blockIdx.x];
-    }
+    for (int s = tid; s < S; s += kPrepThreads) base_s[s] = W.lbase[s] + W.counts[(size_t)s * lay.nb + blockIdx.x];
     const int64_t i = (int64_t)blockIdx.x * kPrepThreads + tid;
-    const uint64_t m = i < n ? W.mask[i] : 0ull;
+    uint64_t m[kMaskWords] = {0, 0, 0, 0};
+    if (i < n)
+        for (int q = 0; q < kMaskWords; ++q) m[q] = W.mask[(size_t)i * kMaskWords + q];
     for (int s = 0; s < S; ++s) {
-        const uint64_t bal = __ballot((m >> s) & 1ull);
+        const uint64_t bal = __ballot((m[s >> 6] >> (s & 63)) & 1ull);
         if (lane == 0) wcnt[w][s] = __popcll(bal);
     }
     __syncthreads();
     for (int s = 0; s < S; ++s) {
-        const bool b = (m >> s) & 1ull;
+        const bool b = (m[s >> 6] >> (s & 63)) & 1ull;
         const uint64_t bal = __ballot(b);
         if (b) {
             int off = base_s[s];
             for (int ww = 0; ww < w; ++ww) off += wcnt[ww][s];
             W.lists[off + ballot_rank(bal)] = (int)i;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Level 2: tile hit words.  One wave per 64-entry chunk of a supertile list.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, BuildLayout lay, Geom g) {
+    __shared__ int sbase[kMaxSuper + 1];
+    __shared__ int stot[kMaxSuper];
+    const LightWs W = light_ws(ws, lay, blockIdx.y);
+    const float4* tcone = reinterpret_cast<const float4*>(ws + lay.tcone);
+    const int tid = threadIdx.x, lane = tid % kWave;
+    for (int s = tid; s <= g.S; s += 256) {
+        sbase[s] = W.lbase[s];
+        if (s < g.S) stot[s] = W.totals[s];
+    }
+    __syncthreads();
+    const int nchunks = sbase[g.S] / 64;
+    const int nwaves = gridDim.x * 4;
+    for (int c = blockIdx.x * 4 + tid / kWave; c < nchunks; c += nwaves) {
+        // supertile of this chunk: the last s with sbase[s] <= 64 c
+        int lo = 0, hi = g.S - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sbase[mid] <= 64 * c) lo = mid; else hi = mid - 1;
+        }
+        const int s = lo;
+        const int e = 64 * c + lane;
+        float4 cone = make_float4(0.f, 0.f, 1.f, -1.f);
+        if (e < sbase[s] + stot[s]) cone = W.cone[W.lists[e]];
+        const SuperSpan sp = super_span(g, s);
+        const int nt = sp.nty * sp.ntx;
+        uint64_t mine = 0;
+        for (int t = 0; t < nt; ++t) {
+            const int ty = sp.ty0 + t / sp.ntx, tx = sp.tx0 + t % sp.ntx;
+            const uint64_t bal = __ballot(cones_touch(cone, tcone[ty * g.TW + tx]));
+            if (lane == t) mine = bal;
+        }
+        const int c0 = sbase[s] / 64, ns = (sbase[s + 1] - sbase[s]) / 64;
+        if (lane < nt) W.bits[64 * (size_t)c0 + (size_t)lane * ns + (c - c0)] = mine;
     }
 }
 
@@ -306,10 +388,115 @@ __device__ inline RecRegs load_rec(ConstF4Ptr base, int gi) {
     return r;
 }
 
+__device__ inline int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ inline uint64_t readlane_u64(uint64_t v, int l) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline double readlane_d(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// Per-lane state of the tile build shared by every pair.
+struct TexelState {
+    double dx, dy, dz;       // texel direction, FP64
+    float fx, fy, fz;        // the same, FP32
+    bool valid;
+    int lane;
+    float lr0, kinv;         // shell coordinate of a radius: (log2 t - lr0) * kinv (geometric)
+    double shd[4];           // lane l holds t_{l + 64 r} in shd[r]
+    double ratio;            // t_{k+1} / t_k (geometric) or t_{k+1} - t_k (uniform)
+    int K;
+    bool geometric;
+    float pair_eps;
+    float* inc;              // LDS [K][64]
+};
+
+__device__ inline double shell_at(const TexelState& ts, int k) {
+    const int r = k >> 6, l = k & 63;
+    const double v = r == 0 ? ts.shd[0] : r == 1 ? ts.shd[1] : r == 2 ? ts.shd[2] : ts.shd[3];
+    return readlane_d(v, l);
+}
+
 // Shell index of a radius (fractional, unclamped); -1 for t <= 0.
-__device__ inline float shell_index(float t, const Geom& g, float lr0, float inv) {
-    if (g.spacing == DGSM_SHELLS_GEOMETRIC) return t > 0.f ? (__log2f(t) - lr0) * inv : -1.f;
-    return t * inv - 0.5f;
+__device__ inline float shell_index(float t, const TexelState& ts) {
+    if (ts.geometric) return t > 0.f ? (__log2f(t) - ts.lr0) * ts.kinv : -1.f;
+    return t * ts.kinv - 0.5f;
+}
+
+// Largest optical depth a pair may drop at either end of its erf ramp.
+constexpr float kRampEps = 1e-10f;
+
+// One (texel, Gaussian) pair for all 64 texels of the wave: Eq. 3 on the
+// shells where the erf ramps, as non-negative per-shell increments.
+template <bool STATS>
+__device__ inline void eval_pair(const RecRegs& r, const TexelState& s, unsigned long long& n_act,
+                                 unsigned long long& n_ramp) {
+    // Ray-line geometry in FP64: v = m x d, t_e = -(m . d).
+    const double vxd = r.my * s.dz - r.mz * s.dy;
+    const double vyd = r.mz * s.dx - r.mx * s.dz;
+    const double vzd = r.mx * s.dy - r.my * s.dx;
+    const double te = -(r.mx * s.dx + r.my * s.dy + r.mz * s.dz);
+    const float vx = (float)vxd, vy = (float)vyd, vz = (float)vzd;
+    // a = |W d|^2 (Eq. 2);  c - b^2/a = |adj(A)^(1/2) (m x d)|^2 / a
+    const float wd0 = r.w[0] * s.fx + r.w[1] * s.fy + r.w[2] * s.fz;
+    const float wd1 = r.w[3] * s.fx + r.w[4] * s.fy + r.w[5] * s.fz;
+    const float wd2 = r.w[6] * s.fx + r.w[7] * s.fy + r.w[8] * s.fz;
+    const float a = wd0 * wd0 + wd1 * wd1 + wd2 * wd2;
+    const float cv0 = r.c[0] * vx + r.c[1] * vy + r.c[2] * vz;
+    const float cv1 = r.c[3] * vx + r.c[4] * vy + r.c[5] * vz;
+    const float cv2 = r.c[6] * vx + r.c[7] * vy + r.c[8] * vz;
+    const float ra = __builtin_amdgcn_rcpf(a);
+    const float e0 = (cv0 * cv0 + cv1 * cv1 + cv2 * cv2) * ra;
+    const float rsa = __builtin_amdgcn_rsqf(a);
+    // prefactor of Eq. 3 times beta: beta sqrt(pi / (2a)) exp(-e0 / 2)
+    const float P0 = r.bp * rsa * __expf(-0.5f * e0);
+    const bool act = s.valid && (P0 + P0 > s.pair_eps);
+    const uint64_t abal = __ballot(act);
+    if (abal == 0ull) return;
+    if (STATS) n_act += __popcll(abal);
+    // Distance along the ray of the Mahalanobis-closest point:
+    // t* = -b/a = t_e - (W d).(W p)/a with p = d x v the perpendicular offset.
+    const float p0 = s.fy * vz - s.fz * vy, p1 = s.fz * vx - s.fx * vz, p2 = s.fx * vy - s.fy * vx;
+    const float wp0 = r.w[0] * p0 + r.w[1] * p1 + r.w[2] * p2;
+    const float wp1 = r.w[3] * p0 + r.w[4] * p1 + r.w[5] * p2;
+    const float wp2 = r.w[6] * p0 + r.w[7] * p1 + r.w[8] * p2;
+    const float corr = (wd0 * wp0 + wd1 * wp1 + wd2 * wp2) * ra;
+    const float sa = a * rsa * 0.70710678118654752f;      // sqrt(a / 2)
+    const float ts = (float)te - corr;                      // t* (shell range, erf at t = 0)
+    // Ramp half-width z: P0 erfc(z) <= P0 exp(-z^2) <= kRampEps.
+    const float z = sqrtf(fmaxf(__logf(P0 * (1.f / kRampEps)), 0.34f));
+    const float xs = -sa * ts;                              // erf argument at t = 0
+    float Ep = -1.f;
+    if (xs > -z) Ep = erf_nr(xs);
+    int ka = s.K, kb = -1;
+    if (act) {
+        const float half = z * __builtin_amdgcn_rcpf(sa);
+        const float klo = fminf(shell_index(ts - half, s), (float)s.K);
+        const float khi = fmaxf(shell_index(ts + half, s), -1.f);
+        // first shell past the ramp start, last shell at or past its end
+        ka = klo < 0.f ? 0 : (int)klo + 1;
+        kb = khi > (float)(s.K - 2) ? s.K - 1 : max(0, (int)khi + 1);
+    }
+    const int kmin = wave_min(ka), kmax = wave_max(kb);
+    if (kmin > kmax) return;
+    if (STATS) n_ramp += (unsigned long long)__popcll(abal) * (kmax - kmin + 1);
+    double tk = shell_at(s, kmin);
+    for (int k = kmin; k <= kmax; ++k) {
+        const float x = sa * ((float)(tk - te) + corr);
+        const float E = fmaxf(erf_nr(x), Ep);        // keep the increments non-negative
+        const float dI = P0 * (E - Ep);
+        Ep = E;
+        if (act && dI > 0.f)
+            __hip_atomic_fetch_add(s.inc + k * kWave + s.lane, dI, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        tk = s.geometric ? tk * s.ratio : tk + s.ratio;
+    }
 }
 
 template <typename OutT, bool STATS>
@@ -317,135 +504,94 @@ __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const Geom& g = p.g;
     const int K = g.K;
-    float* inc = reinterpret_cast<float*>(smem);                   // [K][64] per-shell increments
-    float2* shell = reinterpret_cast<float2*>(inc + (size_t)K * kWave);   // [K] t_k as hi + lo
-    int* hits = reinterpret_cast<int*>(shell + K);                  // [64]
+    float* inc = reinterpret_cast<float*>(smem);      // [K][64] per-shell increments
 
     const int lane = threadIdx.x;
     const int tile = blockIdx.x;
     const int light = blockIdx.y;
     const LightWs W = light_ws(p.ws, p.lay, light);
-    const float4* tcone = reinterpret_cast<const float4*>(p.ws + p.lay.tcone);
     const int ty = tile / g.TW, tx = tile - ty * g.TW;
     const int py = ty * kTile + (lane >> 3), px = tx * kTile + (lane & 7);
-    const bool valid = py < g.H && px < g.W;
-    double dx, dy, dz;
-    texel_dir(min(py, g.H - 1), min(px, g.W - 1), g.H, g.W, dx, dy, dz);
-    const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
 
-    for (int k = lane; k < K; k += kWave) {
-        const double t = shell_radius(k, K, g.spacing, g.r0, g.r1);
-        const float hi = (float)t;
-        shell[k] = make_float2(hi, (float)(t - (double)hi));
+    TexelState st;
+    st.valid = py < g.H && px < g.W;
+    st.lane = lane;
+    texel_dir(min(py, g.H - 1), min(px, g.W - 1), g.H, g.W, st.dx, st.dy, st.dz);
+    st.fx = (float)st.dx; st.fy = (float)st.dy; st.fz = (float)st.dz;
+    st.K = K;
+    st.geometric = g.spacing == DGSM_SHELLS_GEOMETRIC;
+    st.pair_eps = p.pair_eps;
+    st.inc = inc;
+    for (int r = 0; r < 4; ++r) {
+        const int k = lane + 64 * r;
+        st.shd[r] = k < K ? shell_radius(k, K, g.spacing, g.r0, g.r1) : 0.0;
+    }
+    if (st.geometric) {
+        st.lr0 = __log2f(g.r0);
+        st.kinv = (float)(K - 1) / __log2f(g.r1 / g.r0);
+        st.ratio = pow((double)g.r1 / (double)g.r0, 1.0 / (double)(K - 1));
+    } else {
+        st.lr0 = 0.f;
+        st.kinv = (float)K / g.r1;
+        st.ratio = (double)g.r1 / (double)K;
     }
     for (int q = lane; q < K * kWave; q += kWave) inc[q] = 0.f;
-    float lr0, inv;
-    if (g.spacing == DGSM_SHELLS_GEOMETRIC) {
-        lr0 = __log2f(g.r0);
-        inv = (float)(K - 1) / __log2f(g.r1 / g.r0);
-    } else {
-        lr0 = 0.f;
-        inv = (float)K / g.r1;
-    }
 
+    // this tile's hit words: contiguous ns words, one per 64-entry chunk of the supertile list
     const int s = (ty / g.STH) * g.SGW + (tx / g.STW);
-    int base = 0;
-    for (int q = 0; q < s; ++q) base += W.totals[q];
-    const int cnt = W.totals[s];
-    const float4 tc = tcone[tile];
+    const SuperSpan sp = super_span(g, s);
+    const int t_local = (ty - sp.ty0) * sp.ntx + (tx - sp.tx0);
+    const int lb0 = W.lbase[s], lb1 = W.lbase[s + 1];
+    const int c0 = lb0 / 64, ns = (lb1 - lb0) / 64;
+    const uint64_t* words = W.bits + 64 * (size_t)c0 + (size_t)t_local * ns;
+    const int* list = W.lists + lb0;
     const ConstF4Ptr rec = (ConstF4Ptr)(const void*)W.rec;
     unsigned long long n_hits = 0, n_act = 0, n_ramp = 0;
     __syncthreads();
 
-    for (int c0 = 0; c0 < cnt; c0 += kWave) {
-        const int idx = c0 + lane;
-        bool hit = false;
-        int gid = 0;
-        if (idx < cnt) {
-            gid = W.lists[base + idx];
-            hit = cones_touch(W.cone[gid], tc);
-        }
-        const uint64_t bal = __ballot(hit);
-        if (hit) hits[ballot_rank(bal)] = gid;
-        const int nh = __popcll(bal);
-        if (STATS) n_hits += nh;
-        __syncthreads();
-        for (int h = 0; h < nh; ++h) {
-            const int gi = __builtin_amdgcn_readfirstlane(hits[h]);
-            const RecRegs r = load_rec(rec, gi);
-            // Ray-line geometry in FP64: v = m x d, t_e = -(m . d).
-            const double vxd = r.my * dz - r.mz * dy;
-            const double vyd = r.mz * dx - r.mx * dz;
-            const double vzd = r.mx * dy - r.my * dx;
-            const double te = -(r.mx * dx + r.my * dy + r.mz * dz);
-            const float vx = (float)vxd, vy = (float)vyd, vz = (float)vzd;
-            // a = |W d|^2 (Eq. 2);  c - b^2/a = |adj(A)^(1/2) (m x d)|^2 / a
-            const float wd0 = r.w[0] * fx + r.w[1] * fy + r.w[2] * fz;
-            const float wd1 = r.w[3] * fx + r.w[4] * fy + r.w[5] * fz;
-            const float wd2 = r.w[6] * fx + r.w[7] * fy + r.w[8] * fz;
-            const float a = wd0 * wd0 + wd1 * wd1 + wd2 * wd2;
-            const float cv0 = r.c[0] * vx + r.c[1] * vy + r.c[2] * vz;
-            const float cv1 = r.c[3] * vx + r.c[4] * vy + r.c[5] * vz;
-            const float cv2 = r.c[6] * vx + r.c[7] * vy + r.c[8] * vz;
-            const float ra = __builtin_amdgcn_rcpf(a);
-            const float e0 = (cv0 * cv0 + cv1 * cv1 + cv2 * cv2) * ra;
-            const float rsa = __builtin_amdgcn_rsqf(a);
-            // prefactor of Eq. 3 times beta: beta sqrt(pi / (2a)) exp(-e0 / 2)
-            const float P0 = r.bp * rsa * __expf(-0.5f * e0);
-            const bool act = valid && (P0 + P0 > p.pair_eps);
-            const uint64_t abal = __ballot(act);
-            if (abal == 0ull) continue;
-            if (STATS) n_act += __popcll(abal);
-            // Distance along the ray of the Mahalanobis-closest point:
-            // t* = -b/a = t_e - (W d).(W p)/a with p = d x v the perpendicular offset.
-            const float p0 = fy * vz - fz * vy, p1 = fz * vx - fx * vz, p2 = fx * vy - fy * vx;
-            const float wp0 = r.w[0] * p0 + r.w[1] * p1 + r.w[2] * p2;
-            const float wp1 = r.w[3] * p0 + r.w[4] * p1 + r.w[5] * p2;
-            const float wp2 = r.w[6] * p0 + r.w[7] * p1 + r.w[8] * p2;
-            const float corr = (wd0 * wp0 + wd1 * wp1 + wd2 * wp2) * ra;
-            const float th = (float)te;
-            const float tl = (float)(te - (double)th);
-            const float sa = a * rsa * 0.70710678118654752f;      // sqrt(a / 2)
-            const float ts = (th - corr) + tl;                      // t*
-            const float xs = -sa * ts;                              // erf argument at t = 0
-            float Ep = -1.f;
-            if (xs > -kZc) Ep = erff(xs);
-            int ka = K, kb = -1;
-            if (act) {
-                // shells whose erf argument lies in (-kZc, kZc), widened by one on each side
-                const float half = kZc * __builtin_amdgcn_rcpf(sa);
-                const float klo = fminf(shell_index(ts - half, g, lr0, inv), (float)K);
-                const float khi = fmaxf(shell_index(ts + half, g, lr0, inv), -1.f);
-                ka = klo < 1.f ? 0 : (int)klo - 1;
-                kb = khi > (float)(K - 3) ? K - 1 : max(0, (int)khi + 2);
-            }
-            const int kmin = wave_min(ka), kmax = wave_max(kb);
-            if (STATS && kmax >= kmin) n_ramp += (unsigned long long)__popcll(abal) * (kmax - kmin + 1);
-            for (int k = kmin; k <= kmax; ++k) {
-                const float2 tk = shell[k];
-                const float x = sa * (((tk.x - th) + (tk.y - tl)) + corr);
-                const float E = fmaxf(erff(x), Ep);     // keep the increments non-negative
-                const float dI = P0 * (E - Ep);
-                Ep = E;
-                if (act && dI > 0.f)
-                    __hip_atomic_fetch_add(inc + k * kWave + lane, dI, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    for (int gbase = 0; gbase < ns; gbase += 64) {
+        const uint64_t wv = gbase + lane < ns ? words[gbase + lane] : 0ull;
+        uint64_t nz = __ballot(wv != 0ull);
+        if (nz == 0ull) continue;
+        int j = __builtin_ctzll(nz);
+        int gv = list[64 * (gbase + j) + lane];
+        while (nz) {
+            j = __builtin_ctzll(nz);
+            nz &= nz - 1;
+            uint64_t word = readlane_u64(wv, j);
+            const int gcur = gv;
+            if (nz) gv = list[64 * (gbase + __builtin_ctzll(nz)) + lane];   // next chunk's ids, in flight
+            if (STATS) n_hits += __popcll(word);
+            int b = __builtin_ctzll(word);
+            word &= word - 1;
+            RecRegs cur = load_rec(rec, readlane_i(gcur, b));
+            for (;;) {
+                const bool more = word != 0ull;
+                RecRegs nxt;
+                if (more) {                                 // next record, in flight
+                    b = __builtin_ctzll(word);
+                    word &= word - 1;
+                    nxt = load_rec(rec, readlane_i(gcur, b));
+                }
+                eval_pair<STATS>(cur, st, n_act, n_ramp);
+                if (!more) break;
+                cur = nxt;
             }
         }
-        __syncthreads();
     }
 
     if (STATS) {
-        const unsigned long long nvalid = __popcll(__ballot(valid));
+        const unsigned long long nvalid = __popcll(__ballot(st.valid));
         if (lane == 0) {
             atomicAdd(p.stats + 0, n_hits * nvalid);
             atomicAdd(p.stats + 1, n_act);
             atomicAdd(p.stats + 2, n_ramp);
-            atomicAdd(p.stats + 3, (unsigned long long)cnt);
+            atomicAdd(p.stats + 3, (unsigned long long)(lb1 - lb0));
         }
     }
+    __syncthreads();
 
-    if (valid) {
+    if (st.valid) {
         const size_t plane = (size_t)g.H * g.W;
         const size_t off = (size_t)light * K * plane + (size_t)py * g.W + px;
         const float* bt = p.base_tau ? p.base_tau + off : nullptr;
@@ -482,24 +628,25 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
         return o;
     };
     L.nb = (int)((n + kPrepThreads - 1) / kPrepThreads);
+    L.cap = (size_t)n * g.S + 64 * (size_t)g.S;
     L.tcone = take((size_t)g.ntiles * sizeof(float4));
     L.scone = take((size_t)kMaxSuper * sizeof(float4));
     L.light0 = off;
     off = 0;
     L.totals = take((size_t)kMaxSuper * sizeof(int));
+    L.lbase = take((size_t)(kMaxSuper + 1) * sizeof(int));
     L.rec = take((size_t)n * sizeof(GRec));
     L.cone = take((size_t)n * sizeof(float4));
-    L.mask = take((size_t)n * sizeof(uint64_t));
+    L.mask = take((size_t)n * kMaskWords * sizeof(uint64_t));
     L.counts = take((size_t)g.S * (size_t)L.nb * sizeof(int));
-    L.lists = take((size_t)n * (size_t)g.S * sizeof(int));
+    L.lists = take(L.cap * sizeof(int));
+    L.bits = take(L.cap * sizeof(uint64_t));
     L.light_stride = off;
     L.total = L.light0 + (size_t)n_lights * L.light_stride;
     return L;
 }
 
-size_t tile_smem_bytes(const Geom& g) {
-    return (size_t)g.K * kWave * sizeof(float) + (size_t)g.K * sizeof(float2) + kWave * sizeof(int);
-}
+size_t tile_smem_bytes(const Geom& g) { return (size_t)g.K * kWave * sizeof(float); }
 
 template <typename OutT, bool STATS>
 static hipError_t launch_tile(const TileArgs& ta, int n_lights, hipStream_t st) {
@@ -519,7 +666,7 @@ dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, 
     float4* scone = reinterpret_cast<float4*>(ws + L.scone);
     tile_cone_kernel<<<(g.ntiles + 63) / 64, 64, 0, st>>>(g, tcone);
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
-    super_cone_kernel<<<1, 64, 0, st>>>(g, tcone, scone);
+    super_cone_kernel<<<(g.S + 63) / 64, 64, 0, st>>>(g, tcone, scone);
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     if (gs.n > 0) {
         PrepArgs pa{gs.mean, gs.scale, gs.rot, gs.opacity, gs.n, lights.pos, lights.kappa, cull_eps,
@@ -529,8 +676,15 @@ dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, 
     }
     scan_kernel<<<dim3(g.S, lights.n), 256, 0, st>>>(ws, L);
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    bases_kernel<<<lights.n, 256, 0, st>>>(ws, L, g.S);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     if (gs.n > 0) {
         scatter_kernel<<<dim3(L.nb, lights.n), kPrepThreads, 0, st>>>(ws, L, gs.n, g.S);
+        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+        // enough waves to cover the typical chunk count; each strides over the rest
+        const int64_t est = ((int64_t)gs.n * 2 + 64 * (int64_t)g.S) / 64;
+        const int blocks = (int)(est / 4 + 1 < 4096 ? est / 4 + 1 : 4096);
+        tile_mask_kernel<<<dim3(blocks, lights.n), 256, 0, st>>>(ws, L, g);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }
     return DGSM_OK;
@@ -559,7 +713,7 @@ static dgsm_status check_build_args(const dgsm_lights_t* lights, const dgsm_gaus
     if ((st = validate_lights(lights)) != DGSM_OK) return st;
     if ((st = validate_gaussians(gaussians)) != DGSM_OK) return st;
     const Geom g = make_geom(*desc);
-    if (gaussians->n * (int64_t)g.S >= (int64_t)INT32_MAX) return DGSM_EUNSUPPORTED;
+    if ((gaussians->n + 64) * (int64_t)g.S >= (int64_t)INT32_MAX) return DGSM_EUNSUPPORTED;
     return DGSM_OK;
 }
 

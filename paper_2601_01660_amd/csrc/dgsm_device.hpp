@@ -11,12 +11,15 @@ namespace dgsm {
 
 constexpr int kWave = 64;
 constexpr int kTile = 8;          // atlas tile side in texels (Sec. 3.2 buckets 8x8 tiles)
-constexpr int kMaxSuper = 64;     // supertiles per light (one 64-bit mask per Gaussian)
+constexpr int kSuperTiles = 8;    // supertile side in tiles (a supertile holds <= 64 tiles)
+constexpr int kMaxSuper = 256;    // supertiles per light: atlases up to 1024 x 1024 texels
+constexpr int kMaskWords = kMaxSuper / 64;
 constexpr int kPrepThreads = 256;
-constexpr float kZc = 4.5f;       // erf is saturated beyond |x| > 4.5 (erfc(4.5) < 2e-10)
+constexpr int kMaxAtlasSide = kTile * kSuperTiles * 16;   // 1024
 
-// Tiling of one atlas: tiles of kTile x kTile texels, grouped into at most
-// 8 x 8 supertiles (the coarse level of the two-level light-space binning).
+// Tiling of one atlas: tiles of kTile x kTile texels, grouped into supertiles
+// of up to kSuperTiles x kSuperTiles tiles (the coarse level of the two-level
+// light-space binning).
 struct Geom {
     int H, W, K, spacing, dtype;
     float r0, r1;
@@ -33,11 +36,9 @@ inline Geom make_geom(const dgsm_atlas_desc_t& d) {
     g.r0 = d.r0; g.r1 = d.r1;
     g.TH = (d.H + kTile - 1) / kTile;
     g.TW = (d.W + kTile - 1) / kTile;
-    g.SGH = g.TH < 8 ? g.TH : 8;
-    g.SGW = g.TW < 8 ? g.TW : 8;
-    g.STH = (g.TH + g.SGH - 1) / g.SGH;
-    g.STW = (g.TW + g.SGW - 1) / g.SGW;
-    g.SGH = (g.TH + g.STH - 1) / g.STH;   // drop empty supertile rows/cols
+    g.STH = g.TH < kSuperTiles ? g.TH : kSuperTiles;
+    g.STW = g.TW < kSuperTiles ? g.TW : kSuperTiles;
+    g.SGH = (g.TH + g.STH - 1) / g.STH;
     g.SGW = (g.TW + g.STW - 1) / g.STW;
     g.S = g.SGH * g.SGW;
     g.ntiles = g.TH * g.TW;
@@ -95,24 +96,33 @@ __device__ inline double shell_radius(int k, int K, int spacing, float r0, float
     return ((double)k + 0.5) * (double)r1 / (double)K;
 }
 
-template <typename T>
-__device__ inline T wave_min(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        T w = __shfl_xor(v, o, kWave);
-        v = w < v ? w : v;
-    }
-    return v;
-}
+extern "C" __device__ int __ockl_wfred_min_i32(int);
+extern "C" __device__ int __ockl_wfred_max_i32(int);
 
-template <typename T>
-__device__ inline T wave_max(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        T w = __shfl_xor(v, o, kWave);
-        v = w > v ? w : v;
-    }
-    return v;
+// Wave-wide integer min / max (DPP row reductions); call with all lanes active.
+__device__ inline int wave_min(int v) { return __ockl_wfred_min_i32(v); }
+__device__ inline int wave_max(int v) { return __ockl_wfred_max_i32(v); }
+
+// erf(x) from the Chebyshev fit of erfc of Numerical Recipes (Press et al.,
+// 2nd ed., Sec. 6.2, "erfcc"): erfc(z) = t exp(-z^2 + P(t)), t = 1/(1 + z/2),
+// fractional error below 1.2e-7 for z >= 0.  One branch-free evaluation: a
+// reciprocal, a degree-9 Horner chain and an exponential.  Absolute error of
+// the returned erf is below 2e-7 everywhere and it saturates to +-1 exactly.
+__device__ inline float erf_nr(float x) {
+    const float z = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.f));
+    float p = 0.17087277f;
+    p = fmaf(t, p, -0.82215223f);
+    p = fmaf(t, p, 1.48851587f);
+    p = fmaf(t, p, -1.13520398f);
+    p = fmaf(t, p, 0.27886807f);
+    p = fmaf(t, p, -0.18628806f);
+    p = fmaf(t, p, 0.09678418f);
+    p = fmaf(t, p, 0.37409196f);
+    p = fmaf(t, p, 1.00002368f);
+    p = fmaf(t, p, -1.26551223f);
+    const float ec = t * __expf(fmaf(-z, z, p));
+    return copysignf(1.f - ec, x);
 }
 
 __device__ inline int lane_id() { return __lane_id(); }

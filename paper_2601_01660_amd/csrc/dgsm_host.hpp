@@ -10,12 +10,12 @@
 
 namespace dgsm {
 
-constexpr int kMaxShells = 512;
+constexpr int kMaxShells = 256;      // 4 shells per lane of a wave
 
 inline dgsm_status validate_desc(const dgsm_atlas_desc_t* d) {
     if (!d) return DGSM_EINVAL;
     if (d->H < 2 || d->W < 2 || (d->H & 1) || (d->W & 1)) return DGSM_EINVAL;
-    if (d->H > 16384 || d->W > 16384) return DGSM_EINVAL;
+    if (d->H > kMaxAtlasSide || d->W > kMaxAtlasSide) return DGSM_EINVAL;
     if (d->K < 2 || d->K > kMaxShells) return DGSM_EINVAL;
     if (d->spacing != DGSM_SHELLS_UNIFORM && d->spacing != DGSM_SHELLS_GEOMETRIC) return DGSM_EINVAL;
     if (!(d->r1 > 0.f)) return DGSM_EINVAL;
@@ -41,10 +41,12 @@ inline dgsm_status validate_gaussians(const dgsm_gaussians_t* g) {
 // Workspace of the build: shared atlas geometry, then one slice per light.
 struct BuildLayout {
     int nb;                  // preprocess blocks (256 Gaussians each)
-    size_t tcone, scone;     // absolute offsets: tile cones [ntiles], supertile cones [64]
+    size_t cap;              // list / bitmap capacity per light (entries)
+    size_t tcone, scone;     // absolute offsets: tile cones [ntiles], supertile cones [kMaxSuper]
     size_t light0;           // absolute offset of light 0's slice
     size_t light_stride;     // bytes per light slice
-    size_t totals, rec, cone, mask, counts, lists;   // offsets inside a light slice
+    // offsets inside a light slice
+    size_t totals, lbase, rec, cone, mask, counts, lists, bits;
     size_t total;            // bytes for all lights
 };
 
