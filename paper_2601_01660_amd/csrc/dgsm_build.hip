@@ -409,7 +409,7 @@ struct TexelState {
     bool valid;
     int lane;
     float lr0, kinv;         // shell coordinate of a radius: (log2 t - lr0) * kinv (geometric)
-    double shd[4];           // lane l holds t_{l + 64 r} in shd[r]
+    double shd0, shd1, shd2, shd3;   // lane l holds t_l, t_{l+64}, t_{l+128}, t_{l+192}
     double ratio;            // t_{k+1} / t_k (geometric) or t_{k+1} - t_k (uniform)
     int K;
     bool geometric;
@@ -418,9 +418,11 @@ struct TexelState {
 };
 
 __device__ inline double shell_at(const TexelState& ts, int k) {
-    const int r = k >> 6, l = k & 63;
-    const double v = r == 0 ? ts.shd[0] : r == 1 ? ts.shd[1] : r == 2 ? ts.shd[2] : ts.shd[3];
-    return readlane_d(v, l);
+    const int l = k & 63;
+    if (k < 64) return readlane_d(ts.shd0, l);       // k is wave-uniform: scalar branches
+    if (k < 128) return readlane_d(ts.shd1, l);
+    if (k < 192) return readlane_d(ts.shd2, l);
+    return readlane_d(ts.shd3, l);
 }
 
 // Shell index of a radius (fractional, unclamped); -1 for t <= 0.
@@ -435,7 +437,7 @@ constexpr float kRampEps = 1e-10f;
 // One (texel, Gaussian) pair for all 64 texels of the wave: Eq. 3 on the
 // shells where the erf ramps, as non-negative per-shell increments.
 template <bool STATS>
-__device__ inline void eval_pair(const RecRegs& r, const TexelState& s, unsigned long long& n_act,
+__device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r, const TexelState& s, unsigned long long& n_act,
                                  unsigned long long& n_ramp) {
     // Ray-line geometry in FP64: v = m x d, t_e = -(m . d).
     const double vxd = r.my * s.dz - r.mz * s.dy;
@@ -522,10 +524,10 @@ __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
     st.geometric = g.spacing == DGSM_SHELLS_GEOMETRIC;
     st.pair_eps = p.pair_eps;
     st.inc = inc;
-    for (int r = 0; r < 4; ++r) {
-        const int k = lane + 64 * r;
-        st.shd[r] = k < K ? shell_radius(k, K, g.spacing, g.r0, g.r1) : 0.0;
-    }
+    st.shd0 = lane < K ? shell_radius(lane, K, g.spacing, g.r0, g.r1) : 0.0;
+    st.shd1 = lane + 64 < K ? shell_radius(lane + 64, K, g.spacing, g.r0, g.r1) : 0.0;
+    st.shd2 = lane + 128 < K ? shell_radius(lane + 128, K, g.spacing, g.r0, g.r1) : 0.0;
+    st.shd3 = lane + 192 < K ? shell_radius(lane + 192, K, g.spacing, g.r0, g.r1) : 0.0;
     if (st.geometric) {
         st.lr0 = __log2f(g.r0);
         st.kinv = (float)(K - 1) / __log2f(g.r1 / g.r0);
