@@ -402,6 +402,22 @@ __device__ inline double readlane_d(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
+// Per-shell increments are accumulated in LDS as 64-bit fixed point with 32
+// fractional bits.  Integer addition is associative, so the four waves of a
+// tile may add in any interleaving and the result is still bitwise
+// reproducible.  Each increment is truncated to a multiple of 2^-32.
+constexpr float kFixScale = 4294967296.f;   // 2^32
+
+__device__ inline unsigned long long to_fixed(float v) {
+    const unsigned int hi = (unsigned int)v;                           // v >= 0, truncates
+    const unsigned int lo = (unsigned int)((v - (float)hi) * kFixScale);   // exact product, < 2^32
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ inline double from_fixed(unsigned long long q) {
+    return (double)(q >> 32) + (double)(unsigned int)q * (1.0 / 4294967296.0);
+}
+
 // Per-lane state of the tile build shared by every pair.
 struct TexelState {
     double dx, dy, dz;       // texel direction, FP64
@@ -414,7 +430,7 @@ struct TexelState {
     int K;
     bool geometric;
     float pair_eps;
-    float* inc;              // LDS [K][64]
+    unsigned long long* inc; // LDS [K][64], fixed point
 };
 
 __device__ inline double shell_at(const TexelState& ts, int k) {
@@ -437,8 +453,9 @@ constexpr float kRampEps = 1e-10f;
 // One (texel, Gaussian) pair for all 64 texels of the wave: Eq. 3 on the
 // shells where the erf ramps, as non-negative per-shell increments.
 template <bool STATS>
-__device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r, const TexelState& s, unsigned long long& n_act,
-                                 unsigned long long& n_ramp) {
+__device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r, const TexelState& s,
+                                                                unsigned long long& n_act,
+                                                                unsigned long long& n_ramp) {
     // Ray-line geometry in FP64: v = m x d, t_e = -(m . d).
     const double vxd = r.my * s.dz - r.mz * s.dy;
     const double vyd = r.mz * s.dx - r.mx * s.dz;
@@ -495,20 +512,71 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
         const float dI = P0 * (E - Ep);
         Ep = E;
         if (act && dI > 0.f)
-            __hip_atomic_fetch_add(s.inc + k * kWave + s.lane, dI, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(s.inc + k * kWave + s.lane, to_fixed(dI), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         tk = s.geometric ? tk * s.ratio : tk + s.ratio;
     }
 }
 
+// Walk one wave's share of a tile's hit words: for every set bit, the Gaussian
+// id of that supertile-list entry, its record (prefetched one pair ahead into
+// the other of two scalar register sets) and the pair evaluation.
+template <bool STATS>
+__device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* words, int w0, int w1,
+                                                                const int* list, ConstF4Ptr rec,
+                                                                const TexelState& st, unsigned long long& n_hits,
+                                                                unsigned long long& n_act,
+                                                                unsigned long long& n_ramp) {
+    const int lane = st.lane;
+    for (int gbase = w0; gbase < w1; gbase += 64) {
+        const uint64_t wv = gbase + lane < w1 ? words[gbase + lane] : 0ull;
+        uint64_t nz = __ballot(wv != 0ull);
+        if (nz == 0ull) continue;
+        int gv = list[64 * (gbase + __builtin_ctzll(nz)) + lane];
+        while (nz) {
+            const int j = __builtin_ctzll(nz);
+            nz &= nz - 1;
+            uint64_t word = readlane_u64(wv, j);
+            const int gcur = gv;
+            if (nz) gv = list[64 * (gbase + __builtin_ctzll(nz)) + lane];   // next chunk's ids, in flight
+            if (STATS) n_hits += __popcll(word);
+            int b = __builtin_ctzll(word);
+            word &= word - 1;
+            RecRegs ra = load_rec(rec, readlane_i(gcur, b)), rb;
+            for (;;) {
+                if (word) {                                 // B in flight while A is evaluated
+                    b = __builtin_ctzll(word);
+                    word &= word - 1;
+                    rb = load_rec(rec, readlane_i(gcur, b));
+                    eval_pair<STATS>(ra, st, n_act, n_ramp);
+                } else {
+                    eval_pair<STATS>(ra, st, n_act, n_ramp);
+                    break;
+                }
+                if (word) {                                 // A in flight while B is evaluated
+                    b = __builtin_ctzll(word);
+                    word &= word - 1;
+                    ra = load_rec(rec, readlane_i(gcur, b));
+                    eval_pair<STATS>(rb, st, n_act, n_ramp);
+                } else {
+                    eval_pair<STATS>(rb, st, n_act, n_ramp);
+                    break;
+                }
+            }
+        }
+    }
+}
+
+constexpr int kTileWaves = 4;   // waves sharing one tile's accumulators
+
 template <typename OutT, bool STATS>
-__global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
+__global__ __launch_bounds__(kWave * kTileWaves) void tile_build_kernel(TileArgs p) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const Geom& g = p.g;
     const int K = g.K;
-    float* inc = reinterpret_cast<float*>(smem);      // [K][64] per-shell increments
+    unsigned long long* inc = reinterpret_cast<unsigned long long*>(smem);   // [K][64] fixed point
 
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const int tile = blockIdx.x;
     const int light = blockIdx.y;
     const LightWs W = light_ws(p.ws, p.lay, light);
@@ -537,9 +605,10 @@ __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
         st.kinv = (float)K / g.r1;
         st.ratio = (double)g.r1 / (double)K;
     }
-    for (int q = lane; q < K * kWave; q += kWave) inc[q] = 0.f;
+    for (int q = tid; q < K * kWave; q += kWave * kTileWaves) inc[q] = 0ull;
 
-    // this tile's hit words: contiguous ns words, one per 64-entry chunk of the supertile list
+    // this tile's hit words: contiguous ns words, one per 64-entry chunk of the
+    // supertile list; wave w walks the w-th quarter of them
     const int s = (ty / g.STH) * g.SGW + (tx / g.STW);
     const SuperSpan sp = super_span(g, s);
     const int t_local = (ty - sp.ty0) * sp.ntx + (tx - sp.tx0);
@@ -548,39 +617,12 @@ __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
     const uint64_t* words = W.bits + 64 * (size_t)c0 + (size_t)t_local * ns;
     const int* list = W.lists + lb0;
     const ConstF4Ptr rec = (ConstF4Ptr)(const void*)W.rec;
+    const int per = (ns + kTileWaves - 1) / kTileWaves;
+    const int w0 = min(ns, wave * per), w1 = min(ns, w0 + per);
     unsigned long long n_hits = 0, n_act = 0, n_ramp = 0;
     __syncthreads();
 
-    for (int gbase = 0; gbase < ns; gbase += 64) {
-        const uint64_t wv = gbase + lane < ns ? words[gbase + lane] : 0ull;
-        uint64_t nz = __ballot(wv != 0ull);
-        if (nz == 0ull) continue;
-        int j = __builtin_ctzll(nz);
-        int gv = list[64 * (gbase + j) + lane];
-        while (nz) {
-            j = __builtin_ctzll(nz);
-            nz &= nz - 1;
-            uint64_t word = readlane_u64(wv, j);
-            const int gcur = gv;
-            if (nz) gv = list[64 * (gbase + __builtin_ctzll(nz)) + lane];   // next chunk's ids, in flight
-            if (STATS) n_hits += __popcll(word);
-            int b = __builtin_ctzll(word);
-            word &= word - 1;
-            RecRegs cur = load_rec(rec, readlane_i(gcur, b));
-            for (;;) {
-                const bool more = word != 0ull;
-                RecRegs nxt;
-                if (more) {                                 // next record, in flight
-                    b = __builtin_ctzll(word);
-                    word &= word - 1;
-                    nxt = load_rec(rec, readlane_i(gcur, b));
-                }
-                eval_pair<STATS>(cur, st, n_act, n_ramp);
-                if (!more) break;
-                cur = nxt;
-            }
-        }
-    }
+    walk_hits<STATS>(words, w0, w1, list, rec, st, n_hits, n_act, n_ramp);
 
     if (STATS) {
         const unsigned long long nvalid = __popcll(__ballot(st.valid));
@@ -588,26 +630,29 @@ __global__ __launch_bounds__(kWave) void tile_build_kernel(TileArgs p) {
             atomicAdd(p.stats + 0, n_hits * nvalid);
             atomicAdd(p.stats + 1, n_act);
             atomicAdd(p.stats + 2, n_ramp);
-            atomicAdd(p.stats + 3, (unsigned long long)(lb1 - lb0));
+            if (wave == 0) atomicAdd(p.stats + 3, (unsigned long long)(lb1 - lb0));
         }
     }
     __syncthreads();
 
-    if (st.valid) {
+    if (wave == 0 && st.valid) {
         const size_t plane = (size_t)g.H * g.W;
         const size_t off = (size_t)light * K * plane + (size_t)py * g.W + px;
         const float* bt = p.base_tau ? p.base_tau + off : nullptr;
-        float tau = 0.f, Tp = 1.f;
+        unsigned long long acc = 0;
+        float Tp = 1.f;
         if (p.write_tau) {
             float* out = reinterpret_cast<float*>(p.out) + off;
             for (int k = 0; k < K; ++k) {
-                tau += inc[k * kWave + lane];
+                acc += inc[k * kWave + lane];
+                const float tau = (float)from_fixed(acc);
                 out[(size_t)k * plane] = bt ? tau + bt[(size_t)k * plane] : tau;
             }
         } else {
             OutT* out = reinterpret_cast<OutT*>(p.out) + off;
             for (int k = 0; k < K; ++k) {
-                tau += inc[k * kWave + lane];
+                acc += inc[k * kWave + lane];
+                const float tau = (float)from_fixed(acc);
                 const float tt = bt ? tau + bt[(size_t)k * plane] : tau;
                 const float T = fminf(__expf(-tt), Tp);   // exactly non-increasing in k
                 Tp = T;
@@ -648,7 +693,7 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
     return L;
 }
 
-size_t tile_smem_bytes(const Geom& g) { return (size_t)g.K * kWave * sizeof(float); }
+size_t tile_smem_bytes(const Geom& g) { return (size_t)g.K * kWave * sizeof(unsigned long long); }
 
 template <typename OutT, bool STATS>
 static hipError_t launch_tile(const TileArgs& ta, int n_lights, hipStream_t st) {
@@ -658,7 +703,7 @@ static hipError_t launch_tile(const TileArgs& ta, int n_lights, hipStream_t st) 
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
-    tile_build_kernel<OutT, STATS><<<dim3(ta.g.ntiles, n_lights), kWave, smem, st>>>(ta);
+    tile_build_kernel<OutT, STATS><<<dim3(ta.g.ntiles, n_lights), kWave * kTileWaves, smem, st>>>(ta);
     return hipGetLastError();
 }
 
