@@ -186,6 +186,54 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
                         const float* colour_sh, const dgsm_sh_params_t* params, float* scale_out,
                         float* colour_sh_out, float* rgb_out, void* stream);
 
+/*
+ * Batched build + query over animation frames (a plan).
+ *
+ * A plan serves a scene made of a STATIC Gaussian set (copied into the plan at
+ * creation; the caller's arrays may be freed afterwards) and a DYNAMIC set of
+ * n_dynamic Gaussians that moves rigidly: in frame f its means are
+ * base_mean + translations[f] (one FP32 addition per coordinate), its scales,
+ * rotations and opacities fixed.  One dgsm_plan_run evaluates every frame:
+ * the atlas of every light from all static + dynamic Gaussians (exactly what
+ * dgsm_build computes on the union) and a dgsm_query of every light at all
+ * Gaussian centres (static first, then dynamic) into T_out[f][light][point].
+ *
+ * dgsm_plan_opts_t:
+ *   frames        F >= 1 frames per run
+ *   static_cache  1: the static optical depth is built once per run and each
+ *                 frame adds only the dynamic Gaussians to it (tau is a sum over
+ *                 Gaussians, Eq. 2); 0: every frame rebuilds from all Gaussians
+ *   autotune      1: the first run times the waves-per-tile knob of the tile
+ *                 accumulation (2, 4, 8) on frame 0 and keeps the fastest
+ *   tile_waves    knob value when autotune = 0 (2, 4 or 8; else 4)
+ *
+ * dgsm_plan_create allocates all device memory the plan needs (the only
+ * allocating entry points are create and destroy) and synchronises the device.
+ * dgsm_plan_run enqueues on `stream`; with use_graph = 1 the whole run (static
+ * build + all frames) is captured once into a hipGraph and replayed (stream
+ * must then be a created stream, not NULL; a run with different dynamic or
+ * output pointers recaptures).  Runs of one plan must not overlap.
+ *   dynamic_set : device arrays of the dynamic set at its base pose (n = n_dynamic)
+ *   translations: device [F][3]
+ *   T_out       : device [F][lights.n][n_static + n_dynamic] float32
+ */
+typedef struct dgsm_plan_s* dgsm_plan;
+typedef struct {
+    int32_t frames;
+    int32_t static_cache;
+    int32_t autotune;
+    int32_t tile_waves;
+} dgsm_plan_opts_t;
+
+dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc,
+                             const dgsm_gaussians_t* static_set, int64_t n_dynamic,
+                             const dgsm_plan_opts_t* opts, dgsm_plan* out);
+dgsm_status dgsm_plan_run(dgsm_plan plan, const dgsm_gaussians_t* dynamic_set, const float* translations,
+                          float* T_out, int32_t use_graph, void* stream);
+/* The waves-per-tile knob in use (after autotuning, if enabled). */
+int32_t dgsm_plan_tile_waves(const dgsm_plan plan);
+dgsm_status dgsm_plan_destroy(dgsm_plan plan);
+
 /* dgsm_alpha_centroid - c = sum_i alpha_i mu_i / sum_i alpha_i (Sec. 3.2
  * "Receiver-driven region", the alpha-weighted avatar centroid), accumulated
  * in FP64 in a fixed order (bitwise reproducible).  centroid: device [3].

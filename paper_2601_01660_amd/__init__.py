@@ -41,6 +41,11 @@ class _ShParams(ctypes.Structure):
                 ("centroid", ctypes.c_void_p)]
 
 
+class _PlanOpts(ctypes.Structure):
+    _fields_ = [("frames", ctypes.c_int32), ("static_cache", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("tile_waves", ctypes.c_int32)]
+
+
 _LIB = None
 
 # exported symbol -> (restype, argtypes)
@@ -60,6 +65,13 @@ SIGNATURES = {
                                    ctypes.POINTER(_ShParams), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p]),
     "dgsm_alpha_centroid": (ctypes.c_int, [ctypes.POINTER(_Gaussians), ctypes.c_void_p, ctypes.c_void_p]),
+    "dgsm_plan_create": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_AtlasDesc),
+                                        ctypes.POINTER(_Gaussians), ctypes.c_int64, ctypes.POINTER(_PlanOpts),
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "dgsm_plan_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Gaussians), ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_int32, ctypes.c_void_p]),
+    "dgsm_plan_tile_waves": (ctypes.c_int32, [ctypes.c_void_p]),
+    "dgsm_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
 }
 
 
@@ -246,3 +258,58 @@ def sh_transfer(probe_sh, gaussians: GaussianSet, colour_sh=None, centroid=None,
     _check(lib().sh_transfer(_ptr(probe_sh), int(probe_sh.shape[0]), ctypes.byref(gs), _ptr(colour_sh),
                              ctypes.byref(prm), _ptr(s), _ptr(f_out), _ptr(rgb), _stream()))
     return s, f_out, rgb
+
+
+class Plan:
+    """Batched build + query over animation frames (dgsm_plan_* in include/dgsm.h).
+
+    The static set is copied into the plan; each run evaluates ``frames`` frames of
+    the static set plus the dynamic set translated by ``translations[f]``.
+    """
+
+    def __init__(self, lights, atlas: Atlas, static: GaussianSet, n_dynamic: int, frames: int,
+                 static_cache: bool = True, autotune: bool = True, tile_waves: int = 4, kappa: float = 1.0):
+        lights = _dev(lights)
+        self.L = int(lights.shape[0])
+        self.atlas = atlas
+        self.n_static = static.n
+        self.n_dynamic = int(n_dynamic)
+        self.frames = int(frames)
+        d = atlas.struct()
+        lt = _Lights(lights.data_ptr(), self.L, kappa)
+        gs = static.struct()
+        opts = _PlanOpts(self.frames, int(static_cache), int(autotune), int(tile_waves))
+        h = ctypes.c_void_p()
+        _check(lib().dgsm_plan_create(ctypes.byref(lt), ctypes.byref(d), ctypes.byref(gs), self.n_dynamic,
+                                      ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def n_points(self) -> int:
+        return self.n_static + self.n_dynamic
+
+    @property
+    def tile_waves(self) -> int:
+        return int(lib().dgsm_plan_tile_waves(self._h))
+
+    def run(self, dynamic: GaussianSet, translations, out=None, use_graph: bool = True):
+        """T[frames, L, n_static + n_dynamic] for one run; enqueued on the current stream."""
+        translations = _dev(translations)
+        if out is None:
+            out = torch.empty((self.frames, self.L, self.n_points), dtype=torch.float32,
+                              device=translations.device)
+        gs = dynamic.struct()
+        _check(lib().dgsm_plan_run(self._h, ctypes.byref(gs), _ptr(translations), _ptr(out), int(use_graph),
+                                   _stream()))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dgsm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

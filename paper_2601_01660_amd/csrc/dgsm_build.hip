@@ -567,10 +567,10 @@ __device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* 
     }
 }
 
-constexpr int kTileWaves = 4;   // waves sharing one tile's accumulators
-
-template <typename OutT, bool STATS>
-__global__ __launch_bounds__(kWave * kTileWaves) void tile_build_kernel(TileArgs p) {
+// NW waves share one tile's accumulators (a launch knob: more waves per tile
+// split a tile's pairs finer and raise occupancy per LDS byte).
+template <typename OutT, bool STATS, int NW>
+__global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const Geom& g = p.g;
     const int K = g.K;
@@ -605,7 +605,7 @@ __global__ __launch_bounds__(kWave * kTileWaves) void tile_build_kernel(TileArgs
         st.kinv = (float)K / g.r1;
         st.ratio = (double)g.r1 / (double)K;
     }
-    for (int q = tid; q < K * kWave; q += kWave * kTileWaves) inc[q] = 0ull;
+    for (int q = tid; q < K * kWave; q += kWave * NW) inc[q] = 0ull;
 
     // this tile's hit words: contiguous ns words, one per 64-entry chunk of the
     // supertile list; wave w walks the w-th quarter of them
@@ -617,7 +617,7 @@ __global__ __launch_bounds__(kWave * kTileWaves) void tile_build_kernel(TileArgs
     const uint64_t* words = W.bits + 64 * (size_t)c0 + (size_t)t_local * ns;
     const int* list = W.lists + lb0;
     const ConstF4Ptr rec = (ConstF4Ptr)(const void*)W.rec;
-    const int per = (ns + kTileWaves - 1) / kTileWaves;
+    const int per = (ns + NW - 1) / NW;
     const int w0 = min(ns, wave * per), w1 = min(ns, w0 + per);
     unsigned long long n_hits = 0, n_act = 0, n_ramp = 0;
     __syncthreads();
@@ -695,16 +695,25 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
 
 size_t tile_smem_bytes(const Geom& g) { return (size_t)g.K * kWave * sizeof(unsigned long long); }
 
-template <typename OutT, bool STATS>
+template <typename OutT, bool STATS, int NW>
 static hipError_t launch_tile(const TileArgs& ta, int n_lights, hipStream_t st) {
     const size_t smem = tile_smem_bytes(ta.g);
     if (smem > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute((const void*)tile_build_kernel<OutT, STATS>,
+        const hipError_t e = hipFuncSetAttribute((const void*)tile_build_kernel<OutT, STATS, NW>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
-    tile_build_kernel<OutT, STATS><<<dim3(ta.g.ntiles, n_lights), kWave * kTileWaves, smem, st>>>(ta);
+    tile_build_kernel<OutT, STATS, NW><<<dim3(ta.g.ntiles, n_lights), kWave * NW, smem, st>>>(ta);
     return hipGetLastError();
+}
+
+template <typename OutT, bool STATS>
+static hipError_t launch_tile_nw(const TileArgs& ta, int n_lights, int nw, hipStream_t st) {
+    switch (nw) {
+        case 2: return launch_tile<OutT, STATS, 2>(ta, n_lights, st);
+        case 8: return launch_tile<OutT, STATS, 8>(ta, n_lights, st);
+        default: return launch_tile<OutT, STATS, 4>(ta, n_lights, st);
+    }
 }
 
 dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
@@ -742,10 +751,11 @@ dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned cha
     TileArgs ta{g, L, ws, pair_eps, atlas, o.base_tau, o.write_tau ? 1 : 0, o.stats};
     hipError_t e;
     const bool half = g.dtype == DGSM_F16 && !o.write_tau;
+    const int nw = o.tile_waves;
     if (o.stats)
-        e = half ? launch_tile<__half, true>(ta, n_lights, st) : launch_tile<float, true>(ta, n_lights, st);
+        e = half ? launch_tile_nw<__half, true>(ta, n_lights, nw, st) : launch_tile_nw<float, true>(ta, n_lights, nw, st);
     else
-        e = half ? launch_tile<__half, false>(ta, n_lights, st) : launch_tile<float, false>(ta, n_lights, st);
+        e = half ? launch_tile_nw<__half, false>(ta, n_lights, nw, st) : launch_tile_nw<float, false>(ta, n_lights, nw, st);
     return e == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
 
@@ -791,7 +801,7 @@ extern "C" dgsm_status dgsm_accumulate(const dgsm_lights_t* lights, const dgsm_a
     const Geom g = make_geom(*desc);
     const BuildLayout L = build_layout(g, n_gauss, lights->n);
     if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
-    AccumOpts o{nullptr, false, stats};
+    AccumOpts o{nullptr, false, stats, kDefaultTileWaves};
     return enqueue_accumulate(g, L, reinterpret_cast<unsigned char*>(ws), lights->n, desc->cull_eps, atlas, o,
                               reinterpret_cast<hipStream_t>(stream));
 }
@@ -808,6 +818,6 @@ extern "C" dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussi
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
     if ((st = enqueue_bin(g, L, w, *lights, desc->cull_eps, *gaussians, s)) != DGSM_OK) return st;
-    AccumOpts o{nullptr, false, nullptr};
+    AccumOpts o{nullptr, false, nullptr, kDefaultTileWaves};
     return enqueue_accumulate(g, L, w, lights->n, desc->cull_eps, atlas, o, s);
 }

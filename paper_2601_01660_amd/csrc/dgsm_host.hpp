@@ -62,7 +62,10 @@ struct AccumOpts {
     const float* base_tau;   // optional [L][K][H][W] FP32 optical depth added before exp (may be null)
     bool write_tau;          // store tau (FP32) instead of T
     unsigned long long* stats;   // optional device counters [4]
+    int tile_waves;              // waves sharing one tile: 2, 4 or 8
 };
+
+constexpr int kDefaultTileWaves = 4;
 
 // Enqueue the per-tile accumulation of all lights into atlas [L][K][H][W].
 dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned char* ws, int n_lights,

@@ -1,0 +1,270 @@
+// Batched DGSM: many lights x animation frames in one captured HIP graph.
+//
+// A plan owns every buffer it needs (allocated once, at creation).  One run
+// processes F frames of a scene made of a static Gaussian set and a dynamic
+// set that moves rigidly by a per-frame translation:
+//   per frame f: dynamic means = base + t_f; build the atlas of every light
+//   from all Gaussians; query T at all Gaussian centres into T_out[f].
+// With the static cache on, the optical depth of the static set is built once
+// per run (it does not change between frames) and each frame only bins and
+// accumulates the dynamic Gaussians on top of it: tau = tau_static +
+// tau_dynamic is exact because Eq. 2 is a sum over Gaussians.
+// The whole run (static build + all frames) is captured once into a hipGraph
+// and replayed; the waves-per-tile knob of the tile build is chosen on the
+// first run by timing each candidate on frame 0 of the real workload.
+
+#include "dgsm_device.hpp"
+#include "dgsm_host.hpp"
+
+#include <new>
+#include <vector>
+
+namespace dgsm {
+
+// dst[i] = base[i] + t  (one FP32 addition per coordinate)
+__global__ __launch_bounds__(256) void translate_kernel(const float* __restrict__ base, int64_t n,
+                                                        const float* __restrict__ t, float* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= 3 * n) return;
+    dst[i] = base[i] + t[i % 3];
+}
+
+}  // namespace dgsm
+
+using namespace dgsm;
+
+struct dgsm_plan_s {
+    Geom g;
+    dgsm_atlas_desc_t desc;
+    int L;
+    float kappa;
+    int64_t ns, nd, np;
+    int frames;
+    bool cache;
+    int autotune;
+    int tile_waves;
+    bool tuned;
+    // device buffers owned by the plan
+    float* lights;        // [L][3]
+    float* mean;          // [ns + nd][3]: static means, then this frame's dynamic means
+    float* scale;         // [ns + nd][3]
+    float* rot;           // [ns + nd][4]
+    float* opacity;       // [ns + nd]
+    float* tau_static;    // [L][K][H][W] (cache mode)
+    void* atlas;          // [L][K][H][W] of desc.dtype
+    unsigned char* ws_a;  // workspace for the static (cache) or full (no cache) set
+    size_t ws_a_bytes;
+    unsigned char* ws_b;  // workspace for the dynamic set (cache mode)
+    size_t ws_b_bytes;
+    // captured graph and the arguments it was captured for
+    hipGraphExec_t exec;
+    const void* cap_key[6];
+};
+
+namespace {
+
+template <typename T>
+hipError_t dalloc(T** p, size_t bytes) {
+    return hipMalloc(reinterpret_cast<void**>(p), bytes ? bytes : 256);
+}
+
+void plan_free(dgsm_plan p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    void* bufs[] = {p->lights, p->mean, p->scale, p->rot, p->opacity, p->tau_static, p->atlas, p->ws_a, p->ws_b};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    delete p;
+}
+
+dgsm_gaussians_t set_of(const dgsm_plan p, int64_t off, int64_t n) {
+    return dgsm_gaussians_t{p->mean + 3 * off, p->scale + 3 * off, p->rot + 4 * off, p->opacity + off, n};
+}
+
+// Static part of a run: tau of the static set for every light.
+dgsm_status enqueue_static(dgsm_plan p, int tile_waves, hipStream_t st) {
+    const dgsm_lights_t lt{p->lights, p->L, p->kappa};
+    const BuildLayout La = build_layout(p->g, p->ns, p->L);
+    dgsm_status s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, 0, p->ns), st);
+    if (s != DGSM_OK) return s;
+    AccumOpts o{nullptr, true, nullptr, tile_waves};
+    return enqueue_accumulate(p->g, La, p->ws_a, p->L, p->desc.cull_eps, p->tau_static, o, st);
+}
+
+// One frame: dynamic means, build (on top of the static tau in cache mode), query.
+dgsm_status enqueue_frame(dgsm_plan p, int f, const float* dyn_base, const float* translations, float* T_out,
+                          int tile_waves, hipStream_t st) {
+    const dgsm_lights_t lt{p->lights, p->L, p->kappa};
+    if (p->nd > 0) {
+        const int64_t n3 = 3 * p->nd;
+        translate_kernel<<<(unsigned)((n3 + 255) / 256), 256, 0, st>>>(dyn_base, p->nd, translations + 3 * f,
+                                                                        p->mean + 3 * p->ns);
+        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    }
+    dgsm_status s;
+    if (p->cache) {
+        const BuildLayout Lb = build_layout(p->g, p->nd, p->L);
+        s = enqueue_bin(p->g, Lb, p->ws_b, lt, p->desc.cull_eps, set_of(p, p->ns, p->nd), st);
+        if (s != DGSM_OK) return s;
+        AccumOpts o{p->tau_static, false, nullptr, tile_waves};
+        s = enqueue_accumulate(p->g, Lb, p->ws_b, p->L, p->desc.cull_eps, p->atlas, o, st);
+    } else {
+        const BuildLayout La = build_layout(p->g, p->np, p->L);
+        s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, 0, p->np), st);
+        if (s != DGSM_OK) return s;
+        AccumOpts o{nullptr, false, nullptr, tile_waves};
+        s = enqueue_accumulate(p->g, La, p->ws_a, p->L, p->desc.cull_eps, p->atlas, o, st);
+    }
+    if (s != DGSM_OK) return s;
+    if (launch_query(p->g, p->lights, p->L, p->atlas, p->mean, p->np, T_out + (size_t)f * p->L * p->np, st) !=
+        hipSuccess)
+        return DGSM_EHIP;
+    return DGSM_OK;
+}
+
+dgsm_status enqueue_run(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* translations, float* T_out,
+                        hipStream_t st) {
+    if (p->nd > 0) {
+        const int64_t o = p->ns;
+        if (hipMemcpyAsync(p->scale + 3 * o, dyn->scale, 12 * p->nd, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(p->rot + 4 * o, dyn->rot, 16 * p->nd, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(p->opacity + o, dyn->opacity, 4 * p->nd, hipMemcpyDeviceToDevice, st) != hipSuccess)
+            return DGSM_EHIP;
+    }
+    dgsm_status s;
+    if (p->cache && (s = enqueue_static(p, p->tile_waves, st)) != DGSM_OK) return s;
+    for (int f = 0; f < p->frames; ++f)
+        if ((s = enqueue_frame(p, f, dyn->mean, translations, T_out, p->tile_waves, st)) != DGSM_OK) return s;
+    return DGSM_OK;
+}
+
+// Time each waves-per-tile candidate on the accumulation the run repeats most
+// (frame 0: the dynamic accumulation in cache mode, the full one otherwise).
+dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* translations, float* T_out,
+                     hipStream_t st) {
+    const int cand[3] = {2, 4, 8};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DGSM_EHIP;
+    dgsm_status s = DGSM_OK;
+    float best = 1e30f;
+    int best_nw = kDefaultTileWaves;
+    if (p->nd > 0) {
+        const int64_t o = p->ns;
+        (void)hipMemcpyAsync(p->scale + 3 * o, dyn->scale, 12 * p->nd, hipMemcpyDeviceToDevice, st);
+        (void)hipMemcpyAsync(p->rot + 4 * o, dyn->rot, 16 * p->nd, hipMemcpyDeviceToDevice, st);
+        (void)hipMemcpyAsync(p->opacity + o, dyn->opacity, 4 * p->nd, hipMemcpyDeviceToDevice, st);
+    }
+    if (p->cache) s = enqueue_static(p, kDefaultTileWaves, st);
+    for (int rep = 0; rep < 2 && s == DGSM_OK; ++rep)   // first pass warms up
+        for (int c = 0; c < 3 && s == DGSM_OK; ++c) {
+            (void)hipEventRecord(e0, st);
+            s = enqueue_frame(p, 0, dyn->mean, translations, T_out, cand[c], st);
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) s = DGSM_EHIP;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (rep == 1 && ms < best) { best = ms; best_nw = cand[c]; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->tile_waves = best_nw;
+    p->tuned = true;
+    return s;
+}
+
+}  // namespace
+
+extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc,
+                                        const dgsm_gaussians_t* static_set, int64_t n_dynamic,
+                                        const dgsm_plan_opts_t* opts, dgsm_plan* out) {
+    if (!out || !opts) return DGSM_EINVAL;
+    *out = nullptr;
+    dgsm_status st = validate_desc(desc);
+    if (st != DGSM_OK) return st;
+    if ((st = validate_lights(lights)) != DGSM_OK) return st;
+    if ((st = validate_gaussians(static_set)) != DGSM_OK) return st;
+    if (n_dynamic < 0 || opts->frames < 1) return DGSM_EINVAL;
+    const int64_t np = static_set->n + n_dynamic;
+    const Geom g = make_geom(*desc);
+    if (np >= INT32_MAX || (np + 64) * (int64_t)g.S >= (int64_t)INT32_MAX) return DGSM_EUNSUPPORTED;
+    dgsm_plan p = new (std::nothrow) dgsm_plan_s{};
+    if (!p) return DGSM_EHIP;
+    p->g = g;
+    p->desc = *desc;
+    p->L = lights->n;
+    p->kappa = lights->kappa;
+    p->ns = static_set->n;
+    p->nd = n_dynamic;
+    p->np = np;
+    p->frames = opts->frames;
+    p->cache = opts->static_cache != 0;
+    p->autotune = opts->autotune;
+    p->tile_waves = (opts->tile_waves == 2 || opts->tile_waves == 8) ? opts->tile_waves : kDefaultTileWaves;
+    const size_t elem = desc->dtype == DGSM_F16 ? 2 : 4;
+    const size_t table = (size_t)p->L * g.K * g.H * g.W;
+    p->ws_a_bytes = build_layout(g, p->cache ? p->ns : np, p->L).total;
+    p->ws_b_bytes = p->cache ? build_layout(g, p->nd, p->L).total : 0;
+    bool ok = dalloc(&p->lights, 12 * (size_t)p->L) == hipSuccess && dalloc(&p->mean, 12 * (size_t)np) == hipSuccess &&
+              dalloc(&p->scale, 12 * (size_t)np) == hipSuccess && dalloc(&p->rot, 16 * (size_t)np) == hipSuccess &&
+              dalloc(&p->opacity, 4 * (size_t)np) == hipSuccess && dalloc(&p->atlas, table * elem) == hipSuccess &&
+              dalloc(&p->ws_a, p->ws_a_bytes) == hipSuccess &&
+              (!p->cache || (dalloc(&p->tau_static, table * 4) == hipSuccess &&
+                             dalloc(&p->ws_b, p->ws_b_bytes) == hipSuccess));
+    const int64_t n = p->ns;
+    ok = ok && hipMemcpy(p->lights, lights->pos, 12 * (size_t)p->L, hipMemcpyDeviceToDevice) == hipSuccess;
+    if (ok && n > 0)
+        ok = hipMemcpy(p->mean, static_set->mean, 12 * n, hipMemcpyDeviceToDevice) == hipSuccess &&
+             hipMemcpy(p->scale, static_set->scale, 12 * n, hipMemcpyDeviceToDevice) == hipSuccess &&
+             hipMemcpy(p->rot, static_set->rot, 16 * n, hipMemcpyDeviceToDevice) == hipSuccess &&
+             hipMemcpy(p->opacity, static_set->opacity, 4 * n, hipMemcpyDeviceToDevice) == hipSuccess;
+    if (!ok) {
+        plan_free(p);
+        return DGSM_EHIP;
+    }
+    *out = p;
+    return DGSM_OK;
+}
+
+extern "C" dgsm_status dgsm_plan_run(dgsm_plan p, const dgsm_gaussians_t* dynamic_set, const float* translations,
+                                     float* T_out, int32_t use_graph, void* stream) {
+    if (!p || !dynamic_set || !T_out || (p->frames > 0 && !translations)) return DGSM_EINVAL;
+    if (dynamic_set->n != p->nd) return DGSM_EINVAL;
+    dgsm_status st = validate_gaussians(dynamic_set);
+    if (st != DGSM_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (p->autotune && !p->tuned && (st = autotune(p, dynamic_set, translations, T_out, s)) != DGSM_OK) return st;
+    if (!use_graph) return enqueue_run(p, dynamic_set, translations, T_out, s);
+    if (!s) return DGSM_EINVAL;   // the legacy default stream cannot be captured
+    const void* key[6] = {dynamic_set->mean, dynamic_set->scale, dynamic_set->rot, dynamic_set->opacity,
+                          translations, T_out};
+    bool same = p->exec != nullptr;
+    for (int i = 0; i < 6 && same; ++i) same = key[i] == p->cap_key[i];
+    if (!same) {
+        if (p->exec) {
+            (void)hipGraphExecDestroy(p->exec);
+            p->exec = nullptr;
+        }
+        hipGraph_t graph;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) return DGSM_EHIP;
+        st = enqueue_run(p, dynamic_set, translations, T_out, s);
+        const hipError_t ec = hipStreamEndCapture(s, &graph);
+        if (st != DGSM_OK) return st;
+        if (ec != hipSuccess) return DGSM_EHIP;
+        const hipError_t ei = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            p->exec = nullptr;
+            return DGSM_EHIP;
+        }
+        for (int i = 0; i < 6; ++i) p->cap_key[i] = key[i];
+    }
+    return hipGraphLaunch(p->exec, s) == hipSuccess ? DGSM_OK : DGSM_EHIP;
+}
+
+extern "C" int32_t dgsm_plan_tile_waves(const dgsm_plan p) { return p ? p->tile_waves : 0; }
+
+extern "C" dgsm_status dgsm_plan_destroy(dgsm_plan p) {
+    if (!p) return DGSM_EINVAL;
+    plan_free(p);
+    return DGSM_OK;
+}
