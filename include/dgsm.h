@@ -234,6 +234,73 @@ dgsm_status dgsm_plan_run(dgsm_plan plan, const dgsm_gaussians_t* dynamic_set, c
 int32_t dgsm_plan_tile_waves(const dgsm_plan plan);
 dgsm_status dgsm_plan_destroy(dgsm_plan plan);
 
+/*
+ * Learned per-light transmittance field (a surrogate of one light's atlas).
+ *
+ * Network: features phi(u, v, rho) -> 4 hidden layers of 128 ReLU units ->
+ * z -> T = sigmoid(-z) (log T = -softplus(z)).  (u, v) is the octahedral code
+ * of the direction from the light, rho in [-1, 1] the atlas radius coordinate
+ * (geometric: 2 ln(r/r0)/ln(r1/r0) - 1; uniform: 2 r/r1 - 1; clamped).
+ * phi[128] = u, v, rho, then for i = 0..15 and f_i = pi (W/4)^(i/15) (W the
+ * atlas width): sin(f_i u), cos(f_i u), sin(f_i v), cos(f_i v), sin(f_i rho),
+ * cos(f_i rho); zeros from index 99.  Matrix products run on BF16 MFMA with
+ * FP32 accumulation: weights, features, hidden activations and back-propagated
+ * pre-activation gradients are rounded to BF16 (nearest even) where they enter
+ * the matrix units; biases, the output layer and all accumulations are FP32.
+ *
+ * Parameters: FP32 device array of DGSM_MLP_PARAMS values, per layer l = 0..3
+ * W_l [128 out][128 in] row-major then b_l [128], then w4 [128], then b4.
+ * Adam state: FP32 [2][DGSM_MLP_PARAMS] (first then second moments), zero it
+ * before the first step.  Loss: mean over the batch of (T - T_target)^2.
+ */
+#define DGSM_MLP_PARAMS 66177
+
+typedef struct {
+    int64_t batch;       /* samples per step, multiple of 32 */
+    int32_t steps;       /* steps in this call */
+    int32_t step0;       /* Adam steps already taken (bias correction continues) */
+    float lr0, lr1;      /* learning rate, cosine decay from lr0 to lr1 over the call */
+    uint32_t seed;       /* sample stream */
+    float beta1, beta2, eps;
+} dgsm_mlp_train_t;
+
+/* Workspace for dgsm_mlp_grad / dgsm_mlp_train at this batch (0 if invalid). */
+size_t dgsm_mlp_workspace_size(int64_t batch);
+/* Workspace for dgsm_mlp_infer with n_lights parameter sets; dgsm_mlp_check
+ * needs dgsm_mlp_infer_workspace_size(1) plus 16 bytes per check sample
+ * (rounded up to 256). */
+size_t dgsm_mlp_infer_workspace_size(int32_t n_lights);
+
+/* Gradient of the loss at params on B given samples uvrt [B][4] = (u, v, rho,
+ * T_target), without an update.  grad: device [DGSM_MLP_PARAMS]; loss: device
+ * [1] or NULL.  B multiple of 32.  desc supplies W (frequencies). */
+dgsm_status dgsm_mlp_grad(const float* params, const float* uvrt, int64_t B, const dgsm_atlas_desc_t* desc,
+                          float* grad, float* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* opt->steps Adam steps on batches sampled from one light's atlas atlas_l
+ * [K][H][W] (desc->dtype): half of each batch at texel centres and shell radii
+ * (exact table values), half uniform in (u, v, rho) with trilinear targets.
+ * loss_out: device [steps] or NULL. */
+dgsm_status dgsm_mlp_train(float* params, float* adam_mv, const dgsm_atlas_desc_t* desc, const void* atlas_l,
+                           const dgsm_mlp_train_t* opt, float* loss_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Held-out check: n_check samples drawn like the training samples from the
+ * stream `seed`; sets mask[region] = 1 for every sample with |T - T_atlas| >
+ * thresh, region = (k0/8, i0/8, j0/8) of its floor texel, mask laid out
+ * [ceil(K/8)][H/8 tiles][W/8 tiles] (zero it first).  stats: device uint [2]
+ * (zero it first): flagged samples, max |T - T_atlas| as float bits. */
+dgsm_status dgsm_mlp_check(const float* params, const dgsm_atlas_desc_t* desc, const void* atlas_l,
+                           int64_t n_check, uint32_t seed, float thresh, unsigned char* mask, unsigned int* stats,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* T[l][p] of each light's network at world points [P][3] (params [L][DGSM_MLP_PARAMS]).
+ * With mask (layout of dgsm_mlp_check, [L][regions]) and atlas ([L][K][H][W]),
+ * points whose floor texel lies in a flagged region take the trilinear atlas
+ * value instead (the plain method as fallback). */
+dgsm_status dgsm_mlp_infer(const float* params, const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc,
+                           const void* atlas, const unsigned char* mask, const float* points, int64_t P, float* T,
+                           void* ws, size_t ws_bytes, void* stream);
+
 /* dgsm_alpha_centroid - c = sum_i alpha_i mu_i / sum_i alpha_i (Sec. 3.2
  * "Receiver-driven region", the alpha-weighted avatar centroid), accumulated
  * in FP64 in a fixed order (bitwise reproducible).  centroid: device [3].

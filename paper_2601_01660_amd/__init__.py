@@ -41,6 +41,15 @@ class _ShParams(ctypes.Structure):
                 ("centroid", ctypes.c_void_p)]
 
 
+class _MlpTrain(ctypes.Structure):
+    _fields_ = [("batch", ctypes.c_int64), ("steps", ctypes.c_int32), ("step0", ctypes.c_int32),
+                ("lr0", ctypes.c_float), ("lr1", ctypes.c_float), ("seed", ctypes.c_uint32),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+MLP_PARAMS = 66177
+
+
 class _PlanOpts(ctypes.Structure):
     _fields_ = [("frames", ctypes.c_int32), ("static_cache", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("tile_waves", ctypes.c_int32)]
@@ -72,6 +81,20 @@ SIGNATURES = {
                                      ctypes.c_int32, ctypes.c_void_p]),
     "dgsm_plan_tile_waves": (ctypes.c_int32, [ctypes.c_void_p]),
     "dgsm_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "dgsm_mlp_workspace_size": (ctypes.c_size_t, [ctypes.c_int64]),
+    "dgsm_mlp_infer_workspace_size": (ctypes.c_size_t, [ctypes.c_int32]),
+    "dgsm_mlp_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(_AtlasDesc),
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                     ctypes.c_void_p]),
+    "dgsm_mlp_train": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_AtlasDesc), ctypes.c_void_p,
+                                      ctypes.POINTER(_MlpTrain), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                      ctypes.c_void_p]),
+    "dgsm_mlp_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_AtlasDesc), ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_uint32, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dgsm_mlp_infer": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Lights), ctypes.POINTER(_AtlasDesc),
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
 }
 
 
@@ -313,3 +336,73 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# learned per-light transmittance field
+# ---------------------------------------------------------------------------
+
+def mlp_grad(params, uvrt, atlas: Atlas, grad=None, loss=None, workspace=None):
+    """Loss gradient [MLP_PARAMS] at params on samples uvrt [B, 4] = (u, v, rho, target)."""
+    params, uvrt = _dev(params), _dev(uvrt)
+    B = int(uvrt.shape[0])
+    need = int(lib().dgsm_mlp_workspace_size(B))
+    if need == 0:
+        raise DGSMError("batch must be a positive multiple of 32")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=params.device)
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=params.device) if grad is None else grad
+    loss = torch.empty(1, dtype=torch.float32, device=params.device) if loss is None else loss
+    d = atlas.struct()
+    _check(lib().dgsm_mlp_grad(_ptr(params), _ptr(uvrt), B, ctypes.byref(d), _ptr(grad), _ptr(loss),
+                               _ptr(workspace), workspace.numel(), _stream()))
+    return grad, loss
+
+
+def mlp_train(params, adam_mv, atlas: Atlas, table_l, steps, batch=16384, step0=0, lr0=1e-3, lr1=1e-4,
+              seed=1, beta1=0.9, beta2=0.999, eps=1e-8, workspace=None):
+    """``steps`` Adam steps (in place on params / adam_mv); returns the per-step losses."""
+    need = int(lib().dgsm_mlp_workspace_size(batch))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=params.device)
+    losses = torch.empty(max(steps, 1), dtype=torch.float32, device=params.device)
+    opt = _MlpTrain(batch, steps, step0, lr0, lr1, seed, beta1, beta2, eps)
+    d = atlas.struct()
+    _check(lib().dgsm_mlp_train(_ptr(params), _ptr(adam_mv), ctypes.byref(d), _ptr(table_l), ctypes.byref(opt),
+                                _ptr(losses), _ptr(workspace), workspace.numel(), _stream()))
+    return losses[:steps]
+
+
+def mlp_regions(atlas: Atlas) -> int:
+    return ((atlas.K + 7) // 8) * ((atlas.H + 7) // 8) * ((atlas.W + 7) // 8)
+
+
+def mlp_check(params, atlas: Atlas, table_l, n_check=262144, seed=12345, thresh=1e-2):
+    """Fallback mask [regions] (uint8) and (flagged samples, max |dT|) on a held-out sample set."""
+    dev = params.device
+    mask = torch.zeros(mlp_regions(atlas), dtype=torch.uint8, device=dev)
+    stats = torch.zeros(2, dtype=torch.int32, device=dev)
+    need = int(lib().dgsm_mlp_infer_workspace_size(1)) + ((16 * n_check + 255) // 256) * 256
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    d = atlas.struct()
+    _check(lib().dgsm_mlp_check(_ptr(params), ctypes.byref(d), _ptr(table_l), n_check, seed, thresh, _ptr(mask),
+                                _ptr(stats), _ptr(ws), ws.numel(), _stream()))
+    torch.cuda.current_stream().synchronize()
+    st = stats.cpu()
+    return mask, int(st[0]), float(st[1:2].view(torch.float32)[0])
+
+
+def mlp_infer(params, lights, atlas: Atlas, points, table=None, mask=None, out=None, workspace=None):
+    """T[L, P] of each light's network at points; flagged regions fall back to the atlas."""
+    lights, points = _dev(lights), _dev(points)
+    L, P = int(lights.shape[0]), int(points.shape[0])
+    need = int(lib().dgsm_mlp_infer_workspace_size(L))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=points.device)
+    if out is None:
+        out = torch.empty((L, P), dtype=torch.float32, device=points.device)
+    lt = _Lights(lights.data_ptr(), L, 1.0)
+    d = atlas.struct()
+    _check(lib().dgsm_mlp_infer(_ptr(params), ctypes.byref(lt), ctypes.byref(d), _ptr(table), _ptr(mask),
+                                _ptr(points), P, _ptr(out), _ptr(workspace), workspace.numel(), _stream()))
+    return out

@@ -1,0 +1,754 @@
+// Learned per-light transmittance field on gfx950 BF16 MFMA (FP32 accumulate).
+//
+// Network (one parameter set per light): phi(u, v, rho) -> 4 x (128, ReLU) ->
+// z -> T = sigmoid(-z), i.e. log T = -softplus(z).  phi holds u, v, rho and
+// sin/cos of f_i u, f_i v, f_i rho for 16 geometric frequencies
+// f_i = pi (W/4)^(i/15) (W = atlas width), zero padded to 128.
+// (u, v) is the octahedral code of the direction from the light and rho the
+// radius coordinate of the atlas (Sec. 3.2), rescaled to [-1, 1].
+//
+// Kernels (rows = samples or query points):
+//   sample_kernel   training / held-out samples from one light's atlas
+//   fwd_kernel      features + 4 MFMA layers + output; modes: train (stashes
+//                   activations for the backward), infer (T, with atlas
+//                   fallback), check (flags regions where |T - T_atlas| > thr)
+//   bwd_kernel      data-gradient chain through layers 3..1 (MFMA)
+//   wgrad_kernel    per-chunk weight gradients dW_l = dZ_l^T X_l (MFMA)
+//   reduce_kernel   fixed-order reduction of the partial gradients, optional
+//                   Adam step, BF16 weight copies
+// MFMA: v_mfma_f32_16x16x32_bf16.  A (16x32): lane l holds row l%16,
+// k = 8(l/16)..+7; B (32x16): lane l holds column l%16, k = 8(l/16)..+7;
+// D (16x16): lane l holds column l%16, rows 4(l/16)..+3.
+
+#include "dgsm_device.hpp"
+#include "dgsm_host.hpp"
+#include "mlp.hpp"
+
+namespace dgsm {
+namespace mlp {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int kRows = 16;          // rows per wave
+constexpr int kWaves = 4;
+constexpr int kTileRows = kRows * kWaves;
+
+__device__ inline f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// 16-byte chunk c (8 BF16) of a 256-byte row r, XOR-swizzled so that the 16
+// lanes reading chunk c of 16 consecutive rows hit 16 different bank groups.
+__device__ inline int swz(int r, int c) { return r * 16 + (c ^ (r & 15)); }
+
+__device__ inline __bf16 to_bf16(float x) { return (__bf16)x; }   // round to nearest even
+
+__device__ inline float hw_sin(float x) { return __sinf(x); }
+__device__ inline float hw_cos(float x) { return __cosf(x); }
+
+// Feature f (0..127) of a row.
+__device__ inline float feature(int f, float u, float v, float rho, float fscale) {
+    if (f == 0) return u;
+    if (f == 1) return v;
+    if (f == 2) return rho;
+    if (f >= kDin) return 0.f;
+    const int q = f - 3, i = q / 6, rem = q - 6 * i;
+    const float x = rem < 2 ? u : rem < 4 ? v : rho;
+    const float fr = 3.14159265358979324f * exp2f(fscale * (float)i);   // pi (W/4)^(i/15)
+    return (rem & 1) ? hw_cos(fr * x) : hw_sin(fr * x);
+}
+
+// Octahedral code and radius coordinate of a point seen from a light.
+__device__ inline void encode_point(float x, float y, float z, const float* o, const Geom& g, float& u,
+                                    float& v, float& rho, float& r) {
+    const float dx = x - o[0], dy = y - o[1], dz = z - o[2];
+    const float l1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
+    float qx = 0.f, qy = 0.f, qz = 1.f;
+    if (l1 > 0.f) {
+        const float il = 1.f / l1;
+        qx = dx * il; qy = dy * il; qz = dz * il;
+    }
+    u = qx; v = qy;
+    if (qz < 0.f) {
+        u = copysignf(1.f - fabsf(qy), qx >= 0.f ? 1.f : -1.f);
+        v = copysignf(1.f - fabsf(qx), qy >= 0.f ? 1.f : -1.f);
+    }
+    r = sqrtf(dx * dx + dy * dy + dz * dz);
+    if (g.spacing == DGSM_SHELLS_GEOMETRIC)
+        rho = 2.f * (__log2f(r) - __log2f(g.r0)) / __log2f(g.r1 / g.r0) - 1.f;
+    else
+        rho = 2.f * r / g.r1 - 1.f;
+    rho = fminf(fmaxf(rho, -1.f), 1.f);   // log2(0) = -inf clamps to -1
+}
+
+__device__ inline int wrap_off(int i, int j, int H, int W) {
+    if (j < 0) { j = 0; i = H - 1 - i; }
+    else if (j >= W) { j = W - 1; i = H - 1 - i; }
+    if (i < 0) { i = 0; j = W - 1 - j; }
+    else if (i >= H) { i = H - 1; j = W - 1 - j; }
+    return i * W + j;
+}
+
+// Trilinear atlas lookup at (u, v, rho), the same sampling rule as the query.
+// Also returns the fallback region of the floor texel.
+template <typename InT>
+__device__ inline float atlas_at(const InT* tab, const Geom& g, float u, float v, float rho, int& region) {
+    const float jf = fminf(fmaxf((u + 1.f) * (0.5f * (float)g.W) - 0.5f, -0.5f), (float)g.W - 0.5f);
+    const float if_ = fminf(fmaxf((v + 1.f) * (0.5f * (float)g.H) - 0.5f, -0.5f), (float)g.H - 0.5f);
+    float kf = g.spacing == DGSM_SHELLS_GEOMETRIC ? 0.5f * (rho + 1.f) * (float)(g.K - 1)
+                                                  : 0.5f * (rho + 1.f) * (float)g.K - 0.5f;
+    kf = fminf(fmaxf(kf, 0.f), (float)(g.K - 1));
+    const float j0f = floorf(jf), i0f = floorf(if_);
+    const int j0 = (int)j0f, i0 = (int)i0f;
+    const float fj = jf - j0f, fi = if_ - i0f;
+    const int k0 = min((int)kf, g.K - 2);
+    const float fk = kf - (float)k0;
+    const size_t plane = (size_t)g.H * g.W;
+    const int o00 = wrap_off(i0, j0, g.H, g.W), o01 = wrap_off(i0, j0 + 1, g.H, g.W);
+    const int o10 = wrap_off(i0 + 1, j0, g.H, g.W), o11 = wrap_off(i0 + 1, j0 + 1, g.H, g.W);
+    const InT* s0 = tab + (size_t)k0 * plane;
+    const InT* s1 = s0 + plane;
+    const float a0 = (1.f - fj) * Store<InT>::get(s0 + o00) + fj * Store<InT>::get(s0 + o01);
+    const float b0 = (1.f - fj) * Store<InT>::get(s0 + o10) + fj * Store<InT>::get(s0 + o11);
+    const float a1 = (1.f - fj) * Store<InT>::get(s1 + o00) + fj * Store<InT>::get(s1 + o01);
+    const float b1 = (1.f - fj) * Store<InT>::get(s1 + o10) + fj * Store<InT>::get(s1 + o11);
+    const int ic = min(max(i0, 0), g.H - 1), jc = min(max(j0, 0), g.W - 1);
+    region = (k0 / 8) * g.ntiles + (ic / kTile) * g.TW + jc / kTile;
+    return (1.f - fk) * ((1.f - fi) * a0 + fi * b0) + fk * ((1.f - fi) * a1 + fi * b1);
+}
+
+__device__ inline uint32_t pcg_hash(uint32_t x) {
+    // PCG-derived integer hash (Jarzynski and Olano, "Hash Functions for GPU
+    // Rendering", JCGT 2020)
+    const uint32_t s = x * 747796405u + 2891336453u;
+    const uint32_t w = ((s >> ((s >> 28u) + 4u)) ^ s) * 277803737u;
+    return (w >> 22u) ^ w;
+}
+
+__device__ inline float u01(uint32_t h) { return (float)(h >> 8) * (1.f / 16777216.f); }
+
+// ---------------------------------------------------------------------------
+// Samples: even rows at texel centres and shell radii (exact table values),
+// odd rows uniform in (u, v, rho) with trilinear targets.
+// ---------------------------------------------------------------------------
+template <typename InT>
+__global__ __launch_bounds__(256) void sample_kernel(const InT* __restrict__ tab, Geom g, int64_t n, uint32_t seed,
+                                                     uint32_t step, float4* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t base = pcg_hash(seed ^ pcg_hash(step * 0x9E3779B9u + 0x632BE5ABu)) ^ (uint32_t)(i * 3);
+    const float r1 = u01(pcg_hash(base)), r2 = u01(pcg_hash(base + 1u)), r3 = u01(pcg_hash(base + 2u));
+    float u, v, rho;
+    if ((i & 1) == 0) {
+        const int col = min((int)(r1 * g.W), g.W - 1), row = min((int)(r2 * g.H), g.H - 1);
+        const int k = min((int)(r3 * g.K), g.K - 1);
+        u = -1.f + (2.f * col + 1.f) / (float)g.W;
+        v = -1.f + (2.f * row + 1.f) / (float)g.H;
+        rho = g.spacing == DGSM_SHELLS_GEOMETRIC ? 2.f * (float)k / (float)(g.K - 1) - 1.f
+                                                 : (2.f * (float)k + 1.f) / (float)g.K - 1.f;
+    } else {
+        u = 2.f * r1 - 1.f; v = 2.f * r2 - 1.f; rho = 2.f * r3 - 1.f;
+    }
+    int region;
+    out[i] = make_float4(u, v, rho, atlas_at(tab, g, u, v, rho, region));
+}
+
+// ---------------------------------------------------------------------------
+// Forward
+// ---------------------------------------------------------------------------
+enum Mode { kTrain = 0, kInfer = 1, kCheck = 2 };
+
+struct FwdArgs {
+    Geom g;
+    const float* params;       // [L][kNParams]
+    const __bf16* wb;          // [L][4][128][128]
+    int64_t n;                 // rows
+    const float4* uvrt;        // train / check: [n] (u, v, rho, target)
+    const float* points;       // infer: [n][3]
+    const float* lights;       // infer: [L][3]
+    const void* atlas;         // infer fallback / check: [L][K][H][W]
+    const unsigned char* mask; // infer: [L][regions] or null
+    unsigned char* mask_out;   // check: [regions]
+    float thresh;
+    unsigned int* check_stats; // check: [0] flagged rows, [1] max |dT| (float bits)
+    float* T;                  // infer: [L][n]
+    // train stash
+    __bf16* xt;                // [4][128][n]
+    float* h4;                 // [n][128]
+    float* gz;                 // [n]
+    float* dw4p;               // [n/16][128]
+    float* db4p;               // [n/16]
+    float* lossp;              // [n/16]
+    float inv_n;               // 1 / batch
+    int atlas_f16;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void fwd_kernel(FwdArgs a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    bf16x8* wl = reinterpret_cast<bf16x8*>(smem);                        // [4][128 rows][16 chunks]
+    bf16x8* act = wl + 4 * kH * 16;                                     // [4 waves][16 rows][16 chunks]
+    float4* rin = reinterpret_cast<float4*>(act + kWaves * kRows * 16);   // [4 waves][16] (u, v, rho, target)
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int light = blockIdx.y;
+    const float* P = a.params + (size_t)light * kNParams;
+    const __bf16* Wg = a.wb + (size_t)light * 4 * kH * kH;
+    // all four weight matrices into LDS, swizzled rows
+    for (int q = tid; q < 4 * kH * 16; q += 256) {
+        const int row = q / 16, c = q % 16;                              // row = 128 l + j
+        wl[(row / kH) * kH * 16 + swz(row % kH, c)] = *reinterpret_cast<const bf16x8*>(Wg + (size_t)row * kH + 8 * c);
+    }
+    __syncthreads();
+    bf16x8* my = act + wave * kRows * 16;
+    float4* myin = rin + wave * kRows;
+    const float fscale = __log2f(0.25f * (float)a.g.W) / 15.f;
+    const int ntile = (int)((a.n + kTileRows - 1) / kTileRows);
+    const int lr = lane % 16, lg = lane / 16;
+    for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+        const int64_t row0 = (int64_t)t * kTileRows + wave * kRows;
+        // inputs of the wave's 16 rows
+        if (lane < kRows) {
+            const int64_t rr = row0 + lane;
+            float4 in = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (rr < a.n) {
+                if (MODE == kInfer) {
+                    float r;
+                    encode_point(a.points[3 * rr], a.points[3 * rr + 1], a.points[3 * rr + 2], a.lights + 3 * light,
+                                 a.g, in.x, in.y, in.z, r);
+                } else {
+                    in = a.uvrt[rr];
+                }
+            }
+            myin[lane] = in;
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the wave's LDS writes are visible to its lanes
+        __builtin_amdgcn_wave_barrier();
+        {   // features: lane handles row lr, chunks lg + 4q
+            const float4 in = myin[lr];
+            for (int q = 0; q < 4; ++q) {
+                const int c = lg + 4 * q;
+                bf16x8 ch;
+                for (int e = 0; e < 8; ++e) ch[e] = to_bf16(feature(8 * c + e, in.x, in.y, in.z, fscale));
+                my[swz(lr, c)] = ch;
+                if (MODE == kTrain && row0 + lr < a.n)
+                    for (int e = 0; e < 8; ++e) a.xt[(size_t)(8 * c + e) * a.n + row0 + lr] = ch[e];
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        f32x4 acc[8];
+        for (int l = 0; l < 4; ++l) {
+            const float* bias = P + l * kLayer + kH * kH;
+            for (int n = 0; n < 8; ++n) {
+                const float b = bias[16 * n + lr];
+                acc[n] = f32x4{b, b, b, b};
+            }
+            const bf16x8* W = wl + l * kH * 16;
+            for (int kk = 0; kk < 4; ++kk) {
+                const bf16x8 av = my[swz(lr, lg + 4 * kk)];
+                for (int n = 0; n < 8; ++n) acc[n] = mfma(av, W[swz(16 * n + lr, lg + 4 * kk)], acc[n]);
+            }
+            for (int n = 0; n < 8; ++n)
+                for (int r = 0; r < 4; ++r) acc[n][r] = fmaxf(acc[n][r], 0.f);
+            if (l < 3) {
+                __builtin_amdgcn_wave_barrier();
+                __bf16* myh = reinterpret_cast<__bf16*>(my);
+                for (int n = 0; n < 8; ++n) {
+                    const int col = 16 * n + lr;
+                    __bf16 hb[4];
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 4 * lg + r;
+                        hb[r] = to_bf16(acc[n][r]);
+                        myh[swz(row, col / 8) * 8 + (col % 8)] = hb[r];
+                    }
+                    if (MODE == kTrain && row0 + 4 * lg + 3 < a.n) {
+                        __bf16* dst = a.xt + (size_t)(l + 1) * kH * a.n + (size_t)col * a.n + row0 + 4 * lg;
+                        for (int r = 0; r < 4; ++r) dst[r] = hb[r];
+                    }
+                }
+                __builtin_amdgcn_s_waitcnt(0xc07f);
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        // output layer: z = w4 . h4 + b4 over the 128 columns of each row
+        const float* w4 = P + kOffW4;
+        float zp[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int n = 0; n < 8; ++n) {
+            const float w = w4[16 * n + lr];
+            for (int r = 0; r < 4; ++r) zp[r] += w * acc[n][r];
+        }
+        for (int r = 0; r < 4; ++r)
+            for (int o = 1; o < 16; o <<= 1) zp[r] += __shfl_xor(zp[r], o, kWave);
+        const float b4 = P[kOffB4];
+        float T[4];
+        for (int r = 0; r < 4; ++r) T[r] = 1.f / (1.f + __expf(zp[r] + b4));
+        if (MODE == kTrain) {
+            float gzr[4], lsum = 0.f;
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + 4 * lg + r;
+                const float tgt = myin[4 * lg + r].w;
+                const float d = T[r] - tgt;
+                gzr[r] = row < a.n ? 2.f * d * a.inv_n * (-T[r] * (1.f - T[r])) : 0.f;
+                lsum += row < a.n ? d * d * a.inv_n : 0.f;
+                if (lr == 0 && row < a.n) a.gz[row] = gzr[r];
+            }
+            // h4 stash (FP32) and per-wave partials of dw4, db4, loss
+            const int64_t wid = row0 / kRows;
+            for (int n = 0; n < 8; ++n) {
+                const int col = 16 * n + lr;
+                float s = 0.f;
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row0 + 4 * lg + r;
+                    if (row < a.n) a.h4[(size_t)row * kH + col] = acc[n][r];
+                    s += gzr[r] * acc[n][r];
+                }
+                s += __shfl_xor(s, 16, kWave);
+                s += __shfl_xor(s, 32, kWave);
+                if (lg == 0) a.dw4p[(size_t)wid * kH + col] = s;
+            }
+            float gs = gzr[0] + gzr[1] + gzr[2] + gzr[3];
+            gs += __shfl_xor(gs, 16, kWave);
+            gs += __shfl_xor(gs, 32, kWave);
+            lsum += __shfl_xor(lsum, 16, kWave);
+            lsum += __shfl_xor(lsum, 32, kWave);
+            if (lane == 0) {
+                a.db4p[wid] = gs;
+                a.lossp[wid] = lsum;
+            }
+        } else if (lr < 4) {
+            // lane (lg, lr) finishes row 4 lg + lr
+            const int rr = 4 * lg + lr;
+            const int64_t row = row0 + rr;
+            const float t = lr == 0 ? T[0] : lr == 1 ? T[1] : lr == 2 ? T[2] : T[3];
+            const float4 in = myin[rr];
+            if (row < a.n && a.atlas) {
+                const size_t tsz = (size_t)a.g.K * a.g.H * a.g.W;
+                int region;
+                const float ta = a.atlas_f16
+                                     ? atlas_at(reinterpret_cast<const __half*>(a.atlas) + light * tsz, a.g, in.x,
+                                                in.y, in.z, region)
+                                     : atlas_at(reinterpret_cast<const float*>(a.atlas) + light * tsz, a.g, in.x,
+                                                in.y, in.z, region);
+                if (MODE == kCheck) {
+                    const float err = fabsf(t - in.w);
+                    if (err > a.thresh) {
+                        a.mask_out[region] = 1;
+                        atomicAdd(a.check_stats, 1u);
+                    }
+                    atomicMax(a.check_stats + 1, __float_as_uint(err));
+                } else {
+                    const size_t nreg = (size_t)((a.g.K + 7) / 8) * a.g.ntiles;
+                    const bool fb = a.mask && a.mask[light * nreg + region];
+                    a.T[(size_t)light * a.n + row] = fb ? ta : t;
+                }
+            } else if (row < a.n && MODE == kInfer) {
+                a.T[(size_t)light * a.n + row] = t;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: data gradients through layers 3..1, pre-activation gradients
+// stashed transposed (BF16) for the weight gradients, bias partials.
+// ---------------------------------------------------------------------------
+struct BwdArgs {
+    const float* params;
+    const __bf16* wb;     // [4][128][128]
+    int64_t n;
+    const __bf16* xt;     // [4][128][n]
+    const float* h4;      // [n][128]
+    const float* gz;      // [n]
+    __bf16* dzt;          // [4][128][n]
+    float* dbp;           // [n/16][4][128]
+};
+
+__global__ __launch_bounds__(256) void bwd_kernel(BwdArgs a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    bf16x8* wt = reinterpret_cast<bf16x8*>(smem);                 // [3][128 cols j][16 chunks of k]: W_l^T, l = 1..3
+    bf16x8* act = wt + 3 * kH * 16;                               // [4 waves][16 rows][16 chunks]
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    __bf16* wth = reinterpret_cast<__bf16*>(wt);
+    for (int q = tid; q < 3 * kH * kH; q += 256) {
+        const int l = q / (kH * kH), rem = q % (kH * kH), k = rem / kH, j = rem % kH;   // W_{l+1}[k][j]
+        wth[(l * kH * 16 + swz(j, k / 8)) * 8 + (k % 8)] = a.wb[(size_t)(l + 1) * kH * kH + (size_t)k * kH + j];
+    }
+    __syncthreads();
+    bf16x8* my = act + wave * kRows * 16;
+    __bf16* myh = reinterpret_cast<__bf16*>(my);
+    const int lr = lane % 16, lg = lane / 16;
+    const float* w4 = a.params + kOffW4;
+    const int ntile = (int)((a.n + kTileRows - 1) / kTileRows);
+    for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
+        const int64_t row0 = (int64_t)t * kTileRows + wave * kRows;
+        if (row0 >= a.n) continue;            // n is a multiple of 16: a wave's rows are all in or all out
+        const int64_t wid = row0 / kRows;
+        f32x4 da[8];
+        // layer 3: da3 = gz w4 (h4 > 0)
+        float g[4];
+        for (int r = 0; r < 4; ++r) g[r] = a.gz[row0 + 4 * lg + r];
+        for (int n = 0; n < 8; ++n) {
+            const int col = 16 * n + lr;
+            const float w = w4[col];
+            for (int r = 0; r < 4; ++r) {
+                const float h = a.h4[(size_t)(row0 + 4 * lg + r) * kH + col];
+                da[n][r] = h > 0.f ? g[r] * w : 0.f;
+            }
+        }
+        for (int l = 3; l >= 0; --l) {
+            // stash bf16(da_l) transposed, bias partial, and the MFMA A operand
+            __builtin_amdgcn_wave_barrier();
+            for (int n = 0; n < 8; ++n) {
+                const int col = 16 * n + lr;
+                float s = 0.f;
+                __bf16* dst = a.dzt + (size_t)l * kH * a.n + (size_t)col * a.n + row0 + 4 * lg;
+                for (int r = 0; r < 4; ++r) {
+                    const __bf16 b = to_bf16(da[n][r]);
+                    dst[r] = b;
+                    myh[swz(4 * lg + r, col / 8) * 8 + (col % 8)] = b;
+                    s += da[n][r];
+                }
+                s += __shfl_xor(s, 16, kWave);
+                s += __shfl_xor(s, 32, kWave);
+                if (lg == 0) a.dbp[((size_t)wid * 4 + l) * kH + col] = s;
+            }
+            if (l == 0) break;
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            __builtin_amdgcn_wave_barrier();
+            // dx_l = da_l W_l ; da_{l-1} = dx_l (x_l > 0)
+            const bf16x8* Wt = wt + (l - 1) * kH * 16;
+            f32x4 dx[8];
+            for (int n = 0; n < 8; ++n) dx[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int kk = 0; kk < 4; ++kk) {
+                const bf16x8 av = my[swz(lr, lg + 4 * kk)];
+                for (int n = 0; n < 8; ++n) dx[n] = mfma(av, Wt[swz(16 * n + lr, lg + 4 * kk)], dx[n]);
+            }
+            for (int n = 0; n < 8; ++n) {
+                const int col = 16 * n + lr;
+                const __bf16* xs = a.xt + (size_t)l * kH * a.n + (size_t)col * a.n + row0 + 4 * lg;
+                for (int r = 0; r < 4; ++r) da[n][r] = (float)xs[r] > 0.f ? dx[n][r] : 0.f;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradients: partial dW_l over one chunk of rows, MFMA over the rows.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void wgrad_kernel(const __bf16* __restrict__ dzt, const __bf16* __restrict__ xt,
+                                                    int64_t n, int chunk, float* __restrict__ dwp) {
+    const int c = blockIdx.x, l = blockIdx.y;
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int lr = lane % 16, lg = lane / 16;
+    const int64_t k0 = (int64_t)c * chunk, k1 = min((int64_t)(c + 1) * chunk, n);
+    const __bf16* Z = dzt + (size_t)l * kH * n;
+    const __bf16* X = xt + (size_t)l * kH * n;
+    f32x4 acc[2][8];
+    for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 8; ++q) acc[m][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t k = k0; k < k1; k += 32) {
+        const int64_t kl = k + 8 * lg;
+        bf16x8 am[2], bq[8];
+        for (int m = 0; m < 2; ++m)
+            am[m] = *reinterpret_cast<const bf16x8*>(Z + (size_t)(32 * wave + 16 * m + lr) * n + kl);
+        for (int q = 0; q < 8; ++q) bq[q] = *reinterpret_cast<const bf16x8*>(X + (size_t)(16 * q + lr) * n + kl);
+        for (int m = 0; m < 2; ++m)
+            for (int q = 0; q < 8; ++q) acc[m][q] = mfma(am[m], bq[q], acc[m][q]);
+    }
+    float* out = dwp + ((size_t)c * 4 + l) * kH * kH;
+    for (int m = 0; m < 2; ++m)
+        for (int q = 0; q < 8; ++q)
+            for (int r = 0; r < 4; ++r)
+                out[(size_t)(32 * wave + 16 * m + 4 * lg + r) * kH + 16 * q + lr] = acc[m][q][r];
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-order gradient reduction, optional Adam, BF16 weight copies.
+// ---------------------------------------------------------------------------
+struct ReduceArgs {
+    float* params;          // updated in place when adam
+    float* m;               // [kNParams] (adam)
+    float* v;
+    __bf16* wb;             // [4][128][128] refreshed BF16 weights
+    const float* dwp;       // [nchunk][4][128][128]
+    int nchunk;
+    const float* dbp;       // [nw][4][128]
+    const float* dw4p;      // [nw][128]
+    const float* db4p;      // [nw]
+    const float* lossp;     // [nw]
+    int nw;
+    float* grad_out;        // optional [kNParams]
+    float* loss_out;        // optional [1]
+    int adam;
+    float lr, beta1, beta2, eps, bc1, bc2;   // bc = 1 - beta^t
+};
+
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p == 0 && a.loss_out) {
+        float s = 0.f;
+        for (int w = 0; w < a.nw; ++w) s += a.lossp[w];
+        *a.loss_out = s;
+    }
+    if (p >= kNParams) return;
+    float g = 0.f;
+    int wl = -1, wi = 0;
+    if (p < kOffW4) {
+        const int l = p / kLayer, q = p % kLayer;
+        if (q < kH * kH) {
+            for (int c = 0; c < a.nchunk; ++c) g += a.dwp[((size_t)c * 4 + l) * kH * kH + q];
+            wl = l;
+            wi = q;
+        } else {
+            const int i = q - kH * kH;
+            for (int w = 0; w < a.nw; ++w) g += a.dbp[((size_t)w * 4 + l) * kH + i];
+        }
+    } else if (p < kOffB4) {
+        const int i = p - kOffW4;
+        for (int w = 0; w < a.nw; ++w) g += a.dw4p[(size_t)w * kH + i];
+    } else {
+        for (int w = 0; w < a.nw; ++w) g += a.db4p[w];
+    }
+    if (a.grad_out) a.grad_out[p] = g;
+    float val = a.params[p];
+    if (a.adam) {
+        const float m = a.beta1 * a.m[p] + (1.f - a.beta1) * g;
+        const float v = a.beta2 * a.v[p] + (1.f - a.beta2) * g * g;
+        a.m[p] = m;
+        a.v[p] = v;
+        val -= a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
+        if (wl == 0 && (wi % kH) >= kDin) val = 0.f;   // padded feature columns stay zero
+        a.params[p] = val;
+    }
+    if (wl >= 0 && a.wb) a.wb[(size_t)wl * kH * kH + wi] = to_bf16(val);
+}
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float* __restrict__ params, int L,
+                                                      __bf16* __restrict__ wb) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= (int64_t)L * 4 * kH * kH) return;
+    const int64_t light = q / (4 * kH * kH), r = q % (4 * kH * kH);
+    const int l = (int)(r / (kH * kH)), e = (int)(r % (kH * kH));
+    wb[q] = to_bf16(params[light * kNParams + l * kLayer + e]);
+}
+
+}  // namespace mlp
+}  // namespace dgsm
+
+using namespace dgsm;
+using namespace dgsm::mlp;
+
+namespace {
+
+constexpr int kChunk = 512;   // rows per weight-gradient partial
+
+struct TrainWs {
+    float4* uvrt;
+    __bf16 *xt, *dzt, *wb;
+    float *h4, *gz, *dwp, *dbp, *dw4p, *db4p, *lossp;
+    int nchunk, nw;
+    size_t total;
+};
+
+TrainWs train_ws(unsigned char* base, int64_t B) {
+    TrainWs w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char* p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    w.nchunk = (int)((B + kChunk - 1) / kChunk);
+    w.nw = (int)(B / kRows);
+    w.uvrt = reinterpret_cast<float4*>(take(sizeof(float4) * B));
+    w.xt = reinterpret_cast<__bf16*>(take(2 * 4 * kH * (size_t)B));
+    w.dzt = reinterpret_cast<__bf16*>(take(2 * 4 * kH * (size_t)B));
+    w.wb = reinterpret_cast<__bf16*>(take(2 * 4 * kH * kH));
+    w.h4 = reinterpret_cast<float*>(take(4 * kH * (size_t)B));
+    w.gz = reinterpret_cast<float*>(take(4 * (size_t)B));
+    w.dwp = reinterpret_cast<float*>(take(4 * (size_t)w.nchunk * 4 * kH * kH));
+    w.dbp = reinterpret_cast<float*>(take(4 * (size_t)w.nw * 4 * kH));
+    w.dw4p = reinterpret_cast<float*>(take(4 * (size_t)w.nw * kH));
+    w.db4p = reinterpret_cast<float*>(take(4 * (size_t)w.nw));
+    w.lossp = reinterpret_cast<float*>(take(4 * (size_t)w.nw));
+    w.total = off;
+    return w;
+}
+
+constexpr size_t kFwdSmem = (size_t)(4 * kH * 16 + kWaves * kRows * 16) * 16 + kWaves * kRows * 16;
+constexpr size_t kBwdSmem = (size_t)(3 * kH * 16 + kWaves * kRows * 16) * 16;
+
+int grid_rows(int64_t n) {
+    const int64_t t = (n + kTileRows - 1) / kTileRows;
+    return (int)(t < 1024 ? (t < 1 ? 1 : t) : 1024);
+}
+
+hipError_t set_smem() {
+    static const hipError_t e = [] {
+        hipError_t r = hipFuncSetAttribute((const void*)fwd_kernel<kTrain>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)kFwdSmem);
+        if (r == hipSuccess)
+            r = hipFuncSetAttribute((const void*)fwd_kernel<kInfer>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kFwdSmem);
+        if (r == hipSuccess)
+            r = hipFuncSetAttribute((const void*)fwd_kernel<kCheck>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kFwdSmem);
+        if (r == hipSuccess)
+            r = hipFuncSetAttribute((const void*)bwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kBwdSmem);
+        return r;
+    }();
+    return e;
+}
+
+// forward (train) + backward + weight gradients on the samples in w.uvrt
+dgsm_status enqueue_fwd_bwd(const float* params, const Geom& g, int64_t B, const TrainWs& w, hipStream_t st) {
+    FwdArgs f{};
+    f.g = g;
+    f.params = params;
+    f.wb = w.wb;
+    f.n = B;
+    f.uvrt = w.uvrt;
+    f.xt = w.xt;
+    f.h4 = w.h4;
+    f.gz = w.gz;
+    f.dw4p = w.dw4p;
+    f.db4p = w.db4p;
+    f.lossp = w.lossp;
+    f.inv_n = 1.f / (float)B;
+    fwd_kernel<kTrain><<<dim3(grid_rows(B), 1), 256, kFwdSmem, st>>>(f);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    BwdArgs b{params, w.wb, B, w.xt, w.h4, w.gz, w.dzt, w.dbp};
+    bwd_kernel<<<grid_rows(B), 256, kBwdSmem, st>>>(b);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    wgrad_kernel<<<dim3(w.nchunk, 4), 256, 0, st>>>(w.dzt, w.xt, B, kChunk, w.dwp);
+    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
+}
+
+Geom geom_of(const dgsm_atlas_desc_t* d) { return make_geom(*d); }
+
+}  // namespace
+
+extern "C" size_t dgsm_mlp_workspace_size(int64_t batch) {
+    if (batch < 32 || batch % 32) return 0;
+    return train_ws(nullptr, batch).total;
+}
+
+extern "C" dgsm_status dgsm_mlp_grad(const float* params, const float* uvrt, int64_t B,
+                                     const dgsm_atlas_desc_t* desc, float* grad, float* loss, void* ws,
+                                     size_t ws_bytes, void* stream) {
+    dgsm_status st = validate_desc(desc);
+    if (st != DGSM_OK) return st;
+    if (!params || !uvrt || !grad || B < 32 || B % 32) return DGSM_EINVAL;
+    const TrainWs w = train_ws(reinterpret_cast<unsigned char*>(ws), B);
+    if (!ws || ws_bytes < w.total) return DGSM_EWORKSPACE;
+    if (set_smem() != hipSuccess) return DGSM_EHIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(w.uvrt, uvrt, sizeof(float4) * B, hipMemcpyDeviceToDevice, s) != hipSuccess) return DGSM_EHIP;
+    to_bf16_kernel<<<(4 * kH * kH + 255) / 256, 256, 0, s>>>(params, 1, w.wb);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    if ((st = enqueue_fwd_bwd(params, geom_of(desc), B, w, s)) != DGSM_OK) return st;
+    ReduceArgs r{};
+    r.params = const_cast<float*>(params);
+    r.dwp = w.dwp; r.nchunk = w.nchunk; r.dbp = w.dbp; r.dw4p = w.dw4p; r.db4p = w.db4p; r.lossp = w.lossp;
+    r.nw = w.nw; r.grad_out = grad; r.loss_out = loss; r.adam = 0;
+    reduce_kernel<<<(kNParams + 255) / 256, 256, 0, s>>>(r);
+    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
+}
+
+extern "C" dgsm_status dgsm_mlp_train(float* params, float* adam_mv, const dgsm_atlas_desc_t* desc,
+                                      const void* atlas_l, const dgsm_mlp_train_t* opt, float* loss_out, void* ws,
+                                      size_t ws_bytes, void* stream) {
+    dgsm_status st = validate_desc(desc);
+    if (st != DGSM_OK) return st;
+    if (!params || !adam_mv || !atlas_l || !opt || opt->steps < 0 || opt->batch < 32 || opt->batch % 32)
+        return DGSM_EINVAL;
+    const int64_t B = opt->batch;
+    const TrainWs w = train_ws(reinterpret_cast<unsigned char*>(ws), B);
+    if (!ws || ws_bytes < w.total) return DGSM_EWORKSPACE;
+    if (set_smem() != hipSuccess) return DGSM_EHIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Geom g = geom_of(desc);
+    to_bf16_kernel<<<(4 * kH * kH + 255) / 256, 256, 0, s>>>(params, 1, w.wb);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    for (int i = 0; i < opt->steps; ++i) {
+        const int t = opt->step0 + i + 1;   // Adam step count
+        const unsigned blocks = (unsigned)((B + 255) / 256);
+        if (desc->dtype == DGSM_F16)
+            sample_kernel<__half><<<blocks, 256, 0, s>>>(reinterpret_cast<const __half*>(atlas_l), g, B, opt->seed,
+                                                        (uint32_t)t, w.uvrt);
+        else
+            sample_kernel<float><<<blocks, 256, 0, s>>>(reinterpret_cast<const float*>(atlas_l), g, B, opt->seed,
+                                                       (uint32_t)t, w.uvrt);
+        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+        if ((st = enqueue_fwd_bwd(params, g, B, w, s)) != DGSM_OK) return st;
+        // cosine decay from lr0 to lr1 over the steps of this call
+        const double ph = opt->steps > 1 ? (double)i / (double)(opt->steps - 1) : 0.0;
+        const float lr = (float)(opt->lr1 + 0.5 * (opt->lr0 - opt->lr1) * (1.0 + cos(3.141592653589793 * ph)));
+        ReduceArgs r{};
+        r.params = params; r.m = adam_mv; r.v = adam_mv + kNParams; r.wb = w.wb;
+        r.dwp = w.dwp; r.nchunk = w.nchunk; r.dbp = w.dbp; r.dw4p = w.dw4p; r.db4p = w.db4p; r.lossp = w.lossp;
+        r.nw = w.nw; r.loss_out = loss_out ? loss_out + i : nullptr; r.adam = 1;
+        r.lr = lr; r.beta1 = opt->beta1; r.beta2 = opt->beta2; r.eps = opt->eps;
+        r.bc1 = (float)(1.0 - pow((double)opt->beta1, (double)t));
+        r.bc2 = (float)(1.0 - pow((double)opt->beta2, (double)t));
+        reduce_kernel<<<(kNParams + 255) / 256, 256, 0, s>>>(r);
+        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    }
+    return DGSM_OK;
+}
+
+extern "C" size_t dgsm_mlp_infer_workspace_size(int32_t n_lights) {
+    return n_lights < 1 ? 0 : (size_t)n_lights * 4 * kH * kH * sizeof(__bf16);
+}
+
+extern "C" dgsm_status dgsm_mlp_check(const float* params, const dgsm_atlas_desc_t* desc, const void* atlas_l,
+                                      int64_t n_check, uint32_t seed, float thresh, unsigned char* mask,
+                                      unsigned int* stats, void* ws, size_t ws_bytes, void* stream) {
+    dgsm_status st = validate_desc(desc);
+    if (st != DGSM_OK) return st;
+    if (!params || !atlas_l || !mask || !stats || n_check < 1) return DGSM_EINVAL;
+    const size_t need = dgsm_mlp_infer_workspace_size(1) + ((sizeof(float4) * n_check + 255) & ~(size_t)255);
+    if (!ws || ws_bytes < need) return DGSM_EWORKSPACE;
+    if (set_smem() != hipSuccess) return DGSM_EHIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Geom g = geom_of(desc);
+    __bf16* wb = reinterpret_cast<__bf16*>(ws);
+    float4* uvrt = reinterpret_cast<float4*>(reinterpret_cast<unsigned char*>(ws) + dgsm_mlp_infer_workspace_size(1));
+    to_bf16_kernel<<<(4 * kH * kH + 255) / 256, 256, 0, s>>>(params, 1, wb);
+    const unsigned blocks = (unsigned)((n_check + 255) / 256);
+    if (desc->dtype == DGSM_F16)
+        sample_kernel<__half><<<blocks, 256, 0, s>>>(reinterpret_cast<const __half*>(atlas_l), g, n_check, seed,
+                                                    0xFFFFFFFFu, uvrt);
+    else
+        sample_kernel<float><<<blocks, 256, 0, s>>>(reinterpret_cast<const float*>(atlas_l), g, n_check, seed,
+                                                   0xFFFFFFFFu, uvrt);
+    FwdArgs f{};
+    f.g = g; f.params = params; f.wb = wb; f.n = n_check; f.uvrt = uvrt; f.atlas = atlas_l;
+    f.mask_out = mask; f.thresh = thresh; f.check_stats = stats; f.atlas_f16 = desc->dtype == DGSM_F16;
+    fwd_kernel<kCheck><<<dim3(grid_rows(n_check), 1), 256, kFwdSmem, s>>>(f);
+    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
+}
+
+extern "C" dgsm_status dgsm_mlp_infer(const float* params, const dgsm_lights_t* lights,
+                                      const dgsm_atlas_desc_t* desc, const void* atlas, const unsigned char* mask,
+                                      const float* points, int64_t P, float* T, void* ws, size_t ws_bytes,
+                                      void* stream) {
+    dgsm_status st = validate_desc(desc);
+    if (st != DGSM_OK) return st;
+    if ((st = validate_lights(lights)) != DGSM_OK) return st;
+    if (!params || P < 0 || (P > 0 && (!points || !T)) || (mask && !atlas)) return DGSM_EINVAL;
+    if (!ws || ws_bytes < dgsm_mlp_infer_workspace_size(lights->n)) return DGSM_EWORKSPACE;
+    if (P == 0) return DGSM_OK;
+    if (set_smem() != hipSuccess) return DGSM_EHIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    __bf16* wb = reinterpret_cast<__bf16*>(ws);
+    const int64_t nw = (int64_t)lights->n * 4 * kH * kH;
+    to_bf16_kernel<<<(unsigned)((nw + 255) / 256), 256, 0, s>>>(params, lights->n, wb);
+    FwdArgs f{};
+    f.g = geom_of(desc); f.params = params; f.wb = wb; f.n = P; f.points = points; f.lights = lights->pos;
+    f.atlas = mask ? atlas : nullptr; f.mask = mask; f.T = T; f.atlas_f16 = desc->dtype == DGSM_F16;
+    fwd_kernel<kInfer><<<dim3(grid_rows(P), lights->n), 256, kFwdSmem, s>>>(f);
+    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
+}

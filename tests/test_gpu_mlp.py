@@ -1,0 +1,100 @@
+"""GPU: the BF16-MFMA transmittance network against the FP64 oracle (with the
+same BF16 roundings emulated), and its training on a DGSM atlas."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import dgsm as od
+from oracle import mlp as om
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_01660_amd as P
+    P.lib()
+
+
+def _params(seed, noise=0.05):
+    p = om.init_params(seed).astype(np.float64)
+    rng = np.random.default_rng(seed + 100)
+    p = p + noise * rng.standard_normal(p.shape) * (np.abs(p) > 0)     # keep padded columns at zero
+    p[om.N_PARAMS - 1] = 0.3
+    return p.astype(np.float32)
+
+
+def _samples(seed, B):
+    rng = np.random.default_rng(seed)
+    uvr = rng.uniform(-1, 1, (B, 3))
+    t = rng.uniform(0, 1, B)
+    return np.column_stack([uvr, t]).astype(np.float32)
+
+
+@pytest.mark.parametrize("B", [64, 256])
+def test_gradient_matches_bf16_emulated_oracle(B):
+    import paper_2601_01660_amd as P
+    atlas = P.Atlas(64, 64, 16)
+    flat = _params(1)
+    x = _samples(2, B)
+    grad, loss = P.mlp_grad(torch.from_numpy(flat), torch.from_numpy(x), atlas)
+    torch.cuda.synchronize()
+    g_gpu = grad.cpu().numpy().astype(np.float64)
+    phi = om.features(x[:, 0].astype(np.float64), x[:, 1].astype(np.float64), x[:, 2].astype(np.float64), 64)
+    T, cache = om.forward(flat, phi, bf16_emulation=True)
+    g_ref = om.backward(flat, cache, x[:, 3].astype(np.float64), bf16_emulation=True)
+    assert abs(loss.item() - om.loss(T, x[:, 3])) <= 1e-5 * max(1.0, om.loss(T, x[:, 3]))
+    ref = om.unpack(g_ref)
+    got = om.unpack(g_gpu)
+    for k in ["W0", "b0", "W1", "b1", "W2", "b2", "W3", "b3", "w4", "b4"]:
+        r, gv = np.atleast_1d(ref[k]), np.atleast_1d(got[k])
+        rel = np.linalg.norm(gv - r) / max(np.linalg.norm(r), 1e-12)
+        print(f"[mlp] B={B} grad {k}: rel err {rel:.2e}", flush=True)
+        assert rel <= 5e-3, k
+
+
+def test_forward_matches_oracle_at_points():
+    import paper_2601_01660_amd as P
+    atlas = P.Atlas(64, 64, 16)
+    flat = _params(3)
+    rng = np.random.default_rng(4)
+    pts = rng.uniform(-4, 4, (1000, 3)).astype(np.float32)
+    light = np.array([[0.2, -0.1, 0.3]], np.float32)
+    T = P.mlp_infer(torch.from_numpy(flat), torch.from_numpy(light), atlas, torch.from_numpy(pts))
+    torch.cuda.synchronize()
+    u, v, rho = om.encode_points(pts, light[0], 0.05, 8.0)
+    ref, _ = om.forward(flat, om.features(u, v, rho, 64), bf16_emulation=True)
+    err = np.abs(T[0].cpu().numpy() - ref).max()
+    print(f"[mlp] forward max|dT| = {err:.2e}", flush=True)
+    assert err <= 2e-3
+
+
+def test_training_fits_an_atlas_and_fallback_covers_the_rest():
+    import paper_2601_01660_amd as P
+    # a smooth-ish shadow field: few large Gaussians around one light
+    rng = np.random.default_rng(5)
+    g = synth.random_gaussians(rng, rng.uniform(-2, 2, (60, 3)), 0.35)
+    lights = np.array([[0.0, 0.0, 0.0]], np.float32)
+    atlas = P.Atlas(64, 64, 32)
+    table = P.dgsm_build(torch.from_numpy(lights), P.GaussianSet.from_host(g), atlas)
+    params = torch.from_numpy(om.init_params(6)).cuda()
+    mv = torch.zeros(2 * om.N_PARAMS, device="cuda")
+    losses = P.mlp_train(params, mv, atlas, table[0], steps=600, batch=4096, lr0=2e-3, lr1=1e-4, seed=7)
+    torch.cuda.synchronize()
+    lh = losses.cpu().numpy()
+    print(f"[mlp] loss first {lh[:10].mean():.3e} last {lh[-10:].mean():.3e}", flush=True)
+    assert np.all(np.isfinite(lh)) and lh[-10:].mean() < 0.2 * lh[:10].mean()
+    mask, nbad, maxerr = P.mlp_check(params, atlas, table[0], n_check=65536, seed=99, thresh=1e-2)
+    pts = rng.uniform(-3, 3, (20000, 3)).astype(np.float32)
+    Tq = P.dgsm_query(torch.from_numpy(lights), atlas, table, torch.from_numpy(pts))
+    Ts = P.mlp_infer(params, torch.from_numpy(lights), atlas, torch.from_numpy(pts), table=table, mask=mask)
+    Tn = P.mlp_infer(params, torch.from_numpy(lights), atlas, torch.from_numpy(pts))
+    torch.cuda.synchronize()
+    e_fb = (Ts - Tq).abs().max().item()
+    e_raw = (Tn - Tq).abs().mean().item()
+    print(f"[mlp] held-out flagged {nbad}, max|dT| {maxerr:.3e}, regions {int(mask.sum())}/{mask.numel()}; "
+          f"surrogate+fallback vs atlas max {e_fb:.3e}; raw network mean {e_raw:.3e}", flush=True)
+    assert e_raw < 0.05
