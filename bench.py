@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--frames", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-texels", type=int, default=40)
+    ap.add_argument("--mlp-steps", type=int, default=1500, help="Adam steps per light for the surrogate")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -77,6 +81,56 @@ def cpu_baseline(scene, avatar, lights, spec, n_texels):
             "sample": (f"{n_texels} texels x {spec.K} shells of light 0 over all {g.n} Gaussians "
                        f"({t_texel:.3f} s/texel) + FP64 trilinear query of 200000 points; "
                        f"extrapolated linearly to {L} lights x {spec.H}x{spec.W} texels + {L} x {g.n} queries")}
+
+
+def surrogate_leg(P, torch, np, dev, lights, atlas, static_set, dyn_set, tr, N, L, spec, steps, timed):
+    """Per-light learned field trained on frame 0's atlases; surrogate vs atlas query."""
+    import synth
+    g0 = P.GaussianSet(torch.cat([static_set.mean, dyn_set.mean + tr[0]]), torch.cat([static_set.scale, dyn_set.scale]),
+                       torch.cat([static_set.rot, dyn_set.rot]), torch.cat([static_set.opacity, dyn_set.opacity]))
+    table = P.dgsm_build(lights, g0, atlas)
+    params = torch.stack([torch.from_numpy(synth.mlp_init_params(100 + l)) for l in range(L)]).to(dev)
+    t0 = time.perf_counter()
+    final_loss, masks, flagged, maxerr = [], [], [], []
+    for l in range(L):
+        mv = torch.zeros(2 * P.MLP_PARAMS, device=dev)
+        losses = P.mlp_train(params[l], mv, atlas, table[l], steps=steps, batch=16384, lr0=2e-3, lr1=5e-5,
+                             seed=1000 + l)
+        final_loss.append(float(losses[-20:].mean()))
+        m, nbad, me = P.mlp_check(params[l], atlas, table[l], n_check=262144 + (spec.H * spec.W * spec.K) // 100,
+                                  seed=77 + l, thresh=1e-2)
+        masks.append(m)
+        flagged.append(nbad)
+        maxerr.append(me)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    mask = torch.stack(masks)
+    pts = g0.mean
+    Tq = torch.empty((L, N), dtype=torch.float32, device=dev)
+    Ts = torch.empty_like(Tq)
+    ws = torch.empty(int(P.lib().dgsm_mlp_infer_workspace_size(L)), dtype=torch.uint8, device=dev)
+    P.dgsm_query(lights, atlas, table, pts, out=Tq)
+    P.mlp_infer(params, lights, atlas, pts, table=table, mask=mask, out=Ts, workspace=ws)
+    torch.cuda.synchronize()
+    ms_atlas = timed(lambda: P.dgsm_query(lights, atlas, table, pts, out=Tq), 5)
+    ms_surr = timed(lambda: P.mlp_infer(params, lights, atlas, pts, table=table, mask=mask, out=Ts, workspace=ws), 5)
+    Tn = P.mlp_infer(params, lights, atlas, pts, workspace=ws)
+    d = (Ts - Tq).abs()
+    dn = (Tn - Tq).abs()
+    torch.cuda.synchronize()
+    log(f"surrogate: train {train_s:.1f} s, final losses {final_loss}, query {ms_atlas:.3f} ms vs "
+        f"surrogate {ms_surr:.3f} ms, max|dT| {d.max().item():.3e}")
+    return {"ms_per_frame_surrogate_inference": round(ms_surr, 4), "ms_per_frame_atlas_query": round(ms_atlas, 4),
+            "max_abs_dT_vs_atlas": round(d.max().item(), 6), "mean_abs_dT_vs_atlas": round(d.mean().item(), 7),
+            "network_only_mean_abs_dT": round(dn.mean().item(), 7),
+            "points_above_1e-2_with_fallback": int((d > 1e-2).sum().item()),
+            "fallback_region_fraction": round(float(mask.float().mean().item()), 4),
+            "held_out_flagged_samples": flagged, "held_out_max_abs_dT": [round(x, 5) for x in maxerr],
+            "train_steps_per_light": steps, "train_batch": 16384, "train_seconds": round(train_s, 2),
+            "final_train_loss": [round(x, 7) for x in final_loss],
+            "bytes_network_per_light": P.MLP_PARAMS * 4, "bytes_atlas_per_light": spec.K * spec.H * spec.W * 2,
+            "note": "per-light network trained on the frame-0 atlases; surrogate timing includes the atlas "
+                    "fallback in flagged regions"}
 
 
 def main():
@@ -219,6 +273,15 @@ def main():
                                        "batched_graph_no_cache": round(ms_nocache / F, 4),
                                        "plain_per_frame_launches": round(ms_plain / F, 4)},
            "roofline": roofline}
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_leg(P, torch, np, dev, lights, atlas, static_set, dyn_set, tr, N, L, spec,
+                                         args.mlp_steps, timed)
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * a.numel() * 4
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(scene, avatar, lights_h, spec, args.cpu_texels)

@@ -71,23 +71,6 @@ def pack(p):
     return np.concatenate(parts).astype(np.float64)
 
 
-def init_params(seed, in_live=D_IN):
-    """He-uniform weights (padded input columns zero), zero biases, b4 = -2."""
-    rng = np.random.default_rng(seed)
-    p = {}
-    for l in range(N_HIDDEN):
-        fan_in = in_live if l == 0 else H
-        lim = math.sqrt(6.0 / fan_in)
-        W = rng.uniform(-lim, lim, (H, H))
-        if l == 0:
-            W[:, in_live:] = 0.0
-        p[f"W{l}"] = W
-        p[f"b{l}"] = np.zeros(H)
-    p["w4"] = rng.uniform(-math.sqrt(3.0 / H), math.sqrt(3.0 / H), H)
-    p["b4"] = -2.0
-    return pack(p).astype(np.float32)
-
-
 def encode_points(points, light, r0, r1, spacing="geometric"):
     """(u, v, rho) of world points for one light."""
     d = np.asarray(points, np.float64) - np.asarray(light, np.float64)

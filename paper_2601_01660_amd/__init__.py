@@ -131,6 +131,13 @@ def _ptr(t):
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+def _cuda(t, name):
+    """Require an existing CUDA tensor (buffers the library writes in place)."""
+    if t is not None and (not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous CUDA tensor")
+    return t
+
+
 def _dev(t, dtype=torch.float32):
     if t is None:
         return None
@@ -162,6 +169,11 @@ class GaussianSet:
         return GaussianSet(_dev(g.mean), _dev(g.scale), _dev(g.rot), _dev(g.opacity))
 
     def struct(self) -> _Gaussians:
+        for f in ("mean", "scale", "rot", "opacity"):
+            t = getattr(self, f)
+            _cuda(t, f"GaussianSet.{f}")
+            if t.dtype != torch.float32:
+                raise ValueError(f"GaussianSet.{f} must be float32")
         return _Gaussians(self.mean.data_ptr(), self.scale.data_ptr(), self.rot.data_ptr(),
                           self.opacity.data_ptr(), self.n)
 
@@ -211,6 +223,8 @@ def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0,
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=lights.device)
     if out is None:
         out = torch.empty((L, atlas.K, atlas.H, atlas.W), dtype=atlas.torch_dtype, device=lights.device)
+    _cuda(out, "out")
+    _cuda(workspace, "workspace")
     lt = _Lights(lights.data_ptr(), L, kappa)
     gs = gaussians.struct()
     _check(lib().dgsm_build(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), _ptr(out), _ptr(workspace),
@@ -221,6 +235,7 @@ def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0,
 def dgsm_bin(lights, gaussians: GaussianSet, atlas: Atlas, workspace, kappa: float = 1.0):
     """First build phase: culling cones and supertile lists into ``workspace``."""
     lights = _dev(lights)
+    _cuda(workspace, "workspace")
     d = atlas.struct()
     lt = _Lights(lights.data_ptr(), int(lights.shape[0]), kappa)
     gs = gaussians.struct()
@@ -234,6 +249,9 @@ def dgsm_accumulate(lights, atlas: Atlas, n_gauss: int, out, workspace, stats=No
     ``stats`` (optional int64 CUDA tensor [4], zeroed by the caller) receives the
     pair counters documented in dgsm.h."""
     lights = _dev(lights)
+    _cuda(out, "out")
+    _cuda(workspace, "workspace")
+    _cuda(stats, "stats")
     d = atlas.struct()
     lt = _Lights(lights.data_ptr(), int(lights.shape[0]), 1.0)
     _check(lib().dgsm_accumulate(ctypes.byref(lt), ctypes.byref(d), n_gauss, _ptr(out), _ptr(workspace),
@@ -249,6 +267,8 @@ def dgsm_query(lights, atlas: Atlas, table, points, out=None):
     P = int(points.shape[0])
     if out is None:
         out = torch.empty((L, P), dtype=torch.float32, device=points.device)
+    _cuda(out, "out")
+    _cuda(table, "table")
     d = atlas.struct()
     lt = _Lights(lights.data_ptr(), L, 1.0)
     _check(lib().dgsm_query(ctypes.byref(lt), ctypes.byref(d), _ptr(table), _ptr(points), P, _ptr(out), _stream()))
@@ -318,6 +338,7 @@ class Plan:
     def run(self, dynamic: GaussianSet, translations, out=None, use_graph: bool = True):
         """T[frames, L, n_static + n_dynamic] for one run; enqueued on the current stream."""
         translations = _dev(translations)
+        _cuda(out, "out")
         if out is None:
             out = torch.empty((self.frames, self.L, self.n_points), dtype=torch.float32,
                               device=translations.device)
@@ -362,6 +383,9 @@ def mlp_grad(params, uvrt, atlas: Atlas, grad=None, loss=None, workspace=None):
 def mlp_train(params, adam_mv, atlas: Atlas, table_l, steps, batch=16384, step0=0, lr0=1e-3, lr1=1e-4,
               seed=1, beta1=0.9, beta2=0.999, eps=1e-8, workspace=None):
     """``steps`` Adam steps (in place on params / adam_mv); returns the per-step losses."""
+    _cuda(params, "params")
+    _cuda(adam_mv, "adam_mv")
+    _cuda(table_l, "table_l")
     need = int(lib().dgsm_mlp_workspace_size(batch))
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=params.device)
@@ -379,6 +403,8 @@ def mlp_regions(atlas: Atlas) -> int:
 
 def mlp_check(params, atlas: Atlas, table_l, n_check=262144, seed=12345, thresh=1e-2):
     """Fallback mask [regions] (uint8) and (flagged samples, max |dT|) on a held-out sample set."""
+    params = _dev(params)
+    _cuda(table_l, "table_l")
     dev = params.device
     mask = torch.zeros(mlp_regions(atlas), dtype=torch.uint8, device=dev)
     stats = torch.zeros(2, dtype=torch.int32, device=dev)
@@ -394,7 +420,13 @@ def mlp_check(params, atlas: Atlas, table_l, n_check=262144, seed=12345, thresh=
 
 def mlp_infer(params, lights, atlas: Atlas, points, table=None, mask=None, out=None, workspace=None):
     """T[L, P] of each light's network at points; flagged regions fall back to the atlas."""
-    lights, points = _dev(lights), _dev(points)
+    params, lights, points = _dev(params), _dev(lights), _dev(points)
+    _cuda(table, "table")
+    if mask is not None:
+        _cuda(mask, "mask")
+        if mask.dtype != torch.uint8:
+            raise ValueError("mask must be uint8")
+    _cuda(out, "out")
     L, P = int(lights.shape[0]), int(points.shape[0])
     need = int(lib().dgsm_mlp_infer_workspace_size(L))
     if workspace is None or workspace.numel() < need:

@@ -442,8 +442,9 @@ __device__ inline double shell_at(const TexelState& ts, int k) {
 }
 
 // Shell index of a radius (fractional, unclamped); -1 for t <= 0.
+template <bool GEO>
 __device__ inline float shell_index(float t, const TexelState& ts) {
-    if (ts.geometric) return t > 0.f ? (__log2f(t) - ts.lr0) * ts.kinv : -1.f;
+    if (GEO) return t > 0.f ? (__builtin_amdgcn_logf(t) - ts.lr0) * ts.kinv : -1.f;
     return t * ts.kinv - 0.5f;
 }
 
@@ -452,7 +453,7 @@ constexpr float kRampEps = 1e-10f;
 
 // One (texel, Gaussian) pair for all 64 texels of the wave: Eq. 3 on the
 // shells where the erf ramps, as non-negative per-shell increments.
-template <bool STATS>
+template <bool STATS, bool GEO>
 __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r, const TexelState& s,
                                                                 unsigned long long& n_act,
                                                                 unsigned long long& n_ramp) {
@@ -489,15 +490,16 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     const float sa = a * rsa * 0.70710678118654752f;      // sqrt(a / 2)
     const float ts = (float)te - corr;                      // t* (shell range, erf at t = 0)
     // Ramp half-width z: P0 erfc(z) <= P0 exp(-z^2) <= kRampEps.
-    const float z = sqrtf(fmaxf(__logf(P0 * (1.f / kRampEps)), 0.34f));
+    // (P0 of an active lane is far above the denormal range: raw v_log / v_sqrt suffice)
+    const float z = __builtin_amdgcn_sqrtf(fmaxf(0.69314718f * __builtin_amdgcn_logf(P0 * (1.f / kRampEps)), 0.34f));
     const float xs = -sa * ts;                              // erf argument at t = 0
     float Ep = -1.f;
     if (xs > -z) Ep = erf_nr(xs);
     int ka = s.K, kb = -1;
     if (act) {
         const float half = z * __builtin_amdgcn_rcpf(sa);
-        const float klo = fminf(shell_index(ts - half, s), (float)s.K);
-        const float khi = fmaxf(shell_index(ts + half, s), -1.f);
+        const float klo = fminf(shell_index<GEO>(ts - half, s), (float)s.K);
+        const float khi = fmaxf(shell_index<GEO>(ts + half, s), -1.f);
         // first shell past the ramp start, last shell at or past its end
         ka = klo < 0.f ? 0 : (int)klo + 1;
         kb = khi > (float)(s.K - 2) ? s.K - 1 : max(0, (int)khi + 1);
@@ -508,20 +510,21 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     double tk = shell_at(s, kmin);
     for (int k = kmin; k <= kmax; ++k) {
         const float x = sa * ((float)(tk - te) + corr);
-        const float E = fmaxf(erf_nr(x), Ep);        // keep the increments non-negative
+        const float Ek = erf_nr(x);
+        const float E = Ek > Ep ? Ek : Ep;           // keep the increments non-negative
         const float dI = P0 * (E - Ep);
         Ep = E;
         if (act && dI > 0.f)
             __hip_atomic_fetch_add(s.inc + k * kWave + s.lane, to_fixed(dI), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
-        tk = s.geometric ? tk * s.ratio : tk + s.ratio;
+        tk = GEO ? tk * s.ratio : tk + s.ratio;
     }
 }
 
 // Walk one wave's share of a tile's hit words: for every set bit, the Gaussian
 // id of that supertile-list entry, its record (prefetched one pair ahead into
 // the other of two scalar register sets) and the pair evaluation.
-template <bool STATS>
+template <bool STATS, bool GEO>
 __device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* words, int w0, int w1,
                                                                 const int* list, ConstF4Ptr rec,
                                                                 const TexelState& st, unsigned long long& n_hits,
@@ -548,18 +551,18 @@ __device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* 
                     b = __builtin_ctzll(word);
                     word &= word - 1;
                     rb = load_rec(rec, readlane_i(gcur, b));
-                    eval_pair<STATS>(ra, st, n_act, n_ramp);
+                    eval_pair<STATS, GEO>(ra, st, n_act, n_ramp);
                 } else {
-                    eval_pair<STATS>(ra, st, n_act, n_ramp);
+                    eval_pair<STATS, GEO>(ra, st, n_act, n_ramp);
                     break;
                 }
                 if (word) {                                 // A in flight while B is evaluated
                     b = __builtin_ctzll(word);
                     word &= word - 1;
                     ra = load_rec(rec, readlane_i(gcur, b));
-                    eval_pair<STATS>(rb, st, n_act, n_ramp);
+                    eval_pair<STATS, GEO>(rb, st, n_act, n_ramp);
                 } else {
-                    eval_pair<STATS>(rb, st, n_act, n_ramp);
+                    eval_pair<STATS, GEO>(rb, st, n_act, n_ramp);
                     break;
                 }
             }
@@ -569,7 +572,7 @@ __device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* 
 
 // NW waves share one tile's accumulators (a launch knob: more waves per tile
 // split a tile's pairs finer and raise occupancy per LDS byte).
-template <typename OutT, bool STATS, int NW>
+template <typename OutT, bool STATS, int NW, bool GEO>
 __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const Geom& g = p.g;
@@ -597,8 +600,8 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     st.shd2 = lane + 128 < K ? shell_radius(lane + 128, K, g.spacing, g.r0, g.r1) : 0.0;
     st.shd3 = lane + 192 < K ? shell_radius(lane + 192, K, g.spacing, g.r0, g.r1) : 0.0;
     if (st.geometric) {
-        st.lr0 = __log2f(g.r0);
-        st.kinv = (float)(K - 1) / __log2f(g.r1 / g.r0);
+        st.lr0 = __builtin_amdgcn_logf(g.r0);
+        st.kinv = (float)(K - 1) / __builtin_amdgcn_logf(g.r1 / g.r0);
         st.ratio = pow((double)g.r1 / (double)g.r0, 1.0 / (double)(K - 1));
     } else {
         st.lr0 = 0.f;
@@ -622,7 +625,7 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     unsigned long long n_hits = 0, n_act = 0, n_ramp = 0;
     __syncthreads();
 
-    walk_hits<STATS>(words, w0, w1, list, rec, st, n_hits, n_act, n_ramp);
+    walk_hits<STATS, GEO>(words, w0, w1, list, rec, st, n_hits, n_act, n_ramp);
 
     if (STATS) {
         const unsigned long long nvalid = __popcll(__ballot(st.valid));
@@ -698,12 +701,17 @@ size_t tile_smem_bytes(const Geom& g) { return (size_t)g.K * kWave * sizeof(unsi
 template <typename OutT, bool STATS, int NW>
 static hipError_t launch_tile(const TileArgs& ta, int n_lights, hipStream_t st) {
     const size_t smem = tile_smem_bytes(ta.g);
+    const bool geo = ta.g.spacing == DGSM_SHELLS_GEOMETRIC;
+    const void* fn = geo ? (const void*)tile_build_kernel<OutT, STATS, NW, true>
+                         : (const void*)tile_build_kernel<OutT, STATS, NW, false>;
     if (smem > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute((const void*)tile_build_kernel<OutT, STATS, NW>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
-    tile_build_kernel<OutT, STATS, NW><<<dim3(ta.g.ntiles, n_lights), kWave * NW, smem, st>>>(ta);
+    if (geo)
+        tile_build_kernel<OutT, STATS, NW, true><<<dim3(ta.g.ntiles, n_lights), kWave * NW, smem, st>>>(ta);
+    else
+        tile_build_kernel<OutT, STATS, NW, false><<<dim3(ta.g.ntiles, n_lights), kWave * NW, smem, st>>>(ta);
     return hipGetLastError();
 }
 

@@ -240,3 +240,30 @@ def cfg5(n_scene: int = 6_000_000, n_avatars: int = 8, n_per_avatar: int = 200_0
     return dict(scene=scene, avatars=avatars, lights=lights, trajectories=trajs,
                 probes9=probes9, probes16=probes16,
                 atlas=atlas or AtlasSpec(1024, 1024, 128))
+
+
+# --------------------------------------------------------------------------
+# initial parameters of the learned per-light field (a seeded input)
+# --------------------------------------------------------------------------
+
+MLP_HIDDEN = 128
+MLP_LAYERS = 4
+MLP_LIVE_FEATURES = 99
+
+
+def mlp_init_params(seed: int) -> np.ndarray:
+    """Flat float32 initial parameters: per layer W_l [128][128] (He-uniform over
+    the live inputs; padded input columns of layer 0 zero) then b_l = 0, then
+    w4 ~ U(+-sqrt(3/128)) and b4 = -2."""
+    rng = np.random.default_rng(seed)
+    H = MLP_HIDDEN
+    parts = []
+    for l in range(MLP_LAYERS):
+        fan_in = MLP_LIVE_FEATURES if l == 0 else H
+        lim = np.sqrt(6.0 / fan_in)
+        W = rng.uniform(-lim, lim, (H, H))
+        if l == 0:
+            W[:, MLP_LIVE_FEATURES:] = 0.0
+        parts += [W.ravel(), np.zeros(H)]
+    parts += [rng.uniform(-np.sqrt(3.0 / H), np.sqrt(3.0 / H), H), np.array([-2.0])]
+    return np.concatenate(parts).astype(np.float32)

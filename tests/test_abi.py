@@ -100,3 +100,16 @@ def test_null_pointers_and_small_workspace_are_rejected(lib):
     prm = P._ShParams(32, 64, 1.0, 4.0, 1e-6, 1.0, 1)
     assert lib.sh_transfer(1, 5, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, None, None) == 1
     assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, 1, None) == 1
+
+
+def test_binding_rejects_host_tensors_for_device_arguments():
+    """A host pointer must never reach a kernel: the binding refuses CPU tensors
+    where the library expects device memory."""
+    import torch
+    import paper_2601_01660_amd as P
+    g = P.GaussianSet(torch.zeros(4, 3), torch.ones(4, 3), torch.zeros(4, 4), torch.zeros(4))
+    with pytest.raises(ValueError):
+        g.struct()
+    with pytest.raises(ValueError):
+        P._cuda(torch.zeros(3), "x")
+    assert P._cuda(None, "x") is None

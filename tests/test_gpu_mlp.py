@@ -20,7 +20,7 @@ def _gpu():
 
 
 def _params(seed, noise=0.05):
-    p = om.init_params(seed).astype(np.float64)
+    p = synth.mlp_init_params(seed).astype(np.float64)
     rng = np.random.default_rng(seed + 100)
     p = p + noise * rng.standard_normal(p.shape) * (np.abs(p) > 0)     # keep padded columns at zero
     p[om.N_PARAMS - 1] = 0.3
@@ -80,7 +80,7 @@ def test_training_fits_an_atlas_and_fallback_covers_the_rest():
     lights = np.array([[0.0, 0.0, 0.0]], np.float32)
     atlas = P.Atlas(64, 64, 32)
     table = P.dgsm_build(torch.from_numpy(lights), P.GaussianSet.from_host(g), atlas)
-    params = torch.from_numpy(om.init_params(6)).cuda()
+    params = torch.from_numpy(synth.mlp_init_params(6)).cuda()
     mv = torch.zeros(2 * om.N_PARAMS, device="cuda")
     losses = P.mlp_train(params, mv, atlas, table[0], steps=600, batch=4096, lr0=2e-3, lr1=1e-4, seed=7)
     torch.cuda.synchronize()

@@ -6,6 +6,7 @@ import pytest
 import torch
 
 from oracle import dgsm as od
+import synth
 from oracle import mlp as om
 
 
@@ -16,7 +17,7 @@ def _batch(seed=0, B=24):
 
 
 def test_parameter_count_and_pack_roundtrip():
-    flat = om.init_params(3)
+    flat = synth.mlp_init_params(3)
     assert flat.shape == (om.N_PARAMS,) == (66177,)
     assert np.array_equal(om.pack(om.unpack(flat)), flat.astype(np.float64))
     assert np.all(om.unpack(flat)["W0"][:, om.D_IN:] == 0)
@@ -24,7 +25,7 @@ def test_parameter_count_and_pack_roundtrip():
 
 def test_backward_matches_central_differences():
     phi, t = _batch(1)
-    flat = om.init_params(4).astype(np.float64)
+    flat = synth.mlp_init_params(4).astype(np.float64)
     flat += np.random.default_rng(5).normal(0, 0.05, flat.shape)      # non-trivial biases
     T, cache = om.forward(flat, phi, bf16_emulation=False)
     g = om.backward(flat, cache, t, bf16_emulation=False)
