@@ -221,6 +221,24 @@ def build_texels(light, gaussians, rows, cols, K, spacing="geometric", r0=0.05, 
     return np.exp(-optical_depth(dirs, t, light, mean, A, beta))
 
 
+def transmittance_at(light, gaussians, points, kappa=1.0, chunk=4096):
+    """Exact T(d, r) = exp(-tau(d, r)) at world points (Eqs. 2-4 at the point itself,
+    no atlas): d = (x - o_L)/|x - o_L|, r = |x - o_L|."""
+    mean, A, beta = gaussian_terms(gaussians, kappa)
+    diff = np.asarray(points, dtype=np.float64) - np.asarray(light, dtype=np.float64)
+    r = np.linalg.norm(diff, axis=1)
+    dirs = diff / r[:, None]
+    tau = np.zeros(r.shape[0])
+    for s in range(0, mean.shape[0], chunk):
+        e = slice(s, s + chunk)
+        a, b, c = ray_quadratic(dirs, light, mean[e], A[e])
+        pref = beta[e][None, :] * np.sqrt(np.pi / (2 * a)) * np.exp(-0.5 * (c[None, :] - b * b / a))
+        ra = np.sqrt(a / 2)
+        boa = b / a
+        tau += np.sum(pref * erf_difference(ra * (r[:, None] + boa), ra * boa), axis=1)
+    return np.exp(-tau)
+
+
 # ---------------------------------------------------------------------------
 # Query (Sec. 3.3)
 # ---------------------------------------------------------------------------

@@ -370,3 +370,16 @@ def test_normals_are_smallest_axis_and_face_outward():
         ax = int(np.argmin(g.scale[k]))
         assert abs(abs(n[k] @ R[k][:, ax]) - 1) < 1e-12
         assert n[k] @ (g.mean[k] - c) >= 0
+
+
+def test_transmittance_at_points_equals_table_at_texel_centres_and_shells():
+    g = tiny_scene(22, n=20, lo=-2, hi=2, median=0.2)
+    light = np.array([0.05, -0.03, 0.02])
+    H = W = 8
+    K = 6
+    T = od.build(light, g, H, W, K)
+    t = od.shell_radii(K)
+    d = od.texel_directions(H, W).reshape(-1, 3)
+    for k in (0, 3, 5):
+        pts = light + t[k] * d
+        assert np.allclose(od.transmittance_at(light, g, pts), T[k].reshape(-1), rtol=1e-12, atol=1e-14)
