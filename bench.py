@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--cpu-texels", type=int, default=40)
     ap.add_argument("--mlp-steps", type=int, default=1500, help="Adam steps per light for the surrogate")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="run the batched plan as eager launches instead of its captured graph (for counters)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -232,19 +234,19 @@ def main():
     with torch.cuda.stream(side):
         plan = P.Plan(lights, atlas, static_set, avatar.n, F, static_cache=True, autotune=True)
         for _ in range(args.warmup):
-            plan.run(dyn_set, tr, out=T_out, use_graph=True)
+            plan.run(dyn_set, tr, out=T_out, use_graph=not args.eager)
         side.synchronize()
         log(f"warmup done (autotuned tile waves: {plan.tile_waves})")
         wall0 = time.perf_counter()
-        ms_step = timed(lambda: plan.run(dyn_set, tr, out=T_out, use_graph=True), args.steps)
+        ms_step = timed(lambda: plan.run(dyn_set, tr, out=T_out, use_graph=not args.eager), args.steps)
         wall = time.perf_counter() - wall0
         tile_waves = plan.tile_waves
         plan.close()
         plan_nc = P.Plan(lights, atlas, static_set, avatar.n, F, static_cache=False, autotune=False,
                          tile_waves=tile_waves)
-        plan_nc.run(dyn_set, tr, out=T_out, use_graph=True)
+        plan_nc.run(dyn_set, tr, out=T_out, use_graph=not args.eager)
         side.synchronize()
-        ms_nocache = timed(lambda: plan_nc.run(dyn_set, tr, out=T_out, use_graph=True), 1)
+        ms_nocache = timed(lambda: plan_nc.run(dyn_set, tr, out=T_out, use_graph=not args.eager), 1)
         plan_nc.close()
     ms_frame = ms_step / F
     log(f"batched graph + static cache: {ms_frame:.3f} ms/frame (wall {wall:.2f} s for {args.steps} steps); "
