@@ -222,6 +222,8 @@ def main():
     torch.cuda.synchronize()
     ms_plain = timed(lambda: plain_step(record=True), 1)
     acc_ms = float(np.mean([a.elapsed_time(b) for a, b in acc_ev]))
+    units = [P.dgsm_work_units(atlas, N, L, ws, l) for l in range(L)]
+    log(f"work units of the last plain accumulation (extra slices, split tiles, hits/slice, hits): {units}")
     log(f"plain per-frame launches: {ms_plain / F:.3f} ms/frame; accumulate {acc_ms:.3f} ms/launch")
     del ws
     torch.cuda.empty_cache()
@@ -236,14 +238,14 @@ def main():
         for _ in range(args.warmup):
             plan.run(dyn_set, tr, out=T_out, use_graph=not args.eager)
         side.synchronize()
-        log(f"warmup done (autotuned tile waves: {plan.tile_waves})")
+        log(f"warmup done (autotuned: {plan.tile_waves} waves per tile, {plan.split_units} work units)")
         wall0 = time.perf_counter()
         ms_step = timed(lambda: plan.run(dyn_set, tr, out=T_out, use_graph=not args.eager), args.steps)
         wall = time.perf_counter() - wall0
-        tile_waves = plan.tile_waves
+        tile_waves, split_units = plan.tile_waves, plan.split_units
         plan.close()
         plan_nc = P.Plan(lights, atlas, static_set, avatar.n, F, static_cache=False, autotune=False,
-                         tile_waves=tile_waves)
+                         tile_waves=tile_waves, split_units=split_units)
         plan_nc.run(dyn_set, tr, out=T_out, use_graph=not args.eager)
         side.synchronize()
         ms_nocache = timed(lambda: plan_nc.run(dyn_set, tr, out=T_out, use_graph=not args.eager), 1)
@@ -270,7 +272,7 @@ def main():
                       "mode": ("one captured graph per step: static optical depth built once per step, "
                                "then per frame the avatar's binning + accumulation on top of it, "
                                "fp16 store and query of all 2.15M centres"),
-                      "tile_waves": tile_waves},
+                      "tile_waves": tile_waves, "split_units": split_units},
            "comparison_ms_per_frame": {"batched_graph_static_cache": round(ms_frame, 4),
                                        "batched_graph_no_cache": round(ms_nocache / F, 4),
                                        "plain_per_frame_launches": round(ms_plain / F, 4)},

@@ -132,11 +132,21 @@ dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaus
  *   first): texel-Gaussian pairs evaluated at tile granularity, pairs whose
  *   prefactor exceeded cull_eps, erf-ramp evaluations, supertile list entries
  *   scanned.  NULL disables counting (the timed configuration).
+ * A tile with far more Gaussian hits than the launch's mean is cut into
+ * slices evaluated by separate workgroups whose fixed-point sums are added
+ * afterwards; integer sums make the atlas bitwise the same as unsplit.
+ *
+ * dgsm_work_units - how the last dgsm_accumulate on this workspace cut its
+ * tiles, for light `light`: out[0] extra slices, out[1] split tiles, out[2]
+ * hits per slice (0: no splitting), out[3] total (tile, Gaussian) hits.
+ * Copies from the device and synchronises `stream`.
  */
 dgsm_status dgsm_bin(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
                      const dgsm_atlas_desc_t* desc, void* ws, size_t ws_bytes, void* stream);
 dgsm_status dgsm_accumulate(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc, int64_t n_gauss,
                             void* atlas, void* ws, size_t ws_bytes, unsigned long long* stats, void* stream);
+dgsm_status dgsm_work_units(const dgsm_atlas_desc_t* desc, int64_t n_gauss, int32_t n_lights, const void* ws,
+                            size_t ws_bytes, int32_t light, int32_t out[4], void* stream);
 
 /*
  * dgsm_query - sample the atlas at world points (Sec. 3.3): for each light l
@@ -203,9 +213,16 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  *   static_cache  1: the static optical depth is built once per run and each
  *                 frame adds only the dynamic Gaussians to it (tau is a sum over
  *                 Gaussians, Eq. 2); 0: every frame rebuilds from all Gaussians
- *   autotune      1: the first run times the waves-per-tile knob of the tile
- *                 accumulation (2, 4, 8) on frame 0 and keeps the fastest
- *   tile_waves    knob value when autotune = 0 (2, 4 or 8; else 4)
+ *   autotune      1: the first run times the two knobs of the tile
+ *                 accumulation on frame 0 of the real workload and keeps the
+ *                 fastest pair: waves per tile (2, 4, 8) and work units per
+ *                 launch (0, 512, 2048, 8192)
+ *   tile_waves    waves sharing one 8x8 tile when autotune = 0 (2, 4 or 8; else 4)
+ *   split_units   target number of work units per accumulation when
+ *                 autotune = 0: a tile with more hits than (total hits /
+ *                 split_units) is cut into slices run by separate blocks
+ *                 (results are bitwise the same); 0 = default (2048),
+ *                 negative = never split
  *
  * dgsm_plan_create allocates all device memory the plan needs (the only
  * allocating entry points are create and destroy) and synchronises the device.
@@ -223,6 +240,7 @@ typedef struct {
     int32_t static_cache;
     int32_t autotune;
     int32_t tile_waves;
+    int32_t split_units;
 } dgsm_plan_opts_t;
 
 dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc,
@@ -230,8 +248,10 @@ dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_atlas_desc_
                              const dgsm_plan_opts_t* opts, dgsm_plan* out);
 dgsm_status dgsm_plan_run(dgsm_plan plan, const dgsm_gaussians_t* dynamic_set, const float* translations,
                           float* T_out, int32_t use_graph, void* stream);
-/* The waves-per-tile knob in use (after autotuning, if enabled). */
+/* The knobs in use (after autotuning, if enabled): waves per tile, and work
+ * units per accumulation (-1: never split). */
 int32_t dgsm_plan_tile_waves(const dgsm_plan plan);
+int32_t dgsm_plan_split_units(const dgsm_plan plan);
 dgsm_status dgsm_plan_destroy(dgsm_plan plan);
 
 /*

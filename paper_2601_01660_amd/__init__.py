@@ -52,7 +52,7 @@ MLP_PARAMS = 66177
 
 class _PlanOpts(ctypes.Structure):
     _fields_ = [("frames", ctypes.c_int32), ("static_cache", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("tile_waves", ctypes.c_int32)]
+                ("tile_waves", ctypes.c_int32), ("split_units", ctypes.c_int32)]
 
 
 _LIB = None
@@ -79,7 +79,11 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "dgsm_plan_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Gaussians), ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_int32, ctypes.c_void_p]),
+    "dgsm_work_units": (ctypes.c_int, [ctypes.POINTER(_AtlasDesc), ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                       ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.c_void_p]),
     "dgsm_plan_tile_waves": (ctypes.c_int32, [ctypes.c_void_p]),
+    "dgsm_plan_split_units": (ctypes.c_int32, [ctypes.c_void_p]),
     "dgsm_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "dgsm_mlp_workspace_size": (ctypes.c_size_t, [ctypes.c_int64]),
     "dgsm_mlp_infer_workspace_size": (ctypes.c_size_t, [ctypes.c_int32]),
@@ -259,6 +263,16 @@ def dgsm_accumulate(lights, atlas: Atlas, n_gauss: int, out, workspace, stats=No
     return out
 
 
+def dgsm_work_units(atlas: Atlas, n_gauss: int, n_lights: int, workspace, light: int):
+    """(extra slices, split tiles, hits per slice, total hits) of the last accumulation of ``light``."""
+    _cuda(workspace, "workspace")
+    d = atlas.struct()
+    out = (ctypes.c_int32 * 4)()
+    _check(lib().dgsm_work_units(ctypes.byref(d), n_gauss, n_lights, _ptr(workspace), workspace.numel(), light,
+                                 out, _stream()))
+    return tuple(int(x) for x in out)
+
+
 def dgsm_query(lights, atlas: Atlas, table, points, out=None):
     """Trilinear lookup T[L, P] of the atlas at points [P, 3]."""
     lights = _dev(lights)
@@ -311,7 +325,8 @@ class Plan:
     """
 
     def __init__(self, lights, atlas: Atlas, static: GaussianSet, n_dynamic: int, frames: int,
-                 static_cache: bool = True, autotune: bool = True, tile_waves: int = 4, kappa: float = 1.0):
+                 static_cache: bool = True, autotune: bool = True, tile_waves: int = 4, split_units: int = 0,
+                 kappa: float = 1.0):
         lights = _dev(lights)
         self.L = int(lights.shape[0])
         self.atlas = atlas
@@ -321,7 +336,7 @@ class Plan:
         d = atlas.struct()
         lt = _Lights(lights.data_ptr(), self.L, kappa)
         gs = static.struct()
-        opts = _PlanOpts(self.frames, int(static_cache), int(autotune), int(tile_waves))
+        opts = _PlanOpts(self.frames, int(static_cache), int(autotune), int(tile_waves), int(split_units))
         h = ctypes.c_void_p()
         _check(lib().dgsm_plan_create(ctypes.byref(lt), ctypes.byref(d), ctypes.byref(gs), self.n_dynamic,
                                       ctypes.byref(opts), ctypes.byref(h)))
@@ -334,6 +349,10 @@ class Plan:
     @property
     def tile_waves(self) -> int:
         return int(lib().dgsm_plan_tile_waves(self._h))
+
+    @property
+    def split_units(self) -> int:
+        return int(lib().dgsm_plan_split_units(self._h))
 
     def run(self, dynamic: GaussianSet, translations, out=None, use_graph: bool = True):
         """T[frames, L, n_static + n_dynamic] for one run; enqueued on the current stream."""

@@ -101,6 +101,12 @@ struct LightWs {
     int* counts;       // [S][nb] per-block counts, scanned in place
     int* lists;        // [cap] supertile lists, 64-entry chunks
     uint64_t* bits;    // [cap] per supertile: [tile][chunk] hit words
+    int* hits;         // [ntiles] set bits over a tile's hit words
+    int4* tinfo;       // [ntiles] {slices, first partial (-1: not split), end word of slice 0, words}
+    int4* units;       // [units_cap] extra slices: {tile, first word, end word, partial}
+    int2* splits;      // [units_cap] split tiles: {tile, first partial}
+    int* nunits;       // [4] {extra slices, split tiles, hits per slice, total hits}
+    unsigned long long* part;   // [2 units_cap][K][64] fixed-point partial optical depths
 };
 
 __host__ __device__ inline LightWs light_ws(unsigned char* ws, const BuildLayout& L, int l) {
@@ -108,7 +114,10 @@ __host__ __device__ inline LightWs light_ws(unsigned char* ws, const BuildLayout
     return LightWs{reinterpret_cast<int*>(b + L.totals), reinterpret_cast<int*>(b + L.lbase),
                    reinterpret_cast<GRec*>(b + L.rec), reinterpret_cast<float4*>(b + L.cone),
                    reinterpret_cast<uint64_t*>(b + L.mask), reinterpret_cast<int*>(b + L.counts),
-                   reinterpret_cast<int*>(b + L.lists), reinterpret_cast<uint64_t*>(b + L.bits)};
+                   reinterpret_cast<int*>(b + L.lists), reinterpret_cast<uint64_t*>(b + L.bits),
+                   reinterpret_cast<int*>(b + L.hits), reinterpret_cast<int4*>(b + L.tinfo),
+                   reinterpret_cast<int4*>(b + L.units), reinterpret_cast<int2*>(b + L.splits),
+                   reinterpret_cast<int*>(b + L.nunits), reinterpret_cast<unsigned long long*>(b + L.part)};
 }
 
 // Tiles of supertile s: origin, extent and local index t = (ty-ty0)*ntx + (tx-tx0).
@@ -261,7 +270,8 @@ __global__ __launch_bounds__(256) void scan_kernel(unsigned char* ws, BuildLayou
 }
 
 // List base of every supertile, each list padded to a multiple of 64 entries.
-__global__ __launch_bounds__(256) void bases_kernel(unsigned char* ws, BuildLayout lay, int S) {
+// Also clears the per-tile hit counters that the tile masks fill.
+__global__ __launch_bounds__(256) void bases_kernel(unsigned char* ws, BuildLayout lay, int S, int ntiles) {
     __shared__ int wsum[4];
     const LightWs W = light_ws(ws, lay, blockIdx.x);
     const int s = threadIdx.x;
@@ -269,6 +279,7 @@ __global__ __launch_bounds__(256) void bases_kernel(unsigned char* ws, BuildLayo
     const int x = block_scan_incl(v, wsum);
     if (s < S) W.lbase[s] = x - v;
     if (s == S - 1) W.lbase[S] = x;
+    for (int t = s; t < ntiles; t += 256) W.hits[t] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -339,7 +350,120 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
             if (lane == t) mine = bal;
         }
         const int c0 = sbase[s] / 64, ns = (sbase[s + 1] - sbase[s]) / 64;
-        if (lane < nt) W.bits[64 * (size_t)c0 + (size_t)lane * ns + (c - c0)] = mine;
+        if (lane < nt) {
+            W.bits[64 * (size_t)c0 + (size_t)lane * ns + (c - c0)] = mine;
+            if (mine) atomicAdd(W.hits + (sp.ty0 + lane / sp.ntx) * g.TW + sp.tx0 + lane % sp.ntx, __popcll(mine));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Work units.  A tile whose hit count is far above the launch's mean would
+// keep a few blocks busy long after the rest of the chip has drained (an
+// animated avatar covers a few dozen tiles with tens of thousands of hits
+// each).  Such a tile is cut into slices of its hit words; each slice runs in
+// its own block and leaves its fixed-point per-shell sums in a partial buffer,
+// which split_finish_kernel adds in slice order.  The sums are integers, so
+// the atlas is bitwise the same as with unsplit tiles.
+// ---------------------------------------------------------------------------
+
+constexpr int kMaxSlices = 64;         // slices of one tile
+constexpr int kMinSliceHits = 2048;    // below this a slice is not worth its partial buffer
+constexpr int kPlanThreads = 1024;
+
+// per = hits per slice; per <= 0: never split
+__device__ inline int slices_of(int h, int per) {
+    if (per <= 0) return 1;
+    const int q = (int)(((long long)h + per - 1) / per);
+    return q < 1 ? 1 : (q > kMaxSlices ? kMaxSlices : q);
+}
+
+// One block per light: slice size from the light's total hits and the target
+// unit count, then the unit table in tile order (deterministic).
+__global__ __launch_bounds__(kPlanThreads) void split_plan_kernel(unsigned char* ws, BuildLayout lay, Geom g,
+                                                                  int target) {
+    __shared__ long long red[kPlanThreads / kWave];
+    __shared__ int iscan[kPlanThreads / kWave];
+    __shared__ int per_s;
+    const LightWs W = light_ws(ws, lay, blockIdx.x);
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    constexpr int NWV = kPlanThreads / kWave;
+    // this thread's tiles: a contiguous range, so that tile order is scan order
+    const int chunk = (g.ntiles + kPlanThreads - 1) / kPlanThreads;
+    const int t0 = min(g.ntiles, tid * chunk), t1 = min(g.ntiles, t0 + chunk);
+    long long h = 0;
+    for (int t = t0; t < t1; ++t) h += W.hits[t];
+    for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o);
+    if (lane == 0) red[wave] = h;
+    __syncthreads();
+    if (tid == 0) {
+        long long tot = 0;
+        for (int w = 0; w < NWV; ++w) tot += red[w];
+        long long per = target > 0 ? (tot + target - 1) / target : 0;
+        if (target > 0 && per < kMinSliceHits) per = kMinSliceHits;
+        if (per > (1ll << 28)) per = 0;
+        per_s = (int)per;
+        W.nunits[3] = (int)(tot < INT32_MAX ? tot : INT32_MAX);
+    }
+    __syncthreads();
+    // grow the slice size until the extra slices fit the unit table
+    int per = per_s, extra_me = 0, split_me = 0;
+    for (;;) {
+        extra_me = 0;
+        split_me = 0;
+        for (int t = t0; t < t1; ++t) {
+            const int q = slices_of(W.hits[t], per);
+            extra_me += q - 1;
+            split_me += q > 1;
+        }
+        int e = extra_me;
+        for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
+        __syncthreads();
+        if (lane == 0) iscan[wave] = e;
+        __syncthreads();
+        int tot = 0;
+        for (int w = 0; w < NWV; ++w) tot += iscan[w];
+        if (tot <= lay.units_cap || per <= 0) break;
+        per = per >= (1 << 28) ? 0 : 2 * per;
+    }
+    // exclusive scans (tile order) of extra slices and split tiles: pack both in one int64
+    long long v = ((long long)extra_me << 32) | (unsigned)split_me;
+    long long incl = v;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const long long y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    __syncthreads();
+    if (lane == kWave - 1) red[wave] = incl;
+    __syncthreads();
+    long long before = 0, all = 0;
+    for (int w = 0; w < NWV; ++w) {
+        if (w < wave) before += red[w];
+        all += red[w];
+    }
+    long long ex = before + incl - v;
+    int xbase = (int)(ex >> 32), sbase = (int)(ex & 0xffffffffll);
+    for (int t = t0; t < t1; ++t) {
+        const int q = slices_of(W.hits[t], per);
+        const int s = (t / g.TW / g.STH) * g.SGW + (t % g.TW) / g.STW;
+        const int ns = (W.lbase[s + 1] - W.lbase[s]) / 64;
+        int4 info = make_int4(1, -1, ns, ns);
+        if (q > 1) {
+            const int pbase = sbase + xbase;        // partials of earlier split tiles: one per slice
+            info = make_int4(q, pbase, (int)((long long)ns / q), ns);
+            for (int i = 1; i < q; ++i)
+                W.units[xbase + i - 1] = make_int4(t, (int)((long long)i * ns / q),
+                                                   (int)((long long)(i + 1) * ns / q), pbase + i);
+            W.splits[sbase] = make_int2(t, pbase);
+            xbase += q - 1;
+            sbase += 1;
+        }
+        W.tinfo[t] = info;
+    }
+    if (tid == 0) {
+        W.nunits[0] = (int)(all >> 32);
+        W.nunits[1] = (int)(all & 0xffffffffll);
+        W.nunits[2] = per;
     }
 }
 
@@ -352,9 +476,10 @@ struct TileArgs {
     BuildLayout lay;
     unsigned char* ws;
     float pair_eps;
-    void* out;                 // atlas [L][K][H][W]
-    const float* base_tau;     // optional [L][K][H][W]
+    void* out;                 // atlas [L][K][plane]
+    const float* base_tau;     // optional [L][K][plane]
     int write_tau;
+    int tiled;                 // plane order: 0 row-major H x W; 1 tile-major [TH*TW][8x8]
     unsigned long long* stats;
 };
 
@@ -572,6 +697,40 @@ __device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* 
 
 // NW waves share one tile's accumulators (a launch knob: more waves per tile
 // split a tile's pairs finer and raise occupancy per LDS byte).
+// Per texel: prefix of the fixed-point per-shell increments inc(k) over the
+// shells (Eq. 2 as a running sum), optional base optical depth, then either
+// tau (FP32) or T = exp(-tau) (Eq. 4), shell-major.
+template <typename OutT, typename Inc>
+__device__ inline void finish_texel(const TileArgs& p, int light, int py, int px, Inc inc) {
+    const Geom& g = p.g;
+    const int K = g.K;
+    const size_t plane = p.tiled ? (size_t)g.ntiles * kWave : (size_t)g.H * g.W;
+    const size_t texel = p.tiled ? (size_t)((py >> 3) * g.TW + (px >> 3)) * kWave + (py & 7) * kTile + (px & 7)
+                                 : (size_t)py * g.W + px;
+    const size_t off = (size_t)light * K * plane + texel;
+    const float* bt = p.base_tau ? p.base_tau + off : nullptr;
+    unsigned long long acc = 0;
+    float Tp = 1.f;
+    if (p.write_tau) {
+        float* out = reinterpret_cast<float*>(p.out) + off;
+        for (int k = 0; k < K; ++k) {
+            acc += inc(k);
+            const float tau = (float)from_fixed(acc);
+            out[(size_t)k * plane] = bt ? tau + bt[(size_t)k * plane] : tau;
+        }
+    } else {
+        OutT* out = reinterpret_cast<OutT*>(p.out) + off;
+        for (int k = 0; k < K; ++k) {
+            acc += inc(k);
+            const float tau = (float)from_fixed(acc);
+            const float tt = bt ? tau + bt[(size_t)k * plane] : tau;
+            const float T = fminf(__expf(-tt), Tp);   // exactly non-increasing in k
+            Tp = T;
+            Store<OutT>::put(out + (size_t)k * plane, T);
+        }
+    }
+}
+
 template <typename OutT, bool STATS, int NW, bool GEO>
 __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -580,9 +739,26 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     unsigned long long* inc = reinterpret_cast<unsigned long long*>(smem);   // [K][64] fixed point
 
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    const int tile = blockIdx.x;
     const int light = blockIdx.y;
     const LightWs W = light_ws(p.ws, p.lay, light);
+    // Blocks [0, ntiles) take slice 0 of their tile; the rest take the extra
+    // slices of split tiles (block-uniform, so the early return is safe).
+    int tile, wlo, whi, pidx;
+    if ((int)blockIdx.x < g.ntiles) {
+        tile = blockIdx.x;
+        const int4 ti = W.tinfo[tile];
+        wlo = 0;
+        whi = ti.z;
+        pidx = ti.x > 1 ? ti.y : -1;
+    } else {
+        const int e = (int)blockIdx.x - g.ntiles;
+        if (e >= W.nunits[0]) return;
+        const int4 u = W.units[e];
+        tile = u.x;
+        wlo = u.y;
+        whi = u.z;
+        pidx = u.w;
+    }
     const int ty = tile / g.TW, tx = tile - ty * g.TW;
     const int py = ty * kTile + (lane >> 3), px = tx * kTile + (lane & 7);
 
@@ -620,8 +796,8 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     const uint64_t* words = W.bits + 64 * (size_t)c0 + (size_t)t_local * ns;
     const int* list = W.lists + lb0;
     const ConstF4Ptr rec = (ConstF4Ptr)(const void*)W.rec;
-    const int per = (ns + NW - 1) / NW;
-    const int w0 = min(ns, wave * per), w1 = min(ns, w0 + per);
+    const int per = (whi - wlo + NW - 1) / NW;
+    const int w0 = min(whi, wlo + wave * per), w1 = min(whi, w0 + per);
     unsigned long long n_hits = 0, n_act = 0, n_ramp = 0;
     __syncthreads();
 
@@ -633,36 +809,40 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
             atomicAdd(p.stats + 0, n_hits * nvalid);
             atomicAdd(p.stats + 1, n_act);
             atomicAdd(p.stats + 2, n_ramp);
-            if (wave == 0) atomicAdd(p.stats + 3, (unsigned long long)(lb1 - lb0));
+            if (wave == 0 && (int)blockIdx.x < g.ntiles) atomicAdd(p.stats + 3, (unsigned long long)(lb1 - lb0));
         }
     }
     __syncthreads();
-
-    if (wave == 0 && st.valid) {
-        const size_t plane = (size_t)g.H * g.W;
-        const size_t off = (size_t)light * K * plane + (size_t)py * g.W + px;
-        const float* bt = p.base_tau ? p.base_tau + off : nullptr;
-        unsigned long long acc = 0;
-        float Tp = 1.f;
-        if (p.write_tau) {
-            float* out = reinterpret_cast<float*>(p.out) + off;
-            for (int k = 0; k < K; ++k) {
-                acc += inc[k * kWave + lane];
-                const float tau = (float)from_fixed(acc);
-                out[(size_t)k * plane] = bt ? tau + bt[(size_t)k * plane] : tau;
-            }
-        } else {
-            OutT* out = reinterpret_cast<OutT*>(p.out) + off;
-            for (int k = 0; k < K; ++k) {
-                acc += inc[k * kWave + lane];
-                const float tau = (float)from_fixed(acc);
-                const float tt = bt ? tau + bt[(size_t)k * plane] : tau;
-                const float T = fminf(__expf(-tt), Tp);   // exactly non-increasing in k
-                Tp = T;
-                Store<OutT>::put(out + (size_t)k * plane, T);
-            }
-        }
+    if (pidx >= 0) {           // a slice of a split tile: leave the partial sums
+        unsigned long long* dst = W.part + (size_t)pidx * K * kWave;
+        for (int q = tid; q < K * kWave; q += kWave * NW) dst[q] = inc[q];
+        return;
     }
+
+    if (wave == 0 && st.valid)
+        finish_texel<OutT>(p, light, py, px, [&](int k) { return inc[k * kWave + lane]; });
+}
+
+// Split tiles: add the slices' partial sums in slice order, then finish as above.
+template <typename OutT>
+__global__ __launch_bounds__(kWave) void split_finish_kernel(TileArgs p) {
+    const Geom& g = p.g;
+    const int light = blockIdx.y;
+    const LightWs W = light_ws(p.ws, p.lay, light);
+    if ((int)blockIdx.x >= W.nunits[1]) return;
+    const int2 sp = W.splits[blockIdx.x];
+    const int q = W.tinfo[sp.x].x;
+    const int lane = threadIdx.x;
+    const int ty = sp.x / g.TW, tx = sp.x - ty * g.TW;
+    const int py = ty * kTile + (lane >> 3), px = tx * kTile + (lane & 7);
+    if (py >= g.H || px >= g.W) return;
+    const size_t slice = (size_t)g.K * kWave;
+    const unsigned long long* src = W.part + (size_t)sp.y * slice + lane;
+    finish_texel<OutT>(p, light, py, px, [&](int k) {
+        unsigned long long v = 0;
+        for (int i = 0; i < q; ++i) v += src[(size_t)i * slice + (size_t)k * kWave];
+        return v;
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -691,6 +871,13 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
     L.counts = take((size_t)g.S * (size_t)L.nb * sizeof(int));
     L.lists = take(L.cap * sizeof(int));
     L.bits = take(L.cap * sizeof(uint64_t));
+    L.units_cap = 4 * g.ntiles < 1024 ? 4 * g.ntiles : 1024;
+    L.hits = take((size_t)g.ntiles * sizeof(int));
+    L.tinfo = take((size_t)g.ntiles * sizeof(int4));
+    L.units = take((size_t)L.units_cap * sizeof(int4));
+    L.splits = take((size_t)L.units_cap * sizeof(int2));
+    L.nunits = take(4 * sizeof(int));
+    L.part = take(2 * (size_t)L.units_cap * g.K * kWave * sizeof(unsigned long long));
     L.light_stride = off;
     L.total = L.light0 + (size_t)n_lights * L.light_stride;
     return L;
@@ -708,10 +895,11 @@ static hipError_t launch_tile(const TileArgs& ta, int n_lights, hipStream_t st) 
         const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
+    const dim3 grid(ta.g.ntiles + ta.lay.units_cap, n_lights);
     if (geo)
-        tile_build_kernel<OutT, STATS, NW, true><<<dim3(ta.g.ntiles, n_lights), kWave * NW, smem, st>>>(ta);
+        tile_build_kernel<OutT, STATS, NW, true><<<grid, kWave * NW, smem, st>>>(ta);
     else
-        tile_build_kernel<OutT, STATS, NW, false><<<dim3(ta.g.ntiles, n_lights), kWave * NW, smem, st>>>(ta);
+        tile_build_kernel<OutT, STATS, NW, false><<<grid, kWave * NW, smem, st>>>(ta);
     return hipGetLastError();
 }
 
@@ -724,14 +912,18 @@ static hipError_t launch_tile_nw(const TileArgs& ta, int n_lights, int nw, hipSt
     }
 }
 
-dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
-                        float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st) {
+dgsm_status enqueue_cones(const Geom& g, const BuildLayout& L, unsigned char* ws, hipStream_t st) {
     float4* tcone = reinterpret_cast<float4*>(ws + L.tcone);
     float4* scone = reinterpret_cast<float4*>(ws + L.scone);
     tile_cone_kernel<<<(g.ntiles + 63) / 64, 64, 0, st>>>(g, tcone);
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     super_cone_kernel<<<(g.S + 63) / 64, 64, 0, st>>>(g, tcone, scone);
-    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
+}
+
+dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
+                        float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st, bool cones) {
+    if (cones && enqueue_cones(g, L, ws, st) != DGSM_OK) return DGSM_EHIP;
     if (gs.n > 0) {
         PrepArgs pa{gs.mean, gs.scale, gs.rot, gs.opacity, gs.n, lights.pos, lights.kappa, cull_eps,
                     g.S, L, ws};
@@ -740,7 +932,7 @@ dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, 
     }
     scan_kernel<<<dim3(g.S, lights.n), 256, 0, st>>>(ws, L);
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
-    bases_kernel<<<lights.n, 256, 0, st>>>(ws, L, g.S);
+    bases_kernel<<<lights.n, 256, 0, st>>>(ws, L, g.S, g.ntiles);
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     if (gs.n > 0) {
         scatter_kernel<<<dim3(L.nb, lights.n), kPrepThreads, 0, st>>>(ws, L, gs.n, g.S);
@@ -756,15 +948,24 @@ dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, 
 
 dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned char* ws, int n_lights,
                                float pair_eps, void* atlas, const AccumOpts& o, hipStream_t st) {
-    TileArgs ta{g, L, ws, pair_eps, atlas, o.base_tau, o.write_tau ? 1 : 0, o.stats};
+    TileArgs ta{g, L, ws, pair_eps, atlas, o.base_tau, o.write_tau ? 1 : 0, o.tiled ? 1 : 0, o.stats};
     hipError_t e;
     const bool half = g.dtype == DGSM_F16 && !o.write_tau;
     const int nw = o.tile_waves;
+    const int target = o.split_units > 0 ? (o.split_units + n_lights - 1) / n_lights : 0;
+    split_plan_kernel<<<n_lights, kPlanThreads, 0, st>>>(ws, L, g, target);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     if (o.stats)
         e = half ? launch_tile_nw<__half, true>(ta, n_lights, nw, st) : launch_tile_nw<float, true>(ta, n_lights, nw, st);
     else
         e = half ? launch_tile_nw<__half, false>(ta, n_lights, nw, st) : launch_tile_nw<float, false>(ta, n_lights, nw, st);
-    return e == hipSuccess ? DGSM_OK : DGSM_EHIP;
+    if (e != hipSuccess) return DGSM_EHIP;
+    const dim3 fgrid(L.units_cap, n_lights);
+    if (half)
+        split_finish_kernel<__half><<<fgrid, kWave, 0, st>>>(ta);
+    else
+        split_finish_kernel<float><<<fgrid, kWave, 0, st>>>(ta);
+    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
 
 }  // namespace dgsm
@@ -809,9 +1010,27 @@ extern "C" dgsm_status dgsm_accumulate(const dgsm_lights_t* lights, const dgsm_a
     const Geom g = make_geom(*desc);
     const BuildLayout L = build_layout(g, n_gauss, lights->n);
     if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
-    AccumOpts o{nullptr, false, stats, kDefaultTileWaves};
+    AccumOpts o{nullptr, false, stats, kDefaultTileWaves, kDefaultSplitUnits};
     return enqueue_accumulate(g, L, reinterpret_cast<unsigned char*>(ws), lights->n, desc->cull_eps, atlas, o,
                               reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" dgsm_status dgsm_work_units(const dgsm_atlas_desc_t* desc, int64_t n_gauss, int32_t n_lights,
+                                       const void* ws, size_t ws_bytes, int32_t light, int32_t out[4],
+                                       void* stream) {
+    dgsm_status st = validate_desc(desc);
+    if (st != DGSM_OK) return st;
+    if (n_gauss < 0 || n_gauss >= INT32_MAX || n_lights < 1 || light < 0 || light >= n_lights || !out)
+        return DGSM_EINVAL;
+    const Geom g = make_geom(*desc);
+    const BuildLayout L = build_layout(g, n_gauss, n_lights);
+    if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
+    const LightWs W = light_ws(reinterpret_cast<unsigned char*>(const_cast<void*>(ws)), L, light);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(out, W.nunits, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return DGSM_EHIP;
+    return DGSM_OK;
 }
 
 extern "C" dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
@@ -826,6 +1045,6 @@ extern "C" dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussi
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
     if ((st = enqueue_bin(g, L, w, *lights, desc->cull_eps, *gaussians, s)) != DGSM_OK) return st;
-    AccumOpts o{nullptr, false, nullptr, kDefaultTileWaves};
+    AccumOpts o{nullptr, false, nullptr, kDefaultTileWaves, kDefaultSplitUnits};
     return enqueue_accumulate(g, L, w, lights->n, desc->cull_eps, atlas, o, s);
 }

@@ -45,17 +45,23 @@ struct BuildLayout {
     size_t tcone, scone;     // absolute offsets: tile cones [ntiles], supertile cones [kMaxSuper]
     size_t light0;           // absolute offset of light 0's slice
     size_t light_stride;     // bytes per light slice
+    int units_cap;           // extra work units per light (tiles split over several blocks)
     // offsets inside a light slice
     size_t totals, lbase, rec, cone, mask, counts, lists, bits;
+    size_t hits, tinfo, units, splits, nunits, part;
     size_t total;            // bytes for all lights
 };
 
 BuildLayout build_layout(const Geom& g, int64_t n, int n_lights);
 size_t tile_smem_bytes(const Geom& g);
 
-// Enqueue the binning of all lights (geometry, preprocess, scan, scatter).
+// Tile and supertile cones of the atlas geometry (depend on the atlas only).
+dgsm_status enqueue_cones(const Geom& g, const BuildLayout& L, unsigned char* ws, hipStream_t st);
+
+// Enqueue the binning of all lights (preprocess, scan, scatter, tile masks);
+// cones = false reuses cones already in the workspace.
 dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
-                        float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st);
+                        float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st, bool cones = true);
 
 // Options of the per-tile accumulation.
 struct AccumOpts {
@@ -63,14 +69,23 @@ struct AccumOpts {
     bool write_tau;          // store tau (FP32) instead of T
     unsigned long long* stats;   // optional device counters [4]
     int tile_waves;              // waves sharing one tile: 2, 4 or 8
+    int split_units;             // target work units per launch (all lights); <= 0: never split a tile
+    bool tiled = false;          // atlas / base_tau planes in tile-major order (see kTile)
 };
 
+// Elements of one shell plane: H*W row-major, or ntiles*64 tile-major (each
+// 8x8 tile's texels contiguous, row-major inside the tile).
+inline size_t plane_elems(const Geom& g, bool tiled) {
+    return tiled ? (size_t)g.ntiles * kWave : (size_t)g.H * g.W;
+}
+
 constexpr int kDefaultTileWaves = 4;
+constexpr int kDefaultSplitUnits = 2048;
 
 // Enqueue the per-tile accumulation of all lights into atlas [L][K][H][W].
 dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned char* ws, int n_lights,
                                float pair_eps, void* atlas, const AccumOpts& o, hipStream_t st);
 hipError_t launch_query(const Geom& g, const float* lights, int L, const void* atlas, const float* points,
-                        int64_t P, float* T, hipStream_t st);
+                        int64_t P, float* T, hipStream_t st, bool tiled = false);
 
 }  // namespace dgsm

@@ -9,9 +9,14 @@
 // per run (it does not change between frames) and each frame only bins and
 // accumulates the dynamic Gaussians on top of it: tau = tau_static +
 // tau_dynamic is exact because Eq. 2 is a sum over Gaussians.
+// The plan's own atlas and static optical depth store each shell plane in
+// tile-major order (the texels of an 8x8 tile contiguous): a tile's store is
+// one 128/256-byte run per shell, and most trilinear lookups stay inside one
+// tile, so a shell's two texel rows come from one cache line.
 // The whole run (static build + all frames) is captured once into a hipGraph
-// and replayed; the waves-per-tile knob of the tile build is chosen on the
-// first run by timing each candidate on frame 0 of the real workload.
+// and replayed; the knobs of the tile accumulation (waves per tile, work
+// units per launch) are chosen on the first run by timing each candidate pair
+// on frame 0 of the real workload.
 
 #include "dgsm_device.hpp"
 #include "dgsm_host.hpp"
@@ -43,6 +48,7 @@ struct dgsm_plan_s {
     bool cache;
     int autotune;
     int tile_waves;
+    int split_units;
     bool tuned;
     // device buffers owned by the plan
     float* lights;        // [L][3]
@@ -82,18 +88,18 @@ dgsm_gaussians_t set_of(const dgsm_plan p, int64_t off, int64_t n) {
 }
 
 // Static part of a run: tau of the static set for every light.
-dgsm_status enqueue_static(dgsm_plan p, int tile_waves, hipStream_t st) {
+dgsm_status enqueue_static(dgsm_plan p, int tile_waves, int split_units, hipStream_t st) {
     const dgsm_lights_t lt{p->lights, p->L, p->kappa};
     const BuildLayout La = build_layout(p->g, p->ns, p->L);
-    dgsm_status s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, 0, p->ns), st);
+    dgsm_status s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, 0, p->ns), st, false);
     if (s != DGSM_OK) return s;
-    AccumOpts o{nullptr, true, nullptr, tile_waves};
+    AccumOpts o{nullptr, true, nullptr, tile_waves, split_units, true};
     return enqueue_accumulate(p->g, La, p->ws_a, p->L, p->desc.cull_eps, p->tau_static, o, st);
 }
 
 // One frame: dynamic means, build (on top of the static tau in cache mode), query.
 dgsm_status enqueue_frame(dgsm_plan p, int f, const float* dyn_base, const float* translations, float* T_out,
-                          int tile_waves, hipStream_t st) {
+                          int tile_waves, int split_units, hipStream_t st) {
     const dgsm_lights_t lt{p->lights, p->L, p->kappa};
     if (p->nd > 0) {
         const int64_t n3 = 3 * p->nd;
@@ -104,20 +110,20 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, const float* dyn_base, const float
     dgsm_status s;
     if (p->cache) {
         const BuildLayout Lb = build_layout(p->g, p->nd, p->L);
-        s = enqueue_bin(p->g, Lb, p->ws_b, lt, p->desc.cull_eps, set_of(p, p->ns, p->nd), st);
+        s = enqueue_bin(p->g, Lb, p->ws_b, lt, p->desc.cull_eps, set_of(p, p->ns, p->nd), st, false);
         if (s != DGSM_OK) return s;
-        AccumOpts o{p->tau_static, false, nullptr, tile_waves};
+        AccumOpts o{p->tau_static, false, nullptr, tile_waves, split_units, true};
         s = enqueue_accumulate(p->g, Lb, p->ws_b, p->L, p->desc.cull_eps, p->atlas, o, st);
     } else {
         const BuildLayout La = build_layout(p->g, p->np, p->L);
-        s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, 0, p->np), st);
+        s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, 0, p->np), st, false);
         if (s != DGSM_OK) return s;
-        AccumOpts o{nullptr, false, nullptr, tile_waves};
+        AccumOpts o{nullptr, false, nullptr, tile_waves, split_units, true};
         s = enqueue_accumulate(p->g, La, p->ws_a, p->L, p->desc.cull_eps, p->atlas, o, st);
     }
     if (s != DGSM_OK) return s;
-    if (launch_query(p->g, p->lights, p->L, p->atlas, p->mean, p->np, T_out + (size_t)f * p->L * p->np, st) !=
-        hipSuccess)
+    if (launch_query(p->g, p->lights, p->L, p->atlas, p->mean, p->np, T_out + (size_t)f * p->L * p->np, st,
+                     true) != hipSuccess)
         return DGSM_EHIP;
     return DGSM_OK;
 }
@@ -132,42 +138,51 @@ dgsm_status enqueue_run(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* t
             return DGSM_EHIP;
     }
     dgsm_status s;
-    if (p->cache && (s = enqueue_static(p, p->tile_waves, st)) != DGSM_OK) return s;
+    if (p->cache && (s = enqueue_static(p, p->tile_waves, p->split_units, st)) != DGSM_OK) return s;
     for (int f = 0; f < p->frames; ++f)
-        if ((s = enqueue_frame(p, f, dyn->mean, translations, T_out, p->tile_waves, st)) != DGSM_OK) return s;
+        if ((s = enqueue_frame(p, f, dyn->mean, translations, T_out, p->tile_waves, p->split_units, st)) != DGSM_OK)
+            return s;
     return DGSM_OK;
 }
 
-// Time each waves-per-tile candidate on the accumulation the run repeats most
-// (frame 0: the dynamic accumulation in cache mode, the full one otherwise).
+// Time each (waves per tile, work units) candidate on the accumulation the
+// run repeats most (frame 0: the dynamic accumulation in cache mode, the full
+// one otherwise).
 dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* translations, float* T_out,
                      hipStream_t st) {
-    const int cand[3] = {2, 4, 8};
+    const int waves[3] = {2, 4, 8};
+    const int units[4] = {-1, 512, 2048, 8192};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DGSM_EHIP;
     dgsm_status s = DGSM_OK;
     float best = 1e30f;
-    int best_nw = kDefaultTileWaves;
+    int best_nw = kDefaultTileWaves, best_units = kDefaultSplitUnits;
     if (p->nd > 0) {
         const int64_t o = p->ns;
         (void)hipMemcpyAsync(p->scale + 3 * o, dyn->scale, 12 * p->nd, hipMemcpyDeviceToDevice, st);
         (void)hipMemcpyAsync(p->rot + 4 * o, dyn->rot, 16 * p->nd, hipMemcpyDeviceToDevice, st);
         (void)hipMemcpyAsync(p->opacity + o, dyn->opacity, 4 * p->nd, hipMemcpyDeviceToDevice, st);
     }
-    if (p->cache) s = enqueue_static(p, kDefaultTileWaves, st);
+    if (p->cache) s = enqueue_static(p, kDefaultTileWaves, kDefaultSplitUnits, st);
     for (int rep = 0; rep < 2 && s == DGSM_OK; ++rep)   // first pass warms up
-        for (int c = 0; c < 3 && s == DGSM_OK; ++c) {
+        for (int c = 0; c < 12 && s == DGSM_OK; ++c) {
+            const int nw = waves[c % 3], nu = units[c / 3];
             (void)hipEventRecord(e0, st);
-            s = enqueue_frame(p, 0, dyn->mean, translations, T_out, cand[c], st);
+            s = enqueue_frame(p, 0, dyn->mean, translations, T_out, nw, nu, st);
             (void)hipEventRecord(e1, st);
             if (hipEventSynchronize(e1) != hipSuccess) s = DGSM_EHIP;
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            if (rep == 1 && ms < best) { best = ms; best_nw = cand[c]; }
+            if (rep == 1 && ms < best) {
+                best = ms;
+                best_nw = nw;
+                best_units = nu;
+            }
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->tile_waves = best_nw;
+    p->split_units = best_units;
     p->tuned = true;
     return s;
 }
@@ -200,8 +215,9 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     p->cache = opts->static_cache != 0;
     p->autotune = opts->autotune;
     p->tile_waves = (opts->tile_waves == 2 || opts->tile_waves == 8) ? opts->tile_waves : kDefaultTileWaves;
+    p->split_units = opts->split_units == 0 ? kDefaultSplitUnits : (opts->split_units < 0 ? -1 : opts->split_units);
     const size_t elem = desc->dtype == DGSM_F16 ? 2 : 4;
-    const size_t table = (size_t)p->L * g.K * g.H * g.W;
+    const size_t table = (size_t)p->L * g.K * plane_elems(g, true);   // plan-internal: tile-major planes
     p->ws_a_bytes = build_layout(g, p->cache ? p->ns : np, p->L).total;
     p->ws_b_bytes = p->cache ? build_layout(g, p->nd, p->L).total : 0;
     bool ok = dalloc(&p->lights, 12 * (size_t)p->L) == hipSuccess && dalloc(&p->mean, 12 * (size_t)np) == hipSuccess &&
@@ -212,6 +228,10 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
                              dalloc(&p->ws_b, p->ws_b_bytes) == hipSuccess));
     const int64_t n = p->ns;
     ok = ok && hipMemcpy(p->lights, lights->pos, 12 * (size_t)p->L, hipMemcpyDeviceToDevice) == hipSuccess;
+    // the atlas cones never change: computed once into each workspace
+    ok = ok && enqueue_cones(g, build_layout(g, p->cache ? p->ns : np, p->L), p->ws_a, nullptr) == DGSM_OK;
+    ok = ok && (!p->cache || enqueue_cones(g, build_layout(g, p->nd, p->L), p->ws_b, nullptr) == DGSM_OK);
+    ok = ok && hipDeviceSynchronize() == hipSuccess;
     if (ok && n > 0)
         ok = hipMemcpy(p->mean, static_set->mean, 12 * n, hipMemcpyDeviceToDevice) == hipSuccess &&
              hipMemcpy(p->scale, static_set->scale, 12 * n, hipMemcpyDeviceToDevice) == hipSuccess &&
@@ -262,6 +282,8 @@ extern "C" dgsm_status dgsm_plan_run(dgsm_plan p, const dgsm_gaussians_t* dynami
 }
 
 extern "C" int32_t dgsm_plan_tile_waves(const dgsm_plan p) { return p ? p->tile_waves : 0; }
+
+extern "C" int32_t dgsm_plan_split_units(const dgsm_plan p) { return p ? p->split_units : 0; }
 
 extern "C" dgsm_status dgsm_plan_destroy(dgsm_plan p) {
     if (!p) return DGSM_EINVAL;

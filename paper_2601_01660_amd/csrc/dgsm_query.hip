@@ -10,12 +10,14 @@ namespace dgsm {
 // Octahedral mirror wrap of a texel one step outside the grid: across the
 // left/right edge (u = -1/+1) the map identifies (u, v) with (u, -v), across
 // the top/bottom edge (v = -1/+1) it identifies (u, v) with (-u, v).
-__device__ inline int wrap_offset(int i, int j, int H, int W) {
+// Returns the texel's element offset in a shell plane (row-major, or
+// tile-major with 8x8 tiles when tiled).
+__device__ inline int wrap_offset(int i, int j, int H, int W, int TW, bool tiled) {
     if (j < 0) { j = 0; i = H - 1 - i; }
     else if (j >= W) { j = W - 1; i = H - 1 - i; }
     if (i < 0) { i = 0; j = W - 1 - j; }
     else if (i >= H) { i = H - 1; j = W - 1 - j; }
-    return i * W + j;
+    return tiled ? ((i >> 3) * TW + (j >> 3)) * kWave + (i & 7) * kTile + (j & 7) : i * W + j;
 }
 
 struct QueryArgs {
@@ -27,6 +29,7 @@ struct QueryArgs {
     int64_t P;
     float* T;              // [L][P]
     float lr0, kscale;     // shell coordinate: geometric (log2 r - lr0) * kscale, uniform r * kscale - 1/2
+    int tiled;             // plane order of the atlas (see wrap_offset)
 };
 
 template <typename InT>
@@ -35,7 +38,8 @@ __global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
     if (p >= a.P) return;
     const Geom& g = a.g;
     const float x = a.points[3 * p], y = a.points[3 * p + 1], z = a.points[3 * p + 2];
-    const size_t plane = (size_t)g.H * g.W;
+    const bool tiled = a.tiled != 0;
+    const size_t plane = tiled ? (size_t)g.ntiles * kWave : (size_t)g.H * g.W;
     const InT* atlas = reinterpret_cast<const InT*>(a.atlas);
     for (int l = 0; l < a.L; ++l) {
         const float dx = x - a.lights[3 * l], dy = y - a.lights[3 * l + 1], dz = z - a.lights[3 * l + 2];
@@ -61,8 +65,10 @@ __global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
         const float fj = jf - j0f, fi = fi_ - i0f;
         const int k0 = min((int)kf, g.K - 2);
         const float fk = kf - (float)k0;
-        const int o00 = wrap_offset(i0, j0, g.H, g.W), o01 = wrap_offset(i0, j0 + 1, g.H, g.W);
-        const int o10 = wrap_offset(i0 + 1, j0, g.H, g.W), o11 = wrap_offset(i0 + 1, j0 + 1, g.H, g.W);
+        const int o00 = wrap_offset(i0, j0, g.H, g.W, g.TW, tiled);
+        const int o01 = wrap_offset(i0, j0 + 1, g.H, g.W, g.TW, tiled);
+        const int o10 = wrap_offset(i0 + 1, j0, g.H, g.W, g.TW, tiled);
+        const int o11 = wrap_offset(i0 + 1, j0 + 1, g.H, g.W, g.TW, tiled);
         const InT* s0 = atlas + ((size_t)l * g.K + k0) * plane;
         const InT* s1 = s0 + plane;
         const float a0 = (1.f - fj) * Store<InT>::get(s0 + o00) + fj * Store<InT>::get(s0 + o01);
@@ -76,9 +82,9 @@ __global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
 }
 
 hipError_t launch_query(const Geom& g, const float* lights, int L, const void* atlas, const float* points,
-                        int64_t P, float* T, hipStream_t st) {
+                        int64_t P, float* T, hipStream_t st, bool tiled) {
     if (P == 0) return hipSuccess;
-    QueryArgs a{g, lights, L, atlas, points, P, T, 0.f, 0.f};
+    QueryArgs a{g, lights, L, atlas, points, P, T, 0.f, 0.f, tiled ? 1 : 0};
     if (g.spacing == DGSM_SHELLS_GEOMETRIC) {
         a.lr0 = log2f(g.r0);
         a.kscale = (float)(g.K - 1) / log2f(g.r1 / g.r0);

@@ -478,19 +478,41 @@ struct ReduceArgs {
     const float* db4p;      // [nw]
     const float* lossp;     // [nw]
     int nw;
+    float* gvec;            // [kVecOut] reduced small vectors (vec_reduce_kernel)
     float* grad_out;        // optional [kNParams]
     float* loss_out;        // optional [1]
     int adam;
     float lr, beta1, beta2, eps, bc1, bc2;   // bc = 1 - beta^t
 };
 
+// Per-wave partials of the small vectors (biases, w4, b4, loss) summed over
+// the waves: one block per output entry, a strided pass then a fixed tree, so
+// the order (and the result) is the same on every run.
+constexpr int kVecOut = 4 * kH + kH + 2;     // b0..b3, w4, b4, loss
+
+__global__ __launch_bounds__(256) void vec_reduce_kernel(ReduceArgs a) {
+    __shared__ float red[256];
+    const int o = blockIdx.x, tid = threadIdx.x;
+    const float* src;
+    int stride;
+    if (o < 4 * kH) { src = a.dbp + o; stride = 4 * kH; }
+    else if (o < 5 * kH) { src = a.dw4p + (o - 4 * kH); stride = kH; }
+    else if (o == 5 * kH) { src = a.db4p; stride = 1; }
+    else { src = a.lossp; stride = 1; }
+    float s = 0.f;
+    for (int w = tid; w < a.nw; w += 256) s += src[(size_t)w * stride];
+    red[tid] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) a.gvec[o] = red[0];
+}
+
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
     const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p == 0 && a.loss_out) {
-        float s = 0.f;
-        for (int w = 0; w < a.nw; ++w) s += a.lossp[w];
-        *a.loss_out = s;
-    }
+    if (p == 0 && a.loss_out) *a.loss_out = a.gvec[5 * kH + 1];
     if (p >= kNParams) return;
     float g = 0.f;
     int wl = -1, wi = 0;
@@ -501,14 +523,12 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
             wl = l;
             wi = q;
         } else {
-            const int i = q - kH * kH;
-            for (int w = 0; w < a.nw; ++w) g += a.dbp[((size_t)w * 4 + l) * kH + i];
+            g = a.gvec[l * kH + (q - kH * kH)];
         }
     } else if (p < kOffB4) {
-        const int i = p - kOffW4;
-        for (int w = 0; w < a.nw; ++w) g += a.dw4p[(size_t)w * kH + i];
+        g = a.gvec[4 * kH + (p - kOffW4)];
     } else {
-        for (int w = 0; w < a.nw; ++w) g += a.db4p[w];
+        g = a.gvec[5 * kH];
     }
     if (a.grad_out) a.grad_out[p] = g;
     float val = a.params[p];
@@ -546,7 +566,7 @@ constexpr int kChunk = 512;   // rows per weight-gradient partial
 struct TrainWs {
     float4* uvrt;
     __bf16 *xt, *dzt, *wb;
-    float *h4, *gz, *dwp, *dbp, *dw4p, *db4p, *lossp;
+    float *h4, *gz, *dwp, *dbp, *dw4p, *db4p, *lossp, *gvec;
     int nchunk, nw;
     size_t total;
 };
@@ -572,6 +592,7 @@ TrainWs train_ws(unsigned char* base, int64_t B) {
     w.dw4p = reinterpret_cast<float*>(take(4 * (size_t)w.nw * kH));
     w.db4p = reinterpret_cast<float*>(take(4 * (size_t)w.nw));
     w.lossp = reinterpret_cast<float*>(take(4 * (size_t)w.nw));
+    w.gvec = reinterpret_cast<float*>(take(4 * (size_t)kVecOut));
     w.total = off;
     return w;
 }
@@ -652,7 +673,8 @@ extern "C" dgsm_status dgsm_mlp_grad(const float* params, const float* uvrt, int
     ReduceArgs r{};
     r.params = const_cast<float*>(params);
     r.dwp = w.dwp; r.nchunk = w.nchunk; r.dbp = w.dbp; r.dw4p = w.dw4p; r.db4p = w.db4p; r.lossp = w.lossp;
-    r.nw = w.nw; r.grad_out = grad; r.loss_out = loss; r.adam = 0;
+    r.nw = w.nw; r.gvec = w.gvec; r.grad_out = grad; r.loss_out = loss; r.adam = 0;
+    vec_reduce_kernel<<<kVecOut, 256, 0, s>>>(r);
     reduce_kernel<<<(kNParams + 255) / 256, 256, 0, s>>>(r);
     return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
@@ -693,6 +715,8 @@ extern "C" dgsm_status dgsm_mlp_train(float* params, float* adam_mv, const dgsm_
         r.lr = lr; r.beta1 = opt->beta1; r.beta2 = opt->beta2; r.eps = opt->eps;
         r.bc1 = (float)(1.0 - pow((double)opt->beta1, (double)t));
         r.bc2 = (float)(1.0 - pow((double)opt->beta2, (double)t));
+        r.gvec = w.gvec;
+        vec_reduce_kernel<<<kVecOut, 256, 0, s>>>(r);
         reduce_kernel<<<(kNParams + 255) / 256, 256, 0, s>>>(r);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }
