@@ -195,7 +195,7 @@ def main():
             P.dgsm_query(lights, atlas, table, sets[f].mean, out=Tq)
 
     # ---- pair counters for the roofline (untimed) -------------------------------------------
-    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    stats = torch.zeros(8, dtype=torch.int64, device=dev)
     n_stat = min(F, 6)
     for f in range(n_stat):
         P.dgsm_bin(lights, sets[f], atlas, ws)
@@ -204,7 +204,8 @@ def main():
     st = stats.cpu().numpy().astype(np.float64) / n_stat
     flops = (FLOPS_PER_TILE_PAIR * st[0] + FLOPS_PER_ACTIVE_PAIR * st[1] + FLOPS_PER_RAMP_EVAL * st[2])
     log(f"per frame: tile pairs {st[0]:.3e}, active pairs {st[1]:.3e}, ramp evals {st[2]:.3e}, "
-        f"list entries {st[3]:.3e}")
+        f"list entries {st[3]:.3e}, (tile, Gaussian) pairs {st[6]:.3e} of which idle {st[4]:.3e}, "
+        f"wave ramp iterations {st[5]:.3e}")
 
     def timed(fn, steps):
         t0 = torch.cuda.Event(enable_timing=True)
@@ -259,7 +260,9 @@ def main():
                 "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
                 "launch_ms": round(acc_ms, 4),
-                "units_per_launch": {"tile_pairs": st[0], "active_pairs": st[1], "ramp_evals": st[2]}}
+                "units_per_launch": {"tile_pairs": st[0], "active_pairs": st[1], "ramp_evals": st[2],
+                                     "tile_gaussian_pairs": st[6], "idle_tile_gaussian_pairs": st[4],
+                                     "wave_ramp_iterations": st[5]}}
 
     out = {"metric": METRIC, "value": round(ms_frame, 4), "unit": "ms/frame", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),

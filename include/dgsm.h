@@ -128,10 +128,13 @@ dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaus
  * whose cone reaches the tile are evaluated at every texel (Eq. 3), summed
  * over Gaussians in list order (Eq. 2; bitwise reproducible) and stored as T
  * (Eq. 4) in atlas.  n_gauss must equal the count passed to dgsm_bin.
- *   stats: optional device array [4] of counters the call ADDS to (zero it
- *   first): texel-Gaussian pairs evaluated at tile granularity, pairs whose
- *   prefactor exceeded cull_eps, erf-ramp evaluations, supertile list entries
- *   scanned.  NULL disables counting (the timed configuration).
+ *   stats: optional device array [8] of counters the call ADDS to (zero it
+ *   first): [0] texel-Gaussian pairs evaluated at tile granularity, [1] pairs
+ *   whose prefactor exceeded cull_eps, [2] erf-ramp evaluations of those,
+ *   [3] supertile list entries scanned, [4] (tile, Gaussian) pairs with no
+ *   texel above cull_eps, [5] shell iterations of the ramp loops (one per
+ *   wave and shell), [6] (tile, Gaussian) pairs, [7] unused (0).  NULL
+ *   disables counting (the timed configuration).
  * A tile with far more Gaussian hits than the launch's mean is cut into
  * slices evaluated by separate workgroups whose fixed-point sums are added
  * afterwards; integer sums make the atlas bitwise the same as unsplit.
@@ -217,7 +220,7 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  *                 accumulation on frame 0 of the real workload and keeps the
  *                 fastest pair: waves per tile (2, 4, 8) and work units per
  *                 launch (0, 512, 2048, 8192)
- *   tile_waves    waves sharing one 8x8 tile when autotune = 0 (2, 4 or 8; else 4)
+ *   tile_waves    waves sharing one 8x8 tile when autotune = 0 (2, 4 or 8; else 8)
  *   split_units   target number of work units per accumulation when
  *                 autotune = 0: a tile with more hits than (total hits /
  *                 split_units) is cut into slices run by separate blocks
@@ -326,6 +329,15 @@ dgsm_status dgsm_mlp_infer(const float* params, const dgsm_lights_t* lights, con
  * in FP64 in a fixed order (bitwise reproducible).  centroid: device [3].
  * n >= 1 and sum alpha > 0 required for a finite result. */
 dgsm_status dgsm_alpha_centroid(const dgsm_gaussians_t* gaussians, float* centroid, void* stream);
+
+/* dgsm_check_gaussians - count the Gaussians outside the domain of Eqs. 1-5:
+ * a non-finite mean, scale, rotation or opacity, a scale <= 0, an opacity
+ * outside [0, 1) (Eq. 5 takes -ln(1 - alpha)), or a zero quaternion.  The
+ * build does not check its inputs on the device (timing); callers that load
+ * untrusted data run this first.  counter: device int64 scratch (overwritten);
+ * *n_bad: host result.  Synchronises `stream`. */
+dgsm_status dgsm_check_gaussians(const dgsm_gaussians_t* gaussians, long long* counter, long long* n_bad,
+                                 void* stream);
 
 #ifdef __cplusplus
 }

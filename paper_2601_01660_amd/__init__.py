@@ -82,6 +82,8 @@ SIGNATURES = {
     "dgsm_work_units": (ctypes.c_int, [ctypes.POINTER(_AtlasDesc), ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.c_void_p]),
+    "dgsm_check_gaussians": (ctypes.c_int, [ctypes.POINTER(_Gaussians), ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_longlong), ctypes.c_void_p]),
     "dgsm_plan_tile_waves": (ctypes.c_int32, [ctypes.c_void_p]),
     "dgsm_plan_split_units": (ctypes.c_int32, [ctypes.c_void_p]),
     "dgsm_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
@@ -250,12 +252,14 @@ def dgsm_bin(lights, gaussians: GaussianSet, atlas: Atlas, workspace, kappa: flo
 def dgsm_accumulate(lights, atlas: Atlas, n_gauss: int, out, workspace, stats=None):
     """Second build phase: per-tile closed-form accumulation into ``out`` [L, K, H, W].
 
-    ``stats`` (optional int64 CUDA tensor [4], zeroed by the caller) receives the
-    pair counters documented in dgsm.h."""
+    ``stats`` (optional int64 CUDA tensor of >= 8 entries, zeroed by the caller)
+    receives the work counters documented in dgsm.h."""
     lights = _dev(lights)
     _cuda(out, "out")
     _cuda(workspace, "workspace")
     _cuda(stats, "stats")
+    if stats is not None and (stats.dtype != torch.int64 or stats.numel() < 8):
+        raise ValueError("stats must be an int64 tensor of at least 8 entries")
     d = atlas.struct()
     lt = _Lights(lights.data_ptr(), int(lights.shape[0]), 1.0)
     _check(lib().dgsm_accumulate(ctypes.byref(lt), ctypes.byref(d), n_gauss, _ptr(out), _ptr(workspace),
@@ -287,6 +291,15 @@ def dgsm_query(lights, atlas: Atlas, table, points, out=None):
     lt = _Lights(lights.data_ptr(), L, 1.0)
     _check(lib().dgsm_query(ctypes.byref(lt), ctypes.byref(d), _ptr(table), _ptr(points), P, _ptr(out), _stream()))
     return out
+
+
+def dgsm_check_gaussians(gaussians: GaussianSet) -> int:
+    """Number of Gaussians outside the method's domain (see dgsm.h); synchronises."""
+    counter = torch.empty(1, dtype=torch.int64, device=gaussians.mean.device)
+    n_bad = ctypes.c_longlong(0)
+    gs = gaussians.struct()
+    _check(lib().dgsm_check_gaussians(ctypes.byref(gs), _ptr(counter), ctypes.byref(n_bad), _stream()))
+    return int(n_bad.value)
 
 
 def dgsm_alpha_centroid(gaussians: GaussianSet, out=None):
@@ -325,7 +338,7 @@ class Plan:
     """
 
     def __init__(self, lights, atlas: Atlas, static: GaussianSet, n_dynamic: int, frames: int,
-                 static_cache: bool = True, autotune: bool = True, tile_waves: int = 4, split_units: int = 0,
+                 static_cache: bool = True, autotune: bool = True, tile_waves: int = 8, split_units: int = 0,
                  kappa: float = 1.0):
         lights = _dev(lights)
         self.L = int(lights.shape[0])

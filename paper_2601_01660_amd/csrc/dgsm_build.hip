@@ -578,10 +578,18 @@ constexpr float kRampEps = 1e-10f;
 
 // One (texel, Gaussian) pair for all 64 texels of the wave: Eq. 3 on the
 // shells where the erf ramps, as non-negative per-shell increments.
+// Work counters of the STATS variant (per wave, added to the launch totals).
+struct Counters {
+    unsigned long long hits = 0;        // (tile, Gaussian) pairs walked
+    unsigned long long act = 0;         // texel lanes with a prefactor above the pair threshold
+    unsigned long long ramp = 0;        // erf-ramp evaluations of those lanes
+    unsigned long long idle = 0;        // pairs of which no texel lane was active
+    unsigned long long ramp_wave = 0;   // shell iterations of the wave (SIMD work of the ramp)
+};
+
 template <bool STATS, bool GEO>
 __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r, const TexelState& s,
-                                                                unsigned long long& n_act,
-                                                                unsigned long long& n_ramp) {
+                                                                Counters& n) {
     // Ray-line geometry in FP64: v = m x d, t_e = -(m . d).
     const double vxd = r.my * s.dz - r.mz * s.dy;
     const double vyd = r.mz * s.dx - r.mx * s.dz;
@@ -603,8 +611,11 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     const float P0 = r.bp * rsa * __expf(-0.5f * e0);
     const bool act = s.valid && (P0 + P0 > s.pair_eps);
     const uint64_t abal = __ballot(act);
-    if (abal == 0ull) return;
-    if (STATS) n_act += __popcll(abal);
+    if (abal == 0ull) {
+        if (STATS) n.idle += 1;
+        return;
+    }
+    if (STATS) n.act += __popcll(abal);
     // Distance along the ray of the Mahalanobis-closest point:
     // t* = -b/a = t_e - (W d).(W p)/a with p = d x v the perpendicular offset.
     const float p0 = s.fy * vz - s.fz * vy, p1 = s.fz * vx - s.fx * vz, p2 = s.fx * vy - s.fy * vx;
@@ -631,7 +642,10 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     }
     const int kmin = wave_min(ka), kmax = wave_max(kb);
     if (kmin > kmax) return;
-    if (STATS) n_ramp += (unsigned long long)__popcll(abal) * (kmax - kmin + 1);
+    if (STATS) {
+        n.ramp += (unsigned long long)__popcll(abal) * (kmax - kmin + 1);
+        n.ramp_wave += (unsigned long long)(kmax - kmin + 1);
+    }
     double tk = shell_at(s, kmin);
     for (int k = kmin; k <= kmax; ++k) {
         const float x = sa * ((float)(tk - te) + corr);
@@ -652,9 +666,7 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
 template <bool STATS, bool GEO>
 __device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* words, int w0, int w1,
                                                                 const int* list, ConstF4Ptr rec,
-                                                                const TexelState& st, unsigned long long& n_hits,
-                                                                unsigned long long& n_act,
-                                                                unsigned long long& n_ramp) {
+                                                                const TexelState& st, Counters& n) {
     const int lane = st.lane;
     for (int gbase = w0; gbase < w1; gbase += 64) {
         const uint64_t wv = gbase + lane < w1 ? words[gbase + lane] : 0ull;
@@ -667,7 +679,7 @@ __device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* 
             uint64_t word = readlane_u64(wv, j);
             const int gcur = gv;
             if (nz) gv = list[64 * (gbase + __builtin_ctzll(nz)) + lane];   // next chunk's ids, in flight
-            if (STATS) n_hits += __popcll(word);
+            if (STATS) n.hits += __popcll(word);
             int b = __builtin_ctzll(word);
             word &= word - 1;
             RecRegs ra = load_rec(rec, readlane_i(gcur, b)), rb;
@@ -676,18 +688,18 @@ __device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* 
                     b = __builtin_ctzll(word);
                     word &= word - 1;
                     rb = load_rec(rec, readlane_i(gcur, b));
-                    eval_pair<STATS, GEO>(ra, st, n_act, n_ramp);
+                    eval_pair<STATS, GEO>(ra, st, n);
                 } else {
-                    eval_pair<STATS, GEO>(ra, st, n_act, n_ramp);
+                    eval_pair<STATS, GEO>(ra, st, n);
                     break;
                 }
                 if (word) {                                 // A in flight while B is evaluated
                     b = __builtin_ctzll(word);
                     word &= word - 1;
                     ra = load_rec(rec, readlane_i(gcur, b));
-                    eval_pair<STATS, GEO>(rb, st, n_act, n_ramp);
+                    eval_pair<STATS, GEO>(rb, st, n);
                 } else {
-                    eval_pair<STATS, GEO>(rb, st, n_act, n_ramp);
+                    eval_pair<STATS, GEO>(rb, st, n);
                     break;
                 }
             }
@@ -798,17 +810,20 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     const ConstF4Ptr rec = (ConstF4Ptr)(const void*)W.rec;
     const int per = (whi - wlo + NW - 1) / NW;
     const int w0 = min(whi, wlo + wave * per), w1 = min(whi, w0 + per);
-    unsigned long long n_hits = 0, n_act = 0, n_ramp = 0;
+    Counters n;
     __syncthreads();
 
-    walk_hits<STATS, GEO>(words, w0, w1, list, rec, st, n_hits, n_act, n_ramp);
+    walk_hits<STATS, GEO>(words, w0, w1, list, rec, st, n);
 
     if (STATS) {
         const unsigned long long nvalid = __popcll(__ballot(st.valid));
         if (lane == 0) {
-            atomicAdd(p.stats + 0, n_hits * nvalid);
-            atomicAdd(p.stats + 1, n_act);
-            atomicAdd(p.stats + 2, n_ramp);
+            atomicAdd(p.stats + 0, n.hits * nvalid);
+            atomicAdd(p.stats + 1, n.act);
+            atomicAdd(p.stats + 2, n.ramp);
+            atomicAdd(p.stats + 4, n.idle);
+            atomicAdd(p.stats + 5, n.ramp_wave);
+            atomicAdd(p.stats + 6, n.hits);
             if (wave == 0 && (int)blockIdx.x < g.ntiles) atomicAdd(p.stats + 3, (unsigned long long)(lb1 - lb0));
         }
     }

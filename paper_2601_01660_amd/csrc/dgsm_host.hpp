@@ -79,7 +79,7 @@ inline size_t plane_elems(const Geom& g, bool tiled) {
     return tiled ? (size_t)g.ntiles * kWave : (size_t)g.H * g.W;
 }
 
-constexpr int kDefaultTileWaves = 4;
+constexpr int kDefaultTileWaves = 8;
 constexpr int kDefaultSplitUnits = 2048;
 
 // Enqueue the per-tile accumulation of all lights into atlas [L][K][H][W].

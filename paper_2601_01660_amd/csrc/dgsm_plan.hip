@@ -214,7 +214,7 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     p->frames = opts->frames;
     p->cache = opts->static_cache != 0;
     p->autotune = opts->autotune;
-    p->tile_waves = (opts->tile_waves == 2 || opts->tile_waves == 8) ? opts->tile_waves : kDefaultTileWaves;
+    p->tile_waves = (opts->tile_waves == 2 || opts->tile_waves == 4) ? opts->tile_waves : kDefaultTileWaves;
     p->split_units = opts->split_units == 0 ? kDefaultSplitUnits : (opts->split_units < 0 ? -1 : opts->split_units);
     const size_t elem = desc->dtype == DGSM_F16 ? 2 : 4;
     const size_t table = (size_t)p->L * g.K * plane_elems(g, true);   // plan-internal: tile-major planes

@@ -102,6 +102,21 @@ def test_null_pointers_and_small_workspace_are_rejected(lib):
     assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, 1, None) == 1
 
 
+def test_check_and_work_unit_queries_validate_first(lib):
+    import paper_2601_01660_amd as P
+    n_bad = ctypes.c_longlong(-1)
+    gs = P._Gaussians(0, 0, 0, 0, 5)          # n > 0 with null arrays
+    assert lib.dgsm_check_gaussians(ctypes.byref(gs), 1, ctypes.byref(n_bad), None) == 1
+    gs = P._Gaussians(1, 1, 1, 1, 5)
+    assert lib.dgsm_check_gaussians(ctypes.byref(gs), None, ctypes.byref(n_bad), None) == 1
+    assert lib.dgsm_check_gaussians(ctypes.byref(gs), 1, None, None) == 1
+    d = _desc().struct()
+    out = (ctypes.c_int32 * 4)()
+    assert lib.dgsm_work_units(ctypes.byref(d), 100, 2, 1, 16, 0, out, None) == 2       # workspace too small
+    assert lib.dgsm_work_units(ctypes.byref(d), 100, 2, 1, 1 << 40, 2, out, None) == 1  # light out of range
+    assert n_bad.value == -1
+
+
 def test_binding_rejects_host_tensors_for_device_arguments():
     """A host pointer must never reach a kernel: the binding refuses CPU tensors
     where the library expects device memory."""

@@ -265,3 +265,19 @@ def test_sh_transfer_matches_oracle(kp, q):
     ok = ~amb
     assert np.abs(fo.cpu().numpy()[ok] - f_ref[ok]).max() <= 1e-4 * max(1.0, np.abs(f_ref).max())
     assert np.abs(rgb.cpu().numpy()[ok] - rgb_ref[ok]).max() <= 1e-4 * max(1.0, np.abs(rgb_ref).max())
+
+
+def test_domain_check_counts_bad_gaussians():
+    import paper_2601_01660_amd as P
+    rng = np.random.default_rng(3)
+    g = synth.random_gaussians(rng, rng.uniform(-1, 1, (1000, 3)), 0.03)
+    assert P.dgsm_check_gaussians(P.GaussianSet.from_host(g)) == 0
+    mean, scale, rot, opac = g.mean.copy(), g.scale.copy(), g.rot.copy(), g.opacity.copy()
+    mean[5, 1] = np.nan
+    scale[17, 2] = 0.0
+    rot[300] = 0.0
+    opac[999] = 1.0
+    opac[640] = -0.1
+    scale[640, 0] = np.inf          # two faults on one Gaussian count once
+    bad = P.GaussianSet.from_host(synth.Gaussians(mean, scale, rot, opac))
+    assert P.dgsm_check_gaussians(bad) == 5
