@@ -133,7 +133,8 @@ dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaus
  *   whose prefactor exceeded cull_eps, [2] erf-ramp evaluations of those,
  *   [3] supertile list entries scanned, [4] (tile, Gaussian) pairs with no
  *   texel above cull_eps, [5] shell iterations of the ramp loops (one per
- *   wave and shell), [6] (tile, Gaussian) pairs, [7] unused (0).  NULL
+ *   wave and shell), [6] (tile, Gaussian) pairs, [7] idle pairs rejected by
+ *   the distance pre-test (a subset of [4]).  NULL
  *   disables counting (the timed configuration).
  * A tile with far more Gaussian hits than the launch's mean is cut into
  * slices evaluated by separate workgroups whose fixed-point sums are added
@@ -219,7 +220,9 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  *   autotune      1: the first run times the two knobs of the tile
  *                 accumulation on frame 0 of the real workload and keeps the
  *                 fastest pair: waves per tile (2, 4, 8) and work units per
- *                 launch (0, 512, 2048, 8192)
+ *                 launch (never, 512, 2048, 8192); in cache mode they apply
+ *                 to the per-frame dynamic accumulation, the once-per-run
+ *                 static build keeps the defaults (8 waves, 2048 units)
  *   tile_waves    waves sharing one 8x8 tile when autotune = 0 (2, 4 or 8; else 8)
  *   split_units   target number of work units per accumulation when
  *                 autotune = 0: a tile with more hits than (total hits /

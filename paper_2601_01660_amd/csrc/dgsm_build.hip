@@ -191,14 +191,25 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
         r.mx = (double)light[0] - (double)a.mean[3 * i];
         r.my = (double)light[1] - (double)a.mean[3 * i + 1];
         r.mz = (double)light[2] - (double)a.mean[3 * i + 2];
-        r.pad[0] = r.pad[1] = r.pad[2] = 0.f;
+        // Per-texel pre-test radius.  The tile build keeps a texel when
+        // 2 P0 > eps, with P0 = beta sqrt(pi/2) a^(-1/2) exp(-e0/2).  Since
+        // a >= 1/s_max^2 and e0 >= h^2/s_max^2 (h = |m x d|, the distance from
+        // mu to the line of the ray), 2 P0 <= 2 bp s_max exp(-h^2/(2 s_max^2)):
+        // no texel with h^2 >= 2 s_max^2 ln(2 bp s_max / eps) can be kept.
+        const double smax = fmax(s[0], fmax(s[1], s[2]));
+        {
+            const double lim = 2.0 * (double)r.bp * smax;
+            double r2 = 3.0e38;                              // eps = 0: every texel is kept
+            if (a.eps > 0.f) r2 = lim > (double)a.eps ? 2.0 * smax * smax * log(lim / (double)a.eps) : 0.0;
+            r.r2 = (float)fmin(r2 * (1.0 + 1e-5), 3.0e38);
+        }
+        r.pad[0] = r.pad[1] = 0.f;
         W.rec[i] = r;
 
         // Culling cone.  Along any ray the contribution is at most
         // U exp(-h^2 / (2 s_max^2)), U = kappa tau* sqrt(tr A / 3) s_max, with h
         // the distance from mu to the ray (D for rays pointing away).  So it is
         // below eps outside the cone sin(theta) <= (s_max / D) sqrt(2 ln(U / eps)).
-        const double smax = fmax(s[0], fmax(s[1], s[2]));
         const double D = sqrt(r.mx * r.mx + r.my * r.my + r.mz * r.mz);
         const double U = amp * smax;
         if (!(alpha > 0.0) || !(U > (double)a.eps)) {
@@ -491,7 +502,7 @@ typedef const __attribute__((address_space(4))) f4v* ConstF4Ptr;
 
 struct RecRegs {
     double mx, my, mz;
-    float w[9], c[9], bp;
+    float w[9], c[9], bp, r2;
 };
 
 __device__ inline double as_double(float lo, float hi) {
@@ -510,6 +521,7 @@ __device__ inline RecRegs load_rec(ConstF4Ptr base, int gi) {
     r.c[0] = q3.w; r.c[1] = q4.x; r.c[2] = q4.y; r.c[3] = q4.z; r.c[4] = q4.w;
     r.c[5] = q5.x; r.c[6] = q5.y; r.c[7] = q5.z; r.c[8] = q5.w;
     r.bp = q6.x;
+    r.r2 = q6.y;
     return r;
 }
 
@@ -585,6 +597,7 @@ struct Counters {
     unsigned long long ramp = 0;        // erf-ramp evaluations of those lanes
     unsigned long long idle = 0;        // pairs of which no texel lane was active
     unsigned long long ramp_wave = 0;   // shell iterations of the wave (SIMD work of the ramp)
+    unsigned long long pre = 0;         // idle pairs already rejected by the distance pre-test
 };
 
 template <bool STATS, bool GEO>
@@ -596,6 +609,14 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     const double vzd = r.mx * s.dy - r.my * s.dx;
     const double te = -(r.mx * s.dx + r.my * s.dy + r.mz * s.dz);
     const float vx = (float)vxd, vy = (float)vyd, vz = (float)vzd;
+    // cheap pre-test (conservative: it never drops a texel the full test keeps)
+    if (__ballot(s.valid && vx * vx + vy * vy + vz * vz < r.r2) == 0ull) {
+        if (STATS) {
+            n.idle += 1;
+            n.pre += 1;
+        }
+        return;
+    }
     // a = |W d|^2 (Eq. 2);  c - b^2/a = |adj(A)^(1/2) (m x d)|^2 / a
     const float wd0 = r.w[0] * s.fx + r.w[1] * s.fy + r.w[2] * s.fz;
     const float wd1 = r.w[3] * s.fx + r.w[4] * s.fy + r.w[5] * s.fz;
@@ -824,6 +845,7 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
             atomicAdd(p.stats + 4, n.idle);
             atomicAdd(p.stats + 5, n.ramp_wave);
             atomicAdd(p.stats + 6, n.hits);
+            atomicAdd(p.stats + 7, n.pre);
             if (wave == 0 && (int)blockIdx.x < g.ntiles) atomicAdd(p.stats + 3, (unsigned long long)(lb1 - lb0));
         }
     }

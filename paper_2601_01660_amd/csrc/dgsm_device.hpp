@@ -53,7 +53,8 @@ struct __attribute__((aligned(16))) GRec {
     float w[9];
     float c[9];
     float bp;            // beta * sqrt(pi / 2)
-    float pad[3];
+    float r2;            // squared ray-to-mean distance beyond which no texel is active
+    float pad[2];
 };
 static_assert(sizeof(GRec) == 112, "GRec layout");
 

@@ -138,7 +138,9 @@ dgsm_status enqueue_run(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* t
             return DGSM_EHIP;
     }
     dgsm_status s;
-    if (p->cache && (s = enqueue_static(p, p->tile_waves, p->split_units, st)) != DGSM_OK) return s;
+    // the static build is a full-scene accumulation: it keeps the defaults
+    // (the tuned knobs fit the per-frame dynamic accumulation)
+    if (p->cache && (s = enqueue_static(p, kDefaultTileWaves, kDefaultSplitUnits, st)) != DGSM_OK) return s;
     for (int f = 0; f < p->frames; ++f)
         if ((s = enqueue_frame(p, f, dyn->mean, translations, T_out, p->tile_waves, p->split_units, st)) != DGSM_OK)
             return s;

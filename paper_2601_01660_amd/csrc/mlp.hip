@@ -184,48 +184,55 @@ struct FwdArgs {
     int atlas_f16;
 };
 
-template <int MODE>
-__global__ __launch_bounds__(256) void fwd_kernel(FwdArgs a) {
+// Lanes 0..15 hold the inputs of the wave's 16 rows; any lane reads row r's
+// input by a cross-lane shuffle.
+__device__ inline float4 input_of(const float4& mine, int r) {
+    return make_float4(__shfl(mine.x, r, kWave), __shfl(mine.y, r, kWave), __shfl(mine.z, r, kWave),
+                       __shfl(mine.w, r, kWave));
+}
+
+// NWV waves per block share the weights in LDS (inference runs 8 waves, two
+// per SIMD, so that one wave's LDS and MFMA latencies hide behind the
+// other's; training keeps 4 because its stash stores need more registers).
+template <int MODE, int NWV>
+__global__ __launch_bounds__(kWave * NWV) void fwd_kernel(FwdArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    constexpr int kTile = kRows * NWV;
     bf16x8* wl = reinterpret_cast<bf16x8*>(smem);                        // [4][128 rows][16 chunks]
-    bf16x8* act = wl + 4 * kH * 16;                                     // [4 waves][16 rows][16 chunks]
-    float4* rin = reinterpret_cast<float4*>(act + kWaves * kRows * 16);   // [4 waves][16] (u, v, rho, target)
+    bf16x8* act = wl + 4 * kH * 16;                                     // [NWV waves][16 rows][16 chunks]
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const int light = blockIdx.y;
     const float* P = a.params + (size_t)light * kNParams;
     const __bf16* Wg = a.wb + (size_t)light * 4 * kH * kH;
     // all four weight matrices into LDS, swizzled rows
-    for (int q = tid; q < 4 * kH * 16; q += 256) {
+    for (int q = tid; q < 4 * kH * 16; q += kWave * NWV) {
         const int row = q / 16, c = q % 16;                              // row = 128 l + j
         wl[(row / kH) * kH * 16 + swz(row % kH, c)] = *reinterpret_cast<const bf16x8*>(Wg + (size_t)row * kH + 8 * c);
     }
     __syncthreads();
     bf16x8* my = act + wave * kRows * 16;
-    float4* myin = rin + wave * kRows;
     const float fscale = __log2f(0.25f * (float)a.g.W) / 15.f;
-    const int ntile = (int)((a.n + kTileRows - 1) / kTileRows);
+    const int ntile = (int)((a.n + kTile - 1) / kTile);
     const int lr = lane % 16, lg = lane / 16;
     for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
-        const int64_t row0 = (int64_t)t * kTileRows + wave * kRows;
-        // inputs of the wave's 16 rows
+        const int64_t row0 = (int64_t)t * kTile + wave * kRows;
+        // inputs of the wave's 16 rows (u, v, rho, target) in lanes 0..15
+        float4 in_mine = make_float4(0.f, 0.f, 0.f, 0.f);
         if (lane < kRows) {
             const int64_t rr = row0 + lane;
-            float4 in = make_float4(0.f, 0.f, 0.f, 0.f);
             if (rr < a.n) {
                 if (MODE == kInfer) {
                     float r;
                     encode_point(a.points[3 * rr], a.points[3 * rr + 1], a.points[3 * rr + 2], a.lights + 3 * light,
-                                 a.g, in.x, in.y, in.z, r);
+                                 a.g, in_mine.x, in_mine.y, in_mine.z, r);
                 } else {
-                    in = a.uvrt[rr];
+                    in_mine = a.uvrt[rr];
                 }
             }
-            myin[lane] = in;
         }
-        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0): the wave's LDS writes are visible to its lanes
         __builtin_amdgcn_wave_barrier();
         {   // features: lane handles row lr, chunks lg + 4q
-            const float4 in = myin[lr];
+            const float4 in = input_of(in_mine, lr);
             for (int q = 0; q < 4; ++q) {
                 const int c = lg + 4 * q;
                 bf16x8 ch;
@@ -287,7 +294,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs a) {
             float gzr[4], lsum = 0.f;
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = row0 + 4 * lg + r;
-                const float tgt = myin[4 * lg + r].w;
+                const float tgt = __shfl(in_mine.w, 4 * lg + r, kWave);
                 const float d = T[r] - tgt;
                 gzr[r] = row < a.n ? 2.f * d * a.inv_n * (-T[r] * (1.f - T[r])) : 0.f;
                 lsum += row < a.n ? d * d * a.inv_n : 0.f;
@@ -316,13 +323,13 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs a) {
                 a.db4p[wid] = gs;
                 a.lossp[wid] = lsum;
             }
-        } else if (lr < 4) {
-            // lane (lg, lr) finishes row 4 lg + lr
-            const int rr = 4 * lg + lr;
+        } else {
+            // lane (lg, lr < 4) finishes row 4 lg + lr (the shuffle runs in every lane)
+            const int rr = 4 * lg + (lr & 3);
+            const float4 in = input_of(in_mine, rr);
             const int64_t row = row0 + rr;
-            const float t = lr == 0 ? T[0] : lr == 1 ? T[1] : lr == 2 ? T[2] : T[3];
-            const float4 in = myin[rr];
-            if (row < a.n && a.atlas) {
+            const float t = (lr & 3) == 0 ? T[0] : (lr & 3) == 1 ? T[1] : (lr & 3) == 2 ? T[2] : T[3];
+            if (lr < 4 && row < a.n && a.atlas) {
                 const size_t tsz = (size_t)a.g.K * a.g.H * a.g.W;
                 int region;
                 const float ta = a.atlas_f16
@@ -342,7 +349,7 @@ __global__ __launch_bounds__(256) void fwd_kernel(FwdArgs a) {
                     const bool fb = a.mask && a.mask[light * nreg + region];
                     a.T[(size_t)light * a.n + row] = fb ? ta : t;
                 }
-            } else if (row < a.n && MODE == kInfer) {
+            } else if (lr < 4 && row < a.n && MODE == kInfer) {
                 a.T[(size_t)light * a.n + row] = t;
             }
         }
@@ -597,24 +604,28 @@ TrainWs train_ws(unsigned char* base, int64_t B) {
     return w;
 }
 
-constexpr size_t kFwdSmem = (size_t)(4 * kH * 16 + kWaves * kRows * 16) * 16 + kWaves * kRows * 16;
+constexpr int kInferWaves = 8;
+constexpr size_t fwd_smem(int nwv) { return (size_t)(4 * kH * 16 + nwv * kRows * 16) * 16; }
+constexpr size_t kFwdSmem = fwd_smem(kWaves);
+constexpr size_t kInferSmem = fwd_smem(kInferWaves);
+static_assert(kInferSmem <= 160 * 1024, "inference block exceeds the LDS of a CU");
 constexpr size_t kBwdSmem = (size_t)(3 * kH * 16 + kWaves * kRows * 16) * 16;
 
-int grid_rows(int64_t n) {
-    const int64_t t = (n + kTileRows - 1) / kTileRows;
+int grid_rows(int64_t n, int rows = kTileRows) {
+    const int64_t t = (n + rows - 1) / rows;
     return (int)(t < 1024 ? (t < 1 ? 1 : t) : 1024);
 }
 
 hipError_t set_smem() {
     static const hipError_t e = [] {
-        hipError_t r = hipFuncSetAttribute((const void*)fwd_kernel<kTrain>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)kFwdSmem);
+        hipError_t r = hipFuncSetAttribute((const void*)fwd_kernel<kTrain, kWaves>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdSmem);
         if (r == hipSuccess)
-            r = hipFuncSetAttribute((const void*)fwd_kernel<kInfer>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)kFwdSmem);
+            r = hipFuncSetAttribute((const void*)fwd_kernel<kInfer, kInferWaves>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kInferSmem);
         if (r == hipSuccess)
-            r = hipFuncSetAttribute((const void*)fwd_kernel<kCheck>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)kFwdSmem);
+            r = hipFuncSetAttribute((const void*)fwd_kernel<kCheck, kWaves>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdSmem);
         if (r == hipSuccess)
             r = hipFuncSetAttribute((const void*)bwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)kBwdSmem);
@@ -638,7 +649,7 @@ dgsm_status enqueue_fwd_bwd(const float* params, const Geom& g, int64_t B, const
     f.db4p = w.db4p;
     f.lossp = w.lossp;
     f.inv_n = 1.f / (float)B;
-    fwd_kernel<kTrain><<<dim3(grid_rows(B), 1), 256, kFwdSmem, st>>>(f);
+    fwd_kernel<kTrain, kWaves><<<dim3(grid_rows(B), 1), kWave * kWaves, kFwdSmem, st>>>(f);
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     BwdArgs b{params, w.wb, B, w.xt, w.h4, w.gz, w.dzt, w.dbp};
     bwd_kernel<<<grid_rows(B), 256, kBwdSmem, st>>>(b);
@@ -751,7 +762,7 @@ extern "C" dgsm_status dgsm_mlp_check(const float* params, const dgsm_atlas_desc
     FwdArgs f{};
     f.g = g; f.params = params; f.wb = wb; f.n = n_check; f.uvrt = uvrt; f.atlas = atlas_l;
     f.mask_out = mask; f.thresh = thresh; f.check_stats = stats; f.atlas_f16 = desc->dtype == DGSM_F16;
-    fwd_kernel<kCheck><<<dim3(grid_rows(n_check), 1), 256, kFwdSmem, s>>>(f);
+    fwd_kernel<kCheck, kWaves><<<dim3(grid_rows(n_check), 1), kWave * kWaves, kFwdSmem, s>>>(f);
     return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
 
@@ -773,6 +784,7 @@ extern "C" dgsm_status dgsm_mlp_infer(const float* params, const dgsm_lights_t* 
     FwdArgs f{};
     f.g = geom_of(desc); f.params = params; f.wb = wb; f.n = P; f.points = points; f.lights = lights->pos;
     f.atlas = mask ? atlas : nullptr; f.mask = mask; f.T = T; f.atlas_f16 = desc->dtype == DGSM_F16;
-    fwd_kernel<kInfer><<<dim3(grid_rows(P), lights->n), 256, kFwdSmem, s>>>(f);
+    fwd_kernel<kInfer, kInferWaves><<<dim3(grid_rows(P, kRows * kInferWaves), lights->n), kWave * kInferWaves,
+                                      kInferSmem, s>>>(f);
     return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
