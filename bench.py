@@ -25,7 +25,8 @@ METRIC = "DGSM build+query ms/frame (2M Gaussians, 4 lights); surrogate vs atlas
 
 # Algorithmic FP32-equivalent flops of the per-tile accumulation, per counted unit
 # (FMA = 2; transcendental = 1): see the roofline section of the design notes.
-FLOPS_PER_TILE_PAIR = 62      # ray geometry, a, e0, prefactor: every binned (texel, Gaussian) pair
+FLOPS_PER_TILE_PAIR = 14      # distance pre-test (FP64 m x d, |m x d|^2): every binned (texel, Gaussian) pair
+FLOPS_PER_TESTED_PAIR = 53    # m.d, W d, a, adj(A)^1/2 (m x d), e0, prefactor: pairs of waves past the pre-test
 FLOPS_PER_ACTIVE_PAIR = 45    # closest-approach distance, erf scale, shell range: pairs above cull_eps
 FLOPS_PER_RAMP_EVAL = 27      # one shell of the erf ramp: argument, erf, increment
 PEAK_FP32_TFLOPS = 157.3
@@ -202,10 +203,12 @@ def main():
         P.dgsm_accumulate(lights, atlas, N, table, ws, stats=stats)
     torch.cuda.synchronize()
     st = stats.cpu().numpy().astype(np.float64) / n_stat
-    flops = (FLOPS_PER_TILE_PAIR * st[0] + FLOPS_PER_ACTIVE_PAIR * st[1] + FLOPS_PER_RAMP_EVAL * st[2])
+    tested = st[0] * (1.0 - st[7] / max(st[6], 1.0))     # texel pairs of waves the pre-test kept
+    flops = (FLOPS_PER_TILE_PAIR * st[0] + FLOPS_PER_TESTED_PAIR * tested + FLOPS_PER_ACTIVE_PAIR * st[1]
+             + FLOPS_PER_RAMP_EVAL * st[2])
     log(f"per frame: tile pairs {st[0]:.3e}, active pairs {st[1]:.3e}, ramp evals {st[2]:.3e}, "
         f"list entries {st[3]:.3e}, (tile, Gaussian) pairs {st[6]:.3e} of which idle {st[4]:.3e}, "
-        f"wave ramp iterations {st[5]:.3e}")
+        f"wave ramp iterations {st[5]:.3e}, rejected by the pre-test {st[7]:.3e}")
 
     def timed(fn, steps):
         t0 = torch.cuda.Event(enable_timing=True)
@@ -262,7 +265,8 @@ def main():
                 "launch_ms": round(acc_ms, 4),
                 "units_per_launch": {"tile_pairs": st[0], "active_pairs": st[1], "ramp_evals": st[2],
                                      "tile_gaussian_pairs": st[6], "idle_tile_gaussian_pairs": st[4],
-                                     "wave_ramp_iterations": st[5]}}
+                                     "wave_ramp_iterations": st[5], "pretest_rejected_pairs": st[7],
+                                     "texel_pairs_past_pretest": tested}}
 
     out = {"metric": METRIC, "value": round(ms_frame, 4), "unit": "ms/frame", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 3),

@@ -341,7 +341,15 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
     __syncthreads();
     const int nchunks = sbase[g.S] / 64;
     const int nwaves = gridDim.x * 4;
-    for (int c = blockIdx.x * 4 + tid / kWave; c < nchunks; c += nwaves) {
+    // each wave takes a contiguous run of chunks (mostly of one supertile) and
+    // keeps per-tile hit counts in registers (lane t: tile t of the current
+    // supertile), flushed with one atomic per tile when the supertile changes
+    const int per = (nchunks + nwaves - 1) / nwaves;
+    const int gw = blockIdx.x * 4 + tid / kWave;
+    const int cbeg = min(nchunks, gw * per), cend = min(nchunks, cbeg + per);
+    int s_cur = -1, cnt = 0;
+    SuperSpan sp_cur{0, 0, 0, 0};
+    for (int c = cbeg; c < cend; ++c) {
         // supertile of this chunk: the last s with sbase[s] <= 64 c
         int lo = 0, hi = g.S - 1;
         while (lo < hi) {
@@ -349,10 +357,17 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
             if (sbase[mid] <= 64 * c) lo = mid; else hi = mid - 1;
         }
         const int s = lo;
+        if (s != s_cur) {
+            if (cnt && lane < sp_cur.nty * sp_cur.ntx)
+                atomicAdd(W.hits + (sp_cur.ty0 + lane / sp_cur.ntx) * g.TW + sp_cur.tx0 + lane % sp_cur.ntx, cnt);
+            s_cur = s;
+            cnt = 0;
+            sp_cur = super_span(g, s);
+        }
         const int e = 64 * c + lane;
         float4 cone = make_float4(0.f, 0.f, 1.f, -1.f);
         if (e < sbase[s] + stot[s]) cone = W.cone[W.lists[e]];
-        const SuperSpan sp = super_span(g, s);
+        const SuperSpan sp = sp_cur;
         const int nt = sp.nty * sp.ntx;
         uint64_t mine = 0;
         for (int t = 0; t < nt; ++t) {
@@ -363,9 +378,11 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
         const int c0 = sbase[s] / 64, ns = (sbase[s + 1] - sbase[s]) / 64;
         if (lane < nt) {
             W.bits[64 * (size_t)c0 + (size_t)lane * ns + (c - c0)] = mine;
-            if (mine) atomicAdd(W.hits + (sp.ty0 + lane / sp.ntx) * g.TW + sp.tx0 + lane % sp.ntx, __popcll(mine));
+            cnt += __popcll(mine);
         }
     }
+    if (cnt && s_cur >= 0 && lane < sp_cur.nty * sp_cur.ntx)
+        atomicAdd(W.hits + (sp_cur.ty0 + lane / sp_cur.ntx) * g.TW + sp_cur.tx0 + lane % sp_cur.ntx, cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -728,13 +745,13 @@ __device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* 
     }
 }
 
-// NW waves share one tile's accumulators (a launch knob: more waves per tile
-// split a tile's pairs finer and raise occupancy per LDS byte).
-// Per texel: prefix of the fixed-point per-shell increments inc(k) over the
-// shells (Eq. 2 as a running sum), optional base optical depth, then either
-// tau (FP32) or T = exp(-tau) (Eq. 4), shell-major.
-template <typename OutT, typename Inc>
-__device__ inline void finish_texel(const TileArgs& p, int light, int py, int px, Inc inc) {
+constexpr int kFinishGroup = 8;
+
+// Per texel: prefix of the fixed-point per-shell increments over the shells
+// (Eq. 2 as a running sum; load fills one group of increments), optional base
+// optical depth, then either tau (FP32) or T = exp(-tau) (Eq. 4), shell-major.
+template <typename OutT, typename Load>
+__device__ inline void finish_texel(const TileArgs& p, int light, int py, int px, Load load) {
     const Geom& g = p.g;
     const int K = g.K;
     const size_t plane = p.tiled ? (size_t)g.ntiles * kWave : (size_t)g.H * g.W;
@@ -744,26 +761,40 @@ __device__ inline void finish_texel(const TileArgs& p, int light, int py, int px
     const float* bt = p.base_tau ? p.base_tau + off : nullptr;
     unsigned long long acc = 0;
     float Tp = 1.f;
-    if (p.write_tau) {
-        float* out = reinterpret_cast<float*>(p.out) + off;
-        for (int k = 0; k < K; ++k) {
-            acc += inc(k);
-            const float tau = (float)from_fixed(acc);
-            out[(size_t)k * plane] = bt ? tau + bt[(size_t)k * plane] : tau;
-        }
-    } else {
-        OutT* out = reinterpret_cast<OutT*>(p.out) + off;
-        for (int k = 0; k < K; ++k) {
-            acc += inc(k);
-            const float tau = (float)from_fixed(acc);
-            const float tt = bt ? tau + bt[(size_t)k * plane] : tau;
-            const float T = fminf(__expf(-tt), Tp);   // exactly non-increasing in k
-            Tp = T;
-            Store<OutT>::put(out + (size_t)k * plane, T);
+    // groups of kFinishGroup shells: the group's loads are all in flight before
+    // the first use (a shell-by-shell loop would wait one memory latency per shell)
+    for (int k0 = 0; k0 < K; k0 += kFinishGroup) {
+        const int n = min(kFinishGroup, K - k0);
+        unsigned long long iv[kFinishGroup];
+        float bv[kFinishGroup];
+        load(k0, n, iv);
+#pragma unroll
+        for (int j = 0; j < kFinishGroup; ++j) bv[j] = (bt && j < n) ? bt[(size_t)(k0 + j) * plane] : 0.f;
+        if (p.write_tau) {
+            float* out = reinterpret_cast<float*>(p.out) + off;
+#pragma unroll
+            for (int j = 0; j < kFinishGroup; ++j) {
+                if (j >= n) break;
+                acc += iv[j];
+                out[(size_t)(k0 + j) * plane] = (float)from_fixed(acc) + bv[j];
+            }
+        } else {
+            OutT* out = reinterpret_cast<OutT*>(p.out) + off;
+#pragma unroll
+            for (int j = 0; j < kFinishGroup; ++j) {
+                if (j >= n) break;
+                acc += iv[j];
+                const float tt = (float)from_fixed(acc) + bv[j];
+                const float T = fminf(__expf(-tt), Tp);   // exactly non-increasing in k
+                Tp = T;
+                Store<OutT>::put(out + (size_t)(k0 + j) * plane, T);
+            }
         }
     }
 }
 
+// NW waves share one tile's accumulators (a launch knob: more waves per tile
+// split a tile's pairs finer and raise occupancy per LDS byte).
 template <typename OutT, bool STATS, int NW, bool GEO>
 __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -857,7 +888,10 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     }
 
     if (wave == 0 && st.valid)
-        finish_texel<OutT>(p, light, py, px, [&](int k) { return inc[k * kWave + lane]; });
+        finish_texel<OutT>(p, light, py, px, [&](int k0, int n, unsigned long long* iv) {
+#pragma unroll
+            for (int j = 0; j < kFinishGroup; ++j) iv[j] = j < n ? inc[(k0 + j) * kWave + lane] : 0ull;
+        });
 }
 
 // Split tiles: add the slices' partial sums in slice order, then finish as above.
@@ -875,10 +909,15 @@ __global__ __launch_bounds__(kWave) void split_finish_kernel(TileArgs p) {
     if (py >= g.H || px >= g.W) return;
     const size_t slice = (size_t)g.K * kWave;
     const unsigned long long* src = W.part + (size_t)sp.y * slice + lane;
-    finish_texel<OutT>(p, light, py, px, [&](int k) {
-        unsigned long long v = 0;
-        for (int i = 0; i < q; ++i) v += src[(size_t)i * slice + (size_t)k * kWave];
-        return v;
+    finish_texel<OutT>(p, light, py, px, [&](int k0, int n, unsigned long long* iv) {
+#pragma unroll
+        for (int j = 0; j < kFinishGroup; ++j) iv[j] = 0ull;
+        for (int i = 0; i < q; ++i) {
+            const unsigned long long* s0 = src + (size_t)i * slice + (size_t)k0 * kWave;
+#pragma unroll
+            for (int j = 0; j < kFinishGroup; ++j)
+                if (j < n) iv[j] += s0[(size_t)j * kWave];
+        }
     });
 }
 
