@@ -91,35 +91,6 @@ __global__ __launch_bounds__(64) void super_cone_kernel(Geom g, const float4* __
 // Workspace slices
 // ---------------------------------------------------------------------------
 
-// Pointers into one light's slice of the workspace.
-struct LightWs {
-    int* totals;       // [kMaxSuper] list length per supertile
-    int* lbase;        // [kMaxSuper + 1] list base per supertile, multiples of 64
-    GRec* rec;         // [n]
-    float4* cone;      // [n]
-    uint64_t* mask;    // [n][kMaskWords] supertile masks
-    int* counts;       // [S][nb] per-block counts, scanned in place
-    int* lists;        // [cap] supertile lists, 64-entry chunks
-    uint64_t* bits;    // [cap] per supertile: [tile][chunk] hit words
-    int* hits;         // [ntiles] set bits over a tile's hit words
-    int4* tinfo;       // [ntiles] {slices, first partial (-1: not split), end word of slice 0, words}
-    int4* units;       // [units_cap] extra slices: {tile, first word, end word, partial}
-    int2* splits;      // [units_cap] split tiles: {tile, first partial}
-    int* nunits;       // [4] {extra slices, split tiles, hits per slice, total hits}
-    unsigned long long* part;   // [2 units_cap][K][64] fixed-point partial optical depths
-};
-
-__host__ __device__ inline LightWs light_ws(unsigned char* ws, const BuildLayout& L, int l) {
-    unsigned char* b = ws + L.light0 + (size_t)l * L.light_stride;
-    return LightWs{reinterpret_cast<int*>(b + L.totals), reinterpret_cast<int*>(b + L.lbase),
-                   reinterpret_cast<GRec*>(b + L.rec), reinterpret_cast<float4*>(b + L.cone),
-                   reinterpret_cast<uint64_t*>(b + L.mask), reinterpret_cast<int*>(b + L.counts),
-                   reinterpret_cast<int*>(b + L.lists), reinterpret_cast<uint64_t*>(b + L.bits),
-                   reinterpret_cast<int*>(b + L.hits), reinterpret_cast<int4*>(b + L.tinfo),
-                   reinterpret_cast<int4*>(b + L.units), reinterpret_cast<int2*>(b + L.splits),
-                   reinterpret_cast<int*>(b + L.nunits), reinterpret_cast<unsigned long long*>(b + L.part)};
-}
-
 // Tiles of supertile s: origin, extent and local index t = (ty-ty0)*ntx + (tx-tx0).
 struct SuperSpan {
     int ty0, tx0, nty, ntx;
@@ -508,6 +479,7 @@ struct TileArgs {
     const float* base_tau;     // optional [L][K][plane]
     int write_tau;
     int tiled;                 // plane order: 0 row-major H x W; 1 tile-major [TH*TW][8x8]
+    int skip_empty;            // tiles without hits return at once and write nothing
     unsigned long long* stats;
 };
 
@@ -747,48 +719,92 @@ __device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* 
 
 constexpr int kFinishGroup = 8;
 
-// Per texel: prefix of the fixed-point per-shell increments over the shells
-// (Eq. 2 as a running sum; load fills one group of increments), optional base
-// optical depth, then either tau (FP32) or T = exp(-tau) (Eq. 4), shell-major.
-template <typename OutT, typename Load>
-__device__ inline void finish_texel(const TileArgs& p, int light, int py, int px, Load load) {
+// Finish of one tile by all NWB waves of the block: wave w takes shells
+// [w P, (w+1) P), P = ceil(K / NWB).  Per texel (lane) and shell k:
+//   tau_k = prefix over shells of the fixed-point increments inc[k][lane]
+//           (Eq. 2 as a running sum) + optional base optical depth,
+//   T_k   = min(exp(-tau_k), T_{k-1}), T_{-1} = 1 (Eq. 4; exactly non-increasing).
+// Pass 1 publishes each wave's increment total (so every wave knows the sum
+// below its range), pass 2 each wave's minimum of exp(-tau) (the running
+// minimum below its range), pass 3 stores.  Every stored value is bitwise the
+// one a single wave walking all shells in order would store.  Base loads come
+// in groups of kFinishGroup shells, so each group costs one memory latency.
+template <typename OutT, int NWB>
+__device__ inline void finish_tile(const TileArgs& p, int light, int tile, int lane, int wave,
+                                   const unsigned long long* inc, unsigned long long* s_tot, float* s_min) {
     const Geom& g = p.g;
     const int K = g.K;
+    const int ty = tile / g.TW, tx = tile - ty * g.TW;
+    const int py = ty * kTile + (lane >> 3), px = tx * kTile + (lane & 7);
+    const bool valid = py < g.H && px < g.W;
     const size_t plane = p.tiled ? (size_t)g.ntiles * kWave : (size_t)g.H * g.W;
-    const size_t texel = p.tiled ? (size_t)((py >> 3) * g.TW + (px >> 3)) * kWave + (py & 7) * kTile + (px & 7)
-                                 : (size_t)py * g.W + px;
+    const size_t texel = p.tiled ? (size_t)tile * kWave + lane : (size_t)min(py, g.H - 1) * g.W + min(px, g.W - 1);
     const size_t off = (size_t)light * K * plane + texel;
     const float* bt = p.base_tau ? p.base_tau + off : nullptr;
-    unsigned long long acc = 0;
-    float Tp = 1.f;
-    // groups of kFinishGroup shells: the group's loads are all in flight before
-    // the first use (a shell-by-shell loop would wait one memory latency per shell)
-    for (int k0 = 0; k0 < K; k0 += kFinishGroup) {
-        const int n = min(kFinishGroup, K - k0);
-        unsigned long long iv[kFinishGroup];
+    const int per = (K + NWB - 1) / NWB;
+    const int k_lo = min(K, wave * per), k_hi = min(K, k_lo + per);
+
+    unsigned long long tot = 0;
+    for (int k = k_lo; k < k_hi; ++k) tot += inc[k * kWave + lane];
+    s_tot[wave * kWave + lane] = tot;
+    __syncthreads();
+    unsigned long long acc0 = 0;
+    for (int w = 0; w < wave; ++w) acc0 += s_tot[w * kWave + lane];
+
+    // tau_k for a group of shells starting at k0 (n of them), into tt[]
+    auto group_tau = [&](int k0, int n, unsigned long long& acc, float* tt) {
         float bv[kFinishGroup];
-        load(k0, n, iv);
 #pragma unroll
-        for (int j = 0; j < kFinishGroup; ++j) bv[j] = (bt && j < n) ? bt[(size_t)(k0 + j) * plane] : 0.f;
-        if (p.write_tau) {
-            float* out = reinterpret_cast<float*>(p.out) + off;
+        for (int j = 0; j < kFinishGroup; ++j) bv[j] = (bt && valid && j < n) ? bt[(size_t)(k0 + j) * plane] : 0.f;
 #pragma unroll
-            for (int j = 0; j < kFinishGroup; ++j) {
-                if (j >= n) break;
-                acc += iv[j];
-                out[(size_t)(k0 + j) * plane] = (float)from_fixed(acc) + bv[j];
-            }
-        } else {
-            OutT* out = reinterpret_cast<OutT*>(p.out) + off;
+        for (int j = 0; j < kFinishGroup; ++j) {
+            if (j >= n) break;
+            acc += inc[(k0 + j) * kWave + lane];
+            tt[j] = (float)from_fixed(acc) + bv[j];
+        }
+    };
+
+    if (p.write_tau) {
+        unsigned long long acc = acc0;
+        float* out = reinterpret_cast<float*>(p.out) + off;
+        for (int k0 = k_lo; k0 < k_hi; k0 += kFinishGroup) {
+            const int n = min(kFinishGroup, k_hi - k0);
+            float tt[kFinishGroup];
+            group_tau(k0, n, acc, tt);
 #pragma unroll
-            for (int j = 0; j < kFinishGroup; ++j) {
-                if (j >= n) break;
-                acc += iv[j];
-                const float tt = (float)from_fixed(acc) + bv[j];
-                const float T = fminf(__expf(-tt), Tp);   // exactly non-increasing in k
-                Tp = T;
-                Store<OutT>::put(out + (size_t)(k0 + j) * plane, T);
-            }
+            for (int j = 0; j < kFinishGroup; ++j)
+                if (j < n && valid) out[(size_t)(k0 + j) * plane] = tt[j];
+        }
+        return;
+    }
+    float m = 1.f;
+    {
+        unsigned long long acc = acc0;
+        for (int k0 = k_lo; k0 < k_hi; k0 += kFinishGroup) {
+            const int n = min(kFinishGroup, k_hi - k0);
+            float tt[kFinishGroup];
+            group_tau(k0, n, acc, tt);
+#pragma unroll
+            for (int j = 0; j < kFinishGroup; ++j)
+                if (j < n) m = fminf(m, __expf(-tt[j]));
+        }
+    }
+    s_min[wave * kWave + lane] = m;
+    __syncthreads();
+    float Tp = 1.f;
+    for (int w = 0; w < wave; ++w) Tp = fminf(Tp, s_min[w * kWave + lane]);
+    unsigned long long acc = acc0;
+    OutT* out = reinterpret_cast<OutT*>(p.out) + off;
+    for (int k0 = k_lo; k0 < k_hi; k0 += kFinishGroup) {
+        const int n = min(kFinishGroup, k_hi - k0);
+        float tt[kFinishGroup];
+        group_tau(k0, n, acc, tt);
+#pragma unroll
+        for (int j = 0; j < kFinishGroup; ++j) {
+            if (j >= n) break;
+            const float T = fminf(__expf(-tt[j]), Tp);
+            Tp = T;
+            if (valid) Store<OutT>::put(out + (size_t)(k0 + j) * plane, T);
         }
     }
 }
@@ -810,6 +826,7 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     int tile, wlo, whi, pidx;
     if ((int)blockIdx.x < g.ntiles) {
         tile = blockIdx.x;
+        if (p.skip_empty && W.hits[tile] == 0) return;
         const int4 ti = W.tinfo[tile];
         wlo = 0;
         whi = ti.z;
@@ -887,38 +904,46 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
         return;
     }
 
-    if (wave == 0 && st.valid)
-        finish_texel<OutT>(p, light, py, px, [&](int k0, int n, unsigned long long* iv) {
-#pragma unroll
-            for (int j = 0; j < kFinishGroup; ++j) iv[j] = j < n ? inc[(k0 + j) * kWave + lane] : 0ull;
-        });
+    finish_tile<OutT, NW>(p, light, tile, lane, wave, inc, reinterpret_cast<unsigned long long*>(inc + K * kWave),
+                          reinterpret_cast<float*>(inc + K * kWave + NW * kWave));
 }
 
-// Split tiles: add the slices' partial sums in slice order, then finish as above.
+// Split tiles: the slices' partial sums are added in slice order into LDS
+// (wave w sums shells w, w + 8, ...), then the tile is finished as above.
+constexpr int kFinishWaves = 8;
+
 template <typename OutT>
-__global__ __launch_bounds__(kWave) void split_finish_kernel(TileArgs p) {
+__global__ __launch_bounds__(kWave * kFinishWaves) void split_finish_kernel(TileArgs p) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const Geom& g = p.g;
+    const int K = g.K;
+    unsigned long long* inc = reinterpret_cast<unsigned long long*>(smem);   // [K][64]
     const int light = blockIdx.y;
     const LightWs W = light_ws(p.ws, p.lay, light);
     if ((int)blockIdx.x >= W.nunits[1]) return;
     const int2 sp = W.splits[blockIdx.x];
     const int q = W.tinfo[sp.x].x;
-    const int lane = threadIdx.x;
-    const int ty = sp.x / g.TW, tx = sp.x - ty * g.TW;
-    const int py = ty * kTile + (lane >> 3), px = tx * kTile + (lane & 7);
-    if (py >= g.H || px >= g.W) return;
-    const size_t slice = (size_t)g.K * kWave;
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+    const size_t slice = (size_t)K * kWave;
     const unsigned long long* src = W.part + (size_t)sp.y * slice + lane;
-    finish_texel<OutT>(p, light, py, px, [&](int k0, int n, unsigned long long* iv) {
+    for (int k0 = wave * kFinishGroup; k0 < K; k0 += kFinishWaves * kFinishGroup) {
+        const int n = min(kFinishGroup, K - k0);
+        unsigned long long v[kFinishGroup];
 #pragma unroll
-        for (int j = 0; j < kFinishGroup; ++j) iv[j] = 0ull;
+        for (int j = 0; j < kFinishGroup; ++j) v[j] = 0ull;
         for (int i = 0; i < q; ++i) {
             const unsigned long long* s0 = src + (size_t)i * slice + (size_t)k0 * kWave;
 #pragma unroll
             for (int j = 0; j < kFinishGroup; ++j)
-                if (j < n) iv[j] += s0[(size_t)j * kWave];
+                if (j < n) v[j] += s0[(size_t)j * kWave];
         }
-    });
+#pragma unroll
+        for (int j = 0; j < kFinishGroup; ++j)
+            if (j < n) inc[(k0 + j) * kWave + lane] = v[j];
+    }
+    __syncthreads();
+    finish_tile<OutT, kFinishWaves>(p, light, sp.x, lane, wave, inc, inc + K * kWave,
+                                    reinterpret_cast<float*>(inc + K * kWave + kFinishWaves * kWave));
 }
 
 // ---------------------------------------------------------------------------
@@ -947,7 +972,7 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
     L.counts = take((size_t)g.S * (size_t)L.nb * sizeof(int));
     L.lists = take(L.cap * sizeof(int));
     L.bits = take(L.cap * sizeof(uint64_t));
-    L.units_cap = 4 * g.ntiles < 1024 ? 4 * g.ntiles : 1024;
+    L.units_cap = 4 * g.ntiles < 4096 ? 4 * g.ntiles : 4096;
     L.hits = take((size_t)g.ntiles * sizeof(int));
     L.tinfo = take((size_t)g.ntiles * sizeof(int4));
     L.units = take((size_t)L.units_cap * sizeof(int4));
@@ -959,11 +984,15 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
     return L;
 }
 
-size_t tile_smem_bytes(const Geom& g) { return (size_t)g.K * kWave * sizeof(unsigned long long); }
+// LDS of a tile block: increments [K][64] (u64), then the finish's wave totals
+// [NW][64] (u64) and wave minima [NW][64] (f32).
+size_t tile_smem_bytes(const Geom& g, int nw) {
+    return (size_t)g.K * kWave * sizeof(unsigned long long) + (size_t)nw * kWave * (sizeof(unsigned long long) + 4);
+}
 
 template <typename OutT, bool STATS, int NW>
 static hipError_t launch_tile(const TileArgs& ta, int n_lights, hipStream_t st) {
-    const size_t smem = tile_smem_bytes(ta.g);
+    const size_t smem = tile_smem_bytes(ta.g, NW);
     const bool geo = ta.g.spacing == DGSM_SHELLS_GEOMETRIC;
     const void* fn = geo ? (const void*)tile_build_kernel<OutT, STATS, NW, true>
                          : (const void*)tile_build_kernel<OutT, STATS, NW, false>;
@@ -1024,7 +1053,8 @@ dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, 
 
 dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned char* ws, int n_lights,
                                float pair_eps, void* atlas, const AccumOpts& o, hipStream_t st) {
-    TileArgs ta{g, L, ws, pair_eps, atlas, o.base_tau, o.write_tau ? 1 : 0, o.tiled ? 1 : 0, o.stats};
+    TileArgs ta{g, L, ws, pair_eps, atlas, o.base_tau, o.write_tau ? 1 : 0, o.tiled ? 1 : 0,
+                o.skip_empty ? 1 : 0, o.stats};
     hipError_t e;
     const bool half = g.dtype == DGSM_F16 && !o.write_tau;
     const int nw = o.tile_waves;
@@ -1037,10 +1067,15 @@ dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned cha
         e = half ? launch_tile_nw<__half, false>(ta, n_lights, nw, st) : launch_tile_nw<float, false>(ta, n_lights, nw, st);
     if (e != hipSuccess) return DGSM_EHIP;
     const dim3 fgrid(L.units_cap, n_lights);
+    const size_t fsmem = tile_smem_bytes(g, kFinishWaves);
+    const void* ffn = half ? (const void*)split_finish_kernel<__half> : (const void*)split_finish_kernel<float>;
+    if (fsmem > 64 * 1024 && hipFuncSetAttribute(ffn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fsmem) !=
+                                 hipSuccess)
+        return DGSM_EHIP;
     if (half)
-        split_finish_kernel<__half><<<fgrid, kWave, 0, st>>>(ta);
+        split_finish_kernel<__half><<<fgrid, kWave * kFinishWaves, fsmem, st>>>(ta);
     else
-        split_finish_kernel<float><<<fgrid, kWave, 0, st>>>(ta);
+        split_finish_kernel<float><<<fgrid, kWave * kFinishWaves, fsmem, st>>>(ta);
     return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
 

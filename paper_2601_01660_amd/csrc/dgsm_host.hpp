@@ -52,8 +52,37 @@ struct BuildLayout {
     size_t total;            // bytes for all lights
 };
 
+// Pointers into one light's slice of the workspace.
+struct LightWs {
+    int* totals;       // [kMaxSuper] list length per supertile
+    int* lbase;        // [kMaxSuper + 1] list base per supertile, multiples of 64
+    GRec* rec;         // [n]
+    float4* cone;      // [n]
+    uint64_t* mask;    // [n][kMaskWords] supertile masks
+    int* counts;       // [S][nb] per-block counts, scanned in place
+    int* lists;        // [cap] supertile lists, 64-entry chunks
+    uint64_t* bits;    // [cap] per supertile: [tile][chunk] hit words
+    int* hits;         // [ntiles] set bits over a tile's hit words
+    int4* tinfo;       // [ntiles] {slices, first partial (-1: not split), end word of slice 0, words}
+    int4* units;       // [units_cap] extra slices: {tile, first word, end word, partial}
+    int2* splits;      // [units_cap] split tiles: {tile, first partial}
+    int* nunits;       // [4] {extra slices, split tiles, hits per slice, total hits}
+    unsigned long long* part;   // [2 units_cap][K][64] fixed-point partial optical depths
+};
+
+__host__ __device__ inline LightWs light_ws(unsigned char* ws, const BuildLayout& L, int l) {
+    unsigned char* b = ws + L.light0 + (size_t)l * L.light_stride;
+    return LightWs{reinterpret_cast<int*>(b + L.totals), reinterpret_cast<int*>(b + L.lbase),
+                   reinterpret_cast<GRec*>(b + L.rec), reinterpret_cast<float4*>(b + L.cone),
+                   reinterpret_cast<uint64_t*>(b + L.mask), reinterpret_cast<int*>(b + L.counts),
+                   reinterpret_cast<int*>(b + L.lists), reinterpret_cast<uint64_t*>(b + L.bits),
+                   reinterpret_cast<int*>(b + L.hits), reinterpret_cast<int4*>(b + L.tinfo),
+                   reinterpret_cast<int4*>(b + L.units), reinterpret_cast<int2*>(b + L.splits),
+                   reinterpret_cast<int*>(b + L.nunits), reinterpret_cast<unsigned long long*>(b + L.part)};
+}
+
 BuildLayout build_layout(const Geom& g, int64_t n, int n_lights);
-size_t tile_smem_bytes(const Geom& g);
+size_t tile_smem_bytes(const Geom& g, int nw);
 
 // Tile and supertile cones of the atlas geometry (depend on the atlas only).
 dgsm_status enqueue_cones(const Geom& g, const BuildLayout& L, unsigned char* ws, hipStream_t st);
@@ -71,16 +100,17 @@ struct AccumOpts {
     int tile_waves;              // waves sharing one tile: 2, 4 or 8
     int split_units;             // target work units per launch (all lights); <= 0: never split a tile
     bool tiled = false;          // atlas / base_tau planes in tile-major order (see kTile)
+    bool skip_empty = false;     // leave tiles without hits untouched (their atlas values stay as they are)
 };
 
 // Elements of one shell plane: H*W row-major, or ntiles*64 tile-major (each
 // 8x8 tile's texels contiguous, row-major inside the tile).
-inline size_t plane_elems(const Geom& g, bool tiled) {
+__host__ __device__ inline size_t plane_elems(const Geom& g, bool tiled) {
     return tiled ? (size_t)g.ntiles * kWave : (size_t)g.H * g.W;
 }
 
 constexpr int kDefaultTileWaves = 8;
-constexpr int kDefaultSplitUnits = 2048;
+constexpr int kDefaultSplitUnits = 8192;
 
 // Enqueue the per-tile accumulation of all lights into atlas [L][K][H][W].
 dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned char* ws, int n_lights,

@@ -34,6 +34,39 @@ __global__ __launch_bounds__(256) void translate_kernel(const float* __restrict_
     dst[i] = base[i] + t[i % 3];
 }
 
+// T of the static set alone, T = exp(-tau_static) with the running minimum
+// over shells (the same arithmetic as the tile build's finish of a tile that
+// no dynamic Gaussian reaches), into the atlas and into its baseline copy.
+template <typename OutT>
+__global__ __launch_bounds__(kWave) void static_finish_kernel(Geom g, const float* __restrict__ tau,
+                                                              OutT* __restrict__ atlas, OutT* __restrict__ base) {
+    const int tile = blockIdx.x, light = blockIdx.y, lane = threadIdx.x;
+    const int ty = tile / g.TW, tx = tile - ty * g.TW;
+    if (ty * kTile + (lane >> 3) >= g.H || tx * kTile + (lane & 7) >= g.W) return;
+    const size_t plane = plane_elems(g, true);
+    const size_t off = (size_t)light * g.K * plane + (size_t)tile * kWave + lane;
+    float Tp = 1.f;
+    for (int k = 0; k < g.K; ++k) {
+        const float T = fminf(__expf(-tau[off + (size_t)k * plane]), Tp);
+        Tp = T;
+        Store<OutT>::put(atlas + off + (size_t)k * plane, T);
+        Store<OutT>::put(base + off + (size_t)k * plane, T);
+    }
+}
+
+// After a frame's query: tiles the dynamic set reached get their static-only
+// values back, so that the next frame starts from the baseline again.
+template <typename OutT>
+__global__ __launch_bounds__(kWave) void restore_kernel(Geom g, BuildLayout lay, unsigned char* ws,
+                                                        const OutT* __restrict__ base, OutT* __restrict__ atlas) {
+    const int tile = blockIdx.x, light = blockIdx.y, lane = threadIdx.x;
+    const LightWs W = light_ws(ws, lay, light);
+    if (W.hits[tile] == 0) return;
+    const size_t plane = plane_elems(g, true);
+    const size_t off = (size_t)light * g.K * plane + (size_t)tile * kWave + lane;
+    for (int k = 0; k < g.K; ++k) atlas[off + (size_t)k * plane] = base[off + (size_t)k * plane];
+}
+
 }  // namespace dgsm
 
 using namespace dgsm;
@@ -57,7 +90,8 @@ struct dgsm_plan_s {
     float* rot;           // [ns + nd][4]
     float* opacity;       // [ns + nd]
     float* tau_static;    // [L][K][H][W] (cache mode)
-    void* atlas;          // [L][K][H][W] of desc.dtype
+    void* atlas;          // [L][K][plane] of desc.dtype (tile-major planes)
+    void* atlas_static;   // cache mode: T of the static set alone (the per-frame baseline)
     unsigned char* ws_a;  // workspace for the static (cache) or full (no cache) set
     size_t ws_a_bytes;
     unsigned char* ws_b;  // workspace for the dynamic set (cache mode)
@@ -77,7 +111,8 @@ hipError_t dalloc(T** p, size_t bytes) {
 void plan_free(dgsm_plan p) {
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    void* bufs[] = {p->lights, p->mean, p->scale, p->rot, p->opacity, p->tau_static, p->atlas, p->ws_a, p->ws_b};
+    void* bufs[] = {p->lights, p->mean,  p->scale,        p->rot,  p->opacity,
+                    p->tau_static, p->atlas, p->atlas_static, p->ws_a, p->ws_b};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -94,7 +129,16 @@ dgsm_status enqueue_static(dgsm_plan p, int tile_waves, int split_units, hipStre
     dgsm_status s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, 0, p->ns), st, false);
     if (s != DGSM_OK) return s;
     AccumOpts o{nullptr, true, nullptr, tile_waves, split_units, true};
-    return enqueue_accumulate(p->g, La, p->ws_a, p->L, p->desc.cull_eps, p->tau_static, o, st);
+    s = enqueue_accumulate(p->g, La, p->ws_a, p->L, p->desc.cull_eps, p->tau_static, o, st);
+    if (s != DGSM_OK) return s;
+    const dim3 grid(p->g.ntiles, p->L);
+    if (p->desc.dtype == DGSM_F16)
+        static_finish_kernel<__half><<<grid, kWave, 0, st>>>(p->g, p->tau_static, static_cast<__half*>(p->atlas),
+                                                             static_cast<__half*>(p->atlas_static));
+    else
+        static_finish_kernel<float><<<grid, kWave, 0, st>>>(p->g, p->tau_static, static_cast<float*>(p->atlas),
+                                                            static_cast<float*>(p->atlas_static));
+    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
 
 // One frame: dynamic means, build (on top of the static tau in cache mode), query.
@@ -112,7 +156,8 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, const float* dyn_base, const float
         const BuildLayout Lb = build_layout(p->g, p->nd, p->L);
         s = enqueue_bin(p->g, Lb, p->ws_b, lt, p->desc.cull_eps, set_of(p, p->ns, p->nd), st, false);
         if (s != DGSM_OK) return s;
-        AccumOpts o{p->tau_static, false, nullptr, tile_waves, split_units, true};
+        // only tiles the dynamic set reaches are rebuilt; the rest hold the static baseline
+        AccumOpts o{p->tau_static, false, nullptr, tile_waves, split_units, true, true};
         s = enqueue_accumulate(p->g, Lb, p->ws_b, p->L, p->desc.cull_eps, p->atlas, o, st);
     } else {
         const BuildLayout La = build_layout(p->g, p->np, p->L);
@@ -125,6 +170,17 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, const float* dyn_base, const float
     if (launch_query(p->g, p->lights, p->L, p->atlas, p->mean, p->np, T_out + (size_t)f * p->L * p->np, st,
                      true) != hipSuccess)
         return DGSM_EHIP;
+    if (p->cache) {
+        const BuildLayout Lb = build_layout(p->g, p->nd, p->L);
+        const dim3 grid(p->g.ntiles, p->L);
+        if (p->desc.dtype == DGSM_F16)
+            restore_kernel<__half><<<grid, kWave, 0, st>>>(p->g, Lb, p->ws_b, static_cast<const __half*>(p->atlas_static),
+                                                           static_cast<__half*>(p->atlas));
+        else
+            restore_kernel<float><<<grid, kWave, 0, st>>>(p->g, Lb, p->ws_b, static_cast<const float*>(p->atlas_static),
+                                                          static_cast<float*>(p->atlas));
+        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    }
     return DGSM_OK;
 }
 
@@ -153,7 +209,7 @@ dgsm_status enqueue_run(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* t
 dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* translations, float* T_out,
                      hipStream_t st) {
     const int waves[3] = {2, 4, 8};
-    const int units[4] = {-1, 512, 2048, 8192};
+    const int units[4] = {-1, 2048, 8192, 32768};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DGSM_EHIP;
     dgsm_status s = DGSM_OK;
@@ -227,6 +283,7 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
               dalloc(&p->opacity, 4 * (size_t)np) == hipSuccess && dalloc(&p->atlas, table * elem) == hipSuccess &&
               dalloc(&p->ws_a, p->ws_a_bytes) == hipSuccess &&
               (!p->cache || (dalloc(&p->tau_static, table * 4) == hipSuccess &&
+                             dalloc(&p->atlas_static, table * elem) == hipSuccess &&
                              dalloc(&p->ws_b, p->ws_b_bytes) == hipSuccess));
     const int64_t n = p->ns;
     ok = ok && hipMemcpy(p->lights, lights->pos, 12 * (size_t)p->L, hipMemcpyDeviceToDevice) == hipSuccess;
