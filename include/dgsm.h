@@ -220,14 +220,14 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  *   autotune      1: the first run times the two knobs of the tile
  *                 accumulation on frame 0 of the real workload and keeps the
  *                 fastest pair: waves per tile (2, 4, 8) and work units per
- *                 launch (never, 2048, 8192, 32768); in cache mode they apply
+ *                 launch (never, 8192, 32768, 131072); in cache mode they apply
  *                 to the per-frame dynamic accumulation, the once-per-run
- *                 static build keeps the defaults (8 waves, 8192 units)
+ *                 static build keeps the defaults (8 waves, 32768 units)
  *   tile_waves    waves sharing one 8x8 tile when autotune = 0 (2, 4 or 8; else 8)
  *   split_units   target number of work units per accumulation when
  *                 autotune = 0: a tile with more hits than (total hits /
  *                 split_units) is cut into slices run by separate blocks
- *                 (results are bitwise the same); 0 = default (8192),
+ *                 (results are bitwise the same); 0 = default (32768),
  *                 negative = never split
  *
  * dgsm_plan_create allocates all device memory the plan needs (the only

@@ -126,6 +126,7 @@ struct PrepArgs {
 
 __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
     __shared__ int wcnt[kPrepThreads / kWave][kMaxSuper];
+    __shared__ float4 sc[kMaxSuper];     // supertile cones
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     const int l = blockIdx.y;
     const LightWs W = light_ws(a.ws, a.lay, l);
@@ -197,12 +198,19 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
         }
         W.cone[i] = cone;
     }
+    for (int s = tid; s < a.S; s += kPrepThreads) sc[s] = scone[s];
+    __syncthreads();
     uint64_t m[kMaskWords] = {0, 0, 0, 0};
-    for (int s = 0; s < a.S; ++s) {
-        const bool b = in && cones_touch(cone, scone[s]);
-        m[s >> 6] |= (uint64_t)b << (s & 63);
-        const uint64_t bal = __ballot(b);
-        if (lane == 0) wcnt[w][s] = __popcll(bal);
+#pragma unroll
+    for (int q = 0; q < kMaskWords; ++q) {
+        uint64_t mq = 0;
+        for (int s = 64 * q; s < min(a.S, 64 * q + 64); ++s) {
+            const bool b = in && cones_touch(cone, sc[s]);
+            mq |= (uint64_t)b << (s & 63);
+            const uint64_t bal = __ballot(b);
+            if (lane == 0) wcnt[w][s] = __popcll(bal);
+        }
+        m[q] = mq;
     }
     if (in)
         for (int q = 0; q < kMaskWords; ++q) W.mask[(size_t)i * kMaskWords + q] = m[q];
@@ -320,6 +328,7 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
     const int cbeg = min(nchunks, gw * per), cend = min(nchunks, cbeg + per);
     int s_cur = -1, cnt = 0;
     SuperSpan sp_cur{0, 0, 0, 0};
+    float4 tc = make_float4(0.f, 0.f, 1.f, -1.f);   // lane t: cone of tile t of the current supertile
     for (int c = cbeg; c < cend; ++c) {
         // supertile of this chunk: the last s with sbase[s] <= 64 c
         int lo = 0, hi = g.S - 1;
@@ -334,6 +343,9 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
             s_cur = s;
             cnt = 0;
             sp_cur = super_span(g, s);
+            tc = lane < sp_cur.nty * sp_cur.ntx
+                     ? tcone[(sp_cur.ty0 + lane / sp_cur.ntx) * g.TW + sp_cur.tx0 + lane % sp_cur.ntx]
+                     : make_float4(0.f, 0.f, 1.f, -1.f);
         }
         const int e = 64 * c + lane;
         float4 cone = make_float4(0.f, 0.f, 1.f, -1.f);
@@ -342,8 +354,11 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
         const int nt = sp.nty * sp.ntx;
         uint64_t mine = 0;
         for (int t = 0; t < nt; ++t) {
-            const int ty = sp.ty0 + t / sp.ntx, tx = sp.tx0 + t % sp.ntx;
-            const uint64_t bal = __ballot(cones_touch(cone, tcone[ty * g.TW + tx]));
+            const float4 b = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.x), t)),
+                                         __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.y), t)),
+                                         __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.z), t)),
+                                         __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.w), t)));
+            const uint64_t bal = __ballot(cones_touch(cone, b));
             if (lane == t) mine = bal;
         }
         const int c0 = sbase[s] / 64, ns = (sbase[s + 1] - sbase[s]) / 64;
@@ -367,7 +382,7 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
 // ---------------------------------------------------------------------------
 
 constexpr int kMaxSlices = 64;         // slices of one tile
-constexpr int kMinSliceHits = 2048;    // below this a slice is not worth its partial buffer
+constexpr int kMinSliceHits = 1024;    // below this a slice is not worth its partial buffer
 constexpr int kPlanThreads = 1024;
 
 // per = hits per slice; per <= 0: never split
@@ -972,7 +987,7 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
     L.counts = take((size_t)g.S * (size_t)L.nb * sizeof(int));
     L.lists = take(L.cap * sizeof(int));
     L.bits = take(L.cap * sizeof(uint64_t));
-    L.units_cap = 4 * g.ntiles < 4096 ? 4 * g.ntiles : 4096;
+    L.units_cap = 4 * g.ntiles < 8192 ? 4 * g.ntiles : 8192;
     L.hits = take((size_t)g.ntiles * sizeof(int));
     L.tinfo = take((size_t)g.ntiles * sizeof(int4));
     L.units = take((size_t)L.units_cap * sizeof(int4));

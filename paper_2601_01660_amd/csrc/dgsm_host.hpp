@@ -110,7 +110,7 @@ __host__ __device__ inline size_t plane_elems(const Geom& g, bool tiled) {
 }
 
 constexpr int kDefaultTileWaves = 8;
-constexpr int kDefaultSplitUnits = 8192;
+constexpr int kDefaultSplitUnits = 32768;
 
 // Enqueue the per-tile accumulation of all lights into atlas [L][K][H][W].
 dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned char* ws, int n_lights,

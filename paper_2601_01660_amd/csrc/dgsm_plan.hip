@@ -209,7 +209,7 @@ dgsm_status enqueue_run(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* t
 dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* translations, float* T_out,
                      hipStream_t st) {
     const int waves[3] = {2, 4, 8};
-    const int units[4] = {-1, 2048, 8192, 32768};
+    const int units[4] = {-1, 8192, 32768, 131072};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DGSM_EHIP;
     dgsm_status s = DGSM_OK;
