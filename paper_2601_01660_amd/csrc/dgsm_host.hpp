@@ -116,6 +116,7 @@ constexpr int kDefaultSplitUnits = 32768;
 dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned char* ws, int n_lights,
                                float pair_eps, void* atlas, const AccumOpts& o, hipStream_t st);
 hipError_t launch_query(const Geom& g, const float* lights, int L, const void* atlas, const float* points,
-                        int64_t P, float* T, hipStream_t st, bool tiled = false);
+                        int64_t P, float* T, hipStream_t st, bool tiled = false,
+                        const int* out_index = nullptr);
 
 }  // namespace dgsm

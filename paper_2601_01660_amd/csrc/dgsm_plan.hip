@@ -67,6 +67,111 @@ __global__ __launch_bounds__(kWave) void restore_kernel(Geom g, BuildLayout lay,
     for (int k = 0; k < g.K; ++k) atlas[off + (size_t)k * plane] = base[off + (size_t)k * plane];
 }
 
+// ---------------------------------------------------------------------------
+// Spatial order of the static set (once, at plan creation).  Gaussians that
+// are close in space are close in every light's supertile lists, so a tile's
+// hits gather into few hit words and its records share cache lines, and
+// queries of neighbouring points read neighbouring texels.  Keys: 30-bit
+// Morton code of the mean in the set's bounding box, then the index (unique,
+// so the order is deterministic); bitonic sort over the next power of two.
+// The atlas does not depend on the order (the per-shell sums are integers).
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void bbox_partial_kernel(const float* __restrict__ mean, int64_t n,
+                                                           float* __restrict__ part) {
+    __shared__ float red[6][256];
+    const int tid = threadIdx.x;
+    float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fminf(lo[c], mean[3 * i + c]);
+            hi[c] = fmaxf(hi[c], mean[3 * i + c]);
+        }
+    for (int c = 0; c < 3; ++c) {
+        red[c][tid] = lo[c];
+        red[3 + c][tid] = hi[c];
+    }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int c = 0; c < 3; ++c) {
+                red[c][tid] = fminf(red[c][tid], red[c][tid + h]);
+                red[3 + c][tid] = fmaxf(red[3 + c][tid], red[3 + c][tid + h]);
+            }
+        __syncthreads();
+    }
+    if (tid < 6) part[blockIdx.x * 6 + tid] = red[tid][0];
+}
+
+__device__ inline uint32_t spread_bits10(uint32_t v) {      // 10 bits -> every third bit
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ __launch_bounds__(256) void morton_kernel(const float* __restrict__ mean, int64_t n,
+                                                     const float* __restrict__ part, int nparts,
+                                                     uint64_t* __restrict__ keys, int64_t npad) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= npad) return;
+    if (i >= n) {
+        keys[i] = ~0ull;
+        return;
+    }
+    uint32_t code = 0;
+    for (int c = 0; c < 3; ++c) {
+        float lo = 3e38f, hi = -3e38f;
+        for (int b = 0; b < nparts; ++b) {
+            lo = fminf(lo, part[6 * b + c]);
+            hi = fmaxf(hi, part[6 * b + 3 + c]);
+        }
+        const float ext = hi - lo;
+        const float f = ext > 0.f ? (mean[3 * i + c] - lo) / ext : 0.f;
+        const uint32_t q = (uint32_t)fminf(fmaxf(f * 1024.f, 0.f), 1023.f);
+        code |= spread_bits10(q) << c;
+    }
+    keys[i] = ((uint64_t)code << 32) | (uint64_t)i;
+}
+
+__global__ __launch_bounds__(256) void bitonic_kernel(uint64_t* __restrict__ keys, int64_t npad, int64_t j,
+                                                      int64_t k) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= npad) return;
+    const int64_t l = i ^ j;
+    if (l <= i) return;
+    const uint64_t a = keys[i], b = keys[l];
+    const bool up = (i & k) == 0;
+    if ((a > b) == up) {
+        keys[i] = b;
+        keys[l] = a;
+    }
+}
+
+// Sorted static set into the plan's arrays; out_index maps sorted position to
+// the caller's index (the query writes each result to the caller's column).
+__global__ __launch_bounds__(256) void gather_static_kernel(dgsm_gaussians_t src, const uint64_t* __restrict__ keys,
+                                                            float* mean, float* scale, float* rot, float* opacity,
+                                                            int* out_index) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= src.n) return;
+    const int64_t s = (int64_t)(keys[p] & 0xffffffffull);
+    for (int c = 0; c < 3; ++c) {
+        mean[3 * p + c] = src.mean[3 * s + c];
+        scale[3 * p + c] = src.scale[3 * s + c];
+    }
+    for (int c = 0; c < 4; ++c) rot[4 * p + c] = src.rot[4 * s + c];
+    opacity[p] = src.opacity[s];
+    out_index[p] = (int)s;
+}
+
+__global__ __launch_bounds__(256) void iota_kernel(int* __restrict__ v, int64_t from, int64_t to) {
+    const int64_t i = from + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < to) v[i] = (int)i;
+}
+
 }  // namespace dgsm
 
 using namespace dgsm;
@@ -89,6 +194,7 @@ struct dgsm_plan_s {
     float* scale;         // [ns + nd][3]
     float* rot;           // [ns + nd][4]
     float* opacity;       // [ns + nd]
+    int* out_index;       // [ns + nd] caller column of each plan point (static part in spatial order)
     float* tau_static;    // [L][K][H][W] (cache mode)
     void* atlas;          // [L][K][plane] of desc.dtype (tile-major planes)
     void* atlas_static;   // cache mode: T of the static set alone (the per-frame baseline)
@@ -111,7 +217,7 @@ hipError_t dalloc(T** p, size_t bytes) {
 void plan_free(dgsm_plan p) {
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    void* bufs[] = {p->lights, p->mean,  p->scale,        p->rot,  p->opacity,
+    void* bufs[] = {p->lights,     p->mean,  p->scale,        p->rot,  p->opacity, p->out_index,
                     p->tau_static, p->atlas, p->atlas_static, p->ws_a, p->ws_b};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -168,7 +274,7 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, const float* dyn_base, const float
     }
     if (s != DGSM_OK) return s;
     if (launch_query(p->g, p->lights, p->L, p->atlas, p->mean, p->np, T_out + (size_t)f * p->L * p->np, st,
-                     true) != hipSuccess)
+                     true, p->out_index) != hipSuccess)
         return DGSM_EHIP;
     if (p->cache) {
         const BuildLayout Lb = build_layout(p->g, p->nd, p->L);
@@ -245,6 +351,31 @@ dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* tran
     return s;
 }
 
+// Static set into the plan in spatial order (see bitonic_kernel); synchronous.
+dgsm_status sort_static(dgsm_plan p, const dgsm_gaussians_t& src) {
+    const int64_t n = src.n;
+    int64_t npad = 1;
+    while (npad < n) npad <<= 1;
+    const int nparts = 256;
+    float* part = nullptr;
+    uint64_t* keys = nullptr;
+    bool ok = dalloc(&part, sizeof(float) * 6 * nparts) == hipSuccess &&
+              dalloc(&keys, sizeof(uint64_t) * (size_t)npad) == hipSuccess;
+    if (ok) {
+        bbox_partial_kernel<<<nparts, 256>>>(src.mean, n, part);
+        morton_kernel<<<(unsigned)((npad + 255) / 256), 256>>>(src.mean, n, part, nparts, keys, npad);
+        for (int64_t k = 2; k <= npad; k <<= 1)
+            for (int64_t j = k >> 1; j > 0; j >>= 1)
+                bitonic_kernel<<<(unsigned)((npad + 255) / 256), 256>>>(keys, npad, j, k);
+        gather_static_kernel<<<(unsigned)((n + 255) / 256), 256>>>(src, keys, p->mean, p->scale, p->rot, p->opacity,
+                                                                    p->out_index);
+        ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    }
+    if (part) (void)hipFree(part);
+    if (keys) (void)hipFree(keys);
+    return ok ? DGSM_OK : DGSM_EHIP;
+}
+
 }  // namespace
 
 extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc,
@@ -280,7 +411,8 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     p->ws_b_bytes = p->cache ? build_layout(g, p->nd, p->L).total : 0;
     bool ok = dalloc(&p->lights, 12 * (size_t)p->L) == hipSuccess && dalloc(&p->mean, 12 * (size_t)np) == hipSuccess &&
               dalloc(&p->scale, 12 * (size_t)np) == hipSuccess && dalloc(&p->rot, 16 * (size_t)np) == hipSuccess &&
-              dalloc(&p->opacity, 4 * (size_t)np) == hipSuccess && dalloc(&p->atlas, table * elem) == hipSuccess &&
+              dalloc(&p->opacity, 4 * (size_t)np) == hipSuccess && dalloc(&p->out_index, 4 * (size_t)np) == hipSuccess &&
+              dalloc(&p->atlas, table * elem) == hipSuccess &&
               dalloc(&p->ws_a, p->ws_a_bytes) == hipSuccess &&
               (!p->cache || (dalloc(&p->tau_static, table * 4) == hipSuccess &&
                              dalloc(&p->atlas_static, table * elem) == hipSuccess &&
@@ -291,11 +423,11 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     ok = ok && enqueue_cones(g, build_layout(g, p->cache ? p->ns : np, p->L), p->ws_a, nullptr) == DGSM_OK;
     ok = ok && (!p->cache || enqueue_cones(g, build_layout(g, p->nd, p->L), p->ws_b, nullptr) == DGSM_OK);
     ok = ok && hipDeviceSynchronize() == hipSuccess;
-    if (ok && n > 0)
-        ok = hipMemcpy(p->mean, static_set->mean, 12 * n, hipMemcpyDeviceToDevice) == hipSuccess &&
-             hipMemcpy(p->scale, static_set->scale, 12 * n, hipMemcpyDeviceToDevice) == hipSuccess &&
-             hipMemcpy(p->rot, static_set->rot, 16 * n, hipMemcpyDeviceToDevice) == hipSuccess &&
-             hipMemcpy(p->opacity, static_set->opacity, 4 * n, hipMemcpyDeviceToDevice) == hipSuccess;
+    if (ok && n > 0) ok = sort_static(p, *static_set) == DGSM_OK;
+    if (ok && p->nd > 0) {
+        iota_kernel<<<(unsigned)((p->nd + 255) / 256), 256>>>(p->out_index, p->ns, p->np);
+        ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    }
     if (!ok) {
         plan_free(p);
         return DGSM_EHIP;

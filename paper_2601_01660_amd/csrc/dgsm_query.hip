@@ -30,6 +30,7 @@ struct QueryArgs {
     float* T;              // [L][P]
     float lr0, kscale;     // shell coordinate: geometric (log2 r - lr0) * kscale, uniform r * kscale - 1/2
     int tiled;             // plane order of the atlas (see wrap_offset)
+    const int* out_index;  // optional [P]: point p's result goes to column out_index[p]
 };
 
 template <typename InT>
@@ -77,14 +78,14 @@ __global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
         const float b1 = (1.f - fj) * Store<InT>::get(s1 + o10) + fj * Store<InT>::get(s1 + o11);
         const float t0 = (1.f - fi) * a0 + fi * b0;
         const float t1 = (1.f - fi) * a1 + fi * b1;
-        a.T[(size_t)l * a.P + p] = (1.f - fk) * t0 + fk * t1;
+        a.T[(size_t)l * a.P + (a.out_index ? (int64_t)a.out_index[p] : p)] = (1.f - fk) * t0 + fk * t1;
     }
 }
 
 hipError_t launch_query(const Geom& g, const float* lights, int L, const void* atlas, const float* points,
-                        int64_t P, float* T, hipStream_t st, bool tiled) {
+                        int64_t P, float* T, hipStream_t st, bool tiled, const int* out_index) {
     if (P == 0) return hipSuccess;
-    QueryArgs a{g, lights, L, atlas, points, P, T, 0.f, 0.f, tiled ? 1 : 0};
+    QueryArgs a{g, lights, L, atlas, points, P, T, 0.f, 0.f, tiled ? 1 : 0, out_index};
     if (g.spacing == DGSM_SHELLS_GEOMETRIC) {
         a.lr0 = log2f(g.r0);
         a.kscale = (float)(g.K - 1) / log2f(g.r1 / g.r0);
