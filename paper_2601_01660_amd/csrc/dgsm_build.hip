@@ -375,10 +375,12 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
 // Work units.  A tile whose hit count is far above the launch's mean would
 // keep a few blocks busy long after the rest of the chip has drained (an
 // animated avatar covers a few dozen tiles with tens of thousands of hits
-// each).  Such a tile is cut into slices of its hit words; each slice runs in
-// its own block and leaves its fixed-point per-shell sums in a partial buffer,
-// which split_finish_kernel adds in slice order.  The sums are integers, so
-// the atlas is bitwise the same as with unsplit tiles.
+// each).  Such a tile is cut into q slices, slice i taking every q-th of its
+// hit words (interleaved, so that the slices stay even however the hits
+// cluster in the list); each slice runs in its own block and leaves its
+// fixed-point per-shell sums in a partial buffer, which split_finish_kernel
+// adds in slice order.  The sums are integers, so the atlas is bitwise the
+// same as with unsplit tiles.
 // ---------------------------------------------------------------------------
 
 constexpr int kMaxSlices = 64;         // slices of one tile
@@ -461,13 +463,11 @@ __global__ __launch_bounds__(kPlanThreads) void split_plan_kernel(unsigned char*
         const int q = slices_of(W.hits[t], per);
         const int s = (t / g.TW / g.STH) * g.SGW + (t % g.TW) / g.STW;
         const int ns = (W.lbase[s + 1] - W.lbase[s]) / 64;
-        int4 info = make_int4(1, -1, ns, ns);
+        int4 info = make_int4(1, -1, ns, 0);
         if (q > 1) {
             const int pbase = sbase + xbase;        // partials of earlier split tiles: one per slice
-            info = make_int4(q, pbase, (int)((long long)ns / q), ns);
-            for (int i = 1; i < q; ++i)
-                W.units[xbase + i - 1] = make_int4(t, (int)((long long)i * ns / q),
-                                                   (int)((long long)(i + 1) * ns / q), pbase + i);
+            info = make_int4(q, pbase, ns, 0);
+            for (int i = 1; i < q; ++i) W.units[xbase + i - 1] = make_int4(t, i, q, pbase + i);
             W.splits[sbase] = make_int2(t, pbase);
             xbase += q - 1;
             sbase += 1;
@@ -689,21 +689,25 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
 // id of that supertile-list entry, its record (prefetched one pair ahead into
 // the other of two scalar register sets) and the pair evaluation.
 template <bool STATS, bool GEO>
-__device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* words, int w0, int w1,
+// The words a wave walks are every S-th word of the tile starting at o (word
+// m covers chunk m of the supertile list): interleaving keeps the waves and
+// slices of a tile balanced however its hits cluster in the list.
+__device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* words, int ns, int o, int S,
                                                                 const int* list, ConstF4Ptr rec,
                                                                 const TexelState& st, Counters& n) {
     const int lane = st.lane;
-    for (int gbase = w0; gbase < w1; gbase += 64) {
-        const uint64_t wv = gbase + lane < w1 ? words[gbase + lane] : 0ull;
+    const int nw = o < ns ? (ns - 1 - o) / S + 1 : 0;   // words of this wave
+    for (int mbase = 0; mbase < nw; mbase += 64) {
+        const uint64_t wv = mbase + lane < nw ? words[(size_t)(mbase + lane) * S + o] : 0ull;
         uint64_t nz = __ballot(wv != 0ull);
         if (nz == 0ull) continue;
-        int gv = list[64 * (gbase + __builtin_ctzll(nz)) + lane];
+        int gv = list[64 * ((mbase + __builtin_ctzll(nz)) * S + o) + lane];
         while (nz) {
             const int j = __builtin_ctzll(nz);
             nz &= nz - 1;
             uint64_t word = readlane_u64(wv, j);
             const int gcur = gv;
-            if (nz) gv = list[64 * (gbase + __builtin_ctzll(nz)) + lane];   // next chunk's ids, in flight
+            if (nz) gv = list[64 * ((mbase + __builtin_ctzll(nz)) * S + o) + lane];   // next chunk's ids, in flight
             if (STATS) n.hits += __popcll(word);
             int b = __builtin_ctzll(word);
             word &= word - 1;
@@ -838,21 +842,21 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     const LightWs W = light_ws(p.ws, p.lay, light);
     // Blocks [0, ntiles) take slice 0 of their tile; the rest take the extra
     // slices of split tiles (block-uniform, so the early return is safe).
-    int tile, wlo, whi, pidx;
+    int tile, slice, nslice, pidx;
     if ((int)blockIdx.x < g.ntiles) {
         tile = blockIdx.x;
         if (p.skip_empty && W.hits[tile] == 0) return;
         const int4 ti = W.tinfo[tile];
-        wlo = 0;
-        whi = ti.z;
+        slice = 0;
+        nslice = ti.x;
         pidx = ti.x > 1 ? ti.y : -1;
     } else {
         const int e = (int)blockIdx.x - g.ntiles;
         if (e >= W.nunits[0]) return;
         const int4 u = W.units[e];
         tile = u.x;
-        wlo = u.y;
-        whi = u.z;
+        slice = u.y;
+        nslice = u.z;
         pidx = u.w;
     }
     const int ty = tile / g.TW, tx = tile - ty * g.TW;
@@ -883,7 +887,7 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     for (int q = tid; q < K * kWave; q += kWave * NW) inc[q] = 0ull;
 
     // this tile's hit words: contiguous ns words, one per 64-entry chunk of the
-    // supertile list; wave w walks the w-th quarter of them
+    // supertile list; wave w of slice i walks words i NW + w, + nslice NW, ...
     const int s = (ty / g.STH) * g.SGW + (tx / g.STW);
     const SuperSpan sp = super_span(g, s);
     const int t_local = (ty - sp.ty0) * sp.ntx + (tx - sp.tx0);
@@ -892,12 +896,10 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     const uint64_t* words = W.bits + 64 * (size_t)c0 + (size_t)t_local * ns;
     const int* list = W.lists + lb0;
     const ConstF4Ptr rec = (ConstF4Ptr)(const void*)W.rec;
-    const int per = (whi - wlo + NW - 1) / NW;
-    const int w0 = min(whi, wlo + wave * per), w1 = min(whi, w0 + per);
     Counters n;
     __syncthreads();
 
-    walk_hits<STATS, GEO>(words, w0, w1, list, rec, st, n);
+    walk_hits<STATS, GEO>(words, ns, slice * NW + wave, nslice * NW, list, rec, st, n);
 
     if (STATS) {
         const unsigned long long nvalid = __popcll(__ballot(st.valid));

@@ -63,8 +63,8 @@ struct LightWs {
     int* lists;        // [cap] supertile lists, 64-entry chunks
     uint64_t* bits;    // [cap] per supertile: [tile][chunk] hit words
     int* hits;         // [ntiles] set bits over a tile's hit words
-    int4* tinfo;       // [ntiles] {slices, first partial (-1: not split), end word of slice 0, words}
-    int4* units;       // [units_cap] extra slices: {tile, first word, end word, partial}
+    int4* tinfo;       // [ntiles] {slices, first partial (-1: not split), words, 0}
+    int4* units;       // [units_cap] extra slices: {tile, slice index, slices, partial}
     int2* splits;      // [units_cap] split tiles: {tile, first partial}
     int* nunits;       // [4] {extra slices, split tiles, hits per slice, total hits}
     unsigned long long* part;   // [2 units_cap][K][64] fixed-point partial optical depths
