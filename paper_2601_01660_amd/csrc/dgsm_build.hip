@@ -566,21 +566,13 @@ struct TexelState {
     bool valid;
     int lane;
     float lr0, kinv;         // shell coordinate of a radius: (log2 t - lr0) * kinv (geometric)
-    double shd0, shd1, shd2, shd3;   // lane l holds t_l, t_{l+64}, t_{l+128}, t_{l+192}
     double ratio;            // t_{k+1} / t_k (geometric) or t_{k+1} - t_k (uniform)
     int K;
     bool geometric;
     float pair_eps;
     unsigned long long* inc; // LDS [K][64], fixed point
+    const double* shells;    // LDS [K] shell radii t_k (FP64)
 };
-
-__device__ inline double shell_at(const TexelState& ts, int k) {
-    const int l = k & 63;
-    if (k < 64) return readlane_d(ts.shd0, l);       // k is wave-uniform: scalar branches
-    if (k < 128) return readlane_d(ts.shd1, l);
-    if (k < 192) return readlane_d(ts.shd2, l);
-    return readlane_d(ts.shd3, l);
-}
 
 // Shell index of a radius (fractional, unclamped); -1 for t <= 0.
 template <bool GEO>
@@ -656,31 +648,37 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     const float xs = -sa * ts;                              // erf argument at t = 0
     float Ep = -1.f;
     if (xs > -z) Ep = erf_nr(xs);
-    int ka = s.K, kb = -1;
+    // Each lane walks its own ramp shells [ka, ka + len): the first shell past
+    // the ramp start carries everything from t = 0 up to it, the last one (at
+    // or past the ramp end) everything up to the saturated tail.
+    int ka = 0, len = 0;
     if (act) {
         const float half = z * __builtin_amdgcn_rcpf(sa);
         const float klo = fminf(shell_index<GEO>(ts - half, s), (float)s.K);
         const float khi = fmaxf(shell_index<GEO>(ts + half, s), -1.f);
-        // first shell past the ramp start, last shell at or past its end
-        ka = klo < 0.f ? 0 : (int)klo + 1;
-        kb = khi > (float)(s.K - 2) ? s.K - 1 : max(0, (int)khi + 1);
+        ka = klo < 0.f ? 0 : min((int)klo + 1, s.K - 1);
+        const int kb = khi > (float)(s.K - 2) ? s.K - 1 : max(0, (int)khi + 1);
+        len = max(0, kb - ka + 1);
     }
-    const int kmin = wave_min(ka), kmax = wave_max(kb);
-    if (kmin > kmax) return;
+    const int maxlen = wave_max(len);
+    if (maxlen <= 0) return;
     if (STATS) {
-        n.ramp += (unsigned long long)__popcll(abal) * (kmax - kmin + 1);
-        n.ramp_wave += (unsigned long long)(kmax - kmin + 1);
+        int sum = len;
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, kWave);
+        n.ramp += (unsigned long long)sum;
+        n.ramp_wave += (unsigned long long)maxlen;
     }
-    double tk = shell_at(s, kmin);
-    for (int k = kmin; k <= kmax; ++k) {
+    double tk = s.shells[ka];
+    unsigned long long* dst = s.inc + ka * kWave + s.lane;
+    for (int j = 0; j < maxlen; ++j) {
         const float x = sa * ((float)(tk - te) + corr);
         const float Ek = erf_nr(x);
         const float E = Ek > Ep ? Ek : Ep;           // keep the increments non-negative
         const float dI = P0 * (E - Ep);
         Ep = E;
-        if (act && dI > 0.f)
-            __hip_atomic_fetch_add(s.inc + k * kWave + s.lane, to_fixed(dI), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (j < len && dI > 0.f)
+            __hip_atomic_fetch_add(dst, to_fixed(dI), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        dst += kWave;
         tk = GEO ? tk * s.ratio : tk + s.ratio;
     }
 }
@@ -871,10 +869,9 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     st.geometric = g.spacing == DGSM_SHELLS_GEOMETRIC;
     st.pair_eps = p.pair_eps;
     st.inc = inc;
-    st.shd0 = lane < K ? shell_radius(lane, K, g.spacing, g.r0, g.r1) : 0.0;
-    st.shd1 = lane + 64 < K ? shell_radius(lane + 64, K, g.spacing, g.r0, g.r1) : 0.0;
-    st.shd2 = lane + 128 < K ? shell_radius(lane + 128, K, g.spacing, g.r0, g.r1) : 0.0;
-    st.shd3 = lane + 192 < K ? shell_radius(lane + 192, K, g.spacing, g.r0, g.r1) : 0.0;
+    double* shells = reinterpret_cast<double*>(inc + K * kWave + NW * kWave) + (NW * kWave) / 2;   // after s_min
+    for (int k = tid; k < K; k += kWave * NW) shells[k] = shell_radius(k, K, g.spacing, g.r0, g.r1);
+    st.shells = shells;
     if (st.geometric) {
         st.lr0 = __builtin_amdgcn_logf(g.r0);
         st.kinv = (float)(K - 1) / __builtin_amdgcn_logf(g.r1 / g.r0);
@@ -1002,9 +999,10 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
 }
 
 // LDS of a tile block: increments [K][64] (u64), then the finish's wave totals
-// [NW][64] (u64) and wave minima [NW][64] (f32).
+// [NW][64] (u64) and wave minima [NW][64] (f32), then the shell radii [K] (FP64).
 size_t tile_smem_bytes(const Geom& g, int nw) {
-    return (size_t)g.K * kWave * sizeof(unsigned long long) + (size_t)nw * kWave * (sizeof(unsigned long long) + 4);
+    return (size_t)g.K * kWave * sizeof(unsigned long long) + (size_t)nw * kWave * (sizeof(unsigned long long) + 4) +
+           (size_t)g.K * sizeof(double);
 }
 
 template <typename OutT, bool STATS, int NW>

@@ -1,6 +1,5 @@
 // DGSM sampling on gfx950 (Sec. 3.3): trilinear lookup of the octahedral x
-// radial atlas at world points, one thread per point, all lights per thread
-// (the point is read once; each light adds 8 texel gathers and one store).
+// radial atlas at world points, one thread per (point, light).
 
 #include "dgsm_device.hpp"
 #include "dgsm_host.hpp"
@@ -33,53 +32,55 @@ struct QueryArgs {
     const int* out_index;  // optional [P]: point p's result goes to column out_index[p]
 };
 
+// One thread per (point, light): blockIdx.y is the light, so the threads of a
+// wave read 64 consecutive points and write 64 consecutive T values, and each
+// thread has its 8 texel gathers in flight at once.
 template <typename InT>
 __global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= a.P) return;
+    const int l = blockIdx.y;
     const Geom& g = a.g;
-    const float x = a.points[3 * p], y = a.points[3 * p + 1], z = a.points[3 * p + 2];
     const bool tiled = a.tiled != 0;
     const size_t plane = tiled ? (size_t)g.ntiles * kWave : (size_t)g.H * g.W;
     const InT* atlas = reinterpret_cast<const InT*>(a.atlas);
-    for (int l = 0; l < a.L; ++l) {
-        const float dx = x - a.lights[3 * l], dy = y - a.lights[3 * l + 1], dz = z - a.lights[3 * l + 2];
-        const float l1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
-        float qx = 0.f, qy = 0.f, qz = 1.f;
-        if (l1 > 0.f) {
-            const float il = 1.f / l1;
-            qx = dx * il; qy = dy * il; qz = dz * il;
-        }
-        float u = qx, v = qy;
-        if (qz < 0.f) {
-            u = copysignf(1.f - fabsf(qy), qx >= 0.f ? 1.f : -1.f);
-            v = copysignf(1.f - fabsf(qx), qy >= 0.f ? 1.f : -1.f);
-        }
-        // clamped (NaN-safe) so that every gathered texel index stays in the atlas
-        const float jf = fminf(fmaxf((u + 1.f) * (0.5f * (float)g.W) - 0.5f, -0.5f), (float)g.W - 0.5f);
-        const float fi_ = fminf(fmaxf((v + 1.f) * (0.5f * (float)g.H) - 0.5f, -0.5f), (float)g.H - 0.5f);
-        const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-        float kf = g.spacing == DGSM_SHELLS_GEOMETRIC ? (__log2f(r) - a.lr0) * a.kscale : r * a.kscale - 0.5f;
-        kf = fminf(fmaxf(kf, 0.f), (float)(g.K - 1));   // log2(0) = -inf clamps to shell 0
-        const float j0f = floorf(jf), i0f = floorf(fi_);
-        const int j0 = (int)j0f, i0 = (int)i0f;
-        const float fj = jf - j0f, fi = fi_ - i0f;
-        const int k0 = min((int)kf, g.K - 2);
-        const float fk = kf - (float)k0;
-        const int o00 = wrap_offset(i0, j0, g.H, g.W, g.TW, tiled);
-        const int o01 = wrap_offset(i0, j0 + 1, g.H, g.W, g.TW, tiled);
-        const int o10 = wrap_offset(i0 + 1, j0, g.H, g.W, g.TW, tiled);
-        const int o11 = wrap_offset(i0 + 1, j0 + 1, g.H, g.W, g.TW, tiled);
-        const InT* s0 = atlas + ((size_t)l * g.K + k0) * plane;
-        const InT* s1 = s0 + plane;
-        const float a0 = (1.f - fj) * Store<InT>::get(s0 + o00) + fj * Store<InT>::get(s0 + o01);
-        const float b0 = (1.f - fj) * Store<InT>::get(s0 + o10) + fj * Store<InT>::get(s0 + o11);
-        const float a1 = (1.f - fj) * Store<InT>::get(s1 + o00) + fj * Store<InT>::get(s1 + o01);
-        const float b1 = (1.f - fj) * Store<InT>::get(s1 + o10) + fj * Store<InT>::get(s1 + o11);
-        const float t0 = (1.f - fi) * a0 + fi * b0;
-        const float t1 = (1.f - fi) * a1 + fi * b1;
-        a.T[(size_t)l * a.P + (a.out_index ? (int64_t)a.out_index[p] : p)] = (1.f - fk) * t0 + fk * t1;
+    const float x = a.points[3 * p], y = a.points[3 * p + 1], z = a.points[3 * p + 2];
+    const float dx = x - a.lights[3 * l], dy = y - a.lights[3 * l + 1], dz = z - a.lights[3 * l + 2];
+    const float l1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
+    float qx = 0.f, qy = 0.f, qz = 1.f;
+    if (l1 > 0.f) {
+        const float il = 1.f / l1;
+        qx = dx * il; qy = dy * il; qz = dz * il;
     }
+    float u = qx, v = qy;
+    if (qz < 0.f) {
+        u = copysignf(1.f - fabsf(qy), qx >= 0.f ? 1.f : -1.f);
+        v = copysignf(1.f - fabsf(qx), qy >= 0.f ? 1.f : -1.f);
+    }
+    // clamped (NaN-safe) so that every gathered texel index stays in the atlas
+    const float jf = fminf(fmaxf((u + 1.f) * (0.5f * (float)g.W) - 0.5f, -0.5f), (float)g.W - 0.5f);
+    const float fi_ = fminf(fmaxf((v + 1.f) * (0.5f * (float)g.H) - 0.5f, -0.5f), (float)g.H - 0.5f);
+    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+    float kf = g.spacing == DGSM_SHELLS_GEOMETRIC ? (__log2f(r) - a.lr0) * a.kscale : r * a.kscale - 0.5f;
+    kf = fminf(fmaxf(kf, 0.f), (float)(g.K - 1));   // log2(0) = -inf clamps to shell 0
+    const float j0f = floorf(jf), i0f = floorf(fi_);
+    const int j0 = (int)j0f, i0 = (int)i0f;
+    const float fj = jf - j0f, fi = fi_ - i0f;
+    const int k0 = min((int)kf, g.K - 2);
+    const float fk = kf - (float)k0;
+    const int o00 = wrap_offset(i0, j0, g.H, g.W, g.TW, tiled);
+    const int o01 = wrap_offset(i0, j0 + 1, g.H, g.W, g.TW, tiled);
+    const int o10 = wrap_offset(i0 + 1, j0, g.H, g.W, g.TW, tiled);
+    const int o11 = wrap_offset(i0 + 1, j0 + 1, g.H, g.W, g.TW, tiled);
+    const InT* s0 = atlas + ((size_t)l * g.K + k0) * plane;
+    const InT* s1 = s0 + plane;
+    const float a0 = (1.f - fj) * Store<InT>::get(s0 + o00) + fj * Store<InT>::get(s0 + o01);
+    const float b0 = (1.f - fj) * Store<InT>::get(s0 + o10) + fj * Store<InT>::get(s0 + o11);
+    const float a1 = (1.f - fj) * Store<InT>::get(s1 + o00) + fj * Store<InT>::get(s1 + o01);
+    const float b1 = (1.f - fj) * Store<InT>::get(s1 + o10) + fj * Store<InT>::get(s1 + o11);
+    const float t0 = (1.f - fi) * a0 + fi * b0;
+    const float t1 = (1.f - fi) * a1 + fi * b1;
+    a.T[(size_t)l * a.P + (a.out_index ? (int64_t)a.out_index[p] : p)] = (1.f - fk) * t0 + fk * t1;
 }
 
 hipError_t launch_query(const Geom& g, const float* lights, int L, const void* atlas, const float* points,
@@ -92,11 +93,11 @@ hipError_t launch_query(const Geom& g, const float* lights, int L, const void* a
     } else {
         a.kscale = (float)g.K / g.r1;
     }
-    const unsigned blocks = (unsigned)((P + 255) / 256);
+    const dim3 grid((unsigned)((P + 255) / 256), L);
     if (g.dtype == DGSM_F16)
-        query_kernel<__half><<<blocks, 256, 0, st>>>(a);
+        query_kernel<__half><<<grid, 256, 0, st>>>(a);
     else
-        query_kernel<float><<<blocks, 256, 0, st>>>(a);
+        query_kernel<float><<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
