@@ -32,6 +32,29 @@ FLOPS_PER_RAMP_EVAL = 27      # one shell of the erf ramp: argument, erf, increm
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the roofline kernel, from two rocprofv3 counter
+# passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over the full-scene
+# accumulation, each scaled by what the same counter reads for a plain 1 GiB
+# device copy.  Valid only for the kernel sources they were taken on.
+TRAFFIC_SOURCES = ("paper_2601_01660_amd/csrc/dgsm_build.hip", "paper_2601_01660_amd/csrc/dgsm_device.hpp",
+                   "paper_2601_01660_amd/csrc/dgsm_host.hpp")
+TRAFFIC = None   # {"sha256": ..., "fetch_bytes": ..., "write_bytes": ..., "profile": ...}
+
+
+def measured_traffic():
+    """Counter-derived HBM bytes per launch, or None if the kernel changed since."""
+    import hashlib
+    if not TRAFFIC:
+        return None
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != TRAFFIC["sha256"]:
+        return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -230,6 +253,23 @@ def main():
     log(f"work units of the last plain accumulation (extra slices, split tiles, hits/slice, hits): {units}")
     log(f"plain per-frame launches: {ms_plain / F:.3f} ms/frame; accumulate {acc_ms:.3f} ms/launch")
     del ws
+
+    # ---- footprint sampling (Sec. 3.3, Ablation A) on the last frame's atlas --------------------
+    gl = sets[F - 1]
+    z7, w7 = P.dgsm_footprint_stencil7()
+    z7, w7 = z7.to(dev), w7.to(dev)
+    zmc = torch.from_numpy(np.random.default_rng(5).normal(size=(16, 3)).astype(np.float32)).to(dev)
+    wmc = torch.full((16,), 1.0 / 16, device=dev)
+    Tfp = torch.empty((L, N), dtype=torch.float32, device=dev)
+    P.dgsm_query_footprint(lights, atlas, table, gl, z7, w7, out=Tfp)
+    torch.cuda.synchronize()
+    footprint = {"center_query_ms": round(timed(lambda: P.dgsm_query(lights, atlas, table, gl.mean, out=Tq), 5), 4),
+                 "stencil7_ms": round(timed(lambda: P.dgsm_query_footprint(lights, atlas, table, gl, z7, w7,
+                                                                           out=Tfp), 5), 4),
+                 "mc16_ms": round(timed(lambda: P.dgsm_query_footprint(lights, atlas, table, gl, zmc, wmc,
+                                                                       out=Tfp), 5), 4),
+                 "points": N, "lights": L}
+    log(f"footprint sampling over {N} Gaussians x {L} lights: {footprint}")
     torch.cuda.empty_cache()
 
     # ---- batched plan: static cache + captured graph (the headline) -------------------------
@@ -261,7 +301,7 @@ def main():
     achieved = flops / (acc_ms * 1e-3) / 1e12
     roofline = {"kernel": "tile_build_kernel (dgsm_accumulate over all 2.15M Gaussians, 4 lights per launch)",
                 "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": measured_traffic(),
                 "launch_ms": round(acc_ms, 4),
                 "units_per_launch": {"tile_pairs": st[0], "active_pairs": st[1], "ramp_evals": st[2],
                                      "tile_gaussian_pairs": st[6], "idle_tile_gaussian_pairs": st[4],
@@ -283,7 +323,7 @@ def main():
            "comparison_ms_per_frame": {"batched_graph_static_cache": round(ms_frame, 4),
                                        "batched_graph_no_cache": round(ms_nocache / F, 4),
                                        "plain_per_frame_launches": round(ms_plain / F, 4)},
-           "roofline": roofline}
+           "roofline": roofline, "footprint_query": footprint}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(P, torch, np, dev, lights, atlas, static_set, dyn_set, tr, N, L, spec,
                                          args.mlp_steps, timed)

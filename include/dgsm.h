@@ -167,6 +167,27 @@ dgsm_status dgsm_work_units(const dgsm_atlas_desc_t* desc, int64_t n_gauss, int3
 dgsm_status dgsm_query(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc, const void* atlas,
                        const float* points, int64_t P, float* T, void* stream);
 
+/*
+ * dgsm_query_footprint - per-receiver transmittance averaged over a footprint
+ * around each Gaussian (Sec. 3.3 sampling; Ablation A "footprint sampling"):
+ *   T_g = sum_i w[i] T(mu_g + R_g (s_g * z[i])),
+ * R_g the rotation of the unit quaternion, s_g the standard deviations, z[i]
+ * offsets in the principal-axes frame, T the trilinear lookup of dgsm_query.
+ * Monte Carlo sampling passes standard-normal draws z and w = 1/n; the
+ * deterministic stencil is dgsm_footprint_stencil7.
+ *   z: device [n][3], w: device [n] (sum 1 expected, not checked), 1 <= n <= 64
+ *   T: device output [lights.n][gaussians.n] float32
+ */
+dgsm_status dgsm_query_footprint(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc, const void* atlas,
+                                 const dgsm_gaussians_t* gaussians, const float* z, const float* w, int32_t n,
+                                 float* T, void* stream);
+
+/* The 7-point footprint stencil (host arrays): z = 0 and +-e_j (one standard
+ * deviation along each principal axis), weights proportional to the Gaussian
+ * kernel exp(-|z|^2 / 2) at the offsets, normalised to sum 1.  The paper
+ * names the stencil without its offsets or weights; this is the reading used. */
+void dgsm_footprint_stencil7(float z[21], float w[7]);
+
 /* Parameters of the SH radiance transfer (Sec. 3.5).  The lat-long grid has
  * cell centres theta_a = (a + 1/2) pi / n_theta, phi_b = (b + 1/2) 2 pi / n_phi,
  * direction (sin th cos ph, sin th sin ph, cos th) and weight sin(theta).

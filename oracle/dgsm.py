@@ -300,6 +300,37 @@ def query(table, light, points, spacing="geometric", r0=0.05, r1=8.0):
     return out
 
 
+def footprint_stencil7():
+    """Deterministic 7-point footprint stencil (Sec. 3.3, Ablation A): offsets
+    in the principal-axes frame z = 0 and +-e_j (one standard deviation along
+    each axis), weights proportional to the Gaussian kernel exp(-|z|^2 / 2) at
+    each offset, normalised to sum 1.  (The paper names the stencil but not its
+    offsets or weights; this is the reading used throughout.)"""
+    z = np.zeros((7, 3))
+    for j in range(3):
+        z[1 + 2 * j, j] = 1.0
+        z[2 + 2 * j, j] = -1.0
+    k = np.exp(-0.5 * np.sum(z * z, axis=1))
+    return z, k / k.sum()
+
+
+def query_footprint(table, light, gaussians, z, w, spacing="geometric", r0=0.05, r1=8.0):
+    """Footprint-averaged transmittance of each Gaussian (Sec. 3.3, Ablation A):
+    T_g = sum_i w_i T(mu_g + R_g (s_g * z_i)), with T the trilinear atlas
+    lookup.  z [n, 3] offsets in the principal-axes frame (standard-normal
+    draws for Monte Carlo sampling, or a stencil), w [n] weights summing to 1."""
+    z = np.asarray(z, np.float64).reshape(-1, 3)
+    w = np.asarray(w, np.float64).reshape(-1)
+    mu = gaussians.mean.astype(np.float64)
+    R = quaternion_to_matrix(gaussians.rot)
+    s = gaussians.scale.astype(np.float64)
+    out = np.zeros(gaussians.n)
+    for zi, wi in zip(z, w):
+        x = mu + np.einsum("nij,nj->ni", R, s * zi)
+        out += wi * query(table, light, x, spacing, r0, r1)
+    return out
+
+
 def query_exact(light, gaussians, points, H, W, K, spacing="geometric", r0=0.05, r1=8.0,
                 kappa=1.0):
     """Query at points without a stored atlas: the 8 texel values each point

@@ -82,6 +82,10 @@ SIGNATURES = {
     "dgsm_work_units": (ctypes.c_int, [ctypes.POINTER(_AtlasDesc), ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
                                        ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.c_void_p]),
+    "dgsm_query_footprint": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_AtlasDesc), ctypes.c_void_p,
+                                            ctypes.POINTER(_Gaussians), ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "dgsm_footprint_stencil7": (None, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "dgsm_check_gaussians": (ctypes.c_int, [ctypes.POINTER(_Gaussians), ctypes.c_void_p,
                                             ctypes.POINTER(ctypes.c_longlong), ctypes.c_void_p]),
     "dgsm_plan_tile_waves": (ctypes.c_int32, [ctypes.c_void_p]),
@@ -265,6 +269,34 @@ def dgsm_accumulate(lights, atlas: Atlas, n_gauss: int, out, workspace, stats=No
     _check(lib().dgsm_accumulate(ctypes.byref(lt), ctypes.byref(d), n_gauss, _ptr(out), _ptr(workspace),
                                  workspace.numel(), _ptr(stats), _stream()))
     return out
+
+
+def dgsm_query_footprint(lights, atlas: Atlas, table, gaussians: GaussianSet, z, w, out=None):
+    """Footprint-averaged T[L, N] (offsets z [n, 3] in the principal-axes frame, weights w [n])."""
+    lights = _dev(lights)
+    z = _dev(z)
+    w = _dev(w)
+    L = int(lights.shape[0])
+    if z.numel() != 3 * w.numel():
+        raise ValueError("z must be [n, 3] for n weights")
+    if out is None:
+        out = torch.empty((L, gaussians.n), dtype=torch.float32, device=gaussians.mean.device)
+    _cuda(out, "out")
+    _cuda(table, "table")
+    d = atlas.struct()
+    lt = _Lights(lights.data_ptr(), L, 1.0)
+    gs = gaussians.struct()
+    _check(lib().dgsm_query_footprint(ctypes.byref(lt), ctypes.byref(d), _ptr(table), ctypes.byref(gs), _ptr(z),
+                                      _ptr(w), int(w.numel()), _ptr(out), _stream()))
+    return out
+
+
+def dgsm_footprint_stencil7():
+    """(z [7, 3], w [7]) of the library's 7-point stencil, host float32 tensors."""
+    z = (ctypes.c_float * 21)()
+    w = (ctypes.c_float * 7)()
+    lib().dgsm_footprint_stencil7(z, w)
+    return torch.tensor(list(z), dtype=torch.float32).reshape(7, 3), torch.tensor(list(w), dtype=torch.float32)
 
 
 def dgsm_work_units(atlas: Atlas, n_gauss: int, n_lights: int, workspace, light: int):

@@ -32,19 +32,13 @@ struct QueryArgs {
     const int* out_index;  // optional [P]: point p's result goes to column out_index[p]
 };
 
-// One thread per (point, light): blockIdx.y is the light, so the threads of a
-// wave read 64 consecutive points and write 64 consecutive T values, and each
-// thread has its 8 texel gathers in flight at once.
+// Trilinear lookup of light l's atlas at world point (x, y, z).
 template <typename InT>
-__global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= a.P) return;
-    const int l = blockIdx.y;
+__device__ inline float lookup(const QueryArgs& a, int l, float x, float y, float z) {
     const Geom& g = a.g;
     const bool tiled = a.tiled != 0;
     const size_t plane = tiled ? (size_t)g.ntiles * kWave : (size_t)g.H * g.W;
     const InT* atlas = reinterpret_cast<const InT*>(a.atlas);
-    const float x = a.points[3 * p], y = a.points[3 * p + 1], z = a.points[3 * p + 2];
     const float dx = x - a.lights[3 * l], dy = y - a.lights[3 * l + 1], dz = z - a.lights[3 * l + 2];
     const float l1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
     float qx = 0.f, qy = 0.f, qz = 1.f;
@@ -80,7 +74,68 @@ __global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
     const float b1 = (1.f - fj) * Store<InT>::get(s1 + o10) + fj * Store<InT>::get(s1 + o11);
     const float t0 = (1.f - fi) * a0 + fi * b0;
     const float t1 = (1.f - fi) * a1 + fi * b1;
-    a.T[(size_t)l * a.P + (a.out_index ? (int64_t)a.out_index[p] : p)] = (1.f - fk) * t0 + fk * t1;
+    return (1.f - fk) * t0 + fk * t1;
+}
+
+// One thread per (point, light): blockIdx.y is the light, so the threads of a
+// wave read 64 consecutive points and write 64 consecutive T values, and each
+// thread has its 8 texel gathers in flight at once.
+template <typename InT>
+__global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.P) return;
+    const int l = blockIdx.y;
+    const float T = lookup<InT>(a, l, a.points[3 * p], a.points[3 * p + 1], a.points[3 * p + 2]);
+    a.T[(size_t)l * a.P + (a.out_index ? (int64_t)a.out_index[p] : p)] = T;
+}
+
+// Footprint sampling (Sec. 3.3, Ablation A): T_g = sum_i w_i T(mu_g + R_g (s_g * z_i)),
+// one thread per (Gaussian, light); offsets and weights in LDS.
+constexpr int kMaxFootprint = 64;
+
+struct FootArgs {
+    QueryArgs q;
+    dgsm_gaussians_t gs;
+    const float* z;        // [n][3]
+    const float* w;        // [n]
+    int n;
+};
+
+template <typename InT>
+__global__ __launch_bounds__(256) void footprint_kernel(FootArgs f) {
+    __shared__ float sz[kMaxFootprint][3];
+    __shared__ float sw[kMaxFootprint];
+    for (int i = threadIdx.x; i < f.n; i += 256) {
+        sz[i][0] = f.z[3 * i];
+        sz[i][1] = f.z[3 * i + 1];
+        sz[i][2] = f.z[3 * i + 2];
+        sw[i] = f.w[i];
+    }
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= f.gs.n) return;
+    const int l = blockIdx.y;
+    float qw = f.gs.rot[4 * p], qx = f.gs.rot[4 * p + 1], qy = f.gs.rot[4 * p + 2], qz = f.gs.rot[4 * p + 3];
+    const float qn = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+    // columns of R (principal axes) scaled by the standard deviations
+    const float s0 = f.gs.scale[3 * p], s1 = f.gs.scale[3 * p + 1], s2 = f.gs.scale[3 * p + 2];
+    const float c0x = (1.f - 2.f * (qy * qy + qz * qz)) * s0, c0y = 2.f * (qx * qy + qw * qz) * s0,
+                c0z = 2.f * (qx * qz - qw * qy) * s0;
+    const float c1x = 2.f * (qx * qy - qw * qz) * s1, c1y = (1.f - 2.f * (qx * qx + qz * qz)) * s1,
+                c1z = 2.f * (qy * qz + qw * qx) * s1;
+    const float c2x = 2.f * (qx * qz + qw * qy) * s2, c2y = 2.f * (qy * qz - qw * qx) * s2,
+                c2z = (1.f - 2.f * (qx * qx + qy * qy)) * s2;
+    const float mx = f.gs.mean[3 * p], my = f.gs.mean[3 * p + 1], mz = f.gs.mean[3 * p + 2];
+    float acc = 0.f;
+    for (int i = 0; i < f.n; ++i) {
+        const float z0 = sz[i][0], z1 = sz[i][1], z2 = sz[i][2];
+        const float x = mx + c0x * z0 + c1x * z1 + c2x * z2;
+        const float y = my + c0y * z0 + c1y * z1 + c2y * z2;
+        const float zz = mz + c0z * z0 + c1z * z1 + c2z * z2;
+        acc += sw[i] * lookup<InT>(f.q, l, x, y, zz);
+    }
+    f.q.T[(size_t)l * f.gs.n + p] = acc;
 }
 
 hipError_t launch_query(const Geom& g, const float* lights, int L, const void* atlas, const float* points,
@@ -114,6 +169,50 @@ extern "C" dgsm_status dgsm_query(const dgsm_lights_t* lights, const dgsm_atlas_
     const Geom g = make_geom(*desc);
     return launch_query(g, lights->pos, lights->n, atlas, points, P, T,
                         reinterpret_cast<hipStream_t>(stream)) == hipSuccess ? DGSM_OK : DGSM_EHIP;
+}
+
+extern "C" dgsm_status dgsm_query_footprint(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc,
+                                            const void* atlas, const dgsm_gaussians_t* gaussians, const float* z,
+                                            const float* w, int32_t n, float* T, void* stream) {
+    dgsm_status st = validate_desc(desc);
+    if (st != DGSM_OK) return st;
+    if ((st = validate_lights(lights)) != DGSM_OK) return st;
+    if ((st = validate_gaussians(gaussians)) != DGSM_OK) return st;
+    if (n < 1 || n > kMaxFootprint || !z || !w) return DGSM_EINVAL;
+    if (gaussians->n > 0 && (!atlas || !T)) return DGSM_EINVAL;
+    if (gaussians->n == 0) return DGSM_OK;
+    const Geom g = make_geom(*desc);
+    FootArgs f{};
+    f.q = QueryArgs{g, lights->pos, lights->n, atlas, nullptr, gaussians->n, T, 0.f, 0.f, 0, nullptr};
+    if (g.spacing == DGSM_SHELLS_GEOMETRIC) {
+        f.q.lr0 = log2f(g.r0);
+        f.q.kscale = (float)(g.K - 1) / log2f(g.r1 / g.r0);
+    } else {
+        f.q.kscale = (float)g.K / g.r1;
+    }
+    f.gs = *gaussians;
+    f.z = z;
+    f.w = w;
+    f.n = n;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const dim3 grid((unsigned)((gaussians->n + 255) / 256), lights->n);
+    if (g.dtype == DGSM_F16)
+        footprint_kernel<__half><<<grid, 256, 0, s>>>(f);
+    else
+        footprint_kernel<float><<<grid, 256, 0, s>>>(f);
+    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
+}
+
+extern "C" void dgsm_footprint_stencil7(float z[21], float w[7]) {
+    for (int i = 0; i < 21; ++i) z[i] = 0.f;
+    const double e = exp(-0.5);
+    const double norm = 1.0 + 6.0 * e;
+    w[0] = (float)(1.0 / norm);
+    for (int j = 0; j < 3; ++j) {
+        z[3 * (1 + 2 * j) + j] = 1.f;
+        z[3 * (2 + 2 * j) + j] = -1.f;
+        w[1 + 2 * j] = w[2 + 2 * j] = (float)(e / norm);
+    }
 }
 
 extern "C" const char* dgsm_status_string(dgsm_status s) {

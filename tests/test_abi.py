@@ -128,3 +128,23 @@ def test_binding_rejects_host_tensors_for_device_arguments():
     with pytest.raises(ValueError):
         P._cuda(torch.zeros(3), "x")
     assert P._cuda(None, "x") is None
+
+
+def test_library_stencil_matches_the_oracle_reading(lib):
+    import numpy as np
+    import paper_2601_01660_amd as P
+    from oracle import dgsm as od
+    z, w = P.dgsm_footprint_stencil7()
+    zo, wo = od.footprint_stencil7()
+    assert np.array_equal(z.numpy(), zo.astype(np.float32))
+    assert np.allclose(w.numpy(), wo, rtol=0, atol=1e-7)
+
+
+def test_footprint_query_validates_sample_count(lib):
+    import paper_2601_01660_amd as P
+    d = _desc().struct()
+    lt = P._Lights(1, 1, 1.0)
+    gs = P._Gaussians(1, 1, 1, 1, 5)
+    assert lib.dgsm_query_footprint(ctypes.byref(lt), ctypes.byref(d), 1, ctypes.byref(gs), 1, 1, 0, 1, None) == 1
+    assert lib.dgsm_query_footprint(ctypes.byref(lt), ctypes.byref(d), 1, ctypes.byref(gs), 1, 1, 65, 1, None) == 1
+    assert lib.dgsm_query_footprint(ctypes.byref(lt), ctypes.byref(d), 1, ctypes.byref(gs), None, 1, 7, 1, None) == 1

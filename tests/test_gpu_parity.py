@@ -281,3 +281,25 @@ def test_domain_check_counts_bad_gaussians():
     scale[640, 0] = np.inf          # two faults on one Gaussian count once
     bad = P.GaussianSet.from_host(synth.Gaussians(mean, scale, rot, opac))
     assert P.dgsm_check_gaussians(bad) == 5
+
+
+@pytest.mark.parametrize("kind", ["stencil7", "mc16"])
+def test_footprint_query_matches_oracle(cfg1, kind):
+    import paper_2601_01660_amd as P
+    U = _util()
+    g = cfg1["gaussians"]
+    T, atlas = U.gpu_build(g, cfg1["lights"], cfg1["atlas"])
+    if kind == "stencil7":
+        z, w = od.footprint_stencil7()
+    else:
+        z = np.random.default_rng(12).normal(size=(16, 3))
+        w = np.full(16, 1 / 16)
+    got = P.dgsm_query_footprint(torch.from_numpy(cfg1["lights"]), atlas, T, P.GaussianSet.from_host(g),
+                                 torch.from_numpy(z.astype(np.float32)), torch.from_numpy(w.astype(np.float32)))
+    torch.cuda.synchronize()
+    a = cfg1["atlas"]
+    zf = z.astype(np.float32).astype(np.float64)      # the offsets the device saw
+    ref = od.query_footprint(cfg1["oracle_T"], cfg1["lights"][0], g, zf, w, a.spacing, a.r0, a.r1)
+    err = np.abs(got[0].cpu().numpy() - ref).max()
+    _report(f"footprint {kind}", err)
+    assert err <= TOL

@@ -383,3 +383,65 @@ def test_transmittance_at_points_equals_table_at_texel_centres_and_shells():
     for k in (0, 3, 5):
         pts = light + t[k] * d
         assert np.allclose(od.transmittance_at(light, g, pts), T[k].reshape(-1), rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# Footprint sampling (Sec. 3.3, Ablation A)
+# ---------------------------------------------------------------------------
+
+def _footprint_case(seed=21):
+    rng = np.random.default_rng(seed)
+    g = synth.random_gaussians(rng, rng.uniform(-1.5, 1.5, (300, 3)) + [0, 0, 2.0], 0.05)
+    light = np.array([0.2, -0.1, 0.0])
+    T = od.build(light, g, 16, 16, 8)
+    return g, light, T
+
+
+def test_footprint_single_centre_sample_is_the_point_query():
+    g, light, T = _footprint_case()
+    got = od.query_footprint(T, light, g, np.zeros((1, 3)), np.ones(1))
+    assert np.array_equal(got, od.query(T, light, g.mean))
+
+
+def test_footprint_of_a_constant_atlas_is_that_constant():
+    g, light, _ = _footprint_case()
+    z = np.random.default_rng(4).normal(size=(9, 3))
+    got = od.query_footprint(np.full((8, 16, 16), 0.37), light, g, z, np.full(9, 1 / 9))
+    assert np.allclose(got, 0.37, rtol=0, atol=1e-15)
+
+
+def test_footprint_points_follow_the_principal_axes():
+    """A sample at z = e_j lands one standard deviation along the j-th principal
+    axis, mu + s_j R e_j (R e_j the j-th column of the rotation): compared with a
+    point query there."""
+    g, light, T = _footprint_case()
+    R = od.quaternion_to_matrix(g.rot)
+    for j in range(3):
+        zj = np.zeros((1, 3))
+        zj[0, j] = 1.0
+        pts = g.mean + R[:, :, j] * g.scale[:, j:j + 1]
+        assert np.allclose(od.query_footprint(T, light, g, zj, np.ones(1)), od.query(T, light, pts),
+                           rtol=0, atol=1e-15)
+
+
+def test_stencil7_weights_and_symmetry():
+    z, w = od.footprint_stencil7()
+    assert z.shape == (7, 3) and abs(w.sum() - 1) < 1e-15
+    assert np.allclose(z.sum(axis=0), 0) and np.allclose((w[:, None] * z).sum(axis=0), 0)
+    # Gaussian kernel ratio between an axis point and the centre
+    assert abs(w[1] / w[0] - np.exp(-0.5)) < 1e-15 and np.allclose(w[1:], w[1])
+
+
+def test_footprint_is_a_weighted_average_invariant_to_sample_order():
+    g, light, T = _footprint_case()
+    rng = np.random.default_rng(8)
+    z = rng.normal(size=(6, 3))
+    w = rng.uniform(0.1, 1, 6)
+    w /= w.sum()
+    a = od.query_footprint(T, light, g, z, w)
+    perm = rng.permutation(6)
+    b = od.query_footprint(T, light, g, z[perm], w[perm])
+    assert np.allclose(a, b, rtol=0, atol=1e-15)
+    lo = np.min([od.query_footprint(T, light, g, z[i:i + 1], [1.0]) for i in range(6)], axis=0)
+    hi = np.max([od.query_footprint(T, light, g, z[i:i + 1], [1.0]) for i in range(6)], axis=0)
+    assert np.all(a >= lo - 1e-15) and np.all(a <= hi + 1e-15)
