@@ -270,6 +270,25 @@ def main():
                                                                        out=Tfp), 5), 4),
                  "points": N, "lights": L}
     log(f"footprint sampling over {N} Gaussians x {L} lights: {footprint}")
+
+    # ---- receiver-driven region of interest (Sec. 3.2) around the avatar -----------------------
+    cen = P.dgsm_alpha_centroid(P.GaussianSet(means[0, scene.n:], scale[scene.n:], rot[scene.n:], opac[scene.n:]))
+    cx, cy = (float(v) for v in cen[:2].cpu())
+    az = means[0, scene.n:, 2]
+    box = (cx, cy, 2.0, float(az.min()) - 0.1, float(az.max()) + 0.1)
+    g0 = sets[0]
+    ws_r = torch.empty(P.dgsm_build_workspace_size(atlas, N, L), dtype=torch.uint8, device=dev)
+    roi_t = P.dgsm_build_roi(lights, g0, atlas, g0.mean, box=box, workspace=ws_r)
+    full_t = P.dgsm_build(lights, g0, atlas, workspace=ws_r)
+    torch.cuda.synchronize()
+    roi = {"box": [round(v, 3) for v in box],
+           "build_roi_ms": round(timed(lambda: P.dgsm_build_roi(lights, g0, atlas, g0.mean, box=box, out=roi_t,
+                                                                workspace=ws_r), 2), 3),
+           "build_full_ms": round(timed(lambda: P.dgsm_build(lights, g0, atlas, out=full_t, workspace=ws_r), 2), 3),
+           "atlas_fraction_kept": round(float((roi_t != 1).float().mean().item()), 4)}
+    del ws_r, roi_t, full_t
+    torch.cuda.empty_cache()
+    log(f"receiver region around the avatar: {roi}")
     torch.cuda.empty_cache()
 
     # ---- batched plan: static cache + captured graph (the headline) -------------------------
@@ -323,7 +342,7 @@ def main():
            "comparison_ms_per_frame": {"batched_graph_static_cache": round(ms_frame, 4),
                                        "batched_graph_no_cache": round(ms_nocache / F, 4),
                                        "plain_per_frame_launches": round(ms_plain / F, 4)},
-           "roofline": roofline, "footprint_query": footprint}
+           "roofline": roofline, "footprint_query": footprint, "roi_build": roi}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(P, torch, np, dev, lights, atlas, static_set, dyn_set, tr, N, L, spec,
                                          args.mlp_steps, timed)

@@ -153,6 +153,32 @@ dgsm_status dgsm_work_units(const dgsm_atlas_desc_t* desc, int64_t n_gauss, int3
                             size_t ws_bytes, int32_t light, int32_t out[4], void* stream);
 
 /*
+ * dgsm_build_roi - dgsm_build restricted to a receiver-driven region of
+ * interest (Sec. 3.2 "Receiver-driven region of interest"): receivers are the
+ * points of `receivers` inside the box
+ *   |x - cx| <= half, |y - cy| <= half, zmin <= z <= zmax
+ * (half <= 0: every point is a receiver; cx, cy typically the alpha-weighted
+ * avatar centroid from dgsm_alpha_centroid, half the radius R of the paper,
+ * zmin / zmax robust height bounds).  Per light, the region is the set of
+ * texels each receiver's trilinear lookup reads (its cell of dgsm_query, four
+ * texels with the octahedral wrap) times the shell range [k_min, k_max] of
+ * all receivers (each lookup reads shells k0 and k0 + 1).  T equals the full
+ * build inside the region and is 1 outside it, by construction; queries at
+ * receivers therefore equal queries of the full atlas (up to FP32 rounding of
+ * the per-shell sums).  Tiles without receiver texels do no accumulation.
+ *   receivers: device [n_receivers][3] (n_receivers = 0: T = 1 everywhere)
+ *   box      : host
+ *   atlas, ws: as dgsm_build (the same workspace size)
+ */
+typedef struct {
+    float cx, cy, half, zmin, zmax;
+} dgsm_roi_box_t;
+
+dgsm_status dgsm_build_roi(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
+                           const dgsm_atlas_desc_t* desc, const float* receivers, int64_t n_receivers,
+                           const dgsm_roi_box_t* box, void* atlas, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * dgsm_query - sample the atlas at world points (Sec. 3.3): for each light l
  * and point x, r = |x - o_L|, d = (x - o_L)/r (d = +z when r = 0), continuous
  * texel coordinates j_f = (u+1) W/2 - 1/2, i_f = (v+1) H/2 - 1/2 of (u, v) =

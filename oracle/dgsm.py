@@ -300,6 +300,40 @@ def query(table, light, points, spacing="geometric", r0=0.05, r1=8.0):
     return out
 
 
+def roi_region(light, receivers, H, W, K, box=None, spacing="geometric", r0=0.05, r1=8.0):
+    """Receiver-driven region of interest (Sec. 3.2): receivers inside the box
+    B = {|x - cx| <= R, |y - cy| <= R, zmin <= z <= zmax} (box = (cx, cy, R,
+    zmin, zmax); None or R <= 0 keeps every point) mark the texels their
+    trilinear lookup reads (the floor texel and its three neighbours, wrapped);
+    the radial range is [min k0, max k0 + 1] over the receivers.
+    Returns (texel mask [H, W] bool, k_min, k_max); k_min > k_max if empty."""
+    pts = np.asarray(receivers, dtype=np.float64).reshape(-1, 3)
+    if box is not None and box[2] > 0:
+        cx, cy, R, zmin, zmax = box
+        keep = (np.abs(pts[:, 0] - cx) <= R) & (np.abs(pts[:, 1] - cy) <= R) & (pts[:, 2] >= zmin) & \
+               (pts[:, 2] <= zmax)
+        pts = pts[keep]
+    mask = np.zeros((H, W), dtype=bool)
+    if pts.shape[0] == 0:
+        return mask, K, -1
+    i_f, jf, kf = query_coords(light, pts, H, W, K, spacing, r0, r1)
+    i0, j0, k0, _, _, _ = _corner_weights(i_f, jf, kf, K)
+    for di in (0, 1):
+        for dj in (0, 1):
+            ii, jj = wrap_texel(i0 + di, j0 + dj, H, W)
+            mask[ii, jj] = True
+    return mask, int(k0.min()), int(k0.max() + 1)
+
+
+def build_roi(light, gaussians, H, W, K, receivers, box=None, spacing="geometric", r0=0.05, r1=8.0,
+              kappa=1.0):
+    """T[K, H, W] of the full build inside the receiver region, 1 outside it."""
+    mask, k_lo, k_hi = roi_region(light, receivers, H, W, K, box, spacing, r0, r1)
+    T = build(light, gaussians, H, W, K, spacing, r0, r1, kappa)
+    keep = mask[None, :, :] & (np.arange(K)[:, None, None] >= k_lo) & (np.arange(K)[:, None, None] <= k_hi)
+    return np.where(keep, T, 1.0)
+
+
 def footprint_stencil7():
     """Deterministic 7-point footprint stencil (Sec. 3.3, Ablation A): offsets
     in the principal-axes frame z = 0 and +-e_j (one standard deviation along

@@ -50,6 +50,11 @@ class _MlpTrain(ctypes.Structure):
 MLP_PARAMS = 66177
 
 
+class _RoiBox(ctypes.Structure):
+    _fields_ = [("cx", ctypes.c_float), ("cy", ctypes.c_float), ("half", ctypes.c_float), ("zmin", ctypes.c_float),
+                ("zmax", ctypes.c_float)]
+
+
 class _PlanOpts(ctypes.Structure):
     _fields_ = [("frames", ctypes.c_int32), ("static_cache", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("tile_waves", ctypes.c_int32), ("split_units", ctypes.c_int32)]
@@ -63,6 +68,9 @@ SIGNATURES = {
     "dgsm_build_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(_AtlasDesc), ctypes.c_int64, ctypes.c_int32]),
     "dgsm_build": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_Gaussians), ctypes.POINTER(_AtlasDesc),
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dgsm_build_roi": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_Gaussians), ctypes.POINTER(_AtlasDesc),
+                                      ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(_RoiBox), ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "dgsm_bin": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_Gaussians), ctypes.POINTER(_AtlasDesc),
                                 ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "dgsm_accumulate": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_AtlasDesc), ctypes.c_int64,
@@ -239,6 +247,32 @@ def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0,
     gs = gaussians.struct()
     _check(lib().dgsm_build(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), _ptr(out), _ptr(workspace),
                             workspace.numel(), _stream()))
+    return out
+
+
+def dgsm_build_roi(lights, gaussians: GaussianSet, atlas: Atlas, receivers, box=None, kappa: float = 1.0, out=None,
+                   workspace=None):
+    """Build T[L, K, H, W] restricted to the receivers' region (see dgsm_build_roi in
+    include/dgsm.h); box = (cx, cy, half, zmin, zmax) or None (every receiver)."""
+    lights = _dev(lights)
+    receivers = _dev(receivers)
+    L = int(lights.shape[0])
+    d = atlas.struct()
+    ws_bytes = dgsm_build_workspace_size(atlas, gaussians.n, L)
+    if ws_bytes == 0:
+        raise DGSMError("invalid atlas description")
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=lights.device)
+    if out is None:
+        out = torch.empty((L, atlas.K, atlas.H, atlas.W), dtype=atlas.torch_dtype, device=lights.device)
+    _cuda(out, "out")
+    _cuda(workspace, "workspace")
+    bx = _RoiBox(*(box if box is not None else (0.0, 0.0, 0.0, 0.0, 0.0)))
+    lt = _Lights(lights.data_ptr(), L, kappa)
+    gs = gaussians.struct()
+    _check(lib().dgsm_build_roi(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), _ptr(receivers),
+                                int(receivers.shape[0]), ctypes.byref(bx), _ptr(out), _ptr(workspace),
+                                workspace.numel(), _stream()))
     return out
 
 

@@ -372,6 +372,75 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
 }
 
 // ---------------------------------------------------------------------------
+// Receiver region of interest (Sec. 3.2): only the texels and the radial range
+// that receivers read are kept; everything else is T = 1 by construction.
+// A receiver marks the four texels and two shells its trilinear lookup reads
+// (query_cell), so a query at a receiver sees the same values as with the
+// full atlas.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void roi_clear_kernel(unsigned char* ws, BuildLayout lay, Geom g) {
+    const LightWs W = light_ws(ws, lay, blockIdx.y);
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < g.ntiles) W.roi_mask[t] = 0ull;
+    if (t == 0) {
+        W.roi_k[0] = g.K;
+        W.roi_k[1] = -1;
+    }
+}
+
+__global__ __launch_bounds__(256) void roi_mark_kernel(unsigned char* ws, BuildLayout lay, Geom g,
+                                                       const float* __restrict__ lights,
+                                                       const float* __restrict__ pts, int64_t n, RoiBox box,
+                                                       float lr0, float kscale) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+    if (box.half > 0.f &&
+        !(fabsf(x - box.cx) <= box.half && fabsf(y - box.cy) <= box.half && z >= box.zmin && z <= box.zmax))
+        return;
+    const int l = blockIdx.y;
+    const LightWs W = light_ws(ws, lay, l);
+    const Cell c = query_cell(g, lr0, kscale, lights + 3 * l, x, y, z);
+    for (int d = 0; d < 4; ++d) {
+        int ii = c.i0 + (d >> 1), jj = c.j0 + (d & 1);
+        wrap_texel(ii, jj, g.H, g.W);
+        atomicOr(W.roi_mask + (ii >> 3) * g.TW + (jj >> 3), 1ull << ((ii & 7) * kTile + (jj & 7)));
+    }
+    atomicMin(W.roi_k, c.k0);
+    atomicMax(W.roi_k + 1, c.k0 + 1);
+}
+
+// Tiles outside the region do no work: their hit counts are cleared so that
+// the work-unit planner does not split them.
+__global__ __launch_bounds__(256) void roi_prune_kernel(unsigned char* ws, BuildLayout lay, Geom g) {
+    const LightWs W = light_ws(ws, lay, blockIdx.y);
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < g.ntiles && W.roi_mask[t] == 0ull) W.hits[t] = 0;
+}
+
+dgsm_status enqueue_roi(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
+                        const float* points, int64_t n_points, const RoiBox& box, hipStream_t st) {
+    const dim3 tg((g.ntiles + 255) / 256, lights.n);
+    roi_clear_kernel<<<tg, 256, 0, st>>>(ws, L, g);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    if (n_points > 0) {
+        float lr0 = 0.f, kscale;
+        if (g.spacing == DGSM_SHELLS_GEOMETRIC) {
+            lr0 = log2f(g.r0);
+            kscale = (float)(g.K - 1) / log2f(g.r1 / g.r0);
+        } else {
+            kscale = (float)g.K / g.r1;
+        }
+        roi_mark_kernel<<<dim3((unsigned)((n_points + 255) / 256), lights.n), 256, 0, st>>>(
+            ws, L, g, lights.pos, points, n_points, box, lr0, kscale);
+        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    }
+    roi_prune_kernel<<<tg, 256, 0, st>>>(ws, L, g);
+    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
+}
+
+// ---------------------------------------------------------------------------
 // Work units.  A tile whose hit count is far above the launch's mean would
 // keep a few blocks busy long after the rest of the chip has drained (an
 // animated avatar covers a few dozen tiles with tens of thousands of hits
@@ -495,6 +564,7 @@ struct TileArgs {
     int write_tau;
     int tiled;                 // plane order: 0 row-major H x W; 1 tile-major [TH*TW][8x8]
     int skip_empty;            // tiles without hits return at once and write nothing
+    int roi;                   // T = 1 outside the receiver texels / shell range of the light
     unsigned long long* stats;
 };
 
@@ -572,6 +642,7 @@ struct TexelState {
     float pair_eps;
     unsigned long long* inc; // LDS [K][64], fixed point
     const double* shells;    // LDS [K] shell radii t_k (FP64)
+    int kmin, kmax;          // shells kept (the receiver range; 0 .. K-1 without a region)
 };
 
 // Shell index of a radius (fractional, unclamped); -1 for t <= 0.
@@ -658,7 +729,13 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
         const float khi = fmaxf(shell_index<GEO>(ts + half, s), -1.f);
         ka = klo < 0.f ? 0 : min((int)klo + 1, s.K - 1);
         const int kb = khi > (float)(s.K - 2) ? s.K - 1 : max(0, (int)khi + 1);
-        len = max(0, kb - ka + 1);
+        // only shells in [kmin, kmax] are kept: a ramp below the range still
+        // adds its whole step at kmin, one above it adds nothing
+        if (ka <= s.kmax) {
+            const int k0 = max(ka, s.kmin);
+            len = max(min(kb, s.kmax), k0) - k0 + 1;
+            ka = k0;
+        }
     }
     const int maxlen = wave_max(len);
     if (maxlen <= 0) return;
@@ -758,6 +835,15 @@ __device__ inline void finish_tile(const TileArgs& p, int light, int tile, int l
     const size_t texel = p.tiled ? (size_t)tile * kWave + lane : (size_t)min(py, g.H - 1) * g.W + min(px, g.W - 1);
     const size_t off = (size_t)light * K * plane + texel;
     const float* bt = p.base_tau ? p.base_tau + off : nullptr;
+    // receiver region: texels outside it and shells outside [k_lo, k_hi] store T = 1
+    bool in_roi = true;
+    int rk_lo = 0, rk_hi = K - 1;
+    if (p.roi) {
+        const LightWs W = light_ws(p.ws, p.lay, light);
+        in_roi = (W.roi_mask[tile] >> lane) & 1ull;
+        rk_lo = W.roi_k[0];
+        rk_hi = W.roi_k[1];
+    }
     const int per = (K + NWB - 1) / NWB;
     const int k_lo = min(K, wave * per), k_hi = min(K, k_lo + per);
 
@@ -821,7 +907,8 @@ __device__ inline void finish_tile(const TileArgs& p, int light, int tile, int l
             if (j >= n) break;
             const float T = fminf(__expf(-tt[j]), Tp);
             Tp = T;
-            if (valid) Store<OutT>::put(out + (size_t)(k0 + j) * plane, T);
+            const bool keep = in_roi && k0 + j >= rk_lo && k0 + j <= rk_hi;
+            if (valid) Store<OutT>::put(out + (size_t)(k0 + j) * plane, keep ? T : 1.f);
         }
     }
 }
@@ -844,6 +931,19 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     if ((int)blockIdx.x < g.ntiles) {
         tile = blockIdx.x;
         if (p.skip_empty && W.hits[tile] == 0) return;
+        if (p.roi && W.roi_mask[tile] == 0ull) {          // no receiver here: T = 1 by construction
+            const size_t plane = (size_t)g.H * g.W;
+            const int ty = tile / g.TW, tx = tile - ty * g.TW;
+            for (int q = tid; q < K * kWave; q += kWave * NW) {
+                const int k = q / kWave, l = q % kWave;
+                const int py = ty * kTile + (l >> 3), px = tx * kTile + (l & 7);
+                if (py < g.H && px < g.W)
+                    Store<OutT>::put(reinterpret_cast<OutT*>(p.out) + ((size_t)light * K + k) * plane +
+                                         (size_t)py * g.W + px,
+                                     1.f);
+            }
+            return;
+        }
         const int4 ti = W.tinfo[tile];
         slice = 0;
         nslice = ti.x;
@@ -872,6 +972,8 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     double* shells = reinterpret_cast<double*>(inc + K * kWave + NW * kWave) + (NW * kWave) / 2;   // after s_min
     for (int k = tid; k < K; k += kWave * NW) shells[k] = shell_radius(k, K, g.spacing, g.r0, g.r1);
     st.shells = shells;
+    st.kmin = p.roi ? W.roi_k[0] : 0;
+    st.kmax = p.roi ? W.roi_k[1] : K - 1;
     if (st.geometric) {
         st.lr0 = __builtin_amdgcn_logf(g.r0);
         st.kinv = (float)(K - 1) / __builtin_amdgcn_logf(g.r1 / g.r0);
@@ -993,6 +1095,8 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
     L.splits = take((size_t)L.units_cap * sizeof(int2));
     L.nunits = take(4 * sizeof(int));
     L.part = take(2 * (size_t)L.units_cap * g.K * kWave * sizeof(unsigned long long));
+    L.roi_mask = take((size_t)g.ntiles * sizeof(unsigned long long));
+    L.roi_k = take(2 * sizeof(int));
     L.light_stride = off;
     L.total = L.light0 + (size_t)n_lights * L.light_stride;
     return L;
@@ -1069,7 +1173,7 @@ dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, 
 dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned char* ws, int n_lights,
                                float pair_eps, void* atlas, const AccumOpts& o, hipStream_t st) {
     TileArgs ta{g, L, ws, pair_eps, atlas, o.base_tau, o.write_tau ? 1 : 0, o.tiled ? 1 : 0,
-                o.skip_empty ? 1 : 0, o.stats};
+                o.skip_empty ? 1 : 0, o.roi ? 1 : 0, o.stats};
     hipError_t e;
     const bool half = g.dtype == DGSM_F16 && !o.write_tau;
     const int nw = o.tile_waves;
@@ -1157,6 +1261,27 @@ extern "C" dgsm_status dgsm_work_units(const dgsm_atlas_desc_t* desc, int64_t n_
         hipStreamSynchronize(s) != hipSuccess)
         return DGSM_EHIP;
     return DGSM_OK;
+}
+
+extern "C" dgsm_status dgsm_build_roi(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
+                                      const dgsm_atlas_desc_t* desc, const float* receivers, int64_t n_receivers,
+                                      const dgsm_roi_box_t* box, void* atlas, void* ws, size_t ws_bytes,
+                                      void* stream) {
+    dgsm_status st = check_build_args(lights, gaussians, desc);
+    if (st != DGSM_OK) return st;
+    if (!atlas || !box || n_receivers < 0 || (n_receivers > 0 && !receivers)) return DGSM_EINVAL;
+    if (box->half > 0.f && !(box->zmin <= box->zmax)) return DGSM_EINVAL;
+    const Geom g = make_geom(*desc);
+    const BuildLayout L = build_layout(g, gaussians->n, lights->n);
+    if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+    if ((st = enqueue_bin(g, L, w, *lights, desc->cull_eps, *gaussians, s)) != DGSM_OK) return st;
+    const RoiBox rb{box->cx, box->cy, box->half, box->zmin, box->zmax};
+    if ((st = enqueue_roi(g, L, w, *lights, receivers, n_receivers, rb, s)) != DGSM_OK) return st;
+    AccumOpts o{nullptr, false, nullptr, kDefaultTileWaves, kDefaultSplitUnits};
+    o.roi = true;
+    return enqueue_accumulate(g, L, w, lights->n, desc->cull_eps, atlas, o, s);
 }
 
 extern "C" dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,

@@ -97,6 +97,55 @@ __device__ inline double shell_radius(int k, int K, int spacing, float r0, float
     return ((double)k + 0.5) * (double)r1 / (double)K;
 }
 
+// Trilinear cell of a world point seen from a light (Sec. 3.3): the floor
+// texel (i0, j0), the lower shell k0 and the fractions.  lr0, kscale: shell
+// coordinate (log2 r - lr0) * kscale (geometric) or r * kscale - 1/2 (uniform).
+// Clamped (NaN-safe) so that every texel and shell the lookup touches exists.
+struct Cell {
+    int i0, j0, k0;
+    float fi, fj, fk;
+};
+
+__device__ inline Cell query_cell(const Geom& g, float lr0, float kscale, const float* light, float x, float y,
+                                  float z) {
+    const float dx = x - light[0], dy = y - light[1], dz = z - light[2];
+    const float l1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
+    float qx = 0.f, qy = 0.f, qz = 1.f;
+    if (l1 > 0.f) {
+        const float il = 1.f / l1;
+        qx = dx * il; qy = dy * il; qz = dz * il;
+    }
+    float u = qx, v = qy;
+    if (qz < 0.f) {
+        u = copysignf(1.f - fabsf(qy), qx >= 0.f ? 1.f : -1.f);
+        v = copysignf(1.f - fabsf(qx), qy >= 0.f ? 1.f : -1.f);
+    }
+    const float jf = fminf(fmaxf((u + 1.f) * (0.5f * (float)g.W) - 0.5f, -0.5f), (float)g.W - 0.5f);
+    const float fi_ = fminf(fmaxf((v + 1.f) * (0.5f * (float)g.H) - 0.5f, -0.5f), (float)g.H - 0.5f);
+    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+    float kf = g.spacing == DGSM_SHELLS_GEOMETRIC ? (__log2f(r) - lr0) * kscale : r * kscale - 0.5f;
+    kf = fminf(fmaxf(kf, 0.f), (float)(g.K - 1));   // log2(0) = -inf clamps to shell 0
+    const float j0f = floorf(jf), i0f = floorf(fi_);
+    Cell c;
+    c.j0 = (int)j0f;
+    c.i0 = (int)i0f;
+    c.fj = jf - j0f;
+    c.fi = fi_ - i0f;
+    c.k0 = min((int)kf, g.K - 2);
+    c.fk = kf - (float)c.k0;
+    return c;
+}
+
+// A texel one step outside the grid, through the octahedral mirror wrap:
+// across the left/right edge (u = -1/+1) the map identifies (u, v) with
+// (u, -v), across the top/bottom edge (v = -1/+1) (u, v) with (-u, v).
+__device__ inline void wrap_texel(int& i, int& j, int H, int W) {
+    if (j < 0) { j = 0; i = H - 1 - i; }
+    else if (j >= W) { j = W - 1; i = H - 1 - i; }
+    if (i < 0) { i = 0; j = W - 1 - j; }
+    else if (i >= H) { i = H - 1; j = W - 1 - j; }
+}
+
 extern "C" __device__ int __ockl_wfred_min_i32(int);
 extern "C" __device__ int __ockl_wfred_max_i32(int);
 

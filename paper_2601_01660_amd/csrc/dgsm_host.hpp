@@ -48,7 +48,7 @@ struct BuildLayout {
     int units_cap;           // extra work units per light (tiles split over several blocks)
     // offsets inside a light slice
     size_t totals, lbase, rec, cone, mask, counts, lists, bits;
-    size_t hits, tinfo, units, splits, nunits, part;
+    size_t hits, tinfo, units, splits, nunits, part, roi_mask, roi_k;
     size_t total;            // bytes for all lights
 };
 
@@ -68,6 +68,8 @@ struct LightWs {
     int2* splits;      // [units_cap] split tiles: {tile, first partial}
     int* nunits;       // [4] {extra slices, split tiles, hits per slice, total hits}
     unsigned long long* part;   // [2 units_cap][K][64] fixed-point partial optical depths
+    unsigned long long* roi_mask;   // [ntiles] receiver texels of each tile (bit = texel in the tile)
+    int* roi_k;                     // [2] receiver shell range {k_min, k_max}
 };
 
 __host__ __device__ inline LightWs light_ws(unsigned char* ws, const BuildLayout& L, int l) {
@@ -78,7 +80,8 @@ __host__ __device__ inline LightWs light_ws(unsigned char* ws, const BuildLayout
                    reinterpret_cast<int*>(b + L.lists), reinterpret_cast<uint64_t*>(b + L.bits),
                    reinterpret_cast<int*>(b + L.hits), reinterpret_cast<int4*>(b + L.tinfo),
                    reinterpret_cast<int4*>(b + L.units), reinterpret_cast<int2*>(b + L.splits),
-                   reinterpret_cast<int*>(b + L.nunits), reinterpret_cast<unsigned long long*>(b + L.part)};
+                   reinterpret_cast<int*>(b + L.nunits), reinterpret_cast<unsigned long long*>(b + L.part),
+                   reinterpret_cast<unsigned long long*>(b + L.roi_mask), reinterpret_cast<int*>(b + L.roi_k)};
 }
 
 BuildLayout build_layout(const Geom& g, int64_t n, int n_lights);
@@ -101,7 +104,19 @@ struct AccumOpts {
     int split_units;             // target work units per launch (all lights); <= 0: never split a tile
     bool tiled = false;          // atlas / base_tau planes in tile-major order (see kTile)
     bool skip_empty = false;     // leave tiles without hits untouched (their atlas values stay as they are)
+    bool roi = false;            // receiver region: T = 1 outside the marked texels and shell range
 };
+
+// Receiver box of the region of interest (Sec. 3.2): |x - cx|, |y - cy| <= half,
+// zmin <= z <= zmax; half <= 0 takes every receiver point.
+struct RoiBox {
+    float cx, cy, half, zmin, zmax;
+};
+
+// Mark the receiver region of every light: the texels and shells the
+// trilinear lookup of each receiver point inside the box reads.
+dgsm_status enqueue_roi(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
+                        const float* points, int64_t n_points, const RoiBox& box, hipStream_t st);
 
 // Elements of one shell plane: H*W row-major, or ntiles*64 tile-major (each
 // 8x8 tile's texels contiguous, row-major inside the tile).

@@ -6,16 +6,10 @@
 
 namespace dgsm {
 
-// Octahedral mirror wrap of a texel one step outside the grid: across the
-// left/right edge (u = -1/+1) the map identifies (u, v) with (u, -v), across
-// the top/bottom edge (v = -1/+1) it identifies (u, v) with (-u, v).
-// Returns the texel's element offset in a shell plane (row-major, or
+// Element offset of texel (i, j), wrapped, in a shell plane (row-major, or
 // tile-major with 8x8 tiles when tiled).
 __device__ inline int wrap_offset(int i, int j, int H, int W, int TW, bool tiled) {
-    if (j < 0) { j = 0; i = H - 1 - i; }
-    else if (j >= W) { j = W - 1; i = H - 1 - i; }
-    if (i < 0) { i = 0; j = W - 1 - j; }
-    else if (i >= H) { i = H - 1; j = W - 1 - j; }
+    wrap_texel(i, j, H, W);
     return tiled ? ((i >> 3) * TW + (j >> 3)) * kWave + (i & 7) * kTile + (j & 7) : i * W + j;
 }
 
@@ -39,29 +33,9 @@ __device__ inline float lookup(const QueryArgs& a, int l, float x, float y, floa
     const bool tiled = a.tiled != 0;
     const size_t plane = tiled ? (size_t)g.ntiles * kWave : (size_t)g.H * g.W;
     const InT* atlas = reinterpret_cast<const InT*>(a.atlas);
-    const float dx = x - a.lights[3 * l], dy = y - a.lights[3 * l + 1], dz = z - a.lights[3 * l + 2];
-    const float l1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
-    float qx = 0.f, qy = 0.f, qz = 1.f;
-    if (l1 > 0.f) {
-        const float il = 1.f / l1;
-        qx = dx * il; qy = dy * il; qz = dz * il;
-    }
-    float u = qx, v = qy;
-    if (qz < 0.f) {
-        u = copysignf(1.f - fabsf(qy), qx >= 0.f ? 1.f : -1.f);
-        v = copysignf(1.f - fabsf(qx), qy >= 0.f ? 1.f : -1.f);
-    }
-    // clamped (NaN-safe) so that every gathered texel index stays in the atlas
-    const float jf = fminf(fmaxf((u + 1.f) * (0.5f * (float)g.W) - 0.5f, -0.5f), (float)g.W - 0.5f);
-    const float fi_ = fminf(fmaxf((v + 1.f) * (0.5f * (float)g.H) - 0.5f, -0.5f), (float)g.H - 0.5f);
-    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-    float kf = g.spacing == DGSM_SHELLS_GEOMETRIC ? (__log2f(r) - a.lr0) * a.kscale : r * a.kscale - 0.5f;
-    kf = fminf(fmaxf(kf, 0.f), (float)(g.K - 1));   // log2(0) = -inf clamps to shell 0
-    const float j0f = floorf(jf), i0f = floorf(fi_);
-    const int j0 = (int)j0f, i0 = (int)i0f;
-    const float fj = jf - j0f, fi = fi_ - i0f;
-    const int k0 = min((int)kf, g.K - 2);
-    const float fk = kf - (float)k0;
+    const Cell c = query_cell(g, a.lr0, a.kscale, a.lights + 3 * l, x, y, z);
+    const int i0 = c.i0, j0 = c.j0, k0 = c.k0;
+    const float fi = c.fi, fj = c.fj, fk = c.fk;
     const int o00 = wrap_offset(i0, j0, g.H, g.W, g.TW, tiled);
     const int o01 = wrap_offset(i0, j0 + 1, g.H, g.W, g.TW, tiled);
     const int o10 = wrap_offset(i0 + 1, j0, g.H, g.W, g.TW, tiled);

@@ -445,3 +445,32 @@ def test_footprint_is_a_weighted_average_invariant_to_sample_order():
     lo = np.min([od.query_footprint(T, light, g, z[i:i + 1], [1.0]) for i in range(6)], axis=0)
     hi = np.max([od.query_footprint(T, light, g, z[i:i + 1], [1.0]) for i in range(6)], axis=0)
     assert np.all(a >= lo - 1e-15) and np.all(a <= hi + 1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Receiver-driven region of interest (Sec. 3.2)
+# ---------------------------------------------------------------------------
+
+def test_roi_queries_at_receivers_equal_full_queries():
+    """Every value a receiver's lookup reads lies in the region, so its query is
+    the full atlas's query exactly (the point of marking the lookup's cell)."""
+    g, light, T = _footprint_case(31)
+    rng = np.random.default_rng(3)
+    rec = rng.uniform(-1.5, 1.5, (200, 3)) + [0, 0, 2.0]
+    Troi = od.build_roi(light, g, 16, 16, 8, rec)
+    assert np.array_equal(od.query(Troi, light, rec), od.query(T, light, rec))
+    assert np.any(Troi == 1.0) and np.any(Troi < 1.0)
+
+
+def test_roi_without_receivers_is_transparent():
+    g, light, _ = _footprint_case(31)
+    assert np.all(od.build_roi(light, g, 16, 16, 8, np.zeros((0, 3))) == 1.0)
+
+
+def test_roi_box_keeps_only_receivers_inside():
+    g, light, _ = _footprint_case(31)
+    rec = np.array([[0.5, 0.5, 1.5], [-1.0, -1.0, 2.5]])
+    m1, k1a, k1b = od.roi_region(light, rec[:1], 16, 16, 8)
+    mb, kba, kbb = od.roi_region(light, rec, 16, 16, 8, box=(0.5, 0.5, 0.2, 1.0, 2.0))
+    assert np.array_equal(m1, mb) and (k1a, k1b) == (kba, kbb)
+    assert m1.sum() <= 4 and k1b == k1a + 1
