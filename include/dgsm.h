@@ -63,12 +63,23 @@ typedef struct {
     int64_t n;
 } dgsm_gaussians_t;
 
+/* Opacity-to-absorption mapping (Sec. 3.2 Eq. 5 and the alpha -> beta
+ * ablation), with tau* = -ln(1 - alpha) and kappa the strength knob:
+ *   DGSM_BETA_TRACE    beta = kappa tau* sqrt(tr(A)/3) / sqrt(2 pi)   (Eq. 5, default)
+ *   DGSM_BETA_CONSTANT beta = kappa tau*
+ *   DGSM_BETA_DENSITY  beta = kappa tau* / ((2 pi)^(3/2) s_x s_y s_z)
+ *                      (the ablation's det-of-covariance and diagonal-scale
+ *                      forms coincide: det of the covariance = (s_x s_y s_z)^2) */
+typedef enum { DGSM_BETA_TRACE = 0, DGSM_BETA_CONSTANT = 1, DGSM_BETA_DENSITY = 2 } dgsm_beta_mode;
+
 /* Point lights.  pos is a DEVICE pointer [n][3].  kappa is the global
- * strength knob of Eq. 5 (1 reproduces the 3DGS opacity in the far field). */
+ * strength knob of Eq. 5 (1 reproduces the 3DGS opacity in the far field);
+ * beta_mode a dgsm_beta_mode (0 = Eq. 5). */
 typedef struct {
     const float* pos;
     int32_t n;
     float kappa;
+    int32_t beta_mode;
 } dgsm_lights_t;
 
 /* Atlas description.  H and W even, >= 2; K >= 2; r1 > 0, and 0 < r0 < r1

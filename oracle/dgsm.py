@@ -58,10 +58,20 @@ def precision_matrix(scale, rot):
     return np.einsum("nij,nj,nkj->nik", R, 1.0 / (s * s), R)
 
 
-def absorption_amplitude(opacity, A, kappa=1.0):
-    """Eq. 5: beta_i = kappa tau*_i sqrt(tr(A_i)/3) / sqrt(2 pi), tau* = -ln(1 - alpha)."""
+def absorption_amplitude(opacity, A, kappa=1.0, beta="trace"):
+    """Opacity to absorption, tau* = -ln(1 - alpha):
+    "trace"    Eq. 5: beta_i = kappa tau*_i sqrt(tr(A_i)/3) / sqrt(2 pi)
+    "constant" beta_i = kappa tau*_i                        (ablation B, mapping 1)
+    "density"  beta_i = kappa tau*_i sqrt(det A_i) / (2 pi)^(3/2)
+               (ablation B, mappings 3 and 4: A is the precision here, so
+               sqrt(det A) = 1 / (s_x s_y s_z); the absorption then integrates
+               to kappa tau*_i over space)."""
     alpha = np.asarray(opacity, dtype=np.float64)
     tau_star = -np.log1p(-alpha)
+    if beta == "constant":
+        return kappa * tau_star
+    if beta == "density":
+        return kappa * tau_star * np.sqrt(np.linalg.det(A)) / (2.0 * np.pi) ** 1.5
     tr = np.trace(A, axis1=-2, axis2=-1)
     return kappa * tau_star * np.sqrt(tr / 3.0) / np.sqrt(2.0 * np.pi)
 
@@ -173,10 +183,10 @@ def shell_radii(K, spacing="geometric", r0=0.05, r1=8.0):
 # Build
 # ---------------------------------------------------------------------------
 
-def gaussian_terms(g, kappa=1.0):
+def gaussian_terms(g, kappa=1.0, beta="trace"):
     """(mean, A, beta) in float64 for a Gaussian set with .mean/.scale/.rot/.opacity."""
     A = precision_matrix(g.scale, g.rot)
-    beta = absorption_amplitude(g.opacity, A, kappa)
+    beta = absorption_amplitude(g.opacity, A, kappa, beta)
     return np.asarray(g.mean, dtype=np.float64), A, beta
 
 
@@ -201,9 +211,9 @@ def optical_depth(dirs, t, o_L, mean, A, beta, chunk=2048):
     return tau
 
 
-def build(light, gaussians, H, W, K, spacing="geometric", r0=0.05, r1=8.0, kappa=1.0):
+def build(light, gaussians, H, W, K, spacing="geometric", r0=0.05, r1=8.0, kappa=1.0, beta="trace"):
     """Transmittance atlas T[K, H, W] for one point light (Eqs. 2-4, Sec. 3.2)."""
-    mean, A, beta = gaussian_terms(gaussians, kappa)
+    mean, A, beta = gaussian_terms(gaussians, kappa, beta)
     dirs = texel_directions(H, W).reshape(-1, 3)
     t = shell_radii(K, spacing, r0, r1)
     tau = optical_depth(dirs, t, light, mean, A, beta)

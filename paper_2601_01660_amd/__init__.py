@@ -26,7 +26,10 @@ class _Gaussians(ctypes.Structure):
 
 
 class _Lights(ctypes.Structure):
-    _fields_ = [("pos", ctypes.c_void_p), ("n", ctypes.c_int32), ("kappa", ctypes.c_float)]
+    _fields_ = [("pos", ctypes.c_void_p), ("n", ctypes.c_int32), ("kappa", ctypes.c_float), ("beta_mode", ctypes.c_int32)]
+
+
+BETA_MODES = {"trace": 0, "constant": 1, "density": 2}   # dgsm_beta_mode
 
 
 class _AtlasDesc(ctypes.Structure):
@@ -229,7 +232,8 @@ def dgsm_build_workspace_size(atlas: Atlas, n_gauss: int, n_lights: int) -> int:
     return int(lib().dgsm_build_workspace_size(ctypes.byref(d), n_gauss, n_lights))
 
 
-def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0, out=None, workspace=None):
+def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0, out=None, workspace=None,
+               beta: str = "trace"):
     """Build T[L, K, H, W] (see dgsm_build in include/dgsm.h)."""
     lights = _dev(lights)
     L = int(lights.shape[0])
@@ -243,7 +247,7 @@ def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0,
         out = torch.empty((L, atlas.K, atlas.H, atlas.W), dtype=atlas.torch_dtype, device=lights.device)
     _cuda(out, "out")
     _cuda(workspace, "workspace")
-    lt = _Lights(lights.data_ptr(), L, kappa)
+    lt = _Lights(lights.data_ptr(), L, kappa, BETA_MODES[beta])
     gs = gaussians.struct()
     _check(lib().dgsm_build(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), _ptr(out), _ptr(workspace),
                             workspace.numel(), _stream()))
@@ -251,7 +255,7 @@ def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0,
 
 
 def dgsm_build_roi(lights, gaussians: GaussianSet, atlas: Atlas, receivers, box=None, kappa: float = 1.0, out=None,
-                   workspace=None):
+                   workspace=None, beta: str = "trace"):
     """Build T[L, K, H, W] restricted to the receivers' region (see dgsm_build_roi in
     include/dgsm.h); box = (cx, cy, half, zmin, zmax) or None (every receiver)."""
     lights = _dev(lights)
@@ -268,7 +272,7 @@ def dgsm_build_roi(lights, gaussians: GaussianSet, atlas: Atlas, receivers, box=
     _cuda(out, "out")
     _cuda(workspace, "workspace")
     bx = _RoiBox(*(box if box is not None else (0.0, 0.0, 0.0, 0.0, 0.0)))
-    lt = _Lights(lights.data_ptr(), L, kappa)
+    lt = _Lights(lights.data_ptr(), L, kappa, BETA_MODES[beta])
     gs = gaussians.struct()
     _check(lib().dgsm_build_roi(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), _ptr(receivers),
                                 int(receivers.shape[0]), ctypes.byref(bx), _ptr(out), _ptr(workspace),
@@ -276,12 +280,12 @@ def dgsm_build_roi(lights, gaussians: GaussianSet, atlas: Atlas, receivers, box=
     return out
 
 
-def dgsm_bin(lights, gaussians: GaussianSet, atlas: Atlas, workspace, kappa: float = 1.0):
+def dgsm_bin(lights, gaussians: GaussianSet, atlas: Atlas, workspace, kappa: float = 1.0, beta: str = "trace"):
     """First build phase: culling cones and supertile lists into ``workspace``."""
     lights = _dev(lights)
     _cuda(workspace, "workspace")
     d = atlas.struct()
-    lt = _Lights(lights.data_ptr(), int(lights.shape[0]), kappa)
+    lt = _Lights(lights.data_ptr(), int(lights.shape[0]), kappa, BETA_MODES[beta])
     gs = gaussians.struct()
     _check(lib().dgsm_bin(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), _ptr(workspace),
                           workspace.numel(), _stream()))
@@ -405,7 +409,7 @@ class Plan:
 
     def __init__(self, lights, atlas: Atlas, static: GaussianSet, n_dynamic: int, frames: int,
                  static_cache: bool = True, autotune: bool = True, tile_waves: int = 8, split_units: int = 0,
-                 kappa: float = 1.0):
+                 kappa: float = 1.0, beta: str = "trace"):
         lights = _dev(lights)
         self.L = int(lights.shape[0])
         self.atlas = atlas
@@ -413,7 +417,7 @@ class Plan:
         self.n_dynamic = int(n_dynamic)
         self.frames = int(frames)
         d = atlas.struct()
-        lt = _Lights(lights.data_ptr(), self.L, kappa)
+        lt = _Lights(lights.data_ptr(), self.L, kappa, BETA_MODES[beta])
         gs = static.struct()
         opts = _PlanOpts(self.frames, int(static_cache), int(autotune), int(tile_waves), int(split_units))
         h = ctypes.c_void_p()

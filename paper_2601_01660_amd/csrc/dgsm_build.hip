@@ -118,6 +118,7 @@ struct PrepArgs {
     int64_t n;
     const float* lights;   // device [L][3]
     float kappa;
+    int beta_mode;         // dgsm_beta_mode
     float eps;             // culling budget (0: no culling)
     int S;
     BuildLayout lay;
@@ -158,7 +159,11 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
         }
         const double alpha = a.opacity[i];
         const double tau_star = -log1p(-alpha);
-        const double amp = (double)a.kappa * tau_star * sqrt(tr / 3.0);   // beta sqrt(2 pi)
+        // beta sqrt(2 pi) (the line-integral scale of Eq. 3)
+        const double TWO_PI = 6.283185307179586;
+        double amp = (double)a.kappa * tau_star * sqrt(tr / 3.0);          // Eq. 5
+        if (a.beta_mode == DGSM_BETA_CONSTANT) amp = (double)a.kappa * tau_star * sqrt(TWO_PI);
+        else if (a.beta_mode == DGSM_BETA_DENSITY) amp = (double)a.kappa * tau_star / (TWO_PI * s[0] * s[1] * s[2]);
         r.bp = (float)(0.5 * amp);                                        // beta sqrt(pi/2)
         r.mx = (double)light[0] - (double)a.mean[3 * i];
         r.my = (double)light[1] - (double)a.mean[3 * i + 1];
@@ -179,7 +184,7 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
         W.rec[i] = r;
 
         // Culling cone.  Along any ray the contribution is at most
-        // U exp(-h^2 / (2 s_max^2)), U = kappa tau* sqrt(tr A / 3) s_max, with h
+        // U exp(-h^2 / (2 s_max^2)), U = beta sqrt(2 pi) s_max, with h
         // the distance from mu to the ray (D for rays pointing away).  So it is
         // below eps outside the cone sin(theta) <= (s_max / D) sqrt(2 ln(U / eps)).
         const double D = sqrt(r.mx * r.mx + r.my * r.my + r.mz * r.mz);
@@ -394,21 +399,30 @@ __global__ __launch_bounds__(256) void roi_mark_kernel(unsigned char* ws, BuildL
                                                        const float* __restrict__ pts, int64_t n, RoiBox box,
                                                        float lr0, float kscale) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
-    if (box.half > 0.f &&
-        !(fabsf(x - box.cx) <= box.half && fabsf(y - box.cy) <= box.half && z >= box.zmin && z <= box.zmax))
-        return;
+    bool in = i < n;
+    float x = 0.f, y = 0.f, z = 0.f;
+    if (in) {
+        x = pts[3 * i];
+        y = pts[3 * i + 1];
+        z = pts[3 * i + 2];
+        in = !(box.half > 0.f) ||
+             (fabsf(x - box.cx) <= box.half && fabsf(y - box.cy) <= box.half && z >= box.zmin && z <= box.zmax);
+    }
     const int l = blockIdx.y;
     const LightWs W = light_ws(ws, lay, l);
     const Cell c = query_cell(g, lr0, kscale, lights + 3 * l, x, y, z);
-    for (int d = 0; d < 4; ++d) {
-        int ii = c.i0 + (d >> 1), jj = c.j0 + (d & 1);
-        wrap_texel(ii, jj, g.H, g.W);
-        atomicOr(W.roi_mask + (ii >> 3) * g.TW + (jj >> 3), 1ull << ((ii & 7) * kTile + (jj & 7)));
+    if (in)
+        for (int d = 0; d < 4; ++d) {
+            int ii = c.i0 + (d >> 1), jj = c.j0 + (d & 1);
+            wrap_texel(ii, jj, g.H, g.W);
+            atomicOr(W.roi_mask + (ii >> 3) * g.TW + (jj >> 3), 1ull << ((ii & 7) * kTile + (jj & 7)));
+        }
+    // shell range: one atomic per wave (every receiver would hit the same two words)
+    const int kmn = wave_min(in ? c.k0 : g.K), kmx = wave_max(in ? c.k0 + 1 : -1);
+    if ((threadIdx.x % kWave) == 0 && kmn <= kmx) {
+        atomicMin(W.roi_k, kmn);
+        atomicMax(W.roi_k + 1, kmx);
     }
-    atomicMin(W.roi_k, c.k0);
-    atomicMax(W.roi_k + 1, c.k0 + 1);
 }
 
 // Tiles outside the region do no work: their hit counts are cleared so that
@@ -1149,7 +1163,7 @@ dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, 
                         float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st, bool cones) {
     if (cones && enqueue_cones(g, L, ws, st) != DGSM_OK) return DGSM_EHIP;
     if (gs.n > 0) {
-        PrepArgs pa{gs.mean, gs.scale, gs.rot, gs.opacity, gs.n, lights.pos, lights.kappa, cull_eps,
+        PrepArgs pa{gs.mean, gs.scale, gs.rot, gs.opacity, gs.n, lights.pos, lights.kappa, lights.beta_mode, cull_eps,
                     g.S, L, ws};
         preprocess_kernel<<<dim3(L.nb, lights.n), kPrepThreads, 0, st>>>(pa);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;

@@ -28,6 +28,7 @@ inline dgsm_status validate_desc(const dgsm_atlas_desc_t* d) {
 inline dgsm_status validate_lights(const dgsm_lights_t* l) {
     if (!l || !l->pos || l->n < 1) return DGSM_EINVAL;
     if (!(l->kappa >= 0.f)) return DGSM_EINVAL;
+    if (l->beta_mode < DGSM_BETA_TRACE || l->beta_mode > DGSM_BETA_DENSITY) return DGSM_EINVAL;
     return DGSM_OK;
 }
 

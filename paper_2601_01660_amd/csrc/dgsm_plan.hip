@@ -181,6 +181,7 @@ struct dgsm_plan_s {
     dgsm_atlas_desc_t desc;
     int L;
     float kappa;
+    int beta_mode;
     int64_t ns, nd, np;
     int frames;
     bool cache;
@@ -230,7 +231,7 @@ dgsm_gaussians_t set_of(const dgsm_plan p, int64_t off, int64_t n) {
 
 // Static part of a run: tau of the static set for every light.
 dgsm_status enqueue_static(dgsm_plan p, int tile_waves, int split_units, hipStream_t st) {
-    const dgsm_lights_t lt{p->lights, p->L, p->kappa};
+    const dgsm_lights_t lt{p->lights, p->L, p->kappa, p->beta_mode};
     const BuildLayout La = build_layout(p->g, p->ns, p->L);
     dgsm_status s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, 0, p->ns), st, false);
     if (s != DGSM_OK) return s;
@@ -250,7 +251,7 @@ dgsm_status enqueue_static(dgsm_plan p, int tile_waves, int split_units, hipStre
 // One frame: dynamic means, build (on top of the static tau in cache mode), query.
 dgsm_status enqueue_frame(dgsm_plan p, int f, const float* dyn_base, const float* translations, float* T_out,
                           int tile_waves, int split_units, hipStream_t st) {
-    const dgsm_lights_t lt{p->lights, p->L, p->kappa};
+    const dgsm_lights_t lt{p->lights, p->L, p->kappa, p->beta_mode};
     if (p->nd > 0) {
         const int64_t n3 = 3 * p->nd;
         translate_kernel<<<(unsigned)((n3 + 255) / 256), 256, 0, st>>>(dyn_base, p->nd, translations + 3 * f,
@@ -397,6 +398,7 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     p->desc = *desc;
     p->L = lights->n;
     p->kappa = lights->kappa;
+    p->beta_mode = lights->beta_mode;
     p->ns = static_set->n;
     p->nd = n_dynamic;
     p->np = np;

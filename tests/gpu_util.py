@@ -6,10 +6,10 @@ import paper_2601_01660_amd as P
 from oracle import dgsm as od
 
 
-def gpu_build(g, lights, spec, dtype="f32", cull_eps=1e-8, kappa=1.0):
+def gpu_build(g, lights, spec, dtype="f32", cull_eps=1e-8, kappa=1.0, beta="trace"):
     gs = P.GaussianSet.from_host(g)
     atlas = P.Atlas.from_spec(spec, dtype=dtype, cull_eps=cull_eps)
-    T = P.dgsm_build(torch.from_numpy(np.ascontiguousarray(lights, dtype=np.float32)), gs, atlas, kappa)
+    T = P.dgsm_build(torch.from_numpy(np.ascontiguousarray(lights, dtype=np.float32)), gs, atlas, kappa, beta=beta)
     torch.cuda.synchronize()
     return T, atlas
 

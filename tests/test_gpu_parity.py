@@ -303,3 +303,20 @@ def test_footprint_query_matches_oracle(cfg1, kind):
     err = np.abs(got[0].cpu().numpy() - ref).max()
     _report(f"footprint {kind}", err)
     assert err <= TOL
+
+
+@pytest.mark.parametrize("beta", ["constant", "density"])
+def test_beta_mappings_match_oracle(beta):
+    """Ablation B mappings: the build with each opacity-to-absorption mapping
+    against the oracle (small Gaussians make the density mapping strong)."""
+    U = _util()
+    rng = np.random.default_rng(17)
+    g = synth.random_gaussians(rng, rng.uniform(0.5, 2.5, (1500, 3)), 0.03)
+    spec = synth.AtlasSpec(24, 24, 12, "geometric")
+    light = np.zeros((1, 3), np.float32)
+    kappa = 0.05 if beta == "density" else 0.5
+    T, _ = U.gpu_build(g, light, spec, kappa=kappa, beta=beta)
+    ref = od.build(light[0], g, spec.H, spec.W, spec.K, spec.spacing, spec.r0, spec.r1, kappa=kappa, beta=beta)
+    err = np.abs(T[0].cpu().numpy().astype(np.float64) - ref).max()
+    _report(f"beta {beta} (min T {ref.min():.3f})", err)
+    assert ref.min() < 0.9 and err <= TOL

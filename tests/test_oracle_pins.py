@@ -474,3 +474,36 @@ def test_roi_box_keeps_only_receivers_inside():
     mb, kba, kbb = od.roi_region(light, rec, 16, 16, 8, box=(0.5, 0.5, 0.2, 1.0, 2.0))
     assert np.array_equal(m1, mb) and (k1a, k1b) == (kba, kbb)
     assert m1.sum() <= 4 and k1b == k1a + 1
+
+
+# ---------------------------------------------------------------------------
+# Opacity to absorption mappings (ablation B)
+# ---------------------------------------------------------------------------
+
+def test_beta_constant_mapping_is_kappa_tau():
+    rng = np.random.default_rng(2)
+    g = synth.random_gaussians(rng, rng.uniform(-1, 1, (50, 3)), 0.05)
+    A = od.precision_matrix(g.scale, g.rot)
+    b = od.absorption_amplitude(g.opacity, A, kappa=0.7, beta="constant")
+    assert np.allclose(b, -0.7 * np.log(1 - g.opacity.astype(np.float64)), rtol=1e-15, atol=0)
+
+
+def test_beta_density_mapping_integrates_to_kappa_tau():
+    """With the density mapping the absorption of one Gaussian integrates to
+    kappa tau* over space (a Riemann sum over a box of +-7 sigma)."""
+    g = synth.Gaussians(np.zeros((1, 3), np.float32), np.float32([[0.02, 0.05, 0.03]]),
+                        np.float32([[0.9, 0.1, -0.3, 0.2]]) / np.float32(np.linalg.norm([0.9, 0.1, -0.3, 0.2])),
+                        np.float32([0.6]))
+    mean, A, beta = od.gaussian_terms(g, kappa=1.3, beta="density")
+    n = 121
+    ax = np.linspace(-0.35, 0.35, n)
+    X = np.stack(np.meshgrid(ax, ax, ax, indexing="ij"), -1).reshape(-1, 3)
+    total = od.absorption(X, mean, A, beta).sum() * (ax[1] - ax[0]) ** 3
+    assert abs(total - 1.3 * -np.log(1 - 0.6)) < 1e-6
+
+
+def test_beta_trace_mapping_is_equation_5_for_isotropic():
+    s = 0.04
+    A = np.eye(3)[None] / s ** 2
+    b = od.absorption_amplitude(np.array([0.5]), A, beta="trace")
+    assert abs(b[0] - np.log(2) * (1 / s) / np.sqrt(2 * np.pi)) < 1e-12
