@@ -679,6 +679,7 @@ struct Counters {
     unsigned long long idle = 0;        // pairs of which no texel lane was active
     unsigned long long ramp_wave = 0;   // shell iterations of the wave (SIMD work of the ramp)
     unsigned long long pre = 0;         // idle pairs already rejected by the distance pre-test
+    int klo = 1 << 30, khi = -1;        // shells this lane added to (always tracked: partial-sum rows)
 };
 
 template <bool STATS, bool GEO>
@@ -750,6 +751,10 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
             len = max(min(kb, s.kmax), k0) - k0 + 1;
             ka = k0;
         }
+    }
+    if (len > 0) {
+        n.klo = min(n.klo, ka);
+        n.khi = max(n.khi, ka + len - 1);
     }
     const int maxlen = wave_max(len);
     if (maxlen <= 0) return;
@@ -1010,9 +1015,21 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     const int* list = W.lists + lb0;
     const ConstF4Ptr rec = (ConstF4Ptr)(const void*)W.rec;
     Counters n;
+    __shared__ int rows[2];                   // shells any wave added to: partial-sum rows to keep
+    if (tid == 0) {
+        rows[0] = K;
+        rows[1] = -1;
+    }
     __syncthreads();
 
     walk_hits<STATS, GEO>(words, ns, slice * NW + wave, nslice * NW, list, rec, st, n);
+    if (pidx >= 0) {
+        const int lo = wave_min(min(n.klo, K)), hi = wave_max(n.khi);
+        if (lane == 0 && lo <= hi) {
+            atomicMin(rows, lo);
+            atomicMax(rows + 1, hi);
+        }
+    }
 
     if (STATS) {
         const unsigned long long nvalid = __popcll(__ballot(st.valid));
@@ -1028,9 +1045,11 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
         }
     }
     __syncthreads();
-    if (pidx >= 0) {           // a slice of a split tile: leave the partial sums
+    if (pidx >= 0) {           // a slice of a split tile: leave its partial sums (rows it touched)
+        const int lo = rows[0], hi = rows[1];
         unsigned long long* dst = W.part + (size_t)pidx * K * kWave;
-        for (int q = tid; q < K * kWave; q += kWave * NW) dst[q] = inc[q];
+        for (int q = lo * kWave + tid; q < (hi + 1) * kWave; q += kWave * NW) dst[q] = inc[q];
+        if (tid == 0) W.prange[pidx] = make_int2(lo, hi);
         return;
     }
 
@@ -1062,10 +1081,12 @@ __global__ __launch_bounds__(kWave * kFinishWaves) void split_finish_kernel(Tile
 #pragma unroll
         for (int j = 0; j < kFinishGroup; ++j) v[j] = 0ull;
         for (int i = 0; i < q; ++i) {
+            const int2 r = W.prange[sp.y + i];        // rows slice i wrote
+            if (r.y < k0 || r.x >= k0 + n) continue;
             const unsigned long long* s0 = src + (size_t)i * slice + (size_t)k0 * kWave;
 #pragma unroll
             for (int j = 0; j < kFinishGroup; ++j)
-                if (j < n) v[j] += s0[(size_t)j * kWave];
+                if (j < n && k0 + j >= r.x && k0 + j <= r.y) v[j] += s0[(size_t)j * kWave];
         }
 #pragma unroll
         for (int j = 0; j < kFinishGroup; ++j)
@@ -1109,6 +1130,7 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
     L.splits = take((size_t)L.units_cap * sizeof(int2));
     L.nunits = take(4 * sizeof(int));
     L.part = take(2 * (size_t)L.units_cap * g.K * kWave * sizeof(unsigned long long));
+    L.prange = take(2 * (size_t)L.units_cap * sizeof(int2));
     L.roi_mask = take((size_t)g.ntiles * sizeof(unsigned long long));
     L.roi_k = take(2 * sizeof(int));
     L.light_stride = off;

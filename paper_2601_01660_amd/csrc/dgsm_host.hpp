@@ -49,7 +49,7 @@ struct BuildLayout {
     int units_cap;           // extra work units per light (tiles split over several blocks)
     // offsets inside a light slice
     size_t totals, lbase, rec, cone, mask, counts, lists, bits;
-    size_t hits, tinfo, units, splits, nunits, part, roi_mask, roi_k;
+    size_t hits, tinfo, units, splits, nunits, part, prange, roi_mask, roi_k;
     size_t total;            // bytes for all lights
 };
 
@@ -69,6 +69,7 @@ struct LightWs {
     int2* splits;      // [units_cap] split tiles: {tile, first partial}
     int* nunits;       // [4] {extra slices, split tiles, hits per slice, total hits}
     unsigned long long* part;   // [2 units_cap][K][64] fixed-point partial optical depths
+    int2* prange;               // [2 units_cap] shell rows [lo, hi] each partial holds (lo > hi: none)
     unsigned long long* roi_mask;   // [ntiles] receiver texels of each tile (bit = texel in the tile)
     int* roi_k;                     // [2] receiver shell range {k_min, k_max}
 };
@@ -82,6 +83,7 @@ __host__ __device__ inline LightWs light_ws(unsigned char* ws, const BuildLayout
                    reinterpret_cast<int*>(b + L.hits), reinterpret_cast<int4*>(b + L.tinfo),
                    reinterpret_cast<int4*>(b + L.units), reinterpret_cast<int2*>(b + L.splits),
                    reinterpret_cast<int*>(b + L.nunits), reinterpret_cast<unsigned long long*>(b + L.part),
+                   reinterpret_cast<int2*>(b + L.prange),
                    reinterpret_cast<unsigned long long*>(b + L.roi_mask), reinterpret_cast<int*>(b + L.roi_k)};
 }
 
