@@ -60,13 +60,16 @@ __global__ __launch_bounds__(64) void tile_cone_kernel(Geom g, float4* __restric
 
 // A supertile cone bounds the cones of its tiles: half-angle = max over tiles
 // of (angle to the tile axis + tile half-angle).
+// Group cones: group s of a grid of (gh x gw)-tile groups, ngx groups per row
+// (supertiles: gh = STH, gw = STW; quads: 2 x 2 tiles).
 __global__ __launch_bounds__(64) void super_cone_kernel(Geom g, const float4* __restrict__ tcone,
-                                                        float4* __restrict__ scone) {
+                                                        float4* __restrict__ scone, int ngroups, int ngx, int gh,
+                                                        int gw) {
     const int s = blockIdx.x * 64 + threadIdx.x;
-    if (s >= g.S) return;
-    const int sy = s / g.SGW, sx = s - sy * g.SGW;
-    const int ty0 = sy * g.STH, ty1 = min(ty0 + g.STH, g.TH);
-    const int tx0 = sx * g.STW, tx1 = min(tx0 + g.STW, g.TW);
+    if (s >= ngroups) return;
+    const int sy = s / ngx, sx = s - sy * ngx;
+    const int ty0 = sy * gh, ty1 = min(ty0 + gh, g.TH);
+    const int tx0 = sx * gw, tx1 = min(tx0 + gw, g.TW);
     double ax = 0, ay = 0, az = 0;
     for (int ty = ty0; ty < ty1; ++ty)
         for (int tx = tx0; tx < tx1; ++tx) {
@@ -317,6 +320,8 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
     __shared__ int stot[kMaxSuper];
     const LightWs W = light_ws(ws, lay, blockIdx.y);
     const float4* tcone = reinterpret_cast<const float4*>(ws + lay.tcone);
+    const float4* qcone = reinterpret_cast<const float4*>(ws + lay.qcone);
+    const int nqx = (g.TW + 1) / 2;
     const int tid = threadIdx.x, lane = tid % kWave;
     for (int s = tid; s <= g.S; s += 256) {
         sbase[s] = W.lbase[s];
@@ -334,6 +339,8 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
     int s_cur = -1, cnt = 0;
     SuperSpan sp_cur{0, 0, 0, 0};
     float4 tc = make_float4(0.f, 0.f, 1.f, -1.f);   // lane t: cone of tile t of the current supertile
+    float4 qc = make_float4(0.f, 0.f, 1.f, -1.f);   // lane q: cone of 2x2-tile quad q of it
+    int q0y = 0, q0x = 0, nqy_s = 0, nqx_s = 0;
     for (int c = cbeg; c < cend; ++c) {
         // supertile of this chunk: the last s with sbase[s] <= 64 c
         int lo = 0, hi = g.S - 1;
@@ -351,6 +358,12 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
             tc = lane < sp_cur.nty * sp_cur.ntx
                      ? tcone[(sp_cur.ty0 + lane / sp_cur.ntx) * g.TW + sp_cur.tx0 + lane % sp_cur.ntx]
                      : make_float4(0.f, 0.f, 1.f, -1.f);
+            q0y = sp_cur.ty0 / 2;                      // supertile origins are even (8-tile multiples)
+            q0x = sp_cur.tx0 / 2;
+            nqy_s = (sp_cur.nty + 1) / 2;
+            nqx_s = (sp_cur.ntx + 1) / 2;
+            qc = lane < nqy_s * nqx_s ? qcone[(q0y + lane / nqx_s) * nqx + q0x + lane % nqx_s]
+                                      : make_float4(0.f, 0.f, 1.f, -1.f);
         }
         const int e = 64 * c + lane;
         float4 cone = make_float4(0.f, 0.f, 1.f, -1.f);
@@ -358,13 +371,25 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
         const SuperSpan sp = sp_cur;
         const int nt = sp.nty * sp.ntx;
         uint64_t mine = 0;
-        for (int t = 0; t < nt; ++t) {
-            const float4 b = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.x), t)),
-                                         __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.y), t)),
-                                         __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.z), t)),
-                                         __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.w), t)));
-            const uint64_t bal = __ballot(cones_touch(cone, b));
-            if (lane == t) mine = bal;
+        // quads first: the tiles of a quad no lane's cone reaches are skipped
+        for (int q = 0; q < nqy_s * nqx_s; ++q) {
+            const float4 bq = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc.x), q)),
+                                          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc.y), q)),
+                                          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc.z), q)),
+                                          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc.w), q)));
+            if (__ballot(cones_touch(cone, bq)) == 0ull) continue;
+            const int qy = q / nqx_s, qx = q - qy * nqx_s;
+            for (int d = 0; d < 4; ++d) {
+                const int ly = 2 * qy + (d >> 1), lx = 2 * qx + (d & 1);   // tile inside the supertile
+                if (ly >= sp.nty || lx >= sp.ntx) continue;
+                const int t = ly * sp.ntx + lx;
+                const float4 b = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.x), t)),
+                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.y), t)),
+                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.z), t)),
+                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.w), t)));
+                const uint64_t bal = __ballot(cones_touch(cone, b));
+                if (lane == t) mine = bal;
+            }
         }
         const int c0 = sbase[s] / 64, ns = (sbase[s + 1] - sbase[s]) / 64;
         if (lane < nt) {
@@ -1113,6 +1138,7 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
     L.cap = (size_t)n * g.S + 64 * (size_t)g.S;
     L.tcone = take((size_t)g.ntiles * sizeof(float4));
     L.scone = take((size_t)kMaxSuper * sizeof(float4));
+    L.qcone = take((size_t)((g.TH + 1) / 2) * ((g.TW + 1) / 2) * sizeof(float4));
     L.light0 = off;
     off = 0;
     L.totals = take((size_t)kMaxSuper * sizeof(int));
@@ -1175,9 +1201,13 @@ static hipError_t launch_tile_nw(const TileArgs& ta, int n_lights, int nw, hipSt
 dgsm_status enqueue_cones(const Geom& g, const BuildLayout& L, unsigned char* ws, hipStream_t st) {
     float4* tcone = reinterpret_cast<float4*>(ws + L.tcone);
     float4* scone = reinterpret_cast<float4*>(ws + L.scone);
+    float4* qcone = reinterpret_cast<float4*>(ws + L.qcone);
     tile_cone_kernel<<<(g.ntiles + 63) / 64, 64, 0, st>>>(g, tcone);
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
-    super_cone_kernel<<<(g.S + 63) / 64, 64, 0, st>>>(g, tcone, scone);
+    super_cone_kernel<<<(g.S + 63) / 64, 64, 0, st>>>(g, tcone, scone, g.S, g.SGW, g.STH, g.STW);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    const int nqx = (g.TW + 1) / 2, nq = ((g.TH + 1) / 2) * nqx;
+    super_cone_kernel<<<(nq + 63) / 64, 64, 0, st>>>(g, tcone, qcone, nq, nqx, 2, 2);
     return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
 

@@ -44,6 +44,7 @@ struct BuildLayout {
     int nb;                  // preprocess blocks (256 Gaussians each)
     size_t cap;              // list / bitmap capacity per light (entries)
     size_t tcone, scone;     // absolute offsets: tile cones [ntiles], supertile cones [kMaxSuper]
+    size_t qcone;            // absolute offset: cones of 2x2-tile quads [ceil(TH/2) * ceil(TW/2)]
     size_t light0;           // absolute offset of light 0's slice
     size_t light_stride;     // bytes per light slice
     int units_cap;           // extra work units per light (tiles split over several blocks)
