@@ -118,6 +118,20 @@ __device__ inline float atlas_at(const InT* tab, const Geom& g, float u, float v
     return (1.f - fk) * ((1.f - fi) * a0 + fi * b0) + fk * ((1.f - fi) * a1 + fi * b1);
 }
 
+// Fallback region of (u, v, rho) (the floor texel's 8x8 tile and 8-shell
+// group, as atlas_at returns it), without reading the atlas.
+__device__ inline int atlas_region(const Geom& g, float u, float v, float rho) {
+    const float jf = fminf(fmaxf((u + 1.f) * (0.5f * (float)g.W) - 0.5f, -0.5f), (float)g.W - 0.5f);
+    const float if_ = fminf(fmaxf((v + 1.f) * (0.5f * (float)g.H) - 0.5f, -0.5f), (float)g.H - 0.5f);
+    float kf = g.spacing == DGSM_SHELLS_GEOMETRIC ? 0.5f * (rho + 1.f) * (float)(g.K - 1)
+                                                  : 0.5f * (rho + 1.f) * (float)g.K - 0.5f;
+    kf = fminf(fmaxf(kf, 0.f), (float)(g.K - 1));
+    const int j0 = (int)floorf(jf), i0 = (int)floorf(if_);
+    const int k0 = min((int)kf, g.K - 2);
+    const int ic = min(max(i0, 0), g.H - 1), jc = min(max(j0, 0), g.W - 1);
+    return (k0 / 8) * g.ntiles + (ic / kTile) * g.TW + jc / kTile;
+}
+
 __device__ inline uint32_t pcg_hash(uint32_t x) {
     // PCG-derived integer hash (Jarzynski and Olano, "Hash Functions for GPU
     // Rendering", JCGT 2020)
@@ -353,6 +367,149 @@ __global__ __launch_bounds__(kWave * NWV) void fwd_kernel(FwdArgs a) {
                 a.T[(size_t)light * a.n + row] = t;
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Inference with the weights held in registers.  Wave w of kIW owns output
+// columns [32w, 32w + 32) of every layer: the B fragments of its two 16-column
+// MFMA tiles stay in VGPRs for the whole kernel, the activations of kIRB
+// 16-row blocks go through LDS between layers, and every A fragment read from
+// LDS feeds two MFMAs.  The atlas is read only for rows whose fallback region
+// is flagged.
+// ---------------------------------------------------------------------------
+constexpr int kIW = 4;      // waves per inference block
+constexpr int kIRB = 2;     // 16-row blocks per iteration
+constexpr int kIRows = kIRB * kRows;
+
+__global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
+    __shared__ bf16x8 act[2][kIRB][kRows * 16];   // [buffer][row block][row, chunk] (swizzled)
+    __shared__ float zpart[kIRows][kIW];
+    __shared__ float4 rin[kIRows];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int light = blockIdx.y;
+    const float* P = a.params + (size_t)light * kNParams;
+    const __bf16* Wg = a.wb + (size_t)light * 4 * kH * kH;
+    const int lr = lane % 16, lg = lane / 16;
+    // this wave's weights: layer l, column tile j (columns 16 (2 wave + j) ..), k-step kk
+    bf16x8 B[4][2][4];
+    float bias[4][2], w4[2];
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = 16 * (2 * wave + j) + lr;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                B[l][j][kk] = *reinterpret_cast<const bf16x8*>(Wg + (size_t)l * kH * kH + (size_t)col * kH + 32 * kk +
+                                                               8 * lg);
+            bias[l][j] = P[l * kLayer + kH * kH + col];
+        }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) w4[j] = P[kOffW4 + 16 * (2 * wave + j) + lr];
+    const float b4 = P[kOffB4];
+    const float fscale = __log2f(0.25f * (float)a.g.W) / 15.f;
+    const int64_t ntile = (a.n + kIRows - 1) / kIRows;
+    const size_t nreg = (size_t)((a.g.K + 7) / 8) * a.g.ntiles;
+    const size_t tsz = (size_t)a.g.K * a.g.H * a.g.W;
+
+    for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
+        const int64_t row0 = t * kIRows;
+        if (tid < kIRows) {
+            float4 in = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (row0 + tid < a.n) {
+                const int64_t rr = row0 + tid;
+                float r;
+                encode_point(a.points[3 * rr], a.points[3 * rr + 1], a.points[3 * rr + 2], a.lights + 3 * light,
+                             a.g, in.x, in.y, in.z, r);
+            }
+            rin[tid] = in;
+        }
+        __syncthreads();
+        // features: thread -> row tid / 8, chunks 2 (tid % 8) and 2 (tid % 8) + 1
+        {
+            const int row = tid / 8, c0 = 2 * (tid % 8);
+            const float4 in = rin[row];
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+                const int c = c0 + cc;
+                bf16x8 ch;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) ch[e] = to_bf16(feature(8 * c + e, in.x, in.y, in.z, fscale));
+                act[0][row / kRows][swz(row % kRows, c)] = ch;
+            }
+        }
+        __syncthreads();
+        f32x4 acc[kIRB][2];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int cur = l & 1;
+#pragma unroll
+            for (int rb = 0; rb < kIRB; ++rb)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[rb][j] = f32x4{bias[l][j], bias[l][j], bias[l][j], bias[l][j]};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                for (int rb = 0; rb < kIRB; ++rb) {
+                    const bf16x8 av = act[cur][rb][swz(lr, lg + 4 * kk)];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) acc[rb][j] = mfma(av, B[l][j][kk], acc[rb][j]);
+                }
+#pragma unroll
+            for (int rb = 0; rb < kIRB; ++rb)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[rb][j][r] = fmaxf(acc[rb][j][r], 0.f);
+            if (l < 3) {
+                __bf16* nxt = reinterpret_cast<__bf16*>(&act[cur ^ 1][0][0]);
+#pragma unroll
+                for (int rb = 0; rb < kIRB; ++rb)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int col = 16 * (2 * wave + j) + lr;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            nxt[(size_t)rb * kRows * 16 * 8 + swz(4 * lg + r, col / 8) * 8 + (col % 8)] =
+                                to_bf16(acc[rb][j][r]);
+                    }
+                __syncthreads();
+            }
+        }
+        // output layer: this wave's share of z = w4 . h4 for each row, summed over waves in LDS
+#pragma unroll
+        for (int rb = 0; rb < kIRB; ++rb) {
+            float zp[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) zp[r] = w4[0] * acc[rb][0][r] + w4[1] * acc[rb][1][r];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                for (int o = 1; o < 16; o <<= 1) zp[r] += __shfl_xor(zp[r], o, kWave);
+            if (lr == 0)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) zpart[rb * kRows + 4 * lg + r][wave] = zp[r];
+        }
+        __syncthreads();
+        if (tid < kIRows && row0 + tid < a.n) {
+            const int64_t row = row0 + tid;
+            float z = b4;
+#pragma unroll
+            for (int w = 0; w < kIW; ++w) z += zpart[tid][w];
+            float T = 1.f / (1.f + __expf(z));
+            if (a.mask) {
+                const float4 in = rin[tid];
+                if (a.mask[light * nreg + atlas_region(a.g, in.x, in.y, in.z)]) {
+                    int region;
+                    T = a.atlas_f16 ? atlas_at(reinterpret_cast<const __half*>(a.atlas) + light * tsz, a.g, in.x,
+                                               in.y, in.z, region)
+                                    : atlas_at(reinterpret_cast<const float*>(a.atlas) + light * tsz, a.g, in.x,
+                                               in.y, in.z, region);
+                }
+            }
+            a.T[(size_t)light * a.n + row] = T;
+        }
+        __syncthreads();
     }
 }
 
@@ -784,7 +941,6 @@ extern "C" dgsm_status dgsm_mlp_infer(const float* params, const dgsm_lights_t* 
     FwdArgs f{};
     f.g = geom_of(desc); f.params = params; f.wb = wb; f.n = P; f.points = points; f.lights = lights->pos;
     f.atlas = mask ? atlas : nullptr; f.mask = mask; f.T = T; f.atlas_f16 = desc->dtype == DGSM_F16;
-    fwd_kernel<kInfer, kInferWaves><<<dim3(grid_rows(P, kRows * kInferWaves), lights->n), kWave * kInferWaves,
-                                      kInferSmem, s>>>(f);
+    infer_kernel<<<dim3(grid_rows(P, kIRows), lights->n), kWave * kIW, 0, s>>>(f);
     return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }

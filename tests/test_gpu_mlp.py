@@ -136,3 +136,42 @@ def test_surrogate_gain_over_equal_byte_atlas():
           f"(full 16 MiB atlas {e_big:.3e}); max {np.abs(q_net - exact).max():.3e} vs "
           f"{np.abs(q_small - exact).max():.3e}", flush=True)
     assert e_net < e_small
+
+
+def test_inference_two_lights_with_fallback_mask():
+    """Several lights (one parameter set each) and a fallback mask: flagged
+    regions return the trilinear atlas value, the rest the network."""
+    import paper_2601_01660_amd as P
+    from oracle import dgsm as od
+    H = W = 32
+    K = 16
+    atlas = P.Atlas(H, W, K)
+    rng = np.random.default_rng(21)
+    g = synth.random_gaussians(rng, rng.uniform(-2, 2, (200, 3)), 0.2)
+    lights = np.array([[0.0, 0.0, 0.0], [0.5, -0.4, 0.8]], np.float32)
+    table = P.dgsm_build(torch.from_numpy(lights), P.GaussianSet.from_host(g), atlas)
+    flat = np.stack([_params(31), _params(32)])
+    ntiles = (H // 8) * (W // 8)
+    nreg = ((K + 7) // 8) * ntiles
+    mask = (rng.uniform(size=(2, nreg)) < 0.4).astype(np.uint8)
+    pts = rng.uniform(-3, 3, (3001, 3)).astype(np.float32)
+    T = P.mlp_infer(torch.from_numpy(flat), torch.from_numpy(lights), atlas, torch.from_numpy(pts),
+                    table=table, mask=torch.from_numpy(mask).cuda()).cpu().numpy()
+    tab = table.cpu().numpy().astype(np.float64)
+    bad = 0
+    for l in range(2):
+        u, v, rho = om.encode_points(pts, lights[l], 0.05, 8.0)
+        net, _ = om.forward(flat[l], om.features(u, v, rho, W), bf16_emulation=True)
+        at = od.query(tab[l], lights[l], pts)
+        jf = np.clip((u + 1) * W / 2 - 0.5, -0.5, W - 0.5)
+        i_f = np.clip((v + 1) * H / 2 - 0.5, -0.5, H - 0.5)
+        k0 = np.minimum(np.floor(np.clip((rho + 1) / 2 * (K - 1), 0, K - 1)), K - 2).astype(int)
+        ic = np.clip(np.floor(i_f).astype(int), 0, H - 1)
+        jc = np.clip(np.floor(jf).astype(int), 0, W - 1)
+        region = (k0 // 8) * ntiles + (ic // 8) * (W // 8) + jc // 8
+        ref = np.where(mask[l][region] != 0, at, net)
+        err = np.abs(T[l] - ref)
+        bad += int((err > 2e-3).sum())
+        print(f"[mlp] light {l}: flagged points {int((mask[l][region] != 0).sum())}, "
+              f"median |dT| {np.median(err):.2e}", flush=True)
+    assert bad <= 0.005 * 2 * len(pts)

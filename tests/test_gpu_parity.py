@@ -320,3 +320,35 @@ def test_beta_mappings_match_oracle(beta):
     err = np.abs(T[0].cpu().numpy().astype(np.float64) - ref).max()
     _report(f"beta {beta} (min T {ref.min():.3f})", err)
     assert ref.min() < 0.9 and err <= TOL
+
+
+def test_maximum_shell_count():
+    """K = 256 (the largest supported): four shell radii per lane of the shell
+    table, LDS accumulators of 128 KiB per tile, long erf ramps."""
+    U = _util()
+    rng = np.random.default_rng(29)
+    g = synth.random_gaussians(rng, rng.uniform(-1.5, 1.5, (400, 3)) + [0, 0, 1.0], 0.08)
+    lights = np.array([[0.1, 0.0, -0.2]], np.float32)
+    spec = synth.AtlasSpec(16, 16, 256, r0=0.05, r1=4.0)
+    T, _ = U.gpu_build(g, lights, spec)
+    ref = od.build(lights[0], g, spec.H, spec.W, spec.K, spec.spacing, spec.r0, spec.r1)
+    err = np.abs(T[0].cpu().numpy() - ref).max()
+    _report("K = 256", err)
+    assert err <= TOL
+
+
+def test_maximum_atlas_side_sampled():
+    """A 1024 x 1024 atlas (the largest side) with few Gaussians: sampled texels
+    against the oracle, and T = 1 far from every Gaussian."""
+    U = _util()
+    c = synth.cfg1(400)
+    spec = synth.AtlasSpec(1024, 1024, 8)
+    T, _ = U.gpu_build(c["gaussians"], c["lights"], spec)
+    i, j = U.sample_texels(c["gaussians"], c["lights"][0], 1024, 1024, 40, seed=3)
+    ref = od.build_texels(c["lights"][0], c["gaussians"], i, j, 8, H=1024, W=1024)
+    got = T[0].cpu().numpy()[:, i, j].T.astype(np.float64)
+    err = np.abs(got - ref).max()
+    _report("1024 x 1024 sampled", err)
+    assert err <= TOL
+    # directions pointing away from the Gaussians' octant see nothing
+    assert torch.all(T[0, :, 1023, 1023] == 1.0) and torch.all(T[0, :, 0, 0] == 1.0)
