@@ -758,7 +758,7 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     const float z = __builtin_amdgcn_sqrtf(fmaxf(0.69314718f * __builtin_amdgcn_logf(P0 * (1.f / kRampEps)), 0.34f));
     const float xs = -sa * ts;                              // erf argument at t = 0
     float Ep = -1.f;
-    if (xs > -z) Ep = erf_nr(xs);
+    if (xs > -z) Ep = erf_as(xs);
     // Each lane walks its own ramp shells [ka, ka + len): the first shell past
     // the ramp start carries everything from t = 0 up to it, the last one (at
     // or past the ramp end) everything up to the saturated tail.
@@ -789,18 +789,19 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
         n.ramp += (unsigned long long)sum;
         n.ramp_wave += (unsigned long long)maxlen;
     }
-    double tk = s.shells[ka];
+    // erf argument at shell k: sqrt(a/2) (t_k - t*), with t* = t_e - corr kept in FP64
+    const double tsd = te - (double)corr;
+    const int klast = s.K - 1 - ka;                  // table index stays in range past this lane's end
     unsigned long long* dst = s.inc + ka * kWave + s.lane;
     for (int j = 0; j < maxlen; ++j) {
-        const float x = sa * ((float)(tk - te) + corr);
-        const float Ek = erf_nr(x);
+        const float x = sa * (float)(s.shells[ka + min(j, klast)] - tsd);
+        const float Ek = erf_as(x);
         const float E = Ek > Ep ? Ek : Ep;           // keep the increments non-negative
         const float dI = P0 * (E - Ep);
         Ep = E;
         if (j < len && dI > 0.f)
             __hip_atomic_fetch_add(dst, to_fixed(dI), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         dst += kWave;
-        tk = GEO ? tk * s.ratio : tk + s.ratio;
     }
 }
 

@@ -153,25 +153,20 @@ extern "C" __device__ int __ockl_wfred_max_i32(int);
 __device__ inline int wave_min(int v) { return __ockl_wfred_min_i32(v); }
 __device__ inline int wave_max(int v) { return __ockl_wfred_max_i32(v); }
 
-// erf(x) from the Chebyshev fit of erfc of Numerical Recipes (Press et al.,
-// 2nd ed., Sec. 6.2, "erfcc"): erfc(z) = t exp(-z^2 + P(t)), t = 1/(1 + z/2),
-// fractional error below 1.2e-7 for z >= 0.  One branch-free evaluation: a
-// reciprocal, a degree-9 Horner chain and an exponential.  Absolute error of
-// the returned erf is below 2e-7 everywhere and it saturates to +-1 exactly.
-__device__ inline float erf_nr(float x) {
+// erf(x) by the rational approximation of Abramowitz and Stegun, Handbook of
+// Mathematical Functions, 7.1.26 (after Hastings): for z = |x| >= 0,
+// erf(z) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-z^2),
+// t = 1 / (1 + p z); absolute error below 1.5e-7.  Branch-free: a reciprocal,
+// a degree-5 Horner chain and an exponential; saturates to +-1 exactly.
+__device__ inline float erf_as(float x) {
     const float z = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, z, 1.f));
-    float p = 0.17087277f;
-    p = fmaf(t, p, -0.82215223f);
-    p = fmaf(t, p, 1.48851587f);
-    p = fmaf(t, p, -1.13520398f);
-    p = fmaf(t, p, 0.27886807f);
-    p = fmaf(t, p, -0.18628806f);
-    p = fmaf(t, p, 0.09678418f);
-    p = fmaf(t, p, 0.37409196f);
-    p = fmaf(t, p, 1.00002368f);
-    p = fmaf(t, p, -1.26551223f);
-    const float ec = t * __expf(fmaf(-z, z, p));
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, z, 1.f));
+    float p = 1.061405429f;
+    p = fmaf(t, p, -1.453152027f);
+    p = fmaf(t, p, 1.421413741f);
+    p = fmaf(t, p, -0.284496736f);
+    p = fmaf(t, p, 0.254829592f);
+    const float ec = t * p * __expf(-z * z);
     return copysignf(1.f - ec, x);
 }
 

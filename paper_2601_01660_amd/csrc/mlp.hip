@@ -59,6 +59,17 @@ __device__ inline float feature(int f, float u, float v, float rho, float fscale
     return (rem & 1) ? hw_cos(fr * x) : hw_sin(fr * x);
 }
 
+// Feature f (0..127) with the frequencies given (fr[i] = pi (W/4)^(i/15)).
+__device__ inline float feature_fr(int f, float u, float v, float rho, const float* fr) {
+    if (f == 0) return u;
+    if (f == 1) return v;
+    if (f == 2) return rho;
+    if (f >= kDin) return 0.f;
+    const int q = f - 3, i = q / 6, rem = q - 6 * i;
+    const float x = rem < 2 ? u : rem < 4 ? v : rho;
+    return (rem & 1) ? hw_cos(fr[i] * x) : hw_sin(fr[i] * x);
+}
+
 // Octahedral code and radius coordinate of a point seen from a light.
 __device__ inline void encode_point(float x, float y, float z, const float* o, const Geom& g, float& u,
                                     float& v, float& rho, float& r) {
@@ -386,6 +397,7 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
     __shared__ bf16x8 act[2][kIRB][kRows * 16];   // [buffer][row block][row, chunk] (swizzled)
     __shared__ float zpart[kIRows][kIW];
     __shared__ float4 rin[kIRows];
+    __shared__ float freq[kNF];
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const int light = blockIdx.y;
     const float* P = a.params + (size_t)light * kNParams;
@@ -409,22 +421,31 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
     for (int j = 0; j < 2; ++j) w4[j] = P[kOffW4 + 16 * (2 * wave + j) + lr];
     const float b4 = P[kOffB4];
     const float fscale = __log2f(0.25f * (float)a.g.W) / 15.f;
+    if (tid < kNF) freq[tid] = 3.14159265358979324f * exp2f(fscale * (float)tid);   // pi (W/4)^(i/15)
     const int64_t ntile = (a.n + kIRows - 1) / kIRows;
-    const size_t nreg = (size_t)((a.g.K + 7) / 8) * a.g.ntiles;
-    const size_t tsz = (size_t)a.g.K * a.g.H * a.g.W;
+    // the next tile's points are loaded one iteration ahead (lanes tid < kIRows)
+    float px = 0.f, py = 0.f, pz = 0.f;
+    auto load_pt = [&](int64_t tt) {
+        const int64_t rr = tt * kIRows + tid;
+        if (tid < kIRows && tt < ntile && rr < a.n) {
+            px = a.points[3 * rr];
+            py = a.points[3 * rr + 1];
+            pz = a.points[3 * rr + 2];
+        }
+    };
+    load_pt(blockIdx.x);
 
     for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
         const int64_t row0 = t * kIRows;
         if (tid < kIRows) {
             float4 in = make_float4(0.f, 0.f, 0.f, 0.f);
             if (row0 + tid < a.n) {
-                const int64_t rr = row0 + tid;
                 float r;
-                encode_point(a.points[3 * rr], a.points[3 * rr + 1], a.points[3 * rr + 2], a.lights + 3 * light,
-                             a.g, in.x, in.y, in.z, r);
+                encode_point(px, py, pz, a.lights + 3 * light, a.g, in.x, in.y, in.z, r);
             }
             rin[tid] = in;
         }
+        load_pt(t + gridDim.x);
         __syncthreads();
         // features: thread -> row tid / 8, chunks 2 (tid % 8) and 2 (tid % 8) + 1
         {
@@ -435,7 +456,7 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
                 const int c = c0 + cc;
                 bf16x8 ch;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) ch[e] = to_bf16(feature(8 * c + e, in.x, in.y, in.z, fscale));
+                for (int e = 0; e < 8; ++e) ch[e] = to_bf16(feature_fr(8 * c + e, in.x, in.y, in.z, freq));
                 act[0][row / kRows][swz(row % kRows, c)] = ch;
             }
         }
@@ -492,25 +513,30 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
         }
         __syncthreads();
         if (tid < kIRows && row0 + tid < a.n) {
-            const int64_t row = row0 + tid;
             float z = b4;
 #pragma unroll
             for (int w = 0; w < kIW; ++w) z += zpart[tid][w];
-            float T = 1.f / (1.f + __expf(z));
-            if (a.mask) {
-                const float4 in = rin[tid];
-                if (a.mask[light * nreg + atlas_region(a.g, in.x, in.y, in.z)]) {
-                    int region;
-                    T = a.atlas_f16 ? atlas_at(reinterpret_cast<const __half*>(a.atlas) + light * tsz, a.g, in.x,
-                                               in.y, in.z, region)
-                                    : atlas_at(reinterpret_cast<const float*>(a.atlas) + light * tsz, a.g, in.x,
-                                               in.y, in.z, region);
-                }
-            }
-            a.T[(size_t)light * a.n + row] = T;
+            a.T[(size_t)light * a.n + row0 + tid] = 1.f / (1.f + __expf(z));
         }
         __syncthreads();
     }
+}
+
+// Atlas fallback after inference: points whose region is flagged take the
+// trilinear atlas value (one thread per (point, light); the atlas is read
+// only for flagged points).
+template <typename InT>
+__global__ __launch_bounds__(256) void fallback_kernel(FwdArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.n) return;
+    const int light = blockIdx.y;
+    float u, v, rho, r;
+    encode_point(a.points[3 * p], a.points[3 * p + 1], a.points[3 * p + 2], a.lights + 3 * light, a.g, u, v, rho, r);
+    const size_t nreg = (size_t)((a.g.K + 7) / 8) * a.g.ntiles;
+    if (!a.mask[light * nreg + atlas_region(a.g, u, v, rho)]) return;
+    const size_t tsz = (size_t)a.g.K * a.g.H * a.g.W;
+    int region;
+    a.T[(size_t)light * a.n + p] = atlas_at(reinterpret_cast<const InT*>(a.atlas) + light * tsz, a.g, u, v, rho, region);
 }
 
 // ---------------------------------------------------------------------------
@@ -942,5 +968,13 @@ extern "C" dgsm_status dgsm_mlp_infer(const float* params, const dgsm_lights_t* 
     f.g = geom_of(desc); f.params = params; f.wb = wb; f.n = P; f.points = points; f.lights = lights->pos;
     f.atlas = mask ? atlas : nullptr; f.mask = mask; f.T = T; f.atlas_f16 = desc->dtype == DGSM_F16;
     infer_kernel<<<dim3(grid_rows(P, kIRows), lights->n), kWave * kIW, 0, s>>>(f);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    if (mask) {
+        const dim3 grid((unsigned)((P + 255) / 256), lights->n);
+        if (f.atlas_f16)
+            fallback_kernel<__half><<<grid, 256, 0, s>>>(f);
+        else
+            fallback_kernel<float><<<grid, 256, 0, s>>>(f);
+    }
     return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
