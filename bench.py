@@ -289,6 +289,16 @@ def main():
     del ws_r, roi_t, full_t
     torch.cuda.empty_cache()
     log(f"receiver region around the avatar: {roi}")
+
+    # ---- approximate HDRI probe (Sec. 3.4): ridge fit from a 6 x 128^2 cube-map render --------
+    Dc, wc = synth.cubemap_directions(128)
+    Yc = np.random.default_rng(9).uniform(0.0, 2.0, (Dc.shape[0], 3))
+    Dc, wc, Yc = (torch.from_numpy(a.astype(np.float32)).to(dev) for a in (Dc, wc, Yc))
+    probe_out = P.dgsm_probe_fit(Yc, Dc, wc, 16, 1e-3)
+    torch.cuda.synchronize()
+    probe = {"samples": int(wc.numel()), "Kp": 16,
+             "ms": round(timed(lambda: P.dgsm_probe_fit(Yc, Dc, wc, 16, 1e-3, out=probe_out), 10), 4)}
+    log(f"probe fit: {probe}")
     torch.cuda.empty_cache()
 
     # ---- batched plan: static cache + captured graph (the headline) -------------------------
@@ -342,7 +352,7 @@ def main():
            "comparison_ms_per_frame": {"batched_graph_static_cache": round(ms_frame, 4),
                                        "batched_graph_no_cache": round(ms_nocache / F, 4),
                                        "plain_per_frame_launches": round(ms_plain / F, 4)},
-           "roofline": roofline, "footprint_query": footprint, "roi_build": roi}
+           "roofline": roofline, "footprint_query": footprint, "roi_build": roi, "probe_fit": probe}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(P, torch, np, dev, lights, atlas, static_set, dyn_set, tr, N, L, spec,
                                          args.mlp_steps, timed)

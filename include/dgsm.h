@@ -385,6 +385,26 @@ dgsm_status dgsm_mlp_infer(const float* params, const dgsm_lights_t* lights, con
                            const void* atlas, const unsigned char* mask, const float* points, int64_t P, float* T,
                            void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * dgsm_probe_fit - SH coefficients of an approximate environment probe by
+ * weighted ridge least squares (Sec. 3.4):
+ *   A = argmin ||W^(1/2) (B A - Y)||_F^2 + lambda ||A||_F^2,
+ *   (B^T W B + lambda I) A = B^T W Y,
+ * B [n][Kp] the real orthonormal SH basis (the convention of sh_transfer) at
+ * the sample directions, W = diag(w).  Accumulated in FP64 in a fixed order
+ * and solved by Cholesky in FP64 (B^T W B + lambda I must be positive
+ * definite: lambda > 0, or samples that determine every coefficient).
+ *   Y : device [n][3] radiance samples (RGB)
+ *   D : device [n][3] unit directions;  w: device [n] weights (e.g. the solid
+ *       angles of cube-map pixels)
+ *   Kp: 1, 4, 9 or 16 (SH degree 0..3);  lambda >= 0
+ *   A : device output [Kp][3] float32 (the probe sh_transfer consumes)
+ *   ws: device workspace of >= dgsm_probe_fit_workspace_size(Kp) bytes
+ */
+size_t dgsm_probe_fit_workspace_size(int32_t Kp);
+dgsm_status dgsm_probe_fit(const float* Y, const float* D, const float* w, int64_t n, int32_t Kp, float lambda,
+                           float* A, void* ws, size_t ws_bytes, void* stream);
+
 /* dgsm_alpha_centroid - c = sum_i alpha_i mu_i / sum_i alpha_i (Sec. 3.2
  * "Receiver-driven region", the alpha-weighted avatar centroid), accumulated
  * in FP64 in a fixed order (bitwise reproducible).  centroid: device [3].

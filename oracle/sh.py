@@ -132,3 +132,19 @@ def relight(probe, gaussians, colour_sh, centroid=None, n_theta=32, n_phi=64, q=
     f_out = gamma * s[:, None, :] * f
     rgb = np.maximum(0.0, gamma * (0.5 + C0 * f[:, 0, :]) * s)
     return s, f_out, rgb
+
+
+# ---------------------------------------------------------------------------
+# Approximate HDRI probe (Sec. 3.4): weighted ridge least squares of the SH
+# coefficients from radiance samples Y at directions D with weights w (the
+# renderer's output; synth.cubemap_directions makes cube-face samples).
+# ---------------------------------------------------------------------------
+
+def probe_fit(Y, D, w, l_max, lam):
+    """A [K, 3], K = (l_max + 1)^2, minimising ||W^(1/2) (B A - Y)||_F^2 + lam ||A||_F^2
+    with B = real_sh(l_max, D) and W = diag(w): (B^T W B + lam I) A = B^T W Y."""
+    B = real_sh(l_max, D)
+    w = np.asarray(w, dtype=np.float64)
+    G = B.T @ (w[:, None] * B) + lam * np.eye(B.shape[1])
+    R = B.T @ (w[:, None] * np.asarray(Y, dtype=np.float64))
+    return np.linalg.solve(G, R)

@@ -97,6 +97,10 @@ SIGNATURES = {
                                             ctypes.POINTER(_Gaussians), ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "dgsm_footprint_stencil7": (None, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
+    "dgsm_probe_fit_workspace_size": (ctypes.c_size_t, [ctypes.c_int32]),
+    "dgsm_probe_fit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_size_t, ctypes.c_void_p]),
     "dgsm_check_gaussians": (ctypes.c_int, [ctypes.POINTER(_Gaussians), ctypes.c_void_p,
                                             ctypes.POINTER(ctypes.c_longlong), ctypes.c_void_p]),
     "dgsm_plan_tile_waves": (ctypes.c_int32, [ctypes.c_void_p]),
@@ -360,6 +364,26 @@ def dgsm_query(lights, atlas: Atlas, table, points, out=None):
     d = atlas.struct()
     lt = _Lights(lights.data_ptr(), L, 1.0)
     _check(lib().dgsm_query(ctypes.byref(lt), ctypes.byref(d), _ptr(table), _ptr(points), P, _ptr(out), _stream()))
+    return out
+
+
+def dgsm_probe_fit(Y, D, w, Kp: int = 16, lam: float = 0.0, out=None, workspace=None):
+    """SH probe A [Kp, 3] by weighted ridge least squares from samples Y [n, 3] at
+    directions D [n, 3] with weights w [n] (Sec. 3.4)."""
+    Y, D, w = _dev(Y), _dev(D), _dev(w)
+    n = int(w.numel())
+    if Y.numel() != 3 * n or D.numel() != 3 * n:
+        raise ValueError("Y and D must be [n, 3] for n weights")
+    need = int(lib().dgsm_probe_fit_workspace_size(Kp))
+    if need == 0:
+        raise ValueError("Kp must be 1, 4, 9 or 16")
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=w.device)
+    if out is None:
+        out = torch.empty((Kp, 3), dtype=torch.float32, device=w.device)
+    _cuda(out, "out")
+    _check(lib().dgsm_probe_fit(_ptr(Y), _ptr(D), _ptr(w), n, Kp, lam, _ptr(out), _ptr(workspace),
+                                workspace.numel(), _stream()))
     return out
 
 

@@ -13,34 +13,6 @@ namespace dgsm {
 constexpr int kShThreads = 256;
 constexpr int kShChunk = 1024;
 
-// Real orthonormal SH up to degree 3 without the Condon-Shortley phase,
-// index k = l^2 + l + m; writes the first kp values.
-__device__ inline void real_sh16(float x, float y, float z, int kp, float* Y) {
-    Y[0] = 0.28209479177387814f;
-    if (kp <= 1) return;
-    const float c1 = 0.48860251190291992f;           // sqrt(3 / (4 pi))
-    Y[1] = c1 * y; Y[2] = c1 * z; Y[3] = c1 * x;
-    if (kp <= 4) return;
-    const float c2a = 1.0925484305920792f;           // sqrt(15 / pi) / 2
-    const float c2b = 0.31539156525252005f;          // sqrt(5 / pi) / 4
-    const float c2c = 0.54627421529603959f;          // sqrt(15 / pi) / 4
-    Y[4] = c2a * x * y; Y[5] = c2a * y * z; Y[6] = c2b * (3.f * z * z - 1.f);
-    Y[7] = c2a * x * z; Y[8] = c2c * (x * x - y * y);
-    if (kp <= 9) return;
-    const float c3a = 0.59004358992664352f;          // sqrt(35 / (2 pi)) / 4
-    const float c3b = 2.8906114426405538f;           // sqrt(105 / pi) / 2
-    const float c3c = 0.45704579946446572f;          // sqrt(21 / (2 pi)) / 4
-    const float c3d = 0.37317633259011540f;          // sqrt(7 / pi) / 4
-    const float c3e = 1.4453057213202769f;           // sqrt(105 / pi) / 4
-    Y[9] = c3a * y * (3.f * x * x - y * y);
-    Y[10] = c3b * x * y * z;
-    Y[11] = c3c * y * (5.f * z * z - 1.f);
-    Y[12] = c3d * z * (5.f * z * z - 3.f);
-    Y[13] = c3c * x * (5.f * z * z - 1.f);
-    Y[14] = c3e * z * (x * x - y * y);
-    Y[15] = c3a * x * (x * x - 3.f * y * y);
-}
-
 struct ShArgs {
     const float* probe;      // [kp][3]
     int kp;

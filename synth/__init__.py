@@ -267,3 +267,38 @@ def mlp_init_params(seed: int) -> np.ndarray:
         parts += [W.ravel(), np.zeros(H)]
     parts += [rng.uniform(-np.sqrt(3.0 / H), np.sqrt(3.0 / H), H), np.array([-2.0])]
     return np.concatenate(parts).astype(np.float32)
+
+
+# faces: (major axis, u axis, v axis); a pixel's direction is major + a u + b v
+CUBE_FACES = np.array([
+    [[1, 0, 0], [0, 0, -1], [0, -1, 0]],
+    [[-1, 0, 0], [0, 0, 1], [0, -1, 0]],
+    [[0, 1, 0], [1, 0, 0], [0, 0, 1]],
+    [[0, -1, 0], [1, 0, 0], [0, 0, -1]],
+    [[0, 0, 1], [1, 0, 0], [0, -1, 0]],
+    [[0, 0, -1], [-1, 0, 0], [0, -1, 0]],
+], dtype=np.float64)
+
+
+def cubemap_directions(res):
+    """Sample directions of a six-face 90-degree cube-map render (the probe
+    fit's input): pixel-centre unit directions D [6 res^2, 3] and the solid
+    angle w of every pixel.  The solid angle of the face-plane
+    rectangle [x0, x1] x [y0, y1] at unit distance is
+    F(x1, y1) - F(x0, y1) - F(x1, y0) + F(x0, y0), F(x, y) = atan2(x y, sqrt(1 + x^2 + y^2))."""
+    edges = -1.0 + 2.0 * np.arange(res + 1) / res
+    cent = 0.5 * (edges[:-1] + edges[1:])
+    a, b = np.meshgrid(cent, cent, indexing="ij")
+
+    def F(x, y):
+        return np.arctan2(x * y, np.sqrt(1.0 + x * x + y * y))
+
+    x0, y0 = np.meshgrid(edges[:-1], edges[:-1], indexing="ij")
+    x1, y1 = np.meshgrid(edges[1:], edges[1:], indexing="ij")
+    omega = (F(x1, y1) - F(x0, y1) - F(x1, y0) + F(x0, y0)).reshape(-1)
+    dirs, weights = [], []
+    for n, u, v in CUBE_FACES:
+        d = n[None, :] + a.reshape(-1, 1) * u[None, :] + b.reshape(-1, 1) * v[None, :]
+        dirs.append(d / np.linalg.norm(d, axis=1, keepdims=True))
+        weights.append(omega)
+    return np.concatenate(dirs), np.concatenate(weights)

@@ -352,3 +352,26 @@ def test_maximum_atlas_side_sampled():
     assert err <= TOL
     # directions pointing away from the Gaussians' octant see nothing
     assert torch.all(T[0, :, 1023, 1023] == 1.0) and torch.all(T[0, :, 0, 0] == 1.0)
+
+
+@pytest.mark.parametrize("Kp,lam,cube", [(16, 0.0, True), (9, 0.05, True), (16, 0.01, False)])
+def test_probe_fit_matches_oracle(Kp, lam, cube):
+    """Sec. 3.4 weighted ridge fit: cube-map samples (solid-angle weights) or
+    scattered directions with random weights, against the FP64 oracle."""
+    import paper_2601_01660_amd as P
+    rng = np.random.default_rng(40 + Kp)
+    if cube:
+        D, w = synth.cubemap_directions(48)
+    else:
+        D = rng.normal(size=(20000, 3))
+        D /= np.linalg.norm(D, axis=1, keepdims=True)
+        w = rng.uniform(0.2, 1.0, 20000) * (4 * np.pi / 20000)
+    Y = rng.uniform(0.0, 2.0, (D.shape[0], 3))
+    D32, w32, Y32 = D.astype(np.float32), w.astype(np.float32), Y.astype(np.float32)
+    A = P.dgsm_probe_fit(torch.from_numpy(Y32), torch.from_numpy(D32), torch.from_numpy(w32), Kp, lam)
+    torch.cuda.synchronize()
+    ref = osh.probe_fit(Y32.astype(np.float64), D32.astype(np.float64), w32.astype(np.float64),
+                        int(round(math.sqrt(Kp))) - 1, lam)
+    err = np.abs(A.cpu().numpy() - ref).max() / np.abs(ref).max()
+    _report(f"probe fit Kp={Kp} lam={lam} cube={cube} (relative)", err)
+    assert err <= 1e-4

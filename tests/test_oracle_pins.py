@@ -507,3 +507,42 @@ def test_beta_trace_mapping_is_equation_5_for_isotropic():
     A = np.eye(3)[None] / s ** 2
     b = od.absorption_amplitude(np.array([0.5]), A, beta="trace")
     assert abs(b[0] - np.log(2) * (1 / s) / np.sqrt(2 * np.pi)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Approximate HDRI probe fit (Sec. 3.4)
+# ---------------------------------------------------------------------------
+
+def test_cubemap_solid_angles_cover_the_sphere():
+    D, w = synth.cubemap_directions(16)
+    assert D.shape == (6 * 256, 3) and np.allclose(np.linalg.norm(D, axis=1), 1.0, atol=1e-15)
+    assert abs(w.sum() - 4 * np.pi) < 1e-12
+    # face centres are the largest pixels, corners the smallest: ratio 3^(3/2) in the limit
+    assert w.max() / w.min() > 4.0
+
+
+def test_cubemap_quadrature_makes_the_sh_basis_orthonormal():
+    D, w = synth.cubemap_directions(64)
+    B = osh.real_sh(3, D)
+    G = B.T @ (w[:, None] * B)
+    assert np.abs(G - np.eye(16)).max() < 2e-3
+
+
+@pytest.mark.parametrize("l_max", [2, 3])
+def test_probe_fit_recovers_a_known_probe(l_max):
+    rng = np.random.default_rng(13)
+    K = (l_max + 1) ** 2
+    A = rng.normal(size=(K, 3))
+    D, w = synth.cubemap_directions(12)
+    Y = osh.real_sh(l_max, D) @ A
+    assert np.allclose(osh.probe_fit(Y, D, w, l_max, 0.0), A, rtol=0, atol=1e-10)
+
+
+def test_probe_fit_ridge_limit():
+    rng = np.random.default_rng(14)
+    D, w = synth.cubemap_directions(8)
+    Y = rng.uniform(0, 2, (D.shape[0], 3))
+    lam = 1e9
+    A = osh.probe_fit(Y, D, w, 3, lam)
+    B = osh.real_sh(3, D)
+    assert np.allclose(A * lam, B.T @ (w[:, None] * Y), rtol=1e-6, atol=0)
