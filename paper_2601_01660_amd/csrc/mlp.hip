@@ -383,18 +383,25 @@ __global__ __launch_bounds__(kWave * NWV) void fwd_kernel(FwdArgs a) {
 
 // ---------------------------------------------------------------------------
 // Inference with the weights held in registers.  Wave w of kIW owns output
-// columns [32w, 32w + 32) of every layer: the B fragments of its two 16-column
-// MFMA tiles stay in VGPRs for the whole kernel, the activations of kIRB
-// 16-row blocks go through LDS between layers, and every A fragment read from
-// LDS feeds two MFMAs.  The atlas is read only for rows whose fallback region
-// is flagged.
+// features [32w, 32w + 32) of every layer: its weight rows stay in VGPRs as
+// the A operand of the MFMA for the whole kernel, and the activations of kIRB
+// 16-sample blocks are the B operand, so each product H^T = W X^T leaves four
+// consecutive features of one sample per lane (one 8-byte LDS store) and each
+// activation fragment read from LDS feeds two MFMAs.  Features: one thread per
+// (sample, frequency) writes its six sines and cosines; the zero padding of the
+// feature rows is written once.
 // ---------------------------------------------------------------------------
 constexpr int kIW = 4;      // waves per inference block
-constexpr int kIRB = 2;     // 16-row blocks per iteration
+constexpr int kIRB = 2;     // 16-sample blocks per iteration
 constexpr int kIRows = kIRB * kRows;
 
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+
 __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
-    __shared__ bf16x8 act[2][kIRB][kRows * 16];   // [buffer][row block][row, chunk] (swizzled)
+    __shared__ bf16x8 feat[kIRB][kRows * 16];      // [sample block][sample, chunk] (swizzled)
+    __shared__ bf16x8 hid[2][kIRB][kRows * 16];
+    __shared__ float4 btab[4][kH / 4];            // biases of the four layers
+    __shared__ float w4t[kH];
     __shared__ float zpart[kIRows][kIW];
     __shared__ float4 rin[kIRows];
     __shared__ float freq[kNF];
@@ -403,27 +410,32 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
     const float* P = a.params + (size_t)light * kNParams;
     const __bf16* Wg = a.wb + (size_t)light * 4 * kH * kH;
     const int lr = lane % 16, lg = lane / 16;
-    // this wave's weights: layer l, column tile j (columns 16 (2 wave + j) ..), k-step kk
-    bf16x8 B[4][2][4];
-    float bias[4][2], w4[2];
+    // this wave's weight rows: layer l, feature tile j (features 16 (2 wave + j) ..), k-step kk
+    bf16x8 Wf[4][2][4];
 #pragma unroll
     for (int l = 0; l < 4; ++l)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const int col = 16 * (2 * wave + j) + lr;
+            const int row = 16 * (2 * wave + j) + lr;
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk)
-                B[l][j][kk] = *reinterpret_cast<const bf16x8*>(Wg + (size_t)l * kH * kH + (size_t)col * kH + 32 * kk +
-                                                               8 * lg);
-            bias[l][j] = P[l * kLayer + kH * kH + col];
+                Wf[l][j][kk] = *reinterpret_cast<const bf16x8*>(Wg + (size_t)l * kH * kH + (size_t)row * kH + 32 * kk +
+                                                                8 * lg);
         }
+    for (int q = tid; q < 4 * kH; q += kWave * kIW)
+        reinterpret_cast<float*>(btab)[q] = P[(q / kH) * kLayer + kH * kH + q % kH];
+    for (int q = tid; q < kH; q += kWave * kIW) w4t[q] = P[kOffW4 + q];
+    for (int q = tid; q < kIRB * kRows * 16; q += kWave * kIW) {   // zero padding of the feature rows
+        bf16x8 z;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) w4[j] = P[kOffW4 + 16 * (2 * wave + j) + lr];
+        for (int e = 0; e < 8; ++e) z[e] = to_bf16(0.f);
+        (&feat[0][0])[q] = z;
+    }
     const float b4 = P[kOffB4];
     const float fscale = __log2f(0.25f * (float)a.g.W) / 15.f;
     if (tid < kNF) freq[tid] = 3.14159265358979324f * exp2f(fscale * (float)tid);   // pi (W/4)^(i/15)
     const int64_t ntile = (a.n + kIRows - 1) / kIRows;
-    // the next tile's points are loaded one iteration ahead (lanes tid < kIRows)
+    // the next tile's points are loaded one iteration ahead (threads tid < kIRows)
     float px = 0.f, py = 0.f, pz = 0.f;
     auto load_pt = [&](int64_t tt) {
         const int64_t rr = tt * kIRows + tid;
@@ -434,6 +446,7 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
         }
     };
     load_pt(blockIdx.x);
+    __bf16* fe = reinterpret_cast<__bf16*>(&feat[0][0]);
 
     for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
         const int64_t row0 = t * kIRows;
@@ -447,35 +460,46 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
         }
         load_pt(t + gridDim.x);
         __syncthreads();
-        // features: thread -> row tid / 8, chunks 2 (tid % 8) and 2 (tid % 8) + 1
-        {
-            const int row = tid / 8, c0 = 2 * (tid % 8);
-            const float4 in = rin[row];
+        // features: thread -> (sample, frequency) pairs tid and tid + 256 of 32 x 16
 #pragma unroll
-            for (int cc = 0; cc < 2; ++cc) {
-                const int c = c0 + cc;
-                bf16x8 ch;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) ch[e] = to_bf16(feature_fr(8 * c + e, in.x, in.y, in.z, freq));
-                act[0][row / kRows][swz(row % kRows, c)] = ch;
+        for (int h = 0; h < 2; ++h) {
+            const int pr = tid + h * kWave * kIW;
+            const int smp = pr / kNF, i = pr % kNF;
+            const float4 in = rin[smp];
+            __bf16* rowp = fe + (size_t)(smp / kRows) * kRows * 16 * 8;
+            const int r = smp % kRows;
+            auto put = [&](int f, float v) { rowp[swz(r, f / 8) * 8 + (f % 8)] = to_bf16(v); };
+            if (i == 0) {
+                put(0, in.x);
+                put(1, in.y);
+                put(2, in.z);
             }
+            const float fr = freq[i];
+            put(3 + 6 * i, hw_sin(fr * in.x));
+            put(4 + 6 * i, hw_cos(fr * in.x));
+            put(5 + 6 * i, hw_sin(fr * in.y));
+            put(6 + 6 * i, hw_cos(fr * in.y));
+            put(7 + 6 * i, hw_sin(fr * in.z));
+            put(8 + 6 * i, hw_cos(fr * in.z));
         }
         __syncthreads();
         f32x4 acc[kIRB][2];
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
-            const int cur = l & 1;
+            const bf16x8(*src)[kRows * 16] = l == 0 ? feat : hid[(l - 1) & 1];
 #pragma unroll
-            for (int rb = 0; rb < kIRB; ++rb)
+            for (int j = 0; j < 2; ++j) {
+                const float4 bb = btab[l][(16 * (2 * wave + j) + 4 * lg) / 4];
 #pragma unroll
-                for (int j = 0; j < 2; ++j) acc[rb][j] = f32x4{bias[l][j], bias[l][j], bias[l][j], bias[l][j]};
+                for (int rb = 0; rb < kIRB; ++rb) acc[rb][j] = f32x4{bb.x, bb.y, bb.z, bb.w};
+            }
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
                 for (int rb = 0; rb < kIRB; ++rb) {
-                    const bf16x8 av = act[cur][rb][swz(lr, lg + 4 * kk)];
+                    const bf16x8 xv = src[rb][swz(lr, lg + 4 * kk)];
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) acc[rb][j] = mfma(av, B[l][j][kk], acc[rb][j]);
+                    for (int j = 0; j < 2; ++j) acc[rb][j] = mfma(Wf[l][j][kk], xv, acc[rb][j]);
                 }
 #pragma unroll
             for (int rb = 0; rb < kIRB; ++rb)
@@ -484,32 +508,34 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) acc[rb][j][r] = fmaxf(acc[rb][j][r], 0.f);
             if (l < 3) {
-                __bf16* nxt = reinterpret_cast<__bf16*>(&act[cur ^ 1][0][0]);
+                __bf16* dst = reinterpret_cast<__bf16*>(&hid[l & 1][0][0]);
 #pragma unroll
                 for (int rb = 0; rb < kIRB; ++rb)
 #pragma unroll
                     for (int j = 0; j < 2; ++j) {
-                        const int col = 16 * (2 * wave + j) + lr;
+                        const int f0 = 16 * (2 * wave + j) + 4 * lg;   // four consecutive features of sample lr
+                        bf16x4 v;
 #pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            nxt[(size_t)rb * kRows * 16 * 8 + swz(4 * lg + r, col / 8) * 8 + (col % 8)] =
-                                to_bf16(acc[rb][j][r]);
+                        for (int r = 0; r < 4; ++r) v[r] = to_bf16(acc[rb][j][r]);
+                        *reinterpret_cast<bf16x4*>(dst + (size_t)rb * kRows * 16 * 8 + swz(lr, f0 / 8) * 8 + (f0 % 8)) =
+                            v;
                     }
                 __syncthreads();
             }
         }
-        // output layer: this wave's share of z = w4 . h4 for each row, summed over waves in LDS
+        // output layer: this wave's share of z = w4 . h4 per sample, summed over waves in LDS
 #pragma unroll
         for (int rb = 0; rb < kIRB; ++rb) {
-            float zp[4];
+            float zp = 0.f;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) zp[r] = w4[0] * acc[rb][0][r] + w4[1] * acc[rb][1][r];
+            for (int j = 0; j < 2; ++j) {
+                const int f0 = 16 * (2 * wave + j) + 4 * lg;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                for (int o = 1; o < 16; o <<= 1) zp[r] += __shfl_xor(zp[r], o, kWave);
-            if (lr == 0)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) zpart[rb * kRows + 4 * lg + r][wave] = zp[r];
+                for (int r = 0; r < 4; ++r) zp += w4t[f0 + r] * acc[rb][j][r];
+            }
+            zp += __shfl_xor(zp, 16, kWave);
+            zp += __shfl_xor(zp, 32, kWave);
+            if (lg == 0) zpart[rb * kRows + lr][wave] = zp;
         }
         __syncthreads();
         if (tid < kIRows && row0 + tid < a.n) {
