@@ -20,6 +20,7 @@ Conventions (readings of the paper where it is silent):
   radii r_k = r0 (r1/r0)^(k/(K-1)) (the workload configurations).
 * query: bilinear in texel space with the octahedral mirror wrap across the
   outer edges, times linear in the fractional shell index, applied to T.
+* cube-map atlas (Ablation C, param="cubemap"): see the cube-map section.
 """
 from __future__ import annotations
 
@@ -163,10 +164,78 @@ def texel_uv(H, W):
     return np.broadcast_to(u[None, :], (H, W)), np.broadcast_to(v[:, None], (H, W))
 
 
-def texel_directions(H, W):
+def texel_directions(H, W, param="octahedral"):
     """Unit direction of every texel centre, [H, W, 3]."""
+    if param == "cubemap":
+        return cube_texel_directions(H, W)
+    if param != "octahedral":
+        raise ValueError(param)
     u, v = texel_uv(H, W)
     return octahedral_decode(u, v)
+
+
+# ---------------------------------------------------------------------------
+# Cube-map parameterisation (Ablation C)
+# ---------------------------------------------------------------------------
+# The paper compares its octahedral atlas with a six-face cube map but does
+# not fix the cube map's layout or filtering; the reading used here:
+# * faces of F x F texels, face f = 2 m + (0 for the + side, 1 for the - side)
+#   of major axis m in (x, y, z), stored in a 2F x 3F atlas (H = 2F, W = 3F)
+#   at block row f // 3, block column f % 3;
+# * on face (m, sign) texel (b, a) (row b, column a inside the face) has face
+#   coordinates s = -1 + (2a + 1)/F, t = -1 + (2b + 1)/F and the direction
+#   proportional to d[m] = sign, d[(m+1) % 3] = s, d[(m+2) % 3] = t;
+# * a lookup picks the face of the largest |component| (the first axis on
+#   ties) and interpolates bilinearly inside that face, clamped to the face's
+#   edge texels: nothing is filtered across faces (the seams the ablation
+#   measures).
+
+def cube_decode(face, s, t):
+    """Unit direction of face coordinates (s, t) in [-1, 1] on the given faces."""
+    face = np.asarray(face, dtype=np.int64)
+    s, t = np.broadcast_arrays(np.asarray(s, dtype=np.float64), np.asarray(t, dtype=np.float64))
+    face = np.broadcast_to(face, s.shape)
+    m = face // 2
+    sign = np.where(face % 2 == 0, 1.0, -1.0)
+    d = np.zeros(s.shape + (3,))
+    for axis in range(3):
+        sel = m == axis
+        d[sel, axis] = sign[sel]
+        d[sel, (axis + 1) % 3] = s[sel]
+        d[sel, (axis + 2) % 3] = t[sel]
+    return d / np.linalg.norm(d, axis=-1, keepdims=True)
+
+
+def cube_face(d32):
+    """Face of each direction: the axis of the largest |component| (the first
+    on ties) and its sign.  The choice is an integer decided by floating point,
+    so it is taken in FP32 on the FP32 offsets, as the kernel takes it."""
+    a = np.abs(np.asarray(d32, dtype=np.float32))
+    m = np.where((a[..., 0] >= a[..., 1]) & (a[..., 0] >= a[..., 2]), 0, np.where(a[..., 1] >= a[..., 2], 1, 2))
+    comp = np.take_along_axis(np.asarray(d32, dtype=np.float32), m[..., None], axis=-1)[..., 0]
+    return 2 * m + (comp < 0)
+
+
+def cube_encode(d, face):
+    """Face coordinates (s, t) of directions d [..., 3] on the given faces."""
+    d = np.asarray(d, dtype=np.float64)
+    m = np.asarray(face) // 2
+    major = np.abs(np.take_along_axis(d, m[..., None], axis=-1)[..., 0])
+    s = np.take_along_axis(d, ((m + 1) % 3)[..., None], axis=-1)[..., 0] / major
+    t = np.take_along_axis(d, ((m + 2) % 3)[..., None], axis=-1)[..., 0] / major
+    return s, t
+
+
+def cube_texel_directions(H, W):
+    """Unit direction of every texel centre of a 2F x 3F cube-map atlas, [H, W, 3]."""
+    F = H // 2
+    if H != 2 * F or W != 3 * F or F < 2:
+        raise ValueError("cube-map atlas must be 2F x 3F with F >= 2")
+    i, j = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    face = 3 * (i // F) + j // F
+    s = -1 + (2 * (j % F) + 1) / F
+    t = -1 + (2 * (i % F) + 1) / F
+    return cube_decode(face, s, t)
 
 
 def shell_radii(K, spacing="geometric", r0=0.05, r1=8.0):
@@ -211,24 +280,33 @@ def optical_depth(dirs, t, o_L, mean, A, beta, chunk=2048):
     return tau
 
 
-def build(light, gaussians, H, W, K, spacing="geometric", r0=0.05, r1=8.0, kappa=1.0, beta="trace"):
+def build(light, gaussians, H, W, K, spacing="geometric", r0=0.05, r1=8.0, kappa=1.0, beta="trace",
+          param="octahedral"):
     """Transmittance atlas T[K, H, W] for one point light (Eqs. 2-4, Sec. 3.2)."""
     mean, A, beta = gaussian_terms(gaussians, kappa, beta)
-    dirs = texel_directions(H, W).reshape(-1, 3)
+    dirs = texel_directions(H, W, param).reshape(-1, 3)
     t = shell_radii(K, spacing, r0, r1)
     tau = optical_depth(dirs, t, light, mean, A, beta)
     return np.exp(-tau).T.reshape(K, H, W)
 
 
 def build_texels(light, gaussians, rows, cols, K, spacing="geometric", r0=0.05, r1=8.0,
-                 kappa=1.0, H=None, W=None):
+                 kappa=1.0, H=None, W=None, param="octahedral"):
     """T[len(rows), K] at the given texels of an H x W atlas (sampled parity)."""
     mean, A, beta = gaussian_terms(gaussians, kappa)
-    u = -1 + (2 * np.asarray(cols, dtype=np.float64) + 1) / W
-    v = -1 + (2 * np.asarray(rows, dtype=np.float64) + 1) / H
-    dirs = octahedral_decode(u, v)
+    dirs = _texel_dirs_at(rows, cols, H, W, param)
     t = shell_radii(K, spacing, r0, r1)
     return np.exp(-optical_depth(dirs, t, light, mean, A, beta))
+
+
+def _texel_dirs_at(rows, cols, H, W, param):
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    if param == "cubemap":
+        return cube_texel_directions(H, W)[rows, cols]
+    u = -1 + (2 * cols + 1) / W
+    v = -1 + (2 * rows + 1) / H
+    return octahedral_decode(u, v)
 
 
 def transmittance_at(light, gaussians, points, kappa=1.0, chunk=4096):
@@ -296,21 +374,71 @@ def _corner_weights(i_f, jf, kf, K):
     return i0, j0, k0, i_f - i0, jf - j0, kf - k0
 
 
-def query(table, light, points, spacing="geometric", r0=0.05, r1=8.0):
+def _shell_coord(r, K, spacing, r0, r1):
+    if spacing == "geometric":
+        with np.errstate(divide="ignore"):
+            kf = (K - 1) * np.log(np.maximum(r, 1e-300) / r0) / np.log(r1 / r0)
+    else:
+        kf = r * K / r1 - 0.5
+    return np.clip(kf, 0.0, K - 1)
+
+
+def cube_cells(light, points, H, W, K, spacing="geometric", r0=0.05, r1=8.0):
+    """Cube-map lookup cells: floor texel (i0, j0) with i0 + 1, j0 + 1 inside the
+    same face, lower shell k0 and the fractions (fi, fj, fk)."""
+    F = H // 2
+    pts = np.asarray(points, dtype=np.float32).reshape(-1, 3)
+    lt = np.asarray(light, dtype=np.float32)
+    diff = pts.astype(np.float64) - lt.astype(np.float64)
+    r = np.linalg.norm(diff, axis=-1)
+    diff = np.where(r[:, None] > 0, diff, np.array([0.0, 0.0, 1.0]))
+    d32 = np.where(r[:, None] > 0, pts - lt, np.array([0, 0, 1], np.float32))
+    face = cube_face(d32)
+    s, t = cube_encode(diff, face)
+
+    def axis(c):
+        cf = np.clip((c + 1) * F / 2 - 0.5, 0.0, F - 1)
+        c0 = np.minimum(np.floor(cf).astype(np.int64), F - 2)
+        return c0, cf - c0
+
+    a0, fa = axis(s)
+    b0, fb = axis(t)
+    kf = _shell_coord(r, K, spacing, r0, r1)
+    k0 = np.minimum(np.floor(kf).astype(np.int64), K - 2)
+    return (face // 3) * F + b0, (face % 3) * F + a0, k0, fb, fa, kf - k0
+
+
+def _cells(light, points, H, W, K, spacing, r0, r1, param):
+    """(i0, j0, k0, fi, fj, fk) of the trilinear cell of each point."""
+    if param == "cubemap":
+        return cube_cells(light, points, H, W, K, spacing, r0, r1)
+    if param != "octahedral":
+        raise ValueError(param)
+    i_f, jf, kf = query_coords(light, points, H, W, K, spacing, r0, r1)
+    return _corner_weights(i_f, jf, kf, K)
+
+
+def _neighbour(i, j, H, W, param):
+    """Texel read at integer (i, j): octahedral wrap, identity inside a cube face."""
+    if param == "cubemap":
+        return np.asarray(i), np.asarray(j)
+    return wrap_texel(i, j, H, W)
+
+
+def query(table, light, points, spacing="geometric", r0=0.05, r1=8.0, param="octahedral"):
     """Trilinear lookup of T[K, H, W] at world points [P, 3] (Sec. 3.3)."""
     K, H, W = table.shape
-    i_f, jf, kf = query_coords(light, points, H, W, K, spacing, r0, r1)
-    i0, j0, k0, fi, fj, fk = _corner_weights(i_f, jf, kf, K)
-    out = np.zeros(i_f.shape)
+    i0, j0, k0, fi, fj, fk = _cells(light, points, H, W, K, spacing, r0, r1, param)
+    out = np.zeros(i0.shape)
     for di, wi in ((0, 1 - fi), (1, fi)):
         for dj, wj in ((0, 1 - fj), (1, fj)):
-            ii, jj = wrap_texel(i0 + di, j0 + dj, H, W)
+            ii, jj = _neighbour(i0 + di, j0 + dj, H, W, param)
             for dk, wk in ((0, 1 - fk), (1, fk)):
                 out += wi * wj * wk * table[k0 + dk, ii, jj]
     return out
 
 
-def roi_region(light, receivers, H, W, K, box=None, spacing="geometric", r0=0.05, r1=8.0):
+def roi_region(light, receivers, H, W, K, box=None, spacing="geometric", r0=0.05, r1=8.0, param="octahedral"):
     """Receiver-driven region of interest (Sec. 3.2): receivers inside the box
     B = {|x - cx| <= R, |y - cy| <= R, zmin <= z <= zmax} (box = (cx, cy, R,
     zmin, zmax); None or R <= 0 keeps every point) mark the texels their
@@ -326,20 +454,19 @@ def roi_region(light, receivers, H, W, K, box=None, spacing="geometric", r0=0.05
     mask = np.zeros((H, W), dtype=bool)
     if pts.shape[0] == 0:
         return mask, K, -1
-    i_f, jf, kf = query_coords(light, pts, H, W, K, spacing, r0, r1)
-    i0, j0, k0, _, _, _ = _corner_weights(i_f, jf, kf, K)
+    i0, j0, k0, _, _, _ = _cells(light, pts, H, W, K, spacing, r0, r1, param)
     for di in (0, 1):
         for dj in (0, 1):
-            ii, jj = wrap_texel(i0 + di, j0 + dj, H, W)
+            ii, jj = _neighbour(i0 + di, j0 + dj, H, W, param)
             mask[ii, jj] = True
     return mask, int(k0.min()), int(k0.max() + 1)
 
 
 def build_roi(light, gaussians, H, W, K, receivers, box=None, spacing="geometric", r0=0.05, r1=8.0,
-              kappa=1.0):
+              kappa=1.0, param="octahedral"):
     """T[K, H, W] of the full build inside the receiver region, 1 outside it."""
-    mask, k_lo, k_hi = roi_region(light, receivers, H, W, K, box, spacing, r0, r1)
-    T = build(light, gaussians, H, W, K, spacing, r0, r1, kappa)
+    mask, k_lo, k_hi = roi_region(light, receivers, H, W, K, box, spacing, r0, r1, param)
+    T = build(light, gaussians, H, W, K, spacing, r0, r1, kappa, param=param)
     keep = mask[None, :, :] & (np.arange(K)[:, None, None] >= k_lo) & (np.arange(K)[:, None, None] <= k_hi)
     return np.where(keep, T, 1.0)
 
@@ -358,7 +485,7 @@ def footprint_stencil7():
     return z, k / k.sum()
 
 
-def query_footprint(table, light, gaussians, z, w, spacing="geometric", r0=0.05, r1=8.0):
+def query_footprint(table, light, gaussians, z, w, spacing="geometric", r0=0.05, r1=8.0, param="octahedral"):
     """Footprint-averaged transmittance of each Gaussian (Sec. 3.3, Ablation A):
     T_g = sum_i w_i T(mu_g + R_g (s_g * z_i)), with T the trilinear atlas
     lookup.  z [n, 3] offsets in the principal-axes frame (standard-normal
@@ -371,25 +498,22 @@ def query_footprint(table, light, gaussians, z, w, spacing="geometric", r0=0.05,
     out = np.zeros(gaussians.n)
     for zi, wi in zip(z, w):
         x = mu + np.einsum("nij,nj->ni", R, s * zi)
-        out += wi * query(table, light, x, spacing, r0, r1)
+        out += wi * query(table, light, x, spacing, r0, r1, param)
     return out
 
 
 def query_exact(light, gaussians, points, H, W, K, spacing="geometric", r0=0.05, r1=8.0,
-                kappa=1.0):
+                kappa=1.0, param="octahedral"):
     """Query at points without a stored atlas: the 8 texel values each point
     interpolates are computed from Eqs. 2-4 directly (for full-size sampling)."""
     mean, A, beta = gaussian_terms(gaussians, kappa)
-    i_f, jf, kf = query_coords(light, points, H, W, K, spacing, r0, r1)
-    i0, j0, k0, fi, fj, fk = _corner_weights(i_f, jf, kf, K)
+    i0, j0, k0, fi, fj, fk = _cells(light, points, H, W, K, spacing, r0, r1, param)
     t_all = shell_radii(K, spacing, r0, r1)
-    out = np.zeros(i_f.shape)
+    out = np.zeros(i0.shape)
     for di, wi in ((0, 1 - fi), (1, fi)):
         for dj, wj in ((0, 1 - fj), (1, fj)):
-            ii, jj = wrap_texel(i0 + di, j0 + dj, H, W)
-            u = -1 + (2 * jj + 1) / W
-            v = -1 + (2 * ii + 1) / H
-            dirs = octahedral_decode(u, v)
+            ii, jj = _neighbour(i0 + di, j0 + dj, H, W, param)
+            dirs = _texel_dirs_at(ii, jj, H, W, param)
             tau = optical_depth(dirs, t_all, light, mean, A, beta)
             T = np.exp(-tau)
             rows = np.arange(len(ii))

@@ -546,3 +546,127 @@ def test_probe_fit_ridge_limit():
     A = osh.probe_fit(Y, D, w, 3, lam)
     B = osh.real_sh(3, D)
     assert np.allclose(A * lam, B.T @ (w[:, None] * Y), rtol=1e-6, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# Cube-map atlas (Ablation C)
+# ---------------------------------------------------------------------------
+
+def test_cube_texels_are_the_cube_map_render_directions():
+    """The texel centres of the 2F x 3F cube-map atlas are, as a set, the pixel
+    centres of a six-face 90-degree cube-map render (an independent generator
+    with its own face bases)."""
+    F = 6
+    a = np.round(od.cube_texel_directions(2 * F, 3 * F).reshape(-1, 3), 12)
+    b = np.round(synth.cubemap_directions(F)[0], 12)
+    a = a[np.lexsort(a.T)]
+    b = b[np.lexsort(b.T)]
+    assert np.array_equal(a, b)
+
+
+def test_cube_face_centres_are_the_signed_axes():
+    for f in range(6):
+        d = od.cube_decode(np.array([f]), np.array([0.0]), np.array([0.0]))[0]
+        e = np.zeros(3)
+        e[f // 2] = 1.0 if f % 2 == 0 else -1.0
+        assert np.array_equal(d, e)
+        assert od.cube_face(e.astype(np.float32)[None])[0] == f
+
+
+def test_cube_encode_inverts_decode_at_texel_centres():
+    F = 5
+    H, W = 2 * F, 3 * F
+    d = od.cube_texel_directions(H, W)
+    i, j = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    face = od.cube_face(d.astype(np.float32))
+    assert np.array_equal(face, 3 * (i // F) + j // F)
+    s, t = od.cube_encode(d, face)
+    assert np.allclose(s, -1 + (2 * (j % F) + 1) / F, atol=1e-14)
+    assert np.allclose(t, -1 + (2 * (i % F) + 1) / F, atol=1e-14)
+
+
+def test_cube_query_reproduces_texel_values_at_centres_and_shells():
+    K, F = 5, 4
+    H, W = 2 * F, 3 * F
+    table = _random_table(K, H, W)
+    t = od.shell_radii(K, "geometric", 0.05, 8.0)
+    d = od.texel_directions(H, W, "cubemap").reshape(-1, 3)
+    light = np.array([0.25, -0.5, 0.125], np.float32)
+    for k in range(K):
+        pts = light + t[k] * d
+        got = od.query(table, light, pts, param="cubemap")
+        assert np.allclose(got, table[k].reshape(-1), atol=1e-6)
+
+
+def test_cube_query_partition_of_unity_and_bounds():
+    K, F = 6, 4
+    rng = np.random.default_rng(16)
+    pts = rng.uniform(-6, 6, (4000, 3))
+    got = od.query(np.full((K, 2 * F, 3 * F), 0.37), np.zeros(3), pts, param="cubemap")
+    assert np.allclose(got, 0.37, atol=1e-14)
+    table = _random_table(K, 2 * F, 3 * F)
+    got = od.query(table, np.zeros(3), pts, param="cubemap")
+    assert np.all(got >= table.min() - 1e-12) and np.all(got <= table.max() + 1e-12)
+
+
+def test_cube_query_interpolates_linearly_between_face_texel_centres():
+    """A table affine in the in-face texel indices (a, b) is reproduced exactly
+    between the first and last texel centres of every face."""
+    K, F = 3, 6
+    H, W = 2 * F, 3 * F
+    i, j = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    face = 3 * (i // F) + j // F
+    c = np.array([0.1, 0.2, 0.3, 0.4, 0.5, 0.6])
+    table = np.broadcast_to(c[face] + 0.03 * (j % F) - 0.02 * (i % F), (K, H, W)).copy()
+    rng = np.random.default_rng(17)
+    n = 600
+    f = rng.integers(0, 6, n)
+    alpha = rng.uniform(0, F - 1, n)
+    beta = rng.uniform(0, F - 1, n)
+    # face coordinate of the continuous texel index x: the centre map s(x) = -1 + (2x + 1)/F
+    d = od.cube_decode(f, -1 + (2 * alpha + 1) / F, -1 + (2 * beta + 1) / F)
+    got = od.query(table, np.zeros(3), 2.0 * d, param="cubemap")
+    assert np.allclose(got, c[f] + 0.03 * alpha - 0.02 * beta, atol=1e-6)
+
+
+def test_cube_query_clamps_to_the_face_at_its_edges():
+    """Beyond the outermost texel centres the lookup holds the edge texels of
+    the face it is in: nothing is blended across the cube edges."""
+    K, F = 2, 4
+    table = _random_table(K, 2 * F, 3 * F)
+    # +x face (block 0, 0): s = +1 at the face edge, t at the centre of in-face row 1
+    t1 = -1 + 3 / F
+    d = np.array([[1.0, 1.0 - 1e-6, t1]])
+    got = od.query(table, np.zeros(3), 2.0 * d / np.linalg.norm(d), param="cubemap")
+    tk = od.shell_radii(K)
+    fk = (np.log(2.0 / tk[0]) / np.log(tk[1] / tk[0]))
+    want = (1 - fk) * table[0, 1, F - 1] + fk * table[1, 1, F - 1]
+    assert np.allclose(got, want, atol=1e-5)
+    # on the cube edge x = y the tie goes to the first axis (+x face)
+    e = np.array([[1.0, 1.0, t1]], np.float32)
+    assert od.cube_face(e)[0] == 0 and od.cube_face(-e)[0] == 1
+
+
+def test_cube_build_is_the_transmittance_at_texel_centres():
+    g = tiny_scene(23, n=20, lo=-2, hi=2, median=0.2)
+    light = np.array([0.05, -0.03, 0.02])
+    F, K = 4, 6
+    T = od.build(light, g, 2 * F, 3 * F, K, param="cubemap")
+    t = od.shell_radii(K)
+    d = od.cube_texel_directions(2 * F, 3 * F).reshape(-1, 3)
+    for k in (0, 2, 5):
+        assert np.allclose(od.transmittance_at(light, g, light + t[k] * d), T[k].reshape(-1), rtol=1e-12,
+                           atol=1e-14)
+    assert T.min() < 0.9
+
+
+def test_cube_roi_queries_at_receivers_equal_full_queries():
+    rng = np.random.default_rng(33)
+    g = synth.random_gaussians(rng, rng.uniform(-1.5, 1.5, (200, 3)) + [0, 0, 2.0], 0.05)
+    light = np.array([0.2, -0.1, 0.0], np.float32)
+    F, K = 6, 8
+    T = od.build(light, g, 2 * F, 3 * F, K, param="cubemap")
+    rec = rng.uniform(-1.5, 1.5, (150, 3)) + [0, 0, 2.0]
+    Troi = od.build_roi(light, g, 2 * F, 3 * F, K, rec, param="cubemap")
+    assert np.array_equal(od.query(Troi, light, rec, param="cubemap"), od.query(T, light, rec, param="cubemap"))
+    assert np.any(Troi == 1.0) and np.any(Troi < 1.0)
