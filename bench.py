@@ -290,6 +290,23 @@ def main():
     torch.cuda.empty_cache()
     log(f"receiver region around the avatar: {roi}")
 
+    # ---- cube-map atlas (Ablation C) at about the octahedral atlas's texel count --------------
+    Fc = 8 * int(round((spec.H * spec.W / 6) ** 0.5 / 8))      # 512 x 512 -> F = 208: 416 x 624 texels
+    cube = P.Atlas.cube(Fc, spec.K, spacing=spec.spacing, r0=spec.r0, r1=spec.r1, dtype="f16", cull_eps=1e-8)
+    ws_c = torch.empty(P.dgsm_build_workspace_size(cube, N, L), dtype=torch.uint8, device=dev)
+    cube_t = P.dgsm_build(lights, g0, cube, workspace=ws_c)
+    Tc = torch.empty((L, N), dtype=torch.float32, device=dev)
+    P.dgsm_query(lights, cube, cube_t, g0.mean, out=Tc)
+    torch.cuda.synchronize()
+    cubemap = {"face": Fc, "texels": 6 * Fc * Fc, "octahedral_texels": spec.H * spec.W,
+               "build_ms": round(timed(lambda: P.dgsm_build(lights, g0, cube, out=cube_t, workspace=ws_c), 2), 3),
+               "octahedral_build_ms": roi["build_full_ms"],
+               "query_ms": round(timed(lambda: P.dgsm_query(lights, cube, cube_t, g0.mean, out=Tc), 5), 4),
+               "octahedral_query_ms": footprint["center_query_ms"]}
+    del ws_c, cube_t, Tc
+    torch.cuda.empty_cache()
+    log(f"cube-map atlas: {cubemap}")
+
     # ---- approximate HDRI probe (Sec. 3.4): ridge fit from a 6 x 128^2 cube-map render --------
     Dc, wc = synth.cubemap_directions(128)
     Yc = np.random.default_rng(9).uniform(0.0, 2.0, (Dc.shape[0], 3))
@@ -352,7 +369,7 @@ def main():
            "comparison_ms_per_frame": {"batched_graph_static_cache": round(ms_frame, 4),
                                        "batched_graph_no_cache": round(ms_nocache / F, 4),
                                        "plain_per_frame_launches": round(ms_plain / F, 4)},
-           "roofline": roofline, "footprint_query": footprint, "roi_build": roi, "probe_fit": probe}
+           "roofline": roofline, "footprint_query": footprint, "roi_build": roi, "cube_map": cubemap, "probe_fit": probe}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(P, torch, np, dev, lights, atlas, static_set, dyn_set, tr, N, L, spec,
                                          args.mlp_steps, timed)

@@ -82,7 +82,25 @@ typedef struct {
     int32_t beta_mode;
 } dgsm_lights_t;
 
-/* Atlas description.  H and W even, >= 2; K >= 2; r1 > 0, and 0 < r0 < r1
+/* Direction parameterisation of the atlas.
+ *   DGSM_PARAM_OCTAHEDRAL  the octahedral map of Sec. 3.2 (default): texel
+ *       (i, j) has u = -1 + (2j+1)/W, v = -1 + (2i+1)/H; lookups wrap across
+ *       the outer edges through the octahedral mirror (see dgsm_query).
+ *   DGSM_PARAM_CUBEMAP  the six-face cube map the octahedral atlas is compared
+ *       with (Ablation C).  Faces of F x F texels, H = 2F, W = 3F; face
+ *       f = 2m + (0 for the + side, 1 for the - side) of major axis m in
+ *       (x, y, z) sits at block row f / 3, block column f % 3.  Texel (b, a)
+ *       inside face (m, sign) has face coordinates s = -1 + (2a+1)/F,
+ *       t = -1 + (2b+1)/F and direction along d[m] = sign, d[(m+1) % 3] = s,
+ *       d[(m+2) % 3] = t.  A lookup takes the face of the largest |component|
+ *       of the FP32 offset (the first axis on ties) and interpolates
+ *       bilinearly inside that face, clamped to its edge texels (no filtering
+ *       across faces).  The learned field (dgsm_mlp_*) accepts only the
+ *       octahedral atlas. */
+typedef enum { DGSM_PARAM_OCTAHEDRAL = 0, DGSM_PARAM_CUBEMAP = 1 } dgsm_param;
+
+/* Atlas description.  Octahedral: H and W even, >= 2.  Cube map: H = 2F,
+ * W = 3F, F >= 2.  H, W <= 1024; K >= 2; r1 > 0, and 0 < r0 < r1
  * for geometric spacing.  cull_eps is the per-Gaussian contribution bound of
  * the light-space culling (Sec. 3.2 "Occluder culling"): a Gaussian is left
  * out of a tile only where its optical depth along every texel ray of the
@@ -95,6 +113,7 @@ typedef struct {
     float r0, r1;
     int32_t dtype;         /* dgsm_dtype of the stored T: FP32, or FP16 (RNE of the FP32 value) */
     float cull_eps;
+    int32_t param;         /* dgsm_param */
 } dgsm_atlas_desc_t;
 
 /* Human-readable text for a status code (static storage). */
@@ -198,6 +217,9 @@ dgsm_status dgsm_build_roi(const dgsm_lights_t* lights, const dgsm_gaussians_t* 
  * Texel neighbours outside the grid follow the octahedral mirror wrap: a
  * column beyond the left/right edge maps to column 0 / W-1 at row H-1-i, then
  * a row beyond the top/bottom edge maps to row 0 / H-1 at column W-1-j.
+ * A cube-map atlas (desc->param) takes the in-face coordinates instead:
+ * a_f = (s+1) F/2 - 1/2 and b_f = (t+1) F/2 - 1/2 clamped to [0, F-1], with
+ * both neighbours inside the face.
  *   atlas : device [lights.n][K][H][W] of desc->dtype (as written by dgsm_build)
  *   points: device [P][3];  T: device output [lights.n][P] float32.  P may be 0.
  */

@@ -30,12 +30,13 @@ class _Lights(ctypes.Structure):
 
 
 BETA_MODES = {"trace": 0, "constant": 1, "density": 2}   # dgsm_beta_mode
+PARAMS = {"octahedral": 0, "cubemap": 1}                  # dgsm_param
 
 
 class _AtlasDesc(ctypes.Structure):
     _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("K", ctypes.c_int32),
                 ("spacing", ctypes.c_int32), ("r0", ctypes.c_float), ("r1", ctypes.c_float),
-                ("dtype", ctypes.c_int32), ("cull_eps", ctypes.c_float)]
+                ("dtype", ctypes.c_int32), ("cull_eps", ctypes.c_float), ("param", ctypes.c_int32)]
 
 
 class _ShParams(ctypes.Structure):
@@ -215,11 +216,17 @@ class Atlas:
     r1: float = 8.0
     dtype: str = "f32"
     cull_eps: float = 1e-8
+    param: str = "octahedral"
 
     def struct(self) -> _AtlasDesc:
         sp = {"uniform": DGSM_SHELLS_UNIFORM, "geometric": DGSM_SHELLS_GEOMETRIC}[self.spacing]
         dt = {"f32": DGSM_F32, "f16": DGSM_F16}[self.dtype]
-        return _AtlasDesc(self.H, self.W, self.K, sp, self.r0, self.r1, dt, self.cull_eps)
+        return _AtlasDesc(self.H, self.W, self.K, sp, self.r0, self.r1, dt, self.cull_eps, PARAMS[self.param])
+
+    @staticmethod
+    def cube(F: int, K: int, **kw) -> "Atlas":
+        """Cube-map atlas of six F x F faces stored as 2F x 3F texels."""
+        return Atlas(2 * F, 3 * F, K, param="cubemap", **kw)
 
     @property
     def torch_dtype(self):

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(64) void tile_cone_kernel(Geom g, float4* __restric
     for (int i = ty * kTile; i < i1; ++i)
         for (int j = tx * kTile; j < j1; ++j) {
             double x, y, z;
-            texel_dir(i, j, g.H, g.W, x, y, z);
+            texel_dir(g, i, j, x, y, z);
             sx += x; sy += y; sz += z;
         }
     const double nrm = sqrt(sx * sx + sy * sy + sz * sz);
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(64) void tile_cone_kernel(Geom g, float4* __restric
     for (int i = ty * kTile; i < i1; ++i)
         for (int j = tx * kTile; j < j1; ++j) {
             double x, y, z;
-            texel_dir(i, j, g.H, g.W, x, y, z);
+            texel_dir(g, i, j, x, y, z);
             const double c2 = (x - sx) * (x - sx) + (y - sy) * (y - sy) + (z - sz) * (z - sz);
             ch = fmax(ch, c2);
         }
@@ -960,7 +960,9 @@ __device__ inline void finish_tile(const TileArgs& p, int light, int tile, int l
 
 // NW waves share one tile's accumulators (a launch knob: more waves per tile
 // split a tile's pairs finer and raise occupancy per LDS byte).
-template <typename OutT, bool STATS, int NW, bool GEO>
+// CUBE selects the cube-map texel decode at compile time, so that the
+// octahedral kernels carry no code of the other parameterisation.
+template <typename OutT, bool STATS, int NW, bool GEO, bool CUBE>
 __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const Geom& g = p.g;
@@ -1008,7 +1010,10 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     TexelState st;
     st.valid = py < g.H && px < g.W;
     st.lane = lane;
-    texel_dir(min(py, g.H - 1), min(px, g.W - 1), g.H, g.W, st.dx, st.dy, st.dz);
+    if constexpr (CUBE)
+        cube_texel_dir(min(py, g.H - 1), min(px, g.W - 1), g.F, st.dx, st.dy, st.dz);
+    else
+        octa_texel_dir(min(py, g.H - 1), min(px, g.W - 1), g.H, g.W, st.dx, st.dy, st.dz);
     st.fx = (float)st.dx; st.fy = (float)st.dy; st.fz = (float)st.dz;
     st.K = K;
     st.geometric = g.spacing == DGSM_SHELLS_GEOMETRIC;
@@ -1172,22 +1177,28 @@ size_t tile_smem_bytes(const Geom& g, int nw) {
            (size_t)g.K * sizeof(double);
 }
 
-template <typename OutT, bool STATS, int NW>
-static hipError_t launch_tile(const TileArgs& ta, int n_lights, hipStream_t st) {
+template <typename OutT, bool STATS, int NW, bool CUBE>
+static hipError_t launch_tile_map(const TileArgs& ta, int n_lights, hipStream_t st) {
     const size_t smem = tile_smem_bytes(ta.g, NW);
     const bool geo = ta.g.spacing == DGSM_SHELLS_GEOMETRIC;
-    const void* fn = geo ? (const void*)tile_build_kernel<OutT, STATS, NW, true>
-                         : (const void*)tile_build_kernel<OutT, STATS, NW, false>;
+    const void* fn = geo ? (const void*)tile_build_kernel<OutT, STATS, NW, true, CUBE>
+                         : (const void*)tile_build_kernel<OutT, STATS, NW, false, CUBE>;
     if (smem > 64 * 1024) {
         const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
     const dim3 grid(ta.g.ntiles + ta.lay.units_cap, n_lights);
     if (geo)
-        tile_build_kernel<OutT, STATS, NW, true><<<grid, kWave * NW, smem, st>>>(ta);
+        tile_build_kernel<OutT, STATS, NW, true, CUBE><<<grid, kWave * NW, smem, st>>>(ta);
     else
-        tile_build_kernel<OutT, STATS, NW, false><<<grid, kWave * NW, smem, st>>>(ta);
+        tile_build_kernel<OutT, STATS, NW, false, CUBE><<<grid, kWave * NW, smem, st>>>(ta);
     return hipGetLastError();
+}
+
+template <typename OutT, bool STATS, int NW>
+static hipError_t launch_tile(const TileArgs& ta, int n_lights, hipStream_t st) {
+    return ta.g.param == DGSM_PARAM_CUBEMAP ? launch_tile_map<OutT, STATS, NW, true>(ta, n_lights, st)
+                                            : launch_tile_map<OutT, STATS, NW, false>(ta, n_lights, st);
 }
 
 template <typename OutT, bool STATS>

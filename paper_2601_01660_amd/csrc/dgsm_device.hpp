@@ -22,6 +22,8 @@ constexpr int kMaxAtlasSide = kTile * kSuperTiles * 16;   // 1024
 // light-space binning).
 struct Geom {
     int H, W, K, spacing, dtype;
+    int param;       // dgsm_param
+    int F;           // cube-map face side (H / 2); unused for the octahedral map
     float r0, r1;
     int TH, TW;      // tiles per column / row
     int SGH, SGW;    // supertile grid
@@ -33,6 +35,8 @@ struct Geom {
 inline Geom make_geom(const dgsm_atlas_desc_t& d) {
     Geom g{};
     g.H = d.H; g.W = d.W; g.K = d.K; g.spacing = d.spacing; g.dtype = d.dtype;
+    g.param = d.param;
+    g.F = d.H / 2;
     g.r0 = d.r0; g.r1 = d.r1;
     g.TH = (d.H + kTile - 1) / kTile;
     g.TW = (d.W + kTile - 1) / kTile;
@@ -59,7 +63,7 @@ struct __attribute__((aligned(16))) GRec {
 static_assert(sizeof(GRec) == 112, "GRec layout");
 
 // Octahedral decode of the texel centre (i, j) of an H x W atlas (Sec. 3.2).
-__device__ inline void texel_dir(int i, int j, int H, int W, double& x, double& y, double& z) {
+__device__ inline void octa_texel_dir(int i, int j, int H, int W, double& x, double& y, double& z) {
     const double u = -1.0 + (2.0 * j + 1.0) / W;
     const double v = -1.0 + (2.0 * i + 1.0) / H;
     const double au = fabs(u), av = fabs(v);
@@ -73,6 +77,29 @@ __device__ inline void texel_dir(int i, int j, int H, int W, double& x, double& 
     }
     const double inv = 1.0 / sqrt(x * x + y * y + z * z);
     x *= inv; y *= inv; z *= inv;
+}
+
+// Cube-map decode (Ablation C) of the texel centre (i, j) of a 2F x 3F atlas:
+// face f = 3 (i / F) + j / F, m = f / 2, d[m] = +-1, d[(m+1) % 3] = s,
+// d[(m+2) % 3] = t with the face coordinates (s, t) of the texel centre.
+__device__ inline void cube_texel_dir(int i, int j, int F, double& x, double& y, double& z) {
+    const int bi = i / F, bj = j / F;
+    const int f = 3 * bi + bj, m = f >> 1;
+    const double s = -1.0 + (2.0 * (j - bj * F) + 1.0) / F;
+    const double t = -1.0 + (2.0 * (i - bi * F) + 1.0) / F;
+    const double inv = 1.0 / sqrt(1.0 + s * s + t * t);
+    const double a = ((f & 1) ? -1.0 : 1.0) * inv, b = s * inv, c = t * inv;
+    if (m == 0) { x = a; y = b; z = c; }
+    else if (m == 1) { y = a; z = b; x = c; }
+    else { z = a; x = b; y = c; }
+}
+
+// Unit direction of the texel centre (i, j) of either parameterisation.
+__device__ inline void texel_dir(const Geom& g, int i, int j, double& x, double& y, double& z) {
+    if (g.param == DGSM_PARAM_CUBEMAP)
+        cube_texel_dir(i, j, g.F, x, y, z);
+    else
+        octa_texel_dir(i, j, g.H, g.W, x, y, z);
 }
 
 // Two cones (unit axis, sin of half the half-angle) can share a direction iff
@@ -106,31 +133,58 @@ struct Cell {
     float fi, fj, fk;
 };
 
+// In-face cell of one cube-map axis: coordinate (c+1) F/2 - 1/2 clamped to
+// [0, F-1], floor held at <= F-2 so that both neighbours lie in the face.
+__device__ inline void cube_axis(float c, int F, int& c0, float& fc) {
+    const float cf = fminf(fmaxf((c + 1.f) * (0.5f * (float)F) - 0.5f, 0.f), (float)(F - 1));
+    c0 = min((int)cf, F - 2);
+    fc = cf - (float)c0;
+}
+
 __device__ inline Cell query_cell(const Geom& g, float lr0, float kscale, const float* light, float x, float y,
                                   float z) {
     const float dx = x - light[0], dy = y - light[1], dz = z - light[2];
     const float l1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
-    float qx = 0.f, qy = 0.f, qz = 1.f;
-    if (l1 > 0.f) {
-        const float il = 1.f / l1;
-        qx = dx * il; qy = dy * il; qz = dz * il;
+    Cell c;
+    if (g.param == DGSM_PARAM_CUBEMAP) {
+        const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+        float ma = dz, sa = dx, ta = dy;            // r = 0 looks along +z
+        int m = 2;
+        if (l1 > 0.f) {
+            if (ax >= ay && ax >= az) { m = 0; ma = dx; sa = dy; ta = dz; }
+            else if (ay >= az) { m = 1; ma = dy; sa = dz; ta = dx; }
+        } else {
+            ma = 1.f; sa = 0.f; ta = 0.f;
+        }
+        const int f = 2 * m + (ma < 0.f ? 1 : 0);
+        const float im = 1.f / fabsf(ma);
+        int a0, b0;
+        cube_axis(sa * im, g.F, a0, c.fj);
+        cube_axis(ta * im, g.F, b0, c.fi);
+        c.i0 = (f / 3) * g.F + b0;
+        c.j0 = (f % 3) * g.F + a0;
+    } else {
+        float qx = 0.f, qy = 0.f, qz = 1.f;
+        if (l1 > 0.f) {
+            const float il = 1.f / l1;
+            qx = dx * il; qy = dy * il; qz = dz * il;
+        }
+        float u = qx, v = qy;
+        if (qz < 0.f) {
+            u = copysignf(1.f - fabsf(qy), qx >= 0.f ? 1.f : -1.f);
+            v = copysignf(1.f - fabsf(qx), qy >= 0.f ? 1.f : -1.f);
+        }
+        const float jf = fminf(fmaxf((u + 1.f) * (0.5f * (float)g.W) - 0.5f, -0.5f), (float)g.W - 0.5f);
+        const float fi_ = fminf(fmaxf((v + 1.f) * (0.5f * (float)g.H) - 0.5f, -0.5f), (float)g.H - 0.5f);
+        const float j0f = floorf(jf), i0f = floorf(fi_);
+        c.j0 = (int)j0f;
+        c.i0 = (int)i0f;
+        c.fj = jf - j0f;
+        c.fi = fi_ - i0f;
     }
-    float u = qx, v = qy;
-    if (qz < 0.f) {
-        u = copysignf(1.f - fabsf(qy), qx >= 0.f ? 1.f : -1.f);
-        v = copysignf(1.f - fabsf(qx), qy >= 0.f ? 1.f : -1.f);
-    }
-    const float jf = fminf(fmaxf((u + 1.f) * (0.5f * (float)g.W) - 0.5f, -0.5f), (float)g.W - 0.5f);
-    const float fi_ = fminf(fmaxf((v + 1.f) * (0.5f * (float)g.H) - 0.5f, -0.5f), (float)g.H - 0.5f);
     const float r = sqrtf(dx * dx + dy * dy + dz * dz);
     float kf = g.spacing == DGSM_SHELLS_GEOMETRIC ? (__log2f(r) - lr0) * kscale : r * kscale - 0.5f;
     kf = fminf(fmaxf(kf, 0.f), (float)(g.K - 1));   // log2(0) = -inf clamps to shell 0
-    const float j0f = floorf(jf), i0f = floorf(fi_);
-    Cell c;
-    c.j0 = (int)j0f;
-    c.i0 = (int)i0f;
-    c.fj = jf - j0f;
-    c.fi = fi_ - i0f;
     c.k0 = min((int)kf, g.K - 2);
     c.fk = kf - (float)c.k0;
     return c;

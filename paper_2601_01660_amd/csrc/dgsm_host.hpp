@@ -14,7 +14,13 @@ constexpr int kMaxShells = 256;      // 4 shells per lane of a wave
 
 inline dgsm_status validate_desc(const dgsm_atlas_desc_t* d) {
     if (!d) return DGSM_EINVAL;
-    if (d->H < 2 || d->W < 2 || (d->H & 1) || (d->W & 1)) return DGSM_EINVAL;
+    if (d->param == DGSM_PARAM_OCTAHEDRAL) {
+        if (d->H < 2 || d->W < 2 || (d->H & 1) || (d->W & 1)) return DGSM_EINVAL;
+    } else if (d->param == DGSM_PARAM_CUBEMAP) {
+        if (d->H < 4 || (d->H & 1) || 2 * d->W != 3 * d->H) return DGSM_EINVAL;
+    } else {
+        return DGSM_EINVAL;
+    }
     if (d->H > kMaxAtlasSide || d->W > kMaxAtlasSide) return DGSM_EINVAL;
     if (d->K < 2 || d->K > kMaxShells) return DGSM_EINVAL;
     if (d->spacing != DGSM_SHELLS_UNIFORM && d->spacing != DGSM_SHELLS_GEOMETRIC) return DGSM_EINVAL;

@@ -869,6 +869,14 @@ dgsm_status enqueue_fwd_bwd(const float* params, const Geom& g, int64_t B, const
 
 Geom geom_of(const dgsm_atlas_desc_t* d) { return make_geom(*d); }
 
+// The learned field is a function of the octahedral code (u, v) of the
+// direction: it is defined over the octahedral atlas only.
+dgsm_status validate_mlp_desc(const dgsm_atlas_desc_t* d) {
+    const dgsm_status st = validate_desc(d);
+    if (st != DGSM_OK) return st;
+    return d->param == DGSM_PARAM_OCTAHEDRAL ? DGSM_OK : DGSM_EUNSUPPORTED;
+}
+
 }  // namespace
 
 extern "C" size_t dgsm_mlp_workspace_size(int64_t batch) {
@@ -879,7 +887,7 @@ extern "C" size_t dgsm_mlp_workspace_size(int64_t batch) {
 extern "C" dgsm_status dgsm_mlp_grad(const float* params, const float* uvrt, int64_t B,
                                      const dgsm_atlas_desc_t* desc, float* grad, float* loss, void* ws,
                                      size_t ws_bytes, void* stream) {
-    dgsm_status st = validate_desc(desc);
+    dgsm_status st = validate_mlp_desc(desc);
     if (st != DGSM_OK) return st;
     if (!params || !uvrt || !grad || B < 32 || B % 32) return DGSM_EINVAL;
     const TrainWs w = train_ws(reinterpret_cast<unsigned char*>(ws), B);
@@ -902,7 +910,7 @@ extern "C" dgsm_status dgsm_mlp_grad(const float* params, const float* uvrt, int
 extern "C" dgsm_status dgsm_mlp_train(float* params, float* adam_mv, const dgsm_atlas_desc_t* desc,
                                       const void* atlas_l, const dgsm_mlp_train_t* opt, float* loss_out, void* ws,
                                       size_t ws_bytes, void* stream) {
-    dgsm_status st = validate_desc(desc);
+    dgsm_status st = validate_mlp_desc(desc);
     if (st != DGSM_OK) return st;
     if (!params || !adam_mv || !atlas_l || !opt || opt->steps < 0 || opt->batch < 32 || opt->batch % 32)
         return DGSM_EINVAL;
@@ -950,7 +958,7 @@ extern "C" size_t dgsm_mlp_infer_workspace_size(int32_t n_lights) {
 extern "C" dgsm_status dgsm_mlp_check(const float* params, const dgsm_atlas_desc_t* desc, const void* atlas_l,
                                       int64_t n_check, uint32_t seed, float thresh, unsigned char* mask,
                                       unsigned int* stats, void* ws, size_t ws_bytes, void* stream) {
-    dgsm_status st = validate_desc(desc);
+    dgsm_status st = validate_mlp_desc(desc);
     if (st != DGSM_OK) return st;
     if (!params || !atlas_l || !mask || !stats || n_check < 1) return DGSM_EINVAL;
     const size_t need = dgsm_mlp_infer_workspace_size(1) + ((sizeof(float4) * n_check + 255) & ~(size_t)255);
@@ -979,7 +987,7 @@ extern "C" dgsm_status dgsm_mlp_infer(const float* params, const dgsm_lights_t* 
                                       const dgsm_atlas_desc_t* desc, const void* atlas, const unsigned char* mask,
                                       const float* points, int64_t P, float* T, void* ws, size_t ws_bytes,
                                       void* stream) {
-    dgsm_status st = validate_desc(desc);
+    dgsm_status st = validate_mlp_desc(desc);
     if (st != DGSM_OK) return st;
     if ((st = validate_lights(lights)) != DGSM_OK) return st;
     if (!params || P < 0 || (P > 0 && (!points || !T)) || (mask && !atlas)) return DGSM_EINVAL;

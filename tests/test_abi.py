@@ -83,6 +83,28 @@ def test_invalid_descriptions_are_rejected(lib, bad):
     assert st == 1
 
 
+@pytest.mark.parametrize("H,W,ok", [(32, 48, True), (4, 6, True), (30, 45, True), (2, 3, False),
+                                     (32, 32, False), (48, 32, False), (31, 46, False)])
+def test_cube_map_descriptions(lib, H, W, ok):
+    import paper_2601_01660_amd as P
+    assert (P.dgsm_build_workspace_size(_desc(H=H, W=W, param="cubemap"), 10, 1) > 0) == ok
+
+
+def test_unknown_parameterisation_and_cube_map_learned_field_are_rejected(lib):
+    import paper_2601_01660_amd as P
+    d = _desc().struct()
+    d.param = 7
+    assert lib.dgsm_build_workspace_size(ctypes.byref(d), 10, 1) == 0
+    cube = _desc(H=32, W=48, param="cubemap").struct()
+    stats = (ctypes.c_uint32 * 4)()
+    # validation comes first: the device pointers are never dereferenced
+    st = lib.dgsm_mlp_check(1, ctypes.byref(cube), 1, 16, 1, ctypes.c_float(0.01), 1, stats, 1, 1 << 40, None)
+    assert st == 4
+    octa = _desc().struct()
+    st = lib.dgsm_mlp_check(1, ctypes.byref(octa), 1, 16, 1, ctypes.c_float(0.01), 1, stats, 1, 16, None)
+    assert st == 2                         # octahedral passes, then the workspace is too small
+
+
 def test_null_pointers_and_small_workspace_are_rejected(lib):
     import paper_2601_01660_amd as P
     d = _desc().struct()

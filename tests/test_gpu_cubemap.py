@@ -1,0 +1,128 @@
+"""GPU: the cube-map atlas parameterisation (Ablation C).
+
+Build, query, region of interest and the batched plan on a 2F x 3F cube-map
+atlas against the FP64 oracle's reading of the cube map (faces by major axis,
+bilinear inside a face, clamped at its edges).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import dgsm as od
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def scene():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2601_01660_amd as P
+    P.lib()
+    rng = np.random.default_rng(123)
+    # occluders all around the light, so that every face holds shadow
+    g = synth.random_gaussians(rng, rng.uniform(-2.0, 2.0, (900, 3)), 0.06)
+    lights = np.array([[0.1, -0.2, 0.15], [0.9, 0.4, -0.3]], np.float32)
+    return dict(g=g, lights=lights, rng=rng)
+
+
+@pytest.mark.parametrize("F", [16, 13])
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 1e-3)])
+def test_cube_build_matches_oracle(scene, F, dtype, tol):
+    """Every texel and shell; F = 13 puts 8 x 8 tiles across face boundaries."""
+    import paper_2601_01660_amd as P
+    K = 12
+    atlas = P.Atlas.cube(F, K, dtype=dtype)
+    T = P.dgsm_build(torch.from_numpy(scene["lights"]), P.GaussianSet.from_host(scene["g"]), atlas)
+    torch.cuda.synchronize()
+    assert T.shape == (2, K, 2 * F, 3 * F)
+    for l in range(2):
+        ref = od.build(scene["lights"][l], scene["g"], 2 * F, 3 * F, K, param="cubemap")
+        err = np.abs(T[l].float().cpu().numpy() - ref).max()
+        print(f"[cube] F={F} {dtype} light {l}: max|dT| {err:.3e}, min T {ref.min():.3f}")
+        assert ref.min() < 0.3 and err <= tol
+
+
+def test_cube_query_matches_oracle_on_a_random_table(scene):
+    """Random table (an input, not a build): points in every face, on the cube
+    edges and corners (ties between axes), at the light and beyond the shells."""
+    import paper_2601_01660_amd as P
+    F, K = 8, 10
+    rng = np.random.default_rng(5)
+    table = rng.uniform(0, 1, (2, K, 2 * F, 3 * F)).astype(np.float32)
+    lights = scene["lights"]
+    pts = [rng.uniform(-5, 5, (3000, 3))]
+    e = rng.uniform(0.1, 3.0, (200, 1)) * np.array([1.0, -1.0, 0.3]) # |x| == |y| exactly
+    pts.append(lights[0] + e)
+    pts.append(lights[0] + rng.choice([-1.0, 1.0], (200, 3)) * rng.uniform(0.1, 3.0, (200, 1)))   # corners
+    pts.append(lights[0][None, :] + np.zeros((3, 3)))                                                 # r = 0
+    pts.append(rng.normal(size=(100, 3)) * 30.0)                                                      # r > r1
+    pts = np.concatenate(pts).astype(np.float32)
+    atlas = P.Atlas.cube(F, K, dtype="f32")
+    got = P.dgsm_query(torch.from_numpy(lights), atlas, torch.from_numpy(table).cuda(), torch.from_numpy(pts))
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.float64)
+    for l in range(2):
+        ref = od.query(table[l].astype(np.float64), lights[l], pts, param="cubemap")
+        err = np.abs(got[l] - ref).max()
+        print(f"[cube] query light {l}: {pts.shape[0]} points, max|dT| {err:.3e}")
+        assert err <= 2e-5
+
+
+def test_cube_region_of_interest(scene):
+    import paper_2601_01660_amd as P
+    F, K = 12, 10
+    g = scene["g"]
+    rng = np.random.default_rng(8)
+    rec = g.mean[rng.choice(g.n, 120, replace=False)]
+    atlas = P.Atlas.cube(F, K, dtype="f32")
+    lights = torch.from_numpy(scene["lights"])
+    gs = P.GaussianSet.from_host(g)
+    full = P.dgsm_build(lights, gs, atlas)
+    roi = P.dgsm_build_roi(lights, gs, atlas, torch.from_numpy(rec))
+    qf = P.dgsm_query(lights, atlas, full, torch.from_numpy(rec))
+    qr = P.dgsm_query(lights, atlas, roi, torch.from_numpy(rec))
+    torch.cuda.synchronize()
+    err = (qf - qr).abs().max().item()
+    frac = (roi == 1).float().mean().item()
+    ref = od.build_roi(scene["lights"][0], g, 2 * F, 3 * F, K, rec, param="cubemap")
+    bad = np.abs(roi[0].cpu().numpy() - ref) > 1e-4
+    print(f"[cube] roi: receivers' queries vs full {err:.3e}; T == 1 on {frac:.3f}; entries off the oracle {bad.sum()}")
+    assert err <= 1e-6 and 0.1 < frac < 1.0
+    # the device picks the lookup cell in FP32: a receiver within rounding of
+    # a texel or shell boundary may mark a neighbouring cell
+    assert bad.sum() <= 2 * K
+
+
+def test_cube_plan_matches_plain_builds_and_oracle(scene):
+    import paper_2601_01660_amd as P
+    rng = np.random.default_rng(9)
+    static = synth.random_gaussians(rng, rng.uniform(-3, 3, (3000, 3)) * np.array([1, 1, 0.4]) + [0, 0, 1.2], 0.05)
+    dyn = synth.random_gaussians(rng, rng.uniform(-0.3, 0.3, (400, 3)) + [0.8, 0.2, 1.0], 0.02)
+    traj = synth.random_walk(rng, 4, step=0.1, start=(0.8, 0.2))
+    lights = np.array([[0.0, 0.0, 2.8], [1.5, -1.0, 2.5]], np.float32)
+    F, K = 16, 12
+    atlas = P.Atlas.cube(F, K, dtype="f32")
+    plan = P.Plan(torch.from_numpy(lights), atlas, P.GaussianSet.from_host(static), dyn.n, traj.shape[0],
+                  static_cache=True, autotune=False, tile_waves=4)
+    out = plan.run(P.GaussianSet.from_host(dyn), torch.from_numpy(traj).cuda(), use_graph=False)
+    torch.cuda.synchronize()
+    lt = torch.from_numpy(lights).cuda()
+    for f in range(traj.shape[0]):
+        g = synth.Gaussians.concat([static, dyn.translated(traj[f])])
+        gs = P.GaussianSet.from_host(g)
+        T = P.dgsm_build(lt, gs, atlas)
+        q = P.dgsm_query(lt, atlas, T, gs.mean)
+        torch.cuda.synchronize()
+        err = (out[f] - q).abs().max().item()
+        assert err <= 2e-6, (f, err)
+    f = 2
+    g = synth.Gaussians.concat([static, dyn.translated(traj[f])])
+    for l in range(2):
+        T = od.build(lights[l], g, 2 * F, 3 * F, K, param="cubemap")
+        q = od.query(T, lights[l], g.mean, param="cubemap")
+        err = np.abs(out[f, l].cpu().numpy() - q).max()
+        print(f"[cube] plan frame {f} light {l} vs oracle: {err:.3e}")
+        assert err <= 1e-4
+    plan.close()
