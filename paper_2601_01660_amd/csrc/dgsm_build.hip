@@ -182,8 +182,13 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
             double r2 = 3.0e38;                              // eps = 0: every texel is kept
             if (a.eps > 0.f) r2 = lim > (double)a.eps ? 2.0 * smax * smax * log(lim / (double)a.eps) : 0.0;
             r.r2 = (float)fmin(r2 * (1.0 + 1e-5), 3.0e38);
+            // The same bound on the whitened offset: 2 P0 <= 2 bp s_max exp(-e0/2)
+            // (a^(-1/2) <= s_max), so no texel with e0 >= 2 ln(2 bp s_max / eps) is kept.
+            double lg = 3.0e38;
+            if (a.eps > 0.f) lg = lim > (double)a.eps ? 2.0 * log(lim / (double)a.eps) : 0.0;
+            r.lg = (float)fmin(lg * (1.0 + 1e-5) + 1e-3, 3.0e38);
         }
-        r.pad[0] = r.pad[1] = 0.f;
+        for (int j = 0; j < 5; ++j) r.pad[j] = 0.f;
         W.rec[i] = r;
 
         // Culling cone.  Along any ray the contribution is at most
@@ -615,7 +620,7 @@ typedef const __attribute__((address_space(4))) f4v* ConstF4Ptr;
 
 struct RecRegs {
     double mx, my, mz;
-    float w[9], c[9], bp, r2;
+    float w[9], c[9], bp, r2, lg;
 };
 
 __device__ inline double as_double(float lo, float hi) {
@@ -635,10 +640,15 @@ __device__ inline RecRegs load_rec(ConstF4Ptr base, int gi) {
     r.c[5] = q5.x; r.c[6] = q5.y; r.c[7] = q5.z; r.c[8] = q5.w;
     r.bp = q6.x;
     r.r2 = q6.y;
+    r.lg = q6.z;
     return r;
 }
 
 __device__ inline int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// Wave ballot of a lane predicate straight into a scalar mask (no detour
+// through a 0/1 vector register and a second compare).
+__device__ inline uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 
 __device__ inline uint64_t readlane_u64(uint64_t v, int l) {
     const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -659,8 +669,8 @@ __device__ inline double readlane_d(double v, int l) {
 constexpr float kFixScale = 4294967296.f;   // 2^32
 
 __device__ inline unsigned long long to_fixed(float v) {
-    const unsigned int hi = (unsigned int)v;                           // v >= 0, truncates
-    const unsigned int lo = (unsigned int)((v - (float)hi) * kFixScale);   // exact product, < 2^32
+    const unsigned int hi = (unsigned int)v;                                    // v >= 0, truncates
+    const unsigned int lo = (unsigned int)(__builtin_amdgcn_fractf(v) * kFixScale);   // exact product, < 2^32
     return ((unsigned long long)hi << 32) | lo;
 }
 
@@ -673,6 +683,7 @@ struct TexelState {
     double dx, dy, dz;       // texel direction, FP64
     float fx, fy, fz;        // the same, FP32
     bool valid;
+    uint64_t vmask;          // ballot of valid: the lanes that hold a texel of the atlas
     int lane;
     float lr0, kinv;         // shell coordinate of a radius: (log2 t - lr0) * kinv (geometric)
     double ratio;            // t_{k+1} / t_k (geometric) or t_{k+1} - t_k (uniform)
@@ -704,7 +715,6 @@ struct Counters {
     unsigned long long idle = 0;        // pairs of which no texel lane was active
     unsigned long long ramp_wave = 0;   // shell iterations of the wave (SIMD work of the ramp)
     unsigned long long pre = 0;         // idle pairs already rejected by the distance pre-test
-    int klo = 1 << 30, khi = -1;        // shells this lane added to (always tracked: partial-sum rows)
 };
 
 template <bool STATS, bool GEO>
@@ -717,7 +727,7 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     const double te = -(r.mx * s.dx + r.my * s.dy + r.mz * s.dz);
     const float vx = (float)vxd, vy = (float)vyd, vz = (float)vzd;
     // cheap pre-test (conservative: it never drops a texel the full test keeps)
-    if (__ballot(s.valid && vx * vx + vy * vy + vz * vz < r.r2) == 0ull) {
+    if ((ballot(vx * vx + vy * vy + vz * vz < r.r2) & s.vmask) == 0ull) {
         if (STATS) {
             n.idle += 1;
             n.pre += 1;
@@ -732,13 +742,19 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     const float cv0 = r.c[0] * vx + r.c[1] * vy + r.c[2] * vz;
     const float cv1 = r.c[3] * vx + r.c[4] * vy + r.c[5] * vz;
     const float cv2 = r.c[6] * vx + r.c[7] * vy + r.c[8] * vz;
+    const float cc = cv0 * cv0 + cv1 * cv1 + cv2 * cv2;
+    // second conservative test, free of transcendentals: e0 = cc / a >= lg
+    if ((ballot(cc < r.lg * a) & s.vmask) == 0ull) {
+        if (STATS) n.idle += 1;
+        return;
+    }
     const float ra = __builtin_amdgcn_rcpf(a);
-    const float e0 = (cv0 * cv0 + cv1 * cv1 + cv2 * cv2) * ra;
+    const float e0 = cc * ra;
     const float rsa = __builtin_amdgcn_rsqf(a);
     // prefactor of Eq. 3 times beta: beta sqrt(pi / (2a)) exp(-e0 / 2)
     const float P0 = r.bp * rsa * __expf(-0.5f * e0);
     const bool act = s.valid && (P0 + P0 > s.pair_eps);
-    const uint64_t abal = __ballot(act);
+    const uint64_t abal = ballot(P0 + P0 > s.pair_eps) & s.vmask;
     if (abal == 0ull) {
         if (STATS) n.idle += 1;
         return;
@@ -777,29 +793,29 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
             ka = k0;
         }
     }
-    if (len > 0) {
-        n.klo = min(n.klo, ka);
-        n.khi = max(n.khi, ka + len - 1);
-    }
-    const int maxlen = wave_max(len);
-    if (maxlen <= 0) return;
+    if (ballot(len > 0) == 0ull) return;
     if (STATS) {
         int sum = len;
         for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, kWave);
         n.ramp += (unsigned long long)sum;
-        n.ramp_wave += (unsigned long long)maxlen;
+        n.ramp_wave += (unsigned long long)wave_max(len);
     }
-    // erf argument at shell k: sqrt(a/2) (t_k - t*), with t* = t_e - corr kept in FP64
+    // erf argument at shell k: sqrt(a/2) (t_k - t*), with t* = t_e - corr kept in FP64.
+    // The loop runs until no lane has shells left; a finished lane reads on
+    // into the padding of the shell table (2K - 1 entries) and adds nothing.
     const double tsd = te - (double)corr;
-    const int klast = s.K - 1 - ka;                  // table index stays in range past this lane's end
+    const double* sh = s.shells + ka;
     unsigned long long* dst = s.inc + ka * kWave + s.lane;
-    for (int j = 0; j < maxlen; ++j) {
-        const float x = sa * (float)(s.shells[ka + min(j, klast)] - tsd);
-        const float Ek = erf_as(x);
-        const float E = Ek > Ep ? Ek : Ep;           // keep the increments non-negative
+    for (int j = 0;; ++j) {
+        const bool live = j < len;
+        if (ballot(live) == 0ull) break;
+        const float x = sa * (float)(sh[j] - tsd);
+        // erf_as is non-decreasing up to rounding; a negative step from a
+        // rounding dip is skipped and the next step spans the dip
+        const float E = erf_as(x);
         const float dI = P0 * (E - Ep);
         Ep = E;
-        if (j < len && dI > 0.f)
+        if (live && dI > 0.f)
             __hip_atomic_fetch_add(dst, to_fixed(dI), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         dst += kWave;
     }
@@ -819,7 +835,7 @@ __device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* 
     const int nw = o < ns ? (ns - 1 - o) / S + 1 : 0;   // words of this wave
     for (int mbase = 0; mbase < nw; mbase += 64) {
         const uint64_t wv = mbase + lane < nw ? words[(size_t)(mbase + lane) * S + o] : 0ull;
-        uint64_t nz = __ballot(wv != 0ull);
+        uint64_t nz = ballot(wv != 0ull);
         if (nz == 0ull) continue;
         int gv = list[64 * ((mbase + __builtin_ctzll(nz)) * S + o) + lane];
         while (nz) {
@@ -976,7 +992,7 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     // slices of split tiles (block-uniform, so the early return is safe).
     int tile, slice, nslice, pidx;
     if ((int)blockIdx.x < g.ntiles) {
-        tile = blockIdx.x;
+        tile = xcd_tile(g, blockIdx.x);
         if (p.skip_empty && W.hits[tile] == 0) return;
         if (p.roi && W.roi_mask[tile] == 0ull) {          // no receiver here: T = 1 by construction
             const size_t plane = (size_t)g.H * g.W;
@@ -1009,6 +1025,7 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
 
     TexelState st;
     st.valid = py < g.H && px < g.W;
+    st.vmask = ballot(st.valid);
     st.lane = lane;
     if constexpr (CUBE)
         cube_texel_dir(min(py, g.H - 1), min(px, g.W - 1), g.F, st.dx, st.dy, st.dz);
@@ -1020,7 +1037,7 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     st.pair_eps = p.pair_eps;
     st.inc = inc;
     double* shells = reinterpret_cast<double*>(inc + K * kWave + NW * kWave) + (NW * kWave) / 2;   // after s_min
-    for (int k = tid; k < K; k += kWave * NW) shells[k] = shell_radius(k, K, g.spacing, g.r0, g.r1);
+    for (int k = tid; k < 2 * K - 1; k += kWave * NW) shells[k] = shell_radius(min(k, K - 1), K, g.spacing, g.r0, g.r1);
     st.shells = shells;
     st.kmin = p.roi ? W.roi_k[0] : 0;
     st.kmax = p.roi ? W.roi_k[1] : K - 1;
@@ -1054,13 +1071,6 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     __syncthreads();
 
     walk_hits<STATS, GEO>(words, ns, slice * NW + wave, nslice * NW, list, rec, st, n);
-    if (pidx >= 0) {
-        const int lo = wave_min(min(n.klo, K)), hi = wave_max(n.khi);
-        if (lane == 0 && lo <= hi) {
-            atomicMin(rows, lo);
-            atomicMax(rows + 1, hi);
-        }
-    }
 
     if (STATS) {
         const unsigned long long nvalid = __popcll(__ballot(st.valid));
@@ -1076,7 +1086,14 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
         }
     }
     __syncthreads();
-    if (pidx >= 0) {           // a slice of a split tile: leave its partial sums (rows it touched)
+    if (pidx >= 0) {           // a slice of a split tile: leave its partial sums (its non-zero rows)
+        for (int k = wave; k < K; k += NW) {
+            if (ballot(inc[k * kWave + lane] != 0ull) != 0ull && lane == 0) {
+                atomicMin(rows, k);
+                atomicMax(rows + 1, k);
+            }
+        }
+        __syncthreads();
         const int lo = rows[0], hi = rows[1];
         unsigned long long* dst = W.part + (size_t)pidx * K * kWave;
         for (int q = lo * kWave + tid; q < (hi + 1) * kWave; q += kWave * NW) dst[q] = inc[q];
@@ -1171,10 +1188,11 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
 }
 
 // LDS of a tile block: increments [K][64] (u64), then the finish's wave totals
-// [NW][64] (u64) and wave minima [NW][64] (f32), then the shell radii [K] (FP64).
+// [NW][64] (u64) and wave minima [NW][64] (f32), then the shell radii [K] (FP64)
+// and K - 1 copies of the last radius (read by lanes whose ramp has ended).
 size_t tile_smem_bytes(const Geom& g, int nw) {
     return (size_t)g.K * kWave * sizeof(unsigned long long) + (size_t)nw * kWave * (sizeof(unsigned long long) + 4) +
-           (size_t)g.K * sizeof(double);
+           (size_t)(2 * g.K - 1) * sizeof(double);
 }
 
 template <typename OutT, bool STATS, int NW, bool CUBE>

@@ -51,16 +51,41 @@ inline Geom make_geom(const dgsm_atlas_desc_t& d) {
 
 // Per-(light, Gaussian) record read by the tile build with wave-uniform
 // (scalar) loads.  w_j = R e_j / s_j are the rows of the whitening W with
-// A = W^T W; c_j = R e_j / (s_k s_l) are the rows of adj(A)^(1/2).
+// A = W^T W; c_j = R e_j / (s_k s_l) are the rows of adj(A)^(1/2).  Padded to
+// 128 bytes: with the record array 128-byte aligned, every record is exactly
+// one L2 line (a 112-byte record straddles two lines seven times in eight).
 struct __attribute__((aligned(16))) GRec {
     double mx, my, mz;   // o_L - mu, exact in FP64
     float w[9];
     float c[9];
     float bp;            // beta * sqrt(pi / 2)
     float r2;            // squared ray-to-mean distance beyond which no texel is active
-    float pad[2];
+    float lg;            // e0 = |adj(A)^(1/2) (m x d)|^2 / a at or beyond which no texel is active
+    float pad[5];
 };
-static_assert(sizeof(GRec) == 112, "GRec layout");
+static_assert(sizeof(GRec) == 128, "GRec layout");
+
+// Tile of tile-build block b (b < ntiles) in an XCD-aware order.  Workgroups
+// are dealt to the eight XCDs round-robin, so blocks b = x, x + 8, ... share
+// XCD x and its L2.  Runs of C = 8 consecutive tiles of the supertile-major
+// order (all tiles of supertile 0, then supertile 1, ...) go to one XCD, and
+// the XCDs take turns run by run: tiles in flight on one XCD are neighbours
+// in the atlas and walk largely the same Gaussian records (L2 hits), while
+// every XCD still gets tiles from all over the atlas (balanced work).  Blocks
+// past the last whole group of 64 take the rest of the order in block order.
+__host__ __device__ inline int xcd_tile(const Geom& g, int b) {
+    const int n = g.ntiles, C = 8, full = n / (8 * C) * (8 * C);
+    const int x = b % 8, r = b / 8;
+    const int o = b < full ? ((r / C) * 8 + x) * C + r % C : b;   // position in supertile-major order
+    const int sy = o / (g.STH * g.TW);                   // supertile row (full rows before it)
+    const int o1 = o - sy * g.STH * g.TW;
+    const int hy = g.TH - sy * g.STH < g.STH ? g.TH - sy * g.STH : g.STH;
+    const int sx = o1 / (hy * g.STW);                    // supertile in that row (full ones before it)
+    const int o2 = o1 - sx * hy * g.STW;
+    const int ntx = g.TW - sx * g.STW < g.STW ? g.TW - sx * g.STW : g.STW;
+    const int ly = o2 / ntx;
+    return (sy * g.STH + ly) * g.TW + sx * g.STW + (o2 - ly * ntx);
+}
 
 // Octahedral decode of the texel centre (i, j) of an H x W atlas (Sec. 3.2).
 __device__ inline void octa_texel_dir(int i, int j, int H, int W, double& x, double& y, double& z) {
@@ -235,21 +260,21 @@ extern "C" __device__ int __ockl_wfred_max_i32(int);
 __device__ inline int wave_min(int v) { return __ockl_wfred_min_i32(v); }
 __device__ inline int wave_max(int v) { return __ockl_wfred_max_i32(v); }
 
-// erf(x) by the rational approximation of Abramowitz and Stegun, Handbook of
-// Mathematical Functions, 7.1.26 (after Hastings): for z = |x| >= 0,
-// erf(z) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-z^2),
-// t = 1 / (1 + p z); absolute error below 1.5e-7.  Branch-free: a reciprocal,
-// a degree-5 Horner chain and an exponential; saturates to +-1 exactly.
+// erf(x) by Abramowitz and Stegun, Handbook of Mathematical Functions, 7.1.28
+// (after Hastings): for z = |x| >= 0, erf(z) = 1 - (1 + a1 z + ... + a6 z^6)^-16,
+// absolute error below 3e-7.  One reciprocal and no exponential; the
+// 16th power overflows to +inf for large z, which saturates to +-1 exactly.
 __device__ inline float erf_as(float x) {
     const float z = fabsf(x);
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, z, 1.f));
-    float p = 1.061405429f;
-    p = fmaf(t, p, -1.453152027f);
-    p = fmaf(t, p, 1.421413741f);
-    p = fmaf(t, p, -0.284496736f);
-    p = fmaf(t, p, 0.254829592f);
-    const float ec = t * p * __expf(-z * z);
-    return copysignf(1.f - ec, x);
+    float p = 0.0000430638f;
+    p = fmaf(z, p, 0.0002765672f);
+    p = fmaf(z, p, 0.0001520143f);
+    p = fmaf(z, p, 0.0092705272f);
+    p = fmaf(z, p, 0.0422820123f);
+    p = fmaf(z, p, 0.0705230784f);
+    p = fmaf(z, p, 1.f);
+    p *= p; p *= p; p *= p; p *= p;
+    return copysignf(1.f - __builtin_amdgcn_rcpf(p), x);
 }
 
 __device__ inline int lane_id() { return __lane_id(); }

@@ -88,6 +88,22 @@ def test_cfg1_denser_ragged_two_lights():
         assert np.abs(q - od.query(ref, lights[l], pts)).max() <= TOL
 
 
+def test_partial_supertiles_and_tile_order_tail():
+    """80 x 76 texels: 10 x 10 tiles in four supertiles, three of them partial;
+    100 tile blocks, so the XCD-aware tile order covers whole groups of 64 and
+    a tail.  Every texel and shell against the oracle."""
+    U = _util()
+    c = synth.cfg1()
+    g = c["gaussians"]
+    lights = np.array([[0.3, -0.2, 0.4]], np.float32)
+    spec = synth.AtlasSpec(76, 80, 8)
+    T, atlas = U.gpu_build(g, lights, spec)
+    ref = od.build(lights[0], g, spec.H, spec.W, spec.K)
+    err = np.abs(T[0].cpu().numpy().astype(np.float64) - ref).max()
+    _report("76x80x8 partial supertiles", err)
+    assert ref.min() < 0.5 and err <= TOL
+
+
 def test_uniform_shells_and_kappa():
     U = _util()
     c = synth.cfg1(1500)
