@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
         for (int s = 64 * q; s < min(a.S, 64 * q + 64); ++s) {
             const bool b = in && cones_touch(cone, sc[s]);
             mq |= (uint64_t)b << (s & 63);
-            const uint64_t bal = __ballot(b);
+            const uint64_t bal = ballot(b);
             if (lane == 0) wcnt[w][s] = __popcll(bal);
         }
         m[q] = mq;
@@ -301,13 +301,13 @@ __global__ __launch_bounds__(kPrepThreads) void scatter_kernel(unsigned char* ws
     if (i < n)
         for (int q = 0; q < kMaskWords; ++q) m[q] = W.mask[(size_t)i * kMaskWords + q];
     for (int s = 0; s < S; ++s) {
-        const uint64_t bal = __ballot((m[s >> 6] >> (s & 63)) & 1ull);
+        const uint64_t bal = ballot((m[s >> 6] >> (s & 63)) & 1ull);
         if (lane == 0) wcnt[w][s] = __popcll(bal);
     }
     __syncthreads();
     for (int s = 0; s < S; ++s) {
         const bool b = (m[s >> 6] >> (s & 63)) & 1ull;
-        const uint64_t bal = __ballot(b);
+        const uint64_t bal = ballot(b);
         if (b) {
             int off = base_s[s];
             for (int ww = 0; ww < w; ++ww) off += wcnt[ww][s];
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
                                           __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc.y), q)),
                                           __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc.z), q)),
                                           __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc.w), q)));
-            if (__ballot(cones_touch(cone, bq)) == 0ull) continue;
+            if (ballot(cones_touch(cone, bq)) == 0ull) continue;
             const int qy = q / nqx_s, qx = q - qy * nqx_s;
             for (int d = 0; d < 4; ++d) {
                 const int ly = 2 * qy + (d >> 1), lx = 2 * qx + (d & 1);   // tile inside the supertile
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
                                              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.y), t)),
                                              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.z), t)),
                                              __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.w), t)));
-                const uint64_t bal = __ballot(cones_touch(cone, b));
+                const uint64_t bal = ballot(cones_touch(cone, b));
                 if (lane == t) mine = bal;
             }
         }
@@ -646,9 +646,6 @@ __device__ inline RecRegs load_rec(ConstF4Ptr base, int gi) {
 
 __device__ inline int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
-// Wave ballot of a lane predicate straight into a scalar mask (no detour
-// through a 0/1 vector register and a second compare).
-__device__ inline uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 
 __device__ inline uint64_t readlane_u64(uint64_t v, int l) {
     const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
@@ -1073,7 +1070,7 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     walk_hits<STATS, GEO>(words, ns, slice * NW + wave, nslice * NW, list, rec, st, n);
 
     if (STATS) {
-        const unsigned long long nvalid = __popcll(__ballot(st.valid));
+        const unsigned long long nvalid = __popcll(ballot(st.valid));
         if (lane == 0) {
             atomicAdd(p.stats + 0, n.hits * nvalid);
             atomicAdd(p.stats + 1, n.act);
@@ -1108,6 +1105,7 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
 // Split tiles: the slices' partial sums are added in slice order into LDS
 // (wave w sums shells w, w + 8, ...), then the tile is finished as above.
 constexpr int kFinishWaves = 8;
+constexpr int kSliceBatch = 4;
 
 template <typename OutT>
 __global__ __launch_bounds__(kWave * kFinishWaves) void split_finish_kernel(TileArgs p) {
@@ -1128,13 +1126,24 @@ __global__ __launch_bounds__(kWave * kFinishWaves) void split_finish_kernel(Tile
         unsigned long long v[kFinishGroup];
 #pragma unroll
         for (int j = 0; j < kFinishGroup; ++j) v[j] = 0ull;
-        for (int i = 0; i < q; ++i) {
-            const int2 r = W.prange[sp.y + i];        // rows slice i wrote
-            if (r.y < k0 || r.x >= k0 + n) continue;
-            const unsigned long long* s0 = src + (size_t)i * slice + (size_t)k0 * kWave;
+        // kSliceBatch slices at a time: all their row loads are in flight together
+        // (a tile can have up to kMaxSlices slices; one at a time, the loop
+        // would pay one memory latency per slice)
+        for (int i0 = 0; i0 < q; i0 += kSliceBatch) {
+            unsigned long long t[kSliceBatch][kFinishGroup];
 #pragma unroll
-            for (int j = 0; j < kFinishGroup; ++j)
-                if (j < n && k0 + j >= r.x && k0 + j <= r.y) v[j] += s0[(size_t)j * kWave];
+            for (int u = 0; u < kSliceBatch; ++u) {
+                const int i = i0 + u;
+                const int2 r = i < q ? W.prange[sp.y + i] : make_int2(K, -1);   // rows slice i wrote
+                const unsigned long long* s0 = src + (size_t)(i < q ? i : 0) * slice + (size_t)k0 * kWave;
+#pragma unroll
+                for (int j = 0; j < kFinishGroup; ++j)
+                    t[u][j] = (j < n && k0 + j >= r.x && k0 + j <= r.y) ? s0[(size_t)j * kWave] : 0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < kSliceBatch; ++u)
+#pragma unroll
+                for (int j = 0; j < kFinishGroup; ++j) v[j] += t[u][j];
         }
 #pragma unroll
         for (int j = 0; j < kFinishGroup; ++j)

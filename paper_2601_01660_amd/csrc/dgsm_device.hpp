@@ -253,6 +253,10 @@ __device__ inline void real_sh16(float x, float y, float z, int kp, float* Y) {
     Y[15] = c3a * x * (x * x - 3.f * y * y);
 }
 
+// Wave ballot of a lane predicate straight into a scalar mask (no detour
+// through a 0/1 vector register and a second compare).
+__device__ inline uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+
 extern "C" __device__ int __ockl_wfred_min_i32(int);
 extern "C" __device__ int __ockl_wfred_max_i32(int);
 
