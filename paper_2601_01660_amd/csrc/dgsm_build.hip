@@ -90,6 +90,12 @@ __global__ __launch_bounds__(64) void super_cone_kernel(Geom g, const float4* __
     scone[s] = make_float4((float)ax, (float)ay, (float)az, inflate_sh(sin(0.5 * half)));
 }
 
+// cone_cos of n cones, stored beside them for the cone tests.
+__global__ __launch_bounds__(64) void cone_cos_kernel(const float4* __restrict__ c, float* __restrict__ cs, int n) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i < n) cs[i] = cone_cos(c[i]);
+}
+
 // ---------------------------------------------------------------------------
 // Workspace slices
 // ---------------------------------------------------------------------------
@@ -123,18 +129,25 @@ struct PrepArgs {
     float kappa;
     int beta_mode;         // dgsm_beta_mode
     float eps;             // culling budget (0: no culling)
-    int S;
+    int S, SGH, SGW;       // supertile count and grid
     BuildLayout lay;
     unsigned char* ws;
 };
 
 __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
-    __shared__ int wcnt[kPrepThreads / kWave][kMaxSuper];
-    __shared__ float4 sc[kMaxSuper];     // supertile cones
-    const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
+    __shared__ int bcnt[kMaxSuper];          // this block's entries per supertile
+    __shared__ float4 sc[kMaxSuper];         // supertile cones
+    __shared__ float scs[kMaxSuper];         // and their cone_cos
+    __shared__ float4 gc[kMaxSuper / 4];     // cones of 2x2-supertile groups
+    __shared__ float gcs[kMaxSuper / 4];
+    const int tid = threadIdx.x;
     const int l = blockIdx.y;
     const LightWs W = light_ws(a.ws, a.lay, l);
     const float4* scone = reinterpret_cast<const float4*>(a.ws + a.lay.scone);
+    const float* scos = reinterpret_cast<const float*>(a.ws + a.lay.scos);
+    const float4* gcone = reinterpret_cast<const float4*>(a.ws + a.lay.gcone);
+    const float* gcos = reinterpret_cast<const float*>(a.ws + a.lay.gcos);
+    const int ngx = (a.SGW + 1) / 2, ng = ((a.SGH + 1) / 2) * ngx;
     const float* light = a.lights + 3 * l;
     const int64_t i = (int64_t)blockIdx.x * kPrepThreads + tid;
     const bool in = i < a.n;
@@ -177,15 +190,19 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
         // mu to the line of the ray), 2 P0 <= 2 bp s_max exp(-h^2/(2 s_max^2)):
         // no texel with h^2 >= 2 s_max^2 ln(2 bp s_max / eps) can be kept.
         const double smax = fmax(s[0], fmax(s[1], s[2]));
+        // one logarithm serves both pre-test bounds and the culling cone below:
+        // ln(U / eps) with U the larger of 2 bp s_max (bp as stored, FP32) and
+        // beta sqrt(2 pi) s_max (FP64), so each bound holds for either
+        const double U = fmax(amp * smax, 2.0 * (double)r.bp * smax);
+        const double lnU = (a.eps > 0.f && U > (double)a.eps) ? log(U / (double)a.eps) : 0.0;
         {
-            const double lim = 2.0 * (double)r.bp * smax;
             double r2 = 3.0e38;                              // eps = 0: every texel is kept
-            if (a.eps > 0.f) r2 = lim > (double)a.eps ? 2.0 * smax * smax * log(lim / (double)a.eps) : 0.0;
+            if (a.eps > 0.f) r2 = 2.0 * smax * smax * lnU;
             r.r2 = (float)fmin(r2 * (1.0 + 1e-5), 3.0e38);
             // The same bound on the whitened offset: 2 P0 <= 2 bp s_max exp(-e0/2)
             // (a^(-1/2) <= s_max), so no texel with e0 >= 2 ln(2 bp s_max / eps) is kept.
             double lg = 3.0e38;
-            if (a.eps > 0.f) lg = lim > (double)a.eps ? 2.0 * log(lim / (double)a.eps) : 0.0;
+            if (a.eps > 0.f) lg = 2.0 * lnU;
             r.lg = (float)fmin(lg * (1.0 + 1e-5) + 1e-3, 3.0e38);
         }
         for (int j = 0; j < 5; ++j) r.pad[j] = 0.f;
@@ -196,14 +213,14 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
         // the distance from mu to the ray (D for rays pointing away).  So it is
         // below eps outside the cone sin(theta) <= (s_max / D) sqrt(2 ln(U / eps)).
         const double D = sqrt(r.mx * r.mx + r.my * r.my + r.mz * r.mz);
-        const double U = amp * smax;
         if (!(alpha > 0.0) || !(U > (double)a.eps)) {
             cone.w = -1.f;                               // contributes nothing
         } else {
             double shalf = 1.0;                          // global: every direction
             if (a.eps > 0.f && D > 0.0) {
-                const double sig = smax / D * sqrt(2.0 * log(U / (double)a.eps));
-                if (sig < 1.0) shalf = sin(0.5 * asin(sig));
+                const double sig = smax / D * sqrt(2.0 * lnU);
+                // sin(theta / 2) for sin(theta) = sig: sig / sqrt(2 (1 + cos(theta)))
+                if (sig < 1.0) shalf = sig / sqrt(2.0 * (1.0 + sqrt(1.0 - sig * sig)));
             }
             const double gx = D > 0 ? -r.mx / D : 0.0, gy = D > 0 ? -r.my / D : 0.0,
                          gz = D > 0 ? -r.mz / D : 1.0;
@@ -211,28 +228,46 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
         }
         W.cone[i] = cone;
     }
-    for (int s = tid; s < a.S; s += kPrepThreads) sc[s] = scone[s];
+    for (int s = tid; s < a.S; s += kPrepThreads) {
+        sc[s] = scone[s];
+        scs[s] = scos[s];
+        bcnt[s] = 0;
+    }
+    for (int q = tid; q < ng; q += kPrepThreads) {
+        gc[q] = gcone[q];
+        gcs[q] = gcos[q];
+    }
     __syncthreads();
+    // Supertile mask, two levels: a group of 2 x 2 supertiles whose cone this
+    // Gaussian's cone misses holds no texel direction within the cone, so its
+    // supertiles are not tested (their tiles would all fail the tile test).
     uint64_t m[kMaskWords] = {0, 0, 0, 0};
-#pragma unroll
-    for (int q = 0; q < kMaskWords; ++q) {
-        uint64_t mq = 0;
-        for (int s = 64 * q; s < min(a.S, 64 * q + 64); ++s) {
-            const bool b = in && cones_touch(cone, sc[s]);
-            mq |= (uint64_t)b << (s & 63);
-            const uint64_t bal = ballot(b);
-            if (lane == 0) wcnt[w][s] = __popcll(bal);
+    const float ca = cone_cos(cone);
+    const bool live = in && cone.w >= 0.f;
+    for (int q = 0; q < ng; ++q) {
+        const bool hit_g = live && cones_touch_c(cone, ca, gc[q], gcs[q]);
+        if (ballot(hit_g) == 0ull) continue;
+        const int gy = q / ngx, gx = q - gy * ngx;
+        for (int d = 0; d < 4; ++d) {
+            const int sy = 2 * gy + (d >> 1), sx = 2 * gx + (d & 1);
+            if (sy >= a.SGH || sx >= a.SGW) continue;
+            const int sidx = sy * a.SGW + sx;
+            if (hit_g && cones_touch_c(cone, ca, sc[sidx], scs[sidx])) {
+                const uint64_t bit = 1ull << (sidx & 63);
+                switch (sidx >> 6) {
+                    case 0: m[0] |= bit; break;
+                    case 1: m[1] |= bit; break;
+                    case 2: m[2] |= bit; break;
+                    default: m[3] |= bit; break;
+                }
+                atomicAdd(&bcnt[sidx], 1);
+            }
         }
-        m[q] = mq;
     }
     if (in)
         for (int q = 0; q < kMaskWords; ++q) W.mask[(size_t)i * kMaskWords + q] = m[q];
     __syncthreads();
-    for (int s = tid; s < a.S; s += kPrepThreads) {
-        int c = 0;
-        for (int ww = 0; ww < kPrepThreads / kWave; ++ww) c += wcnt[ww][s];
-        W.counts[(size_t)s * a.lay.nb + blockIdx.x] = c;
-    }
+    for (int s = tid; s < a.S; s += kPrepThreads) W.counts[(size_t)s * a.lay.nb + blockIdx.x] = bcnt[s];
 }
 
 // ---------------------------------------------------------------------------
@@ -300,20 +335,32 @@ __global__ __launch_bounds__(kPrepThreads) void scatter_kernel(unsigned char* ws
     uint64_t m[kMaskWords] = {0, 0, 0, 0};
     if (i < n)
         for (int q = 0; q < kMaskWords; ++q) m[q] = W.mask[(size_t)i * kMaskWords + q];
-    for (int s = 0; s < S; ++s) {
-        const uint64_t bal = ballot((m[s >> 6] >> (s & 63)) & 1ull);
-        if (lane == 0) wcnt[w][s] = __popcll(bal);
-    }
+    for (int s = tid; s < (kPrepThreads / kWave) * kMaxSuper; s += kPrepThreads) (&wcnt[0][0])[s] = 0;
     __syncthreads();
-    for (int s = 0; s < S; ++s) {
-        const bool b = (m[s >> 6] >> (s & 63)) & 1ull;
-        const uint64_t bal = ballot(b);
-        if (b) {
-            int off = base_s[s];
-            for (int ww = 0; ww < w; ++ww) off += wcnt[ww][s];
-            W.lists[off + ballot_rank(bal)] = (int)i;
+    // only the supertiles some lane of this wave hits: the union of its masks
+    uint64_t u[kMaskWords];
+#pragma unroll
+    for (int q = 0; q < kMaskWords; ++q) u[q] = 64 * q < S ? wave_or(m[q]) : 0ull;
+#pragma unroll
+    for (int q = 0; q < kMaskWords; ++q)
+        for (uint64_t r = u[q]; r; r &= r - 1) {
+            const int s = 64 * q + __builtin_ctzll(r);
+            const uint64_t bal = ballot((m[q] >> (s & 63)) & 1ull);
+            if (lane == 0) wcnt[w][s] = __popcll(bal);
         }
-    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kMaskWords; ++q)
+        for (uint64_t r = u[q]; r; r &= r - 1) {
+            const int s = 64 * q + __builtin_ctzll(r);
+            const bool b = (m[q] >> (s & 63)) & 1ull;
+            const uint64_t bal = ballot(b);
+            if (b) {
+                int off = base_s[s];
+                for (int ww = 0; ww < w; ++ww) off += wcnt[ww][s];
+                W.lists[off + ballot_rank(bal)] = (int)i;
+            }
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -323,11 +370,19 @@ __global__ __launch_bounds__(kPrepThreads) void scatter_kernel(unsigned char* ws
 __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, BuildLayout lay, Geom g) {
     __shared__ int sbase[kMaxSuper + 1];
     __shared__ int stot[kMaxSuper];
+    // per wave: the cones (and cone_cos) of the tiles and quads of its current
+    // supertile, read back with wave-uniform addresses (broadcast)
+    __shared__ float4 ltc[4][kWave];
+    __shared__ float ltcs[4][kWave];
+    __shared__ float4 lqc[4][16];
+    __shared__ float lqcs[4][16];
     const LightWs W = light_ws(ws, lay, blockIdx.y);
     const float4* tcone = reinterpret_cast<const float4*>(ws + lay.tcone);
     const float4* qcone = reinterpret_cast<const float4*>(ws + lay.qcone);
+    const float* tcos = reinterpret_cast<const float*>(ws + lay.tcos);
+    const float* qcos = reinterpret_cast<const float*>(ws + lay.qcos);
     const int nqx = (g.TW + 1) / 2;
-    const int tid = threadIdx.x, lane = tid % kWave;
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     for (int s = tid; s <= g.S; s += 256) {
         sbase[s] = W.lbase[s];
         if (s < g.S) stot[s] = W.totals[s];
@@ -343,8 +398,6 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
     const int cbeg = min(nchunks, gw * per), cend = min(nchunks, cbeg + per);
     int s_cur = -1, cnt = 0;
     SuperSpan sp_cur{0, 0, 0, 0};
-    float4 tc = make_float4(0.f, 0.f, 1.f, -1.f);   // lane t: cone of tile t of the current supertile
-    float4 qc = make_float4(0.f, 0.f, 1.f, -1.f);   // lane q: cone of 2x2-tile quad q of it
     int q0y = 0, q0x = 0, nqy_s = 0, nqx_s = 0;
     for (int c = cbeg; c < cend; ++c) {
         // supertile of this chunk: the last s with sbase[s] <= 64 c
@@ -360,39 +413,41 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
             s_cur = s;
             cnt = 0;
             sp_cur = super_span(g, s);
-            tc = lane < sp_cur.nty * sp_cur.ntx
-                     ? tcone[(sp_cur.ty0 + lane / sp_cur.ntx) * g.TW + sp_cur.tx0 + lane % sp_cur.ntx]
-                     : make_float4(0.f, 0.f, 1.f, -1.f);
             q0y = sp_cur.ty0 / 2;                      // supertile origins are even (8-tile multiples)
             q0x = sp_cur.tx0 / 2;
             nqy_s = (sp_cur.nty + 1) / 2;
             nqx_s = (sp_cur.ntx + 1) / 2;
-            qc = lane < nqy_s * nqx_s ? qcone[(q0y + lane / nqx_s) * nqx + q0x + lane % nqx_s]
-                                      : make_float4(0.f, 0.f, 1.f, -1.f);
+            __builtin_amdgcn_wave_barrier();           // earlier reads of the cache are done
+            if (lane < sp_cur.nty * sp_cur.ntx) {
+                const int t = (sp_cur.ty0 + lane / sp_cur.ntx) * g.TW + sp_cur.tx0 + lane % sp_cur.ntx;
+                ltc[wv][lane] = tcone[t];
+                ltcs[wv][lane] = tcos[t];
+            }
+            if (lane < nqy_s * nqx_s) {
+                const int qi = (q0y + lane / nqx_s) * nqx + q0x + lane % nqx_s;
+                lqc[wv][lane] = qcone[qi];
+                lqcs[wv][lane] = qcos[qi];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
         const int e = 64 * c + lane;
         float4 cone = make_float4(0.f, 0.f, 1.f, -1.f);
         if (e < sbase[s] + stot[s]) cone = W.cone[W.lists[e]];
         const SuperSpan sp = sp_cur;
         const int nt = sp.nty * sp.ntx;
+        const float ca = cone_cos(cone);
         uint64_t mine = 0;
         // quads first: the tiles of a quad no lane's cone reaches are skipped
         for (int q = 0; q < nqy_s * nqx_s; ++q) {
-            const float4 bq = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc.x), q)),
-                                          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc.y), q)),
-                                          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc.z), q)),
-                                          __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qc.w), q)));
-            if (ballot(cones_touch(cone, bq)) == 0ull) continue;
+            if (ballot(cones_touch_c(cone, ca, lqc[wv][q], lqcs[wv][q])) == 0ull) continue;
             const int qy = q / nqx_s, qx = q - qy * nqx_s;
             for (int d = 0; d < 4; ++d) {
                 const int ly = 2 * qy + (d >> 1), lx = 2 * qx + (d & 1);   // tile inside the supertile
                 if (ly >= sp.nty || lx >= sp.ntx) continue;
                 const int t = ly * sp.ntx + lx;
-                const float4 b = make_float4(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.x), t)),
-                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.y), t)),
-                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.z), t)),
-                                             __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tc.w), t)));
-                const uint64_t bal = ballot(cones_touch(cone, b));
+                const uint64_t bal = ballot(cones_touch_c(cone, ca, ltc[wv][t], ltcs[wv][t]));
                 if (lane == t) mine = bal;
             }
         }
@@ -1171,6 +1226,11 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
     L.tcone = take((size_t)g.ntiles * sizeof(float4));
     L.scone = take((size_t)kMaxSuper * sizeof(float4));
     L.qcone = take((size_t)((g.TH + 1) / 2) * ((g.TW + 1) / 2) * sizeof(float4));
+    L.gcone = take((size_t)(kMaxSuper / 4) * sizeof(float4));
+    L.tcos = take((size_t)g.ntiles * sizeof(float));
+    L.scos = take((size_t)kMaxSuper * sizeof(float));
+    L.qcos = take((size_t)((g.TH + 1) / 2) * ((g.TW + 1) / 2) * sizeof(float));
+    L.gcos = take((size_t)(kMaxSuper / 4) * sizeof(float));
     L.light0 = off;
     off = 0;
     L.totals = take((size_t)kMaxSuper * sizeof(int));
@@ -1247,7 +1307,20 @@ dgsm_status enqueue_cones(const Geom& g, const BuildLayout& L, unsigned char* ws
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     const int nqx = (g.TW + 1) / 2, nq = ((g.TH + 1) / 2) * nqx;
     super_cone_kernel<<<(nq + 63) / 64, 64, 0, st>>>(g, tcone, qcone, nq, nqx, 2, 2);
-    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    float4* gcone = reinterpret_cast<float4*>(ws + L.gcone);
+    const int ngx = (g.SGW + 1) / 2, ng = ((g.SGH + 1) / 2) * ngx;
+    super_cone_kernel<<<(ng + 63) / 64, 64, 0, st>>>(g, tcone, gcone, ng, ngx, 2 * g.STH, 2 * g.STW);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    const float4* cones[4] = {tcone, scone, qcone, gcone};
+    const size_t cos_off[4] = {L.tcos, L.scos, L.qcos, L.gcos};
+    const int counts[4] = {g.ntiles, g.S, nq, ng};
+    for (int c = 0; c < 4; ++c) {
+        cone_cos_kernel<<<(counts[c] + 63) / 64, 64, 0, st>>>(cones[c], reinterpret_cast<float*>(ws + cos_off[c]),
+                                                              counts[c]);
+        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    }
+    return DGSM_OK;
 }
 
 dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
@@ -1255,7 +1328,7 @@ dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, 
     if (cones && enqueue_cones(g, L, ws, st) != DGSM_OK) return DGSM_EHIP;
     if (gs.n > 0) {
         PrepArgs pa{gs.mean, gs.scale, gs.rot, gs.opacity, gs.n, lights.pos, lights.kappa, lights.beta_mode, cull_eps,
-                    g.S, L, ws};
+                    g.S, g.SGH, g.SGW, L, ws};
         preprocess_kernel<<<dim3(L.nb, lights.n), kPrepThreads, 0, st>>>(pa);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }

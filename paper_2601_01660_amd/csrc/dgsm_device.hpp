@@ -131,10 +131,22 @@ __device__ inline void texel_dir(const Geom& g, int i, int j, double& x, double&
 // the angle between the axes is at most the sum of the half-angles.  Tested
 // with the chord |a - b| = 2 sin(angle / 2), which stays accurate for small
 // angles.  sh < 0 marks an empty cone.
+// cos of half the half-angle of a cone, as the cone tests use it.
+__device__ inline float cone_cos(float4 c) { return sqrtf(fmaxf(0.f, 1.f - c.w * c.w)); }
+
+// The same test with both cosines given (cone_cos of each): the form for
+// loops that test one cone against many whose cosines are stored.
+__device__ inline bool cones_touch_c(float4 a, float ca, float4 b, float cb) {
+    const float sh = a.w * cb + ca * b.w;        // sin((ta + tb) / 2)
+    const float chh = ca * cb - a.w * b.w;       // cos((ta + tb) / 2)
+    const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    return a.w >= 0.f && b.w >= 0.f && (chh <= 0.f || dx * dx + dy * dy + dz * dz <= 4.f * sh * sh);
+}
+
 __device__ inline bool cones_touch(float4 a, float4 b) {
     if (a.w < 0.f || b.w < 0.f) return false;
-    const float ca = sqrtf(fmaxf(0.f, 1.f - a.w * a.w));
-    const float cb = sqrtf(fmaxf(0.f, 1.f - b.w * b.w));
+    const float ca = cone_cos(a);
+    const float cb = cone_cos(b);
     const float sh = a.w * cb + ca * b.w;        // sin((ta + tb) / 2)
     const float chh = ca * cb - a.w * b.w;       // cos((ta + tb) / 2)
     if (chh <= 0.f) return true;                 // half-angles sum to >= pi
@@ -258,11 +270,15 @@ __device__ inline void real_sh16(float x, float y, float z, int kp, float* Y) {
 __device__ inline uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
 
 extern "C" __device__ int __ockl_wfred_min_i32(int);
+extern "C" __device__ unsigned int __ockl_wfred_or_u32(unsigned int);
 extern "C" __device__ int __ockl_wfred_max_i32(int);
 
 // Wave-wide integer min / max (DPP row reductions); call with all lanes active.
 __device__ inline int wave_min(int v) { return __ockl_wfred_min_i32(v); }
 __device__ inline int wave_max(int v) { return __ockl_wfred_max_i32(v); }
+__device__ inline uint64_t wave_or(uint64_t v) {
+    return ((uint64_t)__ockl_wfred_or_u32((unsigned int)(v >> 32)) << 32) | __ockl_wfred_or_u32((unsigned int)v);
+}
 
 // erf(x) by Abramowitz and Stegun, Handbook of Mathematical Functions, 7.1.28
 // (after Hastings): for z = |x| >= 0, erf(z) = 1 - (1 + a1 z + ... + a6 z^6)^-16,

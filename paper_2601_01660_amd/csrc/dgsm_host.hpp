@@ -51,6 +51,8 @@ struct BuildLayout {
     size_t cap;              // list / bitmap capacity per light (entries)
     size_t tcone, scone;     // absolute offsets: tile cones [ntiles], supertile cones [kMaxSuper]
     size_t qcone;            // absolute offset: cones of 2x2-tile quads [ceil(TH/2) * ceil(TW/2)]
+    size_t gcone;            // absolute offset: cones of 2x2-supertile groups [kMaxSuper / 4]
+    size_t tcos, scos, qcos, gcos;   // absolute offsets: cone_cos of each cone above
     size_t light0;           // absolute offset of light 0's slice
     size_t light_stride;     // bytes per light slice
     int units_cap;           // extra work units per light (tiles split over several blocks)
