@@ -28,7 +28,7 @@ METRIC = "DGSM build+query ms/frame (2M Gaussians, 4 lights); surrogate vs atlas
 FLOPS_PER_TILE_PAIR = 14      # distance pre-test (FP64 m x d, |m x d|^2): every binned (texel, Gaussian) pair
 FLOPS_PER_TESTED_PAIR = 53    # m.d, W d, a, adj(A)^1/2 (m x d), e0, prefactor: pairs of waves past the pre-test
 FLOPS_PER_ACTIVE_PAIR = 45    # closest-approach distance, erf scale, shell range: pairs above cull_eps
-FLOPS_PER_RAMP_EVAL = 27      # one shell of the erf ramp: argument, erf, increment
+FLOPS_PER_RAMP_EVAL = 22      # one shell of the erf ramp: argument 2, erf 18 (A&S 7.1.28), increment 2
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
@@ -38,7 +38,9 @@ PEAK_HBM_GBS = 8000.0
 # device copy.  Valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("paper_2601_01660_amd/csrc/dgsm_build.hip", "paper_2601_01660_amd/csrc/dgsm_device.hpp",
                    "paper_2601_01660_amd/csrc/dgsm_host.hpp")
-TRAFFIC = None   # {"sha256": ..., "fetch_bytes": ..., "write_bytes": ..., "profile": ...}
+TRAFFIC = {"sha256": "7911b64c9cddcda41c13240375d169c5d5fc22ea400e2ded4bba4f323a2970eb",
+           "fetch_bytes": 34980595997, "write_bytes": 1191475749,
+           "profile": "profiles/tile_build_counters__room2M_avatar150k_4lights_512x512x64_f16.md"}
 
 
 def measured_traffic():
