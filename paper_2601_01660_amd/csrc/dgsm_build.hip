@@ -1241,7 +1241,15 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
     L.counts = take((size_t)g.S * (size_t)L.nb * sizeof(int));
     L.lists = take(L.cap * sizeof(int));
     L.bits = take(L.cap * sizeof(uint64_t));
-    L.units_cap = 4 * g.ntiles < 8192 ? 4 * g.ntiles : 8192;
+    // Extra slices per light: at most 4 per tile and 8192, and no more than a
+    // set of n Gaussians can fill (about 8 tile hits each, kMinSliceHits per
+    // slice); every slot is a block of each tile-build launch, so a small
+    // (per-frame avatar) set does not pay for thousands of empty ones.
+    {
+        const int64_t by_n = (n * 8) / kMinSliceHits + 256;
+        const int cap = 4 * g.ntiles < 8192 ? 4 * g.ntiles : 8192;
+        L.units_cap = by_n < cap ? (int)by_n : cap;
+    }
     L.hits = take((size_t)g.ntiles * sizeof(int));
     L.tinfo = take((size_t)g.ntiles * sizeof(int4));
     L.units = take((size_t)L.units_cap * sizeof(int4));
