@@ -738,6 +738,7 @@ struct TexelState {
     uint64_t vmask;          // ballot of valid: the lanes that hold a texel of the atlas
     int lane;
     float lr0, kinv;         // shell coordinate of a radius: (log2 t - lr0) * kinv (geometric)
+    float lr0k;              // lr0 * kinv
     double ratio;            // t_{k+1} / t_k (geometric) or t_{k+1} - t_k (uniform)
     int K;
     bool geometric;
@@ -747,10 +748,12 @@ struct TexelState {
     int kmin, kmax;          // shells kept (the receiver range; 0 .. K-1 without a region)
 };
 
-// Shell index of a radius (fractional, unclamped); -1 for t <= 0.
+// Shell coordinate of a radius (fractional, unclamped).  Geometric shells:
+// a radius <= 0 gives -inf or NaN (log2 of 0 or of a negative number), which
+// the callers treat as "before shell 0".
 template <bool GEO>
-__device__ inline float shell_index(float t, const TexelState& ts) {
-    if (GEO) return t > 0.f ? (__builtin_amdgcn_logf(t) - ts.lr0) * ts.kinv : -1.f;
+__device__ inline float shell_coord(float t, const TexelState& ts) {
+    if (GEO) return __builtin_amdgcn_logf(t) * ts.kinv - ts.lr0k;
     return t * ts.kinv - 0.5f;
 }
 
@@ -821,22 +824,23 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     const float corr = (wd0 * wp0 + wd1 * wp1 + wd2 * wp2) * ra;
     const float sa = a * rsa * 0.70710678118654752f;      // sqrt(a / 2)
     const float ts = (float)te - corr;                      // t* (shell range, erf at t = 0)
-    // Ramp half-width z: P0 erfc(z) <= P0 exp(-z^2) <= kRampEps.
-    // (P0 of an active lane is far above the denormal range: raw v_log / v_sqrt suffice)
-    const float z = __builtin_amdgcn_sqrtf(fmaxf(0.69314718f * __builtin_amdgcn_logf(P0 * (1.f / kRampEps)), 0.34f));
-    const float xs = -sa * ts;                              // erf argument at t = 0
+    // Ramp half-width in t: P0 erfc(z) <= P0 exp(-z^2) <= kRampEps for
+    // z^2 = ln(P0 / kRampEps) (at least 0.34), and z = sqrt(a/2) half, so
+    // half = sqrt(2 z^2 / a).  (P0 of an active lane is far above the
+    // denormal range: raw v_log / v_sqrt suffice.)
+    const float half =
+        __builtin_amdgcn_sqrtf(fmaxf(1.38629436f * __builtin_amdgcn_logf(P0 * (1.f / kRampEps)), 0.68f) * ra);
     float Ep = -1.f;
-    if (xs > -z) Ep = erf_as(xs);
+    if (ts < half) Ep = erf_as(-sa * ts);                   // the ramp reaches back to t = 0: erf there
     // Each lane walks its own ramp shells [ka, ka + len): the first shell past
     // the ramp start carries everything from t = 0 up to it, the last one (at
     // or past the ramp end) everything up to the saturated tail.
     int ka = 0, len = 0;
     if (act) {
-        const float half = z * __builtin_amdgcn_rcpf(sa);
-        const float klo = fminf(shell_index<GEO>(ts - half, s), (float)s.K);
-        const float khi = fmaxf(shell_index<GEO>(ts + half, s), -1.f);
-        ka = klo < 0.f ? 0 : min((int)klo + 1, s.K - 1);
-        const int kb = khi > (float)(s.K - 2) ? s.K - 1 : max(0, (int)khi + 1);
+        const float klo = shell_coord<GEO>(ts - half, s);
+        const float khi = fmaxf(shell_coord<GEO>(ts + half, s), -1.f);
+        ka = klo >= 0.f ? min((int)klo, s.K - 2) + 1 : 0;
+        const int kb = khi > (float)(s.K - 2) ? s.K - 1 : (int)khi + 1;
         // only shells in [kmin, kmax] are kept: a ramp below the range still
         // adds its whole step at kmin, one above it adds nothing
         if (ka <= s.kmax) {
@@ -858,6 +862,7 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     const double tsd = te - (double)corr;
     const double* sh = s.shells + ka;
     unsigned long long* dst = s.inc + ka * kWave + s.lane;
+#pragma unroll 2
     for (int j = 0;; ++j) {
         const bool live = j < len;
         if (ballot(live) == 0ull) break;
@@ -1096,10 +1101,12 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     if (st.geometric) {
         st.lr0 = __builtin_amdgcn_logf(g.r0);
         st.kinv = (float)(K - 1) / __builtin_amdgcn_logf(g.r1 / g.r0);
+        st.lr0k = st.lr0 * st.kinv;
         st.ratio = pow((double)g.r1 / (double)g.r0, 1.0 / (double)(K - 1));
     } else {
         st.lr0 = 0.f;
         st.kinv = (float)K / g.r1;
+        st.lr0k = 0.f;
         st.ratio = (double)g.r1 / (double)K;
     }
     for (int q = tid; q < K * kWave; q += kWave * NW) inc[q] = 0ull;
