@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void sample_kernel(const InT* __restrict__ tab
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
-enum Mode { kTrain = 0, kInfer = 1, kCheck = 2 };
+enum Mode { kTrain = 0, kCheck = 2 };   // forward of training samples / of check samples
 
 struct FwdArgs {
     Geom g;
@@ -246,13 +246,7 @@ __global__ __launch_bounds__(kWave * NWV) void fwd_kernel(FwdArgs a) {
         if (lane < kRows) {
             const int64_t rr = row0 + lane;
             if (rr < a.n) {
-                if (MODE == kInfer) {
-                    float r;
-                    encode_point(a.points[3 * rr], a.points[3 * rr + 1], a.points[3 * rr + 2], a.lights + 3 * light,
-                                 a.g, in_mine.x, in_mine.y, in_mine.z, r);
-                } else {
-                    in_mine = a.uvrt[rr];
-                }
+                in_mine = a.uvrt[rr];
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -349,33 +343,20 @@ __global__ __launch_bounds__(kWave * NWV) void fwd_kernel(FwdArgs a) {
                 a.lossp[wid] = lsum;
             }
         } else {
-            // lane (lg, lr < 4) finishes row 4 lg + lr (the shuffle runs in every lane)
+            // check: lane (lg, lr < 4) compares row 4 lg + lr with the atlas
+            // (the shuffle runs in every lane)
             const int rr = 4 * lg + (lr & 3);
             const float4 in = input_of(in_mine, rr);
             const int64_t row = row0 + rr;
             const float t = (lr & 3) == 0 ? T[0] : (lr & 3) == 1 ? T[1] : (lr & 3) == 2 ? T[2] : T[3];
-            if (lr < 4 && row < a.n && a.atlas) {
-                const size_t tsz = (size_t)a.g.K * a.g.H * a.g.W;
-                int region;
-                const float ta = a.atlas_f16
-                                     ? atlas_at(reinterpret_cast<const __half*>(a.atlas) + light * tsz, a.g, in.x,
-                                                in.y, in.z, region)
-                                     : atlas_at(reinterpret_cast<const float*>(a.atlas) + light * tsz, a.g, in.x,
-                                                in.y, in.z, region);
-                if (MODE == kCheck) {
-                    const float err = fabsf(t - in.w);
-                    if (err > a.thresh) {
-                        a.mask_out[region] = 1;
-                        atomicAdd(a.check_stats, 1u);
-                    }
-                    atomicMax(a.check_stats + 1, __float_as_uint(err));
-                } else {
-                    const size_t nreg = (size_t)((a.g.K + 7) / 8) * a.g.ntiles;
-                    const bool fb = a.mask && a.mask[light * nreg + region];
-                    a.T[(size_t)light * a.n + row] = fb ? ta : t;
+            if (lr < 4 && row < a.n) {
+                const int region = atlas_region(a.g, in.x, in.y, in.z);
+                const float err = fabsf(t - in.w);
+                if (err > a.thresh) {
+                    a.mask_out[region] = 1;
+                    atomicAdd(a.check_stats, 1u);
                 }
-            } else if (lr < 4 && row < a.n && MODE == kInfer) {
-                a.T[(size_t)light * a.n + row] = t;
+                atomicMax(a.check_stats + 1, __float_as_uint(err));
             }
         }
     }
@@ -813,11 +794,8 @@ TrainWs train_ws(unsigned char* base, int64_t B) {
     return w;
 }
 
-constexpr int kInferWaves = 8;
 constexpr size_t fwd_smem(int nwv) { return (size_t)(4 * kH * 16 + nwv * kRows * 16) * 16; }
 constexpr size_t kFwdSmem = fwd_smem(kWaves);
-constexpr size_t kInferSmem = fwd_smem(kInferWaves);
-static_assert(kInferSmem <= 160 * 1024, "inference block exceeds the LDS of a CU");
 constexpr size_t kBwdSmem = (size_t)(3 * kH * 16 + kWaves * kRows * 16) * 16;
 
 int grid_rows(int64_t n, int rows = kTileRows) {
@@ -829,9 +807,6 @@ hipError_t set_smem() {
     static const hipError_t e = [] {
         hipError_t r = hipFuncSetAttribute((const void*)fwd_kernel<kTrain, kWaves>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdSmem);
-        if (r == hipSuccess)
-            r = hipFuncSetAttribute((const void*)fwd_kernel<kInfer, kInferWaves>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kInferSmem);
         if (r == hipSuccess)
             r = hipFuncSetAttribute((const void*)fwd_kernel<kCheck, kWaves>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFwdSmem);
