@@ -126,3 +126,31 @@ def test_cube_plan_matches_plain_builds_and_oracle(scene):
         print(f"[cube] plan frame {f} light {l} vs oracle: {err:.3e}")
         assert err <= 1e-4
     plan.close()
+
+
+def test_cube_footprint_matches_oracle(scene):
+    """Footprint sampling (7-point stencil) on a cube-map atlas.  The lookup is
+    discontinuous across face edges (no filtering between faces), so Gaussians
+    with a sample point within rounding of a face edge are left out."""
+    import paper_2601_01660_amd as P
+    F, K = 12, 10
+    g = scene["g"]
+    light = scene["lights"][:1]
+    atlas = P.Atlas.cube(F, K, dtype="f32")
+    T = P.dgsm_build(torch.from_numpy(light), P.GaussianSet.from_host(g), atlas)
+    z, w = od.footprint_stencil7()
+    got = P.dgsm_query_footprint(torch.from_numpy(light), atlas, T, P.GaussianSet.from_host(g),
+                                 torch.from_numpy(z.astype(np.float32)), torch.from_numpy(w.astype(np.float32)))
+    torch.cuda.synchronize()
+    ref_T = od.build(light[0], g, 2 * F, 3 * F, K, param="cubemap")
+    ref = od.query_footprint(ref_T, light[0], g, z, w, param="cubemap")
+    # sample points in FP64; keep Gaussians whose points are all clear of the face edges
+    R = od.quaternion_to_matrix(g.rot)
+    keep = np.ones(g.n, bool)
+    for zi in z:
+        x = g.mean.astype(np.float64) + np.einsum("nij,nj->ni", R, g.scale.astype(np.float64) * zi)
+        a = np.sort(np.abs(x - light[0].astype(np.float64)), axis=1)
+        keep &= (a[:, 2] - a[:, 1]) > 1e-4 * a[:, 2]
+    err = np.abs(got[0].cpu().numpy()[keep] - ref[keep]).max()
+    print(f"[cube] footprint stencil7: {keep.sum()} of {g.n} Gaussians, max|dT| {err:.3e}")
+    assert keep.sum() > 0.9 * g.n and err <= 1e-4
