@@ -130,6 +130,7 @@ struct PrepArgs {
     int beta_mode;         // dgsm_beta_mode
     float eps;             // culling budget (0: no culling)
     int S, SGH, SGW;       // supertile count and grid
+    int shape_cached;      // the records hold this set's shapes already: update m and the cone only
     BuildLayout lay;
     unsigned char* ws;
 };
@@ -153,77 +154,95 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
     const bool in = i < a.n;
     float4 cone = make_float4(0.f, 0.f, 1.f, -1.f);
     if (in) {
-        double qw = a.rot[4 * i], qx = a.rot[4 * i + 1], qy = a.rot[4 * i + 2], qz = a.rot[4 * i + 3];
-        const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-        qw *= qn; qx *= qn; qy *= qn; qz *= qn;
-        // columns of R: the principal axes
-        const double col[3][3] = {
-            {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy + qw * qz), 2 * (qx * qz - qw * qy)},
-            {2 * (qx * qy - qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz + qw * qx)},
-            {2 * (qx * qz + qw * qy), 2 * (qy * qz - qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
-        const double s[3] = {a.scale[3 * i], a.scale[3 * i + 1], a.scale[3 * i + 2]};
-        GRec r;
-        double tr = 0;
-        for (int j = 0; j < 3; ++j) {
-            const double is = 1.0 / s[j];
-            const double ip = 1.0 / (s[(j + 1) % 3] * s[(j + 2) % 3]);
-            tr += is * is;
-            for (int c = 0; c < 3; ++c) {
-                r.w[3 * j + c] = (float)(col[j][c] * is);
-                r.c[3 * j + c] = (float)(col[j][c] * ip);
+        // Culling-cone numerator R0 = s_max sqrt(2 ln(U / eps)) (see below): -1 for
+        // a Gaussian that contributes nothing, +inf without culling.  It depends
+        // on the Gaussian's shape only, like the rest of the record but m, and is
+        // kept in the record for later frames of a rigidly moving set.
+        double R0;
+        if (!a.shape_cached) {
+            double qw = a.rot[4 * i], qx = a.rot[4 * i + 1], qy = a.rot[4 * i + 2], qz = a.rot[4 * i + 3];
+            const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+            qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+            // columns of R: the principal axes
+            const double col[3][3] = {
+                {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy + qw * qz), 2 * (qx * qz - qw * qy)},
+                {2 * (qx * qy - qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz + qw * qx)},
+                {2 * (qx * qz + qw * qy), 2 * (qy * qz - qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
+            const double s[3] = {a.scale[3 * i], a.scale[3 * i + 1], a.scale[3 * i + 2]};
+            GRec r;
+            double tr = 0;
+            for (int j = 0; j < 3; ++j) {
+                const double is = 1.0 / s[j];
+                const double ip = 1.0 / (s[(j + 1) % 3] * s[(j + 2) % 3]);
+                tr += is * is;
+                for (int c = 0; c < 3; ++c) {
+                    r.w[3 * j + c] = (float)(col[j][c] * is);
+                    r.c[3 * j + c] = (float)(col[j][c] * ip);
+                }
             }
+            const double alpha = a.opacity[i];
+            const double tau_star = -log1p(-alpha);
+            // beta sqrt(2 pi) (the line-integral scale of Eq. 3)
+            const double TWO_PI = 6.283185307179586;
+            double amp = (double)a.kappa * tau_star * sqrt(tr / 3.0);          // Eq. 5
+            if (a.beta_mode == DGSM_BETA_CONSTANT) amp = (double)a.kappa * tau_star * sqrt(TWO_PI);
+            else if (a.beta_mode == DGSM_BETA_DENSITY) amp = (double)a.kappa * tau_star / (TWO_PI * s[0] * s[1] * s[2]);
+            r.bp = (float)(0.5 * amp);                                        // beta sqrt(pi/2)
+            // Per-texel pre-test radius.  The tile build keeps a texel when
+            // 2 P0 > eps, with P0 = beta sqrt(pi/2) a^(-1/2) exp(-e0/2).  Since
+            // a >= 1/s_max^2 and e0 >= h^2/s_max^2 (h = |m x d|, the distance from
+            // mu to the line of the ray), 2 P0 <= 2 bp s_max exp(-h^2/(2 s_max^2)):
+            // no texel with h^2 >= 2 s_max^2 ln(2 bp s_max / eps) can be kept.
+            const double smax = fmax(s[0], fmax(s[1], s[2]));
+            // one logarithm serves both pre-test bounds and the culling cone below:
+            // ln(U / eps) with U the larger of 2 bp s_max (bp as stored, FP32) and
+            // beta sqrt(2 pi) s_max (FP64), so each bound holds for either
+            const double U = fmax(amp * smax, 2.0 * (double)r.bp * smax);
+            const double lnU = (a.eps > 0.f && U > (double)a.eps) ? log(U / (double)a.eps) : 0.0;
+            {
+                double r2 = 3.0e38;                              // eps = 0: every texel is kept
+                if (a.eps > 0.f) r2 = 2.0 * smax * smax * lnU;
+                r.r2 = (float)fmin(r2 * (1.0 + 1e-5), 3.0e38);
+                // The same bound on the whitened offset: 2 P0 <= 2 bp s_max exp(-e0/2)
+                // (a^(-1/2) <= s_max), so no texel with e0 >= 2 ln(2 bp s_max / eps) is kept.
+                double lg = 3.0e38;
+                if (a.eps > 0.f) lg = 2.0 * lnU;
+                r.lg = (float)fmin(lg * (1.0 + 1e-5) + 1e-3, 3.0e38);
+            }
+            if (!(alpha > 0.0) || !(U > (double)a.eps)) R0 = -1.0;
+            else R0 = a.eps > 0.f ? smax * sqrt(2.0 * lnU) : INFINITY;
+            r.r0 = (float)R0;
+            R0 = (double)r.r0;                           // as later frames will read it
+            for (int j = 0; j < 4; ++j) r.pad[j] = 0.f;
+            r.mx = (double)light[0] - (double)a.mean[3 * i];
+            r.my = (double)light[1] - (double)a.mean[3 * i + 1];
+            r.mz = (double)light[2] - (double)a.mean[3 * i + 2];
+            W.rec[i] = r;
+        } else {
+            R0 = (double)W.rec[i].r0;
+            W.rec[i].mx = (double)light[0] - (double)a.mean[3 * i];
+            W.rec[i].my = (double)light[1] - (double)a.mean[3 * i + 1];
+            W.rec[i].mz = (double)light[2] - (double)a.mean[3 * i + 2];
         }
-        const double alpha = a.opacity[i];
-        const double tau_star = -log1p(-alpha);
-        // beta sqrt(2 pi) (the line-integral scale of Eq. 3)
-        const double TWO_PI = 6.283185307179586;
-        double amp = (double)a.kappa * tau_star * sqrt(tr / 3.0);          // Eq. 5
-        if (a.beta_mode == DGSM_BETA_CONSTANT) amp = (double)a.kappa * tau_star * sqrt(TWO_PI);
-        else if (a.beta_mode == DGSM_BETA_DENSITY) amp = (double)a.kappa * tau_star / (TWO_PI * s[0] * s[1] * s[2]);
-        r.bp = (float)(0.5 * amp);                                        // beta sqrt(pi/2)
-        r.mx = (double)light[0] - (double)a.mean[3 * i];
-        r.my = (double)light[1] - (double)a.mean[3 * i + 1];
-        r.mz = (double)light[2] - (double)a.mean[3 * i + 2];
-        // Per-texel pre-test radius.  The tile build keeps a texel when
-        // 2 P0 > eps, with P0 = beta sqrt(pi/2) a^(-1/2) exp(-e0/2).  Since
-        // a >= 1/s_max^2 and e0 >= h^2/s_max^2 (h = |m x d|, the distance from
-        // mu to the line of the ray), 2 P0 <= 2 bp s_max exp(-h^2/(2 s_max^2)):
-        // no texel with h^2 >= 2 s_max^2 ln(2 bp s_max / eps) can be kept.
-        const double smax = fmax(s[0], fmax(s[1], s[2]));
-        // one logarithm serves both pre-test bounds and the culling cone below:
-        // ln(U / eps) with U the larger of 2 bp s_max (bp as stored, FP32) and
-        // beta sqrt(2 pi) s_max (FP64), so each bound holds for either
-        const double U = fmax(amp * smax, 2.0 * (double)r.bp * smax);
-        const double lnU = (a.eps > 0.f && U > (double)a.eps) ? log(U / (double)a.eps) : 0.0;
-        {
-            double r2 = 3.0e38;                              // eps = 0: every texel is kept
-            if (a.eps > 0.f) r2 = 2.0 * smax * smax * lnU;
-            r.r2 = (float)fmin(r2 * (1.0 + 1e-5), 3.0e38);
-            // The same bound on the whitened offset: 2 P0 <= 2 bp s_max exp(-e0/2)
-            // (a^(-1/2) <= s_max), so no texel with e0 >= 2 ln(2 bp s_max / eps) is kept.
-            double lg = 3.0e38;
-            if (a.eps > 0.f) lg = 2.0 * lnU;
-            r.lg = (float)fmin(lg * (1.0 + 1e-5) + 1e-3, 3.0e38);
-        }
-        for (int j = 0; j < 5; ++j) r.pad[j] = 0.f;
-        W.rec[i] = r;
 
         // Culling cone.  Along any ray the contribution is at most
         // U exp(-h^2 / (2 s_max^2)), U = beta sqrt(2 pi) s_max, with h
         // the distance from mu to the ray (D for rays pointing away).  So it is
-        // below eps outside the cone sin(theta) <= (s_max / D) sqrt(2 ln(U / eps)).
-        const double D = sqrt(r.mx * r.mx + r.my * r.my + r.mz * r.mz);
-        if (!(alpha > 0.0) || !(U > (double)a.eps)) {
+        // below eps outside the cone sin(theta) <= (s_max / D) sqrt(2 ln(U / eps)) = R0 / D.
+        const double mx = (double)light[0] - (double)a.mean[3 * i];
+        const double my = (double)light[1] - (double)a.mean[3 * i + 1];
+        const double mz = (double)light[2] - (double)a.mean[3 * i + 2];
+        const double D = sqrt(mx * mx + my * my + mz * mz);
+        if (R0 < 0.0) {
             cone.w = -1.f;                               // contributes nothing
         } else {
             double shalf = 1.0;                          // global: every direction
-            if (a.eps > 0.f && D > 0.0) {
-                const double sig = smax / D * sqrt(2.0 * lnU);
+            if (D > 0.0) {
+                const double sig = R0 / D;
                 // sin(theta / 2) for sin(theta) = sig: sig / sqrt(2 (1 + cos(theta)))
                 if (sig < 1.0) shalf = sig / sqrt(2.0 * (1.0 + sqrt(1.0 - sig * sig)));
             }
-            const double gx = D > 0 ? -r.mx / D : 0.0, gy = D > 0 ? -r.my / D : 0.0,
-                         gz = D > 0 ? -r.mz / D : 1.0;
+            const double gx = D > 0 ? -mx / D : 0.0, gy = D > 0 ? -my / D : 0.0, gz = D > 0 ? -mz / D : 1.0;
             cone = make_float4((float)gx, (float)gy, (float)gz, inflate_sh(shalf));
         }
         W.cone[i] = cone;
@@ -1339,11 +1358,11 @@ dgsm_status enqueue_cones(const Geom& g, const BuildLayout& L, unsigned char* ws
 }
 
 dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
-                        float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st, bool cones) {
+                        float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st, bool cones, bool shape_cached) {
     if (cones && enqueue_cones(g, L, ws, st) != DGSM_OK) return DGSM_EHIP;
     if (gs.n > 0) {
         PrepArgs pa{gs.mean, gs.scale, gs.rot, gs.opacity, gs.n, lights.pos, lights.kappa, lights.beta_mode, cull_eps,
-                    g.S, g.SGH, g.SGW, L, ws};
+                    g.S, g.SGH, g.SGW, shape_cached ? 1 : 0, L, ws};
         preprocess_kernel<<<dim3(L.nb, lights.n), kPrepThreads, 0, st>>>(pa);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }

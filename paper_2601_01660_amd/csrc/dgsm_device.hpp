@@ -61,7 +61,8 @@ struct __attribute__((aligned(16))) GRec {
     float bp;            // beta * sqrt(pi / 2)
     float r2;            // squared ray-to-mean distance beyond which no texel is active
     float lg;            // e0 = |adj(A)^(1/2) (m x d)|^2 / a at or beyond which no texel is active
-    float pad[5];
+    float r0;            // culling-cone numerator s_max sqrt(2 ln(U / eps)); -1: contributes nothing
+    float pad[4];
 };
 static_assert(sizeof(GRec) == 128, "GRec layout");
 

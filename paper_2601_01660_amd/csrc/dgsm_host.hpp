@@ -105,7 +105,8 @@ dgsm_status enqueue_cones(const Geom& g, const BuildLayout& L, unsigned char* ws
 // Enqueue the binning of all lights (preprocess, scan, scatter, tile masks);
 // cones = false reuses cones already in the workspace.
 dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
-                        float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st, bool cones = true);
+                        float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st, bool cones = true,
+                        bool shape_cached = false);
 
 // Options of the per-tile accumulation.
 struct AccumOpts {

@@ -261,7 +261,9 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, const float* dyn_base, const float
     dgsm_status s;
     if (p->cache) {
         const BuildLayout Lb = build_layout(p->g, p->nd, p->L);
-        s = enqueue_bin(p->g, Lb, p->ws_b, lt, p->desc.cull_eps, set_of(p, p->ns, p->nd), st, false);
+        // the dynamic set moves rigidly: from the run's second frame on, its
+        // records keep their shape part and only the light-to-mean offsets change
+        s = enqueue_bin(p->g, Lb, p->ws_b, lt, p->desc.cull_eps, set_of(p, p->ns, p->nd), st, false, f > 0);
         if (s != DGSM_OK) return s;
         // only tiles the dynamic set reaches are rebuilt; the rest hold the static baseline
         AccumOpts o{p->tau_static, false, nullptr, tile_waves, split_units, true, true};
