@@ -38,8 +38,8 @@ PEAK_HBM_GBS = 8000.0
 # device copy.  Valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("paper_2601_01660_amd/csrc/dgsm_build.hip", "paper_2601_01660_amd/csrc/dgsm_device.hpp",
                    "paper_2601_01660_amd/csrc/dgsm_host.hpp")
-TRAFFIC = {"sha256": "7911b64c9cddcda41c13240375d169c5d5fc22ea400e2ded4bba4f323a2970eb",
-           "fetch_bytes": 34980595997, "write_bytes": 1191475749,
+TRAFFIC = {"sha256": "a0833d65021adcdcdd4d361b1dcfeea764bc2816b6ab2d4d5fbb11ae3b206bb7",
+           "fetch_bytes": 34889565594, "write_bytes": 1190770025,
            "profile": "profiles/tile_build_counters__room2M_avatar150k_4lights_512x512x64_f16.md"}
 
 
