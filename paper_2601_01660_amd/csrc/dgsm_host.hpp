@@ -143,8 +143,9 @@ constexpr int kDefaultSplitUnits = 32768;
 // Enqueue the per-tile accumulation of all lights into atlas [L][K][H][W].
 dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned char* ws, int n_lights,
                                float pair_eps, void* atlas, const AccumOpts& o, hipStream_t st);
+// T [L][P] (light-major), or [P][L] (point-major) with point_major.
 hipError_t launch_query(const Geom& g, const float* lights, int L, const void* atlas, const float* points,
                         int64_t P, float* T, hipStream_t st, bool tiled = false,
-                        const int* out_index = nullptr);
+                        const int* out_index = nullptr, bool point_major = false);
 
 }  // namespace dgsm

@@ -167,6 +167,32 @@ __global__ __launch_bounds__(256) void gather_static_kernel(dgsm_gaussians_t src
     out_index[p] = (int)s;
 }
 
+// Inverse of the point order: in_pos[caller column] = plan position.
+__global__ __launch_bounds__(256) void invert_kernel(const int* __restrict__ out_index, int64_t n,
+                                                     int* __restrict__ in_pos) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < n) in_pos[out_index[p]] = (int)p;
+}
+
+// Frame results from the point-major staging [np][L] (plan order) into the
+// caller's [L][np]: thread i gathers caller point i's L values (one contiguous
+// read) and writes them coalesced, one light after another.
+__global__ __launch_bounds__(256) void unstage_kernel(const float* __restrict__ tq, const int* __restrict__ in_pos,
+                                                      int64_t n, int L, float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float* src = tq + (size_t)in_pos[i] * L;
+    if (L == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(src);
+        out[i] = v.x;
+        out[n + i] = v.y;
+        out[2 * n + i] = v.z;
+        out[3 * n + i] = v.w;
+    } else {
+        for (int l = 0; l < L; ++l) out[(size_t)l * n + i] = src[l];
+    }
+}
+
 __global__ __launch_bounds__(256) void iota_kernel(int* __restrict__ v, int64_t from, int64_t to) {
     const int64_t i = from + (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i < to) v[i] = (int)i;
@@ -196,6 +222,8 @@ struct dgsm_plan_s {
     float* rot;           // [ns + nd][4]
     float* opacity;       // [ns + nd]
     int* out_index;       // [ns + nd] caller column of each plan point (static part in spatial order)
+    int* in_pos;          // [ns + nd] plan position of each caller column
+    float* tq;            // [ns + nd][L] one frame's query results in plan order (point-major)
     float* tau_static;    // [L][K][H][W] (cache mode)
     void* atlas;          // [L][K][plane] of desc.dtype (tile-major planes)
     void* atlas_static;   // cache mode: T of the static set alone (the per-frame baseline)
@@ -219,7 +247,8 @@ void plan_free(dgsm_plan p) {
     if (!p) return;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     void* bufs[] = {p->lights,     p->mean,  p->scale,        p->rot,  p->opacity, p->out_index,
-                    p->tau_static, p->atlas, p->atlas_static, p->ws_a, p->ws_b};
+                    p->tau_static, p->atlas, p->atlas_static, p->ws_a, p->ws_b,    p->in_pos,
+                    p->tq};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -276,9 +305,17 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, const float* dyn_base, const float
         s = enqueue_accumulate(p->g, La, p->ws_a, p->L, p->desc.cull_eps, p->atlas, o, st);
     }
     if (s != DGSM_OK) return s;
-    if (launch_query(p->g, p->lights, p->L, p->atlas, p->mean, p->np, T_out + (size_t)f * p->L * p->np, st,
-                     true, p->out_index) != hipSuccess)
+    // Query in plan (spatial) order with coalesced point-major writes, then one
+    // gather into the caller's order: writing straight to the caller's columns
+    // scatters 4-byte stores over the whole output.
+    if (launch_query(p->g, p->lights, p->L, p->atlas, p->mean, p->np, p->tq, st, true, nullptr, true) !=
+        hipSuccess)
         return DGSM_EHIP;
+    if (p->np > 0) {
+        unstage_kernel<<<(unsigned)((p->np + 255) / 256), 256, 0, st>>>(p->tq, p->in_pos, p->np, p->L,
+                                                                        T_out + (size_t)f * p->L * p->np);
+        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    }
     if (p->cache) {
         const BuildLayout Lb = build_layout(p->g, p->nd, p->L);
         const dim3 grid(p->g.ntiles, p->L);
@@ -416,6 +453,8 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     bool ok = dalloc(&p->lights, 12 * (size_t)p->L) == hipSuccess && dalloc(&p->mean, 12 * (size_t)np) == hipSuccess &&
               dalloc(&p->scale, 12 * (size_t)np) == hipSuccess && dalloc(&p->rot, 16 * (size_t)np) == hipSuccess &&
               dalloc(&p->opacity, 4 * (size_t)np) == hipSuccess && dalloc(&p->out_index, 4 * (size_t)np) == hipSuccess &&
+              dalloc(&p->in_pos, 4 * (size_t)np) == hipSuccess &&
+              dalloc(&p->tq, 4 * (size_t)np * p->L) == hipSuccess &&
               dalloc(&p->atlas, table * elem) == hipSuccess &&
               dalloc(&p->ws_a, p->ws_a_bytes) == hipSuccess &&
               (!p->cache || (dalloc(&p->tau_static, table * 4) == hipSuccess &&
@@ -430,6 +469,10 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     if (ok && n > 0) ok = sort_static(p, *static_set) == DGSM_OK;
     if (ok && p->nd > 0) {
         iota_kernel<<<(unsigned)((p->nd + 255) / 256), 256>>>(p->out_index, p->ns, p->np);
+        ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    }
+    if (ok && np > 0) {
+        invert_kernel<<<(unsigned)((np + 255) / 256), 256>>>(p->out_index, np, p->in_pos);
         ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
     }
     if (!ok) {

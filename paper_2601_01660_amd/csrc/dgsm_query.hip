@@ -24,6 +24,7 @@ struct QueryArgs {
     float lr0, kscale;     // shell coordinate: geometric (log2 r - lr0) * kscale, uniform r * kscale - 1/2
     int tiled;             // plane order of the atlas (see wrap_offset)
     const int* out_index;  // optional [P]: point p's result goes to column out_index[p]
+    int point_major;       // T [P][L] instead of [L][P]
 };
 
 // Trilinear lookup of light l's atlas at world point (x, y, z).
@@ -60,7 +61,8 @@ __global__ __launch_bounds__(256) void query_kernel(QueryArgs a) {
     if (p >= a.P) return;
     const int l = blockIdx.y;
     const float T = lookup<InT>(a, l, a.points[3 * p], a.points[3 * p + 1], a.points[3 * p + 2]);
-    a.T[(size_t)l * a.P + (a.out_index ? (int64_t)a.out_index[p] : p)] = T;
+    const int64_t col = a.out_index ? (int64_t)a.out_index[p] : p;
+    a.T[a.point_major ? (size_t)col * a.L + l : (size_t)l * a.P + col] = T;
 }
 
 // Footprint sampling (Sec. 3.3, Ablation A): T_g = sum_i w_i T(mu_g + R_g (s_g * z_i)),
@@ -113,9 +115,9 @@ __global__ __launch_bounds__(256) void footprint_kernel(FootArgs f) {
 }
 
 hipError_t launch_query(const Geom& g, const float* lights, int L, const void* atlas, const float* points,
-                        int64_t P, float* T, hipStream_t st, bool tiled, const int* out_index) {
+                        int64_t P, float* T, hipStream_t st, bool tiled, const int* out_index, bool point_major) {
     if (P == 0) return hipSuccess;
-    QueryArgs a{g, lights, L, atlas, points, P, T, 0.f, 0.f, tiled ? 1 : 0, out_index};
+    QueryArgs a{g, lights, L, atlas, points, P, T, 0.f, 0.f, tiled ? 1 : 0, out_index, point_major ? 1 : 0};
     if (g.spacing == DGSM_SHELLS_GEOMETRIC) {
         a.lr0 = log2f(g.r0);
         a.kscale = (float)(g.K - 1) / log2f(g.r1 / g.r0);
@@ -157,7 +159,7 @@ extern "C" dgsm_status dgsm_query_footprint(const dgsm_lights_t* lights, const d
     if (gaussians->n == 0) return DGSM_OK;
     const Geom g = make_geom(*desc);
     FootArgs f{};
-    f.q = QueryArgs{g, lights->pos, lights->n, atlas, nullptr, gaussians->n, T, 0.f, 0.f, 0, nullptr};
+    f.q = QueryArgs{g, lights->pos, lights->n, atlas, nullptr, gaussians->n, T, 0.f, 0.f, 0, nullptr, 0};
     if (g.spacing == DGSM_SHELLS_GEOMETRIC) {
         f.q.lr0 = log2f(g.r0);
         f.q.kscale = (float)(g.K - 1) / log2f(g.r1 / g.r0);
