@@ -418,7 +418,23 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
     int s_cur = -1, cnt = 0;
     SuperSpan sp_cur{0, 0, 0, 0};
     int q0y = 0, q0x = 0, nqy_s = 0, nqx_s = 0;
+    // cone of this lane's entry of chunk c (one chunk ahead: the dependent
+    // list -> cone loads of the next chunk are in flight while this one is tested)
+    auto entry_cone = [&](int c) {
+        int lo = 0, hi = g.S - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sbase[mid] <= 64 * c) lo = mid; else hi = mid - 1;
+        }
+        const int e = 64 * c + lane;
+        float4 cn = make_float4(0.f, 0.f, 1.f, -1.f);
+        if (e < sbase[lo] + stot[lo]) cn = W.cone[W.lists[e]];
+        return cn;
+    };
+    float4 next_cone = cbeg < cend ? entry_cone(cbeg) : make_float4(0.f, 0.f, 1.f, -1.f);
     for (int c = cbeg; c < cend; ++c) {
+        const float4 cone = next_cone;
+        if (c + 1 < cend) next_cone = entry_cone(c + 1);
         // supertile of this chunk: the last s with sbase[s] <= 64 c
         int lo = 0, hi = g.S - 1;
         while (lo < hi) {
@@ -451,9 +467,6 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        const int e = 64 * c + lane;
-        float4 cone = make_float4(0.f, 0.f, 1.f, -1.f);
-        if (e < sbase[s] + stot[s]) cone = W.cone[W.lists[e]];
         const SuperSpan sp = sp_cur;
         const int nt = sp.nty * sp.ntx;
         const float ca = cone_cos(cone);
@@ -1373,9 +1386,9 @@ dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, 
     if (gs.n > 0) {
         scatter_kernel<<<dim3(L.nb, lights.n), kPrepThreads, 0, st>>>(ws, L, gs.n, g.S);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
-        // enough waves to cover the typical chunk count; each strides over the rest
+        // about two chunks per wave (the next chunk's loads overlap this one's tests)
         const int64_t est = ((int64_t)gs.n * 2 + 64 * (int64_t)g.S) / 64;
-        const int blocks = (int)(est / 4 + 1 < 4096 ? est / 4 + 1 : 4096);
+        const int blocks = (int)(est / 8 + 1 < 4096 ? est / 8 + 1 : 4096);
         tile_mask_kernel<<<dim3(blocks, lights.n), 256, 0, st>>>(ws, L, g);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }
