@@ -38,8 +38,8 @@ PEAK_HBM_GBS = 8000.0
 # device copy.  Valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("paper_2601_01660_amd/csrc/dgsm_build.hip", "paper_2601_01660_amd/csrc/dgsm_device.hpp",
                    "paper_2601_01660_amd/csrc/dgsm_host.hpp")
-TRAFFIC = {"sha256": "a0833d65021adcdcdd4d361b1dcfeea764bc2816b6ab2d4d5fbb11ae3b206bb7",
-           "fetch_bytes": 34889565594, "write_bytes": 1190770025,
+TRAFFIC = {"sha256": "af1ba472f9eed025f0c4e40c40a6179140abef999a12cbb60792f6fc1e5c3e38",
+           "fetch_bytes": 34883184252, "write_bytes": 1190232503,
            "profile": "profiles/tile_build_counters__room2M_avatar150k_4lights_512x512x64_f16.md"}
 
 
