@@ -315,7 +315,11 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  * dgsm_plan_run enqueues on `stream`; with use_graph = 1 the whole run (static
  * build + all frames) is captured once into a hipGraph and replayed (stream
  * must then be a created stream, not NULL; a run with different dynamic or
- * output pointers recaptures).  Runs of one plan must not overlap.
+ * output pointers recaptures).  Runs of one plan must not overlap.  In cache
+ * mode with F >= 2 the frames alternate between two chains of buffers; the
+ * odd frames run on a stream the plan owns, forked from `stream` after the
+ * static build and joined back into it before the run ends, so work enqueued
+ * on `stream` afterwards sees every frame.
  *   dynamic_set : device arrays of the dynamic set at its base pose (n = n_dynamic)
  *   translations: device [F][3]
  *   T_out       : device [F][lights.n][n_static + n_dynamic] float32

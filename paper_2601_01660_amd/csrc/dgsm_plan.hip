@@ -13,6 +13,9 @@
 // tile-major order (the texels of an 8x8 tile contiguous): a tile's store is
 // one 128/256-byte run per shell, and most trilinear lookups stay inside one
 // tile, so a shell's two texel rows come from one cache line.
+// In cache mode the frames alternate between independent chains of buffers
+// on their own streams (see kMaxChains), so that the short launches of one
+// frame overlap the tile build of the next.
 // The whole run (static build + all frames) is captured once into a hipGraph
 // and replayed; the knobs of the tile accumulation (waves per tile, work
 // units per launch) are chosen on the first run by timing each candidate pair
@@ -34,12 +37,24 @@ __global__ __launch_bounds__(256) void translate_kernel(const float* __restrict_
     dst[i] = base[i] + t[i % 3];
 }
 
+// Frames of a cached run are spread over up to kMaxChains independent chains
+// (frame f on chain f mod chains), each on its own stream with its own atlas,
+// query staging, means and dynamic workspace: one frame's short binning,
+// finish, query and restore launches overlap another frame's tile build.
+constexpr int kMaxChains = 2;
+
 // T of the static set alone, T = exp(-tau_static) with the running minimum
 // over shells (the same arithmetic as the tile build's finish of a tile that
-// no dynamic Gaussian reaches), into the atlas and into its baseline copy.
+// no dynamic Gaussian reaches), into its baseline copy and into the atlas of
+// every chain (atlas[c] null past the plan's chains).
+template <typename OutT>
+struct ChainAtlases {
+    OutT* a[kMaxChains];
+};
+
 template <typename OutT>
 __global__ __launch_bounds__(kWave) void static_finish_kernel(Geom g, const float* __restrict__ tau,
-                                                              OutT* __restrict__ atlas, OutT* __restrict__ base) {
+                                                              ChainAtlases<OutT> atlas, OutT* __restrict__ base) {
     const int tile = blockIdx.x, light = blockIdx.y, lane = threadIdx.x;
     const int ty = tile / g.TW, tx = tile - ty * g.TW;
     if (ty * kTile + (lane >> 3) >= g.H || tx * kTile + (lane & 7) >= g.W) return;
@@ -49,8 +64,10 @@ __global__ __launch_bounds__(kWave) void static_finish_kernel(Geom g, const floa
     for (int k = 0; k < g.K; ++k) {
         const float T = fminf(__expf(-tau[off + (size_t)k * plane]), Tp);
         Tp = T;
-        Store<OutT>::put(atlas + off + (size_t)k * plane, T);
         Store<OutT>::put(base + off + (size_t)k * plane, T);
+#pragma unroll
+        for (int c = 0; c < kMaxChains; ++c)
+            if (atlas.a[c]) Store<OutT>::put(atlas.a[c] + off + (size_t)k * plane, T);
     }
 }
 
@@ -231,6 +248,16 @@ struct dgsm_plan_s {
     size_t ws_a_bytes;
     unsigned char* ws_b;  // workspace for the dynamic set (cache mode)
     size_t ws_b_bytes;
+    // frame chains (cache mode): chain 0 uses mean, tq, atlas, ws_b and the
+    // caller's stream; chain c > 0 its own copies and stream, forked from and
+    // joined back into the caller's stream around the frames
+    int chains;
+    float* cmean[kMaxChains];
+    float* ctq[kMaxChains];
+    void* catlas[kMaxChains];
+    unsigned char* cws[kMaxChains];
+    hipStream_t cstream[kMaxChains];
+    hipEvent_t ev_fork, ev_join[kMaxChains];
     // captured graph and the arguments it was captured for
     hipGraphExec_t exec;
     const void* cap_key[6];
@@ -251,68 +278,85 @@ void plan_free(dgsm_plan p) {
                     p->tq};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
+    for (int c = 1; c < kMaxChains; ++c) {
+        void* cb[] = {p->cmean[c], p->ctq[c], p->catlas[c], p->cws[c]};
+        for (void* b : cb)
+            if (b) (void)hipFree(b);
+        if (p->cstream[c]) (void)hipStreamDestroy(p->cstream[c]);
+        if (p->ev_join[c]) (void)hipEventDestroy(p->ev_join[c]);
+    }
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     delete p;
 }
 
-dgsm_gaussians_t set_of(const dgsm_plan p, int64_t off, int64_t n) {
-    return dgsm_gaussians_t{p->mean + 3 * off, p->scale + 3 * off, p->rot + 4 * off, p->opacity + off, n};
+dgsm_gaussians_t set_of(const dgsm_plan p, const float* mean, int64_t off, int64_t n) {
+    return dgsm_gaussians_t{mean + 3 * off, p->scale + 3 * off, p->rot + 4 * off, p->opacity + off, n};
 }
 
 // Static part of a run: tau of the static set for every light.
 dgsm_status enqueue_static(dgsm_plan p, int tile_waves, int split_units, hipStream_t st) {
     const dgsm_lights_t lt{p->lights, p->L, p->kappa, p->beta_mode};
     const BuildLayout La = build_layout(p->g, p->ns, p->L);
-    dgsm_status s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, 0, p->ns), st, false);
+    dgsm_status s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, p->mean, 0, p->ns), st, false);
     if (s != DGSM_OK) return s;
     AccumOpts o{nullptr, true, nullptr, tile_waves, split_units, true};
     s = enqueue_accumulate(p->g, La, p->ws_a, p->L, p->desc.cull_eps, p->tau_static, o, st);
     if (s != DGSM_OK) return s;
     const dim3 grid(p->g.ntiles, p->L);
-    if (p->desc.dtype == DGSM_F16)
-        static_finish_kernel<__half><<<grid, kWave, 0, st>>>(p->g, p->tau_static, static_cast<__half*>(p->atlas),
-                                                             static_cast<__half*>(p->atlas_static));
-    else
-        static_finish_kernel<float><<<grid, kWave, 0, st>>>(p->g, p->tau_static, static_cast<float*>(p->atlas),
-                                                            static_cast<float*>(p->atlas_static));
+    if (p->desc.dtype == DGSM_F16) {
+        ChainAtlases<__half> a{};
+        for (int c = 0; c < p->chains; ++c) a.a[c] = static_cast<__half*>(p->catlas[c]);
+        static_finish_kernel<__half><<<grid, kWave, 0, st>>>(p->g, p->tau_static, a, static_cast<__half*>(p->atlas_static));
+    } else {
+        ChainAtlases<float> a{};
+        for (int c = 0; c < p->chains; ++c) a.a[c] = static_cast<float*>(p->catlas[c]);
+        static_finish_kernel<float><<<grid, kWave, 0, st>>>(p->g, p->tau_static, a, static_cast<float*>(p->atlas_static));
+    }
     return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
 
-// One frame: dynamic means, build (on top of the static tau in cache mode), query.
-dgsm_status enqueue_frame(dgsm_plan p, int f, const float* dyn_base, const float* translations, float* T_out,
+// One frame on chain c (its stream st): dynamic means, build (on top of the
+// static tau in cache mode), query, and in cache mode the restore of the
+// chain's atlas to the static baseline.
+dgsm_status enqueue_frame(dgsm_plan p, int f, int c, const float* dyn_base, const float* translations, float* T_out,
                           int tile_waves, int split_units, hipStream_t st) {
     const dgsm_lights_t lt{p->lights, p->L, p->kappa, p->beta_mode};
+    float* mean = p->cmean[c];
+    void* atlas = p->catlas[c];
+    unsigned char* ws_b = p->cws[c];
     if (p->nd > 0) {
         const int64_t n3 = 3 * p->nd;
         translate_kernel<<<(unsigned)((n3 + 255) / 256), 256, 0, st>>>(dyn_base, p->nd, translations + 3 * f,
-                                                                        p->mean + 3 * p->ns);
+                                                                        mean + 3 * p->ns);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }
     dgsm_status s;
     if (p->cache) {
         const BuildLayout Lb = build_layout(p->g, p->nd, p->L);
-        // the dynamic set moves rigidly: from the run's second frame on, its
-        // records keep their shape part and only the light-to-mean offsets change
-        s = enqueue_bin(p->g, Lb, p->ws_b, lt, p->desc.cull_eps, set_of(p, p->ns, p->nd), st, false, f > 0);
+        // the dynamic set moves rigidly: from the chain's second frame of the
+        // run on, its records keep their shape part and only the light-to-mean
+        // offsets change
+        s = enqueue_bin(p->g, Lb, ws_b, lt, p->desc.cull_eps, set_of(p, mean, p->ns, p->nd), st, false,
+                        f >= p->chains);
         if (s != DGSM_OK) return s;
         // only tiles the dynamic set reaches are rebuilt; the rest hold the static baseline
         AccumOpts o{p->tau_static, false, nullptr, tile_waves, split_units, true, true};
-        s = enqueue_accumulate(p->g, Lb, p->ws_b, p->L, p->desc.cull_eps, p->atlas, o, st);
+        s = enqueue_accumulate(p->g, Lb, ws_b, p->L, p->desc.cull_eps, atlas, o, st);
     } else {
         const BuildLayout La = build_layout(p->g, p->np, p->L);
-        s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, 0, p->np), st, false);
+        s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, mean, 0, p->np), st, false);
         if (s != DGSM_OK) return s;
         AccumOpts o{nullptr, false, nullptr, tile_waves, split_units, true};
-        s = enqueue_accumulate(p->g, La, p->ws_a, p->L, p->desc.cull_eps, p->atlas, o, st);
+        s = enqueue_accumulate(p->g, La, p->ws_a, p->L, p->desc.cull_eps, atlas, o, st);
     }
     if (s != DGSM_OK) return s;
     // Query in plan (spatial) order with coalesced point-major writes, then one
     // gather into the caller's order: writing straight to the caller's columns
     // scatters 4-byte stores over the whole output.
-    if (launch_query(p->g, p->lights, p->L, p->atlas, p->mean, p->np, p->tq, st, true, nullptr, true) !=
-        hipSuccess)
+    if (launch_query(p->g, p->lights, p->L, atlas, mean, p->np, p->ctq[c], st, true, nullptr, true) != hipSuccess)
         return DGSM_EHIP;
     if (p->np > 0) {
-        unstage_kernel<<<(unsigned)((p->np + 255) / 256), 256, 0, st>>>(p->tq, p->in_pos, p->np, p->L,
+        unstage_kernel<<<(unsigned)((p->np + 255) / 256), 256, 0, st>>>(p->ctq[c], p->in_pos, p->np, p->L,
                                                                         T_out + (size_t)f * p->L * p->np);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }
@@ -320,11 +364,11 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, const float* dyn_base, const float
         const BuildLayout Lb = build_layout(p->g, p->nd, p->L);
         const dim3 grid(p->g.ntiles, p->L);
         if (p->desc.dtype == DGSM_F16)
-            restore_kernel<__half><<<grid, kWave, 0, st>>>(p->g, Lb, p->ws_b, static_cast<const __half*>(p->atlas_static),
-                                                           static_cast<__half*>(p->atlas));
+            restore_kernel<__half><<<grid, kWave, 0, st>>>(p->g, Lb, ws_b, static_cast<const __half*>(p->atlas_static),
+                                                           static_cast<__half*>(atlas));
         else
-            restore_kernel<float><<<grid, kWave, 0, st>>>(p->g, Lb, p->ws_b, static_cast<const float*>(p->atlas_static),
-                                                          static_cast<float*>(p->atlas));
+            restore_kernel<float><<<grid, kWave, 0, st>>>(p->g, Lb, ws_b, static_cast<const float*>(p->atlas_static),
+                                                          static_cast<float*>(atlas));
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }
     return DGSM_OK;
@@ -343,10 +387,25 @@ dgsm_status enqueue_run(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* t
     // the static build is a full-scene accumulation: it keeps the defaults
     // (the tuned knobs fit the per-frame dynamic accumulation)
     if (p->cache && (s = enqueue_static(p, kDefaultTileWaves, kDefaultSplitUnits, st)) != DGSM_OK) return s;
-    for (int f = 0; f < p->frames; ++f)
-        if ((s = enqueue_frame(p, f, dyn->mean, translations, T_out, p->tile_waves, p->split_units, st)) != DGSM_OK)
-            return s;
-    return DGSM_OK;
+    // fork: every chain starts after the static build (and the copies above)
+    hipStream_t cs[kMaxChains];
+    cs[0] = st;
+    if (p->chains > 1 && hipEventRecord(p->ev_fork, st) != hipSuccess) return DGSM_EHIP;
+    for (int c = 1; c < p->chains; ++c) {
+        cs[c] = p->cstream[c];
+        if (hipStreamWaitEvent(cs[c], p->ev_fork, 0) != hipSuccess) return DGSM_EHIP;
+    }
+    s = DGSM_OK;
+    for (int f = 0; f < p->frames && s == DGSM_OK; ++f) {
+        const int c = f % p->chains;
+        s = enqueue_frame(p, f, c, dyn->mean, translations, T_out, p->tile_waves, p->split_units, cs[c]);
+    }
+    // join: the caller's stream waits for every chain (also after a failed
+    // enqueue, so that a capture never ends with a stream left forked)
+    for (int c = 1; c < p->chains; ++c)
+        if (hipEventRecord(p->ev_join[c], cs[c]) != hipSuccess || hipStreamWaitEvent(st, p->ev_join[c], 0) != hipSuccess)
+            return DGSM_EHIP;
+    return s;
 }
 
 // Time each (waves per tile, work units) candidate on the accumulation the
@@ -372,7 +431,7 @@ dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* tran
         for (int c = 0; c < 12 && s == DGSM_OK; ++c) {
             const int nw = waves[c % 3], nu = units[c / 3];
             (void)hipEventRecord(e0, st);
-            s = enqueue_frame(p, 0, dyn->mean, translations, T_out, nw, nu, st);
+            s = enqueue_frame(p, 0, 0, dyn->mean, translations, T_out, nw, nu, st);
             (void)hipEventRecord(e1, st);
             if (hipEventSynchronize(e1) != hipSuccess) s = DGSM_EHIP;
             float ms = 0.f;
@@ -460,13 +519,29 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
               (!p->cache || (dalloc(&p->tau_static, table * 4) == hipSuccess &&
                              dalloc(&p->atlas_static, table * elem) == hipSuccess &&
                              dalloc(&p->ws_b, p->ws_b_bytes) == hipSuccess));
+    p->chains = p->cache ? (p->frames < kMaxChains ? p->frames : kMaxChains) : 1;
+    p->cmean[0] = p->mean;
+    p->ctq[0] = p->tq;
+    p->catlas[0] = p->atlas;
+    p->cws[0] = p->ws_b;
+    for (int c = 1; c < p->chains && ok; ++c)
+        ok = dalloc(&p->cmean[c], 12 * (size_t)np) == hipSuccess &&
+             dalloc(&p->ctq[c], 4 * (size_t)np * p->L) == hipSuccess &&
+             dalloc(&p->catlas[c], table * elem) == hipSuccess && dalloc(&p->cws[c], p->ws_b_bytes) == hipSuccess &&
+             hipStreamCreateWithFlags(&p->cstream[c], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&p->ev_join[c], hipEventDisableTiming) == hipSuccess;
+    ok = ok && (p->chains < 2 || hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) == hipSuccess);
     const int64_t n = p->ns;
     ok = ok && hipMemcpy(p->lights, lights->pos, 12 * (size_t)p->L, hipMemcpyDeviceToDevice) == hipSuccess;
     // the atlas cones never change: computed once into each workspace
     ok = ok && enqueue_cones(g, build_layout(g, p->cache ? p->ns : np, p->L), p->ws_a, nullptr) == DGSM_OK;
-    ok = ok && (!p->cache || enqueue_cones(g, build_layout(g, p->nd, p->L), p->ws_b, nullptr) == DGSM_OK);
+    for (int c = 0; c < p->chains && ok && p->cache; ++c)
+        ok = enqueue_cones(g, build_layout(g, p->nd, p->L), p->cws[c], nullptr) == DGSM_OK;
     ok = ok && hipDeviceSynchronize() == hipSuccess;
     if (ok && n > 0) ok = sort_static(p, *static_set) == DGSM_OK;
+    // every chain's means start with the static set in plan order
+    for (int c = 1; c < p->chains && ok && n > 0; ++c)
+        ok = hipMemcpy(p->cmean[c], p->mean, 12 * (size_t)n, hipMemcpyDeviceToDevice) == hipSuccess;
     if (ok && p->nd > 0) {
         iota_kernel<<<(unsigned)((p->nd + 255) / 256), 256>>>(p->out_index, p->ns, p->np);
         ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
