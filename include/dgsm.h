@@ -316,10 +316,11 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  * build + all frames) is captured once into a hipGraph and replayed (stream
  * must then be a created stream, not NULL; a run with different dynamic or
  * output pointers recaptures).  Runs of one plan must not overlap.  In cache
- * mode with F >= 2 the frames alternate between two chains of buffers; the
- * odd frames run on a stream the plan owns, forked from `stream` after the
- * static build and joined back into it before the run ends, so work enqueued
- * on `stream` afterwards sees every frame.
+ * mode with F >= 2 the frames are dealt round-robin to min(F, 3) chains of
+ * buffers; frame f runs on chain f mod chains, chain 0 on `stream` and the
+ * others on streams the plan owns, forked from `stream` after the static
+ * build and joined back into it before the run ends, so work enqueued on
+ * `stream` afterwards sees every frame.
  *   dynamic_set : device arrays of the dynamic set at its base pose (n = n_dynamic)
  *   translations: device [F][3]
  *   T_out       : device [F][lights.n][n_static + n_dynamic] float32

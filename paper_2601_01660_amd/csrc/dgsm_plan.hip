@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void translate_kernel(const float* __restrict_
 // (frame f on chain f mod chains), each on its own stream with its own atlas,
 // query staging, means and dynamic workspace: one frame's short binning,
 // finish, query and restore launches overlap another frame's tile build.
-constexpr int kMaxChains = 2;
+constexpr int kMaxChains = 3;
 
 // T of the static set alone, T = exp(-tau_static) with the running minimum
 // over shells (the same arithmetic as the tile build's finish of a tile that
