@@ -471,15 +471,19 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
         const int nt = sp.nty * sp.ntx;
         const float ca = cone_cos(cone);
         uint64_t mine = 0;
-        // quads first: the tiles of a quad no lane's cone reaches are skipped
+        // quads first: the tiles of a quad no lane's cone reaches are skipped.
+        // A lane keeps a tile only if its own cone reaches the quad too, so the
+        // result never depends on which entries share the wave (with rounding,
+        // a tile test can pass where the enclosing quad's test fails).
         for (int q = 0; q < nqy_s * nqx_s; ++q) {
-            if (ballot(cones_touch_c(cone, ca, lqc[wv][q], lqcs[wv][q])) == 0ull) continue;
+            const bool hit_q = cones_touch_c(cone, ca, lqc[wv][q], lqcs[wv][q]);
+            if (ballot(hit_q) == 0ull) continue;
             const int qy = q / nqx_s, qx = q - qy * nqx_s;
             for (int d = 0; d < 4; ++d) {
                 const int ly = 2 * qy + (d >> 1), lx = 2 * qx + (d & 1);   // tile inside the supertile
                 if (ly >= sp.nty || lx >= sp.ntx) continue;
                 const int t = ly * sp.ntx + lx;
-                const uint64_t bal = ballot(cones_touch_c(cone, ca, ltc[wv][t], ltcs[wv][t]));
+                const uint64_t bal = ballot(hit_q && cones_touch_c(cone, ca, ltc[wv][t], ltcs[wv][t]));
                 if (lane == t) mine = bal;
             }
         }
@@ -785,8 +789,9 @@ struct TexelState {
 // the callers treat as "before shell 0".
 template <bool GEO>
 __device__ inline float shell_coord(float t, const TexelState& ts) {
-    if (GEO) return __builtin_amdgcn_logf(t) * ts.kinv - ts.lr0k;
-    return t * ts.kinv - 0.5f;
+#pragma clang fp contract(off)
+    if (GEO) return fmaf(__builtin_amdgcn_logf(t), ts.kinv, -ts.lr0k);
+    return fmaf(t, ts.kinv, -0.5f);
 }
 
 // Largest optical depth a pair may drop at either end of its erf ramp.
@@ -804,17 +809,30 @@ struct Counters {
     unsigned long long pre = 0;         // idle pairs already rejected by the distance pre-test
 };
 
+// Three-term dot products with the fused multiply-adds spelled out.
+__device__ inline float dot3(float a0, float a1, float a2, float b0, float b1, float b2) {
+#pragma clang fp contract(off)
+    return fmaf(a0, b0, fmaf(a1, b1, a2 * b2));
+}
+
+// The pair evaluation is inlined twice (the two record register sets of
+// walk_hits), and which copy evaluates a pair depends on the pair's place in
+// its list word.  Contraction is therefore off here and every fused
+// multiply-add is written out: the compiler may not fuse a*b + c*d one way in
+// one copy and the other way in the other, so a pair's increments are bitwise
+// the same whatever the order of the Gaussians.
 template <bool STATS, bool GEO>
 __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r, const TexelState& s,
                                                                 Counters& n) {
+#pragma clang fp contract(off)
     // Ray-line geometry in FP64: v = m x d, t_e = -(m . d).
-    const double vxd = r.my * s.dz - r.mz * s.dy;
-    const double vyd = r.mz * s.dx - r.mx * s.dz;
-    const double vzd = r.mx * s.dy - r.my * s.dx;
-    const double te = -(r.mx * s.dx + r.my * s.dy + r.mz * s.dz);
+    const double vxd = fma(r.my, s.dz, -(r.mz * s.dy));
+    const double vyd = fma(r.mz, s.dx, -(r.mx * s.dz));
+    const double vzd = fma(r.mx, s.dy, -(r.my * s.dx));
+    const double te = -fma(r.mx, s.dx, fma(r.my, s.dy, r.mz * s.dz));
     const float vx = (float)vxd, vy = (float)vyd, vz = (float)vzd;
     // cheap pre-test (conservative: it never drops a texel the full test keeps)
-    if ((ballot(vx * vx + vy * vy + vz * vz < r.r2) & s.vmask) == 0ull) {
+    if ((ballot(dot3(vx, vy, vz, vx, vy, vz) < r.r2) & s.vmask) == 0ull) {
         if (STATS) {
             n.idle += 1;
             n.pre += 1;
@@ -822,14 +840,14 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
         return;
     }
     // a = |W d|^2 (Eq. 2);  c - b^2/a = |adj(A)^(1/2) (m x d)|^2 / a
-    const float wd0 = r.w[0] * s.fx + r.w[1] * s.fy + r.w[2] * s.fz;
-    const float wd1 = r.w[3] * s.fx + r.w[4] * s.fy + r.w[5] * s.fz;
-    const float wd2 = r.w[6] * s.fx + r.w[7] * s.fy + r.w[8] * s.fz;
-    const float a = wd0 * wd0 + wd1 * wd1 + wd2 * wd2;
-    const float cv0 = r.c[0] * vx + r.c[1] * vy + r.c[2] * vz;
-    const float cv1 = r.c[3] * vx + r.c[4] * vy + r.c[5] * vz;
-    const float cv2 = r.c[6] * vx + r.c[7] * vy + r.c[8] * vz;
-    const float cc = cv0 * cv0 + cv1 * cv1 + cv2 * cv2;
+    const float wd0 = dot3(r.w[0], r.w[1], r.w[2], s.fx, s.fy, s.fz);
+    const float wd1 = dot3(r.w[3], r.w[4], r.w[5], s.fx, s.fy, s.fz);
+    const float wd2 = dot3(r.w[6], r.w[7], r.w[8], s.fx, s.fy, s.fz);
+    const float a = dot3(wd0, wd1, wd2, wd0, wd1, wd2);
+    const float cv0 = dot3(r.c[0], r.c[1], r.c[2], vx, vy, vz);
+    const float cv1 = dot3(r.c[3], r.c[4], r.c[5], vx, vy, vz);
+    const float cv2 = dot3(r.c[6], r.c[7], r.c[8], vx, vy, vz);
+    const float cc = dot3(cv0, cv1, cv2, cv0, cv1, cv2);
     // second conservative test, free of transcendentals: e0 = cc / a >= lg
     if ((ballot(cc < r.lg * a) & s.vmask) == 0ull) {
         if (STATS) n.idle += 1;
@@ -849,11 +867,12 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     if (STATS) n.act += __popcll(abal);
     // Distance along the ray of the Mahalanobis-closest point:
     // t* = -b/a = t_e - (W d).(W p)/a with p = d x v the perpendicular offset.
-    const float p0 = s.fy * vz - s.fz * vy, p1 = s.fz * vx - s.fx * vz, p2 = s.fx * vy - s.fy * vx;
-    const float wp0 = r.w[0] * p0 + r.w[1] * p1 + r.w[2] * p2;
-    const float wp1 = r.w[3] * p0 + r.w[4] * p1 + r.w[5] * p2;
-    const float wp2 = r.w[6] * p0 + r.w[7] * p1 + r.w[8] * p2;
-    const float corr = (wd0 * wp0 + wd1 * wp1 + wd2 * wp2) * ra;
+    const float p0 = fmaf(s.fy, vz, -(s.fz * vy)), p1 = fmaf(s.fz, vx, -(s.fx * vz)),
+                p2 = fmaf(s.fx, vy, -(s.fy * vx));
+    const float wp0 = dot3(r.w[0], r.w[1], r.w[2], p0, p1, p2);
+    const float wp1 = dot3(r.w[3], r.w[4], r.w[5], p0, p1, p2);
+    const float wp2 = dot3(r.w[6], r.w[7], r.w[8], p0, p1, p2);
+    const float corr = dot3(wd0, wd1, wd2, wp0, wp1, wp2) * ra;
     const float sa = a * rsa * 0.70710678118654752f;      // sqrt(a / 2)
     const float ts = (float)te - corr;                      // t* (shell range, erf at t = 0)
     // Ramp half-width in t: P0 erfc(z) <= P0 exp(-z^2) <= kRampEps for

@@ -150,6 +150,26 @@ def test_empty_and_transparent_scene():
     assert np.all(q == 1.0)
 
 
+def test_build_does_not_depend_on_gaussian_order():
+    """tau is a sum over Gaussians (Eq. 2) accumulated in fixed point, and
+    every culling decision is taken per Gaussian: the atlas of a 400k-Gaussian
+    room under 4 lights is bitwise the same for the caller's order, a random
+    permutation and a spatially sorted order (the binning waves then hold
+    different mixes of entries)."""
+    U = _util()
+    rng = np.random.default_rng(2024)
+    g = synth.random_gaussians(rng, synth.room_centres(rng, 400_000), 0.03)
+    lights = synth.CFG3_LIGHTS
+    spec = synth.AtlasSpec(256, 256, 32)
+    T0, _ = U.gpu_build(g, lights, spec, dtype="f16")
+    perm = rng.permutation(g.n)
+    zyx = np.lexsort((g.mean[:, 0], g.mean[:, 1], np.floor(g.mean[:, 2] * 4)))
+    for order in (perm, zyx):
+        T1, _ = U.gpu_build(g.subset(order), lights, spec, dtype="f16")
+        assert torch.equal(T0, T1)
+    assert T0.float().min().item() < 0.5
+
+
 def test_monotone_bounded_and_deterministic(cfg1):
     U = _util()
     spec = synth.AtlasSpec(64, 64, 32)
