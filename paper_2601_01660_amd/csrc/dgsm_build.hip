@@ -774,7 +774,7 @@ struct TexelState {
     uint64_t vmask;          // ballot of valid: the lanes that hold a texel of the atlas
     int lane;
     float lr0, kinv;         // shell coordinate of a radius: (log2 t - lr0) * kinv (geometric)
-    float lr0k;              // lr0 * kinv
+    float lr0k1;             // 1 - lr0 * kinv (geometric), 0.5 (uniform): the coordinate plus one
     double ratio;            // t_{k+1} / t_k (geometric) or t_{k+1} - t_k (uniform)
     int K;
     bool geometric;
@@ -782,16 +782,18 @@ struct TexelState {
     unsigned long long* inc; // LDS [K][64], fixed point
     const double* shells;    // LDS [K] shell radii t_k (FP64)
     int kmin, kmax;          // shells kept (the receiver range; 0 .. K-1 without a region)
+    bool roi;                // a receiver region is set (wave-uniform)
 };
 
-// Shell coordinate of a radius (fractional, unclamped).  Geometric shells:
-// a radius <= 0 gives -inf or NaN (log2 of 0 or of a negative number), which
-// the callers treat as "before shell 0".
+// Shell coordinate of a radius plus one (fractional, unclamped): its integer
+// part is the index of the first shell radius past t.  Geometric shells: a
+// radius <= 0 gives -inf or NaN (log2 of 0 or of a negative number), which
+// the callers floor at 0 (before shell 0).
 template <bool GEO>
-__device__ inline float shell_coord(float t, const TexelState& ts) {
+__device__ inline float shell_coord1(float t, const TexelState& ts) {
 #pragma clang fp contract(off)
-    if (GEO) return fmaf(__builtin_amdgcn_logf(t), ts.kinv, -ts.lr0k);
-    return fmaf(t, ts.kinv, -0.5f);
+    if (GEO) return fmaf(__builtin_amdgcn_logf(t), ts.kinv, ts.lr0k1);
+    return fmaf(t, ts.kinv, ts.lr0k1);
 }
 
 // Largest optical depth a pair may drop at either end of its erf ramp.
@@ -879,8 +881,9 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     // z^2 = ln(P0 / kRampEps) (at least 0.34), and z = sqrt(a/2) half, so
     // half = sqrt(2 z^2 / a).  (P0 of an active lane is far above the
     // denormal range: raw v_log / v_sqrt suffice.)
+    // (2 ln 2 log2(P0 / kRampEps) = 2 ln 2 log2 P0 + 46.0517, kRampEps = 1e-10)
     const float half =
-        __builtin_amdgcn_sqrtf(fmaxf(1.38629436f * __builtin_amdgcn_logf(P0 * (1.f / kRampEps)), 0.68f) * ra);
+        __builtin_amdgcn_sqrtf(fmaxf(fmaf(__builtin_amdgcn_logf(P0), 1.38629436f, 46.0517019f), 0.68f) * ra);
     float Ep = -1.f;
     if (ts < half) Ep = erf_as(-sa * ts);                   // the ramp reaches back to t = 0: erf there
     // Each lane walks its own ramp shells [ka, ka + len): the first shell past
@@ -888,13 +891,15 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     // or past the ramp end) everything up to the saturated tail.
     int ka = 0, len = 0;
     if (act) {
-        const float klo = shell_coord<GEO>(ts - half, s);
-        const float khi = fmaxf(shell_coord<GEO>(ts + half, s), -1.f);
-        ka = klo >= 0.f ? min((int)klo, s.K - 2) + 1 : 0;
-        const int kb = khi > (float)(s.K - 2) ? s.K - 1 : (int)khi + 1;
-        // only shells in [kmin, kmax] are kept: a ramp below the range still
-        // adds its whole step at kmin, one above it adds nothing
-        if (ka <= s.kmax) {
+        // ka: the first shell past the ramp start, kb: the first at or past its
+        // end (fmaxf takes 0 over a NaN coordinate)
+        ka = min((int)fmaxf(shell_coord1<GEO>(ts - half, s), 0.f), s.K - 1);
+        const int kb = min((int)fmaxf(shell_coord1<GEO>(ts + half, s), 0.f), s.K - 1);
+        if (!s.roi) {
+            len = max(kb, ka) - ka + 1;
+        } else if (ka <= s.kmax) {
+            // only shells in [kmin, kmax] are kept: a ramp below the range
+            // still adds its whole step at kmin, one above it adds nothing
             const int k0 = max(ka, s.kmin);
             len = max(min(kb, s.kmax), k0) - k0 + 1;
             ka = k0;
@@ -1147,17 +1152,18 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     double* shells = reinterpret_cast<double*>(inc + K * kWave + NW * kWave) + (NW * kWave) / 2;   // after s_min
     for (int k = tid; k < 2 * K - 1; k += kWave * NW) shells[k] = shell_radius(min(k, K - 1), K, g.spacing, g.r0, g.r1);
     st.shells = shells;
+    st.roi = p.roi != 0;
     st.kmin = p.roi ? W.roi_k[0] : 0;
     st.kmax = p.roi ? W.roi_k[1] : K - 1;
     if (st.geometric) {
         st.lr0 = __builtin_amdgcn_logf(g.r0);
         st.kinv = (float)(K - 1) / __builtin_amdgcn_logf(g.r1 / g.r0);
-        st.lr0k = st.lr0 * st.kinv;
+        st.lr0k1 = 1.f - st.lr0 * st.kinv;
         st.ratio = pow((double)g.r1 / (double)g.r0, 1.0 / (double)(K - 1));
     } else {
         st.lr0 = 0.f;
         st.kinv = (float)K / g.r1;
-        st.lr0k = 0.f;
+        st.lr0k1 = 0.5f;
         st.ratio = (double)g.r1 / (double)K;
     }
     for (int q = tid; q < K * kWave; q += kWave * NW) inc[q] = 0ull;
