@@ -778,7 +778,7 @@ struct TexelState {
     double ratio;            // t_{k+1} / t_k (geometric) or t_{k+1} - t_k (uniform)
     int K;
     bool geometric;
-    float pair_eps;
+    float half_eps;          // half the pair threshold: a lane is active when 2 P0 exceeds it
     unsigned long long* inc; // LDS [K][64], fixed point
     const double* shells;    // LDS [K] shell radii t_k (FP64)
     int kmin, kmax;          // shells kept (the receiver range; 0 .. K-1 without a region)
@@ -819,10 +819,11 @@ __device__ inline float dot3(float a0, float a1, float a2, float b0, float b1, f
 
 // The pair evaluation is inlined twice (the two record register sets of
 // walk_hits), and which copy evaluates a pair depends on the pair's place in
-// its list word.  Contraction is therefore off here and every fused
-// multiply-add is written out: the compiler may not fuse a*b + c*d one way in
-// one copy and the other way in the other, so a pair's increments are bitwise
-// the same whatever the order of the Gaussians.
+// its list word.  Every sum of two products is therefore written with explicit
+// fused multiply-adds (and contraction is off for the rest): the compiler has
+// no a*b + c*d left to fuse one way in one copy and the other way in the
+// other, so a pair's increments are bitwise the same whatever the order of
+// the Gaussians.
 template <bool STATS, bool GEO>
 __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r, const TexelState& s,
                                                                 Counters& n) {
@@ -859,9 +860,10 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     const float e0 = cc * ra;
     const float rsa = __builtin_amdgcn_rsqf(a);
     // prefactor of Eq. 3 times beta: beta sqrt(pi / (2a)) exp(-e0 / 2)
-    const float P0 = r.bp * rsa * __expf(-0.5f * e0);
-    const bool act = s.valid && (P0 + P0 > s.pair_eps);
-    const uint64_t abal = ballot(P0 + P0 > s.pair_eps) & s.vmask;
+    // (exp(-e0/2) = 2^(e0 * (-log2(e)/2)); 2 P0 > eps  <=>  P0 > eps/2, both exact)
+    const float P0 = r.bp * rsa * __builtin_amdgcn_exp2f(e0 * -0.72134752f);
+    const bool act = s.valid && (P0 > s.half_eps);
+    const uint64_t abal = ballot(P0 > s.half_eps) & s.vmask;
     if (abal == 0ull) {
         if (STATS) n.idle += 1;
         return;
@@ -874,9 +876,10 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     const float wp0 = dot3(r.w[0], r.w[1], r.w[2], p0, p1, p2);
     const float wp1 = dot3(r.w[3], r.w[4], r.w[5], p0, p1, p2);
     const float wp2 = dot3(r.w[6], r.w[7], r.w[8], p0, p1, p2);
-    const float corr = dot3(wd0, wd1, wd2, wp0, wp1, wp2) * ra;
+    const float dwp = dot3(wd0, wd1, wd2, wp0, wp1, wp2);
+    const float corr = dwp * ra;
     const float sa = a * rsa * 0.70710678118654752f;      // sqrt(a / 2)
-    const float ts = (float)te - corr;                      // t* (shell range, erf at t = 0)
+    const float ts = fmaf(-dwp, ra, (float)te);             // t* (shell range, erf at t = 0)
     // Ramp half-width in t: P0 erfc(z) <= P0 exp(-z^2) <= kRampEps for
     // z^2 = ln(P0 / kRampEps) (at least 0.34), and z = sqrt(a/2) half, so
     // half = sqrt(2 z^2 / a).  (P0 of an active lane is far above the
@@ -915,22 +918,27 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     // erf argument at shell k: sqrt(a/2) (t_k - t*), with t* = t_e - corr kept in FP64.
     // The loop runs until no lane has shells left; a finished lane reads on
     // into the padding of the shell table (2K - 1 entries) and adds nothing.
+    // Two shells per trip: the second reads and adds at fixed offsets from the
+    // first, and the previous erf value alternates between two registers.
+    // erf_as is non-decreasing up to rounding; a negative step from a rounding
+    // dip is skipped and the next step spans the dip.
     const double tsd = te - (double)corr;
     const double* sh = s.shells + ka;
     unsigned long long* dst = s.inc + ka * kWave + s.lane;
-#pragma unroll 2
-    for (int j = 0;; ++j) {
-        const bool live = j < len;
-        if (ballot(live) == 0ull) break;
-        const float x = sa * (float)(sh[j] - tsd);
-        // erf_as is non-decreasing up to rounding; a negative step from a
-        // rounding dip is skipped and the next step spans the dip
-        const float E = erf_as(x);
-        const float dI = P0 * (E - Ep);
-        Ep = E;
-        if (live && dI > 0.f)
-            __hip_atomic_fetch_add(dst, to_fixed(dI), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        dst += kWave;
+    for (int j = 0;; j += 2) {
+        if (ballot(j < len) == 0ull) break;
+        const float Ea = erf_as(sa * (float)(sh[0] - tsd));
+        const float dIa = P0 * (Ea - Ep);
+        if (j < len && dIa > 0.f)
+            __hip_atomic_fetch_add(dst, to_fixed(dIa), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (ballot(j + 1 < len) == 0ull) break;
+        const float Eb = erf_as(sa * (float)(sh[1] - tsd));
+        const float dIb = P0 * (Eb - Ea);
+        if (j + 1 < len && dIb > 0.f)
+            __hip_atomic_fetch_add(dst + kWave, to_fixed(dIb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        Ep = Eb;
+        sh += 2;
+        dst += 2 * kWave;
     }
 }
 
@@ -1147,7 +1155,7 @@ __global__ __launch_bounds__(kWave * NW) void tile_build_kernel(TileArgs p) {
     st.fx = (float)st.dx; st.fy = (float)st.dy; st.fz = (float)st.dz;
     st.K = K;
     st.geometric = g.spacing == DGSM_SHELLS_GEOMETRIC;
-    st.pair_eps = p.pair_eps;
+    st.half_eps = 0.5f * p.pair_eps;
     st.inc = inc;
     double* shells = reinterpret_cast<double*>(inc + K * kWave + NW * kWave) + (NW * kWave) / 2;   // after s_min
     for (int k = tid; k < 2 * K - 1; k += kWave * NW) shells[k] = shell_radius(min(k, K - 1), K, g.spacing, g.r0, g.r1);
