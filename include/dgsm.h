@@ -311,7 +311,9 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  *                 negative = never split
  *
  * dgsm_plan_create allocates all device memory the plan needs (the only
- * allocating entry points are create and destroy) and synchronises the device.
+ * allocating entry points are create and destroy) and synchronises the device;
+ * dgsm_plan_destroy synchronises the device (a run may still be in flight)
+ * before it frees the plan's buffers, streams and events.
  * dgsm_plan_run enqueues on `stream`; with use_graph = 1 the whole run (static
  * build + all frames) is captured once into a hipGraph and replayed (stream
  * must then be a created stream, not NULL; a run with different dynamic or

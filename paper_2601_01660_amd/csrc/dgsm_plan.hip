@@ -272,6 +272,8 @@ hipError_t dalloc(T** p, size_t bytes) {
 
 void plan_free(dgsm_plan p) {
     if (!p) return;
+    // a run may still be in flight on the caller's stream or the chain streams
+    (void)hipDeviceSynchronize();
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     void* bufs[] = {p->lights,     p->mean,  p->scale,        p->rot,  p->opacity, p->out_index,
                     p->tau_static, p->atlas, p->atlas_static, p->ws_a, p->ws_b,    p->in_pos,
