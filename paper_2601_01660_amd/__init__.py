@@ -164,6 +164,23 @@ def _cuda(t, name):
     return t
 
 
+def _buf(t, shape, dtype, name):
+    """Require a contiguous CUDA tensor of exactly this shape and dtype: the library
+    reads or writes it through a raw pointer sized from the other arguments."""
+    _cuda(t, name)
+    if t is not None and (tuple(t.shape) != tuple(shape) or t.dtype != dtype):
+        raise ValueError(f"{name} must be a {dtype} tensor of shape {tuple(shape)}, "
+                         f"got {t.dtype} of shape {tuple(t.shape)}")
+    return t
+
+
+def _rows(t, width, name):
+    """Require an [n, width] tensor (after conversion to a float32 CUDA tensor)."""
+    if t.dim() != 2 or t.shape[1] != width:
+        raise ValueError(f"{name} must be [n, {width}], got shape {tuple(t.shape)}")
+    return t
+
+
 def _dev(t, dtype=torch.float32):
     if t is None:
         return None
@@ -246,7 +263,7 @@ def dgsm_build_workspace_size(atlas: Atlas, n_gauss: int, n_lights: int) -> int:
 def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0, out=None, workspace=None,
                beta: str = "trace"):
     """Build T[L, K, H, W] (see dgsm_build in include/dgsm.h)."""
-    lights = _dev(lights)
+    lights = _rows(_dev(lights), 3, "lights")
     L = int(lights.shape[0])
     d = atlas.struct()
     ws_bytes = dgsm_build_workspace_size(atlas, gaussians.n, L)
@@ -256,7 +273,7 @@ def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0,
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=lights.device)
     if out is None:
         out = torch.empty((L, atlas.K, atlas.H, atlas.W), dtype=atlas.torch_dtype, device=lights.device)
-    _cuda(out, "out")
+    _buf(out, (L, atlas.K, atlas.H, atlas.W), atlas.torch_dtype, "out")
     _cuda(workspace, "workspace")
     lt = _Lights(lights.data_ptr(), L, kappa, BETA_MODES[beta])
     gs = gaussians.struct()
@@ -269,8 +286,8 @@ def dgsm_build_roi(lights, gaussians: GaussianSet, atlas: Atlas, receivers, box=
                    workspace=None, beta: str = "trace"):
     """Build T[L, K, H, W] restricted to the receivers' region (see dgsm_build_roi in
     include/dgsm.h); box = (cx, cy, half, zmin, zmax) or None (every receiver)."""
-    lights = _dev(lights)
-    receivers = _dev(receivers)
+    lights = _rows(_dev(lights), 3, "lights")
+    receivers = _rows(_dev(receivers), 3, "receivers")
     L = int(lights.shape[0])
     d = atlas.struct()
     ws_bytes = dgsm_build_workspace_size(atlas, gaussians.n, L)
@@ -280,7 +297,7 @@ def dgsm_build_roi(lights, gaussians: GaussianSet, atlas: Atlas, receivers, box=
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=lights.device)
     if out is None:
         out = torch.empty((L, atlas.K, atlas.H, atlas.W), dtype=atlas.torch_dtype, device=lights.device)
-    _cuda(out, "out")
+    _buf(out, (L, atlas.K, atlas.H, atlas.W), atlas.torch_dtype, "out")
     _cuda(workspace, "workspace")
     bx = _RoiBox(*(box if box is not None else (0.0, 0.0, 0.0, 0.0, 0.0)))
     lt = _Lights(lights.data_ptr(), L, kappa, BETA_MODES[beta])
@@ -293,7 +310,7 @@ def dgsm_build_roi(lights, gaussians: GaussianSet, atlas: Atlas, receivers, box=
 
 def dgsm_bin(lights, gaussians: GaussianSet, atlas: Atlas, workspace, kappa: float = 1.0, beta: str = "trace"):
     """First build phase: culling cones and supertile lists into ``workspace``."""
-    lights = _dev(lights)
+    lights = _rows(_dev(lights), 3, "lights")
     _cuda(workspace, "workspace")
     d = atlas.struct()
     lt = _Lights(lights.data_ptr(), int(lights.shape[0]), kappa, BETA_MODES[beta])
@@ -307,8 +324,8 @@ def dgsm_accumulate(lights, atlas: Atlas, n_gauss: int, out, workspace, stats=No
 
     ``stats`` (optional int64 CUDA tensor of >= 8 entries, zeroed by the caller)
     receives the work counters documented in dgsm.h."""
-    lights = _dev(lights)
-    _cuda(out, "out")
+    lights = _rows(_dev(lights), 3, "lights")
+    _buf(out, (int(lights.shape[0]), atlas.K, atlas.H, atlas.W), atlas.torch_dtype, "out")
     _cuda(workspace, "workspace")
     _cuda(stats, "stats")
     if stats is not None and (stats.dtype != torch.int64 or stats.numel() < 8):
@@ -322,7 +339,7 @@ def dgsm_accumulate(lights, atlas: Atlas, n_gauss: int, out, workspace, stats=No
 
 def dgsm_query_footprint(lights, atlas: Atlas, table, gaussians: GaussianSet, z, w, out=None):
     """Footprint-averaged T[L, N] (offsets z [n, 3] in the principal-axes frame, weights w [n])."""
-    lights = _dev(lights)
+    lights = _rows(_dev(lights), 3, "lights")
     z = _dev(z)
     w = _dev(w)
     L = int(lights.shape[0])
@@ -330,8 +347,8 @@ def dgsm_query_footprint(lights, atlas: Atlas, table, gaussians: GaussianSet, z,
         raise ValueError("z must be [n, 3] for n weights")
     if out is None:
         out = torch.empty((L, gaussians.n), dtype=torch.float32, device=gaussians.mean.device)
-    _cuda(out, "out")
-    _cuda(table, "table")
+    _buf(out, (L, gaussians.n), torch.float32, "out")
+    _buf(table, (L, atlas.K, atlas.H, atlas.W), atlas.torch_dtype, "table")
     d = atlas.struct()
     lt = _Lights(lights.data_ptr(), L, 1.0)
     gs = gaussians.struct()
@@ -360,14 +377,14 @@ def dgsm_work_units(atlas: Atlas, n_gauss: int, n_lights: int, workspace, light:
 
 def dgsm_query(lights, atlas: Atlas, table, points, out=None):
     """Trilinear lookup T[L, P] of the atlas at points [P, 3]."""
-    lights = _dev(lights)
-    points = _dev(points)
+    lights = _rows(_dev(lights), 3, "lights")
+    points = _rows(_dev(points), 3, "points")
     L = int(lights.shape[0])
     P = int(points.shape[0])
     if out is None:
         out = torch.empty((L, P), dtype=torch.float32, device=points.device)
-    _cuda(out, "out")
-    _cuda(table, "table")
+    _buf(out, (L, P), torch.float32, "out")
+    _buf(table, (L, atlas.K, atlas.H, atlas.W), atlas.torch_dtype, "table")
     d = atlas.struct()
     lt = _Lights(lights.data_ptr(), L, 1.0)
     _check(lib().dgsm_query(ctypes.byref(lt), ctypes.byref(d), _ptr(table), _ptr(points), P, _ptr(out), _stream()))
@@ -388,7 +405,7 @@ def dgsm_probe_fit(Y, D, w, Kp: int = 16, lam: float = 0.0, out=None, workspace=
         workspace = torch.empty(need, dtype=torch.uint8, device=w.device)
     if out is None:
         out = torch.empty((Kp, 3), dtype=torch.float32, device=w.device)
-    _cuda(out, "out")
+    _buf(out, (Kp, 3), torch.float32, "out")
     _check(lib().dgsm_probe_fit(_ptr(Y), _ptr(D), _ptr(w), n, Kp, lam, _ptr(out), _ptr(workspace),
                                 workspace.numel(), _stream()))
     return out
@@ -406,6 +423,7 @@ def dgsm_check_gaussians(gaussians: GaussianSet) -> int:
 def dgsm_alpha_centroid(gaussians: GaussianSet, out=None):
     if out is None:
         out = torch.empty(3, dtype=torch.float32, device=gaussians.mean.device)
+    _buf(out, (3,), torch.float32, "out")
     gs = gaussians.struct()
     _check(lib().dgsm_alpha_centroid(ctypes.byref(gs), _ptr(out), _stream()))
     return out
@@ -441,7 +459,7 @@ class Plan:
     def __init__(self, lights, atlas: Atlas, static: GaussianSet, n_dynamic: int, frames: int,
                  static_cache: bool = True, autotune: bool = True, tile_waves: int = 8, split_units: int = 0,
                  kappa: float = 1.0, beta: str = "trace"):
-        lights = _dev(lights)
+        lights = _rows(_dev(lights), 3, "lights")
         self.L = int(lights.shape[0])
         self.atlas = atlas
         self.n_static = static.n
@@ -471,10 +489,14 @@ class Plan:
     def run(self, dynamic: GaussianSet, translations, out=None, use_graph: bool = True):
         """T[frames, L, n_static + n_dynamic] for one run; enqueued on the current stream."""
         translations = _dev(translations)
-        _cuda(out, "out")
+        if tuple(translations.shape) != (self.frames, 3):
+            raise ValueError(f"translations must be [{self.frames}, 3], got shape {tuple(translations.shape)}")
+        if dynamic.n != self.n_dynamic:
+            raise ValueError(f"the plan was made for {self.n_dynamic} dynamic Gaussians, got {dynamic.n}")
         if out is None:
             out = torch.empty((self.frames, self.L, self.n_points), dtype=torch.float32,
                               device=translations.device)
+        _buf(out, (self.frames, self.L, self.n_points), torch.float32, "out")
         gs = dynamic.struct()
         _check(lib().dgsm_plan_run(self._h, ctypes.byref(gs), _ptr(translations), _ptr(out), int(use_graph),
                                    _stream()))
@@ -498,7 +520,9 @@ class Plan:
 
 def mlp_grad(params, uvrt, atlas: Atlas, grad=None, loss=None, workspace=None):
     """Loss gradient [MLP_PARAMS] at params on samples uvrt [B, 4] = (u, v, rho, target)."""
-    params, uvrt = _dev(params), _dev(uvrt)
+    params, uvrt = _dev(params), _rows(_dev(uvrt), 4, "uvrt")
+    if params.numel() != MLP_PARAMS:
+        raise ValueError(f"params must hold {MLP_PARAMS} values")
     B = int(uvrt.shape[0])
     need = int(lib().dgsm_mlp_workspace_size(B))
     if need == 0:
@@ -507,6 +531,8 @@ def mlp_grad(params, uvrt, atlas: Atlas, grad=None, loss=None, workspace=None):
         workspace = torch.empty(need, dtype=torch.uint8, device=params.device)
     grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=params.device) if grad is None else grad
     loss = torch.empty(1, dtype=torch.float32, device=params.device) if loss is None else loss
+    _buf(grad, (MLP_PARAMS,), torch.float32, "grad")
+    _buf(loss, (1,), torch.float32, "loss")
     d = atlas.struct()
     _check(lib().dgsm_mlp_grad(_ptr(params), _ptr(uvrt), B, ctypes.byref(d), _ptr(grad), _ptr(loss),
                                _ptr(workspace), workspace.numel(), _stream()))
@@ -516,9 +542,9 @@ def mlp_grad(params, uvrt, atlas: Atlas, grad=None, loss=None, workspace=None):
 def mlp_train(params, adam_mv, atlas: Atlas, table_l, steps, batch=16384, step0=0, lr0=1e-3, lr1=1e-4,
               seed=1, beta1=0.9, beta2=0.999, eps=1e-8, workspace=None):
     """``steps`` Adam steps (in place on params / adam_mv); returns the per-step losses."""
-    _cuda(params, "params")
-    _cuda(adam_mv, "adam_mv")
-    _cuda(table_l, "table_l")
+    _buf(params, (MLP_PARAMS,), torch.float32, "params")
+    _buf(adam_mv, (2 * MLP_PARAMS,), torch.float32, "adam_mv")
+    _buf(table_l, (atlas.K, atlas.H, atlas.W), atlas.torch_dtype, "table_l")
     need = int(lib().dgsm_mlp_workspace_size(batch))
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=params.device)
@@ -537,7 +563,9 @@ def mlp_regions(atlas: Atlas) -> int:
 def mlp_check(params, atlas: Atlas, table_l, n_check=262144, seed=12345, thresh=1e-2):
     """Fallback mask [regions] (uint8) and (flagged samples, max |dT|) on a held-out sample set."""
     params = _dev(params)
-    _cuda(table_l, "table_l")
+    if params.numel() != MLP_PARAMS:
+        raise ValueError(f"params must hold {MLP_PARAMS} values")
+    _buf(table_l, (atlas.K, atlas.H, atlas.W), atlas.torch_dtype, "table_l")
     dev = params.device
     mask = torch.zeros(mlp_regions(atlas), dtype=torch.uint8, device=dev)
     stats = torch.zeros(2, dtype=torch.int32, device=dev)
@@ -553,14 +581,16 @@ def mlp_check(params, atlas: Atlas, table_l, n_check=262144, seed=12345, thresh=
 
 def mlp_infer(params, lights, atlas: Atlas, points, table=None, mask=None, out=None, workspace=None):
     """T[L, P] of each light's network at points; flagged regions fall back to the atlas."""
-    params, lights, points = _dev(params), _dev(lights), _dev(points)
-    _cuda(table, "table")
+    params, lights, points = _dev(params), _rows(_dev(lights), 3, "lights"), _rows(_dev(points), 3, "points")
+    L, P = int(lights.shape[0]), int(points.shape[0])
+    if params.numel() != L * MLP_PARAMS:
+        raise ValueError(f"params must hold {L} x {MLP_PARAMS} values")
+    _buf(table, (L, atlas.K, atlas.H, atlas.W), atlas.torch_dtype, "table")
     if mask is not None:
         _cuda(mask, "mask")
-        if mask.dtype != torch.uint8:
-            raise ValueError("mask must be uint8")
-    _cuda(out, "out")
-    L, P = int(lights.shape[0]), int(points.shape[0])
+        if mask.dtype != torch.uint8 or mask.numel() != L * mlp_regions(atlas):
+            raise ValueError(f"mask must be uint8 with {L} x {mlp_regions(atlas)} entries")
+    _buf(out, (L, P), torch.float32, "out")
     need = int(lib().dgsm_mlp_infer_workspace_size(L))
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(need, dtype=torch.uint8, device=points.device)

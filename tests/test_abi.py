@@ -152,6 +152,19 @@ def test_binding_rejects_host_tensors_for_device_arguments():
     assert P._cuda(None, "x") is None
 
 
+def test_binding_shape_helpers():
+    """[n, 3] inputs and exactly-sized buffers are checked before any call."""
+    import torch
+    import paper_2601_01660_amd as P
+    assert P._rows(torch.zeros(5, 3), 3, "points").shape == (5, 3)
+    for bad in (torch.zeros(5), torch.zeros(5, 4), torch.zeros(2, 5, 3)):
+        with pytest.raises(ValueError):
+            P._rows(bad, 3, "points")
+    with pytest.raises(ValueError):
+        P._buf(torch.zeros(2, 3), (2, 3), torch.float32, "out")     # host tensor
+    assert P._buf(None, (2, 3), torch.float32, "out") is None
+
+
 def test_library_stencil_matches_the_oracle_reading(lib):
     import numpy as np
     import paper_2601_01660_amd as P

@@ -170,6 +170,39 @@ def test_build_does_not_depend_on_gaussian_order():
     assert T0.float().min().item() < 0.5
 
 
+def test_binding_rejects_buffers_of_the_wrong_shape(cfg1):
+    """Outputs, tables, points and translations reach the library as raw
+    pointers: a tensor of the wrong shape or dtype is refused before any launch."""
+    import paper_2601_01660_amd as P
+    g, lights = cfg1["gaussians"], cfg1["lights"]
+    atlas = P.Atlas(32, 32, 16, dtype="f32")
+    gs = P.GaussianSet.from_host(g)
+    lt = torch.from_numpy(np.ascontiguousarray(lights, dtype=np.float32)).cuda()
+    L = lt.shape[0]
+    T = P.dgsm_build(lt, gs, atlas)
+    with pytest.raises(ValueError):
+        P.dgsm_build(lt, gs, atlas, out=torch.empty((L, 16, 32, 16), device="cuda"))
+    with pytest.raises(ValueError):
+        P.dgsm_build(lt, gs, atlas, out=torch.empty((L, 16, 32, 32), dtype=torch.float16, device="cuda"))
+    pts = torch.zeros((10, 3), device="cuda")
+    with pytest.raises(ValueError):
+        P.dgsm_query(lt, atlas, T, pts, out=torch.empty((L, 5), device="cuda"))
+    with pytest.raises(ValueError):
+        P.dgsm_query(lt, atlas, T[:, :8].contiguous(), pts)
+    with pytest.raises(ValueError):
+        P.dgsm_query(lt, atlas, T, torch.zeros((10, 4), device="cuda"))
+    plan = P.Plan(lt, atlas, gs, 0, 3, static_cache=True, autotune=False)
+    empty = P.GaussianSet.from_host(synth.Gaussians.empty())
+    with pytest.raises(ValueError):
+        plan.run(empty, torch.zeros((2, 3), device="cuda"))
+    with pytest.raises(ValueError):
+        plan.run(empty, torch.zeros((3, 3), device="cuda"), out=torch.empty((3, L, 7), device="cuda"))
+    out = plan.run(empty, torch.zeros((3, 3), device="cuda"), use_graph=False)
+    torch.cuda.synchronize()
+    assert out.shape == (3, L, g.n)
+    plan.close()
+
+
 def test_monotone_bounded_and_deterministic(cfg1):
     U = _util()
     spec = synth.AtlasSpec(64, 64, 32)
