@@ -38,8 +38,8 @@ PEAK_HBM_GBS = 8000.0
 # device copy.  Valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("paper_2601_01660_amd/csrc/dgsm_build.hip", "paper_2601_01660_amd/csrc/dgsm_device.hpp",
                    "paper_2601_01660_amd/csrc/dgsm_host.hpp")
-TRAFFIC = {"sha256": "0af8bc4d871954eb680d50a76944921c86e7c8cd0339b20c9401d2175fe1ca12",
-           "fetch_bytes": 34763304578, "write_bytes": 1190505033,
+TRAFFIC = {"sha256": "f259b9101183ae5ea833c44699ca8e2a032055bf56d82848afb5fc36ac569d7b",
+           "fetch_bytes": 34961702563, "write_bytes": 1493166226,
            "profile": "profiles/tile_build_counters__room2M_avatar150k_4lights_512x512x64_f16.md"}
 
 
