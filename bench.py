@@ -320,6 +320,22 @@ def main():
     log(f"probe fit: {probe}")
     torch.cuda.empty_cache()
 
+    # ---- per-Gaussian SH radiance transfer (Sec. 3.5) of the avatar, 16-coefficient probe ----
+    rng_sh = np.random.default_rng(11)
+    probe_sh = torch.from_numpy(synth.sh_probe(rng_sh, 16)).to(dev)
+    colour_sh = torch.from_numpy(synth.sh_colours(rng_sh, avatar.n)).to(dev)
+    av_set = P.GaussianSet(av, scale[scene.n:], rot[scene.n:], opac[scene.n:])
+    centroid = P.dgsm_alpha_centroid(av_set)
+    P.sh_transfer(probe_sh, av_set, colour_sh, centroid=centroid)
+    torch.cuda.synchronize()
+    ms_sh = timed(lambda: P.sh_transfer(probe_sh, av_set, colour_sh, centroid=centroid), 10)
+    flop_sh = avatar.n * 32 * 64 * 14      # Gaussian x grid direction: dot 5, max 1, 4 FMA 8
+    sh_tr = {"gaussians": avatar.n, "probe_coeffs": 16, "grid": [32, 64], "ms": round(ms_sh, 4),
+             "tflops_algorithmic": round(flop_sh / (ms_sh * 1e-3) / 1e12, 2), "peak_tflops": PEAK_FP32_TFLOPS}
+    log(f"SH transfer: {sh_tr}")
+    del colour_sh
+    torch.cuda.empty_cache()
+
     # ---- batched plan: static cache + captured graph (the headline) -------------------------
     static_set = P.GaussianSet(means[0, :scene.n], scale[:scene.n], rot[:scene.n], opac[:scene.n])
     dyn_set = P.GaussianSet(av, scale[scene.n:], rot[scene.n:], opac[scene.n:])
@@ -371,7 +387,8 @@ def main():
            "comparison_ms_per_frame": {"batched_graph_static_cache": round(ms_frame, 4),
                                        "batched_graph_no_cache": round(ms_nocache / F, 4),
                                        "plain_per_frame_launches": round(ms_plain / F, 4)},
-           "roofline": roofline, "footprint_query": footprint, "roi_build": roi, "cube_map": cubemap, "probe_fit": probe}
+           "roofline": roofline, "footprint_query": footprint, "roi_build": roi, "cube_map": cubemap, "probe_fit": probe,
+           "sh_transfer": sh_tr}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(P, torch, np, dev, lights, atlas, static_set, dyn_set, tr, N, L, spec,
                                          args.mlp_steps, timed)

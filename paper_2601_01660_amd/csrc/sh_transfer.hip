@@ -2,8 +2,11 @@
 //
 // Each workgroup stages chunks of the lat-long grid in LDS as
 // (w_x, w_y, w_z, weight) and (weight * L_r, weight * L_g, weight * L_b)
-// with L = B(w) A evaluated from the probe; every thread then owns one
-// Gaussian and sweeps the staged directions with broadcast LDS reads.
+// with L = B(w) A evaluated from the probe.  A workgroup serves 128 Gaussians
+// (two per lane, so each broadcast pair of LDS reads feeds both); its four
+// waves sweep every fourth staged direction, and the four partial sums are
+// added in wave order at the end (more waves than one Gaussian per thread
+// sweeping every direction, for latency).
 
 #include "dgsm_device.hpp"
 #include "dgsm_host.hpp"
@@ -11,7 +14,9 @@
 namespace dgsm {
 
 constexpr int kShThreads = 256;
-constexpr int kShChunk = 1024;
+constexpr int kShWaves = kShThreads / kWave;   // waves sharing one lane's Gaussian
+constexpr int kShChunk = 512;
+constexpr int kShG = 1;                        // Gaussians per lane
 
 struct ShArgs {
     const float* probe;      // [kp][3]
@@ -29,32 +34,61 @@ struct ShArgs {
     float* rgb_out;
 };
 
+// Normal of Gaussian i: rotation column of its smallest scale, facing away
+// from the centroid.
+__device__ inline float3 gaussian_normal(const ShArgs& a, int64_t i) {
+    float qw = a.rot[4 * i], qx = a.rot[4 * i + 1], qy = a.rot[4 * i + 2], qz = a.rot[4 * i + 3];
+    const float qn = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+    const float s0 = a.scale[3 * i], s1 = a.scale[3 * i + 1], s2 = a.scale[3 * i + 2];
+    int ax = 0;
+    if (s1 < s0) ax = 1;
+    if (s2 < (ax == 0 ? s0 : s1)) ax = 2;
+    float nx, ny, nz;
+    if (ax == 0) { nx = 1 - 2 * (qy * qy + qz * qz); ny = 2 * (qx * qy + qw * qz); nz = 2 * (qx * qz - qw * qy); }
+    else if (ax == 1) { nx = 2 * (qx * qy - qw * qz); ny = 1 - 2 * (qx * qx + qz * qz); nz = 2 * (qy * qz + qw * qx); }
+    else { nx = 2 * (qx * qz + qw * qy); ny = 2 * (qy * qz - qw * qx); nz = 1 - 2 * (qx * qx + qy * qy); }
+    const float side = nx * (a.mean[3 * i] - a.centroid[0]) + ny * (a.mean[3 * i + 1] - a.centroid[1]) +
+                       nz * (a.mean[3 * i + 2] - a.centroid[2]);
+    if (side < 0.f) { nx = -nx; ny = -ny; nz = -nz; }
+    return make_float3(nx, ny, nz);
+}
+
+// Clipped per-channel scale from the sums (n_r, n_g, n_b, den), then the relit
+// SH coefficients and RGB of Gaussian i.
+__device__ inline void finish_gaussian(const ShArgs& a, int64_t i, float4 acc) {
+    const float inv = 1.f / (acc.w + a.eps);
+    const float s[3] = {fminf(fmaxf(acc.x * inv, 0.f), a.clip_max), fminf(fmaxf(acc.y * inv, 0.f), a.clip_max),
+                        fminf(fmaxf(acc.z * inv, 0.f), a.clip_max)};
+    for (int c = 0; c < 3; ++c) a.scale_out[3 * i + c] = s[c];
+    if (a.colour_sh) {
+        const float* f = a.colour_sh + 48 * i;
+        if (a.colour_sh_out) {
+            float* fo = a.colour_sh_out + 48 * i;
+            for (int k = 0; k < 16; ++k)
+                for (int c = 0; c < 3; ++c) fo[3 * k + c] = a.gamma * s[c] * f[3 * k + c];
+        }
+        if (a.rgb_out)
+            for (int c = 0; c < 3; ++c)
+                a.rgb_out[3 * i + c] = fmaxf(0.f, a.gamma * (0.5f + 0.28209479177387814f * f[c]) * s[c]);
+    }
+}
+
 __global__ __launch_bounds__(kShThreads) void sh_transfer_kernel(ShArgs a) {
     __shared__ float4 dirw[kShChunk];
     __shared__ float4 lw[kShChunk];
-    const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * kShThreads + tid;
-    const bool in = i < a.n;
+    __shared__ float4 part[kShWaves][kShG * kWave];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    // lane's Gaussians: i0 + 64 g, g < kShG
+    const int64_t i0 = (int64_t)blockIdx.x * (kShG * kWave) + lane;
+    float3 nrm[kShG];
+#pragma unroll
+    for (int g = 0; g < kShG; ++g)
+        nrm[g] = i0 + kWave * g < a.n ? gaussian_normal(a, i0 + kWave * g) : make_float3(0.f, 0.f, 1.f);
 
-    // normal: rotation column of the smallest scale, facing away from the centroid
-    float nx = 0.f, ny = 0.f, nz = 1.f;
-    if (in) {
-        float qw = a.rot[4 * i], qx = a.rot[4 * i + 1], qy = a.rot[4 * i + 2], qz = a.rot[4 * i + 3];
-        const float qn = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
-        qw *= qn; qx *= qn; qy *= qn; qz *= qn;
-        const float s0 = a.scale[3 * i], s1 = a.scale[3 * i + 1], s2 = a.scale[3 * i + 2];
-        int ax = 0;
-        if (s1 < s0) ax = 1;
-        if (s2 < (ax == 0 ? s0 : s1)) ax = 2;
-        if (ax == 0) { nx = 1 - 2 * (qy * qy + qz * qz); ny = 2 * (qx * qy + qw * qz); nz = 2 * (qx * qz - qw * qy); }
-        else if (ax == 1) { nx = 2 * (qx * qy - qw * qz); ny = 1 - 2 * (qx * qx + qz * qz); nz = 2 * (qy * qz + qw * qx); }
-        else { nx = 2 * (qx * qz + qw * qy); ny = 2 * (qy * qz - qw * qx); nz = 1 - 2 * (qx * qx + qy * qy); }
-        const float side = nx * (a.mean[3 * i] - a.centroid[0]) + ny * (a.mean[3 * i + 1] - a.centroid[1]) +
-                           nz * (a.mean[3 * i + 2] - a.centroid[2]);
-        if (side < 0.f) { nx = -nx; ny = -ny; nz = -nz; }
-    }
-
-    float n0 = 0.f, n1 = 0.f, n2 = 0.f, den = 0.f;
+    float4 acc[kShG];
+#pragma unroll
+    for (int g = 0; g < kShG; ++g) acc[g] = make_float4(0.f, 0.f, 0.f, 0.f);
     const int M = a.n_theta * a.n_phi;
     const float dth = 3.14159265358979324f / (float)a.n_theta;
     const float dph = 6.28318530717958648f / (float)a.n_phi;
@@ -80,39 +114,43 @@ __global__ __launch_bounds__(kShThreads) void sh_transfer_kernel(ShArgs a) {
             lw[j] = make_float4(st * L0, st * L1, st * L2, 0.f);
         }
         __syncthreads();
+        // the cosine lobe max(0, n.w)^q; q = 1 (the default) without the power
         if (a.q == 1.f) {
-            for (int j = 0; j < cnt; ++j) {
+            for (int j = wave; j < cnt; j += kShWaves) {
                 const float4 d = dirw[j];
-                const float S = fmaxf(0.f, nx * d.x + ny * d.y + nz * d.z);
                 const float4 l = lw[j];
-                n0 += l.x * S; n1 += l.y * S; n2 += l.z * S; den += d.w * S;
+#pragma unroll
+                for (int g = 0; g < kShG; ++g) {
+                    const float S = fmaxf(0.f, nrm[g].x * d.x + nrm[g].y * d.y + nrm[g].z * d.z);
+                    acc[g].x += l.x * S; acc[g].y += l.y * S; acc[g].z += l.z * S; acc[g].w += d.w * S;
+                }
             }
         } else {
-            for (int j = 0; j < cnt; ++j) {
+            for (int j = wave; j < cnt; j += kShWaves) {
                 const float4 d = dirw[j];
-                const float c = nx * d.x + ny * d.y + nz * d.z;
-                const float S = c > 0.f ? __powf(c, a.q) : 0.f;
                 const float4 l = lw[j];
-                n0 += l.x * S; n1 += l.y * S; n2 += l.z * S; den += d.w * S;
+#pragma unroll
+                for (int g = 0; g < kShG; ++g) {
+                    const float c = nrm[g].x * d.x + nrm[g].y * d.y + nrm[g].z * d.z;
+                    const float S = c > 0.f ? __powf(c, a.q) : 0.f;
+                    acc[g].x += l.x * S; acc[g].y += l.y * S; acc[g].z += l.z * S; acc[g].w += d.w * S;
+                }
             }
         }
     }
-    if (!in) return;
-    const float inv = 1.f / (den + a.eps);
-    const float s[3] = {fminf(fmaxf(n0 * inv, 0.f), a.clip_max), fminf(fmaxf(n1 * inv, 0.f), a.clip_max),
-                        fminf(fmaxf(n2 * inv, 0.f), a.clip_max)};
-    for (int c = 0; c < 3; ++c) a.scale_out[3 * i + c] = s[c];
-    if (a.colour_sh) {
-        const float* f = a.colour_sh + 48 * i;
-        if (a.colour_sh_out) {
-            float* fo = a.colour_sh_out + 48 * i;
-            for (int k = 0; k < 16; ++k)
-                for (int c = 0; c < 3; ++c) fo[3 * k + c] = a.gamma * s[c] * f[3 * k + c];
-        }
-        if (a.rgb_out)
-            for (int c = 0; c < 3; ++c)
-                a.rgb_out[3 * i + c] = fmaxf(0.f, a.gamma * (0.5f + 0.28209479177387814f * f[c]) * s[c]);
+    // the waves' partial sums, added in wave order; wave g finishes Gaussian i0 + 64 g
+#pragma unroll
+    for (int g = 0; g < kShG; ++g) part[wave][g * kWave + lane] = acc[g];
+    __syncthreads();
+    if (wave >= kShG) return;
+    const int64_t i = i0 + kWave * wave;
+    if (i >= a.n) return;
+    float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int w = 0; w < kShWaves; ++w) {
+        const float4 q = part[w][wave * kWave + lane];
+        sum.x += q.x; sum.y += q.y; sum.z += q.z; sum.w += q.w;
     }
+    finish_gaussian(a, i, sum);
 }
 
 // Alpha-weighted centroid, one workgroup, FP64 partial sums in a fixed order.
@@ -156,7 +194,7 @@ extern "C" dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm
     ShArgs a{probe_sh, Kp, gaussians->mean, gaussians->scale, gaussians->rot, gaussians->n, colour_sh,
              params->centroid, params->n_theta, params->n_phi, params->q, params->clip_max, params->eps,
              params->gamma, scale_out, colour_sh_out, rgb_out};
-    const unsigned blocks = (unsigned)((gaussians->n + kShThreads - 1) / kShThreads);
+    const unsigned blocks = (unsigned)((gaussians->n + kShG * kWave - 1) / (kShG * kWave));
     sh_transfer_kernel<<<blocks, kShThreads, 0, reinterpret_cast<hipStream_t>(stream)>>>(a);
     return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
