@@ -181,6 +181,19 @@ def _rows(t, width, name):
     return t
 
 
+def _shape(t, shape, name, rows=None, width=None):
+    """Check the shape of an input before it is moved to the device (None passes):
+    an exact ``shape``, or ``rows`` in an allowed set with ``width`` columns."""
+    if t is None:
+        return None
+    got = tuple(t.shape) if hasattr(t, "shape") else tuple(torch.as_tensor(t).shape)
+    if shape is not None and got != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {got}")
+    if rows is not None and (len(got) != 2 or got[0] not in rows or got[1] != width):
+        raise ValueError(f"{name} must be [n, {width}] with n in {rows}, got {got}")
+    return t
+
+
 def _dev(t, dtype=torch.float32):
     if t is None:
         return None
@@ -212,11 +225,18 @@ class GaussianSet:
         return GaussianSet(_dev(g.mean), _dev(g.scale), _dev(g.rot), _dev(g.opacity))
 
     def struct(self) -> _Gaussians:
-        for f in ("mean", "scale", "rot", "opacity"):
+        """The C struct of the set, after checking every array against N = mean.shape[0]:
+        the library reads 3, 3, 4 and 1 floats per Gaussian through raw pointers."""
+        n = int(self.mean.shape[0]) if self.mean.dim() >= 1 else -1
+        for f, shape in (("mean", (n, 3)), ("scale", (n, 3)), ("rot", (n, 4)), ("opacity", (n,))):
             t = getattr(self, f)
-            _cuda(t, f"GaussianSet.{f}")
+            if not isinstance(t, torch.Tensor) or tuple(t.shape) != shape:
+                got = tuple(t.shape) if isinstance(t, torch.Tensor) else type(t).__name__
+                raise ValueError(f"GaussianSet.{f} must have shape {shape}, got {got}")
             if t.dtype != torch.float32:
                 raise ValueError(f"GaussianSet.{f} must be float32")
+        for f in ("mean", "scale", "rot", "opacity"):
+            _cuda(getattr(self, f), f"GaussianSet.{f}")
         return _Gaussians(self.mean.data_ptr(), self.scale.data_ptr(), self.rot.data_ptr(),
                           self.opacity.data_ptr(), self.n)
 
@@ -432,12 +452,16 @@ def dgsm_alpha_centroid(gaussians: GaussianSet, out=None):
 def sh_transfer(probe_sh, gaussians: GaussianSet, colour_sh=None, centroid=None, n_theta=32, n_phi=64,
                 q=1.0, clip_max=4.0, eps=1e-6, gamma=1.0):
     """Per-Gaussian lighting scale [N,3], relit SH [N,16,3] and RGB [N,3] (Sec. 3.5)."""
+    N = gaussians.n
+    _shape(probe_sh, None, "probe_sh", rows=(1, 4, 9, 16), width=3)
+    _shape(colour_sh, (N, 16, 3), "colour_sh")
+    _shape(centroid, (3,), "centroid")
+    gaussians.struct()
     probe_sh = _dev(probe_sh)
     colour_sh = _dev(colour_sh)
     if centroid is None:
         centroid = dgsm_alpha_centroid(gaussians)
     centroid = _dev(centroid)
-    N = gaussians.n
     dev = gaussians.mean.device
     s = torch.empty((N, 3), dtype=torch.float32, device=dev)
     f_out = torch.empty((N, 16, 3), dtype=torch.float32, device=dev) if colour_sh is not None else None
@@ -487,15 +511,20 @@ class Plan:
         return int(lib().dgsm_plan_split_units(self._h))
 
     def run(self, dynamic: GaussianSet, translations, out=None, use_graph: bool = True):
-        """T[frames, L, n_static + n_dynamic] for one run; enqueued on the current stream."""
+        """T[frames, L, n_static + n_dynamic] for one run; enqueued on the current stream.
+        Without ``out`` the result is the plan's own buffer, overwritten by the next run."""
         translations = _dev(translations)
         if tuple(translations.shape) != (self.frames, 3):
             raise ValueError(f"translations must be [{self.frames}, 3], got shape {tuple(translations.shape)}")
         if dynamic.n != self.n_dynamic:
             raise ValueError(f"the plan was made for {self.n_dynamic} dynamic Gaussians, got {dynamic.n}")
         if out is None:
-            out = torch.empty((self.frames, self.L, self.n_points), dtype=torch.float32,
-                              device=translations.device)
+            # one plan-owned output, so that the captured graph's key stays the same
+            # from run to run (a new pointer forces a recapture)
+            if getattr(self, "_out", None) is None:
+                self._out = torch.empty((self.frames, self.L, self.n_points), dtype=torch.float32,
+                                        device=translations.device)
+            out = self._out
         _buf(out, (self.frames, self.L, self.n_points), torch.float32, "out")
         gs = dynamic.struct()
         _check(lib().dgsm_plan_run(self._h, ctypes.byref(gs), _ptr(translations), _ptr(out), int(use_graph),

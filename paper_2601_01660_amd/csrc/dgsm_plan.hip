@@ -576,6 +576,8 @@ extern "C" dgsm_status dgsm_plan_run(dgsm_plan p, const dgsm_gaussians_t* dynami
     for (int i = 0; i < 6 && same; ++i) same = key[i] == p->cap_key[i];
     if (!same) {
         if (p->exec) {
+            // a replay of the old graph may still run on the stream
+            if (hipStreamSynchronize(s) != hipSuccess) return DGSM_EHIP;
             (void)hipGraphExecDestroy(p->exec);
             p->exec = nullptr;
         }

@@ -9,9 +9,11 @@
 //
 // Kernels (rows = samples or query points):
 //   sample_kernel   training / held-out samples from one light's atlas
-//   fwd_kernel      features + 4 MFMA layers + output; modes: train (stashes
-//                   activations for the backward), infer (T, with atlas
-//                   fallback), check (flags regions where |T - T_atlas| > thr)
+//   fwd_kernel      features + 4 MFMA layers (weights in LDS) + output;
+//                   modes: train (stashes activations for the backward) and
+//                   check (flags regions where |T - T_atlas| > thr)
+//   infer_kernel    inference at world points with the weights in registers
+//   fallback_kernel trilinear atlas value for points in flagged regions
 //   bwd_kernel      data-gradient chain through layers 3..1 (MFMA)
 //   wgrad_kernel    per-chunk weight gradients dW_l = dZ_l^T X_l (MFMA)
 //   reduce_kernel   fixed-order reduction of the partial gradients, optional

@@ -2,11 +2,11 @@
 //
 // Each workgroup stages chunks of the lat-long grid in LDS as
 // (w_x, w_y, w_z, weight) and (weight * L_r, weight * L_g, weight * L_b)
-// with L = B(w) A evaluated from the probe.  A workgroup serves 128 Gaussians
-// (two per lane, so each broadcast pair of LDS reads feeds both); its four
-// waves sweep every fourth staged direction, and the four partial sums are
-// added in wave order at the end (more waves than one Gaussian per thread
-// sweeping every direction, for latency).
+// with L = B(w) A evaluated from the probe.  A workgroup serves 64 Gaussians
+// (one per lane, the same 64 in each of its four waves); the four waves sweep
+// every fourth staged direction, and their partial sums are added in wave
+// order at the end (four times the waves of one Gaussian per thread sweeping
+// every direction, for latency).
 
 #include "dgsm_device.hpp"
 #include "dgsm_host.hpp"
