@@ -206,13 +206,14 @@ def cube_decode(face, s, t):
     return d / np.linalg.norm(d, axis=-1, keepdims=True)
 
 
-def cube_face(d32):
-    """Face of each direction: the axis of the largest |component| (the first
-    on ties) and its sign.  The choice is an integer decided by floating point,
-    so it is taken in FP32 on the FP32 offsets, as the kernel takes it."""
-    a = np.abs(np.asarray(d32, dtype=np.float32))
+def cube_face(d):
+    """Face of each direction d [..., 3] (FP64): the axis of the largest
+    |component| (the first on ties) and its sign.  Points within rounding of a
+    tie can land on the other face in a lower precision; tests leave them out."""
+    d = np.asarray(d, dtype=np.float64)
+    a = np.abs(d)
     m = np.where((a[..., 0] >= a[..., 1]) & (a[..., 0] >= a[..., 2]), 0, np.where(a[..., 1] >= a[..., 2], 1, 2))
-    comp = np.take_along_axis(np.asarray(d32, dtype=np.float32), m[..., None], axis=-1)[..., 0]
+    comp = np.take_along_axis(d, m[..., None], axis=-1)[..., 0]
     return 2 * m + (comp < 0)
 
 
@@ -387,13 +388,10 @@ def cube_cells(light, points, H, W, K, spacing="geometric", r0=0.05, r1=8.0):
     """Cube-map lookup cells: floor texel (i0, j0) with i0 + 1, j0 + 1 inside the
     same face, lower shell k0 and the fractions (fi, fj, fk)."""
     F = H // 2
-    pts = np.asarray(points, dtype=np.float32).reshape(-1, 3)
-    lt = np.asarray(light, dtype=np.float32)
-    diff = pts.astype(np.float64) - lt.astype(np.float64)
+    diff = np.asarray(points, dtype=np.float64).reshape(-1, 3) - np.asarray(light, dtype=np.float64)
     r = np.linalg.norm(diff, axis=-1)
     diff = np.where(r[:, None] > 0, diff, np.array([0.0, 0.0, 1.0]))
-    d32 = np.where(r[:, None] > 0, pts - lt, np.array([0, 0, 1], np.float32))
-    face = cube_face(d32)
+    face = cube_face(diff)
     s, t = cube_encode(diff, face)
 
     def axis(c):

@@ -64,10 +64,27 @@ def test_cube_query_matches_oracle_on_a_random_table(scene):
     torch.cuda.synchronize()
     got = got.cpu().numpy().astype(np.float64)
     for l in range(2):
-        ref = od.query(table[l].astype(np.float64), lights[l], pts, param="cubemap")
-        err = np.abs(got[l] - ref).max()
-        print(f"[cube] query light {l}: {pts.shape[0]} points, max|dT| {err:.3e}")
-        assert err <= 2e-5
+        tab = table[l].astype(np.float64)
+        diff = pts.astype(np.float64) - lights[l].astype(np.float64)
+        a = np.abs(diff)
+        amax = a.max(axis=1)
+        tied = (a >= amax[:, None] * (1 - 1e-6)) & (amax[:, None] > 0)
+        tie = tied.sum(axis=1) > 1
+        # unique face: the oracle's value
+        ref = od.query(tab, lights[l], pts[~tie], param="cubemap")
+        err = np.abs(got[l][~tie] - ref).max()
+        # within rounding of a cube edge or corner either face is a valid lookup:
+        # the kernel's value must be the oracle's lookup on one of the tied faces
+        best = np.full(tie.sum(), np.inf)
+        for ax in range(3):
+            nudged = diff[tie].copy()
+            nudged[:, ax] *= 1 + 1e-7
+            cand = od.query(tab, lights[l], lights[l].astype(np.float64) + nudged, param="cubemap")
+            ok = tied[tie][:, ax]
+            best = np.where(ok, np.minimum(best, np.abs(got[l][tie] - cand)), best)
+        print(f"[cube] query light {l}: {(~tie).sum()} points on one face, max|dT| {err:.3e}; "
+              f"{tie.sum()} on an edge or corner, max|dT| to the nearest tied face {best.max():.3e}")
+        assert (l > 0 or tie.sum() >= 300) and err <= 2e-5 and best.max(initial=0.0) <= 2e-5
 
 
 def test_cube_region_of_interest(scene):

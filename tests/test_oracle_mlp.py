@@ -94,3 +94,35 @@ def test_point_encoding_matches_octahedral_map():
     inside = (r > 0.05) & (r < 8.0)
     k = od.query_coords(light, pts, 8, 8, 33)[2]       # fractional shell of 33 geometric shells
     assert np.allclose(rho[inside], 2 * k[inside] / 32 - 1, atol=1e-12)
+
+
+def test_adam_constant_gradient_steps_are_lr_sign_at_every_t():
+    """With a constant gradient g the moments are m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so the bias-corrected step is lr sign(g) at every t
+    (eps = 0); a wrong power in a bias correction moves steps 2 and 3."""
+    rng = np.random.default_rng(11)
+    p = rng.normal(size=64)
+    g = rng.normal(size=64)
+    m = np.zeros(64)
+    v = np.zeros(64)
+    p0 = p.copy()
+    for t in (1, 2, 3):
+        p, m, v = om.adam(p, g, m, v, t, lr=1e-2, eps=0.0)
+        assert np.allclose(p, p0 - t * 1e-2 * np.sign(g), rtol=0, atol=1e-14)
+        assert np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-13, atol=0)
+        assert np.allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-12, atol=0)
+
+
+def test_adam_second_step_closed_form_with_changing_gradient():
+    """Two steps with gradients g1 then g2: m_hat = (b1 g1 + g2)/(1 + b1),
+    v_hat = (b2 g1^2 + g2^2)/(1 + b2), and the second update is
+    lr m_hat / (sqrt(v_hat) + eps)."""
+    rng = np.random.default_rng(12)
+    p0 = rng.normal(size=40)
+    g1, g2 = rng.normal(size=40), rng.normal(size=40)
+    b1, b2, lr, eps = 0.8, 0.95, 3e-3, 1e-7
+    p1, m, v = om.adam(p0, g1, np.zeros(40), np.zeros(40), 1, lr=lr, beta1=b1, beta2=b2, eps=eps)
+    p2, m, v = om.adam(p1, g2, m, v, 2, lr=lr, beta1=b1, beta2=b2, eps=eps)
+    mh = (b1 * g1 + g2) / (1 + b1)
+    vh = (b2 * g1 * g1 + g2 * g2) / (1 + b2)
+    assert np.allclose(p2, p1 - lr * mh / (np.sqrt(vh) + eps), rtol=0, atol=1e-15)

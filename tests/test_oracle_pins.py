@@ -670,3 +670,134 @@ def test_cube_roi_queries_at_receivers_equal_full_queries():
     Troi = od.build_roi(light, g, 2 * F, 3 * F, K, rec, param="cubemap")
     assert np.array_equal(od.query(Troi, light, rec, param="cubemap"), od.query(T, light, rec, param="cubemap"))
     assert np.any(Troi == 1.0) and np.any(Troi < 1.0)
+
+
+# ---------------------------------------------------------------------------
+# Uniform radial bins (Sec. 3.2 "Directional parameterization": K uniform bins
+# of [0, t_max] sampled at their centres t_k = (k + 1/2) t_max / K)
+# ---------------------------------------------------------------------------
+
+def test_uniform_build_samples_the_bin_centres():
+    """Shell k of a uniform atlas holds the exact transmittance at the centre of
+    radial bin k; a table sampled at the bin edges k t_max / K (the plausible
+    slip) differs wherever T varies along the ray."""
+    g = tiny_scene(31, n=30, lo=-2.2, hi=2.2, median=0.25)
+    light = np.array([0.05, -0.03, 0.02])
+    H, W, K, r1 = 8, 12, 7, 5.0
+    T = od.build(light, g, H, W, K, spacing="uniform", r1=r1)
+    d = od.texel_directions(H, W).reshape(-1, 3)
+    varied = 0
+    for k in range(K):
+        centre = light + ((k + 0.5) * r1 / K) * d
+        edge = light + (k * r1 / K + 1e-3) * d
+        exact_c = od.transmittance_at(light, g, centre)
+        assert np.allclose(T[k].reshape(-1), exact_c, rtol=1e-12, atol=1e-14)
+        varied += np.abs(od.transmittance_at(light, g, edge) - exact_c).max() > 1e-3
+    assert varied >= K - 1
+
+
+def test_uniform_query_reads_bin_centres_and_interpolates_linearly_between_them():
+    K, H, W, r1 = 6, 8, 8, 4.0
+    table = _random_table(K, H, W, seed=41)
+    light = np.array([0.2, 0.1, -0.3])
+    d = od.texel_directions(H, W).reshape(-1, 3)
+    for k in range(K):
+        got = od.query(table, light, light + ((k + 0.5) * r1 / K) * d, spacing="uniform", r1=r1)
+        assert np.allclose(got, table[k].reshape(-1), atol=1e-12)
+    for k in range(K - 1):        # bin edge between two centres: the mean of the two shells
+        got = od.query(table, light, light + ((k + 1) * r1 / K) * d, spacing="uniform", r1=r1)
+        assert np.allclose(got, 0.5 * (table[k] + table[k + 1]).reshape(-1), atol=1e-12)
+    # inside the first half bin and beyond the last centre: clamped to the end shells
+    assert np.allclose(od.query(table, light, light + 0.2 * r1 / K * d, spacing="uniform", r1=r1),
+                       table[0].reshape(-1), atol=1e-12)
+    assert np.allclose(od.query(table, light, light + 1.3 * r1 * d, spacing="uniform", r1=r1),
+                       table[K - 1].reshape(-1), atol=1e-12)
+
+
+def test_geometric_query_is_linear_in_log_radius():
+    """Between two geometric shells the lookup is linear in the fractional shell
+    index, i.e. in log r: the geometric mean of two radii gives the mean value."""
+    K, H, W = 5, 8, 8
+    table = _random_table(K, H, W, seed=42)
+    light = np.zeros(3)
+    d = od.texel_directions(H, W).reshape(-1, 3)
+    r = 0.05 * 160.0 ** (np.arange(K) / (K - 1))      # 0.05 .. 8 m
+    for k in range(K - 1):
+        got = od.query(table, light, math.sqrt(r[k] * r[k + 1]) * d)
+        assert np.allclose(got, 0.5 * (table[k] + table[k + 1]).reshape(-1), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# The sampled-texel and point paths the full-size GPU checks use, against the
+# full table on a small atlas that includes the folded (lower-hemisphere) texels
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("spacing", ["geometric", "uniform"])
+@pytest.mark.parametrize("param,H,W", [("octahedral", 8, 12), ("octahedral", 10, 6), ("cubemap", 8, 12)])
+def test_build_texels_equals_the_full_table(spacing, param, H, W):
+    g = tiny_scene(43, n=40, lo=-2.0, hi=2.0, median=0.25)       # occluders in every direction
+    light = np.array([0.1, 0.05, -0.07])
+    K = 6
+    T = od.build(light, g, H, W, K, spacing=spacing, r1=6.0, param=param)
+    rows, cols = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    rows, cols = rows.ravel(), cols.ravel()
+    got = od.build_texels(light, g, rows, cols, K, spacing=spacing, r1=6.0, H=H, W=W, param=param)
+    assert got.shape == (H * W, K)
+    assert np.allclose(got, T[:, rows, cols].T, rtol=1e-12, atol=1e-15)
+    if param == "octahedral":
+        u, v = od.texel_uv(H, W)
+        assert (np.abs(u) + np.abs(v) > 1).sum() > 0.3 * H * W          # folded texels are covered
+        assert T.min() < 0.5 and (T < 0.999).mean() > 0.2                # and the table is not flat
+
+
+@pytest.mark.parametrize("spacing", ["geometric", "uniform"])
+@pytest.mark.parametrize("param,H,W", [("octahedral", 8, 12), ("cubemap", 8, 12)])
+def test_query_exact_equals_query_of_the_full_table(spacing, param, H, W):
+    g = tiny_scene(44, n=40, lo=-2.0, hi=2.0, median=0.25)
+    light = np.array([-0.1, 0.05, 0.08])
+    K = 6
+    rng = np.random.default_rng(45)
+    pts = light + rng.normal(size=(400, 3)) * rng.uniform(0.05, 3.0, (400, 1))
+    # points on the octahedral seams of the lower hemisphere (x = 0 or y = 0, z < 0)
+    seam = rng.normal(size=(60, 3))
+    seam[:30, 0] = 0.0
+    seam[30:, 1] = 0.0
+    seam[:, 2] = -np.abs(seam[:, 2])
+    pts = np.concatenate([pts, light + seam])
+    T = od.build(light, g, H, W, K, spacing=spacing, r1=6.0, param=param)
+    ref = od.query(T, light, pts, spacing=spacing, r1=6.0, param=param)
+    got = od.query_exact(light, g, pts, H, W, K, spacing=spacing, r1=6.0, param=param)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-14)
+    assert ref.min() < 0.7
+
+
+# ---------------------------------------------------------------------------
+# Relighting outputs (Sec. 3.5, the relit colour) on a hand-computed case
+# ---------------------------------------------------------------------------
+
+def test_relight_hand_computed_constant_probe():
+    """A probe with only the DC coefficient A_0c = 2 sqrt(pi) L_c radiates L_c in
+    every direction (Y_00 = 1 / (2 sqrt(pi))); with eps = 0 the per-channel scale
+    is s_c = clip(L_c, 0, t_max) whatever the normal.  L = (0.8, 2.5, 5.0),
+    t_max = 4, gamma = 1.7:
+      s      = (0.8, 2.5, 4.0)
+      f'     = gamma s_c f            (every SH coefficient, no clamp)
+      rgb'   = max(0, gamma (0.5 + f_0 / (2 sqrt(pi))) s_c)
+    for f_0 = (-2, 0.3, 1):  f'_0 = (-2.72, 1.275, 6.8) and
+      rgb' = (0,  1.7 * (0.5 + 0.3 * 0.28209479177387814) * 2.5,
+                  1.7 * (0.5 + 0.28209479177387814) * 4)
+           = (0, 2.4846708595116946, 5.318244584062371)."""
+    L = np.array([0.8, 2.5, 5.0])
+    probe = np.zeros((9, 3))
+    probe[0] = 2.0 * math.sqrt(math.pi) * L
+    rng = np.random.default_rng(46)
+    g = synth.random_gaussians(rng, rng.normal(size=(4, 3)), 0.05)
+    f = np.zeros((4, 16, 3))
+    f[:, 0] = [-2.0, 0.3, 1.0]
+    f[:, 5] = [1.0, -2.0, 3.0]
+    s, f_out, rgb = osh.relight(probe, g, f, clip_max=4.0, eps=0.0, gamma=1.7)
+    assert np.allclose(s, [0.8, 2.5, 4.0], rtol=0, atol=1e-12)
+    assert np.allclose(f_out[:, 0], [-2.72, 1.275, 6.8], rtol=0, atol=1e-12)
+    assert np.allclose(f_out[:, 5], [1.7 * 0.8, -1.7 * 5.0, 1.7 * 12.0], rtol=0, atol=1e-12)
+    assert np.all(f_out[:, 1:5] == 0) and np.all(f_out[:, 6:] == 0)
+    assert np.allclose(rgb, [0.0, 2.4846708595116946, 5.318244584062371], rtol=0, atol=1e-12)
