@@ -83,7 +83,7 @@ def test_cube_query_matches_oracle_on_a_random_table(scene):
             ok = tied[tie][:, ax]
             best = np.where(ok, np.minimum(best, np.abs(got[l][tie] - cand)), best)
         print(f"[cube] query light {l}: {(~tie).sum()} points on one face, max|dT| {err:.3e}; "
-              f"{tie.sum()} on an edge or corner, max|dT| to the nearest tied face {best.max():.3e}")
+              f"{tie.sum()} on an edge or corner, max|dT| to the nearest tied face {best.max(initial=0.0):.3e}")
         assert (l > 0 or tie.sum() >= 300) and err <= 2e-5 and best.max(initial=0.0) <= 2e-5
 
 
