@@ -19,7 +19,8 @@
  *    non-zero dgsm_status means nothing was enqueued (DGSM_EHIP: a HIP launch
  *    failed; earlier kernels of the same call may have run).
  *  - Calls on distinct output and workspace buffers may run concurrently on
- *    different streams.  The library holds no global mutable state.
+ *    different streams.  The library holds no global mutable state except the
+ *    per-GPU scratch array of dgsm_build_noalloc.
  *
  * Gaussian records (Sec. 3.2, first paragraph): mean mu, covariance
  * Sigma = R diag(s^2) R^T with R from a quaternion (w, x, y, z) that the
@@ -141,6 +142,31 @@ size_t dgsm_build_workspace_size(const dgsm_atlas_desc_t* desc, int64_t n_gauss,
 dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
                        const dgsm_atlas_desc_t* desc, void* atlas, void* ws, size_t ws_bytes,
                        void* stream);
+
+/*
+ * dgsm_build_noalloc - dgsm_build for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and result as dgsm_build, but the
+ * workspace is a fixed array inside the library instead of a caller buffer:
+ * the call performs no hipMalloc, hipFree or other allocation.
+ *   - Limit: the request must fit DGSM_BUILD_SCRATCH_BYTES (64 MiB), i.e.
+ *     dgsm_build_workspace_size(desc, gaussians->n, lights->n) <= that
+ *     (for example 50k Gaussians at 128 x 128 x 32, 20k at 256 x 256 x 64, one
+ *     light); larger requests return DGSM_EWORKSPACE and enqueue nothing.
+ *   - Each GPU holds its own copy of the array from the first call on it until
+ *     the process ends; its address is looked up once per device, with that
+ *     device current, on the first call there (DGSM_EHIP if the lookup fails).
+ *   - Every call on one GPU shares that GPU's array.  Calls that overlap on one
+ *     GPU (concurrent streams, or host threads enqueuing at once with no
+ *     ordering between their streams) race on it and give undefined results;
+ *     stream-ordered calls are safe.  Nothing the previous call left in the
+ *     array is read.
+ * dgsm_build_noalloc_max_bytes returns DGSM_BUILD_SCRATCH_BYTES.
+ */
+#define DGSM_BUILD_SCRATCH_BYTES (64u * 1024u * 1024u)
+dgsm_status dgsm_build_noalloc(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
+                               const dgsm_atlas_desc_t* desc, void* atlas, void* stream);
+size_t dgsm_build_noalloc_max_bytes(void);
 
 /*
  * dgsm_build in two phases, for callers that schedule or time them apart.

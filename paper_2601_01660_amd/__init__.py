@@ -72,6 +72,9 @@ SIGNATURES = {
     "dgsm_build_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(_AtlasDesc), ctypes.c_int64, ctypes.c_int32]),
     "dgsm_build": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_Gaussians), ctypes.POINTER(_AtlasDesc),
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dgsm_build_noalloc": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_Gaussians),
+                                          ctypes.POINTER(_AtlasDesc), ctypes.c_void_p, ctypes.c_void_p]),
+    "dgsm_build_noalloc_max_bytes": (ctypes.c_size_t, []),
     "dgsm_build_roi": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_Gaussians), ctypes.POINTER(_AtlasDesc),
                                       ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(_RoiBox), ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
@@ -300,6 +303,25 @@ def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0,
     _check(lib().dgsm_build(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), _ptr(out), _ptr(workspace),
                             workspace.numel(), _stream()))
     return out
+
+
+def dgsm_build_noalloc(lights, gaussians: GaussianSet, atlas: Atlas, out, kappa: float = 1.0,
+                       beta: str = "trace"):
+    """dgsm_build into a caller-allocated ``out`` [L, K, H, W] with the library's
+    fixed scratch array as workspace (no device allocation by the library;
+    requests above ``dgsm_build_noalloc_max_bytes()`` raise)."""
+    lights = _rows(_dev(lights), 3, "lights")
+    L = int(lights.shape[0])
+    _buf(out, (L, atlas.K, atlas.H, atlas.W), atlas.torch_dtype, "out")
+    d = atlas.struct()
+    lt = _Lights(lights.data_ptr(), L, kappa, BETA_MODES[beta])
+    gs = gaussians.struct()
+    _check(lib().dgsm_build_noalloc(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), _ptr(out), _stream()))
+    return out
+
+
+def dgsm_build_noalloc_max_bytes() -> int:
+    return int(lib().dgsm_build_noalloc_max_bytes())
 
 
 def dgsm_build_roi(lights, gaussians: GaussianSet, atlas: Atlas, receivers, box=None, kappa: float = 1.0, out=None,

@@ -22,6 +22,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace dgsm {
 
 // ---------------------------------------------------------------------------
@@ -1558,6 +1560,60 @@ extern "C" dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussi
     if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+    if ((st = enqueue_bin(g, L, w, *lights, desc->cull_eps, *gaussians, s)) != DGSM_OK) return st;
+    AccumOpts o{nullptr, false, nullptr, kDefaultTileWaves, kDefaultSplitUnits};
+    return enqueue_accumulate(g, L, w, lights->n, desc->cull_eps, atlas, o, s);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free build: the workspace is a fixed device array of the library
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)DGSM_BUILD_SCRATCH_BYTES;
+constexpr int kScratchDevices = 64;
+
+// One copy per GPU the library runs on, held until the process ends.  In host
+// code this name is only a stand-in for the symbol: the device address of each
+// GPU's copy comes from hipGetSymbolAddress and is what kernels receive.
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of the current device's scratch copy, looked up once per
+// device with that device current; nullptr if the lookup fails.
+unsigned char* scratch_address() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = reinterpret_cast<unsigned char*>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" size_t dgsm_build_noalloc_max_bytes(void) { return kScratchBytes; }
+
+extern "C" dgsm_status dgsm_build_noalloc(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
+                                          const dgsm_atlas_desc_t* desc, void* atlas, void* stream) {
+    dgsm_status st = check_build_args(lights, gaussians, desc);
+    if (st != DGSM_OK) return st;
+    if (!atlas) return DGSM_EINVAL;
+    const Geom g = make_geom(*desc);
+    const BuildLayout L = build_layout(g, gaussians->n, lights->n);
+    if (L.total > kScratchBytes) return DGSM_EWORKSPACE;
+    unsigned char* w = scratch_address();
+    if (!w) return DGSM_EHIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // The same kernels as dgsm_build on the scratch copy: the binning writes
+    // every workspace word the accumulation reads, so what an earlier call left
+    // there is never read.
     if ((st = enqueue_bin(g, L, w, *lights, desc->cull_eps, *gaussians, s)) != DGSM_OK) return st;
     AccumOpts o{nullptr, false, nullptr, kDefaultTileWaves, kDefaultSplitUnits};
     return enqueue_accumulate(g, L, w, lights->n, desc->cull_eps, atlas, o, s);

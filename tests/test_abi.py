@@ -137,6 +137,22 @@ def test_null_pointers_and_small_workspace_are_rejected(lib):
 
 
 @fake_pointers
+def test_noalloc_build_validates_and_refuses_oversized_requests_first(lib):
+    import paper_2601_01660_amd as P
+    assert lib.dgsm_build_noalloc_max_bytes() == 64 * 1024 * 1024
+    d = _desc().struct()
+    lt = P._Lights(1, 1, 1.0)
+    gs = P._Gaussians(0, 0, 0, 0, 5)          # n > 0 with null arrays
+    assert lib.dgsm_build_noalloc(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), 1, None) == 1
+    gs = P._Gaussians(1, 1, 1, 1, 5)
+    assert lib.dgsm_build_noalloc(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), None, None) == 1
+    big = _desc(H=512, W=512, K=64).struct()
+    gs = P._Gaussians(1, 1, 1, 1, 2_000_000)
+    assert lib.dgsm_build_workspace_size(ctypes.byref(big), 2_000_000, 1) > lib.dgsm_build_noalloc_max_bytes()
+    assert lib.dgsm_build_noalloc(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(big), 1, None) == 2
+
+
+@fake_pointers
 def test_check_and_work_unit_queries_validate_first(lib):
     import paper_2601_01660_amd as P
     n_bad = ctypes.c_longlong(-1)
