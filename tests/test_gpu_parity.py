@@ -69,6 +69,52 @@ def test_cfg1_query_matches_oracle(cfg1):
     assert np.abs(got - own).max() <= 2e-5
 
 
+@pytest.mark.parametrize("spacing", ["geometric", "uniform"])
+def test_octahedral_query_edge_cases_on_a_random_table(spacing):
+    """Random table (an input, not a build) on a non-square atlas: points on the
+    fold seams (x = 0 or y = 0 below the light), straight below it (the corner
+    of the map), on the horizon plane z = 0 (the inner diamond), on the inner
+    coordinate planes, beside the outer edges (wrapped neighbours), at the
+    light (r = 0), inside r0 and beyond r1; FP32 lookup against the FP64 oracle."""
+    U = _util()
+    import paper_2601_01660_amd as P
+    H, W, K = 24, 40, 12
+    r0, r1 = 0.05, 8.0
+    rng = np.random.default_rng(17)
+    light = np.array([[0.25, -0.5, 1.0]], np.float32)          # exact in FP32
+    table = rng.uniform(0, 1, (1, K, H, W)).astype(np.float32)
+    n = 400
+    rad = rng.uniform(0.02, 12.0, (n, 1))
+    a, b = rng.uniform(-1, 1, (n, 1)), rng.uniform(-1, 1, (n, 1))
+    down = -np.abs(rng.uniform(0.05, 1, (n, 1)))
+    offs = {
+        "random": rng.normal(size=(n, 3)) * rad,
+        "seam x=0, z<0": np.hstack([0 * a, a, down]) * rad,
+        "seam y=0, z<0": np.hstack([a, 0 * a, down]) * rad,
+        "straight below": np.hstack([0 * a, 0 * a, down]) * rad,
+        "horizon z=0": np.hstack([a, b, 0 * a]) * rad,
+        "plane x=0, z>0": np.hstack([0 * a, a, -down]) * rad,
+        "plane y=0, z>0": np.hstack([a, 0 * a, -down]) * rad,
+        "near outer edge": np.hstack([np.sign(a) * (1 - 1e-3 * np.abs(b)), 1e-3 * b, -np.ones_like(a)]) * rad,
+        "at the light": np.zeros((4, 3)),
+        "inside r0": rng.normal(size=(n, 3)) * 0.01,
+        "beyond r1": rng.normal(size=(n, 3)) * 40.0,
+    }
+    atlas = P.Atlas(H, W, K, spacing=spacing, r0=r0, r1=r1)
+    Tt = torch.from_numpy(table).cuda()
+    worst = 0.0
+    for name, o in offs.items():
+        pts = (light[0] + o.astype(np.float32)).astype(np.float32)
+        got = U.gpu_query(light, atlas, Tt, pts)[0]
+        ref = od.query(table[0].astype(np.float64), light[0].astype(np.float64), pts.astype(np.float64),
+                       spacing, r0, r1)
+        err = np.abs(got - ref).max()
+        worst = max(worst, err)
+        print(f"[parity] octahedral query {spacing} {name}: max|dT| = {err:.2e}", flush=True)
+        assert err <= 2e-5, name
+    _report(f"octahedral query edge cases, {spacing}", worst)
+
+
 def test_cfg1_denser_ragged_two_lights():
     """The 5k scene at 36 x 36 (ragged 8x8 tiles) x 24 shells, two lights, one inside the cloud."""
     U = _util()
@@ -278,6 +324,12 @@ def test_cfg2_full_size_sampled():
     err = np.abs(q - qref).max()
     _report("cfg2 sampled queries", err)
     assert err <= TOL
+    # the query kernel at every Gaussian centre: FP64 trilinear of the GPU's own table
+    qall = U.gpu_query(c["lights"], atlas, T, g.mean)[0]
+    own = od.query(T[0].cpu().numpy().astype(np.float64), light, g.mean, spec.spacing, spec.r0, spec.r1)
+    err = np.abs(qall - own).max()
+    _report(f"cfg2 query of all {g.n} centres vs FP64 trilinear of the GPU table", err)
+    assert err <= 2e-5
 
 
 @pytest.mark.parametrize("dtype,tol", [("f32", TOL), ("f16", 1e-2)])
@@ -296,6 +348,13 @@ def test_cfg3_frame0_full_size_sampled(dtype, tol):
         err = np.abs(host[l][:, i, j].T - ref).max()
         _report(f"cfg3 {dtype} light {l} sampled texels", err)
         assert err <= tol
+    # the query kernel at all 2.15M centres and 4 lights: FP64 trilinear of the GPU's own table
+    qall = U.gpu_query(c["lights"], atlas, T, g.mean)
+    for l in range(4):
+        own = od.query(host[l].astype(np.float64), c["lights"][l], g.mean, spec.spacing, spec.r0, spec.r1)
+        err = np.abs(qall[l] - own).max()
+        _report(f"cfg3 {dtype} light {l} query of all {g.n} centres vs FP64 trilinear of the GPU table", err)
+        assert err <= 2e-5
 
 
 # ---------------------------------------------------------------------------
@@ -444,3 +503,35 @@ def test_probe_fit_matches_oracle(Kp, lam, cube):
     err = np.abs(A.cpu().numpy() - ref).max() / np.abs(ref).max()
     _report(f"probe fit Kp={Kp} lam={lam} cube={cube} (relative)", err)
     assert err <= 1e-4
+
+
+def test_workspace_sized_for_the_set():
+    """A workspace holding exactly the list entries a set needs (counted by
+    dgsm_count_entries) gives the atlas of the worst-case workspace bit for bit;
+    one too small for the set is refused by nothing but leaves every list empty
+    (T = 1, no write past its end) and says so through dgsm_list_entries."""
+    import paper_2601_01660_amd as P
+    c = synth.cfg1(3000)
+    g, lights = c["gaussians"], torch.from_numpy(np.array([[0.0, 0.0, 0.0], [1.0, 2.0, 0.5]], np.float32)).cuda()
+    atlas = P.Atlas(96, 80, 12)
+    gs = P.GaussianSet.from_host(g)
+    entries = P.dgsm_count_entries(lights, gs, atlas)
+    worst = P.dgsm_build_workspace_size(atlas, g.n, 2)
+    exact = P.dgsm_build_workspace_size_entries(atlas, g.n, 2, entries)
+    assert 0 < exact < worst
+    ws = torch.empty(exact, dtype=torch.uint8, device="cuda")
+    T_exact = P.dgsm_build(lights, gs, atlas, workspace=ws)
+    T_worst = P.dgsm_build(lights, gs, atlas)
+    torch.cuda.synchronize()
+    assert torch.equal(T_exact, T_worst)
+    for l in range(2):
+        need, cap = P.dgsm_list_entries(atlas, g.n, 2, ws, l)
+        assert need <= cap and cap >= entries
+    small = torch.empty(P.dgsm_build_workspace_size_entries(atlas, g.n, 2, 0), dtype=torch.uint8, device="cuda")
+    T_small = P.dgsm_build(lights, gs, atlas, workspace=small)
+    torch.cuda.synchronize()
+    need, cap = P.dgsm_list_entries(atlas, g.n, 2, small, 0)
+    print(f"[parity] workspace for the set: {entries} entries, {exact} vs {worst} bytes; too small: need {need} "
+          f"> capacity {cap}", flush=True)
+    assert need > cap and need == P.dgsm_list_entries(atlas, g.n, 2, ws, 0)[0]
+    assert torch.all(T_small == 1.0)
