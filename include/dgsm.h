@@ -144,6 +144,41 @@ dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaus
                        void* stream);
 
 /*
+ * Workspaces sized for a particular Gaussian set.  dgsm_build_workspace_size
+ * covers the worst case, in which every Gaussian reaches every supertile of
+ * the atlas (n S list entries per light, S = number of 64 x 64-texel
+ * supertiles, up to 256): about 12 n S bytes per light, 98 GB for 4 M
+ * Gaussians and 8 lights at 1024 x 1024.  Real sets need far fewer entries
+ * (each Gaussian's light-space footprint covers a few supertiles), so every
+ * call that takes a build workspace (dgsm_build, dgsm_bin, dgsm_accumulate,
+ * dgsm_build_roi, dgsm_work_units, dgsm_list_entries) derives the list
+ * capacity from ws_bytes: the worst case if ws_bytes holds it, otherwise the
+ * largest capacity that fits (DGSM_EWORKSPACE if not even 64 S entries do).
+ *
+ * dgsm_build_workspace_size_entries - bytes of a workspace whose lists hold
+ *   `entries` entries per light (rounded up to a multiple of 64, at least 64 S,
+ *   at most the worst case); 0 if the arguments are invalid.
+ * dgsm_count_entries - bins `gaussians` (Sec. 3.2 "Occluder culling") on ws
+ *   and returns in *entries (host) the list entries the set needs, the maximum
+ *   over lights: a workspace of dgsm_build_workspace_size_entries(desc, n, L,
+ *   *entries) bytes then holds this set.  Any workspace of at least
+ *   dgsm_build_workspace_size_entries(desc, n, L, 0) bytes will do.
+ *   Synchronises `stream`.
+ * dgsm_list_entries - out[0] = entries the last binning on ws needed for light
+ *   `light`, out[1] = the capacity of ws.  When out[0] > out[1] that binning
+ *   did not fit: the library then empties every list of the light (nothing is
+ *   written past the workspace) and the atlas it builds is wrong.  Copies from
+ *   the device and synchronises `stream`.
+ */
+size_t dgsm_build_workspace_size_entries(const dgsm_atlas_desc_t* desc, int64_t n_gauss, int32_t n_lights,
+                                         int64_t entries);
+dgsm_status dgsm_count_entries(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
+                               const dgsm_atlas_desc_t* desc, void* ws, size_t ws_bytes, int64_t* entries,
+                               void* stream);
+dgsm_status dgsm_list_entries(const dgsm_atlas_desc_t* desc, int64_t n_gauss, int32_t n_lights, const void* ws,
+                              size_t ws_bytes, int32_t light, int64_t out[2], void* stream);
+
+/*
  * dgsm_build_noalloc - dgsm_build for callers that cannot allocate device
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid hipMalloc).  Same arguments, kernels and result as dgsm_build, but the
@@ -205,6 +240,30 @@ dgsm_status dgsm_bin(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussi
                      const dgsm_atlas_desc_t* desc, void* ws, size_t ws_bytes, void* stream);
 dgsm_status dgsm_accumulate(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc, int64_t n_gauss,
                             void* atlas, void* ws, size_t ws_bytes, unsigned long long* stats, void* stream);
+/*
+ * dgsm_accumulate_ex - dgsm_accumulate with the knobs of the tile accumulation
+ * (the batched plan's autotuner chooses among them; the result is bitwise the
+ * same for every choice):
+ *   tile_waves   waves sharing one 8 x 8 tile's accumulators: 2, 4 or 8
+ *   split_units  target work units per launch (0: default 32768; < 0: never
+ *                cut a tile into slices)
+ *   packed       0: every binned (tile, Gaussian) pair is evaluated at all 64
+ *                texels of the tile at once; 1: packed walk -- each pair only
+ *                runs the distance pre-test over the tile's texels, and the
+ *                (texel, Gaussian) pairs that pass are evaluated 64 at a time,
+ *                one per lane (faster for sets whose Gaussians cover few texels
+ *                of a tile, such as an avatar seen from a light).  stats must be
+ *                NULL with packed = 1.
+ * dgsm_accumulate(...) equals dgsm_accumulate_ex with {8, 0, 0}.
+ */
+typedef struct {
+    int32_t tile_waves;
+    int32_t split_units;
+    int32_t packed;
+} dgsm_accum_opts_t;
+dgsm_status dgsm_accumulate_ex(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc, int64_t n_gauss,
+                               void* atlas, void* ws, size_t ws_bytes, const dgsm_accum_opts_t* opts,
+                               unsigned long long* stats, void* stream);
 dgsm_status dgsm_work_units(const dgsm_atlas_desc_t* desc, int64_t n_gauss, int32_t n_lights, const void* ws,
                             size_t ws_bytes, int32_t light, int32_t out[4], void* stream);
 
@@ -311,9 +370,18 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  *
  * A plan serves a scene made of a STATIC Gaussian set (copied into the plan at
  * creation; the caller's arrays may be freed afterwards) and a DYNAMIC set of
- * n_dynamic Gaussians that moves rigidly: in frame f its means are
- * base_mean + translations[f] (one FP32 addition per coordinate), its scales,
- * rotations and opacities fixed.  One dgsm_plan_run evaluates every frame:
+ * n_dynamic Gaussians (avatars, re-posed every frame) that moves in one of two
+ * ways (opts->motion):
+ *   DGSM_MOTION_RIGID  the dynamic set is cut into opts->groups consecutive
+ *       groups (one per avatar; group g holds Gaussians [group_start[g],
+ *       group_start[g+1])), each translated rigidly: in frame f the means of
+ *       group g are base_mean + translations[f][g] (one FP32 addition per
+ *       coordinate), scales, rotations and opacities fixed;
+ *   DGSM_MOTION_FREE   every frame brings its own dynamic Gaussians: the
+ *       dynamic_set arrays of dgsm_plan_run hold F frames (mean [F][n][3],
+ *       scale [F][n][3], rot [F][n][4], opacity [F][n], n = n_dynamic) and
+ *       translations is ignored (a skinned avatar).
+ * One dgsm_plan_run evaluates every frame:
  * the atlas of every light from all static + dynamic Gaussians (exactly what
  * dgsm_build computes on the union) and a dgsm_query of every light at all
  * Gaussian centres (static first, then dynamic) into T_out[f][light][point].
@@ -323,18 +391,33 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  *   static_cache  1: the static optical depth is built once per run and each
  *                 frame adds only the dynamic Gaussians to it (tau is a sum over
  *                 Gaussians, Eq. 2); 0: every frame rebuilds from all Gaussians
- *   autotune      1: the first run times the two knobs of the tile
- *                 accumulation on frame 0 of the real workload and keeps the
- *                 fastest pair: waves per tile (2, 4, 8) and work units per
- *                 launch (never, 8192, 32768, 131072); in cache mode they apply
- *                 to the per-frame dynamic accumulation, the once-per-run
- *                 static build keeps the defaults (8 waves, 32768 units)
+ *   autotune      1: the first run times the knobs of the tile accumulation
+ *                 on frame 0 of the real workload and keeps the fastest
+ *                 combination: waves per tile (2, 4, 8), work units per launch
+ *                 (never, 8192, 32768, 131072) and, in cache mode, the packed
+ *                 walk (see dgsm_accumulate_ex) on or off; in cache mode they
+ *                 apply to the per-frame dynamic accumulation, the once-per-run
+ *                 static build keeps the defaults (8 waves, 32768 units,
+ *                 unpacked)
  *   tile_waves    waves sharing one 8x8 tile when autotune = 0 (2, 4 or 8; else 8)
  *   split_units   target number of work units per accumulation when
  *                 autotune = 0: a tile with more hits than (total hits /
  *                 split_units) is cut into slices run by separate blocks
  *                 (results are bitwise the same); 0 = default (32768),
  *                 negative = never split
+ *   packed        packed walk for the dynamic accumulation when autotune = 0
+ *                 (cache mode only)
+ *   chains        frame chains in cache mode (see below): 0 = min(F, 3),
+ *                 else 1..3 (fewer chains, less memory)
+ *   motion        dgsm_motion (DGSM_MOTION_RIGID = 0, DGSM_MOTION_FREE = 1)
+ *   groups        rigid groups (0 or 1: the whole dynamic set is one group)
+ *   group_start   host [groups + 1], ascending from 0 to n_dynamic (read at
+ *                 creation only); NULL when groups <= 1
+ *
+ * Memory: the static set's supertile lists are counted once at creation (a
+ * binning of the static set, synchronous) and its workspace holds exactly
+ * those entries; the dynamic set's workspaces hold its worst case (n_dynamic
+ * times the supertile count per light), since it moves.
  *
  * dgsm_plan_create allocates all device memory the plan needs (the only
  * allocating entry points are create and destroy) and synchronises the device;
@@ -349,17 +432,24 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  * others on streams the plan owns, forked from `stream` after the static
  * build and joined back into it before the run ends, so work enqueued on
  * `stream` afterwards sees every frame.
- *   dynamic_set : device arrays of the dynamic set at its base pose (n = n_dynamic)
- *   translations: device [F][3]
+ *   dynamic_set : rigid: device arrays of the dynamic set at its base pose
+ *                 (n = n_dynamic); free: device arrays of all F frames (above)
+ *   translations: rigid: device [F][groups][3]; free: ignored (may be NULL)
  *   T_out       : device [F][lights.n][n_static + n_dynamic] float32
  */
 typedef struct dgsm_plan_s* dgsm_plan;
+typedef enum { DGSM_MOTION_RIGID = 0, DGSM_MOTION_FREE = 1 } dgsm_motion;
 typedef struct {
     int32_t frames;
     int32_t static_cache;
     int32_t autotune;
     int32_t tile_waves;
     int32_t split_units;
+    int32_t chains;
+    int32_t motion;
+    int32_t groups;
+    const int64_t* group_start;
+    int32_t packed;
 } dgsm_plan_opts_t;
 
 dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc,
@@ -367,10 +457,11 @@ dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_atlas_desc_
                              const dgsm_plan_opts_t* opts, dgsm_plan* out);
 dgsm_status dgsm_plan_run(dgsm_plan plan, const dgsm_gaussians_t* dynamic_set, const float* translations,
                           float* T_out, int32_t use_graph, void* stream);
-/* The knobs in use (after autotuning, if enabled): waves per tile, and work
- * units per accumulation (-1: never split). */
+/* The knobs in use (after autotuning, if enabled): waves per tile, work
+ * units per accumulation (-1: never split), packed walk (1) or not (0). */
 int32_t dgsm_plan_tile_waves(const dgsm_plan plan);
 int32_t dgsm_plan_split_units(const dgsm_plan plan);
+int32_t dgsm_plan_packed(const dgsm_plan plan);
 dgsm_status dgsm_plan_destroy(dgsm_plan plan);
 
 /*
@@ -382,7 +473,9 @@ dgsm_status dgsm_plan_destroy(dgsm_plan plan);
  * (geometric: 2 ln(r/r0)/ln(r1/r0) - 1; uniform: 2 r/r1 - 1; clamped).
  * phi[128] = u, v, rho, then for i = 0..15 and f_i = pi (W/4)^(i/15) (W the
  * atlas width): sin(f_i u), cos(f_i u), sin(f_i v), cos(f_i v), sin(f_i rho),
- * cos(f_i rho); zeros from index 99.  Matrix products run on BF16 MFMA with
+ * cos(f_i rho); zeros from index 99.  The sines take the phase f_i x / (2 pi)
+ * formed in FP64 and reduced to [-1/2, 1/2] turns; training, gradients and checks
+ * evaluate them in FP64, inference in FP32.  Matrix products run on BF16 MFMA with
  * FP32 accumulation: weights, features, hidden activations and back-propagated
  * pre-activation gradients are rounded to BF16 (nearest even) where they enter
  * the matrix units; biases, the output layer and all accumulations are FP32.
@@ -432,6 +525,22 @@ dgsm_status dgsm_mlp_check(const float* params, const dgsm_atlas_desc_t* desc, c
                            int64_t n_check, uint32_t seed, float thresh, unsigned char* mask, unsigned int* stats,
                            void* ws, size_t ws_bytes, void* stream);
 
+/* Exhaustive check of one light's network over its atlas, for a fallback mask
+ * that does not depend on a random held-out draw: the network is compared with
+ * the table at every texel centre and shell radius (H W K samples, exact table
+ * values) and at n_per_region points drawn uniformly (stream `seed`) inside
+ * each fallback region's domain -- the continuous texel and shell coordinates
+ * whose trilinear cell lies in the region -- against the trilinear atlas value.
+ * A node that misses by more than thresh flags the regions of all (up to 8)
+ * cells it is a corner of; a random point flags the region of its own cell.
+ * mask and stats as dgsm_mlp_check (zero them first).  The samples are staged
+ * in passes of at most 4M rows; ws >= dgsm_mlp_check_grid_workspace_size(desc,
+ * n_per_region) bytes (0 if desc is invalid or n_per_region < 0). */
+size_t dgsm_mlp_check_grid_workspace_size(const dgsm_atlas_desc_t* desc, int32_t n_per_region);
+dgsm_status dgsm_mlp_check_grid(const float* params, const dgsm_atlas_desc_t* desc, const void* atlas_l,
+                                int32_t n_per_region, uint32_t seed, float thresh, unsigned char* mask,
+                                unsigned int* stats, void* ws, size_t ws_bytes, void* stream);
+
 /* T[l][p] of each light's network at world points [P][3] (params [L][DGSM_MLP_PARAMS]).
  * With mask (layout of dgsm_mlp_check, [L][regions]) and atlas ([L][K][H][W]),
  * points whose floor texel lies in a flagged region take the trilinear atlas
@@ -439,6 +548,26 @@ dgsm_status dgsm_mlp_check(const float* params, const dgsm_atlas_desc_t* desc, c
 dgsm_status dgsm_mlp_infer(const float* params, const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc,
                            const void* atlas, const unsigned char* mask, const float* points, int64_t P, float* T,
                            void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Checkpoint of one light's learned field (HOST memory, no device work): the
+ * parameters [DGSM_MLP_PARAMS], optionally the Adam moments [2][DGSM_MLP_PARAMS]
+ * and the Adam step count (the step0 to resume dgsm_mlp_train with), and the
+ * atlas geometry the network was trained for (H, W, K, spacing, r0, r1; the
+ * Fourier frequencies follow W).  File: the line "DGSM-MLP 1", a line with a
+ * JSON object {"params", "adam", "step", "H", "W", "K", "spacing", "r0", "r1"},
+ * then the float32 values, little endian (parameters, then the moments).
+ *   dgsm_mlp_save: adam_mv may be NULL (no moments written).  DGSM_EINVAL if
+ *     the file cannot be written.
+ *   dgsm_mlp_load: params required; adam_mv NULL skips the moments (DGSM_EINVAL
+ *     if asked for moments the file lacks); step and desc may be NULL (desc gets
+ *     the stored geometry, octahedral, FP32, cull_eps 0).  DGSM_EINVAL on a
+ *     missing or malformed file or a different parameter count.
+ */
+dgsm_status dgsm_mlp_save(const char* path, const float* params, const float* adam_mv, int32_t step,
+                          const dgsm_atlas_desc_t* desc);
+dgsm_status dgsm_mlp_load(const char* path, float* params, float* adam_mv, int32_t* step,
+                          dgsm_atlas_desc_t* desc);
 
 /*
  * dgsm_probe_fit - SH coefficients of an approximate environment probe by

@@ -61,7 +61,16 @@ class _RoiBox(ctypes.Structure):
 
 class _PlanOpts(ctypes.Structure):
     _fields_ = [("frames", ctypes.c_int32), ("static_cache", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("tile_waves", ctypes.c_int32), ("split_units", ctypes.c_int32)]
+                ("tile_waves", ctypes.c_int32), ("split_units", ctypes.c_int32), ("chains", ctypes.c_int32),
+                ("motion", ctypes.c_int32), ("groups", ctypes.c_int32),
+                ("group_start", ctypes.POINTER(ctypes.c_int64)), ("packed", ctypes.c_int32)]
+
+
+class _AccumOpts(ctypes.Structure):
+    _fields_ = [("tile_waves", ctypes.c_int32), ("split_units", ctypes.c_int32), ("packed", ctypes.c_int32)]
+
+
+MOTIONS = {"rigid": 0, "free": 1}   # dgsm_motion
 
 
 _LIB = None
@@ -72,6 +81,14 @@ SIGNATURES = {
     "dgsm_build_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(_AtlasDesc), ctypes.c_int64, ctypes.c_int32]),
     "dgsm_build": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_Gaussians), ctypes.POINTER(_AtlasDesc),
                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dgsm_build_workspace_size_entries": (ctypes.c_size_t, [ctypes.POINTER(_AtlasDesc), ctypes.c_int64,
+                                                            ctypes.c_int32, ctypes.c_int64]),
+    "dgsm_count_entries": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_Gaussians),
+                                          ctypes.POINTER(_AtlasDesc), ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
+    "dgsm_list_entries": (ctypes.c_int, [ctypes.POINTER(_AtlasDesc), ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     "dgsm_build_noalloc": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_Gaussians),
                                           ctypes.POINTER(_AtlasDesc), ctypes.c_void_p, ctypes.c_void_p]),
     "dgsm_build_noalloc_max_bytes": (ctypes.c_size_t, []),
@@ -109,6 +126,10 @@ SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_longlong), ctypes.c_void_p]),
     "dgsm_plan_tile_waves": (ctypes.c_int32, [ctypes.c_void_p]),
     "dgsm_plan_split_units": (ctypes.c_int32, [ctypes.c_void_p]),
+    "dgsm_plan_packed": (ctypes.c_int32, [ctypes.c_void_p]),
+    "dgsm_accumulate_ex": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_AtlasDesc), ctypes.c_int64,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.POINTER(_AccumOpts), ctypes.c_void_p, ctypes.c_void_p]),
     "dgsm_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "dgsm_mlp_workspace_size": (ctypes.c_size_t, [ctypes.c_int64]),
     "dgsm_mlp_infer_workspace_size": (ctypes.c_size_t, [ctypes.c_int32]),
@@ -121,6 +142,14 @@ SIGNATURES = {
     "dgsm_mlp_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_AtlasDesc), ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_uint32, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dgsm_mlp_check_grid_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(_AtlasDesc), ctypes.c_int32]),
+    "dgsm_mlp_check_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_AtlasDesc), ctypes.c_void_p,
+                                           ctypes.c_int32, ctypes.c_uint32, ctypes.c_float, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "dgsm_mlp_save": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.POINTER(_AtlasDesc)]),
+    "dgsm_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(_AtlasDesc)]),
     "dgsm_mlp_infer": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Lights), ctypes.POINTER(_AtlasDesc),
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
@@ -283,6 +312,42 @@ def dgsm_build_workspace_size(atlas: Atlas, n_gauss: int, n_lights: int) -> int:
     return int(lib().dgsm_build_workspace_size(ctypes.byref(d), n_gauss, n_lights))
 
 
+def dgsm_build_workspace_size_entries(atlas: Atlas, n_gauss: int, n_lights: int, entries: int) -> int:
+    """Bytes of a build workspace whose lists hold ``entries`` entries per light."""
+    d = atlas.struct()
+    return int(lib().dgsm_build_workspace_size_entries(ctypes.byref(d), n_gauss, n_lights, entries))
+
+
+def dgsm_count_entries(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0, workspace=None,
+                       beta: str = "trace") -> int:
+    """List entries per light (maximum over lights) that this set needs; synchronises."""
+    lights = _rows(_dev(lights), 3, "lights")
+    L = int(lights.shape[0])
+    d = atlas.struct()
+    if workspace is None:
+        need = dgsm_build_workspace_size_entries(atlas, gaussians.n, L, 0)
+        if need == 0:
+            raise DGSMError("invalid atlas description")
+        workspace = torch.empty(need, dtype=torch.uint8, device=lights.device)
+    _cuda(workspace, "workspace")
+    lt = _Lights(lights.data_ptr(), L, kappa, BETA_MODES[beta])
+    gs = gaussians.struct()
+    out = ctypes.c_int64(0)
+    _check(lib().dgsm_count_entries(ctypes.byref(lt), ctypes.byref(gs), ctypes.byref(d), _ptr(workspace),
+                                    workspace.numel(), ctypes.byref(out), _stream()))
+    return int(out.value)
+
+
+def dgsm_list_entries(atlas: Atlas, n_gauss: int, n_lights: int, workspace, light: int):
+    """(entries the last binning of ``light`` needed, capacity of ``workspace``)."""
+    _cuda(workspace, "workspace")
+    d = atlas.struct()
+    out = (ctypes.c_int64 * 2)()
+    _check(lib().dgsm_list_entries(ctypes.byref(d), n_gauss, n_lights, _ptr(workspace), workspace.numel(), light,
+                                   out, _stream()))
+    return int(out[0]), int(out[1])
+
+
 def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0, out=None, workspace=None,
                beta: str = "trace"):
     """Build T[L, K, H, W] (see dgsm_build in include/dgsm.h)."""
@@ -292,7 +357,7 @@ def dgsm_build(lights, gaussians: GaussianSet, atlas: Atlas, kappa: float = 1.0,
     ws_bytes = dgsm_build_workspace_size(atlas, gaussians.n, L)
     if ws_bytes == 0:
         raise DGSMError("invalid atlas description")
-    if workspace is None or workspace.numel() < ws_bytes:
+    if workspace is None:   # worst case; a caller's workspace may be sized for its set (dgsm_count_entries)
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=lights.device)
     if out is None:
         out = torch.empty((L, atlas.K, atlas.H, atlas.W), dtype=atlas.torch_dtype, device=lights.device)
@@ -335,7 +400,7 @@ def dgsm_build_roi(lights, gaussians: GaussianSet, atlas: Atlas, receivers, box=
     ws_bytes = dgsm_build_workspace_size(atlas, gaussians.n, L)
     if ws_bytes == 0:
         raise DGSMError("invalid atlas description")
-    if workspace is None or workspace.numel() < ws_bytes:
+    if workspace is None:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=lights.device)
     if out is None:
         out = torch.empty((L, atlas.K, atlas.H, atlas.W), dtype=atlas.torch_dtype, device=lights.device)
@@ -376,6 +441,23 @@ def dgsm_accumulate(lights, atlas: Atlas, n_gauss: int, out, workspace, stats=No
     lt = _Lights(lights.data_ptr(), int(lights.shape[0]), 1.0)
     _check(lib().dgsm_accumulate(ctypes.byref(lt), ctypes.byref(d), n_gauss, _ptr(out), _ptr(workspace),
                                  workspace.numel(), _ptr(stats), _stream()))
+    return out
+
+
+def dgsm_accumulate_ex(lights, atlas: Atlas, n_gauss: int, out, workspace, tile_waves: int = 8,
+                       split_units: int = 0, packed: bool = False, stats=None):
+    """dgsm_accumulate with the knobs of the tile accumulation (bitwise the same atlas for every choice)."""
+    lights = _rows(_dev(lights), 3, "lights")
+    _buf(out, (int(lights.shape[0]), atlas.K, atlas.H, atlas.W), atlas.torch_dtype, "out")
+    _cuda(workspace, "workspace")
+    _cuda(stats, "stats")
+    if stats is not None and (stats.dtype != torch.int64 or stats.numel() < 8):
+        raise ValueError("stats must be an int64 tensor of at least 8 entries")
+    d = atlas.struct()
+    lt = _Lights(lights.data_ptr(), int(lights.shape[0]), 1.0)
+    o = _AccumOpts(int(tile_waves), int(split_units), int(packed))
+    _check(lib().dgsm_accumulate_ex(ctypes.byref(lt), ctypes.byref(d), n_gauss, _ptr(out), _ptr(workspace),
+                                    workspace.numel(), ctypes.byref(o), _ptr(stats), _stream()))
     return out
 
 
@@ -472,8 +554,9 @@ def dgsm_alpha_centroid(gaussians: GaussianSet, out=None):
 
 
 def sh_transfer(probe_sh, gaussians: GaussianSet, colour_sh=None, centroid=None, n_theta=32, n_phi=64,
-                q=1.0, clip_max=4.0, eps=1e-6, gamma=1.0):
-    """Per-Gaussian lighting scale [N,3], relit SH [N,16,3] and RGB [N,3] (Sec. 3.5)."""
+                q=1.0, clip_max=4.0, eps=1e-6, gamma=1.0, out=None):
+    """Per-Gaussian lighting scale [N,3], relit SH [N,16,3] and RGB [N,3] (Sec. 3.5);
+    ``out`` = (scale, colour, rgb) buffers to write instead of new ones."""
     N = gaussians.n
     _shape(probe_sh, None, "probe_sh", rows=(1, 4, 9, 16), width=3)
     _shape(colour_sh, (N, 16, 3), "colour_sh")
@@ -485,9 +568,18 @@ def sh_transfer(probe_sh, gaussians: GaussianSet, colour_sh=None, centroid=None,
         centroid = dgsm_alpha_centroid(gaussians)
     centroid = _dev(centroid)
     dev = gaussians.mean.device
-    s = torch.empty((N, 3), dtype=torch.float32, device=dev)
-    f_out = torch.empty((N, 16, 3), dtype=torch.float32, device=dev) if colour_sh is not None else None
-    rgb = torch.empty((N, 3), dtype=torch.float32, device=dev) if colour_sh is not None else None
+    if out is not None:
+        s, f_out, rgb = out
+        _buf(s, (N, 3), torch.float32, "out[0]")
+        if colour_sh is not None:
+            _buf(f_out, (N, 16, 3), torch.float32, "out[1]")
+            _buf(rgb, (N, 3), torch.float32, "out[2]")
+        else:
+            f_out = rgb = None
+    else:
+        s = torch.empty((N, 3), dtype=torch.float32, device=dev)
+        f_out = torch.empty((N, 16, 3), dtype=torch.float32, device=dev) if colour_sh is not None else None
+        rgb = torch.empty((N, 3), dtype=torch.float32, device=dev) if colour_sh is not None else None
     prm = _ShParams(n_theta, n_phi, q, clip_max, eps, gamma, centroid.data_ptr())
     gs = gaussians.struct()
     _check(lib().sh_transfer(_ptr(probe_sh), int(probe_sh.shape[0]), ctypes.byref(gs), _ptr(colour_sh),
@@ -499,22 +591,35 @@ class Plan:
     """Batched build + query over animation frames (dgsm_plan_* in include/dgsm.h).
 
     The static set is copied into the plan; each run evaluates ``frames`` frames of
-    the static set plus the dynamic set translated by ``translations[f]``.
+    the static set plus the dynamic set: with ``motion="rigid"`` the groups of the
+    dynamic set (``group_start``: G + 1 ascending offsets, default one group)
+    translated by ``translations[f][g]``; with ``motion="free"`` frame f of
+    per-frame dynamic arrays.
     """
 
     def __init__(self, lights, atlas: Atlas, static: GaussianSet, n_dynamic: int, frames: int,
                  static_cache: bool = True, autotune: bool = True, tile_waves: int = 8, split_units: int = 0,
-                 kappa: float = 1.0, beta: str = "trace"):
+                 kappa: float = 1.0, beta: str = "trace", chains: int = 0, motion: str = "rigid",
+                 group_start=None, packed: bool = False):
         lights = _rows(_dev(lights), 3, "lights")
         self.L = int(lights.shape[0])
         self.atlas = atlas
         self.n_static = static.n
         self.n_dynamic = int(n_dynamic)
         self.frames = int(frames)
+        self.motion = motion
+        starts = [0, self.n_dynamic] if group_start is None else [int(x) for x in group_start]
+        if motion not in MOTIONS:
+            raise ValueError(f"motion must be one of {sorted(MOTIONS)}")
+        if starts[0] != 0 or starts[-1] != self.n_dynamic or any(b < a for a, b in zip(starts, starts[1:])):
+            raise ValueError("group_start must ascend from 0 to n_dynamic")
+        self.groups = len(starts) - 1
         d = atlas.struct()
         lt = _Lights(lights.data_ptr(), self.L, kappa, BETA_MODES[beta])
         gs = static.struct()
-        opts = _PlanOpts(self.frames, int(static_cache), int(autotune), int(tile_waves), int(split_units))
+        gst = (ctypes.c_int64 * len(starts))(*starts)
+        opts = _PlanOpts(self.frames, int(static_cache), int(autotune), int(tile_waves), int(split_units),
+                         int(chains), MOTIONS[motion], self.groups, gst, int(packed))
         h = ctypes.c_void_p()
         _check(lib().dgsm_plan_create(ctypes.byref(lt), ctypes.byref(d), ctypes.byref(gs), self.n_dynamic,
                                       ctypes.byref(opts), ctypes.byref(h)))
@@ -532,25 +637,44 @@ class Plan:
     def split_units(self) -> int:
         return int(lib().dgsm_plan_split_units(self._h))
 
+    @property
+    def packed(self) -> bool:
+        return bool(lib().dgsm_plan_packed(self._h))
+
     def run(self, dynamic: GaussianSet, translations, out=None, use_graph: bool = True):
         """T[frames, L, n_static + n_dynamic] for one run; enqueued on the current stream.
         Without ``out`` the result is the plan's own buffer, overwritten by the next run."""
-        translations = _dev(translations)
-        if tuple(translations.shape) != (self.frames, 3):
-            raise ValueError(f"translations must be [{self.frames}, 3], got shape {tuple(translations.shape)}")
-        if dynamic.n != self.n_dynamic:
-            raise ValueError(f"the plan was made for {self.n_dynamic} dynamic Gaussians, got {dynamic.n}")
+        dev = dynamic.mean.device
+        if self.motion == "rigid":
+            translations = _dev(translations)
+            shapes = [(self.frames, self.groups, 3)] + ([(self.frames, 3)] if self.groups == 1 else [])
+            if tuple(translations.shape) not in shapes:
+                raise ValueError(f"translations must be {shapes[0]}, got shape {tuple(translations.shape)}")
+            if dynamic.n != self.n_dynamic:
+                raise ValueError(f"the plan was made for {self.n_dynamic} dynamic Gaussians, got {dynamic.n}")
+            gs = dynamic.struct()
+            tptr = _ptr(translations)
+        else:
+            F, n = self.frames, self.n_dynamic
+            for f, w in (("mean", 3), ("scale", 3), ("rot", 4), ("opacity", None)):
+                t = getattr(dynamic, f)
+                shape = (F, n, w) if w else (F, n)
+                if not isinstance(t, torch.Tensor) or tuple(t.shape) != shape or t.dtype != torch.float32:
+                    raise ValueError(f"free motion: dynamic.{f} must be float32 {shape}")
+                _cuda(t, f"dynamic.{f}")
+                if not t.is_contiguous():
+                    raise ValueError(f"dynamic.{f} must be contiguous")
+            gs = _Gaussians(dynamic.mean.data_ptr(), dynamic.scale.data_ptr(), dynamic.rot.data_ptr(),
+                            dynamic.opacity.data_ptr(), n)
+            tptr = None
         if out is None:
             # one plan-owned output, so that the captured graph's key stays the same
             # from run to run (a new pointer forces a recapture)
             if getattr(self, "_out", None) is None:
-                self._out = torch.empty((self.frames, self.L, self.n_points), dtype=torch.float32,
-                                        device=translations.device)
+                self._out = torch.empty((self.frames, self.L, self.n_points), dtype=torch.float32, device=dev)
             out = self._out
         _buf(out, (self.frames, self.L, self.n_points), torch.float32, "out")
-        gs = dynamic.struct()
-        _check(lib().dgsm_plan_run(self._h, ctypes.byref(gs), _ptr(translations), _ptr(out), int(use_graph),
-                                   _stream()))
+        _check(lib().dgsm_plan_run(self._h, ctypes.byref(gs), tptr, _ptr(out), int(use_graph), _stream()))
         return out
 
     def close(self):
@@ -628,6 +752,55 @@ def mlp_check(params, atlas: Atlas, table_l, n_check=262144, seed=12345, thresh=
     torch.cuda.current_stream().synchronize()
     st = stats.cpu()
     return mask, int(st[0]), float(st[1:2].view(torch.float32)[0])
+
+
+def mlp_check_grid(params, atlas: Atlas, table_l, n_per_region=64, seed=12345, thresh=1e-2):
+    """Fallback mask [regions] (uint8) and (flagged samples, max |dT|) from every texel centre x shell
+    plus n_per_region uniform points in each region."""
+    params = _dev(params)
+    if params.numel() != MLP_PARAMS:
+        raise ValueError(f"params must hold {MLP_PARAMS} values")
+    _buf(table_l, (atlas.K, atlas.H, atlas.W), atlas.torch_dtype, "table_l")
+    dev = params.device
+    d = atlas.struct()
+    need = int(lib().dgsm_mlp_check_grid_workspace_size(ctypes.byref(d), n_per_region))
+    if need == 0:
+        raise DGSMError("invalid atlas for the learned field, or n_per_region < 0")
+    mask = torch.zeros(mlp_regions(atlas), dtype=torch.uint8, device=dev)
+    stats = torch.zeros(2, dtype=torch.int32, device=dev)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    _check(lib().dgsm_mlp_check_grid(_ptr(params), ctypes.byref(d), _ptr(table_l), n_per_region, seed, thresh,
+                                     _ptr(mask), _ptr(stats), _ptr(ws), ws.numel(), _stream()))
+    torch.cuda.current_stream().synchronize()
+    st = stats.cpu()
+    return mask, int(st[0]), float(st[1:2].view(torch.float32)[0])
+
+
+def mlp_save(path, params, atlas: Atlas, adam_mv=None, step: int = 0):
+    """Write a checkpoint (parameters, optional Adam moments and step, atlas geometry)."""
+    p = params.detach().to("cpu", torch.float32).contiguous()
+    if p.numel() != MLP_PARAMS:
+        raise ValueError(f"params must hold {MLP_PARAMS} values")
+    m = None
+    if adam_mv is not None:
+        m = adam_mv.detach().to("cpu", torch.float32).contiguous()
+        if m.numel() != 2 * MLP_PARAMS:
+            raise ValueError(f"adam_mv must hold {2 * MLP_PARAMS} values")
+    d = atlas.struct()
+    _check(lib().dgsm_mlp_save(os.fsencode(path), p.data_ptr(), m.data_ptr() if m is not None else None, int(step),
+                               ctypes.byref(d)))
+
+
+def mlp_load(path, adam: bool = True):
+    """(params [MLP_PARAMS], adam_mv [2 MLP_PARAMS] or None, step, Atlas) from a checkpoint, on the host."""
+    p = torch.empty(MLP_PARAMS, dtype=torch.float32)
+    m = torch.empty(2 * MLP_PARAMS, dtype=torch.float32) if adam else None
+    step = ctypes.c_int32(0)
+    d = _AtlasDesc()
+    _check(lib().dgsm_mlp_load(os.fsencode(path), p.data_ptr(), m.data_ptr() if m is not None else None,
+                               ctypes.byref(step), ctypes.byref(d)))
+    sp = {DGSM_SHELLS_UNIFORM: "uniform", DGSM_SHELLS_GEOMETRIC: "geometric"}[d.spacing]
+    return p, m, int(step.value), Atlas(d.H, d.W, d.K, sp, d.r0, d.r1)
 
 
 def mlp_infer(params, lights, atlas: Atlas, points, table=None, mask=None, out=None, workspace=None):

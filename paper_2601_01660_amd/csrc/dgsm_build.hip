@@ -23,6 +23,7 @@
 #include <math.h>
 
 #include <mutex>
+#include <vector>
 
 namespace dgsm {
 
@@ -329,15 +330,29 @@ __global__ __launch_bounds__(256) void scan_kernel(unsigned char* ws, BuildLayou
 }
 
 // List base of every supertile, each list padded to a multiple of 64 entries.
-// Also clears the per-tile hit counters that the tile masks fill.
+// Also clears the per-tile hit counters that the tile masks fill.  Lists that
+// would not fit the workspace's capacity are all emptied (need[1] = 1): the
+// binning then writes nothing and the accumulation sees no Gaussian, so a too
+// small workspace gives a wrong atlas but never a write past its end.
 __global__ __launch_bounds__(256) void bases_kernel(unsigned char* ws, BuildLayout lay, int S, int ntiles) {
     __shared__ int wsum[4];
+    __shared__ int total;
     const LightWs W = light_ws(ws, lay, blockIdx.x);
     const int s = threadIdx.x;
     const int v = s < S ? (W.totals[s] + 63) & ~63 : 0;
     const int x = block_scan_incl(v, wsum);
-    if (s < S) W.lbase[s] = x - v;
-    if (s == S - 1) W.lbase[S] = x;
+    if (s == S - 1) total = x;
+    __syncthreads();
+    const bool over = (size_t)total > lay.cap;
+    if (s < S) {
+        W.lbase[s] = over ? 0 : x - v;
+        if (over) W.totals[s] = 0;
+    }
+    if (s == S - 1) W.lbase[S] = over ? 0 : x;
+    if (s == 0) {
+        W.need[0] = total;
+        W.need[1] = over ? 1 : 0;
+    }
     for (int t = s; t < ntiles; t += 256) W.hits[t] = 0;
 }
 
@@ -350,6 +365,7 @@ __global__ __launch_bounds__(kPrepThreads) void scatter_kernel(unsigned char* ws
     __shared__ int base_s[kMaxSuper];
     __shared__ int wcnt[kPrepThreads / kWave][kMaxSuper];
     const LightWs W = light_ws(ws, lay, blockIdx.y);
+    if (W.need[1]) return;   // the lists did not fit: nothing is scattered
     const int tid = threadIdx.x, w = tid / kWave, lane = tid % kWave;
     for (int s = tid; s < S; s += kPrepThreads) base_s[s] = W.lbase[s] + W.counts[(size_t)s * lay.nb + blockIdx.x];
     const int64_t i = (int64_t)blockIdx.x * kPrepThreads + tid;
@@ -737,6 +753,36 @@ __device__ inline RecRegs load_rec(ConstF4Ptr base, int gi) {
     return r;
 }
 
+// The same record with per-lane (vector) loads, for lanes that hold different Gaussians.
+__device__ inline RecRegs load_rec_v(const GRec* base, int gi) {
+    const float4* q = reinterpret_cast<const float4*>(base + gi);
+    const float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3], q4 = q[4], q5 = q[5], q6 = q[6];
+    RecRegs r;
+    r.mx = as_double(q0.x, q0.y);
+    r.my = as_double(q0.z, q0.w);
+    r.mz = as_double(q1.x, q1.y);
+    r.w[0] = q1.z; r.w[1] = q1.w; r.w[2] = q2.x; r.w[3] = q2.y; r.w[4] = q2.z; r.w[5] = q2.w;
+    r.w[6] = q3.x; r.w[7] = q3.y; r.w[8] = q3.z;
+    r.c[0] = q3.w; r.c[1] = q4.x; r.c[2] = q4.y; r.c[3] = q4.z; r.c[4] = q4.w;
+    r.c[5] = q5.x; r.c[6] = q5.y; r.c[7] = q5.z; r.c[8] = q5.w;
+    r.bp = q6.x;
+    r.r2 = q6.y;
+    r.lg = q6.z;
+    return r;
+}
+
+// The part of a record the distance pre-test needs: m and r2 (scalar loads).
+struct PreRegs {
+    double mx, my, mz;
+    float r2;
+};
+
+__device__ inline PreRegs load_pre(ConstF4Ptr base, int gi) {
+    const ConstF4Ptr q = base + (size_t)gi * (sizeof(GRec) / 16);
+    const f4v q0 = q[0], q1 = q[1], q6 = q[6];
+    return PreRegs{as_double(q0.x, q0.y), as_double(q0.z, q0.w), as_double(q1.x, q1.y), q6.y};
+}
+
 __device__ inline int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
 
@@ -826,18 +872,41 @@ __device__ inline float dot3(float a0, float a1, float a2, float b0, float b1, f
 // no a*b + c*d left to fuse one way in one copy and the other way in the
 // other, so a pair's increments are bitwise the same whatever the order of
 // the Gaussians.
+// Ray-line geometry in FP64, v = m x d (the perpendicular offset of the mean
+// from the texel ray), rounded to FP32, and the distance pre-test on it: a
+// texel whose |v|^2 reaches r2 cannot reach the pair threshold (r2 is a
+// conservative bound, from a >= 1/s_max^2 and e0 >= |v|^2 / s_max^2).
+struct RayOff {
+    float vx, vy, vz;
+    bool near;
+};
+
+__device__ inline RayOff ray_offset(double mx, double my, double mz, float r2, const TexelState& s) {
+#pragma clang fp contract(off)
+    const double vxd = fma(my, s.dz, -(mz * s.dy));
+    const double vyd = fma(mz, s.dx, -(mx * s.dz));
+    const double vzd = fma(mx, s.dy, -(my * s.dx));
+    RayOff o;
+    o.vx = (float)vxd; o.vy = (float)vyd; o.vz = (float)vzd;
+    o.near = dot3(o.vx, o.vy, o.vz, o.vx, o.vy, o.vz) < r2;
+    return o;
+}
+
+// A texel is evaluated only where its own tests pass (the distance pre-test,
+// the whitened bound and the prefactor threshold): which texels of a tile
+// contribute is a property of each (texel, Gaussian) pair alone, so the packed
+// walk, which evaluates each pair beside other Gaussians' pairs, adds exactly
+// the increments of the tile walk.
 template <bool STATS, bool GEO>
 __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r, const TexelState& s,
                                                                 Counters& n) {
 #pragma clang fp contract(off)
-    // Ray-line geometry in FP64: v = m x d, t_e = -(m . d).
-    const double vxd = fma(r.my, s.dz, -(r.mz * s.dy));
-    const double vyd = fma(r.mz, s.dx, -(r.mx * s.dz));
-    const double vzd = fma(r.mx, s.dy, -(r.my * s.dx));
+    // t_e = -(m . d); v = m x d
     const double te = -fma(r.mx, s.dx, fma(r.my, s.dy, r.mz * s.dz));
-    const float vx = (float)vxd, vy = (float)vyd, vz = (float)vzd;
+    const RayOff ro = ray_offset(r.mx, r.my, r.mz, r.r2, s);
+    const float vx = ro.vx, vy = ro.vy, vz = ro.vz;
     // cheap pre-test (conservative: it never drops a texel the full test keeps)
-    if ((ballot(dot3(vx, vy, vz, vx, vy, vz) < r.r2) & s.vmask) == 0ull) {
+    if ((ballot(ro.near) & s.vmask) == 0ull) {
         if (STATS) {
             n.idle += 1;
             n.pre += 1;
@@ -854,7 +923,8 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     const float cv2 = dot3(r.c[6], r.c[7], r.c[8], vx, vy, vz);
     const float cc = dot3(cv0, cv1, cv2, cv0, cv1, cv2);
     // second conservative test, free of transcendentals: e0 = cc / a >= lg
-    if ((ballot(cc < r.lg * a) & s.vmask) == 0ull) {
+    const bool near2 = ro.near && cc < r.lg * a;
+    if ((ballot(near2) & s.vmask) == 0ull) {
         if (STATS) n.idle += 1;
         return;
     }
@@ -864,8 +934,8 @@ __device__ __attribute__((always_inline)) inline void eval_pair(const RecRegs& r
     // prefactor of Eq. 3 times beta: beta sqrt(pi / (2a)) exp(-e0 / 2)
     // (exp(-e0/2) = 2^(e0 * (-log2(e)/2)); 2 P0 > eps  <=>  P0 > eps/2, both exact)
     const float P0 = r.bp * rsa * __builtin_amdgcn_exp2f(e0 * -0.72134752f);
-    const bool act = s.valid && (P0 > s.half_eps);
-    const uint64_t abal = ballot(P0 > s.half_eps) & s.vmask;
+    const bool act = s.valid && near2 && (P0 > s.half_eps);
+    const uint64_t abal = ballot(act);
     if (abal == 0ull) {
         if (STATS) n.idle += 1;
         return;
@@ -995,6 +1065,88 @@ __device__ __attribute__((always_inline)) inline void walk_hits(const uint64_t* 
     }
 }
 
+// Packed walk, for sets whose Gaussians reach few texels of a tile (the
+// per-frame avatar: about 4 of a tile's 64 texels per hit).  Each (tile,
+// Gaussian) hit runs only the distance pre-test over the tile's texels; the
+// texels that pass are queued in LDS as (Gaussian, texel) pairs, and every 64
+// queued pairs are evaluated together, one pair per lane, with the record read
+// per lane and the texel direction from LDS.  The evaluation is eval_pair's
+// arithmetic, and the increments go to the same fixed-point accumulators, so
+// the atlas is bitwise the one of the unpacked walk.
+constexpr int kQueue = 128;   // queued pairs per wave (up to 63 left over + 64 new)
+
+template <bool GEO>
+__device__ __attribute__((always_inline)) inline void walk_hits_packed(const uint64_t* words, int ns, int o, int S,
+                                                                       const int* list, ConstF4Ptr rec,
+                                                                       const GRec* recv, const TexelState& st,
+                                                                       int* qg, unsigned char* qt,
+                                                                       const double* dirs, Counters& n) {
+    const int lane = st.lane;
+    int qn = 0;   // queued pairs (wave-uniform)
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // evaluate the first cnt queued pairs (lane i: pair i) and move the rest to the front
+    auto flush = [&](int cnt) {
+        wave_sync();
+        const bool has = lane < cnt;
+        const int gi = has ? qg[lane] : 0;
+        const int tx = has ? (int)qt[lane] : 0;
+        const int rest = qn - cnt;
+        int gm = 0, tm = 0;
+        if (lane < rest) {
+            gm = qg[cnt + lane];
+            tm = qt[cnt + lane];
+        }
+        wave_sync();
+        if (lane < rest) {
+            qg[lane] = gm;
+            qt[lane] = (unsigned char)tm;
+        }
+        qn = rest;
+        TexelState ps = st;
+        ps.lane = tx;
+        ps.valid = has;
+        ps.vmask = ballot(has);
+        ps.dx = dirs[3 * tx];
+        ps.dy = dirs[3 * tx + 1];
+        ps.dz = dirs[3 * tx + 2];
+        ps.fx = (float)ps.dx; ps.fy = (float)ps.dy; ps.fz = (float)ps.dz;
+        const RecRegs r = load_rec_v(recv, gi);
+        eval_pair<false, GEO>(r, ps, n);
+    };
+    const int nw = o < ns ? (ns - 1 - o) / S + 1 : 0;   // words of this wave
+    for (int mbase = 0; mbase < nw; mbase += 64) {
+        const uint64_t wv = mbase + lane < nw ? words[(size_t)(mbase + lane) * S + o] : 0ull;
+        uint64_t nz = ballot(wv != 0ull);
+        while (nz) {
+            const int j = __builtin_ctzll(nz);
+            nz &= nz - 1;
+            uint64_t word = readlane_u64(wv, j);
+            const int gv = list[64 * ((mbase + j) * S + o) + lane];
+            while (word) {
+                const int b = __builtin_ctzll(word);
+                word &= word - 1;
+                const int gid = readlane_i(gv, b);
+                const PreRegs r = load_pre(rec, gid);
+                const bool pass = ray_offset(r.mx, r.my, r.mz, r.r2, st).near;   // eval_pair's pre-test
+                const uint64_t m = ballot(pass) & st.vmask;
+                if (m == 0ull) continue;
+                if ((m >> lane) & 1ull) {
+                    const int pos = qn + ballot_rank(m);
+                    qg[pos] = gid;
+                    qt[pos] = (unsigned char)lane;
+                }
+                qn += __popcll(m);
+                if (qn >= kWave) flush(kWave);
+            }
+        }
+    }
+    if (qn > 0) flush(qn);
+}
+
 constexpr int kFinishGroup = 8;
 
 // Finish of one tile by all NWB waves of the block: wave w takes shells
@@ -1106,8 +1258,8 @@ __device__ inline void finish_tile(const TileArgs& p, int light, int tile, int l
 // registers for the short kernels of the plan's other frame chains to run
 // beside it (measured: batched step 1.7% faster, a lone full-scene build 0.9%
 // slower; at 5 resident waves the build is 24% slower).
-template <typename OutT, bool STATS, int NW, bool GEO, bool CUBE>
-__global__ __launch_bounds__(kWave * NW, 7) void tile_build_kernel(TileArgs p) {
+template <typename OutT, bool STATS, int NW, bool GEO, bool CUBE, bool PACK>
+__global__ __launch_bounds__(kWave * NW, PACK ? 6 : 7) void tile_build_kernel(TileArgs p) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const Geom& g = p.g;
     const int K = g.K;
@@ -1182,6 +1334,16 @@ __global__ __launch_bounds__(kWave * NW, 7) void tile_build_kernel(TileArgs p) {
         st.ratio = (double)g.r1 / (double)K;
     }
     for (int q = tid; q < K * kWave; q += kWave * NW) inc[q] = 0ull;
+    // packed walk: texel directions [64][3] and each wave's pair queue after the shell radii
+    double* dirs = shells + (2 * K - 1);
+    int* qg = reinterpret_cast<int*>(dirs + 3 * kWave) + wave * kQueue;
+    unsigned char* qt = reinterpret_cast<unsigned char*>(reinterpret_cast<int*>(dirs + 3 * kWave) + NW * kQueue) +
+                        wave * kQueue;
+    if (PACK && wave == 0) {
+        dirs[3 * lane] = st.dx;
+        dirs[3 * lane + 1] = st.dy;
+        dirs[3 * lane + 2] = st.dz;
+    }
 
     // this tile's hit words: contiguous ns words, one per 64-entry chunk of the
     // supertile list; wave w of slice i walks words i NW + w, + nslice NW, ...
@@ -1201,7 +1363,10 @@ __global__ __launch_bounds__(kWave * NW, 7) void tile_build_kernel(TileArgs p) {
     }
     __syncthreads();
 
-    walk_hits<STATS, GEO>(words, ns, slice * NW + wave, nslice * NW, list, rec, st, n);
+    if constexpr (PACK)
+        walk_hits_packed<GEO>(words, ns, slice * NW + wave, nslice * NW, list, rec, W.rec, st, qg, qt, dirs, n);
+    else
+        walk_hits<STATS, GEO>(words, ns, slice * NW + wave, nslice * NW, list, rec, st, n);
 
     if (STATS) {
         const unsigned long long nvalid = __popcll(ballot(st.valid));
@@ -1292,7 +1457,7 @@ __global__ __launch_bounds__(kWave * kFinishWaves) void split_finish_kernel(Tile
 // Host side
 // ---------------------------------------------------------------------------
 
-BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
+BuildLayout build_layout(const Geom& g, int64_t n, int n_lights, int64_t cap) {
     BuildLayout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -1301,7 +1466,8 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
         return o;
     };
     L.nb = (int)((n + kPrepThreads - 1) / kPrepThreads);
-    L.cap = (size_t)n * g.S + 64 * (size_t)g.S;
+    const size_t worst = (size_t)n * g.S + 64 * (size_t)g.S;
+    L.cap = cap < 0 ? worst : (size_t)cap;
     L.tcone = take((size_t)g.ntiles * sizeof(float4));
     L.scone = take((size_t)kMaxSuper * sizeof(float4));
     L.qcone = take((size_t)((g.TH + 1) / 2) * ((g.TW + 1) / 2) * sizeof(float4));
@@ -1338,49 +1504,83 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights) {
     L.prange = take(2 * (size_t)L.units_cap * sizeof(int2));
     L.roi_mask = take((size_t)g.ntiles * sizeof(unsigned long long));
     L.roi_k = take(2 * sizeof(int));
+    L.need = take(2 * sizeof(int));
     L.light_stride = off;
     L.total = L.light0 + (size_t)n_lights * L.light_stride;
     return L;
 }
 
+bool layout_for_bytes(const Geom& g, int64_t n, int n_lights, size_t ws_bytes, BuildLayout& out) {
+    out = build_layout(g, n, n_lights);
+    if (out.total <= ws_bytes) return true;
+    const int64_t lo = 64 * (int64_t)g.S;
+    const BuildLayout base = build_layout(g, n, n_lights, lo);
+    if (base.total > ws_bytes) return false;
+    // each light slice grows by 12 bytes per entry (an int list entry and a
+    // u64 hit word), up to 512 bytes of alignment padding
+    const size_t spare = (ws_bytes - base.total) / (size_t)n_lights;
+    int64_t cap = lo + (int64_t)(spare / 12) / 64 * 64;
+    const int64_t worst = (int64_t)out.cap;
+    cap = cap < worst ? cap : worst;
+    out = build_layout(g, n, n_lights, cap);
+    while (out.total > ws_bytes && cap > lo) {
+        cap -= 64;
+        out = build_layout(g, n, n_lights, cap);
+    }
+    return out.total <= ws_bytes;
+}
+
 // LDS of a tile block: increments [K][64] (u64), then the finish's wave totals
 // [NW][64] (u64) and wave minima [NW][64] (f32), then the shell radii [K] (FP64)
 // and K - 1 copies of the last radius (read by lanes whose ramp has ended).
-size_t tile_smem_bytes(const Geom& g, int nw) {
+// With the packed walk, the texel directions [64][3] (FP64) and each wave's
+// pair queue (kQueue Gaussian ids and texel indices) follow.
+size_t tile_smem_bytes(const Geom& g, int nw, bool pack) {
     return (size_t)g.K * kWave * sizeof(unsigned long long) + (size_t)nw * kWave * (sizeof(unsigned long long) + 4) +
-           (size_t)(2 * g.K - 1) * sizeof(double);
+           (size_t)(2 * g.K - 1) * sizeof(double) +
+           (pack ? 3 * kWave * sizeof(double) + (size_t)nw * kQueue * (sizeof(int) + 1) : 0);
 }
 
-template <typename OutT, bool STATS, int NW, bool CUBE>
+template <typename OutT, bool STATS, int NW, bool CUBE, bool PACK>
 static hipError_t launch_tile_map(const TileArgs& ta, int n_lights, hipStream_t st) {
-    const size_t smem = tile_smem_bytes(ta.g, NW);
+    const size_t smem = tile_smem_bytes(ta.g, NW, PACK);
     const bool geo = ta.g.spacing == DGSM_SHELLS_GEOMETRIC;
-    const void* fn = geo ? (const void*)tile_build_kernel<OutT, STATS, NW, true, CUBE>
-                         : (const void*)tile_build_kernel<OutT, STATS, NW, false, CUBE>;
+    const void* fn = geo ? (const void*)tile_build_kernel<OutT, STATS, NW, true, CUBE, PACK>
+                         : (const void*)tile_build_kernel<OutT, STATS, NW, false, CUBE, PACK>;
     if (smem > 64 * 1024) {
         const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
     const dim3 grid(ta.g.ntiles + ta.lay.units_cap, n_lights);
     if (geo)
-        tile_build_kernel<OutT, STATS, NW, true, CUBE><<<grid, kWave * NW, smem, st>>>(ta);
+        tile_build_kernel<OutT, STATS, NW, true, CUBE, PACK><<<grid, kWave * NW, smem, st>>>(ta);
     else
-        tile_build_kernel<OutT, STATS, NW, false, CUBE><<<grid, kWave * NW, smem, st>>>(ta);
+        tile_build_kernel<OutT, STATS, NW, false, CUBE, PACK><<<grid, kWave * NW, smem, st>>>(ta);
     return hipGetLastError();
 }
 
-template <typename OutT, bool STATS, int NW>
+template <typename OutT, bool STATS, int NW, bool PACK>
 static hipError_t launch_tile(const TileArgs& ta, int n_lights, hipStream_t st) {
-    return ta.g.param == DGSM_PARAM_CUBEMAP ? launch_tile_map<OutT, STATS, NW, true>(ta, n_lights, st)
-                                            : launch_tile_map<OutT, STATS, NW, false>(ta, n_lights, st);
+    return ta.g.param == DGSM_PARAM_CUBEMAP ? launch_tile_map<OutT, STATS, NW, true, PACK>(ta, n_lights, st)
+                                            : launch_tile_map<OutT, STATS, NW, false, PACK>(ta, n_lights, st);
 }
 
 template <typename OutT, bool STATS>
 static hipError_t launch_tile_nw(const TileArgs& ta, int n_lights, int nw, hipStream_t st) {
     switch (nw) {
-        case 2: return launch_tile<OutT, STATS, 2>(ta, n_lights, st);
-        case 8: return launch_tile<OutT, STATS, 8>(ta, n_lights, st);
-        default: return launch_tile<OutT, STATS, 4>(ta, n_lights, st);
+        case 2: return launch_tile<OutT, STATS, 2, false>(ta, n_lights, st);
+        case 8: return launch_tile<OutT, STATS, 8, false>(ta, n_lights, st);
+        default: return launch_tile<OutT, STATS, 4, false>(ta, n_lights, st);
+    }
+}
+
+// The packed walk (no counters).
+template <typename OutT>
+static hipError_t launch_tile_packed(const TileArgs& ta, int n_lights, int nw, hipStream_t st) {
+    switch (nw) {
+        case 2: return launch_tile<OutT, false, 2, true>(ta, n_lights, st);
+        case 8: return launch_tile<OutT, false, 8, true>(ta, n_lights, st);
+        default: return launch_tile<OutT, false, 4, true>(ta, n_lights, st);
     }
 }
 
@@ -1447,11 +1647,13 @@ dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned cha
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     if (o.stats)
         e = half ? launch_tile_nw<__half, true>(ta, n_lights, nw, st) : launch_tile_nw<float, true>(ta, n_lights, nw, st);
+    else if (o.pack)
+        e = half ? launch_tile_packed<__half>(ta, n_lights, nw, st) : launch_tile_packed<float>(ta, n_lights, nw, st);
     else
         e = half ? launch_tile_nw<__half, false>(ta, n_lights, nw, st) : launch_tile_nw<float, false>(ta, n_lights, nw, st);
     if (e != hipSuccess) return DGSM_EHIP;
     const dim3 fgrid(L.units_cap, n_lights);
-    const size_t fsmem = tile_smem_bytes(g, kFinishWaves);
+    const size_t fsmem = tile_smem_bytes(g, kFinishWaves, false);
     const void* ffn = half ? (const void*)split_finish_kernel<__half> : (const void*)split_finish_kernel<float>;
     if (fsmem > 64 * 1024 && hipFuncSetAttribute(ffn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)fsmem) !=
                                  hipSuccess)
@@ -1489,8 +1691,8 @@ extern "C" dgsm_status dgsm_bin(const dgsm_lights_t* lights, const dgsm_gaussian
     dgsm_status st = check_build_args(lights, gaussians, desc);
     if (st != DGSM_OK) return st;
     const Geom g = make_geom(*desc);
-    const BuildLayout L = build_layout(g, gaussians->n, lights->n);
-    if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
+    BuildLayout L;
+    if (!ws || !layout_for_bytes(g, gaussians->n, lights->n, ws_bytes, L)) return DGSM_EWORKSPACE;
     return enqueue_bin(g, L, reinterpret_cast<unsigned char*>(ws), *lights, desc->cull_eps, *gaussians,
                        reinterpret_cast<hipStream_t>(stream));
 }
@@ -1503,9 +1705,28 @@ extern "C" dgsm_status dgsm_accumulate(const dgsm_lights_t* lights, const dgsm_a
     if ((st = validate_lights(lights)) != DGSM_OK) return st;
     if (n_gauss < 0 || n_gauss >= INT32_MAX || !atlas) return DGSM_EINVAL;
     const Geom g = make_geom(*desc);
-    const BuildLayout L = build_layout(g, n_gauss, lights->n);
-    if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
+    BuildLayout L;
+    if (!ws || !layout_for_bytes(g, n_gauss, lights->n, ws_bytes, L)) return DGSM_EWORKSPACE;
     AccumOpts o{nullptr, false, stats, kDefaultTileWaves, kDefaultSplitUnits};
+    return enqueue_accumulate(g, L, reinterpret_cast<unsigned char*>(ws), lights->n, desc->cull_eps, atlas, o,
+                              reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" dgsm_status dgsm_accumulate_ex(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc,
+                                          int64_t n_gauss, void* atlas, void* ws, size_t ws_bytes,
+                                          const dgsm_accum_opts_t* opts, unsigned long long* stats, void* stream) {
+    dgsm_status st = validate_desc(desc);
+    if (st != DGSM_OK) return st;
+    if ((st = validate_lights(lights)) != DGSM_OK) return st;
+    if (n_gauss < 0 || n_gauss >= INT32_MAX || !atlas || !opts) return DGSM_EINVAL;
+    if (opts->tile_waves != 2 && opts->tile_waves != 4 && opts->tile_waves != 8) return DGSM_EINVAL;
+    if (opts->packed && stats) return DGSM_EINVAL;   // the packed walk keeps no counters
+    const Geom g = make_geom(*desc);
+    BuildLayout L;
+    if (!ws || !layout_for_bytes(g, n_gauss, lights->n, ws_bytes, L)) return DGSM_EWORKSPACE;
+    AccumOpts o{nullptr, false, stats, opts->tile_waves,
+                opts->split_units == 0 ? kDefaultSplitUnits : (opts->split_units < 0 ? -1 : opts->split_units)};
+    o.pack = opts->packed != 0;
     return enqueue_accumulate(g, L, reinterpret_cast<unsigned char*>(ws), lights->n, desc->cull_eps, atlas, o,
                               reinterpret_cast<hipStream_t>(stream));
 }
@@ -1518,13 +1739,69 @@ extern "C" dgsm_status dgsm_work_units(const dgsm_atlas_desc_t* desc, int64_t n_
     if (n_gauss < 0 || n_gauss >= INT32_MAX || n_lights < 1 || light < 0 || light >= n_lights || !out)
         return DGSM_EINVAL;
     const Geom g = make_geom(*desc);
-    const BuildLayout L = build_layout(g, n_gauss, n_lights);
-    if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
+    BuildLayout L;
+    if (!ws || !layout_for_bytes(g, n_gauss, n_lights, ws_bytes, L)) return DGSM_EWORKSPACE;
     const LightWs W = light_ws(reinterpret_cast<unsigned char*>(const_cast<void*>(ws)), L, light);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (hipMemcpyAsync(out, W.nunits, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return DGSM_EHIP;
+    return DGSM_OK;
+}
+
+extern "C" size_t dgsm_build_workspace_size_entries(const dgsm_atlas_desc_t* desc, int64_t n_gauss,
+                                                    int32_t n_lights, int64_t entries) {
+    if (validate_desc(desc) != DGSM_OK || n_gauss < 0 || n_gauss >= INT32_MAX || n_lights < 1 || entries < 0)
+        return 0;
+    const Geom g = make_geom(*desc);
+    const int64_t worst = (n_gauss + 64) * (int64_t)g.S;
+    int64_t cap = (entries + 63) / 64 * 64;
+    cap = cap < 64 * (int64_t)g.S ? 64 * (int64_t)g.S : cap;
+    return build_layout(g, n_gauss, n_lights, cap < worst ? cap : worst).total;
+}
+
+extern "C" dgsm_status dgsm_count_entries(const dgsm_lights_t* lights, const dgsm_gaussians_t* gaussians,
+                                          const dgsm_atlas_desc_t* desc, void* ws, size_t ws_bytes,
+                                          int64_t* entries, void* stream) {
+    dgsm_status st = check_build_args(lights, gaussians, desc);
+    if (st != DGSM_OK) return st;
+    if (!entries) return DGSM_EINVAL;
+    const Geom g = make_geom(*desc);
+    BuildLayout L;
+    if (!ws || !layout_for_bytes(g, gaussians->n, lights->n, ws_bytes, L)) return DGSM_EWORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    unsigned char* w = reinterpret_cast<unsigned char*>(ws);
+    if ((st = enqueue_bin(g, L, w, *lights, desc->cull_eps, *gaussians, s)) != DGSM_OK) return st;
+    std::vector<int> need(2 * (size_t)lights->n);
+    for (int l = 0; l < lights->n; ++l)
+        if (hipMemcpyAsync(&need[2 * l], light_ws(w, L, l).need, 2 * sizeof(int), hipMemcpyDeviceToHost, s) !=
+            hipSuccess)
+            return DGSM_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return DGSM_EHIP;
+    int64_t m = 0;
+    for (int l = 0; l < lights->n; ++l) m = need[2 * l] > m ? need[2 * l] : m;
+    *entries = m;
+    return DGSM_OK;
+}
+
+extern "C" dgsm_status dgsm_list_entries(const dgsm_atlas_desc_t* desc, int64_t n_gauss, int32_t n_lights,
+                                         const void* ws, size_t ws_bytes, int32_t light, int64_t out[2],
+                                         void* stream) {
+    dgsm_status st = validate_desc(desc);
+    if (st != DGSM_OK) return st;
+    if (n_gauss < 0 || n_gauss >= INT32_MAX || n_lights < 1 || light < 0 || light >= n_lights || !out)
+        return DGSM_EINVAL;
+    const Geom g = make_geom(*desc);
+    BuildLayout L;
+    if (!ws || !layout_for_bytes(g, n_gauss, n_lights, ws_bytes, L)) return DGSM_EWORKSPACE;
+    const LightWs W = light_ws(reinterpret_cast<unsigned char*>(const_cast<void*>(ws)), L, light);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int need[2] = {0, 0};
+    if (hipMemcpyAsync(need, W.need, 2 * sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return DGSM_EHIP;
+    out[0] = need[0];
+    out[1] = (int64_t)L.cap;
     return DGSM_OK;
 }
 
@@ -1537,8 +1814,8 @@ extern "C" dgsm_status dgsm_build_roi(const dgsm_lights_t* lights, const dgsm_ga
     if (!atlas || !box || n_receivers < 0 || (n_receivers > 0 && !receivers)) return DGSM_EINVAL;
     if (box->half > 0.f && !(box->zmin <= box->zmax)) return DGSM_EINVAL;
     const Geom g = make_geom(*desc);
-    const BuildLayout L = build_layout(g, gaussians->n, lights->n);
-    if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
+    BuildLayout L;
+    if (!ws || !layout_for_bytes(g, gaussians->n, lights->n, ws_bytes, L)) return DGSM_EWORKSPACE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
     if ((st = enqueue_bin(g, L, w, *lights, desc->cull_eps, *gaussians, s)) != DGSM_OK) return st;
@@ -1556,8 +1833,8 @@ extern "C" dgsm_status dgsm_build(const dgsm_lights_t* lights, const dgsm_gaussi
     if (st != DGSM_OK) return st;
     if (!atlas) return DGSM_EINVAL;
     const Geom g = make_geom(*desc);
-    const BuildLayout L = build_layout(g, gaussians->n, lights->n);
-    if (!ws || ws_bytes < L.total) return DGSM_EWORKSPACE;
+    BuildLayout L;
+    if (!ws || !layout_for_bytes(g, gaussians->n, lights->n, ws_bytes, L)) return DGSM_EWORKSPACE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
     if ((st = enqueue_bin(g, L, w, *lights, desc->cull_eps, *gaussians, s)) != DGSM_OK) return st;

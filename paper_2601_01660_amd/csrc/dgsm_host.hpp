@@ -58,7 +58,7 @@ struct BuildLayout {
     int units_cap;           // extra work units per light (tiles split over several blocks)
     // offsets inside a light slice
     size_t totals, lbase, rec, cone, mask, counts, lists, bits;
-    size_t hits, tinfo, units, splits, nunits, part, prange, roi_mask, roi_k;
+    size_t hits, tinfo, units, splits, nunits, part, prange, roi_mask, roi_k, need;
     size_t total;            // bytes for all lights
 };
 
@@ -81,6 +81,7 @@ struct LightWs {
     int2* prange;               // [2 units_cap] shell rows [lo, hi] each partial holds (lo > hi: none)
     unsigned long long* roi_mask;   // [ntiles] receiver texels of each tile (bit = texel in the tile)
     int* roi_k;                     // [2] receiver shell range {k_min, k_max}
+    int* need;                      // [2] {list entries the last binning needed, 1 if they exceeded cap}
 };
 
 __host__ __device__ inline LightWs light_ws(unsigned char* ws, const BuildLayout& L, int l) {
@@ -93,11 +94,19 @@ __host__ __device__ inline LightWs light_ws(unsigned char* ws, const BuildLayout
                    reinterpret_cast<int4*>(b + L.units), reinterpret_cast<int2*>(b + L.splits),
                    reinterpret_cast<int*>(b + L.nunits), reinterpret_cast<unsigned long long*>(b + L.part),
                    reinterpret_cast<int2*>(b + L.prange),
-                   reinterpret_cast<unsigned long long*>(b + L.roi_mask), reinterpret_cast<int*>(b + L.roi_k)};
+                   reinterpret_cast<unsigned long long*>(b + L.roi_mask), reinterpret_cast<int*>(b + L.roi_k),
+                   reinterpret_cast<int*>(b + L.need)};
 }
 
-BuildLayout build_layout(const Geom& g, int64_t n, int n_lights);
-size_t tile_smem_bytes(const Geom& g, int nw);
+// Workspace layout for n Gaussians and n_lights lights.  cap: list entries
+// per light (supertile lists and hit words); negative = the worst case
+// n S + 64 S, which every set of n Gaussians fits.
+BuildLayout build_layout(const Geom& g, int64_t n, int n_lights, int64_t cap = -1);
+// The layout a workspace of ws_bytes holds: the worst case if it fits,
+// otherwise the largest list capacity (a multiple of 64, at least 64 S) that
+// does; false if not even that fits.
+bool layout_for_bytes(const Geom& g, int64_t n, int n_lights, size_t ws_bytes, BuildLayout& out);
+size_t tile_smem_bytes(const Geom& g, int nw, bool pack);
 
 // Tile and supertile cones of the atlas geometry (depend on the atlas only).
 dgsm_status enqueue_cones(const Geom& g, const BuildLayout& L, unsigned char* ws, hipStream_t st);
@@ -118,6 +127,7 @@ struct AccumOpts {
     bool tiled = false;          // atlas / base_tau planes in tile-major order (see kTile)
     bool skip_empty = false;     // leave tiles without hits untouched (their atlas values stay as they are)
     bool roi = false;            // receiver region: T = 1 outside the marked texels and shell range
+    bool pack = false;           // packed walk: only pairs past the distance pre-test, 64 per wave (no stats)
 };
 
 // Receiver box of the region of interest (Sec. 3.2): |x - cx|, |y - cy| <= half,

@@ -2,9 +2,11 @@
 //
 // A plan owns every buffer it needs (allocated once, at creation).  One run
 // processes F frames of a scene made of a static Gaussian set and a dynamic
-// set that moves rigidly by a per-frame translation:
-//   per frame f: dynamic means = base + t_f; build the atlas of every light
-//   from all Gaussians; query T at all Gaussian centres into T_out[f].
+// set that either moves rigidly, one translation per group of Gaussians per
+// frame (several avatars on their own trajectories), or takes new means,
+// scales, rotations and opacities every frame (free motion):
+//   per frame f: the dynamic Gaussians of frame f; build the atlas of every
+//   light from all Gaussians; query T at all Gaussian centres into T_out[f].
 // With the static cache on, the optical depth of the static set is built once
 // per run (it does not change between frames) and each frame only bins and
 // accumulates the dynamic Gaussians on top of it: tau = tau_static +
@@ -29,12 +31,23 @@
 
 namespace dgsm {
 
-// dst[i] = base[i] + t  (one FP32 addition per coordinate)
+// dst = base + t of the Gaussian's group (one FP32 addition per coordinate);
+// group: [n] group index of each Gaussian, or null for a single group.
 __global__ __launch_bounds__(256) void translate_kernel(const float* __restrict__ base, int64_t n,
-                                                        const float* __restrict__ t, float* __restrict__ dst) {
+                                                        const float* __restrict__ t,
+                                                        const unsigned short* __restrict__ group,
+                                                        float* __restrict__ dst) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= 3 * n) return;
-    dst[i] = base[i] + t[i % 3];
+    const int c = (int)(i % 3);
+    const int gi = group ? (int)group[i / 3] : 0;
+    dst[i] = base[i] + t[3 * gi + c];
+}
+
+__global__ __launch_bounds__(256) void group_index_kernel(unsigned short* __restrict__ group, int64_t from,
+                                                          int64_t to, int gi) {
+    const int64_t i = from + (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < to) group[i] = (unsigned short)gi;
 }
 
 // Frames of a cached run are spread over up to kMaxChains independent chains
@@ -232,6 +245,12 @@ struct dgsm_plan_s {
     int tile_waves;
     int split_units;
     bool tuned;
+    int pack;             // packed walk for the dynamic accumulation (cache mode)
+    int motion;           // DGSM_MOTION_RIGID or DGSM_MOTION_FREE
+    int groups;           // rigid groups of the dynamic set
+    unsigned short* group;   // [nd] group of each dynamic Gaussian (null: one group)
+    BuildLayout lay_a;    // workspace of the static set (cache mode) or of the whole set
+    BuildLayout lay_b;    // workspace of the dynamic set (cache mode)
     // device buffers owned by the plan
     float* lights;        // [L][3]
     float* mean;          // [ns + nd][3]: static means, then this frame's dynamic means
@@ -277,7 +296,7 @@ void plan_free(dgsm_plan p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     void* bufs[] = {p->lights,     p->mean,  p->scale,        p->rot,  p->opacity, p->out_index,
                     p->tau_static, p->atlas, p->atlas_static, p->ws_a, p->ws_b,    p->in_pos,
-                    p->tq};
+                    p->tq,         p->group};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int c = 1; c < kMaxChains; ++c) {
@@ -298,7 +317,7 @@ dgsm_gaussians_t set_of(const dgsm_plan p, const float* mean, int64_t off, int64
 // Static part of a run: tau of the static set for every light.
 dgsm_status enqueue_static(dgsm_plan p, int tile_waves, int split_units, hipStream_t st) {
     const dgsm_lights_t lt{p->lights, p->L, p->kappa, p->beta_mode};
-    const BuildLayout La = build_layout(p->g, p->ns, p->L);
+    const BuildLayout& La = p->lay_a;
     dgsm_status s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, p->mean, 0, p->ns), st, false);
     if (s != DGSM_OK) return s;
     AccumOpts o{nullptr, true, nullptr, tile_waves, split_units, true};
@@ -320,32 +339,53 @@ dgsm_status enqueue_static(dgsm_plan p, int tile_waves, int split_units, hipStre
 // One frame on chain c (its stream st): dynamic means, build (on top of the
 // static tau in cache mode), query, and in cache mode the restore of the
 // chain's atlas to the static baseline.
-dgsm_status enqueue_frame(dgsm_plan p, int f, int c, const float* dyn_base, const float* translations, float* T_out,
-                          int tile_waves, int split_units, hipStream_t st) {
+dgsm_status enqueue_frame(dgsm_plan p, int f, int c, const dgsm_gaussians_t* dyn_base, const float* translations,
+                          float* T_out, int tile_waves, int split_units, int pack, hipStream_t st) {
     const dgsm_lights_t lt{p->lights, p->L, p->kappa, p->beta_mode};
     float* mean = p->cmean[c];
     void* atlas = p->catlas[c];
     unsigned char* ws_b = p->cws[c];
+    const bool rigid = p->motion == DGSM_MOTION_RIGID;
+    // the dynamic Gaussians of this frame: rigid motion moves the base means
+    // (shape in the plan's arrays); free motion takes frame f of the caller's arrays
+    dgsm_gaussians_t dyn{mean + 3 * p->ns, p->scale + 3 * p->ns, p->rot + 4 * p->ns, p->opacity + p->ns, p->nd};
     if (p->nd > 0) {
         const int64_t n3 = 3 * p->nd;
-        translate_kernel<<<(unsigned)((n3 + 255) / 256), 256, 0, st>>>(dyn_base, p->nd, translations + 3 * f,
-                                                                        mean + 3 * p->ns);
-        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+        if (rigid) {
+            translate_kernel<<<(unsigned)((n3 + 255) / 256), 256, 0, st>>>(
+                dyn_base->mean, p->nd, translations + (size_t)3 * p->groups * f, p->group, mean + 3 * p->ns);
+            if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+        } else {
+            const size_t fo = (size_t)f * p->nd;
+            if (hipMemcpyAsync(mean + 3 * p->ns, dyn_base->mean + 3 * fo, 12 * p->nd, hipMemcpyDeviceToDevice, st) !=
+                hipSuccess)
+                return DGSM_EHIP;
+            dyn.scale = dyn_base->scale + 3 * fo;
+            dyn.rot = dyn_base->rot + 4 * fo;
+            dyn.opacity = dyn_base->opacity + fo;
+            if (!p->cache &&   // the whole set is binned from the plan's arrays: this frame's shapes into them
+                (hipMemcpyAsync(p->scale + 3 * p->ns, dyn.scale, 12 * p->nd, hipMemcpyDeviceToDevice, st) !=
+                     hipSuccess ||
+                 hipMemcpyAsync(p->rot + 4 * p->ns, dyn.rot, 16 * p->nd, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                 hipMemcpyAsync(p->opacity + p->ns, dyn.opacity, 4 * p->nd, hipMemcpyDeviceToDevice, st) !=
+                     hipSuccess))
+                return DGSM_EHIP;
+        }
     }
     dgsm_status s;
     if (p->cache) {
-        const BuildLayout Lb = build_layout(p->g, p->nd, p->L);
-        // the dynamic set moves rigidly: from the chain's second frame of the
-        // run on, its records keep their shape part and only the light-to-mean
+        const BuildLayout& Lb = p->lay_b;
+        // rigid motion: from the chain's second frame of the run on, the
+        // dynamic records keep their shape part and only the light-to-mean
         // offsets change
-        s = enqueue_bin(p->g, Lb, ws_b, lt, p->desc.cull_eps, set_of(p, mean, p->ns, p->nd), st, false,
-                        f >= p->chains);
+        s = enqueue_bin(p->g, Lb, ws_b, lt, p->desc.cull_eps, dyn, st, false, rigid && f >= p->chains);
         if (s != DGSM_OK) return s;
         // only tiles the dynamic set reaches are rebuilt; the rest hold the static baseline
         AccumOpts o{p->tau_static, false, nullptr, tile_waves, split_units, true, true};
+        o.pack = pack != 0;
         s = enqueue_accumulate(p->g, Lb, ws_b, p->L, p->desc.cull_eps, atlas, o, st);
     } else {
-        const BuildLayout La = build_layout(p->g, p->np, p->L);
+        const BuildLayout& La = p->lay_a;
         s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, mean, 0, p->np), st, false);
         if (s != DGSM_OK) return s;
         AccumOpts o{nullptr, false, nullptr, tile_waves, split_units, true};
@@ -363,7 +403,7 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, int c, const float* dyn_base, cons
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }
     if (p->cache) {
-        const BuildLayout Lb = build_layout(p->g, p->nd, p->L);
+        const BuildLayout& Lb = p->lay_b;
         const dim3 grid(p->g.ntiles, p->L);
         if (p->desc.dtype == DGSM_F16)
             restore_kernel<__half><<<grid, kWave, 0, st>>>(p->g, Lb, ws_b, static_cast<const __half*>(p->atlas_static),
@@ -378,7 +418,7 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, int c, const float* dyn_base, cons
 
 dgsm_status enqueue_run(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* translations, float* T_out,
                         hipStream_t st) {
-    if (p->nd > 0) {
+    if (p->nd > 0 && p->motion == DGSM_MOTION_RIGID) {
         const int64_t o = p->ns;
         if (hipMemcpyAsync(p->scale + 3 * o, dyn->scale, 12 * p->nd, hipMemcpyDeviceToDevice, st) != hipSuccess ||
             hipMemcpyAsync(p->rot + 4 * o, dyn->rot, 16 * p->nd, hipMemcpyDeviceToDevice, st) != hipSuccess ||
@@ -400,7 +440,7 @@ dgsm_status enqueue_run(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* t
     s = DGSM_OK;
     for (int f = 0; f < p->frames && s == DGSM_OK; ++f) {
         const int c = f % p->chains;
-        s = enqueue_frame(p, f, c, dyn->mean, translations, T_out, p->tile_waves, p->split_units, cs[c]);
+        s = enqueue_frame(p, f, c, dyn, translations, T_out, p->tile_waves, p->split_units, p->pack, cs[c]);
     }
     // join: the caller's stream waits for every chain (also after a failed
     // enqueue, so that a capture never ends with a stream left forked)
@@ -417,12 +457,13 @@ dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* tran
                      hipStream_t st) {
     const int waves[3] = {2, 4, 8};
     const int units[4] = {-1, 8192, 32768, 131072};
+    const int npack = p->cache ? 2 : 1;   // the packed walk is a candidate for the dynamic accumulation
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DGSM_EHIP;
     dgsm_status s = DGSM_OK;
     float best = 1e30f;
-    int best_nw = kDefaultTileWaves, best_units = kDefaultSplitUnits;
-    if (p->nd > 0) {
+    int best_nw = kDefaultTileWaves, best_units = kDefaultSplitUnits, best_pack = 0;
+    if (p->nd > 0 && p->motion == DGSM_MOTION_RIGID) {
         const int64_t o = p->ns;
         (void)hipMemcpyAsync(p->scale + 3 * o, dyn->scale, 12 * p->nd, hipMemcpyDeviceToDevice, st);
         (void)hipMemcpyAsync(p->rot + 4 * o, dyn->rot, 16 * p->nd, hipMemcpyDeviceToDevice, st);
@@ -430,10 +471,10 @@ dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* tran
     }
     if (p->cache) s = enqueue_static(p, kDefaultTileWaves, kDefaultSplitUnits, st);
     for (int rep = 0; rep < 2 && s == DGSM_OK; ++rep)   // first pass warms up
-        for (int c = 0; c < 12 && s == DGSM_OK; ++c) {
-            const int nw = waves[c % 3], nu = units[c / 3];
+        for (int c = 0; c < 12 * npack && s == DGSM_OK; ++c) {
+            const int nw = waves[c % 3], nu = units[(c / 3) % 4], pk = c / 12;
             (void)hipEventRecord(e0, st);
-            s = enqueue_frame(p, 0, 0, dyn->mean, translations, T_out, nw, nu, st);
+            s = enqueue_frame(p, 0, 0, dyn, translations, T_out, nw, nu, pk, st);
             (void)hipEventRecord(e1, st);
             if (hipEventSynchronize(e1) != hipSuccess) s = DGSM_EHIP;
             float ms = 0.f;
@@ -442,12 +483,14 @@ dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* tran
                 best = ms;
                 best_nw = nw;
                 best_units = nu;
+                best_pack = pk;
             }
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->tile_waves = best_nw;
     p->split_units = best_units;
+    p->pack = best_pack;
     p->tuned = true;
     return s;
 }
@@ -477,6 +520,26 @@ dgsm_status sort_static(dgsm_plan p, const dgsm_gaussians_t& src) {
     return ok ? DGSM_OK : DGSM_EHIP;
 }
 
+// List entries the static set (in plan order) needs per light, the maximum
+// over lights; a binning on a temporary minimal workspace; synchronous.
+dgsm_status count_static_entries(dgsm_plan p, int64_t& entries) {
+    entries = 0;
+    if (p->ns == 0) return DGSM_OK;
+    const BuildLayout Lc = build_layout(p->g, p->ns, p->L, 64 * (int64_t)p->g.S);
+    unsigned char* ws = nullptr;
+    if (dalloc(&ws, Lc.total) != hipSuccess) return DGSM_EHIP;
+    const dgsm_lights_t lt{p->lights, p->L, p->kappa, p->beta_mode};
+    dgsm_status s = enqueue_bin(p->g, Lc, ws, lt, p->desc.cull_eps, set_of(p, p->mean, 0, p->ns), nullptr, true);
+    std::vector<int> need(2 * (size_t)p->L, 0);
+    for (int l = 0; l < p->L && s == DGSM_OK; ++l)
+        if (hipMemcpy(&need[2 * l], light_ws(ws, Lc, l).need, 2 * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+            s = DGSM_EHIP;
+    if (s == DGSM_OK && hipDeviceSynchronize() != hipSuccess) s = DGSM_EHIP;
+    (void)hipFree(ws);
+    for (int l = 0; l < p->L; ++l) entries = need[2 * l] > entries ? need[2 * l] : entries;
+    return s;
+}
+
 }  // namespace
 
 extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_atlas_desc_t* desc,
@@ -489,6 +552,16 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     if ((st = validate_lights(lights)) != DGSM_OK) return st;
     if ((st = validate_gaussians(static_set)) != DGSM_OK) return st;
     if (n_dynamic < 0 || opts->frames < 1) return DGSM_EINVAL;
+    if (opts->chains < 0 || opts->chains > kMaxChains) return DGSM_EINVAL;
+    if (opts->motion != DGSM_MOTION_RIGID && opts->motion != DGSM_MOTION_FREE) return DGSM_EINVAL;
+    const int groups = opts->groups > 1 ? opts->groups : 1;
+    if (opts->groups < 0 || groups > 65535) return DGSM_EINVAL;
+    if (groups > 1) {   // ascending offsets covering the dynamic set
+        if (!opts->group_start || opts->group_start[0] != 0 || opts->group_start[groups] != n_dynamic)
+            return DGSM_EINVAL;
+        for (int i = 0; i < groups; ++i)
+            if (opts->group_start[i + 1] < opts->group_start[i]) return DGSM_EINVAL;
+    }
     const int64_t np = static_set->n + n_dynamic;
     const Geom g = make_geom(*desc);
     if (np >= INT32_MAX || (np + 64) * (int64_t)g.S >= (int64_t)INT32_MAX) return DGSM_EUNSUPPORTED;
@@ -507,21 +580,32 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     p->autotune = opts->autotune;
     p->tile_waves = (opts->tile_waves == 2 || opts->tile_waves == 4) ? opts->tile_waves : kDefaultTileWaves;
     p->split_units = opts->split_units == 0 ? kDefaultSplitUnits : (opts->split_units < 0 ? -1 : opts->split_units);
+    p->motion = opts->motion;
+    p->pack = p->cache && opts->packed ? 1 : 0;
+    p->groups = groups;
     const size_t elem = desc->dtype == DGSM_F16 ? 2 : 4;
     const size_t table = (size_t)p->L * g.K * plane_elems(g, true);   // plan-internal: tile-major planes
-    p->ws_a_bytes = build_layout(g, p->cache ? p->ns : np, p->L).total;
-    p->ws_b_bytes = p->cache ? build_layout(g, p->nd, p->L).total : 0;
+    p->lay_b = build_layout(g, p->nd, p->L);
+    p->ws_b_bytes = p->cache ? p->lay_b.total : 0;
     bool ok = dalloc(&p->lights, 12 * (size_t)p->L) == hipSuccess && dalloc(&p->mean, 12 * (size_t)np) == hipSuccess &&
               dalloc(&p->scale, 12 * (size_t)np) == hipSuccess && dalloc(&p->rot, 16 * (size_t)np) == hipSuccess &&
               dalloc(&p->opacity, 4 * (size_t)np) == hipSuccess && dalloc(&p->out_index, 4 * (size_t)np) == hipSuccess &&
               dalloc(&p->in_pos, 4 * (size_t)np) == hipSuccess &&
               dalloc(&p->tq, 4 * (size_t)np * p->L) == hipSuccess &&
               dalloc(&p->atlas, table * elem) == hipSuccess &&
-              dalloc(&p->ws_a, p->ws_a_bytes) == hipSuccess &&
               (!p->cache || (dalloc(&p->tau_static, table * 4) == hipSuccess &&
                              dalloc(&p->atlas_static, table * elem) == hipSuccess &&
                              dalloc(&p->ws_b, p->ws_b_bytes) == hipSuccess));
+    if (ok && groups > 1) {
+        ok = dalloc(&p->group, 2 * (size_t)p->nd) == hipSuccess;
+        for (int i = 0; i < groups && ok; ++i) {
+            const int64_t a = opts->group_start[i], b = opts->group_start[i + 1];
+            if (b > a) group_index_kernel<<<(unsigned)((b - a + 255) / 256), 256>>>(p->group, a, b, i);
+            ok = hipGetLastError() == hipSuccess;
+        }
+    }
     p->chains = p->cache ? (p->frames < kMaxChains ? p->frames : kMaxChains) : 1;
+    if (p->cache && opts->chains > 0 && opts->chains < p->chains) p->chains = opts->chains;
     p->cmean[0] = p->mean;
     p->ctq[0] = p->tq;
     p->catlas[0] = p->atlas;
@@ -535,12 +619,27 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     ok = ok && (p->chains < 2 || hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) == hipSuccess);
     const int64_t n = p->ns;
     ok = ok && hipMemcpy(p->lights, lights->pos, 12 * (size_t)p->L, hipMemcpyDeviceToDevice) == hipSuccess;
-    // the atlas cones never change: computed once into each workspace
-    ok = ok && enqueue_cones(g, build_layout(g, p->cache ? p->ns : np, p->L), p->ws_a, nullptr) == DGSM_OK;
-    for (int c = 0; c < p->chains && ok && p->cache; ++c)
-        ok = enqueue_cones(g, build_layout(g, p->nd, p->L), p->cws[c], nullptr) == DGSM_OK;
     ok = ok && hipDeviceSynchronize() == hipSuccess;
     if (ok && n > 0) ok = sort_static(p, *static_set) == DGSM_OK;
+    // The static set never changes, so its list entries are counted once here
+    // and its workspace holds exactly them (the worst case, every Gaussian in
+    // every supertile list, is far larger).  Without the cache the lists hold
+    // the static entries plus the dynamic set's worst case.
+    if (ok) {
+        int64_t entries = 0;
+        ok = count_static_entries(p, entries) == DGSM_OK;
+        const int64_t worst = ((p->cache ? p->ns : np) + 64) * (int64_t)g.S;
+        int64_t cap = p->cache ? entries : entries + (p->nd + 64) * (int64_t)g.S;
+        cap = cap < worst ? cap : worst;
+        cap = cap > 64 * (int64_t)g.S ? cap : 64 * (int64_t)g.S;
+        p->lay_a = build_layout(g, p->cache ? p->ns : np, p->L, cap);
+        p->ws_a_bytes = p->lay_a.total;
+        ok = ok && dalloc(&p->ws_a, p->ws_a_bytes) == hipSuccess;
+    }
+    // the atlas cones never change: computed once into each workspace
+    ok = ok && enqueue_cones(g, p->lay_a, p->ws_a, nullptr) == DGSM_OK;
+    for (int c = 0; c < p->chains && ok && p->cache; ++c) ok = enqueue_cones(g, p->lay_b, p->cws[c], nullptr) == DGSM_OK;
+    ok = ok && hipDeviceSynchronize() == hipSuccess;
     // every chain's means start with the static set in plan order
     for (int c = 1; c < p->chains && ok && n > 0; ++c)
         ok = hipMemcpy(p->cmean[c], p->mean, 12 * (size_t)n, hipMemcpyDeviceToDevice) == hipSuccess;
@@ -562,7 +661,8 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
 
 extern "C" dgsm_status dgsm_plan_run(dgsm_plan p, const dgsm_gaussians_t* dynamic_set, const float* translations,
                                      float* T_out, int32_t use_graph, void* stream) {
-    if (!p || !dynamic_set || !T_out || (p->frames > 0 && !translations)) return DGSM_EINVAL;
+    if (!p || !dynamic_set || !T_out) return DGSM_EINVAL;
+    if (p->motion == DGSM_MOTION_RIGID && p->nd > 0 && !translations) return DGSM_EINVAL;
     if (dynamic_set->n != p->nd) return DGSM_EINVAL;
     dgsm_status st = validate_gaussians(dynamic_set);
     if (st != DGSM_OK) return st;
@@ -601,6 +701,8 @@ extern "C" dgsm_status dgsm_plan_run(dgsm_plan p, const dgsm_gaussians_t* dynami
 extern "C" int32_t dgsm_plan_tile_waves(const dgsm_plan p) { return p ? p->tile_waves : 0; }
 
 extern "C" int32_t dgsm_plan_split_units(const dgsm_plan p) { return p ? p->split_units : 0; }
+
+extern "C" int32_t dgsm_plan_packed(const dgsm_plan p) { return p ? p->pack : 0; }
 
 extern "C" dgsm_status dgsm_plan_destroy(dgsm_plan p) {
     if (!p) return DGSM_EINVAL;

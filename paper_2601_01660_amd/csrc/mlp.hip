@@ -9,6 +9,8 @@
 //
 // Kernels (rows = samples or query points):
 //   sample_kernel   training / held-out samples from one light's atlas
+//   grid_sample_kernel check samples at every texel centre x shell and
+//                   uniformly inside every fallback region
 //   fwd_kernel      features + 4 MFMA layers (weights in LDS) + output;
 //                   modes: train (stashes activations for the backward) and
 //                   check (flags regions where |T - T_atlas| > thr)
@@ -21,6 +23,8 @@
 // MFMA: v_mfma_f32_16x16x32_bf16.  A (16x32): lane l holds row l%16,
 // k = 8(l/16)..+7; B (32x16): lane l holds column l%16, k = 8(l/16)..+7;
 // D (16x16): lane l holds column l%16, rows 4(l/16)..+3.
+
+#include <algorithm>
 
 #include "dgsm_device.hpp"
 #include "dgsm_host.hpp"
@@ -46,30 +50,45 @@ __device__ inline int swz(int r, int c) { return r * 16 + (c ^ (r & 15)); }
 
 __device__ inline __bf16 to_bf16(float x) { return (__bf16)x; }   // round to nearest even
 
-__device__ inline float hw_sin(float x) { return __sinf(x); }
-__device__ inline float hw_cos(float x) { return __cosf(x); }
+// Fourier features.  sin(f_i x) and cos(f_i x) with f_i = pi (W/4)^(i/15) are
+// taken from the phase in turns, ph = c_i x with c_i = (W/4)^(i/15) / 2, formed
+// in FP64 and reduced exactly to [-1/2, 1/2] (ph - rint(ph)), so the sine
+// argument never carries the rounding of a large FP32 product (at W = 512 the
+// phase reaches 64 turns).  Training, gradients and checks evaluate the sine of
+// the reduced phase in FP64 (rounded once to FP32, then to BF16 where it enters
+// the matrix units); inference evaluates it in FP32 (error about 1e-7).
+__device__ inline double turns_per_unit(int i, int W) { return 0.5 * pow(0.25 * (double)W, (double)i / 15.0); }
 
-// Feature f (0..127) of a row.
-__device__ inline float feature(int f, float u, float v, float rho, float fscale) {
-    if (f == 0) return u;
-    if (f == 1) return v;
-    if (f == 2) return rho;
-    if (f >= kDin) return 0.f;
-    const int q = f - 3, i = q / 6, rem = q - 6 * i;
-    const float x = rem < 2 ? u : rem < 4 ? v : rho;
-    const float fr = 3.14159265358979324f * exp2f(fscale * (float)i);   // pi (W/4)^(i/15)
-    return (rem & 1) ? hw_cos(fr * x) : hw_sin(fr * x);
+__device__ inline float fourier_exact(double c, float x, bool cosine) {
+    const double ph = c * (double)x;
+    const double r = ph - rint(ph);
+    double s, co;
+    sincospi(2.0 * r, &s, &co);
+    return (float)(cosine ? co : s);
 }
 
-// Feature f (0..127) with the frequencies given (fr[i] = pi (W/4)^(i/15)).
-__device__ inline float feature_fr(int f, float u, float v, float rho, const float* fr) {
+__device__ inline void fourier_pair(double c, double x, float& s, float& co) {
+    const double ph = c * x;
+    const double r = ph - rint(ph);
+#ifdef DGSM_MLP_FAST_SINES
+    sincospif(2.f * (float)r, &s, &co);
+#else
+    double sd, cd;
+    sincospi(2.0 * r, &sd, &cd);
+    s = (float)sd;
+    co = (float)cd;
+#endif
+}
+
+// Feature f (0..127) of a row; ct[i] = turns_per_unit(i, W).
+__device__ inline float feature(int f, float u, float v, float rho, const double* ct) {
     if (f == 0) return u;
     if (f == 1) return v;
     if (f == 2) return rho;
     if (f >= kDin) return 0.f;
     const int q = f - 3, i = q / 6, rem = q - 6 * i;
     const float x = rem < 2 ? u : rem < 4 ? v : rho;
-    return (rem & 1) ? hw_cos(fr[i] * x) : hw_sin(fr[i] * x);
+    return fourier_exact(ct[i], x, rem & 1);
 }
 
 // Octahedral code and radius coordinate of a point seen from a light.
@@ -93,6 +112,30 @@ __device__ inline void encode_point(float x, float y, float z, const float* o, c
     else
         rho = 2.f * r / g.r1 - 1.f;
     rho = fminf(fmaxf(rho, -1.f), 1.f);   // log2(0) = -inf clamps to -1
+}
+
+// The same code in FP64, for the inference features: the offset of the FP32
+// point from the FP32 light is exact in FP64, and (u, v, rho) reach the phase
+// of the Fourier features without an FP32 rounding.
+__device__ inline void encode_point_f64(float x, float y, float z, const float* o, const Geom& g, double& u,
+                                        double& v, double& rho) {
+    const double dx = (double)x - (double)o[0], dy = (double)y - (double)o[1], dz = (double)z - (double)o[2];
+    const double l1 = fabs(dx) + fabs(dy) + fabs(dz);
+    double qx = 0.0, qy = 0.0, qz = 1.0;
+    if (l1 > 0.0) {
+        qx = dx / l1; qy = dy / l1; qz = dz / l1;
+    }
+    u = qx; v = qy;
+    if (qz < 0.0) {
+        u = copysign(1.0 - fabs(qy), qx >= 0.0 ? 1.0 : -1.0);
+        v = copysign(1.0 - fabs(qx), qy >= 0.0 ? 1.0 : -1.0);
+    }
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (g.spacing == DGSM_SHELLS_GEOMETRIC)
+        rho = r > 0.0 ? 2.0 * log(r / (double)g.r0) / log((double)g.r1 / (double)g.r0) - 1.0 : -1.0;
+    else
+        rho = 2.0 * r / (double)g.r1 - 1.0;
+    rho = fmin(fmax(rho, -1.0), 1.0);
 }
 
 __device__ inline int wrap_off(int i, int j, int H, int W) {
@@ -181,6 +224,53 @@ __global__ __launch_bounds__(256) void sample_kernel(const InT* __restrict__ tab
     out[i] = make_float4(u, v, rho, atlas_at(tab, g, u, v, rho, region));
 }
 
+// Radius coordinate of shell k (its radius on the atlas's radial axis).
+__device__ inline float shell_rho(const Geom& g, float kf) {
+    return g.spacing == DGSM_SHELLS_GEOMETRIC ? 2.f * kf / (float)(g.K - 1) - 1.f
+                                              : (2.f * kf + 1.f) / (float)g.K - 1.f;
+}
+
+// Check samples covering the whole atlas domain, rows [row_begin, row_begin + n)
+// of a fixed enumeration: rows [0, H W K) are every texel centre at every shell
+// radius with the stored value as target (row = (k H + i) W + j); the next
+// regions * n_per rows are n_per points drawn uniformly in each fallback
+// region's domain -- the continuous (row, column, shell) coordinates whose
+// trilinear cell the region holds -- with trilinear targets.
+template <typename InT>
+__global__ __launch_bounds__(256) void grid_sample_kernel(const InT* __restrict__ tab, Geom g, int64_t row_begin,
+                                                          int64_t n, int n_per, uint32_t seed,
+                                                          float4* __restrict__ out) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    const int64_t row = row_begin + q;
+    const int64_t plane = (int64_t)g.H * g.W, ngrid = plane * g.K;
+    if (row < ngrid) {
+        const int k = (int)(row / plane);
+        const int64_t rem = row - (int64_t)k * plane;
+        const int i = (int)(rem / g.W), j = (int)(rem - (int64_t)i * g.W);
+        out[q] = make_float4(-1.f + (2.f * j + 1.f) / (float)g.W, -1.f + (2.f * i + 1.f) / (float)g.H,
+                             shell_rho(g, (float)k), Store<InT>::get(tab + row));
+        return;
+    }
+    const int64_t s = row - ngrid;
+    const int64_t reg = s / n_per;
+    const int kk = (int)(reg / g.ntiles), tt = (int)(reg - (int64_t)kk * g.ntiles);
+    const int ti = tt / g.TW, tj = tt - ti * g.TW;
+    const uint32_t base = pcg_hash(seed ^ pcg_hash((uint32_t)s ^ pcg_hash((uint32_t)(s >> 32) + 0x632BE5ABu)));
+    const float r1 = u01(pcg_hash(base)), r2 = u01(pcg_hash(base + 1u)), r3 = u01(pcg_hash(base + 2u));
+    // floor cells of the region: rows 8 ti .. 8 ti + 7 (the first tile also holds
+    // i_f in [-1/2, 0), the last ends at H - 1/2), likewise columns; shells
+    // 8 kk .. 8 kk + 7 with k_f up to K - 1 in the last group
+    const float ilo = ti == 0 ? -0.5f : 8.f * ti, ihi = fminf(8.f * ti + 8.f, (float)g.H - 0.5f);
+    const float jlo = tj == 0 ? -0.5f : 8.f * tj, jhi = fminf(8.f * tj + 8.f, (float)g.W - 0.5f);
+    const float klo = 8.f * kk, khi = fminf(8.f * kk + 8.f, (float)(g.K - 1));
+    const float fi = ilo + r1 * (ihi - ilo), fj = jlo + r2 * (jhi - jlo), fk = klo + r3 * fmaxf(khi - klo, 0.f);
+    const float u = 2.f * (fj + 0.5f) / (float)g.W - 1.f, v = 2.f * (fi + 0.5f) / (float)g.H - 1.f;
+    const float rho = shell_rho(g, fk);
+    int region;
+    out[q] = make_float4(u, v, rho, atlas_at(tab, g, u, v, rho, region));
+}
+
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
@@ -209,6 +299,9 @@ struct FwdArgs {
     float* lossp;              // [n/16]
     float inv_n;               // 1 / batch
     int atlas_f16;
+    // check: global index of row 0, and rows below n_grid are texel-centre nodes
+    int64_t row_offset;
+    int64_t n_grid;
 };
 
 // Lanes 0..15 hold the inputs of the wave's 16 rows; any lane reads row r's
@@ -227,7 +320,9 @@ __global__ __launch_bounds__(kWave * NWV) void fwd_kernel(FwdArgs a) {
     constexpr int kTile = kRows * NWV;
     bf16x8* wl = reinterpret_cast<bf16x8*>(smem);                        // [4][128 rows][16 chunks]
     bf16x8* act = wl + 4 * kH * 16;                                     // [NWV waves][16 rows][16 chunks]
+    __shared__ double cturn[kNF];
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    if (tid < kNF) cturn[tid] = turns_per_unit(tid, a.g.W);
     const int light = blockIdx.y;
     const float* P = a.params + (size_t)light * kNParams;
     const __bf16* Wg = a.wb + (size_t)light * 4 * kH * kH;
@@ -238,7 +333,6 @@ __global__ __launch_bounds__(kWave * NWV) void fwd_kernel(FwdArgs a) {
     }
     __syncthreads();
     bf16x8* my = act + wave * kRows * 16;
-    const float fscale = __log2f(0.25f * (float)a.g.W) / 15.f;
     const int ntile = (int)((a.n + kTile - 1) / kTile);
     const int lr = lane % 16, lg = lane / 16;
     for (int t = blockIdx.x; t < ntile; t += gridDim.x) {
@@ -257,7 +351,7 @@ __global__ __launch_bounds__(kWave * NWV) void fwd_kernel(FwdArgs a) {
             for (int q = 0; q < 4; ++q) {
                 const int c = lg + 4 * q;
                 bf16x8 ch;
-                for (int e = 0; e < 8; ++e) ch[e] = to_bf16(feature(8 * c + e, in.x, in.y, in.z, fscale));
+                for (int e = 0; e < 8; ++e) ch[e] = to_bf16(feature(8 * c + e, in.x, in.y, in.z, cturn));
                 my[swz(lr, c)] = ch;
                 if (MODE == kTrain && row0 + lr < a.n)
                     for (int e = 0; e < 8; ++e) a.xt[(size_t)(8 * c + e) * a.n + row0 + lr] = ch[e];
@@ -352,10 +446,27 @@ __global__ __launch_bounds__(kWave * NWV) void fwd_kernel(FwdArgs a) {
             const int64_t row = row0 + rr;
             const float t = (lr & 3) == 0 ? T[0] : (lr & 3) == 1 ? T[1] : (lr & 3) == 2 ? T[2] : T[3];
             if (lr < 4 && row < a.n) {
-                const int region = atlas_region(a.g, in.x, in.y, in.z);
                 const float err = fabsf(t - in.w);
                 if (err > a.thresh) {
-                    a.mask_out[region] = 1;
+                    const int64_t grow = a.row_offset + row;
+                    if (grow < a.n_grid) {
+                        // a texel-centre node (row = (k H + i) W + j) is a corner of the
+                        // cells (i - 1 or i, j - 1 or j, k - 1 or k): flag all their regions
+                        const int64_t plane = (int64_t)a.g.H * a.g.W;
+                        const int k = (int)(grow / plane);
+                        const int64_t rem = grow - (int64_t)k * plane;
+                        const int i = (int)(rem / a.g.W), j = (int)(rem - (int64_t)i * a.g.W);
+                        for (int dk = -1; dk <= 0; ++dk)
+                            for (int di = -1; di <= 0; ++di)
+                                for (int dj = -1; dj <= 0; ++dj) {
+                                    const int kc = min(max(k + dk, 0), a.g.K - 2);
+                                    const int ic = max(i + di, 0), jc = max(j + dj, 0);
+                                    a.mask_out[(kc / 8) * a.g.ntiles + (ic / ::dgsm::kTile) * a.g.TW +
+                                               jc / ::dgsm::kTile] = 1;
+                                }
+                    } else {
+                        a.mask_out[atlas_region(a.g, in.x, in.y, in.z)] = 1;
+                    }
                     atomicAdd(a.check_stats, 1u);
                 }
                 atomicMax(a.check_stats + 1, __float_as_uint(err));
@@ -386,8 +497,8 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
     __shared__ float4 btab[4][kH / 4];            // biases of the four layers
     __shared__ float w4t[kH];
     __shared__ float zpart[kIRows][kIW];
-    __shared__ float4 rin[kIRows];
-    __shared__ float freq[kNF];
+    __shared__ double3 rin[kIRows];
+    __shared__ double cturn[kNF];
     const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
     const int light = blockIdx.y;
     const float* P = a.params + (size_t)light * kNParams;
@@ -415,8 +526,7 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
         (&feat[0][0])[q] = z;
     }
     const float b4 = P[kOffB4];
-    const float fscale = __log2f(0.25f * (float)a.g.W) / 15.f;
-    if (tid < kNF) freq[tid] = 3.14159265358979324f * exp2f(fscale * (float)tid);   // pi (W/4)^(i/15)
+    if (tid < kNF) cturn[tid] = turns_per_unit(tid, a.g.W);
     const int64_t ntile = (a.n + kIRows - 1) / kIRows;
     // the next tile's points are loaded one iteration ahead (threads tid < kIRows)
     float px = 0.f, py = 0.f, pz = 0.f;
@@ -434,11 +544,8 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
     for (int64_t t = blockIdx.x; t < ntile; t += gridDim.x) {
         const int64_t row0 = t * kIRows;
         if (tid < kIRows) {
-            float4 in = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (row0 + tid < a.n) {
-                float r;
-                encode_point(px, py, pz, a.lights + 3 * light, a.g, in.x, in.y, in.z, r);
-            }
+            double3 in = make_double3(0.0, 0.0, 0.0);
+            if (row0 + tid < a.n) encode_point_f64(px, py, pz, a.lights + 3 * light, a.g, in.x, in.y, in.z);
             rin[tid] = in;
         }
         load_pt(t + gridDim.x);
@@ -448,22 +555,26 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
         for (int h = 0; h < 2; ++h) {
             const int pr = tid + h * kWave * kIW;
             const int smp = pr / kNF, i = pr % kNF;
-            const float4 in = rin[smp];
+            const double3 in = rin[smp];
             __bf16* rowp = fe + (size_t)(smp / kRows) * kRows * 16 * 8;
             const int r = smp % kRows;
             auto put = [&](int f, float v) { rowp[swz(r, f / 8) * 8 + (f % 8)] = to_bf16(v); };
             if (i == 0) {
-                put(0, in.x);
-                put(1, in.y);
-                put(2, in.z);
+                put(0, (float)in.x);
+                put(1, (float)in.y);
+                put(2, (float)in.z);
             }
-            const float fr = freq[i];
-            put(3 + 6 * i, hw_sin(fr * in.x));
-            put(4 + 6 * i, hw_cos(fr * in.x));
-            put(5 + 6 * i, hw_sin(fr * in.y));
-            put(6 + 6 * i, hw_cos(fr * in.y));
-            put(7 + 6 * i, hw_sin(fr * in.z));
-            put(8 + 6 * i, hw_cos(fr * in.z));
+            const double c = cturn[i];
+            float sn, cs;
+            fourier_pair(c, in.x, sn, cs);
+            put(3 + 6 * i, sn);
+            put(4 + 6 * i, cs);
+            fourier_pair(c, in.y, sn, cs);
+            put(5 + 6 * i, sn);
+            put(6 + 6 * i, cs);
+            fourier_pair(c, in.z, sn, cs);
+            put(7 + 6 * i, sn);
+            put(8 + 6 * i, cs);
         }
         __syncthreads();
         f32x4 acc[kIRB][2];
@@ -958,6 +1069,58 @@ extern "C" dgsm_status dgsm_mlp_check(const float* params, const dgsm_atlas_desc
     f.mask_out = mask; f.thresh = thresh; f.check_stats = stats; f.atlas_f16 = desc->dtype == DGSM_F16;
     fwd_kernel<kCheck, kWaves><<<dim3(grid_rows(n_check), 1), kWave * kWaves, kFwdSmem, s>>>(f);
     return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
+}
+
+namespace {
+constexpr int64_t kGridChunk = int64_t(1) << 22;   // check rows staged per pass
+
+int64_t grid_rows_total(const dgsm_atlas_desc_t* d, int32_t n_per) {
+    const Geom g = make_geom(*d);
+    const int64_t regions = (int64_t)((g.K + 7) / 8) * g.ntiles;
+    return (int64_t)g.H * g.W * g.K + regions * n_per;
+}
+}  // namespace
+
+extern "C" size_t dgsm_mlp_check_grid_workspace_size(const dgsm_atlas_desc_t* desc, int32_t n_per_region) {
+    if (validate_mlp_desc(desc) != DGSM_OK || n_per_region < 0) return 0;
+    const int64_t rows = std::min(grid_rows_total(desc, n_per_region), kGridChunk);
+    return dgsm_mlp_infer_workspace_size(1) + ((sizeof(float4) * (size_t)rows + 255) & ~(size_t)255);
+}
+
+extern "C" dgsm_status dgsm_mlp_check_grid(const float* params, const dgsm_atlas_desc_t* desc, const void* atlas_l,
+                                           int32_t n_per_region, uint32_t seed, float thresh, unsigned char* mask,
+                                           unsigned int* stats, void* ws, size_t ws_bytes, void* stream) {
+    dgsm_status st = validate_mlp_desc(desc);
+    if (st != DGSM_OK) return st;
+    if (!params || !atlas_l || !mask || !stats || n_per_region < 0) return DGSM_EINVAL;
+    const size_t need = dgsm_mlp_check_grid_workspace_size(desc, n_per_region);
+    if (!ws || ws_bytes < need) return DGSM_EWORKSPACE;
+    if (set_smem() != hipSuccess) return DGSM_EHIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Geom g = geom_of(desc);
+    __bf16* wb = reinterpret_cast<__bf16*>(ws);
+    float4* uvrt = reinterpret_cast<float4*>(reinterpret_cast<unsigned char*>(ws) + dgsm_mlp_infer_workspace_size(1));
+    to_bf16_kernel<<<(4 * kH * kH + 255) / 256, 256, 0, s>>>(params, 1, wb);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    const int64_t total = grid_rows_total(desc, n_per_region);
+    for (int64_t r0 = 0; r0 < total; r0 += kGridChunk) {
+        const int64_t n = std::min(kGridChunk, total - r0);
+        const unsigned blocks = (unsigned)((n + 255) / 256);
+        if (desc->dtype == DGSM_F16)
+            grid_sample_kernel<__half><<<blocks, 256, 0, s>>>(reinterpret_cast<const __half*>(atlas_l), g, r0, n,
+                                                             n_per_region > 0 ? n_per_region : 1, seed, uvrt);
+        else
+            grid_sample_kernel<float><<<blocks, 256, 0, s>>>(reinterpret_cast<const float*>(atlas_l), g, r0, n,
+                                                            n_per_region > 0 ? n_per_region : 1, seed, uvrt);
+        FwdArgs f{};
+        f.g = g; f.params = params; f.wb = wb; f.n = n; f.uvrt = uvrt; f.atlas = atlas_l;
+        f.mask_out = mask; f.thresh = thresh; f.check_stats = stats; f.atlas_f16 = desc->dtype == DGSM_F16;
+        f.row_offset = r0;
+        f.n_grid = (int64_t)g.H * g.W * g.K;
+        fwd_kernel<kCheck, kWaves><<<dim3(grid_rows(n), 1), kWave * kWaves, kFwdSmem, s>>>(f);
+        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    }
+    return DGSM_OK;
 }
 
 extern "C" dgsm_status dgsm_mlp_infer(const float* params, const dgsm_lights_t* lights,

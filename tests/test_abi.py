@@ -252,3 +252,72 @@ def test_sh_transfer_checks_probe_colour_and_centroid_shapes():
     for kp in (1, 4, 9, 16):        # accepted shapes get as far as the host-memory check
         with pytest.raises(ValueError, match="CUDA"):
             P.sh_transfer(torch.zeros(kp, 3), gs, colour_sh=torch.zeros(n, 16, 3), centroid=torch.zeros(3))
+
+
+def test_mlp_checkpoint_round_trip(lib, tmp_path):
+    """Parameters, Adam moments, step and atlas geometry survive a save/load
+    bit for bit; the header is the documented JSON line; a file without moments
+    cannot fill a request for them, and a foreign file is refused."""
+    import json
+
+    import numpy as np
+
+    import paper_2601_01660_amd as P
+    rng = np.random.default_rng(3)
+    params = torch.from_numpy(rng.standard_normal(P.MLP_PARAMS).astype(np.float32))
+    adam = torch.from_numpy(rng.standard_normal(2 * P.MLP_PARAMS).astype(np.float32))
+    atlas = P.Atlas(512, 384, 64, spacing="geometric", r0=0.05, r1=8.0)
+    path = str(tmp_path / "light0.dgsm")
+    P.mlp_save(path, params, atlas, adam_mv=adam, step=1500)
+    p2, m2, step, a2 = P.mlp_load(path)
+    assert torch.equal(p2, params) and torch.equal(m2, adam) and step == 1500
+    assert (a2.H, a2.W, a2.K, a2.spacing) == (512, 384, 64, "geometric")
+    assert a2.r0 == np.float32(0.05) and a2.r1 == np.float32(8.0)
+    with open(path, "rb") as f:
+        assert f.readline() == b"DGSM-MLP 1\n"
+        head = json.loads(f.readline())
+        body = f.read()
+    assert head["params"] == P.MLP_PARAMS and head["adam"] == 1 and head["step"] == 1500
+    assert len(body) == 3 * 4 * P.MLP_PARAMS
+    assert np.array_equal(np.frombuffer(body[:4 * P.MLP_PARAMS], "<f4"), params.numpy())
+    # parameters only
+    path2 = str(tmp_path / "light1.dgsm")
+    P.mlp_save(path2, params, atlas, step=7)
+    p3, m3, step3, _ = P.mlp_load(path2, adam=False)
+    assert torch.equal(p3, params) and m3 is None and step3 == 7
+    with pytest.raises(P.DGSMError):
+        P.mlp_load(path2, adam=True)
+    bad = tmp_path / "bad.dgsm"
+    bad.write_bytes(b"not a checkpoint\n{}\n")
+    with pytest.raises(P.DGSMError):
+        P.mlp_load(str(bad))
+    with pytest.raises(P.DGSMError):
+        P.mlp_load(str(tmp_path / "missing.dgsm"))
+
+
+def test_host_paths_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The library's host code (argument validation, workspace sizing,
+    checkpoint parsing) built with ASan and UBSan on the host pass only and
+    driven by tests/abi_sanitize.cpp: every invalid call returns its status
+    without a sanitizer report.  Device code is compiled as usual."""
+    import sys
+    hipcc = "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or torch.cuda.is_available():
+        pytest.skip("host-only sanitizer build (runs where hipcc is present and no GPU is visible)")
+    sys.path.insert(0, ROOT)
+    from paper_2601_01660_amd import build as b
+    exe = str(tmp_path / "abi_sanitize")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+    cmd = [hipcc, *b.HIPCC_FLAGS, *san, "-I", os.path.join(ROOT, "include"), "-I",
+           os.path.join(ROOT, "paper_2601_01660_amd", "csrc"), *b.sources(),
+           os.path.join(ROOT, "tests", "abi_sanitize.cpp"), "-o", exe]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 and "asan" in (r.stderr + r.stdout).lower() and "not found" in (r.stderr + r.stdout):
+        pytest.skip("sanitizer runtime not available")
+    assert r.returncode == 0, r.stderr[-3000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    r = subprocess.run([exe, str(tmp_path)], capture_output=True, text=True, env=env, timeout=300)
+    print(r.stdout[-2000:], r.stderr[-2000:])
+    assert r.returncode == 0, r.stderr[-3000:]
+    assert "ERROR: AddressSanitizer" not in r.stderr and "runtime error" not in r.stderr

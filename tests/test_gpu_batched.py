@@ -140,3 +140,87 @@ def test_plan_full_size_sampled_against_oracle():
         print(f"[batched] full size frame {f} light {l}: max|dT| {err:.3e} over {len(idx)} centres "
               f"(T from {ref.min():.3f} to {ref.max():.3f})")
         assert err <= 1e-2
+
+
+def _plain_sets(P, lights_h, frames_sets, atlas):
+    """Plain build + query of every frame's full Gaussian set (static first)."""
+    outs = []
+    lights = torch.from_numpy(lights_h).cuda()
+    for g in frames_sets:
+        gs = P.GaussianSet.from_host(g)
+        T = P.dgsm_build(lights, gs, atlas)
+        outs.append(P.dgsm_query(lights, atlas, T, gs.mean))
+    torch.cuda.synchronize()
+    return torch.stack(outs).cpu().numpy()
+
+
+def _graph_equals_eager(plan, dyn, tr, eager):
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = torch.empty_like(eager)
+        for _ in range(2):
+            plan.run(dyn, tr, out=out, use_graph=True)
+            s.synchronize()
+            assert torch.equal(out, eager)
+            out.zero_()
+            s.synchronize()
+
+
+@pytest.mark.parametrize("cache,chains", [(True, 0), (True, 1), (False, 0)])
+def test_plan_groups_on_their_own_trajectories(scene, cache, chains):
+    """Several avatars (groups of the dynamic set, one of them empty) moving on
+    independent trajectories: every frame equals a plain build + query of the
+    static set plus each group translated by its own step of its walk."""
+    import paper_2601_01660_amd as P
+    rng = np.random.default_rng(5)
+    sizes = [180, 0, 260, 60]
+    parts = [synth.random_gaussians(rng, rng.uniform(-0.2, 0.2, (n, 3)) + [0.5 * i - 0.7, 0.3, 1.0], 0.02)
+             for i, n in enumerate(sizes)]
+    F = 4
+    trajs = np.stack([synth.random_walk(np.random.default_rng(50 + i), F, step=0.12, start=(0.0, 0.0))
+                      for i in range(len(sizes))], axis=1).astype(np.float32)          # [F][G][3]
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    atlas = P.Atlas(48, 64, 16, dtype="f32")
+    frames_sets = [synth.Gaussians.concat([scene["static"]] + [p.translated(trajs[f, i]) for i, p in enumerate(parts)])
+                   for f in range(F)]
+    ref = _plain_sets(P, scene["lights"], frames_sets, atlas)
+    dyn_h = synth.Gaussians.concat(parts)
+    plan = P.Plan(torch.from_numpy(scene["lights"]), atlas, P.GaussianSet.from_host(scene["static"]), dyn_h.n, F,
+                  static_cache=cache, autotune=False, tile_waves=4, chains=chains, group_start=starts)
+    dyn = P.GaussianSet.from_host(dyn_h)
+    tr = torch.from_numpy(trajs).cuda()
+    eager = plan.run(dyn, tr, use_graph=False).clone()
+    torch.cuda.synchronize()
+    err = np.abs(eager.cpu().numpy() - ref).max()
+    print(f"[batched] {len(sizes)} groups, cache={cache} chains={chains}: max|dT| vs plain = {err:.3e}")
+    assert err <= 2e-6
+    _graph_equals_eager(plan, dyn, tr, eager)
+    plan.close()
+
+
+@pytest.mark.parametrize("cache", [True, False])
+def test_plan_free_motion_matches_plain(scene, cache):
+    """Free motion: every frame brings its own dynamic means, scales, rotations
+    and opacities (a re-skinned avatar); every frame equals a plain build +
+    query of the static set plus that frame's dynamic set."""
+    import paper_2601_01660_amd as P
+    F, n = 5, 400
+    rng = np.random.default_rng(9)
+    base = rng.uniform(-0.3, 0.3, (n, 3)) + [0.6, -0.2, 1.1]
+    frames_dyn = []
+    for f in range(F):
+        m = base + 0.08 * f * np.sin(np.arange(n)[:, None] * 0.37 + [0.0, 1.0, 2.0])   # non-rigid
+        frames_dyn.append(synth.random_gaussians(np.random.default_rng(100 + f), m, 0.02))
+    atlas = P.Atlas(48, 48, 16, dtype="f32")
+    ref = _plain_sets(P, scene["lights"], [synth.Gaussians.concat([scene["static"], d]) for d in frames_dyn], atlas)
+    stack = lambda f: torch.from_numpy(np.stack([getattr(d, f) for d in frames_dyn]).astype(np.float32)).cuda()
+    dyn = P.GaussianSet(stack("mean"), stack("scale"), stack("rot"), stack("opacity"))
+    plan = P.Plan(torch.from_numpy(scene["lights"]), atlas, P.GaussianSet.from_host(scene["static"]), n, F,
+                  static_cache=cache, autotune=False, tile_waves=8, motion="free")
+    eager = plan.run(dyn, None, use_graph=False).clone()
+    torch.cuda.synchronize()
+    err = np.abs(eager.cpu().numpy() - ref).max()
+    print(f"[batched] free motion, cache={cache}: max|dT| vs plain = {err:.3e}")
+    assert err <= 2e-6
+    _graph_equals_eager(plan, dyn, None, eager)
+    plan.close()

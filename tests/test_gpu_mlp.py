@@ -53,7 +53,7 @@ def test_gradient_matches_bf16_emulated_oracle(B):
         r, gv = np.atleast_1d(ref[k]), np.atleast_1d(got[k])
         rel = np.linalg.norm(gv - r) / max(np.linalg.norm(r), 1e-12)
         print(f"[mlp] B={B} grad {k}: rel err {rel:.2e}", flush=True)
-        assert rel <= 5e-3, k
+        assert rel <= 1e-4, k
 
 
 def test_forward_matches_oracle_at_points():
@@ -65,29 +65,40 @@ def test_forward_matches_oracle_at_points():
     light = np.array([[0.2, -0.1, 0.3]], np.float32)
     T = P.mlp_infer(torch.from_numpy(flat), torch.from_numpy(light), atlas, torch.from_numpy(pts))
     torch.cuda.synchronize()
-    u, v, rho = om.encode_points(pts, light[0], 0.05, 8.0)
+    # the atlas description carries r0, r1 in FP32
+    u, v, rho = om.encode_points(pts, light[0], float(np.float32(0.05)), float(np.float32(8.0)))
     ref, _ = om.forward(flat, om.features(u, v, rho, 64), bf16_emulation=True)
-    err = np.abs(T[0].cpu().numpy() - ref).max()
-    print(f"[mlp] forward max|dT| = {err:.2e}", flush=True)
-    assert err <= 2e-3
+    err = np.abs(T[0].cpu().numpy() - ref)
+    print(f"[mlp] forward max|dT| = {err.max():.2e}, median {np.median(err):.2e}, "
+          f"points above 1e-6: {int((err > 1e-6).sum())} of {err.size}", flush=True)
+    # A hidden activation whose FP32 sum lies within an FP32 ulp of a BF16
+    # rounding boundary can round the other way than the oracle's FP64 sum and
+    # move T of that point by up to ~1e-3 for these random networks (simulated
+    # with FP32 sums on the CPU: 2.6e-4 here); every other point agrees to FP32
+    # rounding.
+    assert err.max() <= 2e-3
+    assert (err <= 1e-6).mean() >= 0.99
 
 
 def test_training_fits_an_atlas_and_fallback_covers_the_rest():
     import paper_2601_01660_amd as P
-    # a smooth-ish shadow field: few large Gaussians around one light
+    # a smooth shadow field: a cluster of large Gaussians on one side of the
+    # light, so that part of the atlas is unshadowed
     rng = np.random.default_rng(5)
-    g = synth.random_gaussians(rng, rng.uniform(-2, 2, (60, 3)), 0.35)
+    g = synth.random_gaussians(rng, rng.uniform([0.6, -1.0, -1.0], [2.0, 1.0, 1.0], (30, 3)), 0.3)
     lights = np.array([[0.0, 0.0, 0.0]], np.float32)
     atlas = P.Atlas(64, 64, 32)
     table = P.dgsm_build(torch.from_numpy(lights), P.GaussianSet.from_host(g), atlas)
     params = torch.from_numpy(synth.mlp_init_params(6)).cuda()
     mv = torch.zeros(2 * om.N_PARAMS, device="cuda")
-    losses = P.mlp_train(params, mv, atlas, table[0], steps=600, batch=4096, lr0=2e-3, lr1=1e-4, seed=7)
+    losses = P.mlp_train(params, mv, atlas, table[0], steps=1000, batch=4096, lr0=2e-3, lr1=1e-4, seed=7)
     torch.cuda.synchronize()
     lh = losses.cpu().numpy()
     print(f"[mlp] loss first {lh[:10].mean():.3e} last {lh[-10:].mean():.3e}", flush=True)
     assert np.all(np.isfinite(lh)) and lh[-10:].mean() < 0.2 * lh[:10].mean()
-    mask, nbad, maxerr = P.mlp_check(params, atlas, table[0], n_check=65536, seed=99, thresh=1e-2)
+    # fallback regions from every texel centre x shell and 16 uniform points per region,
+    # flagged at half the 1e-2 bar so that points between the checked ones stay inside it
+    mask, nbad, maxerr = P.mlp_check_grid(params, atlas, table[0], n_per_region=16, seed=99, thresh=5e-3)
     pts = rng.uniform(-3, 3, (20000, 3)).astype(np.float32)
     Tq = P.dgsm_query(torch.from_numpy(lights), atlas, table, torch.from_numpy(pts))
     Ts = P.mlp_infer(params, torch.from_numpy(lights), atlas, torch.from_numpy(pts), table=table, mask=mask)
@@ -98,6 +109,8 @@ def test_training_fits_an_atlas_and_fallback_covers_the_rest():
     print(f"[mlp] held-out flagged {nbad}, max|dT| {maxerr:.3e}, regions {int(mask.sum())}/{mask.numel()}; "
           f"surrogate+fallback vs atlas max {e_fb:.3e}; raw network mean {e_raw:.3e}", flush=True)
     assert e_raw < 0.05
+    assert 0 < int(mask.sum()) < mask.numel()     # some regions fall back, some keep the network
+    assert e_fb <= 1e-2
 
 
 def test_surrogate_gain_over_equal_byte_atlas():
@@ -158,20 +171,102 @@ def test_inference_two_lights_with_fallback_mask():
     T = P.mlp_infer(torch.from_numpy(flat), torch.from_numpy(lights), atlas, torch.from_numpy(pts),
                     table=table, mask=torch.from_numpy(mask).cuda()).cpu().numpy()
     tab = table.cpu().numpy().astype(np.float64)
-    bad = 0
+    r0, r1 = float(np.float32(0.05)), float(np.float32(8.0))     # FP32 in the atlas description
     for l in range(2):
-        u, v, rho = om.encode_points(pts, lights[l], 0.05, 8.0)
+        u, v, rho = om.encode_points(pts, lights[l], r0, r1)
         net, _ = om.forward(flat[l], om.features(u, v, rho, W), bf16_emulation=True)
         at = od.query(tab[l], lights[l], pts)
         jf = np.clip((u + 1) * W / 2 - 0.5, -0.5, W - 0.5)
         i_f = np.clip((v + 1) * H / 2 - 0.5, -0.5, H - 0.5)
-        k0 = np.minimum(np.floor(np.clip((rho + 1) / 2 * (K - 1), 0, K - 1)), K - 2).astype(int)
+        kf = np.clip((rho + 1) / 2 * (K - 1), 0, K - 1)
+        k0 = np.minimum(np.floor(kf), K - 2).astype(int)
         ic = np.clip(np.floor(i_f).astype(int), 0, H - 1)
         jc = np.clip(np.floor(jf).astype(int), 0, W - 1)
         region = (k0 // 8) * ntiles + (ic // 8) * (W // 8) + jc // 8
-        ref = np.where(mask[l][region] != 0, at, net)
+        # within FP32 rounding of a region boundary (a multiple of 8 texels or
+        # shells) the kernel may take either region: either answer is valid there
+        def near8(x):
+            return np.abs(x - 8 * np.round(x / 8)) < 1e-4
+        edge = near8(jf) | near8(i_f) | near8(kf)
+        flagged = mask[l][region] != 0
+        ref = np.where(flagged, at, net)
         err = np.abs(T[l] - ref)
-        bad += int((err > 2e-3).sum())
-        print(f"[mlp] light {l}: flagged points {int((mask[l][region] != 0).sum())}, "
-              f"median |dT| {np.median(err):.2e}", flush=True)
-    assert bad <= 0.005 * 2 * len(pts)
+        other = np.minimum(np.abs(T[l] - at), np.abs(T[l] - net))
+        err = np.where(edge, other, err)
+        print(f"[mlp] light {l}: flagged points {int(flagged.sum())}, boundary points {int(edge.sum())}, "
+              f"max |dT| atlas {err[flagged].max():.2e}, network {err[~flagged].max():.2e}", flush=True)
+        # atlas points: FP32 trilinear vs FP64; network points: as in the forward test
+        assert np.all(err[flagged & ~edge] <= 2e-5)
+        assert np.all(err <= 2e-3) and (err[~flagged] <= 1e-6).mean() >= 0.99
+
+
+def test_grid_check_flags_every_texel_region_like_the_oracle():
+    """dgsm_mlp_check_grid with no extra points compares the network with the
+    table at every texel centre x shell.  The table is the oracle's network
+    (BF16-emulated FP64 forward) at the nodes, moved by 0.3 at a few random
+    nodes: the mask must hold exactly the regions of the cells those nodes are
+    corners of, and the largest miss must be the oracle's."""
+    import paper_2601_01660_amd as P
+    H, W, K = 32, 48, 24
+    atlas = P.Atlas(H, W, K)
+    rng = np.random.default_rng(41)
+    flat = _params(42, noise=0.02)
+    k, i, j = np.meshgrid(np.arange(K), np.arange(H), np.arange(W), indexing="ij")
+    k, i, j = k.ravel(), i.ravel(), j.ravel()
+    f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    u = f32(-1 + (2 * j + 1) / W)
+    v = f32(-1 + (2 * i + 1) / H)
+    rho = f32(2 * k / (K - 1) - 1)
+    Tn, _ = om.forward(flat, om.features(u, v, rho, W), bf16_emulation=True)
+    table = Tn.copy()
+    bad = rng.choice(table.size, 10, replace=False)
+    table[bad] = np.where(table[bad] > 0.5, table[bad] - 0.3, table[bad] + 0.3)
+    tab32 = torch.from_numpy(table.astype(np.float32).reshape(K, H, W)).cuda()
+    thresh = 0.05
+    mask, nbad, maxerr = P.mlp_check_grid(torch.from_numpy(flat), atlas, tab32, n_per_region=0, seed=1,
+                                          thresh=thresh)
+    err = np.abs(Tn - table.astype(np.float32))
+    nreg = P.mlp_regions(atlas)
+    want = np.zeros(nreg, bool)
+    for dk in (-1, 0):
+        for di in (-1, 0):
+            for dj in (-1, 0):
+                kc = np.clip(k[bad] + dk, 0, K - 2)
+                ic = np.maximum(i[bad] + di, 0)
+                jc = np.maximum(j[bad] + dj, 0)
+                want[(kc // 8) * ((H // 8) * (W // 8)) + (ic // 8) * (W // 8) + jc // 8] = True
+    got = mask.cpu().numpy().astype(bool)
+    print(f"[mlp] grid check: {int(got.sum())} of {nreg} regions flagged (oracle {int(want.sum())}); "
+          f"flagged nodes {nbad}, max|dT| {maxerr:.5f} vs oracle {err.max():.5f}; "
+          f"largest miss elsewhere {np.delete(err, bad).max():.2e}", flush=True)
+    assert 0 < want.sum() < nreg
+    assert np.array_equal(got, want)
+    assert nbad == len(bad)
+    assert abs(maxerr - err.max()) <= 1e-4
+
+
+def test_training_resumes_from_a_checkpoint(tmp_path):
+    """Adam training interrupted after 40 steps, saved, loaded and continued for
+    30 more (step0 = 40: the same sample stream and bias corrections) equals 70
+    uninterrupted steps bit for bit (constant learning rate)."""
+    import paper_2601_01660_amd as P
+    rng = np.random.default_rng(61)
+    g = synth.random_gaussians(rng, rng.uniform(-2, 2, (40, 3)), 0.3)
+    lights = np.zeros((1, 3), np.float32)
+    atlas = P.Atlas(32, 32, 16)
+    table = P.dgsm_build(torch.from_numpy(lights), P.GaussianSet.from_host(g), atlas)
+    p_full = torch.from_numpy(synth.mlp_init_params(62)).cuda()
+    mv_full = torch.zeros(2 * om.N_PARAMS, device="cuda")
+    P.mlp_train(p_full, mv_full, atlas, table[0], steps=70, batch=1024, lr0=1e-3, lr1=1e-3, seed=63)
+    p = torch.from_numpy(synth.mlp_init_params(62)).cuda()
+    mv = torch.zeros(2 * om.N_PARAMS, device="cuda")
+    P.mlp_train(p, mv, atlas, table[0], steps=40, batch=1024, lr0=1e-3, lr1=1e-3, seed=63)
+    torch.cuda.synchronize()
+    path = str(tmp_path / "ckpt.dgsm")
+    P.mlp_save(path, p, atlas, adam_mv=mv, step=40)
+    p2, mv2, step, a2 = P.mlp_load(path)
+    assert step == 40 and (a2.H, a2.W, a2.K) == (32, 32, 16)
+    p2, mv2 = p2.cuda(), mv2.cuda()
+    P.mlp_train(p2, mv2, a2, table[0], steps=30, step0=step, batch=1024, lr0=1e-3, lr1=1e-3, seed=63)
+    torch.cuda.synchronize()
+    assert torch.equal(p2, p_full) and torch.equal(mv2, mv_full)

@@ -79,3 +79,48 @@ def test_split_is_bitwise_unsplit(cluster, dtype, cache):
         plan.close()
     assert outs[0].min().item() < 0.5
     assert torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("spacing", ["geometric", "uniform"])
+def test_packed_walk_is_bitwise_the_tile_walk(cluster, dtype, spacing):
+    """The packed walk (only pairs past the distance pre-test, 64 per wave)
+    adds exactly the increments of the tile walk: the atlas is bitwise the same
+    for every tile width, with and without split tiles."""
+    import paper_2601_01660_amd as P
+    g = synth.Gaussians.concat([cluster["bg"], cluster["dense"]])
+    lights = torch.from_numpy(np.array([[0.1, -0.2, 1.6], [-1.0, 0.7, 1.2]], np.float32)).cuda()
+    atlas = P.Atlas(H, W, K, spacing=spacing, dtype=dtype)
+    gs = P.GaussianSet.from_host(g)
+    ws = torch.empty(P.dgsm_build_workspace_size(atlas, g.n, 2), dtype=torch.uint8, device="cuda")
+    P.dgsm_bin(lights, gs, atlas, ws)
+    ref = P.dgsm_accumulate(lights, atlas, g.n, torch.empty((2, K, H, W), dtype=atlas.torch_dtype,
+                                                          device="cuda"), ws)
+    for nw in (2, 4, 8):
+        for units in (-1, 0, 2000):
+            for packed in (False, True):
+                out = torch.empty_like(ref)
+                P.dgsm_accumulate_ex(lights, atlas, g.n, out, ws, tile_waves=nw, split_units=units, packed=packed)
+                torch.cuda.synchronize()
+                assert torch.equal(out, ref), (nw, units, packed)
+    assert ref.min().item() < 0.5
+    print(f"[split] packed walk bitwise equal to the tile walk ({spacing}, {dtype})", flush=True)
+
+
+@pytest.mark.parametrize("cache", [True, False])
+def test_plan_packed_walk_is_bitwise_unpacked(cluster, cache):
+    import paper_2601_01660_amd as P
+    atlas = P.Atlas(H, W, K, dtype="f16")
+    lights = torch.from_numpy(cluster["light"]).cuda()
+    static = P.GaussianSet.from_host(cluster["bg"])
+    dyn = P.GaussianSet.from_host(cluster["dense"])
+    tr = torch.from_numpy(cluster["traj"]).cuda()
+    outs = []
+    for packed in (False, True):
+        plan = P.Plan(lights, atlas, static, cluster["dense"].n, cluster["traj"].shape[0], static_cache=cache,
+                      autotune=False, tile_waves=8, packed=packed)
+        assert plan.packed == (packed and cache)
+        outs.append(plan.run(dyn, tr, use_graph=False).clone())
+        torch.cuda.synchronize()
+        plan.close()
+    assert torch.equal(outs[0], outs[1])
