@@ -30,7 +30,10 @@ FLOPS_PER_TESTED_PAIR = 53    # m.d, W d, a, adj(A)^1/2 (m x d), e0, prefactor: 
 FLOPS_PER_ACTIVE_PAIR = 45    # closest-approach distance, erf scale, shell range: pairs above cull_eps
 FLOPS_PER_RAMP_EVAL = 22      # one shell of the erf ramp: argument 2, erf 18 (A&S 7.1.28), increment 2
 PEAK_FP32_TFLOPS = 157.3
+CHECK_PER_REGION = 16       # learned field: uniform check points per fallback region (plus every texel x shell)
+CHECK_THRESH = 5e-3         # learned field: a region falls back where the network misses by more than this
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
 
 # HBM bytes per launch of the roofline kernel, from two rocprofv3 counter
 # passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over the full-scene
@@ -65,9 +68,12 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--frames", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-texels", type=int, default=40)
+    ap.add_argument("--cpu-texels", type=int, default=320)
     ap.add_argument("--mlp-steps", type=int, default=1500, help="Adam steps per light for the surrogate")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-composite", action="store_true",
+                    help="skip the 6M + 8 x 200k Gaussian, 8-light, 1024x1024x128 composite workload")
+    ap.add_argument("--composite-frames", type=int, default=60)
     ap.add_argument("--eager", action="store_true",
                     help="run the batched plan as eager launches instead of its captured graph (for counters)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -79,36 +85,91 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(scene, avatar, lights, spec, n_texels):
-    """Time the FP64 oracle on a bounded sample and extrapolate to one frame."""
-    import numpy as np
-    import synth
-    from oracle import dgsm as od
+_ORACLE_INPUT = {}   # set before the workers are forked: they inherit it instead of receiving it
+
+
+def _one_thread():
     try:
         from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
+        threadpool_limits(1)
     except Exception:  # pragma: no cover
-        limiter = None
+        pass
+
+
+def _oracle_texels(sl):
+    """Optical depth of the sampled texels over one worker's share of the
+    Gaussians (Eq. 2 is a sum over Gaussians; FP64 oracle, one thread)."""
+    from oracle import dgsm as od
+    _one_thread()
+    d = _ORACLE_INPUT
+    spec, g = d["spec"], d["g"]
+    part = type(g)(g.mean[sl[0]:sl[1]], g.scale[sl[0]:sl[1]], g.rot[sl[0]:sl[1]], g.opacity[sl[0]:sl[1]])
+    mean, A, beta = od.gaussian_terms(part)
+    dirs = od.octahedral_decode(-1 + (2 * d["j"] + 1) / spec.W, -1 + (2 * d["i"] + 1) / spec.H)
+    t = od.shell_radii(spec.K, spec.spacing, spec.r0, spec.r1)
+    return od.optical_depth(dirs, t, d["light"], mean, A, beta)
+
+
+def _oracle_query(sl):
+    from oracle import dgsm as od
+    _one_thread()
+    d = _ORACLE_INPUT
+    spec = d["spec"]
+    od.query(d["table"], d["light"], d["pts"][sl[0]:sl[1]], spec.spacing, spec.r0, spec.r1)
+    return sl[1] - sl[0]
+
+
+def _one_thread_ready(_):
+    _one_thread()
+    return 0
+
+
+def host_cores():
+    """Cores this process may run on, capped at the 16-core share of one GPU."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(scene, avatar, lights, spec, n_texels):
+    """Time the FP64 oracle on a bounded sample, on every host core (forked
+    workers, one thread each; run before the GPU is touched), and extrapolate to
+    one frame."""
+    import multiprocessing as mp
+
+    import numpy as np
+    import synth
+    cores = host_cores()
     g = synth.Gaussians.concat([scene, avatar])
     rng = np.random.default_rng(7)
     i = rng.integers(0, spec.H, n_texels)
     j = rng.integers(0, spec.W, n_texels)
-    t0 = time.perf_counter()
-    od.build_texels(lights[0], g, i, j, spec.K, spec.spacing, spec.r0, spec.r1, H=spec.H, W=spec.W)
-    t_texel = (time.perf_counter() - t0) / n_texels
     table = rng.uniform(0, 1, (spec.K, spec.H, spec.W))
-    pts = g.mean[:200_000]
-    t0 = time.perf_counter()
-    od.query(table, lights[0], pts, spec.spacing, spec.r0, spec.r1)
-    t_point = (time.perf_counter() - t0) / pts.shape[0]
+    pts = g.mean[:400_000]
+    _ORACLE_INPUT.update(light=lights[0], g=g, table=table, pts=pts, spec=spec, i=i, j=j)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        pool.map(_one_thread_ready, range(cores))       # workers up before the clock starts
+        gstep = (g.n + cores - 1) // cores
+        t0 = time.perf_counter()
+        tau = sum(pool.map(_oracle_texels, [(c * gstep, min(g.n, (c + 1) * gstep)) for c in range(cores)]))
+        np.exp(-tau)
+        t_texel = (time.perf_counter() - t0) / n_texels
+        step = (pts.shape[0] + cores - 1) // cores
+        t0 = time.perf_counter()
+        pool.map(_oracle_query, [(c * step, min(pts.shape[0], (c + 1) * step)) for c in range(cores)])
+        t_point = (time.perf_counter() - t0) / pts.shape[0]
+    _ORACLE_INPUT.clear()
     L = lights.shape[0]
     ms = 1e3 * (t_texel * spec.H * spec.W * L + t_point * g.n * L)
-    if limiter is not None:
-        limiter.unregister()
-    return {"value": ms, "unit": "ms/frame", "cores": 1, "kind": "oracle",
-            "sample": (f"{n_texels} texels x {spec.K} shells of light 0 over all {g.n} Gaussians "
-                       f"({t_texel:.3f} s/texel) + FP64 trilinear query of 200000 points; "
-                       f"extrapolated linearly to {L} lights x {spec.H}x{spec.W} texels + {L} x {g.n} queries")}
+    return {"value": ms, "unit": "ms/frame", "cores": cores, "kind": "oracle",
+            "sample": (f"{n_texels} texels x {spec.K} shells of light 0 over all {g.n} Gaussians, each of "
+                       f"{cores} worker processes summing Eq. 2 over its share of the Gaussians "
+                       f"({t_texel:.4f} s of wall time per texel) + FP64 trilinear "
+                       f"query of {pts.shape[0]} points; wall time extrapolated linearly to {L} lights x "
+                       f"{spec.H}x{spec.W} texels + {L} x {g.n} queries")}
 
 
 def surrogate_leg(P, torch, np, dev, lights, atlas, static_set, dyn_set, tr, N, L, spec, steps, timed):
@@ -125,8 +186,10 @@ def surrogate_leg(P, torch, np, dev, lights, atlas, static_set, dyn_set, tr, N, 
         losses = P.mlp_train(params[l], mv, atlas, table[l], steps=steps, batch=16384, lr0=2e-3, lr1=5e-5,
                              seed=1000 + l)
         final_loss.append(float(losses[-20:].mean()))
-        m, nbad, me = P.mlp_check(params[l], atlas, table[l], n_check=262144 + (spec.H * spec.W * spec.K) // 100,
-                                  seed=77 + l, thresh=1e-2)
+        # fallback regions: every texel centre x shell plus 16 uniform points per
+        # (8 x 8 texel x 8 shell) region, flagged at half the 1e-2 bar
+        m, nbad, me = P.mlp_check_grid(params[l], atlas, table[l], n_per_region=CHECK_PER_REGION, seed=77 + l,
+                                       thresh=CHECK_THRESH)
         masks.append(m)
         flagged.append(nbad)
         maxerr.append(me)
@@ -148,17 +211,189 @@ def surrogate_leg(P, torch, np, dev, lights, atlas, static_set, dyn_set, tr, N, 
     torch.cuda.synchronize()
     log(f"surrogate: train {train_s:.1f} s, final losses {final_loss}, query {ms_atlas:.3f} ms vs "
         f"surrogate {ms_surr:.3f} ms, max|dT| {d.max().item():.3e}")
+    mfma_flop = 2.0 * 128 * 128 * 4 * N * L      # four 128 x 128 layers per (point, light)
     return {"ms_per_frame_surrogate_inference": round(ms_surr, 4), "ms_per_frame_atlas_query": round(ms_atlas, 4),
+            "inference_roofline": {"bound": "mfma", "achieved": round(mfma_flop / (ms_surr * 1e-3) / 1e12, 1),
+                                   "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": round(mfma_flop / (ms_surr * 1e-3) / 1e12 / PEAK_BF16_TFLOPS, 4),
+                                   "note": "includes the Fourier features (FP64 phases and sines) and the atlas "
+                                           "fallback"},
             "max_abs_dT_vs_atlas": round(d.max().item(), 6), "mean_abs_dT_vs_atlas": round(d.mean().item(), 7),
             "network_only_mean_abs_dT": round(dn.mean().item(), 7),
             "points_above_1e-2_with_fallback": int((d > 1e-2).sum().item()),
             "fallback_region_fraction": round(float(mask.float().mean().item()), 4),
-            "held_out_flagged_samples": flagged, "held_out_max_abs_dT": [round(x, 5) for x in maxerr],
+            "check": {"samples_per_light": spec.H * spec.W * spec.K + CHECK_PER_REGION * P.mlp_regions(atlas),
+                      "texel_x_shell_nodes": spec.H * spec.W * spec.K, "uniform_per_region": CHECK_PER_REGION,
+                      "flag_threshold": CHECK_THRESH},
+            "check_flagged_samples": flagged, "check_max_abs_dT": [round(x, 5) for x in maxerr],
             "train_steps_per_light": steps, "train_batch": 16384, "train_seconds": round(train_s, 2),
             "final_train_loss": [round(x, 7) for x in final_loss],
             "bytes_network_per_light": P.MLP_PARAMS * 4, "bytes_atlas_per_light": spec.K * spec.H * spec.W * 2,
             "note": "per-light network trained on the frame-0 atlases; surrogate timing includes the atlas "
                     "fallback in flagged regions"}
+
+
+def other_rooflines(query_ms, N, L, spec, sh_tr):
+    """Query (algorithmic bytes: 12 B per point, 4 B per (point, light) result,
+    the FP16 table read once) against HBM; SH transfer against the FP32 peak."""
+    qbytes = 12 * N + 4 * N * L + 2 * L * spec.K * spec.H * spec.W
+    qach = qbytes / (query_ms * 1e-3) / 1e9
+    return {"query": {"kernel": f"query_kernel, {N} points x {L} lights in the caller's order", "bound": "hbm",
+                      "achieved": round(qach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                      "frac": round(qach / PEAK_HBM_GBS, 4), "algorithmic_bytes": qbytes,
+                      "note": ("a gather: each lookup reads two 2x2 texel groups of a 134 MB table in random order, "
+                               "served from the last-level cache, not a stream")},
+            "sh_transfer": {"kernel": "sh_transfer_kernel", "bound": "alu", "achieved": sh_tr["tflops_algorithmic"],
+                            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": sh_tr["frac"]}}
+
+
+def composite_leg(P, torch, np, dev, frames, mlp_steps, timed):
+    """The full composite workload: a 6M-Gaussian room, 8 avatars x 200k Gaussians
+    walking on their own seeded trajectories, 8 point lights, 1024 x 1024 x 128
+    geometric shells, FP16 atlas; per frame the build and query of all 7.6M
+    centres, and the SH relighting of every avatar from its 9 x 3 and 16 x 3
+    probes.  Batched plan (static cache, one rigid group per avatar) against
+    plain per-frame launches, and the learned field against the atlas query."""
+    import synth
+    t_gen = time.perf_counter()
+    c = synth.cfg5(frames=frames)
+    scene, avatars, lights_h, spec = c["scene"], c["avatars"], c["lights"], c["atlas"]
+    F, L = frames, lights_h.shape[0]
+    dyn_h = synth.Gaussians.concat(avatars)
+    ns, nd = scene.n, dyn_h.n
+    N = ns + nd
+    starts = np.cumsum([0] + [a.n for a in avatars])
+    tr_h = np.stack(c["trajectories"], axis=1).astype(np.float32)           # [F][avatars][3]
+    lights = torch.from_numpy(lights_h).to(dev)
+    atlas = P.Atlas.from_spec(spec, dtype="f16", cull_eps=1e-8)
+    static_set = P.GaussianSet.from_host(scene)
+    dyn_set = P.GaussianSet.from_host(dyn_h)
+    tr = torch.from_numpy(tr_h).to(dev)
+    log(f"composite: {ns} room + {len(avatars)} x {avatars[0].n} avatar Gaussians, {L} lights, "
+        f"{spec.H}x{spec.W}x{spec.K} fp16, {F} frames (inputs in {time.perf_counter() - t_gen:.1f} s)")
+
+    # ---- batched plan: static cache, one rigid group per avatar, one chain -----------------
+    T_out = torch.empty((F, L, N), dtype=torch.float32, device=dev)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        t0 = time.perf_counter()
+        plan = P.Plan(lights, atlas, static_set, nd, F, static_cache=True, autotune=True, chains=1,
+                      group_start=starts)
+        side.synchronize()
+        t_create = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        plan.run(dyn_set, tr, out=T_out, use_graph=True)      # autotunes, then the first run
+        side.synchronize()
+        t_first = time.perf_counter() - t0
+        ms_step = timed(lambda: plan.run(dyn_set, tr, out=T_out, use_graph=True), 1)
+        phases = np.median(np.array([plan.time_frame(dyn_set, tr, T_out) for _ in range(3)]), axis=0)
+        knobs = {"tile_waves": plan.tile_waves, "split_units": plan.split_units, "packed_walk": plan.packed,
+                 "static_tile_waves_and_units": list(plan.static_knobs)}
+        plan.close()
+    del T_out
+    torch.cuda.empty_cache()
+    log(f"composite batched: {ms_step / F:.3f} ms/frame ({ms_step:.1f} ms per {F}-frame step; plan created "
+        f"in {t_create:.1f} s, autotuned + first run {t_first:.1f} s; knobs {knobs}; frame phases {phases})")
+
+    # ---- SH relighting of every avatar (Sec. 3.5), its 9 x 3 and its 16 x 3 probe -----------
+    rng_sh = np.random.default_rng(55)
+    relight = []
+    for a, av in enumerate(avatars):
+        m = torch.from_numpy(av.translated(tr_h[0, a]).mean).to(dev)
+        gs = P.GaussianSet(m, dyn_set.scale[starts[a]:starts[a + 1]], dyn_set.rot[starts[a]:starts[a + 1]],
+                           dyn_set.opacity[starts[a]:starts[a + 1]])
+        col = torch.from_numpy(synth.sh_colours(rng_sh, av.n)).to(dev)
+        cen = P.dgsm_alpha_centroid(gs)
+        for pr in (c["probes9"][a], c["probes16"][a]):
+            relight.append((torch.from_numpy(pr).to(dev), gs, col, cen))
+    outs = [(torch.empty((g.n, 3), device=dev), torch.empty_like(col), torch.empty((g.n, 3), device=dev))
+            for _, g, col, _ in relight]
+
+    def relight_all():
+        for (pr, g, col, cen), (so, co, ro) in zip(relight, outs):
+            P.sh_transfer(pr, g, col, centroid=cen, out=(so, co, ro))
+    relight_all()
+    torch.cuda.synchronize()
+    ms_sh = timed(relight_all, 3)
+    del relight, outs
+    log(f"composite SH relighting, {len(avatars)} avatars x 2 probes: {ms_sh:.3f} ms/frame")
+
+    # ---- plain per-frame launches on a workspace sized for the frames' list entries --------
+    n_plain = 2
+    sets = []
+    for f in range(n_plain):
+        g = synth.Gaussians.concat([scene] + [av.translated(tr_h[f, a]) for a, av in enumerate(avatars)])
+        sets.append(P.GaussianSet.from_host(g))
+    entries = max(P.dgsm_count_entries(lights, s_, atlas) for s_ in sets)
+    ws = torch.empty(P.dgsm_build_workspace_size_entries(atlas, N, L, entries), dtype=torch.uint8, device=dev)
+    table = torch.empty((L, spec.K, spec.H, spec.W), dtype=torch.float16, device=dev)
+    Tq = torch.empty((L, N), dtype=torch.float32, device=dev)
+
+    def plain(f):
+        P.dgsm_bin(lights, sets[f], atlas, ws)
+        P.dgsm_accumulate(lights, atlas, N, table, ws)
+        P.dgsm_query(lights, atlas, table, sets[f].mean, out=Tq)
+    plain(1)
+    torch.cuda.synchronize()
+    ms_plain = timed(lambda: [plain(f) for f in range(n_plain)], 1) / n_plain
+    fits = all(P.dgsm_list_entries(atlas, N, L, ws, l)[0] <= P.dgsm_list_entries(atlas, N, L, ws, l)[1]
+               for l in range(L))
+    plain(0)     # frame 0's atlas stays in `table` for the learned field
+    torch.cuda.synchronize()
+    log(f"composite plain per-frame launches: {ms_plain:.1f} ms/frame (workspace {ws.numel() / 2**30:.1f} GiB for "
+        f"{entries} list entries per light; worst case {P.dgsm_build_workspace_size(atlas, N, L) / 2**30:.0f} GiB)")
+    assert fits
+    del ws
+    torch.cuda.empty_cache()
+
+    # ---- learned field per light on frame 0's atlases, against the atlas query -------------
+    params = torch.stack([torch.from_numpy(synth.mlp_init_params(500 + l)) for l in range(L)]).to(dev)
+    t0 = time.perf_counter()
+    masks, final_loss = [], []
+    for l in range(L):
+        mv = torch.zeros(2 * P.MLP_PARAMS, device=dev)
+        losses = P.mlp_train(params[l], mv, atlas, table[l], steps=mlp_steps, batch=16384, lr0=2e-3, lr1=5e-5,
+                             seed=2000 + l)
+        final_loss.append(float(losses[-20:].mean()))
+        m, _, _ = P.mlp_check_grid(params[l], atlas, table[l], n_per_region=CHECK_PER_REGION, seed=300 + l,
+                                   thresh=CHECK_THRESH)
+        masks.append(m)
+    mask = torch.stack(masks)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    pts = sets[0].mean
+    wsi = torch.empty(int(P.lib().dgsm_mlp_infer_workspace_size(L)), dtype=torch.uint8, device=dev)
+    Ts = torch.empty_like(Tq)
+    P.dgsm_query(lights, atlas, table, pts, out=Tq)
+    P.mlp_infer(params, lights, atlas, pts, table=table, mask=mask, out=Ts, workspace=wsi)
+    torch.cuda.synchronize()
+    ms_q = timed(lambda: P.dgsm_query(lights, atlas, table, pts, out=Tq), 3)
+    ms_s = timed(lambda: P.mlp_infer(params, lights, atlas, pts, table=table, mask=mask, out=Ts, workspace=wsi), 3)
+    d = (Ts - Tq).abs()
+    surr = {"ms_per_frame_surrogate_inference": round(ms_s, 3), "ms_per_frame_atlas_query": round(ms_q, 3),
+            "max_abs_dT_vs_atlas": round(d.max().item(), 6), "points_above_1e-2_with_fallback": int((d > 1e-2).sum()),
+            "fallback_region_fraction": round(float(mask.float().mean()), 4), "train_seconds": round(t_train, 2),
+            "final_train_loss": [round(x, 5) for x in final_loss],
+            "bytes_network_per_light": P.MLP_PARAMS * 4, "bytes_atlas_per_light": spec.K * spec.H * spec.W * 2}
+    log(f"composite surrogate: {surr}")
+    out = {"workload": (f"room {ns} static + {len(avatars)} avatars x {avatars[0].n} Gaussians on their own rigid "
+                        f"walks, {L} point lights, {spec.H}x{spec.W}x{spec.K} geometric shells 0.05-8 m, fp16 atlas, "
+                        f"build + query of all {N} centres and SH relighting of every avatar (9x3 and 16x3 probes) "
+                        f"every frame"),
+           "frames_per_step": F,
+           "ms_per_frame": {"batched_graph_static_cache": round(ms_step / F, 3), "sh_relighting": round(ms_sh, 3),
+                            "batched_total": round(ms_step / F + ms_sh, 3),
+                            "plain_per_frame_launches": round(ms_plain, 3),
+                            "plain_total": round(ms_plain + ms_sh, 3)},
+           "plan_create_s": round(t_create, 2), "autotune_and_first_run_s": round(t_first, 2), "knobs": knobs,
+           "frame_phases_ms": {"binning": round(float(phases[0]), 3), "accumulation": round(float(phases[1]), 3),
+                               "query": round(float(phases[2]), 3), "restore": round(float(phases[3]), 3),
+                               "static_accumulation_once_per_step": round(float(phases[4]), 3)},
+           "list_entries_per_light": entries,
+           "surrogate": surr}
+    del table, Tq, Ts, params, mask, sets
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -175,11 +410,18 @@ def main():
     import paper_2601_01660_amd as P
     import synth
 
+    F = args.frames
+    c = synth.cfg3(frames=F)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before anything touches the GPU: the oracle's workers are forked
+        log(f"timing the FP64 oracle on a sample ({host_cores()} cores)")
+        cpu = cpu_baseline(c["scene"], c["avatar"], c["lights"], c["atlas"], args.cpu_texels)
+        log(f"oracle: {cpu['value']:.3e} ms/frame")
+
     P.lib()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    F = args.frames
-    c = synth.cfg3(frames=F)
     scene, avatar, lights_h, traj, spec = c["scene"], c["avatar"], c["lights"], c["trajectory"], c["atlas"]
     N = scene.n + avatar.n
     L = lights_h.shape[0]
@@ -326,14 +568,19 @@ def main():
     colour_sh = torch.from_numpy(synth.sh_colours(rng_sh, avatar.n)).to(dev)
     av_set = P.GaussianSet(av, scale[scene.n:], rot[scene.n:], opac[scene.n:])
     centroid = P.dgsm_alpha_centroid(av_set)
-    P.sh_transfer(probe_sh, av_set, colour_sh, centroid=centroid)
+    ws_sh = torch.empty(int(P.lib().sh_transfer_workspace_size(32, 64)), dtype=torch.uint8, device=dev)
+    sh_out = (torch.empty((avatar.n, 3), device=dev), torch.empty_like(colour_sh),
+              torch.empty((avatar.n, 3), device=dev))
+    P.sh_transfer(probe_sh, av_set, colour_sh, centroid=centroid, out=sh_out, workspace=ws_sh)
     torch.cuda.synchronize()
-    ms_sh = timed(lambda: P.sh_transfer(probe_sh, av_set, colour_sh, centroid=centroid), 10)
+    ms_sh = timed(lambda: P.sh_transfer(probe_sh, av_set, colour_sh, centroid=centroid, out=sh_out,
+                                        workspace=ws_sh), 10)
     flop_sh = avatar.n * 32 * 64 * 14      # Gaussian x grid direction: dot 5, max 1, 4 FMA 8
     sh_tr = {"gaussians": avatar.n, "probe_coeffs": 16, "grid": [32, 64], "ms": round(ms_sh, 4),
-             "tflops_algorithmic": round(flop_sh / (ms_sh * 1e-3) / 1e12, 2), "peak_tflops": PEAK_FP32_TFLOPS}
+             "tflops_algorithmic": round(flop_sh / (ms_sh * 1e-3) / 1e12, 2), "peak_tflops": PEAK_FP32_TFLOPS,
+             "frac": round(flop_sh / (ms_sh * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)}
     log(f"SH transfer: {sh_tr}")
-    del colour_sh
+    del colour_sh, sh_out
     torch.cuda.empty_cache()
 
     # ---- batched plan: static cache + captured graph (the headline) -------------------------
@@ -346,11 +593,16 @@ def main():
         for _ in range(args.warmup):
             plan.run(dyn_set, tr, out=T_out, use_graph=not args.eager)
         side.synchronize()
-        log(f"warmup done (autotuned: {plan.tile_waves} waves per tile, {plan.split_units} work units)")
+        log(f"warmup done (autotuned: {plan.tile_waves} waves per tile, {plan.split_units} work units, "
+            f"packed walk {plan.packed}, static build {plan.static_knobs})")
         wall0 = time.perf_counter()
         ms_step = timed(lambda: plan.run(dyn_set, tr, out=T_out, use_graph=not args.eager), args.steps)
         wall = time.perf_counter() - wall0
-        tile_waves, split_units = plan.tile_waves, plan.split_units
+        tile_waves, split_units, packed = plan.tile_waves, plan.split_units, plan.packed
+        # the per-frame dynamic accumulation, timed on its own (HIP events around
+        # the launches of frame 0 on this stream; median of 5)
+        phases = np.array([plan.time_frame(dyn_set, tr, T_out) for _ in range(5)])
+        frame_ms = np.median(phases, axis=0)
         plan.close()
         plan_nc = P.Plan(lights, atlas, static_set, avatar.n, F, static_cache=False, autotune=False,
                          tile_waves=tile_waves, split_units=split_units)
@@ -361,6 +613,38 @@ def main():
     ms_frame = ms_step / F
     log(f"batched graph + static cache: {ms_frame:.3f} ms/frame (wall {wall:.2f} s for {args.steps} steps); "
         f"batched without cache: {ms_nocache / F:.3f} ms/frame")
+
+    # work counters of the avatar alone at frame 0 (the pairs the plan's dynamic
+    # accumulation evaluates: its binning is the same, the static depth only
+    # enters the finish)
+    av0 = P.GaussianSet(means[0, scene.n:], scale[scene.n:], rot[scene.n:], opac[scene.n:])
+    ws_d = torch.empty(P.dgsm_build_workspace_size(atlas, avatar.n, L), dtype=torch.uint8, device=dev)
+    tab_d = torch.empty((L, spec.K, spec.H, spec.W), dtype=torch.float16, device=dev)
+    stats_d = torch.zeros(8, dtype=torch.int64, device=dev)
+    P.dgsm_bin(lights, av0, atlas, ws_d)
+    P.dgsm_accumulate(lights, atlas, avatar.n, tab_d, ws_d, stats=stats_d)
+    torch.cuda.synchronize()
+    sd = stats_d.cpu().numpy().astype(np.float64)
+    tested_d = sd[0] * (1.0 - sd[7] / max(sd[6], 1.0))
+    flops_d = (FLOPS_PER_TILE_PAIR * sd[0] + FLOPS_PER_TESTED_PAIR * tested_d + FLOPS_PER_ACTIVE_PAIR * sd[1]
+               + FLOPS_PER_RAMP_EVAL * sd[2])
+    del ws_d, tab_d
+    achieved_d = flops_d / (frame_ms[1] * 1e-3) / 1e12
+    roofline_dyn = {"kernel": (f"tile_build_kernel ({'packed walk' if packed else 'tile walk'}, {tile_waves} waves "
+                               f"per tile): the plan's per-frame accumulation of the {avatar.n} avatar Gaussians "
+                               f"on the cached static depth, {L} lights per launch"),
+                    "bound": "alu", "achieved": round(achieved_d, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved_d / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                    "launch_ms": round(float(frame_ms[1]), 4),
+                    "frame_phases_ms": {"binning": round(float(frame_ms[0]), 4),
+                                        "accumulation": round(float(frame_ms[1]), 4),
+                                        "query": round(float(frame_ms[2]), 4),
+                                        "restore": round(float(frame_ms[3]), 4),
+                                        "static_accumulation_once_per_step": round(float(frame_ms[4]), 4)},
+                    "units_per_launch": {"tile_pairs": sd[0], "active_pairs": sd[1], "ramp_evals": sd[2],
+                                         "tile_gaussian_pairs": sd[6], "idle_tile_gaussian_pairs": sd[4],
+                                         "texel_pairs_past_pretest": tested_d}}
+    log(f"per-frame dynamic accumulation: {roofline_dyn}")
 
     achieved = flops / (acc_ms * 1e-3) / 1e12
     roofline = {"kernel": "tile_build_kernel (dgsm_accumulate over all 2.15M Gaussians, 4 lights per launch)",
@@ -383,24 +667,33 @@ def main():
                       "mode": ("one captured graph per step: static optical depth built once per step, "
                                "then per frame the avatar's binning + accumulation on top of it, "
                                "fp16 store and query of all 2.15M centres"),
-                      "tile_waves": tile_waves, "split_units": split_units},
+                      "tile_waves": tile_waves, "split_units": split_units, "packed_walk": bool(packed)},
            "comparison_ms_per_frame": {"batched_graph_static_cache": round(ms_frame, 4),
                                        "batched_graph_no_cache": round(ms_nocache / F, 4),
                                        "plain_per_frame_launches": round(ms_plain / F, 4)},
-           "roofline": roofline, "footprint_query": footprint, "roi_build": roi, "cube_map": cubemap, "probe_fit": probe,
+           "roofline": roofline, "roofline_dynamic": roofline_dyn,
+           "roofline_other": other_rooflines(footprint["center_query_ms"], N, L, spec, sh_tr),
+           "footprint_query": footprint, "roi_build": roi, "cube_map": cubemap, "probe_fit": probe,
            "sh_transfer": sh_tr}
     if not args.no_surrogate:
         out["surrogate"] = surrogate_leg(P, torch, np, dev, lights, atlas, static_set, dyn_set, tr, N, L, spec,
                                          args.mlp_steps, timed)
+    if not args.no_composite:
+        del T_out
+        torch.cuda.empty_cache()
+        try:
+            out["composite"] = composite_leg(P, torch, np, dev, args.composite_frames, args.mlp_steps, timed)
+        except (RuntimeError, AssertionError, ValueError) as e:   # keep the headline line if this leg fails
+            log(f"composite workload failed: {e!r}")
+            out["composite"] = {"error": repr(e)}
     if args.calibrate_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = 2 * a.numel() * 4
-    if not args.no_cpu_baseline:
-        log("timing the FP64 oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(scene, avatar, lights_h, spec, args.cpu_texels)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

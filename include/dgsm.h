@@ -360,10 +360,17 @@ typedef struct {
  *   rgb_out       : device [n][3] = max(0, gamma (0.5 + C0 f_0) s) with
  *                   C0 = 1/(2 sqrt(pi)) (the DC colour), or NULL
  *   colour_sh_out and rgb_out require colour_sh.
+ *   ws            : device workspace of >= sh_transfer_workspace_size(n_theta,
+ *                   n_phi) bytes (32 bytes per grid direction): the probe's
+ *                   radiance and weight on the grid, evaluated once per call
+ *                   and then read by every Gaussian's sum
+ * The sums run in FP32 in a fixed order (each of four quarters of the grid
+ * in direction order, the quarters added in order): bitwise reproducible.
  */
+size_t sh_transfer_workspace_size(int32_t n_theta, int32_t n_phi);
 dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_t* gaussians,
                         const float* colour_sh, const dgsm_sh_params_t* params, float* scale_out,
-                        float* colour_sh_out, float* rgb_out, void* stream);
+                        float* colour_sh_out, float* rgb_out, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Batched build + query over animation frames (a plan).
@@ -391,14 +398,16 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  *   static_cache  1: the static optical depth is built once per run and each
  *                 frame adds only the dynamic Gaussians to it (tau is a sum over
  *                 Gaussians, Eq. 2); 0: every frame rebuilds from all Gaussians
- *   autotune      1: the first run times the knobs of the tile accumulation
+ *   autotune      1: the first run (unless the tuning cache below holds this
+ *                 workload) times the knobs of the tile accumulation
  *                 on frame 0 of the real workload and keeps the fastest
  *                 combination: waves per tile (2, 4, 8), work units per launch
  *                 (never, 8192, 32768, 131072) and, in cache mode, the packed
  *                 walk (see dgsm_accumulate_ex) on or off; in cache mode they
- *                 apply to the per-frame dynamic accumulation, the once-per-run
- *                 static build keeps the defaults (8 waves, 32768 units,
- *                 unpacked)
+ *                 apply to the per-frame dynamic accumulation, and the
+ *                 once-per-run static build gets its own waves per tile and
+ *                 work units, timed on the static set (tile walk); without
+ *                 autotuning the static build takes the defaults (8, 32768)
  *   tile_waves    waves sharing one 8x8 tile when autotune = 0 (2, 4 or 8; else 8)
  *   split_units   target number of work units per accumulation when
  *                 autotune = 0: a tile with more hits than (total hits /
@@ -457,11 +466,33 @@ dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_atlas_desc_
                              const dgsm_plan_opts_t* opts, dgsm_plan* out);
 dgsm_status dgsm_plan_run(dgsm_plan plan, const dgsm_gaussians_t* dynamic_set, const float* translations,
                           float* T_out, int32_t use_graph, void* stream);
+/* dgsm_plan_time_frame - one frame of the plan (frame 0, on the caller's
+ * stream, eagerly, after the static build in cache mode) with HIP events
+ * between its phases: ms[0] dynamic binning (the whole set without the cache),
+ * ms[1] tile accumulation (work-unit planning, tile build, finish of split
+ * tiles), ms[2] query and reordering into T_out, ms[3] restore of the reached
+ * tiles (cache mode), ms[4] the static set's accumulation into its cached
+ * optical depth (cache mode; 0 otherwise).  Writes T_out[0]; synchronises
+ * `stream`.  For measuring the launches; results as dgsm_plan_run. */
+dgsm_status dgsm_plan_time_frame(dgsm_plan plan, const dgsm_gaussians_t* dynamic_set, const float* translations,
+                                 float* T_out, float ms[5], void* stream);
+
 /* The knobs in use (after autotuning, if enabled): waves per tile, work
  * units per accumulation (-1: never split), packed walk (1) or not (0). */
 int32_t dgsm_plan_tile_waves(const dgsm_plan plan);
 int32_t dgsm_plan_split_units(const dgsm_plan plan);
 int32_t dgsm_plan_packed(const dgsm_plan plan);
+/* Tuning cache: the autotuner's choice is kept for the process, keyed by the
+ * workload (atlas H, W, K, spacing, storage type and parameterisation, light
+ * count, cache mode, motion, and the static and dynamic Gaussian counts to the
+ * nearest power of two); a later plan with the same key takes it without
+ * timing.  The cache is guarded by a mutex (plans may be created and run from
+ * several host threads).  dgsm_plan_tuned_from_cache: 1 if this plan's knobs
+ * came from the cache; dgsm_autotune_cache_clear empties it. */
+int32_t dgsm_plan_tuned_from_cache(const dgsm_plan plan);
+/* out = {waves per tile, work units} of the static build; returns 1 (0 if plan or out is NULL). */
+int32_t dgsm_plan_static_knobs(const dgsm_plan plan, int32_t out[2]);
+void dgsm_autotune_cache_clear(void);
 dgsm_status dgsm_plan_destroy(dgsm_plan plan);
 
 /*

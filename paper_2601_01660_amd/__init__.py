@@ -102,9 +102,10 @@ SIGNATURES = {
                                        ctypes.c_void_p]),
     "dgsm_query": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_AtlasDesc), ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "sh_transfer_workspace_size": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32]),
     "sh_transfer": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_Gaussians), ctypes.c_void_p,
                                    ctypes.POINTER(_ShParams), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                   ctypes.c_void_p]),
+                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "dgsm_alpha_centroid": (ctypes.c_int, [ctypes.POINTER(_Gaussians), ctypes.c_void_p, ctypes.c_void_p]),
     "dgsm_plan_create": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_AtlasDesc),
                                         ctypes.POINTER(_Gaussians), ctypes.c_int64, ctypes.POINTER(_PlanOpts),
@@ -127,6 +128,11 @@ SIGNATURES = {
     "dgsm_plan_tile_waves": (ctypes.c_int32, [ctypes.c_void_p]),
     "dgsm_plan_split_units": (ctypes.c_int32, [ctypes.c_void_p]),
     "dgsm_plan_packed": (ctypes.c_int32, [ctypes.c_void_p]),
+    "dgsm_plan_tuned_from_cache": (ctypes.c_int32, [ctypes.c_void_p]),
+    "dgsm_plan_static_knobs": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "dgsm_autotune_cache_clear": (None, []),
+    "dgsm_plan_time_frame": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Gaussians), ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]),
     "dgsm_accumulate_ex": (ctypes.c_int, [ctypes.POINTER(_Lights), ctypes.POINTER(_AtlasDesc), ctypes.c_int64,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                           ctypes.POINTER(_AccumOpts), ctypes.c_void_p, ctypes.c_void_p]),
@@ -554,7 +560,7 @@ def dgsm_alpha_centroid(gaussians: GaussianSet, out=None):
 
 
 def sh_transfer(probe_sh, gaussians: GaussianSet, colour_sh=None, centroid=None, n_theta=32, n_phi=64,
-                q=1.0, clip_max=4.0, eps=1e-6, gamma=1.0, out=None):
+                q=1.0, clip_max=4.0, eps=1e-6, gamma=1.0, out=None, workspace=None):
     """Per-Gaussian lighting scale [N,3], relit SH [N,16,3] and RGB [N,3] (Sec. 3.5);
     ``out`` = (scale, colour, rgb) buffers to write instead of new ones."""
     N = gaussians.n
@@ -582,8 +588,13 @@ def sh_transfer(probe_sh, gaussians: GaussianSet, colour_sh=None, centroid=None,
         rgb = torch.empty((N, 3), dtype=torch.float32, device=dev) if colour_sh is not None else None
     prm = _ShParams(n_theta, n_phi, q, clip_max, eps, gamma, centroid.data_ptr())
     gs = gaussians.struct()
+    need = int(lib().sh_transfer_workspace_size(n_theta, n_phi))
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _cuda(workspace, "workspace")
     _check(lib().sh_transfer(_ptr(probe_sh), int(probe_sh.shape[0]), ctypes.byref(gs), _ptr(colour_sh),
-                             ctypes.byref(prm), _ptr(s), _ptr(f_out), _ptr(rgb), _stream()))
+                             ctypes.byref(prm), _ptr(s), _ptr(f_out), _ptr(rgb), _ptr(workspace),
+                             workspace.numel(), _stream()))
     return s, f_out, rgb
 
 
@@ -641,6 +652,17 @@ class Plan:
     def packed(self) -> bool:
         return bool(lib().dgsm_plan_packed(self._h))
 
+    @property
+    def static_knobs(self):
+        """(waves per tile, work units) of the once-per-run static build."""
+        out = (ctypes.c_int32 * 2)()
+        lib().dgsm_plan_static_knobs(self._h, out)
+        return int(out[0]), int(out[1])
+
+    @property
+    def tuned_from_cache(self) -> bool:
+        return bool(lib().dgsm_plan_tuned_from_cache(self._h))
+
     def run(self, dynamic: GaussianSet, translations, out=None, use_graph: bool = True):
         """T[frames, L, n_static + n_dynamic] for one run; enqueued on the current stream.
         Without ``out`` the result is the plan's own buffer, overwritten by the next run."""
@@ -676,6 +698,18 @@ class Plan:
         _buf(out, (self.frames, self.L, self.n_points), torch.float32, "out")
         _check(lib().dgsm_plan_run(self._h, ctypes.byref(gs), tptr, _ptr(out), int(use_graph), _stream()))
         return out
+
+    def time_frame(self, dynamic: GaussianSet, translations, out):
+        """(binning, accumulation, query, restore, static accumulation) ms of frame 0, eagerly
+        on the current stream."""
+        if self.motion != "rigid":
+            raise ValueError("time_frame takes the rigid form of the dynamic set")
+        translations = _dev(translations)
+        _buf(out, (self.frames, self.L, self.n_points), torch.float32, "out")
+        gs = dynamic.struct()
+        ms = (ctypes.c_float * 5)()
+        _check(lib().dgsm_plan_time_frame(self._h, ctypes.byref(gs), _ptr(translations), _ptr(out), ms, _stream()))
+        return tuple(float(x) for x in ms)
 
     def close(self):
         if getattr(self, "_h", None):

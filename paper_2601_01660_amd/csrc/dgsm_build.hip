@@ -1126,21 +1126,33 @@ __device__ __attribute__((always_inline)) inline void walk_hits_packed(const uin
             nz &= nz - 1;
             uint64_t word = readlane_u64(wv, j);
             const int gv = list[64 * ((mbase + j) * S + o) + lane];
-            while (word) {
-                const int b = __builtin_ctzll(word);
-                word &= word - 1;
-                const int gid = readlane_i(gv, b);
-                const PreRegs r = load_pre(rec, gid);
+            // the next hit's offset and bound are loaded while this one is tested
+            int gid = readlane_i(gv, __builtin_ctzll(word));
+            word &= word - 1;
+            PreRegs r = load_pre(rec, gid);
+            for (;;) {
+                const bool more = word != 0ull;
+                int gnext = gid;
+                PreRegs rn = r;
+                if (more) {
+                    gnext = readlane_i(gv, __builtin_ctzll(word));
+                    word &= word - 1;
+                    rn = load_pre(rec, gnext);
+                }
                 const bool pass = ray_offset(r.mx, r.my, r.mz, r.r2, st).near;   // eval_pair's pre-test
                 const uint64_t m = ballot(pass) & st.vmask;
-                if (m == 0ull) continue;
-                if ((m >> lane) & 1ull) {
-                    const int pos = qn + ballot_rank(m);
-                    qg[pos] = gid;
-                    qt[pos] = (unsigned char)lane;
+                if (m != 0ull) {
+                    if ((m >> lane) & 1ull) {
+                        const int pos = qn + ballot_rank(m);
+                        qg[pos] = gid;
+                        qt[pos] = (unsigned char)lane;
+                    }
+                    qn += __popcll(m);
+                    if (qn >= kWave) flush(kWave);
                 }
-                qn += __popcll(m);
-                if (qn >= kWave) flush(kWave);
+                if (!more) break;
+                gid = gnext;
+                r = rn;
             }
         }
     }

@@ -26,7 +26,10 @@
 #include "dgsm_device.hpp"
 #include "dgsm_host.hpp"
 
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 namespace dgsm {
@@ -245,7 +248,10 @@ struct dgsm_plan_s {
     int tile_waves;
     int split_units;
     bool tuned;
+    bool tuned_cached;    // the knobs came from the tuning cache
     int pack;             // packed walk for the dynamic accumulation (cache mode)
+    int static_waves;     // knobs of the once-per-run static build (cache mode)
+    int static_units;
     int motion;           // DGSM_MOTION_RIGID or DGSM_MOTION_FREE
     int groups;           // rigid groups of the dynamic set
     unsigned short* group;   // [nd] group of each dynamic Gaussian (null: one group)
@@ -315,14 +321,16 @@ dgsm_gaussians_t set_of(const dgsm_plan p, const float* mean, int64_t off, int64
 }
 
 // Static part of a run: tau of the static set for every light.
-dgsm_status enqueue_static(dgsm_plan p, int tile_waves, int split_units, hipStream_t st) {
+dgsm_status enqueue_static(dgsm_plan p, int tile_waves, int split_units, hipStream_t st, hipEvent_t* ev = nullptr) {
     const dgsm_lights_t lt{p->lights, p->L, p->kappa, p->beta_mode};
     const BuildLayout& La = p->lay_a;
     dgsm_status s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, p->mean, 0, p->ns), st, false);
     if (s != DGSM_OK) return s;
+    if (ev) (void)hipEventRecord(ev[0], st);
     AccumOpts o{nullptr, true, nullptr, tile_waves, split_units, true};
     s = enqueue_accumulate(p->g, La, p->ws_a, p->L, p->desc.cull_eps, p->tau_static, o, st);
     if (s != DGSM_OK) return s;
+    if (ev) (void)hipEventRecord(ev[1], st);
     const dim3 grid(p->g.ntiles, p->L);
     if (p->desc.dtype == DGSM_F16) {
         ChainAtlases<__half> a{};
@@ -340,7 +348,12 @@ dgsm_status enqueue_static(dgsm_plan p, int tile_waves, int split_units, hipStre
 // static tau in cache mode), query, and in cache mode the restore of the
 // chain's atlas to the static baseline.
 dgsm_status enqueue_frame(dgsm_plan p, int f, int c, const dgsm_gaussians_t* dyn_base, const float* translations,
-                          float* T_out, int tile_waves, int split_units, int pack, hipStream_t st) {
+                          float* T_out, int tile_waves, int split_units, int pack, hipStream_t st,
+                          hipEvent_t* ev = nullptr) {
+    // ev (optional, 5 events): recorded before the dynamic binning, before the
+    // accumulation, before the query, before the restore and at the end
+    auto mark = [&](int i) { if (ev) (void)hipEventRecord(ev[i], st); };
+    mark(0);
     const dgsm_lights_t lt{p->lights, p->L, p->kappa, p->beta_mode};
     float* mean = p->cmean[c];
     void* atlas = p->catlas[c];
@@ -380,6 +393,7 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, int c, const dgsm_gaussians_t* dyn
         // offsets change
         s = enqueue_bin(p->g, Lb, ws_b, lt, p->desc.cull_eps, dyn, st, false, rigid && f >= p->chains);
         if (s != DGSM_OK) return s;
+        mark(1);
         // only tiles the dynamic set reaches are rebuilt; the rest hold the static baseline
         AccumOpts o{p->tau_static, false, nullptr, tile_waves, split_units, true, true};
         o.pack = pack != 0;
@@ -388,10 +402,12 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, int c, const dgsm_gaussians_t* dyn
         const BuildLayout& La = p->lay_a;
         s = enqueue_bin(p->g, La, p->ws_a, lt, p->desc.cull_eps, set_of(p, mean, 0, p->np), st, false);
         if (s != DGSM_OK) return s;
+        mark(1);
         AccumOpts o{nullptr, false, nullptr, tile_waves, split_units, true};
         s = enqueue_accumulate(p->g, La, p->ws_a, p->L, p->desc.cull_eps, atlas, o, st);
     }
     if (s != DGSM_OK) return s;
+    mark(2);
     // Query in plan (spatial) order with coalesced point-major writes, then one
     // gather into the caller's order: writing straight to the caller's columns
     // scatters 4-byte stores over the whole output.
@@ -402,6 +418,7 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, int c, const dgsm_gaussians_t* dyn
                                                                         T_out + (size_t)f * p->L * p->np);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }
+    mark(3);
     if (p->cache) {
         const BuildLayout& Lb = p->lay_b;
         const dim3 grid(p->g.ntiles, p->L);
@@ -413,6 +430,7 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, int c, const dgsm_gaussians_t* dyn
                                                           static_cast<float*>(atlas));
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }
+    mark(4);
     return DGSM_OK;
 }
 
@@ -428,7 +446,7 @@ dgsm_status enqueue_run(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* t
     dgsm_status s;
     // the static build is a full-scene accumulation: it keeps the defaults
     // (the tuned knobs fit the per-frame dynamic accumulation)
-    if (p->cache && (s = enqueue_static(p, kDefaultTileWaves, kDefaultSplitUnits, st)) != DGSM_OK) return s;
+    if (p->cache && (s = enqueue_static(p, p->static_waves, p->static_units, st)) != DGSM_OK) return s;
     // fork: every chain starts after the static build (and the copies above)
     hipStream_t cs[kMaxChains];
     cs[0] = st;
@@ -450,9 +468,35 @@ dgsm_status enqueue_run(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* t
     return s;
 }
 
-// Time each (waves per tile, work units) candidate on the accumulation the
-// run repeats most (frame 0: the dynamic accumulation in cache mode, the full
-// one otherwise).
+// Knobs found by the autotuner, shared by the plans of the process: a plan
+// whose workload matches an earlier one's (atlas H, W, K, spacing, storage and
+// parameterisation, light count, cache mode, motion, and the static and
+// dynamic Gaussian counts to the nearest power of two) takes its knobs without
+// timing.  Guarded by a mutex; dgsm_autotune_cache_clear empties it.
+struct TuneKnobs {
+    int waves, units, pack, static_waves, static_units;
+};
+using TuneKey = std::tuple<int, int, int, int, int, int, int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneKnobs> g_tune;
+
+int log2_bucket(int64_t n) {
+    int b = 0;
+    while (n > 1) {
+        n >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+TuneKey tune_key(const dgsm_plan p) {
+    return TuneKey{p->g.H, p->g.W, p->g.K, p->g.spacing, p->desc.dtype, p->g.param, p->L, p->cache ? 1 : 0,
+                   p->motion, log2_bucket(p->ns), log2_bucket(p->nd)};
+}
+
+// Time each (waves per tile, work units, packed walk) candidate on the
+// accumulation the run repeats most (frame 0: the dynamic accumulation in
+// cache mode, the full one otherwise).
 dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* translations, float* T_out,
                      hipStream_t st) {
     const int waves[3] = {2, 4, 8};
@@ -469,7 +513,33 @@ dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* tran
         (void)hipMemcpyAsync(p->rot + 4 * o, dyn->rot, 16 * p->nd, hipMemcpyDeviceToDevice, st);
         (void)hipMemcpyAsync(p->opacity + o, dyn->opacity, 4 * p->nd, hipMemcpyDeviceToDevice, st);
     }
-    if (p->cache) s = enqueue_static(p, kDefaultTileWaves, kDefaultSplitUnits, st);
+    // the once-per-run static build (cache mode): 4 or 8 waves per tile x
+    // 32768 or 131072 work units (a full-scene build; 2 waves and unsplit tiles
+    // lose there), each timed once after a warm-up build with the defaults
+    int best_sw = kDefaultTileWaves, best_su = kDefaultSplitUnits;
+    if (p->cache && p->ns > 0) {
+        const int swaves[2] = {4, 8}, sunits[2] = {32768, 131072};
+        hipEvent_t ea[2];
+        if (hipEventCreate(&ea[0]) != hipSuccess || hipEventCreate(&ea[1]) != hipSuccess) return DGSM_EHIP;
+        float sbest = 1e30f;
+        for (int c = -1; c < 4 && s == DGSM_OK; ++c) {
+            const int nw = c < 0 ? kDefaultTileWaves : swaves[c % 2], nu = c < 0 ? kDefaultSplitUnits : sunits[c / 2];
+            s = enqueue_static(p, nw, nu, st, ea);
+            if (s == DGSM_OK && hipEventSynchronize(ea[1]) != hipSuccess) s = DGSM_EHIP;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ea[0], ea[1]);
+            if (c >= 0 && ms < sbest) {
+                sbest = ms;
+                best_sw = nw;
+                best_su = nu;
+            }
+        }
+        (void)hipEventDestroy(ea[0]);
+        (void)hipEventDestroy(ea[1]);
+    }
+    p->static_waves = best_sw;
+    p->static_units = best_su;
+    if (p->cache && s == DGSM_OK) s = enqueue_static(p, best_sw, best_su, st);
     for (int rep = 0; rep < 2 && s == DGSM_OK; ++rep)   // first pass warms up
         for (int c = 0; c < 12 * npack && s == DGSM_OK; ++c) {
             const int nw = waves[c % 3], nu = units[(c / 3) % 4], pk = c / 12;
@@ -492,7 +562,26 @@ dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* tran
     p->split_units = best_units;
     p->pack = best_pack;
     p->tuned = true;
+    if (s == DGSM_OK) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[tune_key(p)] = TuneKnobs{best_nw, best_units, best_pack, p->static_waves, p->static_units};
+    }
     return s;
+}
+
+// Knobs of an earlier plan with the same workload, if any.
+bool tune_from_cache(dgsm_plan p) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(tune_key(p));
+    if (it == g_tune.end()) return false;
+    p->tile_waves = it->second.waves;
+    p->split_units = it->second.units;
+    p->pack = it->second.pack;
+    p->static_waves = it->second.static_waves;
+    p->static_units = it->second.static_units;
+    p->tuned = true;
+    p->tuned_cached = true;
+    return true;
 }
 
 // Static set into the plan in spatial order (see bitonic_kernel); synchronous.
@@ -582,6 +671,8 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     p->split_units = opts->split_units == 0 ? kDefaultSplitUnits : (opts->split_units < 0 ? -1 : opts->split_units);
     p->motion = opts->motion;
     p->pack = p->cache && opts->packed ? 1 : 0;
+    p->static_waves = kDefaultTileWaves;
+    p->static_units = kDefaultSplitUnits;
     p->groups = groups;
     const size_t elem = desc->dtype == DGSM_F16 ? 2 : 4;
     const size_t table = (size_t)p->L * g.K * plane_elems(g, true);   // plan-internal: tile-major planes
@@ -667,7 +758,9 @@ extern "C" dgsm_status dgsm_plan_run(dgsm_plan p, const dgsm_gaussians_t* dynami
     dgsm_status st = validate_gaussians(dynamic_set);
     if (st != DGSM_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    if (p->autotune && !p->tuned && (st = autotune(p, dynamic_set, translations, T_out, s)) != DGSM_OK) return st;
+    if (p->autotune && !p->tuned && !tune_from_cache(p) &&
+        (st = autotune(p, dynamic_set, translations, T_out, s)) != DGSM_OK)
+        return st;
     if (!use_graph) return enqueue_run(p, dynamic_set, translations, T_out, s);
     if (!s) return DGSM_EINVAL;   // the legacy default stream cannot be captured
     const void* key[6] = {dynamic_set->mean, dynamic_set->scale, dynamic_set->rot, dynamic_set->opacity,
@@ -698,11 +791,61 @@ extern "C" dgsm_status dgsm_plan_run(dgsm_plan p, const dgsm_gaussians_t* dynami
     return hipGraphLaunch(p->exec, s) == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
 
+extern "C" dgsm_status dgsm_plan_time_frame(dgsm_plan p, const dgsm_gaussians_t* dynamic_set,
+                                            const float* translations, float* T_out, float ms[5], void* stream) {
+    if (!p || !dynamic_set || !T_out || !ms) return DGSM_EINVAL;
+    if (dynamic_set->n != p->nd) return DGSM_EINVAL;
+    if (p->motion == DGSM_MOTION_RIGID && p->nd > 0 && !translations) return DGSM_EINVAL;
+    dgsm_status st = validate_gaussians(dynamic_set);
+    if (st != DGSM_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t ev[5] = {};
+    for (int i = 0; i < 5; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) st = DGSM_EHIP;
+    if (st == DGSM_OK && p->nd > 0 && p->motion == DGSM_MOTION_RIGID) {
+        const int64_t o = p->ns;
+        if (hipMemcpyAsync(p->scale + 3 * o, dynamic_set->scale, 12 * p->nd, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(p->rot + 4 * o, dynamic_set->rot, 16 * p->nd, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(p->opacity + o, dynamic_set->opacity, 4 * p->nd, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            st = DGSM_EHIP;
+    }
+    hipEvent_t es[2] = {};
+    if (st == DGSM_OK && (hipEventCreate(&es[0]) != hipSuccess || hipEventCreate(&es[1]) != hipSuccess))
+        st = DGSM_EHIP;
+    if (st == DGSM_OK && p->cache) st = enqueue_static(p, p->static_waves, p->static_units, s, es);
+    if (st == DGSM_OK)
+        st = enqueue_frame(p, 0, 0, dynamic_set, translations, T_out, p->tile_waves, p->split_units, p->pack, s, ev);
+    if (st == DGSM_OK && hipEventSynchronize(ev[4]) != hipSuccess) st = DGSM_EHIP;
+    for (int i = 0; i < 4 && st == DGSM_OK; ++i)
+        if (hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]) != hipSuccess) st = DGSM_EHIP;
+    ms[4] = 0.f;
+    if (st == DGSM_OK && p->cache && hipEventElapsedTime(&ms[4], es[0], es[1]) != hipSuccess) st = DGSM_EHIP;
+    for (int i = 0; i < 5; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i < 2; ++i)
+        if (es[i]) (void)hipEventDestroy(es[i]);
+    return st;
+}
+
 extern "C" int32_t dgsm_plan_tile_waves(const dgsm_plan p) { return p ? p->tile_waves : 0; }
 
 extern "C" int32_t dgsm_plan_split_units(const dgsm_plan p) { return p ? p->split_units : 0; }
 
 extern "C" int32_t dgsm_plan_packed(const dgsm_plan p) { return p ? p->pack : 0; }
+
+extern "C" int32_t dgsm_plan_tuned_from_cache(const dgsm_plan p) { return p && p->tuned_cached ? 1 : 0; }
+
+extern "C" int32_t dgsm_plan_static_knobs(const dgsm_plan p, int32_t out[2]) {
+    if (!p || !out) return 0;
+    out[0] = p->static_waves;
+    out[1] = p->static_units;
+    return 1;
+}
+
+extern "C" void dgsm_autotune_cache_clear(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+}
 
 extern "C" dgsm_status dgsm_plan_destroy(dgsm_plan p) {
     if (!p) return DGSM_EINVAL;

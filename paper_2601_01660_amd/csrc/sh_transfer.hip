@@ -1,12 +1,14 @@
 // Per-Gaussian SH radiance transfer on gfx950 (Sec. 3.4 evaluation, Sec. 3.5).
 //
-// Each workgroup stages chunks of the lat-long grid in LDS as
-// (w_x, w_y, w_z, weight) and (weight * L_r, weight * L_g, weight * L_b)
-// with L = B(w) A evaluated from the probe.  A workgroup serves 64 Gaussians
-// (one per lane, the same 64 in each of its four waves); the four waves sweep
-// every fourth staged direction, and their partial sums are added in wave
-// order at the end (four times the waves of one Gaussian per thread sweeping
-// every direction, for latency).
+// probe_table_kernel evaluates the probe once per call on the lat-long grid
+// into the caller's workspace: per direction j, (w_x, w_y, w_z, weight) and
+// (weight * L_r, weight * L_g, weight * L_b, 0) with L = B(w) A.
+// sh_transfer_kernel streams that table: a workgroup serves 64 Gaussians (one
+// per lane, the same 64 in each of its four waves); wave w sweeps the w-th
+// quarter of the directions, reading each direction with wave-uniform scalar
+// loads (the table entry lands in scalar registers and feeds the vector
+// arithmetic directly, with no LDS traffic), and the four partial sums are
+// added in wave order at the end.
 
 #include "dgsm_device.hpp"
 #include "dgsm_host.hpp"
@@ -15,8 +17,6 @@ namespace dgsm {
 
 constexpr int kShThreads = 256;
 constexpr int kShWaves = kShThreads / kWave;   // waves sharing one lane's Gaussian
-constexpr int kShChunk = 512;
-constexpr int kShG = 1;                        // Gaussians per lane
 
 struct ShArgs {
     const float* probe;      // [kp][3]
@@ -32,6 +32,7 @@ struct ShArgs {
     float* scale_out;
     float* colour_sh_out;
     float* rgb_out;
+    const float4* table;     // [M][2] probe table
 };
 
 // Normal of Gaussian i: rotation column of its smallest scale, facing away
@@ -74,80 +75,66 @@ __device__ inline void finish_gaussian(const ShArgs& a, int64_t i, float4 acc) {
     }
 }
 
-__global__ __launch_bounds__(kShThreads) void sh_transfer_kernel(ShArgs a) {
-    __shared__ float4 dirw[kShChunk];
-    __shared__ float4 lw[kShChunk];
-    __shared__ float4 part[kShWaves][kShG * kWave];
-    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
-    // lane's Gaussians: i0 + 64 g, g < kShG
-    const int64_t i0 = (int64_t)blockIdx.x * (kShG * kWave) + lane;
-    float3 nrm[kShG];
-#pragma unroll
-    for (int g = 0; g < kShG; ++g)
-        nrm[g] = i0 + kWave * g < a.n ? gaussian_normal(a, i0 + kWave * g) : make_float3(0.f, 0.f, 1.f);
-
-    float4 acc[kShG];
-#pragma unroll
-    for (int g = 0; g < kShG; ++g) acc[g] = make_float4(0.f, 0.f, 0.f, 0.f);
-    const int M = a.n_theta * a.n_phi;
-    const float dth = 3.14159265358979324f / (float)a.n_theta;
-    const float dph = 6.28318530717958648f / (float)a.n_phi;
-    for (int c0 = 0; c0 < M; c0 += kShChunk) {
-        const int cnt = min(kShChunk, M - c0);
-        __syncthreads();
-        for (int j = tid; j < cnt; j += kShThreads) {
-            const int gj = c0 + j;
-            const int ia = gj / a.n_phi, ib = gj - ia * a.n_phi;
-            float st, ct, sp, cp;
-            sincosf(((float)ia + 0.5f) * dth, &st, &ct);
-            sincosf(((float)ib + 0.5f) * dph, &sp, &cp);
-            const float wx = st * cp, wy = st * sp, wz = ct;
-            float Y[16];
-            real_sh16(wx, wy, wz, a.kp, Y);
-            float L0 = 0.f, L1 = 0.f, L2 = 0.f;
-            for (int k = 0; k < a.kp; ++k) {
-                L0 += Y[k] * a.probe[3 * k];
-                L1 += Y[k] * a.probe[3 * k + 1];
-                L2 += Y[k] * a.probe[3 * k + 2];
-            }
-            dirw[j] = make_float4(wx, wy, wz, st);
-            lw[j] = make_float4(st * L0, st * L1, st * L2, 0.f);
-        }
-        __syncthreads();
-        // the cosine lobe max(0, n.w)^q; q = 1 (the default) without the power
-        if (a.q == 1.f) {
-            for (int j = wave; j < cnt; j += kShWaves) {
-                const float4 d = dirw[j];
-                const float4 l = lw[j];
-#pragma unroll
-                for (int g = 0; g < kShG; ++g) {
-                    const float S = fmaxf(0.f, nrm[g].x * d.x + nrm[g].y * d.y + nrm[g].z * d.z);
-                    acc[g].x += l.x * S; acc[g].y += l.y * S; acc[g].z += l.z * S; acc[g].w += d.w * S;
-                }
-            }
-        } else {
-            for (int j = wave; j < cnt; j += kShWaves) {
-                const float4 d = dirw[j];
-                const float4 l = lw[j];
-#pragma unroll
-                for (int g = 0; g < kShG; ++g) {
-                    const float c = nrm[g].x * d.x + nrm[g].y * d.y + nrm[g].z * d.z;
-                    const float S = c > 0.f ? __powf(c, a.q) : 0.f;
-                    acc[g].x += l.x * S; acc[g].y += l.y * S; acc[g].z += l.z * S; acc[g].w += d.w * S;
-                }
-            }
-        }
+// Probe radiance and solid-angle weight of every grid direction (cell centres
+// theta_a = (a + 1/2) pi / n_theta, phi_b = (b + 1/2) 2 pi / n_phi, weight
+// sin theta), one thread per direction.
+__global__ __launch_bounds__(256) void probe_table_kernel(const float* __restrict__ probe, int kp, int n_theta,
+                                                          int n_phi, float4* __restrict__ table) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n_theta * n_phi) return;
+    const int ia = j / n_phi, ib = j - ia * n_phi;
+    float st, ct, sp, cp;
+    sincosf(((float)ia + 0.5f) * (3.14159265358979324f / (float)n_theta), &st, &ct);
+    sincosf(((float)ib + 0.5f) * (6.28318530717958648f / (float)n_phi), &sp, &cp);
+    const float wx = st * cp, wy = st * sp, wz = ct;
+    float Y[16];
+    real_sh16(wx, wy, wz, kp, Y);
+    float L0 = 0.f, L1 = 0.f, L2 = 0.f;
+    for (int k = 0; k < kp; ++k) {
+        L0 += Y[k] * probe[3 * k];
+        L1 += Y[k] * probe[3 * k + 1];
+        L2 += Y[k] * probe[3 * k + 2];
     }
-    // the waves' partial sums, added in wave order; wave g finishes Gaussian i0 + 64 g
-#pragma unroll
-    for (int g = 0; g < kShG; ++g) part[wave][g * kWave + lane] = acc[g];
+    table[2 * j] = make_float4(wx, wy, wz, st);
+    table[2 * j + 1] = make_float4(st * L0, st * L1, st * L2, 0.f);
+}
+
+// Table entries are read with a wave-uniform index through the constant
+// address space, so that they land in scalar registers.
+typedef float shf4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) shf4* ShConstPtr;
+
+template <bool LAMBERT>
+__global__ __launch_bounds__(kShThreads) void sh_transfer_kernel(ShArgs a) {
+    __shared__ float4 part[kShWaves][kWave];
+    const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+    const int64_t i = (int64_t)blockIdx.x * kWave + lane;
+    const float3 nrm = i < a.n ? gaussian_normal(a, i) : make_float3(0.f, 0.f, 1.f);
+    const int M = a.n_theta * a.n_phi;
+    const int per = (M + kShWaves - 1) / kShWaves;
+    const int j0 = min(M, wave * per), j1 = min(M, j0 + per);
+    const ShConstPtr tab = (ShConstPtr)(const void*)a.table;
+    float ax = 0.f, ay = 0.f, az = 0.f, aw = 0.f;
+    for (int j = j0; j < j1; ++j) {
+        const shf4 d = tab[2 * j], l = tab[2 * j + 1];
+        const float c = fmaf(nrm.x, d.x, fmaf(nrm.y, d.y, nrm.z * d.z));
+        float S;
+        if (LAMBERT)
+            S = fmaxf(0.f, c);     // the cosine lobe max(0, n.w)^q at q = 1
+        else
+            S = c > 0.f ? __powf(c, a.q) : 0.f;
+        ax = fmaf(l.x, S, ax);
+        ay = fmaf(l.y, S, ay);
+        az = fmaf(l.z, S, az);
+        aw = fmaf(d.w, S, aw);
+    }
+    // the waves' partial sums, added in wave order; wave 0 finishes the Gaussians
+    part[wave][lane] = make_float4(ax, ay, az, aw);
     __syncthreads();
-    if (wave >= kShG) return;
-    const int64_t i = i0 + kWave * wave;
-    if (i >= a.n) return;
+    if (wave != 0 || i >= a.n) return;
     float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int w = 0; w < kShWaves; ++w) {
-        const float4 q = part[w][wave * kWave + lane];
+        const float4 q = part[w][lane];
         sum.x += q.x; sum.y += q.y; sum.z += q.z; sum.w += q.w;
     }
     finish_gaussian(a, i, sum);
@@ -178,9 +165,15 @@ __global__ __launch_bounds__(1024) void centroid_kernel(const float* __restrict_
 
 using namespace dgsm;
 
+extern "C" size_t sh_transfer_workspace_size(int32_t n_theta, int32_t n_phi) {
+    if (n_theta < 1 || n_phi < 1 || (int64_t)n_theta * n_phi > (1 << 24)) return 0;
+    return (size_t)n_theta * n_phi * 2 * sizeof(float4);
+}
+
 extern "C" dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_t* gaussians,
                                    const float* colour_sh, const dgsm_sh_params_t* params, float* scale_out,
-                                   float* colour_sh_out, float* rgb_out, void* stream) {
+                                   float* colour_sh_out, float* rgb_out, void* ws, size_t ws_bytes,
+                                   void* stream) {
     if (!probe_sh || !(Kp == 1 || Kp == 4 || Kp == 9 || Kp == 16)) return DGSM_EINVAL;
     dgsm_status st = validate_gaussians(gaussians);
     if (st != DGSM_OK) return st;
@@ -190,12 +183,21 @@ extern "C" dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm
     if ((int64_t)params->n_theta * params->n_phi > (1 << 24)) return DGSM_EINVAL;
     if ((colour_sh_out || rgb_out) && !colour_sh) return DGSM_EINVAL;
     if (gaussians->n > 0 && !scale_out) return DGSM_EINVAL;
+    if (!ws || ws_bytes < sh_transfer_workspace_size(params->n_theta, params->n_phi)) return DGSM_EWORKSPACE;
     if (gaussians->n == 0) return DGSM_OK;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int M = params->n_theta * params->n_phi;
+    float4* table = reinterpret_cast<float4*>(ws);
+    probe_table_kernel<<<(M + 255) / 256, 256, 0, s>>>(probe_sh, Kp, params->n_theta, params->n_phi, table);
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     ShArgs a{probe_sh, Kp, gaussians->mean, gaussians->scale, gaussians->rot, gaussians->n, colour_sh,
              params->centroid, params->n_theta, params->n_phi, params->q, params->clip_max, params->eps,
-             params->gamma, scale_out, colour_sh_out, rgb_out};
-    const unsigned blocks = (unsigned)((gaussians->n + kShG * kWave - 1) / (kShG * kWave));
-    sh_transfer_kernel<<<blocks, kShThreads, 0, reinterpret_cast<hipStream_t>(stream)>>>(a);
+             params->gamma, scale_out, colour_sh_out, rgb_out, table};
+    const unsigned blocks = (unsigned)((gaussians->n + kWave - 1) / kWave);
+    if (params->q == 1.f)
+        sh_transfer_kernel<true><<<blocks, kShThreads, 0, s>>>(a);
+    else
+        sh_transfer_kernel<false><<<blocks, kShThreads, 0, s>>>(a);
     return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
 

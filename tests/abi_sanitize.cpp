@@ -84,8 +84,11 @@ int main(int argc, char** argv) {
     EXPECT(dgsm_plan_tile_waves(nullptr) == 0 && dgsm_plan_packed(nullptr) == 0);
 
     dgsm_sh_params_t sp{32, 64, 1.f, 4.f, 1e-6f, 1.f, ff};
-    EXPECT(sh_transfer(ff, 5, &G, nullptr, &sp, static_cast<float*>(fake), nullptr, nullptr, nullptr) ==
-           DGSM_EINVAL);
+    EXPECT(sh_transfer(ff, 5, &G, nullptr, &sp, static_cast<float*>(fake), nullptr, nullptr, fake, 1 << 20,
+                       nullptr) == DGSM_EINVAL);
+    EXPECT(sh_transfer(ff, 9, &G, nullptr, &sp, static_cast<float*>(fake), nullptr, nullptr, fake, 16, nullptr) ==
+           DGSM_EWORKSPACE);
+    EXPECT(sh_transfer_workspace_size(32, 64) == 32 * 64 * 32 && sh_transfer_workspace_size(0, 64) == 0);
     EXPECT(dgsm_probe_fit_workspace_size(3) == 0);
     EXPECT(dgsm_mlp_workspace_size(33) == 0);
     EXPECT(dgsm_mlp_check_grid_workspace_size(&d, -1) == 0);

@@ -130,10 +130,13 @@ def test_null_pointers_and_small_workspace_are_rejected(lib):
     assert lib.dgsm_build(ctypes.byref(lt0), ctypes.byref(gs), ctypes.byref(d), 1, 1, 1 << 40, None) == 1
     assert lib.dgsm_query(ctypes.byref(lt), ctypes.byref(d), None, 1, 10, 1, None) == 1
     prm = P._ShParams(32, 64, 1.0, 4.0, 1e-6, 1.0, 0)
-    assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, None, None) == 1
+    ws = 1 << 20
+    assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, None, 1, ws, None) == 1
     prm = P._ShParams(32, 64, 1.0, 4.0, 1e-6, 1.0, 1)
-    assert lib.sh_transfer(1, 5, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, None, None) == 1
-    assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, 1, None) == 1
+    assert lib.sh_transfer(1, 5, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, None, 1, ws, None) == 1
+    assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, 1, 1, ws, None) == 1
+    assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, None, 1, 64, None) == 2
+    assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, None, None, ws, None) == 2
 
 
 @fake_pointers

@@ -224,3 +224,33 @@ def test_plan_free_motion_matches_plain(scene, cache):
     assert err <= 2e-6
     _graph_equals_eager(plan, dyn, None, eager)
     plan.close()
+
+
+def test_autotune_cache_serves_a_second_plan_of_the_same_workload(scene):
+    import paper_2601_01660_amd as P
+    lib = P.lib()
+    lib.dgsm_autotune_cache_clear()
+    atlas = P.Atlas(40, 40, 12, dtype="f16")
+    lights = torch.from_numpy(scene["lights"])
+    static = P.GaussianSet.from_host(scene["static"])
+    dyn = P.GaussianSet.from_host(scene["dyn"])
+    tr = torch.from_numpy(scene["traj"]).cuda()
+    F = scene["traj"].shape[0]
+    a = P.Plan(lights, atlas, static, scene["dyn"].n, F, autotune=True)
+    out_a = a.run(dyn, tr, use_graph=False).clone()
+    torch.cuda.synchronize()
+    knobs = (a.tile_waves, a.split_units, a.packed)
+    assert not a.tuned_from_cache
+    b = P.Plan(lights, atlas, static, scene["dyn"].n, F, autotune=True)
+    out_b = b.run(dyn, tr, use_graph=False).clone()
+    torch.cuda.synchronize()
+    assert b.tuned_from_cache and (b.tile_waves, b.split_units, b.packed) == knobs
+    assert torch.equal(out_a, out_b)
+    lib.dgsm_autotune_cache_clear()
+    c = P.Plan(lights, atlas, static, scene["dyn"].n, F, autotune=True)
+    c.run(dyn, tr, use_graph=False)
+    torch.cuda.synchronize()
+    assert not c.tuned_from_cache
+    print(f"[batched] tuned knobs {knobs} served from the cache to a second plan", flush=True)
+    for p in (a, b, c):
+        p.close()
