@@ -70,14 +70,10 @@ __device__ inline float fourier_exact(double c, float x, bool cosine) {
 __device__ inline void fourier_pair(double c, double x, float& s, float& co) {
     const double ph = c * x;
     const double r = ph - rint(ph);
-#ifdef DGSM_MLP_FAST_SINES
-    sincospif(2.f * (float)r, &s, &co);
-#else
     double sd, cd;
     sincospi(2.0 * r, &sd, &cd);
     s = (float)sd;
     co = (float)cd;
-#endif
 }
 
 // Feature f (0..127) of a row; ct[i] = turns_per_unit(i, W).

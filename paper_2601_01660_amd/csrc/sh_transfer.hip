@@ -104,6 +104,24 @@ __global__ __launch_bounds__(256) void probe_table_kernel(const float* __restric
 typedef float shf4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) shf4* ShConstPtr;
 
+// One direction's contribution to a lane's four sums.
+template <bool LAMBERT>
+__device__ inline void sh_accum(const float3& nrm, float q, float dx, float dy, float dz, float dw, float lx,
+                                float ly, float lz, float& ax, float& ay, float& az, float& aw) {
+    const float c = fmaf(nrm.x, dx, fmaf(nrm.y, dy, nrm.z * dz));
+    float S;
+    if (LAMBERT)
+        S = fmaxf(0.f, c);     // the cosine lobe max(0, n.w)^q at q = 1
+    else
+        S = c > 0.f ? __powf(c, q) : 0.f;
+    ax = fmaf(lx, S, ax);
+    ay = fmaf(ly, S, ay);
+    az = fmaf(lz, S, az);
+    aw = fmaf(dw, S, aw);
+}
+
+constexpr int kShUnroll = 8;   // directions per scalar-load batch
+
 template <bool LAMBERT>
 __global__ __launch_bounds__(kShThreads) void sh_transfer_kernel(ShArgs a) {
     __shared__ float4 part[kShWaves][kWave];
@@ -112,22 +130,31 @@ __global__ __launch_bounds__(kShThreads) void sh_transfer_kernel(ShArgs a) {
     const float3 nrm = i < a.n ? gaussian_normal(a, i) : make_float3(0.f, 0.f, 1.f);
     const int M = a.n_theta * a.n_phi;
     const int per = (M + kShWaves - 1) / kShWaves;
-    const int j0 = min(M, wave * per), j1 = min(M, j0 + per);
-    const ShConstPtr tab = (ShConstPtr)(const void*)a.table;
+    // wave-uniform range (readfirstlane: the compiler then knows it, and the
+    // table reads below become scalar loads)
+    const int j0 = __builtin_amdgcn_readfirstlane(min(M, wave * per));
+    const int j1 = __builtin_amdgcn_readfirstlane(min(M, j0 + per));
     float ax = 0.f, ay = 0.f, az = 0.f, aw = 0.f;
-    for (int j = j0; j < j1; ++j) {
-        const shf4 d = tab[2 * j], l = tab[2 * j + 1];
-        const float c = fmaf(nrm.x, d.x, fmaf(nrm.y, d.y, nrm.z * d.z));
-        float S;
-        if (LAMBERT)
-            S = fmaxf(0.f, c);     // the cosine lobe max(0, n.w)^q at q = 1
-        else
-            S = c > 0.f ? __powf(c, a.q) : 0.f;
-        ax = fmaf(l.x, S, ax);
-        ay = fmaf(l.y, S, ay);
-        az = fmaf(l.z, S, az);
-        aw = fmaf(d.w, S, aw);
+    const ShConstPtr tab = (ShConstPtr)(const void*)a.table;
+    int j = j0;
+    // batches of kShUnroll directions: all their scalar loads are issued before
+    // the arithmetic that uses them
+    for (; j + kShUnroll <= j1; j += kShUnroll) {
+        shf4 d[kShUnroll], l[kShUnroll];
+#pragma unroll
+        for (int u = 0; u < kShUnroll; ++u) {
+            d[u] = tab[2 * (j + u)];
+            l[u] = tab[2 * (j + u) + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kShUnroll; ++u)
+            sh_accum<LAMBERT>(nrm, a.q, d[u].x, d[u].y, d[u].z, d[u].w, l[u].x, l[u].y, l[u].z, ax, ay, az, aw);
     }
+    for (; j < j1; ++j) {
+        const shf4 d = tab[2 * j], l = tab[2 * j + 1];
+        sh_accum<LAMBERT>(nrm, a.q, d.x, d.y, d.z, d.w, l.x, l.y, l.z, ax, ay, az, aw);
+    }
+
     // the waves' partial sums, added in wave order; wave 0 finishes the Gaussians
     part[wave][lane] = make_float4(ax, ay, az, aw);
     __syncthreads();

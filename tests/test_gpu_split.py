@@ -86,7 +86,7 @@ def test_split_is_bitwise_unsplit(cluster, dtype, cache):
 def test_packed_walk_is_bitwise_the_tile_walk(cluster, dtype, spacing):
     """The packed walk (only pairs past the distance pre-test, 64 per wave)
     adds exactly the increments of the tile walk: the atlas is bitwise the same
-    for every tile width, with and without split tiles."""
+    for every number of waves per tile, with and without split tiles."""
     import paper_2601_01660_amd as P
     g = synth.Gaussians.concat([cluster["bg"], cluster["dense"]])
     lights = torch.from_numpy(np.array([[0.1, -0.2, 1.6], [-1.0, 0.7, 1.2]], np.float32)).cuda()
