@@ -330,13 +330,14 @@ def transmittance_at(light, gaussians, points, kappa=1.0, chunk=4096):
 
 def dropped_depth_bound(light, gaussians, rows, cols, H, W, eps, kappa=1.0, param="octahedral", chunk=65536):
     """Error budget of a culled build at the given texels (Sec. 3.2 "Occluder
-    culling via light-space footprints").  A culled build may leave Gaussian i
-    out along a texel direction d only where its whole-line optical depth,
-    2 P0 = 2 beta_i sqrt(pi / (2 a)) exp(-(c - b^2/a) / 2) (Eq. 3 taken from
-    t = -inf to +inf, an upper bound of every partial integral), is at most
-    eps.  Returns per texel (sum of 2 P0 over the Gaussians at or below eps --
-    the most optical depth such a build can drop there -- and the number of
-    Gaussians above eps, each of which a build evaluates)."""
+    culling via light-space footprints").  A shell's optical depth integrates
+    Eq. 2 along the texel ray from the light (t >= 0), so leaving Gaussian i
+    out along direction d lowers every shell by at most its depth along the
+    whole ray, beta_i times Eq. 3 with t -> inf; a culled build may leave a
+    Gaussian out only where that depth is at most eps.  Returns per texel (the
+    sum of the ray depths at or below eps -- the most optical depth such a
+    build can drop there -- and the number of Gaussians above eps, each of
+    which a build evaluates)."""
     mean, A, beta = gaussian_terms(gaussians, kappa)
     dirs = _texel_dirs_at(rows, cols, H, W, param)
     dropped = np.zeros(dirs.shape[0])
@@ -344,9 +345,9 @@ def dropped_depth_bound(light, gaussians, rows, cols, H, W, eps, kappa=1.0, para
     for s in range(0, mean.shape[0], chunk):
         e = slice(s, s + chunk)
         a, b, c = ray_quadratic(dirs, light, mean[e], A[e])
-        full = 2 * beta[e][None, :] * np.sqrt(np.pi / (2 * a)) * np.exp(-0.5 * (c[None, :] - b * b / a))
-        small = full <= eps
-        dropped += np.where(small, full, 0.0).sum(axis=1)
+        ray = beta[e][None, :] * line_integral(a, b, c[None, :], np.inf)
+        small = ray <= eps
+        dropped += np.where(small, ray, 0.0).sum(axis=1)
         kept += (~small).sum(axis=1)
     return dropped, kept
 
