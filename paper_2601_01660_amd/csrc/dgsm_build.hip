@@ -10,8 +10,9 @@
 //   bases_kernel       supertile list bases, padded to 64-entry chunks
 //   scatter_kernel     stable compaction of Gaussian ids into supertile lists
 //                      (ascending id within a list: the summation order is fixed)
-//   tile_mask_kernel   each list entry against the <= 64 tiles of its supertile,
-//                      transposed into one 64-bit hit word per (tile, chunk)
+//   tile_mask_kernel   each list entry against the <= 64 tiles of its supertile
+//                      (cone test, then a separating-plane test), transposed
+//                      into one 64-bit hit word per (tile, chunk)
 //   tile_build_kernel  one wave per tile: walk its hit words; for every
 //        (texel, Gaussian) pair evaluate Eq. 3 on the shells where the erf
 //        ramps and add the per-shell increments in LDS; prefix over shells,
@@ -138,6 +139,16 @@ struct PrepArgs {
     unsigned char* ws;
 };
 
+// Scale of the tile test's separating plane (see tile_mask_kernel): the
+// squared light-to-mean distance over lg P^2, with P^2 = det(Sigma) =
+// (s_1 s_2 s_3)^2, and a 3% margin for the FP32 rounding of that test.  0 (the
+// plane test never culls) without culling or where the ratio is not finite.
+__device__ inline float plane_q(double mx, double my, double mz, float lg, float P2, float eps) {
+    if (!(eps > 0.f)) return 0.f;
+    const double q = (mx * mx + my * my + mz * mz) / ((double)lg * (double)P2 * 1.03);
+    return (q >= 0.0 && q < 3.0e38) ? (float)q : 0.f;
+}
+
 __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
     __shared__ int bcnt[kMaxSuper];          // this block's entries per supertile
     __shared__ float4 sc[kMaxSuper];         // supertile cones
@@ -217,15 +228,22 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
             r.r0 = (float)R0;
             R0 = (double)r.r0;                           // as later frames will read it
             for (int j = 0; j < 4; ++j) r.pad[j] = 0.f;
+            r.pad[1] = (float)(s[0] * s[1] * s[2] * s[0] * s[1] * s[2]);   // det(Sigma) = P^2
+            r.pad[2] = (float)fmin(smax / fmin(s[0], fmin(s[1], s[2])), 3.0e38);   // kappa(C) = s_max / s_min
             r.mx = (double)light[0] - (double)a.mean[3 * i];
             r.my = (double)light[1] - (double)a.mean[3 * i + 1];
             r.mz = (double)light[2] - (double)a.mean[3 * i + 2];
+            r.pad[0] = plane_q(r.mx, r.my, r.mz, r.lg, r.pad[1], a.eps);
             W.rec[i] = r;
         } else {
             R0 = (double)W.rec[i].r0;
-            W.rec[i].mx = (double)light[0] - (double)a.mean[3 * i];
-            W.rec[i].my = (double)light[1] - (double)a.mean[3 * i + 1];
-            W.rec[i].mz = (double)light[2] - (double)a.mean[3 * i + 2];
+            const double mx = (double)light[0] - (double)a.mean[3 * i];
+            const double my = (double)light[1] - (double)a.mean[3 * i + 1];
+            const double mz = (double)light[2] - (double)a.mean[3 * i + 2];
+            W.rec[i].mx = mx;
+            W.rec[i].my = my;
+            W.rec[i].mz = mz;
+            W.rec[i].pad[0] = plane_q(mx, my, mz, W.rec[i].lg, W.rec[i].pad[1], a.eps);
         }
 
         // Culling cone.  Along any ray the contribution is at most
@@ -274,7 +292,8 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
             const int sy = 2 * gy + (d >> 1), sx = 2 * gx + (d & 1);
             if (sy >= a.SGH || sx >= a.SGW) continue;
             const int sidx = sy * a.SGW + sx;
-            if (hit_g && cones_touch_c(cone, ca, sc[sidx], scs[sidx])) {
+            const bool hit = hit_g && cones_touch_c(cone, ca, sc[sidx], scs[sidx]);
+            if (hit) {
                 const uint64_t bit = 1ull << (sidx & 63);
                 switch (sidx >> 6) {
                     case 0: m[0] |= bit; break;
@@ -282,8 +301,11 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
                     case 2: m[2] |= bit; break;
                     default: m[3] |= bit; break;
                 }
-                atomicAdd(&bcnt[sidx], 1);
             }
+            // one LDS add per wave and supertile (the Gaussians of a wave tend to
+            // reach the same few supertiles: per-lane adds would serialise)
+            const uint64_t hb = ballot(hit);
+            if (hb != 0ull && lane_id() == __builtin_ctzll(hb)) atomicAdd(&bcnt[sidx], __popcll(hb));
         }
     }
     if (in)
@@ -404,13 +426,95 @@ __global__ __launch_bounds__(kPrepThreads) void scatter_kernel(unsigned char* ws
 // Level 2: tile hit words.  One wave per 64-entry chunk of a supertile list.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, BuildLayout lay, Geom g) {
+// Anisotropic tile test (Sec. 3.2 "Occluder culling via light-space
+// footprints"), after the cone test.  Let E be the ellipsoid
+// (x - mu)^T Sigma^-1 (x - mu) < lg around the mean (mu relative to the light,
+// D = |mu|, g = mu / D).  A ray from the light that misses E carries at most
+// cull_eps of the Gaussian's optical depth (the bound behind lg, with e >= lg
+// along the whole ray).  E and the ray cone of a tile (axis c, half-angle
+// alpha, beta = angle(g, c) > alpha) are separated by the plane through the
+// light with normal n = sin(th) g - cos(th) u, th = min(beta - alpha, pi/2), u
+// the unit vector from g towards c in their plane: every ray of the cone has
+// n.x <= 0, and E lies in n.x > 0 when D sin(th) > sqrt(lg n^T Sigma n).  With
+// Sigma = P^2 C^T C (C the rows c_j of the record, P^2 = det Sigma) and
+// n sin(beta) = cos(alpha) g - cos(th) c, the test reads
+//   (sin(beta) sin(th))^2 D^2 / (lg P^2) > |C (cos(alpha) g - cos(th) c)|^2
+// (th < pi/2), or D^2 / (lg P^2) > |C g|^2 (th = pi/2); q = D^2 / (lg P^2) is
+// kept with a 3% margin.  For an isotropic Gaussian this is the cone test; for
+// the room's Gaussians it drops about a third of the cone test's tile hits.
+// FP32 rounding: alpha is inflated by the tile cone (>= 2e-6 rad against
+// 2e-7 of axis rounding); the errors (<= 3e-7) of sin(th), cos(th), g and c
+// move |C (cos(alpha) g - cos(th) c)| by at most 7e-7 kappa / sin(beta)
+// relative (kappa = s_max / s_min, the condition number of C; the vector is
+// at least sigma_min(C) sin(beta) long) and sin(th) by 3e-7 / sin(th), so the
+// test culls only where sin(th) > 2e-4 and kappa < 7000 sin(beta): the squared
+// sides then move by at most 1% and 0.3%, inside the margin.
+struct MaskEntry {
+    float4 cone;
+    float C[9];    // rows c_j of the record
+    float q;       // plane scale (0: never culls)
+    float kappa;   // s_max / s_min
+};
+
+struct PlaneEntry {
+    float gx, gy, gz;      // cone axis g
+    float Cg0, Cg1, Cg2;   // C g
+    float gg;              // |C g|^2
+    float q, kappa;
+    const float* C;
+};
+
+__device__ inline PlaneEntry plane_entry(const MaskEntry& e) {
+    PlaneEntry p;
+    p.gx = e.cone.x; p.gy = e.cone.y; p.gz = e.cone.z;
+    p.Cg0 = e.C[0] * p.gx + e.C[1] * p.gy + e.C[2] * p.gz;
+    p.Cg1 = e.C[3] * p.gx + e.C[4] * p.gy + e.C[5] * p.gz;
+    p.Cg2 = e.C[6] * p.gx + e.C[7] * p.gy + e.C[8] * p.gz;
+    p.gg = p.Cg0 * p.Cg0 + p.Cg1 * p.Cg1 + p.Cg2 * p.Cg2;
+    p.q = e.q;
+    p.kappa = e.kappa;
+    p.C = e.C;
+    return p;
+}
+
+// cos and sin of a tile cone's half-angle alpha from sin(alpha/2) and cos(alpha/2)
+__device__ inline float2 cone_cos_sin(float4 tc, float tcs) {
+    return make_float2(1.f - 2.f * tc.w * tc.w, 2.f * tc.w * tcs);
+}
+
+// true unless the plane separates the tile cone (axis tc.xyz, half-angle with
+// cosine and sine cs) from the entry's ellipsoid
+__device__ inline bool plane_keeps(const PlaneEntry& p, float4 tc, float2 cs) {
+    const float cb = p.gx * tc.x + p.gy * tc.y + p.gz * tc.z;
+    const float xx = p.gy * tc.z - p.gz * tc.y, xy = p.gz * tc.x - p.gx * tc.z, xz = p.gx * tc.y - p.gy * tc.x;
+    const float sb = __builtin_amdgcn_sqrtf(xx * xx + xy * xy + xz * xz);
+    const float cal = cs.x, sal = cs.y;
+    const float sth = sb * cal - cb * sal;                                 // sin(beta - alpha)
+    if (!(sth > 2e-4f) || !(sb * 7000.f > p.kappa)) return true;
+    const float cth = cb * cal + sb * sal;                                 // cos(beta - alpha)
+    if (cth <= 0.f) return !(p.q > p.gg);                                  // th = pi/2: n = g
+    const float* C = p.C;
+    const float v0 = cal * p.Cg0 - cth * (C[0] * tc.x + C[1] * tc.y + C[2] * tc.z);
+    const float v1 = cal * p.Cg1 - cth * (C[3] * tc.x + C[4] * tc.y + C[5] * tc.z);
+    const float v2 = cal * p.Cg2 - cth * (C[6] * tc.x + C[7] * tc.y + C[8] * tc.z);
+    const float ss = sb * sth;
+    return !(ss * ss * p.q > v0 * v0 + v1 * v1 + v2 * v2);
+}
+
+__global__ __launch_bounds__(256, 8) void tile_mask_kernel(unsigned char* ws, BuildLayout lay, Geom g) {
     __shared__ int sbase[kMaxSuper + 1];
     __shared__ int stot[kMaxSuper];
     // per wave: the cones (and cone_cos) of the tiles and quads of its current
     // supertile, read back with wave-uniform addresses (broadcast)
     __shared__ float4 ltc[4][kWave];
     __shared__ float ltcs[4][kWave];
+    __shared__ float2 ltca[4][kWave];      // cos, sin of each tile cone's half-angle (plane test)
+    __shared__ unsigned long long lres[4][kWave];   // per wave: tile words of the current chunk
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
     __shared__ float4 lqc[4][16];
     __shared__ float lqcs[4][16];
     const LightWs W = light_ws(ws, lay, blockIdx.y);
@@ -436,23 +540,33 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
     int s_cur = -1, cnt = 0;
     SuperSpan sp_cur{0, 0, 0, 0};
     int q0y = 0, q0x = 0, nqy_s = 0, nqx_s = 0;
-    // cone of this lane's entry of chunk c (one chunk ahead: the dependent
-    // list -> cone loads of the next chunk are in flight while this one is tested)
-    auto entry_cone = [&](int c) {
+    // The list ids and cones of chunk c + 1 are loaded while chunk c is tested
+    // (the cone load waits for its id only).  The loads are unconditional -- a
+    // lane without an entry reads the chunk's padding and Gaussian 0 and
+    // discards them -- so each wait covers just the loads it needs.  The plane
+    // test's record rows are loaded after the cone tests (kept out of the
+    // registers of the cone loop: 8 waves per SIMD).
+    const float4 kDead = make_float4(0.f, 0.f, 1.f, -1.f);
+    auto list_id = [&](int c, bool& valid) {
         int lo = 0, hi = g.S - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (sbase[mid] <= 64 * c) lo = mid; else hi = mid - 1;
         }
         const int e = 64 * c + lane;
-        float4 cn = make_float4(0.f, 0.f, 1.f, -1.f);
-        if (e < sbase[lo] + stot[lo]) cn = W.cone[W.lists[e]];
-        return cn;
+        valid = e < sbase[lo] + stot[lo];
+        return W.lists[e];                         // e < lbase[S]: inside the lists
     };
-    float4 next_cone = cbeg < cend ? entry_cone(cbeg) : make_float4(0.f, 0.f, 1.f, -1.f);
+    bool nvalid = false;
+    int nid = cbeg < cend ? list_id(cbeg, nvalid) : 0;
+    float4 ncone = kDead;
+    if (cbeg < cend) ncone = W.cone[nvalid ? nid : 0];
     for (int c = cbeg; c < cend; ++c) {
-        const float4 cone = next_cone;
-        if (c + 1 < cend) next_cone = entry_cone(c + 1);
+        const bool valid = nvalid;
+        const int gi = valid ? nid : 0;
+        const float4 cone = valid ? ncone : kDead;   // dead (w < 0): never reaches a tile
+        if (c + 1 < cend) nid = list_id(c + 1, nvalid);
+        if (c + 1 < cend) ncone = W.cone[nvalid ? nid : 0];
         // supertile of this chunk: the last s with sbase[s] <= 64 c
         int lo = 0, hi = g.S - 1;
         while (lo < hi) {
@@ -475,6 +589,7 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
                 const int t = (sp_cur.ty0 + lane / sp_cur.ntx) * g.TW + sp_cur.tx0 + lane % sp_cur.ntx;
                 ltc[wv][lane] = tcone[t];
                 ltcs[wv][lane] = tcos[t];
+                ltca[wv][lane] = cone_cos_sin(tcone[t], tcos[t]);
             }
             if (lane < nqy_s * nqx_s) {
                 const int qi = (q0y + lane / nqx_s) * nqx + q0x + lane % nqx_s;
@@ -488,11 +603,13 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
         const SuperSpan sp = sp_cur;
         const int nt = sp.nty * sp.ntx;
         const float ca = cone_cos(cone);
-        uint64_t mine = 0;
+        uint64_t mine = 0, row = 0;
         // quads first: the tiles of a quad no lane's cone reaches are skipped.
         // A lane keeps a tile only if its own cone reaches the quad too, so the
         // result never depends on which entries share the wave (with rounding,
         // a tile test can pass where the enclosing quad's test fails).
+        // mine (lane t): the entries whose cone reaches tile t; row: the tiles
+        // this lane's cone reaches.
         for (int q = 0; q < nqy_s * nqx_s; ++q) {
             const bool hit_q = cones_touch_c(cone, ca, lqc[wv][q], lqcs[wv][q]);
             if (ballot(hit_q) == 0ull) continue;
@@ -501,10 +618,39 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
                 const int ly = 2 * qy + (d >> 1), lx = 2 * qx + (d & 1);   // tile inside the supertile
                 if (ly >= sp.nty || lx >= sp.ntx) continue;
                 const int t = ly * sp.ntx + lx;
-                const uint64_t bal = ballot(hit_q && cones_touch_c(cone, ca, ltc[wv][t], ltcs[wv][t]));
+                const bool hit = hit_q && cones_touch_c(cone, ca, ltc[wv][t], ltcs[wv][t]);
+                const uint64_t bal = ballot(hit);
+                if (hit) row |= 1ull << t;
                 if (lane == t) mine = bal;
             }
         }
+        // The plane test on each lane's own cone hits only: the SIMD work is
+        // the largest number of such tiles of any lane (a few), not every tile
+        // some lane's cone reaches (most of the supertile).  A failed test
+        // clears the lane's bit in the tile's word.
+        lres[wv][lane] = mine;
+        wave_sync();
+        MaskEntry ent;                                  // the plane test's rows and scale
+        ent.cone = cone;
+        {
+            const GRec* rp = W.rec + gi;
+            for (int j = 0; j < 9; ++j) ent.C[j] = rp->c[j];
+            ent.q = rp->pad[0];
+            ent.kappa = rp->pad[2];
+        }
+        const PlaneEntry pe = plane_entry(ent);
+        while (ballot(row != 0ull) != 0ull) {
+            if (row != 0ull) {
+                const int t = __builtin_ctzll(row);
+                row &= row - 1;
+                if (!plane_keeps(pe, ltc[wv][t], ltca[wv][t]))
+                    __hip_atomic_fetch_and(&lres[wv][t], ~(1ull << lane), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+        wave_sync();
+        mine = lres[wv][lane];
+        wave_sync();                                   // read before the next chunk overwrites it
         const int c0 = sbase[s] / 64, ns = (sbase[s + 1] - sbase[s]) / 64;
         if (lane < nt) {
             W.bits[64 * (size_t)c0 + (size_t)lane * ns + (c - c0)] = mine;
@@ -515,6 +661,7 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
         atomicAdd(W.hits + (sp_cur.ty0 + lane / sp_cur.ntx) * g.TW + sp_cur.tx0 + lane % sp_cur.ntx, cnt);
 }
 
+
 // ---------------------------------------------------------------------------
 // Receiver region of interest (Sec. 3.2): only the texels and the radial range
 // that receivers read are kept; everything else is T = 1 by construction.
@@ -523,53 +670,88 @@ __global__ __launch_bounds__(256) void tile_mask_kernel(unsigned char* ws, Build
 // full atlas.
 // ---------------------------------------------------------------------------
 
+// Receiver marks go to a byte per texel (plain stores of 1: every receiver
+// that reads a texel writes the same value, so no atomics are needed), kept
+// in the storage of the supertile masks, which nothing reads after the
+// scatter.  A pack pass then turns each tile's 64 bytes into its 64-bit
+// region mask.  The shell range is reduced per block before its two atomics.
 __global__ __launch_bounds__(256) void roi_clear_kernel(unsigned char* ws, BuildLayout lay, Geom g) {
     const LightWs W = light_ws(ws, lay, blockIdx.y);
     const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t < g.ntiles) W.roi_mask[t] = 0ull;
+    uint32_t* map = reinterpret_cast<uint32_t*>(W.mask);
+    const int nw = (g.H * g.W + 3) / 4;
+    for (int q = t; q < nw; q += gridDim.x * 256) map[q] = 0u;
     if (t == 0) {
         W.roi_k[0] = g.K;
         W.roi_k[1] = -1;
     }
 }
 
+constexpr int kRoiMarkBlocks = 1024;   // blocks per light of the (grid-stride) marking pass
+
 __global__ __launch_bounds__(256) void roi_mark_kernel(unsigned char* ws, BuildLayout lay, Geom g,
                                                        const float* __restrict__ lights,
                                                        const float* __restrict__ pts, int64_t n, RoiBox box,
                                                        float lr0, float kscale) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool in = i < n;
-    float x = 0.f, y = 0.f, z = 0.f;
-    if (in) {
-        x = pts[3 * i];
-        y = pts[3 * i + 1];
-        z = pts[3 * i + 2];
-        in = !(box.half > 0.f) ||
-             (fabsf(x - box.cx) <= box.half && fabsf(y - box.cy) <= box.half && z >= box.zmin && z <= box.zmax);
-    }
+    __shared__ int red[2][256 / kWave];
     const int l = blockIdx.y;
     const LightWs W = light_ws(ws, lay, l);
-    const Cell c = query_cell(g, lr0, kscale, lights + 3 * l, x, y, z);
-    if (in)
+    unsigned char* map = reinterpret_cast<unsigned char*>(W.mask);
+    int kmn = g.K, kmx = -1;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
+        const bool in = !(box.half > 0.f) || (fabsf(x - box.cx) <= box.half && fabsf(y - box.cy) <= box.half &&
+                                              z >= box.zmin && z <= box.zmax);
+        if (!in) continue;
+        const Cell c = query_cell(g, lr0, kscale, lights + 3 * l, x, y, z);
         for (int d = 0; d < 4; ++d) {
             int ii = c.i0 + (d >> 1), jj = c.j0 + (d & 1);
             wrap_texel(ii, jj, g.H, g.W);
-            atomicOr(W.roi_mask + (ii >> 3) * g.TW + (jj >> 3), 1ull << ((ii & 7) * kTile + (jj & 7)));
+            map[(size_t)ii * g.W + jj] = 1;
         }
-    // shell range: one atomic per wave (every receiver would hit the same two words)
-    const int kmn = wave_min(in ? c.k0 : g.K), kmx = wave_max(in ? c.k0 + 1 : -1);
-    if ((threadIdx.x % kWave) == 0 && kmn <= kmx) {
-        atomicMin(W.roi_k, kmn);
-        atomicMax(W.roi_k + 1, kmx);
+        kmn = min(kmn, c.k0);
+        kmx = max(kmx, c.k0 + 1);
+    }
+    kmn = wave_min(kmn);
+    kmx = wave_max(kmx);
+    const int wave = threadIdx.x / kWave;
+    if (threadIdx.x % kWave == 0) {
+        red[0][wave] = kmn;
+        red[1][wave] = kmx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 256 / kWave; ++w) {
+            kmn = min(kmn, red[0][w]);
+            kmx = max(kmx, red[1][w]);
+        }
+        if (kmn <= kmx) {
+            atomicMin(W.roi_k, kmn);
+            atomicMax(W.roi_k + 1, kmx);
+        }
     }
 }
 
-// Tiles outside the region do no work: their hit counts are cleared so that
-// the work-unit planner does not split them.
-__global__ __launch_bounds__(256) void roi_prune_kernel(unsigned char* ws, BuildLayout lay, Geom g) {
+// Region mask of every tile from the texel bytes; tiles outside the region
+// do no work: their hit counts are cleared so that the work-unit planner does
+// not split them.
+__global__ __launch_bounds__(256) void roi_pack_kernel(unsigned char* ws, BuildLayout lay, Geom g) {
     const LightWs W = light_ws(ws, lay, blockIdx.y);
     const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t < g.ntiles && W.roi_mask[t] == 0ull) W.hits[t] = 0;
+    if (t >= g.ntiles) return;
+    const unsigned char* map = reinterpret_cast<const unsigned char*>(W.mask);
+    const int ty = t / g.TW, tx = t - ty * g.TW;
+    uint64_t m = 0;
+    for (int r = 0; r < kTile; ++r) {
+        const int i = ty * kTile + r;
+        if (i >= g.H) break;
+        for (int c = 0; c < kTile; ++c) {
+            const int j = tx * kTile + c;
+            if (j < g.W && map[(size_t)i * g.W + j]) m |= 1ull << (r * kTile + c);
+        }
+    }
+    W.roi_mask[t] = m;
+    if (m == 0ull) W.hits[t] = 0;
 }
 
 dgsm_status enqueue_roi(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
@@ -585,11 +767,12 @@ dgsm_status enqueue_roi(const Geom& g, const BuildLayout& L, unsigned char* ws, 
         } else {
             kscale = (float)g.K / g.r1;
         }
-        roi_mark_kernel<<<dim3((unsigned)((n_points + 255) / 256), lights.n), 256, 0, st>>>(
+        const int64_t nb = (n_points + 255) / 256;
+        roi_mark_kernel<<<dim3((unsigned)(nb < kRoiMarkBlocks ? nb : kRoiMarkBlocks), lights.n), 256, 0, st>>>(
             ws, L, g, lights.pos, points, n_points, box, lr0, kscale);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }
-    roi_prune_kernel<<<tg, 256, 0, st>>>(ws, L, g);
+    roi_pack_kernel<<<tg, 256, 0, st>>>(ws, L, g);
     return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
 
@@ -1494,7 +1677,11 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights, int64_t cap) {
     L.lbase = take((size_t)(kMaxSuper + 1) * sizeof(int));
     L.rec = take((size_t)n * sizeof(GRec));
     L.cone = take((size_t)n * sizeof(float4));
-    L.mask = take((size_t)n * kMaskWords * sizeof(uint64_t));
+    // supertile masks (preprocess -> scatter), then the receiver region's texel bytes
+    {
+        const size_t mb = (size_t)n * kMaskWords * sizeof(uint64_t), tb = (size_t)g.H * g.W;
+        L.mask = take(mb > tb ? mb : tb);
+    }
     L.counts = take((size_t)g.S * (size_t)L.nb * sizeof(int));
     L.lists = take(L.cap * sizeof(int));
     L.bits = take(L.cap * sizeof(uint64_t));

@@ -62,7 +62,8 @@ struct __attribute__((aligned(16))) GRec {
     float r2;            // squared ray-to-mean distance beyond which no texel is active
     float lg;            // e0 = |adj(A)^(1/2) (m x d)|^2 / a at or beyond which no texel is active
     float r0;            // culling-cone numerator s_max sqrt(2 ln(U / eps)); -1: contributes nothing
-    float pad[4];
+    float pad[4];        // [0] the tile test's plane scale (per light and frame), [1] det(Sigma),
+                         // [2] s_max / s_min, [3] 0
 };
 static_assert(sizeof(GRec) == 128, "GRec layout");
 

@@ -68,7 +68,7 @@ struct LightWs {
     int* lbase;        // [kMaxSuper + 1] list base per supertile, multiples of 64
     GRec* rec;         // [n]
     float4* cone;      // [n]
-    uint64_t* mask;    // [n][kMaskWords] supertile masks
+    uint64_t* mask;    // [n][kMaskWords] supertile masks; after the scatter: [H][W] receiver texel bytes
     int* counts;       // [S][nb] per-block counts, scanned in place
     int* lists;        // [cap] supertile lists, 64-entry chunks
     uint64_t* bits;    // [cap] per supertile: [tile][chunk] hit words

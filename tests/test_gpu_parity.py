@@ -269,6 +269,27 @@ def test_culling_matches_unculled(cfg1):
     assert err <= 1e-6
 
 
+def test_culling_matches_unculled_around_the_light():
+    """Anisotropic Gaussians on every side of a light, some within a few
+    centimetres of it (the tile tests' separating plane and cone face Gaussians
+    ahead of, beside and behind the light): culled vs unculled within the
+    culling budget of 1e-5, on a 64x64 atlas (8x8-texel tiles of about 0.1 rad)
+    and a 256x256 one (0.025 rad)."""
+    U = _util()
+    rng = np.random.default_rng(321)
+    light = np.array([[0.2, -0.1, 1.3]], np.float32)
+    far = rng.uniform(-3, 3, (15000, 3)) + light[0]
+    near = rng.normal(0, 0.15, (500, 3)) + light[0]
+    g = synth.random_gaussians(rng, np.concatenate([far, near]).astype(np.float32), 0.03)
+    for spec in (synth.AtlasSpec(64, 64, 16), synth.AtlasSpec(256, 256, 16)):
+        Tc, _ = U.gpu_build(g, light, spec, cull_eps=1e-8)
+        Tn, _ = U.gpu_build(g, light, spec, cull_eps=0.0)
+        err = (Tc - Tn).abs().max().item()
+        _report(f"culled vs unculled around the light {spec.H}x{spec.W}", err)
+        assert Tn.min().item() < 0.5
+        assert err <= 1e-5
+
+
 def test_additivity_on_gpu(cfg1):
     U = _util()
     g = cfg1["gaussians"]
