@@ -41,8 +41,8 @@ PEAK_BF16_TFLOPS = 2500.0
 # device copy.  Valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("paper_2601_01660_amd/csrc/dgsm_build.hip", "paper_2601_01660_amd/csrc/dgsm_device.hpp",
                    "paper_2601_01660_amd/csrc/dgsm_host.hpp")
-TRAFFIC = {"sha256": "f259b9101183ae5ea833c44699ca8e2a032055bf56d82848afb5fc36ac569d7b",
-           "fetch_bytes": 34961702563, "write_bytes": 1493166226,
+TRAFFIC = {"sha256": "8070967026f3c756a1447153a50fdf3e196f24753d205af6a3129155599f53fa",
+           "fetch_bytes": 25534264822, "write_bytes": 1500268590,
            "profile": "profiles/tile_build_counters__room2M_avatar150k_4lights_512x512x64_f16.md"}
 
 
