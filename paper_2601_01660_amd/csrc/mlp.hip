@@ -59,19 +59,48 @@ __device__ inline __bf16 to_bf16(float x) { return (__bf16)x; }   // round to ne
 // the matrix units); inference evaluates it in FP32 (error about 1e-7).
 __device__ inline double turns_per_unit(int i, int W) { return 0.5 * pow(0.25 * (double)W, (double)i / 15.0); }
 
+// sin and cos of 2 pi ph for a phase ph in turns, in FP64: quarter turns
+// y = 4 ph = q + f with q = rint(y) (both steps exact), th = f pi/2 in
+// [-pi/4, pi/4], the Taylor series of sin to th^15 and of cos to th^16
+// (truncation below 5e-17 on that interval), then the quadrant q mod 4.
+__device__ inline void sincos_turns(double ph, double& s, double& c) {
+    const double y = 4.0 * ph;
+    const double q = rint(y);
+    const double th = (y - q) * 1.5707963267948966;
+    const double t2 = th * th;
+    double ps = -1.0 / 1307674368000.0;              // -1/15!
+    ps = fma(ps, t2, 1.0 / 6227020800.0);            // 1/13!
+    ps = fma(ps, t2, -1.0 / 39916800.0);             // -1/11!
+    ps = fma(ps, t2, 1.0 / 362880.0);                // 1/9!
+    ps = fma(ps, t2, -1.0 / 5040.0);                 // -1/7!
+    ps = fma(ps, t2, 1.0 / 120.0);                   // 1/5!
+    ps = fma(ps, t2, -1.0 / 6.0);                    // -1/3!
+    const double sn = fma(th * t2, ps, th);
+    double pc = 1.0 / 20922789888000.0;              // 1/16!
+    pc = fma(pc, t2, -1.0 / 87178291200.0);          // -1/14!
+    pc = fma(pc, t2, 1.0 / 479001600.0);             // 1/12!
+    pc = fma(pc, t2, -1.0 / 3628800.0);              // -1/10!
+    pc = fma(pc, t2, 1.0 / 40320.0);                 // 1/8!
+    pc = fma(pc, t2, -1.0 / 720.0);                  // -1/6!
+    pc = fma(pc, t2, 1.0 / 24.0);                    // 1/4!
+    pc = fma(pc, t2, -0.5);
+    const double cs = fma(t2, pc, 1.0);
+    const int quad = (int)(long long)q & 3;          // angle = quad pi/2 + th
+    s = (quad & 1) ? cs : sn;
+    c = (quad & 1) ? sn : cs;
+    if (quad == 2 || quad == 3) s = -s;
+    if (quad == 1 || quad == 2) c = -c;
+}
+
 __device__ inline float fourier_exact(double c, float x, bool cosine) {
-    const double ph = c * (double)x;
-    const double r = ph - rint(ph);
     double s, co;
-    sincospi(2.0 * r, &s, &co);
+    sincos_turns(c * (double)x, s, co);
     return (float)(cosine ? co : s);
 }
 
 __device__ inline void fourier_pair(double c, double x, float& s, float& co) {
-    const double ph = c * x;
-    const double r = ph - rint(ph);
     double sd, cd;
-    sincospi(2.0 * r, &sd, &cd);
+    sincos_turns(c * x, sd, cd);
     s = (float)sd;
     co = (float)cd;
 }
@@ -546,9 +575,10 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
         }
         load_pt(t + gridDim.x);
         __syncthreads();
-        // features: thread -> (sample, frequency) pairs tid and tid + 256 of 32 x 16
+        // features: thread -> (sample, frequency) pairs tid, tid + 256, ... of kIRows x kNF
+        static_assert(kIRows * kNF % (kWave * kIW) == 0, "whole (sample, frequency) sweeps");
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < kIRows * kNF / (kWave * kIW); ++h) {
             const int pr = tid + h * kWave * kIW;
             const int smp = pr / kNF, i = pr % kNF;
             const double3 in = rin[smp];
