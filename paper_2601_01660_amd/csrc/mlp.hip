@@ -502,7 +502,7 @@ __global__ __launch_bounds__(kWave * NWV) void fwd_kernel(FwdArgs a) {
 
 // ---------------------------------------------------------------------------
 // Inference with the weights held in registers.  Wave w of kIW owns output
-// features [32w, 32w + 32) of every layer: its weight rows stay in VGPRs as
+// features [16 kIJ w, 16 kIJ (w + 1)) of every layer: its weight rows stay in VGPRs as
 // the A operand of the MFMA for the whole kernel, and the activations of kIRB
 // 16-sample blocks are the B operand, so each product H^T = W X^T leaves four
 // consecutive features of one sample per lane (one 8-byte LDS store) and each
@@ -511,6 +511,7 @@ __global__ __launch_bounds__(kWave * NWV) void fwd_kernel(FwdArgs a) {
 // feature rows is written once.
 // ---------------------------------------------------------------------------
 constexpr int kIW = 4;      // waves per inference block
+constexpr int kIJ = kH / 16 / kIW;   // 16-feature output tiles per wave
 constexpr int kIRB = 2;     // 16-sample blocks per iteration
 constexpr int kIRows = kIRB * kRows;
 
@@ -530,12 +531,12 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
     const __bf16* Wg = a.wb + (size_t)light * 4 * kH * kH;
     const int lr = lane % 16, lg = lane / 16;
     // this wave's weight rows: layer l, feature tile j (features 16 (2 wave + j) ..), k-step kk
-    bf16x8 Wf[4][2][4];
+    bf16x8 Wf[4][kIJ][4];
 #pragma unroll
     for (int l = 0; l < 4; ++l)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int row = 16 * (2 * wave + j) + lr;
+        for (int j = 0; j < kIJ; ++j) {
+            const int row = 16 * (kIJ * wave + j) + lr;
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk)
                 Wf[l][j][kk] = *reinterpret_cast<const bf16x8*>(Wg + (size_t)l * kH * kH + (size_t)row * kH + 32 * kk +
@@ -603,13 +604,13 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
             put(8 + 6 * i, cs);
         }
         __syncthreads();
-        f32x4 acc[kIRB][2];
+        f32x4 acc[kIRB][kIJ];
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
             const bf16x8(*src)[kRows * 16] = l == 0 ? feat : hid[(l - 1) & 1];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const float4 bb = btab[l][(16 * (2 * wave + j) + 4 * lg) / 4];
+            for (int j = 0; j < kIJ; ++j) {
+                const float4 bb = btab[l][(16 * (kIJ * wave + j) + 4 * lg) / 4];
 #pragma unroll
                 for (int rb = 0; rb < kIRB; ++rb) acc[rb][j] = f32x4{bb.x, bb.y, bb.z, bb.w};
             }
@@ -619,12 +620,12 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
                 for (int rb = 0; rb < kIRB; ++rb) {
                     const bf16x8 xv = src[rb][swz(lr, lg + 4 * kk)];
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) acc[rb][j] = mfma(Wf[l][j][kk], xv, acc[rb][j]);
+                    for (int j = 0; j < kIJ; ++j) acc[rb][j] = mfma(Wf[l][j][kk], xv, acc[rb][j]);
                 }
 #pragma unroll
             for (int rb = 0; rb < kIRB; ++rb)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < kIJ; ++j)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) acc[rb][j][r] = fmaxf(acc[rb][j][r], 0.f);
             if (l < 3) {
@@ -632,8 +633,8 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
 #pragma unroll
                 for (int rb = 0; rb < kIRB; ++rb)
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const int f0 = 16 * (2 * wave + j) + 4 * lg;   // four consecutive features of sample lr
+                    for (int j = 0; j < kIJ; ++j) {
+                        const int f0 = 16 * (kIJ * wave + j) + 4 * lg;   // four consecutive features of sample lr
                         bf16x4 v;
 #pragma unroll
                         for (int r = 0; r < 4; ++r) v[r] = to_bf16(acc[rb][j][r]);
@@ -648,8 +649,8 @@ __global__ __launch_bounds__(kWave * kIW, 2) void infer_kernel(FwdArgs a) {
         for (int rb = 0; rb < kIRB; ++rb) {
             float zp = 0.f;
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int f0 = 16 * (2 * wave + j) + 4 * lg;
+            for (int j = 0; j < kIJ; ++j) {
+                const int f0 = 16 * (kIJ * wave + j) + 4 * lg;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) zp += w4t[f0 + r] * acc[rb][j][r];
             }
