@@ -37,68 +37,77 @@ __device__ inline float inflate_sh(double sh) {
     return (float)(v > 1.0 ? 1.0 : v);
 }
 
-__global__ __launch_bounds__(64) void tile_cone_kernel(Geom g, float4* __restrict__ tcone) {
-    const int t = blockIdx.x * 64 + threadIdx.x;
-    if (t >= g.ntiles) return;
+// FP64 sum and maximum over a wave (fixed butterfly order: deterministic).
+__device__ inline double wave_sum_d(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ inline double wave_max_d(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// One wave per tile, one lane per texel: axis = normalised sum of the
+// texel-centre directions, half-angle from the largest chord to the axis.
+// The cone and its cone_cos are stored.
+__global__ __launch_bounds__(256) void tile_cone_kernel(Geom g, float4* __restrict__ tcone, float* __restrict__ tcos) {
+    const int lane = threadIdx.x % kWave;
+    const int t = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    if (t >= g.ntiles) return;                               // wave-uniform
     const int ty = t / g.TW, tx = t - ty * g.TW;
-    const int i1 = min(ty * kTile + kTile, g.H), j1 = min(tx * kTile + kTile, g.W);
-    double sx = 0, sy = 0, sz = 0;
-    for (int i = ty * kTile; i < i1; ++i)
-        for (int j = tx * kTile; j < j1; ++j) {
-            double x, y, z;
-            texel_dir(g, i, j, x, y, z);
-            sx += x; sy += y; sz += z;
-        }
+    const int i = ty * kTile + (lane >> 3), j = tx * kTile + (lane & 7);
+    const bool in = i < g.H && j < g.W;
+    double x = 0, y = 0, z = 0;
+    if (in) texel_dir(g, i, j, x, y, z);
+    double sx = wave_sum_d(x), sy = wave_sum_d(y), sz = wave_sum_d(z);
     const double nrm = sqrt(sx * sx + sy * sy + sz * sz);
     sx /= nrm; sy /= nrm; sz /= nrm;
-    double ch = 0;
-    for (int i = ty * kTile; i < i1; ++i)
-        for (int j = tx * kTile; j < j1; ++j) {
-            double x, y, z;
-            texel_dir(g, i, j, x, y, z);
-            const double c2 = (x - sx) * (x - sx) + (y - sy) * (y - sy) + (z - sz) * (z - sz);
-            ch = fmax(ch, c2);
-        }
-    tcone[t] = make_float4((float)sx, (float)sy, (float)sz, inflate_sh(0.5 * sqrt(ch)));
+    const double ch = wave_max_d(in ? (x - sx) * (x - sx) + (y - sy) * (y - sy) + (z - sz) * (z - sz) : 0.0);
+    if (lane == 0) {
+        const float4 c = make_float4((float)sx, (float)sy, (float)sz, inflate_sh(0.5 * sqrt(ch)));
+        tcone[t] = c;
+        tcos[t] = cone_cos(c);
+    }
 }
 
 // A supertile cone bounds the cones of its tiles: half-angle = max over tiles
 // of (angle to the tile axis + tile half-angle).
 // Group cones: group s of a grid of (gh x gw)-tile groups, ngx groups per row
-// (supertiles: gh = STH, gw = STW; quads: 2 x 2 tiles).
-__global__ __launch_bounds__(64) void super_cone_kernel(Geom g, const float4* __restrict__ tcone,
-                                                        float4* __restrict__ scone, int ngroups, int ngx, int gh,
-                                                        int gw) {
-    const int s = blockIdx.x * 64 + threadIdx.x;
-    if (s >= ngroups) return;
+// (supertiles: gh = STH, gw = STW; quads: 2 x 2 tiles; 2 x 2 supertiles).
+// One wave per group, the lanes striding over its tiles.
+__global__ __launch_bounds__(256) void super_cone_kernel(Geom g, const float4* __restrict__ tcone,
+                                                         float4* __restrict__ scone, float* __restrict__ scos,
+                                                         int ngroups, int ngx, int gh, int gw) {
+    const int lane = threadIdx.x % kWave;
+    const int s = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+    if (s >= ngroups) return;                                // wave-uniform
     const int sy = s / ngx, sx = s - sy * ngx;
     const int ty0 = sy * gh, ty1 = min(ty0 + gh, g.TH);
     const int tx0 = sx * gw, tx1 = min(tx0 + gw, g.TW);
+    const int nw = tx1 - tx0, nt = (ty1 - ty0) * nw;
     double ax = 0, ay = 0, az = 0;
-    for (int ty = ty0; ty < ty1; ++ty)
-        for (int tx = tx0; tx < tx1; ++tx) {
-            const float4 c = tcone[ty * g.TW + tx];
-            ax += c.x; ay += c.y; az += c.z;
-        }
+    for (int q = lane; q < nt; q += kWave) {
+        const float4 c = tcone[(ty0 + q / nw) * g.TW + tx0 + q % nw];
+        ax += c.x; ay += c.y; az += c.z;
+    }
+    ax = wave_sum_d(ax); ay = wave_sum_d(ay); az = wave_sum_d(az);
     const double nrm = sqrt(ax * ax + ay * ay + az * az);
     ax /= nrm; ay /= nrm; az /= nrm;
     double half = 0;
-    for (int ty = ty0; ty < ty1; ++ty)
-        for (int tx = tx0; tx < tx1; ++tx) {
-            const float4 c = tcone[ty * g.TW + tx];
-            const double ch = sqrt((c.x - ax) * (c.x - ax) + (c.y - ay) * (c.y - ay) + (c.z - az) * (c.z - az));
-            const double ang = 2.0 * asin(fmin(1.0, 0.5 * ch)) + 2.0 * asin(fmin(1.0, (double)c.w));
-            half = fmax(half, ang);
-        }
-    half = fmin(half, M_PI);
-    scone[s] = make_float4((float)ax, (float)ay, (float)az, inflate_sh(sin(0.5 * half)));
+    for (int q = lane; q < nt; q += kWave) {
+        const float4 c = tcone[(ty0 + q / nw) * g.TW + tx0 + q % nw];
+        const double ch = sqrt((c.x - ax) * (c.x - ax) + (c.y - ay) * (c.y - ay) + (c.z - az) * (c.z - az));
+        const double ang = 2.0 * asin(fmin(1.0, 0.5 * ch)) + 2.0 * asin(fmin(1.0, (double)c.w));
+        half = fmax(half, ang);
+    }
+    half = fmin(wave_max_d(half), M_PI);
+    if (lane == 0) {
+        const float4 c = make_float4((float)ax, (float)ay, (float)az, inflate_sh(sin(0.5 * half)));
+        scone[s] = c;
+        scos[s] = cone_cos(c);
+    }
 }
 
-// cone_cos of n cones, stored beside them for the cone tests.
-__global__ __launch_bounds__(64) void cone_cos_kernel(const float4* __restrict__ c, float* __restrict__ cs, int n) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    if (i < n) cs[i] = cone_cos(c[i]);
-}
 
 // ---------------------------------------------------------------------------
 // Workspace slices
@@ -135,6 +144,7 @@ struct PrepArgs {
     float eps;             // culling budget (0: no culling)
     int S, SGH, SGW;       // supertile count and grid
     int shape_cached;      // the records hold this set's shapes already: update m and the cone only
+    int roi;               // a receiver region is marked: supertiles without a region texel get no entries
     BuildLayout lay;
     unsigned char* ws;
 };
@@ -292,6 +302,7 @@ __global__ __launch_bounds__(kPrepThreads) void preprocess_kernel(PrepArgs a) {
             const int sy = 2 * gy + (d >> 1), sx = 2 * gx + (d & 1);
             if (sy >= a.SGH || sx >= a.SGW) continue;
             const int sidx = sy * a.SGW + sx;
+            if (a.roi && !W.roi_super[sidx]) continue;
             const bool hit = hit_g && cones_touch_c(cone, ca, sc[sidx], scs[sidx]);
             if (hit) {
                 const uint64_t bit = 1ull << (sidx & 63);
@@ -501,7 +512,8 @@ __device__ inline bool plane_keeps(const PlaneEntry& p, float4 tc, float2 cs) {
     return !(ss * ss * p.q > v0 * v0 + v1 * v1 + v2 * v2);
 }
 
-__global__ __launch_bounds__(256, 8) void tile_mask_kernel(unsigned char* ws, BuildLayout lay, Geom g) {
+// roi: a receiver region is marked; tiles without a region texel get no hits.
+__global__ __launch_bounds__(256, 8) void tile_mask_kernel(unsigned char* ws, BuildLayout lay, Geom g, int roi) {
     __shared__ int sbase[kMaxSuper + 1];
     __shared__ int stot[kMaxSuper];
     // per wave: the cones (and cone_cos) of the tiles and quads of its current
@@ -510,6 +522,7 @@ __global__ __launch_bounds__(256, 8) void tile_mask_kernel(unsigned char* ws, Bu
     __shared__ float ltcs[4][kWave];
     __shared__ float2 ltca[4][kWave];      // cos, sin of each tile cone's half-angle (plane test)
     __shared__ unsigned long long lres[4][kWave];   // per wave: tile words of the current chunk
+    __shared__ int lroi[4][kWave];                   // per wave: the supertile's tiles that hold a region texel
     auto wave_sync = [] {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -587,6 +600,7 @@ __global__ __launch_bounds__(256, 8) void tile_mask_kernel(unsigned char* ws, Bu
             __builtin_amdgcn_wave_barrier();           // earlier reads of the cache are done
             if (lane < sp_cur.nty * sp_cur.ntx) {
                 const int t = (sp_cur.ty0 + lane / sp_cur.ntx) * g.TW + sp_cur.tx0 + lane % sp_cur.ntx;
+                lroi[wv][lane] = !roi || W.roi_mask[t] != 0ull;
                 ltc[wv][lane] = tcone[t];
                 ltcs[wv][lane] = tcos[t];
                 ltca[wv][lane] = cone_cos_sin(tcone[t], tcos[t]);
@@ -618,6 +632,7 @@ __global__ __launch_bounds__(256, 8) void tile_mask_kernel(unsigned char* ws, Bu
                 const int ly = 2 * qy + (d >> 1), lx = 2 * qx + (d & 1);   // tile inside the supertile
                 if (ly >= sp.nty || lx >= sp.ntx) continue;
                 const int t = ly * sp.ntx + lx;
+                if (!lroi[wv][t]) continue;                  // no receiver reads this tile
                 const bool hit = hit_q && cones_touch_c(cone, ca, ltc[wv][t], ltcs[wv][t]);
                 const uint64_t bal = ballot(hit);
                 if (hit) row |= 1ull << t;
@@ -670,17 +685,20 @@ __global__ __launch_bounds__(256, 8) void tile_mask_kernel(unsigned char* ws, Bu
 // full atlas.
 // ---------------------------------------------------------------------------
 
-// Receiver marks go to a byte per texel (plain stores of 1: every receiver
-// that reads a texel writes the same value, so no atomics are needed), kept
-// in the storage of the supertile masks, which nothing reads after the
-// scatter.  A pack pass then turns each tile's 64 bytes into its 64-bit
-// region mask.  The shell range is reduced per block before its two atomics.
+// The region is marked before the binning, so that the binning leaves out
+// the tiles and supertiles no receiver reads.  Receiver marks go to a byte per
+// texel (plain stores of 1: every receiver that reads a texel writes the same
+// value, so no atomics are needed), kept in the storage of the split tiles'
+// partial sums, which only the accumulation uses.  A pack pass then turns
+// each tile's 64 bytes into its 64-bit region mask and flags the supertiles
+// that hold one.  The shell range is reduced per block before its two atomics.
 __global__ __launch_bounds__(256) void roi_clear_kernel(unsigned char* ws, BuildLayout lay, Geom g) {
     const LightWs W = light_ws(ws, lay, blockIdx.y);
     const int t = blockIdx.x * 256 + threadIdx.x;
-    uint32_t* map = reinterpret_cast<uint32_t*>(W.mask);
+    uint32_t* map = reinterpret_cast<uint32_t*>(W.part);
     const int nw = (g.H * g.W + 3) / 4;
     for (int q = t; q < nw; q += gridDim.x * 256) map[q] = 0u;
+    for (int q = t; q < g.S; q += gridDim.x * 256) W.roi_super[q] = 0;
     if (t == 0) {
         W.roi_k[0] = g.K;
         W.roi_k[1] = -1;
@@ -696,7 +714,7 @@ __global__ __launch_bounds__(256) void roi_mark_kernel(unsigned char* ws, BuildL
     __shared__ int red[2][256 / kWave];
     const int l = blockIdx.y;
     const LightWs W = light_ws(ws, lay, l);
-    unsigned char* map = reinterpret_cast<unsigned char*>(W.mask);
+    unsigned char* map = reinterpret_cast<unsigned char*>(W.part);
     int kmn = g.K, kmx = -1;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const float x = pts[3 * i], y = pts[3 * i + 1], z = pts[3 * i + 2];
@@ -732,14 +750,13 @@ __global__ __launch_bounds__(256) void roi_mark_kernel(unsigned char* ws, BuildL
     }
 }
 
-// Region mask of every tile from the texel bytes; tiles outside the region
-// do no work: their hit counts are cleared so that the work-unit planner does
-// not split them.
+// Region mask of every tile from the texel bytes, and the supertiles that
+// hold a region texel (plain stores of 1).
 __global__ __launch_bounds__(256) void roi_pack_kernel(unsigned char* ws, BuildLayout lay, Geom g) {
     const LightWs W = light_ws(ws, lay, blockIdx.y);
     const int t = blockIdx.x * 256 + threadIdx.x;
     if (t >= g.ntiles) return;
-    const unsigned char* map = reinterpret_cast<const unsigned char*>(W.mask);
+    const unsigned char* map = reinterpret_cast<const unsigned char*>(W.part);
     const int ty = t / g.TW, tx = t - ty * g.TW;
     uint64_t m = 0;
     for (int r = 0; r < kTile; ++r) {
@@ -751,7 +768,7 @@ __global__ __launch_bounds__(256) void roi_pack_kernel(unsigned char* ws, BuildL
         }
     }
     W.roi_mask[t] = m;
-    if (m == 0ull) W.hits[t] = 0;
+    if (m != 0ull) W.roi_super[(ty / g.STH) * g.SGW + tx / g.STW] = 1;
 }
 
 dgsm_status enqueue_roi(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
@@ -1677,11 +1694,7 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights, int64_t cap) {
     L.lbase = take((size_t)(kMaxSuper + 1) * sizeof(int));
     L.rec = take((size_t)n * sizeof(GRec));
     L.cone = take((size_t)n * sizeof(float4));
-    // supertile masks (preprocess -> scatter), then the receiver region's texel bytes
-    {
-        const size_t mb = (size_t)n * kMaskWords * sizeof(uint64_t), tb = (size_t)g.H * g.W;
-        L.mask = take(mb > tb ? mb : tb);
-    }
+    L.mask = take((size_t)n * kMaskWords * sizeof(uint64_t));
     L.counts = take((size_t)g.S * (size_t)L.nb * sizeof(int));
     L.lists = take(L.cap * sizeof(int));
     L.bits = take(L.cap * sizeof(uint64_t));
@@ -1699,10 +1712,14 @@ BuildLayout build_layout(const Geom& g, int64_t n, int n_lights, int64_t cap) {
     L.units = take((size_t)L.units_cap * sizeof(int4));
     L.splits = take((size_t)L.units_cap * sizeof(int2));
     L.nunits = take(4 * sizeof(int));
-    L.part = take(2 * (size_t)L.units_cap * g.K * kWave * sizeof(unsigned long long));
+    {
+        const size_t pb = 2 * (size_t)L.units_cap * g.K * kWave * sizeof(unsigned long long), tb = (size_t)g.H * g.W;
+        L.part = take(pb > tb ? pb : tb);
+    }
     L.prange = take(2 * (size_t)L.units_cap * sizeof(int2));
     L.roi_mask = take((size_t)g.ntiles * sizeof(unsigned long long));
     L.roi_k = take(2 * sizeof(int));
+    L.roi_super = take((size_t)kMaxSuper * sizeof(int));
     L.need = take(2 * sizeof(int));
     L.light_stride = off;
     L.total = L.light0 + (size_t)n_lights * L.light_stride;
@@ -1787,34 +1804,30 @@ dgsm_status enqueue_cones(const Geom& g, const BuildLayout& L, unsigned char* ws
     float4* tcone = reinterpret_cast<float4*>(ws + L.tcone);
     float4* scone = reinterpret_cast<float4*>(ws + L.scone);
     float4* qcone = reinterpret_cast<float4*>(ws + L.qcone);
-    tile_cone_kernel<<<(g.ntiles + 63) / 64, 64, 0, st>>>(g, tcone);
+    float4* gcone = reinterpret_cast<float4*>(ws + L.gcone);
+    auto cosp = [&](size_t off) { return reinterpret_cast<float*>(ws + off); };
+    constexpr int kPer = 256 / kWave;                        // cones per block
+    tile_cone_kernel<<<(g.ntiles + kPer - 1) / kPer, 256, 0, st>>>(g, tcone, cosp(L.tcos));
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
-    super_cone_kernel<<<(g.S + 63) / 64, 64, 0, st>>>(g, tcone, scone, g.S, g.SGW, g.STH, g.STW);
+    super_cone_kernel<<<(g.S + kPer - 1) / kPer, 256, 0, st>>>(g, tcone, scone, cosp(L.scos), g.S, g.SGW, g.STH,
+                                                                 g.STW);
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     const int nqx = (g.TW + 1) / 2, nq = ((g.TH + 1) / 2) * nqx;
-    super_cone_kernel<<<(nq + 63) / 64, 64, 0, st>>>(g, tcone, qcone, nq, nqx, 2, 2);
+    super_cone_kernel<<<(nq + kPer - 1) / kPer, 256, 0, st>>>(g, tcone, qcone, cosp(L.qcos), nq, nqx, 2, 2);
     if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
-    float4* gcone = reinterpret_cast<float4*>(ws + L.gcone);
     const int ngx = (g.SGW + 1) / 2, ng = ((g.SGH + 1) / 2) * ngx;
-    super_cone_kernel<<<(ng + 63) / 64, 64, 0, st>>>(g, tcone, gcone, ng, ngx, 2 * g.STH, 2 * g.STW);
-    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
-    const float4* cones[4] = {tcone, scone, qcone, gcone};
-    const size_t cos_off[4] = {L.tcos, L.scos, L.qcos, L.gcos};
-    const int counts[4] = {g.ntiles, g.S, nq, ng};
-    for (int c = 0; c < 4; ++c) {
-        cone_cos_kernel<<<(counts[c] + 63) / 64, 64, 0, st>>>(cones[c], reinterpret_cast<float*>(ws + cos_off[c]),
-                                                              counts[c]);
-        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
-    }
-    return DGSM_OK;
+    super_cone_kernel<<<(ng + kPer - 1) / kPer, 256, 0, st>>>(g, tcone, gcone, cosp(L.gcos), ng, ngx, 2 * g.STH,
+                                                               2 * g.STW);
+    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
 }
 
 dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
-                        float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st, bool cones, bool shape_cached) {
+                        float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st, bool cones, bool shape_cached,
+                        bool roi) {
     if (cones && enqueue_cones(g, L, ws, st) != DGSM_OK) return DGSM_EHIP;
     if (gs.n > 0) {
         PrepArgs pa{gs.mean, gs.scale, gs.rot, gs.opacity, gs.n, lights.pos, lights.kappa, lights.beta_mode, cull_eps,
-                    g.S, g.SGH, g.SGW, shape_cached ? 1 : 0, L, ws};
+                    g.S, g.SGH, g.SGW, shape_cached ? 1 : 0, roi ? 1 : 0, L, ws};
         preprocess_kernel<<<dim3(L.nb, lights.n), kPrepThreads, 0, st>>>(pa);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }
@@ -1828,7 +1841,7 @@ dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, 
         // about two chunks per wave (the next chunk's loads overlap this one's tests)
         const int64_t est = ((int64_t)gs.n * 2 + 64 * (int64_t)g.S) / 64;
         const int blocks = (int)(est / 8 + 1 < 4096 ? est / 8 + 1 : 4096);
-        tile_mask_kernel<<<dim3(blocks, lights.n), 256, 0, st>>>(ws, L, g);
+        tile_mask_kernel<<<dim3(blocks, lights.n), 256, 0, st>>>(ws, L, g, roi ? 1 : 0);
         if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
     }
     return DGSM_OK;
@@ -2017,9 +2030,9 @@ extern "C" dgsm_status dgsm_build_roi(const dgsm_lights_t* lights, const dgsm_ga
     if (!ws || !layout_for_bytes(g, gaussians->n, lights->n, ws_bytes, L)) return DGSM_EWORKSPACE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     unsigned char* w = reinterpret_cast<unsigned char*>(ws);
-    if ((st = enqueue_bin(g, L, w, *lights, desc->cull_eps, *gaussians, s)) != DGSM_OK) return st;
     const RoiBox rb{box->cx, box->cy, box->half, box->zmin, box->zmax};
     if ((st = enqueue_roi(g, L, w, *lights, receivers, n_receivers, rb, s)) != DGSM_OK) return st;
+    if ((st = enqueue_bin(g, L, w, *lights, desc->cull_eps, *gaussians, s, true, false, true)) != DGSM_OK) return st;
     AccumOpts o{nullptr, false, nullptr, kDefaultTileWaves, kDefaultSplitUnits};
     o.roi = true;
     return enqueue_accumulate(g, L, w, lights->n, desc->cull_eps, atlas, o, s);

@@ -58,7 +58,7 @@ struct BuildLayout {
     int units_cap;           // extra work units per light (tiles split over several blocks)
     // offsets inside a light slice
     size_t totals, lbase, rec, cone, mask, counts, lists, bits;
-    size_t hits, tinfo, units, splits, nunits, part, prange, roi_mask, roi_k, need;
+    size_t hits, tinfo, units, splits, nunits, part, prange, roi_mask, roi_k, roi_super, need;
     size_t total;            // bytes for all lights
 };
 
@@ -68,7 +68,7 @@ struct LightWs {
     int* lbase;        // [kMaxSuper + 1] list base per supertile, multiples of 64
     GRec* rec;         // [n]
     float4* cone;      // [n]
-    uint64_t* mask;    // [n][kMaskWords] supertile masks; after the scatter: [H][W] receiver texel bytes
+    uint64_t* mask;    // [n][kMaskWords] supertile masks
     int* counts;       // [S][nb] per-block counts, scanned in place
     int* lists;        // [cap] supertile lists, 64-entry chunks
     uint64_t* bits;    // [cap] per supertile: [tile][chunk] hit words
@@ -77,10 +77,12 @@ struct LightWs {
     int4* units;       // [units_cap] extra slices: {tile, slice index, slices, partial}
     int2* splits;      // [units_cap] split tiles: {tile, first partial}
     int* nunits;       // [4] {extra slices, split tiles, hits per slice, total hits}
-    unsigned long long* part;   // [2 units_cap][K][64] fixed-point partial optical depths
+    unsigned long long* part;   // [2 units_cap][K][64] fixed-point partial optical depths (at least H W
+                                // bytes: before the binning of a receiver-region build, the texel marks)
     int2* prange;               // [2 units_cap] shell rows [lo, hi] each partial holds (lo > hi: none)
     unsigned long long* roi_mask;   // [ntiles] receiver texels of each tile (bit = texel in the tile)
     int* roi_k;                     // [2] receiver shell range {k_min, k_max}
+    int* roi_super;                 // [kMaxSuper] 1 where a supertile holds a receiver texel
     int* need;                      // [2] {list entries the last binning needed, 1 if they exceeded cap}
 };
 
@@ -95,7 +97,7 @@ __host__ __device__ inline LightWs light_ws(unsigned char* ws, const BuildLayout
                    reinterpret_cast<int*>(b + L.nunits), reinterpret_cast<unsigned long long*>(b + L.part),
                    reinterpret_cast<int2*>(b + L.prange),
                    reinterpret_cast<unsigned long long*>(b + L.roi_mask), reinterpret_cast<int*>(b + L.roi_k),
-                   reinterpret_cast<int*>(b + L.need)};
+                   reinterpret_cast<int*>(b + L.roi_super), reinterpret_cast<int*>(b + L.need)};
 }
 
 // Workspace layout for n Gaussians and n_lights lights.  cap: list entries
@@ -112,10 +114,11 @@ size_t tile_smem_bytes(const Geom& g, int nw, bool pack);
 dgsm_status enqueue_cones(const Geom& g, const BuildLayout& L, unsigned char* ws, hipStream_t st);
 
 // Enqueue the binning of all lights (preprocess, scan, scatter, tile masks);
-// cones = false reuses cones already in the workspace.
+// cones = false reuses cones already in the workspace; roi = true bins only
+// the tiles of a receiver region already marked (enqueue_roi).
 dgsm_status enqueue_bin(const Geom& g, const BuildLayout& L, unsigned char* ws, const dgsm_lights_t& lights,
                         float cull_eps, const dgsm_gaussians_t& gs, hipStream_t st, bool cones = true,
-                        bool shape_cached = false);
+                        bool shape_cached = false, bool roi = false);
 
 // Options of the per-tile accumulation.
 struct AccumOpts {
