@@ -41,8 +41,8 @@ PEAK_BF16_TFLOPS = 2500.0
 # device copy.  Valid only for the kernel sources they were taken on.
 TRAFFIC_SOURCES = ("paper_2601_01660_amd/csrc/dgsm_build.hip", "paper_2601_01660_amd/csrc/dgsm_device.hpp",
                    "paper_2601_01660_amd/csrc/dgsm_host.hpp")
-TRAFFIC = {"sha256": "8070967026f3c756a1447153a50fdf3e196f24753d205af6a3129155599f53fa",
-           "fetch_bytes": 25534264822, "write_bytes": 1500268590,
+TRAFFIC = {"sha256": "3c4cd02f47d83889b25b08dc49dd80700301741c179e0d5e6710c35c5a8a311a",
+           "fetch_bytes": 25533813051, "write_bytes": 1499445294,
            "profile": "profiles/tile_build_counters__room2M_avatar150k_4lights_512x512x64_f16.md"}
 
 
