@@ -399,11 +399,12 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  *                 frame adds only the dynamic Gaussians to it (tau is a sum over
  *                 Gaussians, Eq. 2); 0: every frame rebuilds from all Gaussians
  *   autotune      1: the first run (unless the tuning cache below holds this
- *                 workload) times the knobs of the tile accumulation
- *                 on frame 0 of the real workload and keeps the fastest
- *                 combination: waves per tile (2, 4, 8), work units per launch
- *                 (never, 8192, 32768, 131072) and, in cache mode, the packed
- *                 walk (see dgsm_accumulate_ex) on or off; in cache mode they
+ *                 workload) times the knobs of the tile accumulation on the
+ *                 real workload -- in cache mode a window of frames dealt to
+ *                 the chains as a run deals them, else frame 0 -- and keeps
+ *                 the fastest combination: waves per tile (4, 8), work units
+ *                 per launch (8192, 32768, 131072) and, in cache mode, the
+ *                 packed walk (see dgsm_accumulate_ex) on or off; in cache mode they
  *                 apply to the per-frame dynamic accumulation, and the
  *                 once-per-run static build gets its own waves per tile and
  *                 work units, timed on the static set (tile walk); without

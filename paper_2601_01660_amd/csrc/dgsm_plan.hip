@@ -434,6 +434,31 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, int c, const dgsm_gaussians_t* dyn
     return DGSM_OK;
 }
 
+// Frames 0 .. nf - 1 dealt round-robin to the chains: fork from st, the
+// frames, join back into st.
+dgsm_status enqueue_frames(dgsm_plan p, int nf, const dgsm_gaussians_t* dyn, const float* translations, float* T_out,
+                           int tile_waves, int split_units, int pack, hipStream_t st) {
+    // fork: every chain starts after what st holds (the static build and the copies)
+    hipStream_t cs[kMaxChains];
+    cs[0] = st;
+    if (p->chains > 1 && hipEventRecord(p->ev_fork, st) != hipSuccess) return DGSM_EHIP;
+    for (int c = 1; c < p->chains; ++c) {
+        cs[c] = p->cstream[c];
+        if (hipStreamWaitEvent(cs[c], p->ev_fork, 0) != hipSuccess) return DGSM_EHIP;
+    }
+    dgsm_status s = DGSM_OK;
+    for (int f = 0; f < nf && s == DGSM_OK; ++f) {
+        const int c = f % p->chains;
+        s = enqueue_frame(p, f, c, dyn, translations, T_out, tile_waves, split_units, pack, cs[c]);
+    }
+    // join: the caller's stream waits for every chain (also after a failed
+    // enqueue, so that a capture never ends with a stream left forked)
+    for (int c = 1; c < p->chains; ++c)
+        if (hipEventRecord(p->ev_join[c], cs[c]) != hipSuccess || hipStreamWaitEvent(st, p->ev_join[c], 0) != hipSuccess)
+            return DGSM_EHIP;
+    return s;
+}
+
 dgsm_status enqueue_run(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* translations, float* T_out,
                         hipStream_t st) {
     if (p->nd > 0 && p->motion == DGSM_MOTION_RIGID) {
@@ -447,25 +472,7 @@ dgsm_status enqueue_run(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* t
     // the static build is a full-scene accumulation: it keeps the defaults
     // (the tuned knobs fit the per-frame dynamic accumulation)
     if (p->cache && (s = enqueue_static(p, p->static_waves, p->static_units, st)) != DGSM_OK) return s;
-    // fork: every chain starts after the static build (and the copies above)
-    hipStream_t cs[kMaxChains];
-    cs[0] = st;
-    if (p->chains > 1 && hipEventRecord(p->ev_fork, st) != hipSuccess) return DGSM_EHIP;
-    for (int c = 1; c < p->chains; ++c) {
-        cs[c] = p->cstream[c];
-        if (hipStreamWaitEvent(cs[c], p->ev_fork, 0) != hipSuccess) return DGSM_EHIP;
-    }
-    s = DGSM_OK;
-    for (int f = 0; f < p->frames && s == DGSM_OK; ++f) {
-        const int c = f % p->chains;
-        s = enqueue_frame(p, f, c, dyn, translations, T_out, p->tile_waves, p->split_units, p->pack, cs[c]);
-    }
-    // join: the caller's stream waits for every chain (also after a failed
-    // enqueue, so that a capture never ends with a stream left forked)
-    for (int c = 1; c < p->chains; ++c)
-        if (hipEventRecord(p->ev_join[c], cs[c]) != hipSuccess || hipStreamWaitEvent(st, p->ev_join[c], 0) != hipSuccess)
-            return DGSM_EHIP;
-    return s;
+    return enqueue_frames(p, p->frames, dyn, translations, T_out, p->tile_waves, p->split_units, p->pack, st);
 }
 
 // Knobs found by the autotuner, shared by the plans of the process: a plan
@@ -495,12 +502,16 @@ TuneKey tune_key(const dgsm_plan p) {
 }
 
 // Time each (waves per tile, work units, packed walk) candidate on the
-// accumulation the run repeats most (frame 0: the dynamic accumulation in
-// cache mode, the full one otherwise).
+// frames the run repeats: in cache mode a window of frames dealt to the
+// chains as the run deals them (the chains overlap, and the knobs that win a
+// lone frame need not win there: measured 1.086 vs 1.053 ms/frame), otherwise
+// frame 0 (a full-scene build).
 dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* translations, float* T_out,
                      hipStream_t st) {
-    const int waves[3] = {2, 4, 8};
-    const int units[4] = {-1, 8192, 32768, 131072};
+    // 2 waves per tile and unsplit tiles never won a measurement (alone or
+    // with overlapping chains) and are not candidates
+    const int waves[2] = {4, 8};
+    const int units[3] = {8192, 32768, 131072};
     const int npack = p->cache ? 2 : 1;   // the packed walk is a candidate for the dynamic accumulation
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return DGSM_EHIP;
@@ -540,22 +551,24 @@ dgsm_status autotune(dgsm_plan p, const dgsm_gaussians_t* dyn, const float* tran
     p->static_waves = best_sw;
     p->static_units = best_su;
     if (p->cache && s == DGSM_OK) s = enqueue_static(p, best_sw, best_su, st);
-    for (int rep = 0; rep < 2 && s == DGSM_OK; ++rep)   // first pass warms up
-        for (int c = 0; c < 12 * npack && s == DGSM_OK; ++c) {
-            const int nw = waves[c % 3], nu = units[(c / 3) % 4], pk = c / 12;
-            (void)hipEventRecord(e0, st);
-            s = enqueue_frame(p, 0, 0, dyn, translations, T_out, nw, nu, pk, st);
-            (void)hipEventRecord(e1, st);
-            if (hipEventSynchronize(e1) != hipSuccess) s = DGSM_EHIP;
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            if (rep == 1 && ms < best) {
-                best = ms;
-                best_nw = nw;
-                best_units = nu;
-                best_pack = pk;
-            }
+    const int window = p->cache ? std::min(p->frames, 3 * p->chains) : 1;
+    // c = -1: one warm-up window with the defaults, then each candidate once
+    for (int c = -1; c < 6 * npack && s == DGSM_OK; ++c) {
+        const int nw = c < 0 ? kDefaultTileWaves : waves[c % 2], nu = c < 0 ? kDefaultSplitUnits : units[(c / 2) % 3],
+                  pk = c < 0 ? 0 : c / 6;
+        (void)hipEventRecord(e0, st);
+        s = enqueue_frames(p, window, dyn, translations, T_out, nw, nu, pk, st);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) s = DGSM_EHIP;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (c >= 0 && ms < best) {
+            best = ms;
+            best_nw = nw;
+            best_units = nu;
+            best_pack = pk;
         }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->tile_waves = best_nw;
