@@ -361,11 +361,16 @@ typedef struct {
  *                   C0 = 1/(2 sqrt(pi)) (the DC colour), or NULL
  *   colour_sh_out and rgb_out require colour_sh.
  *   ws            : device workspace of >= sh_transfer_workspace_size(n_theta,
- *                   n_phi) bytes (32 bytes per grid direction): the probe's
- *                   radiance and weight on the grid, evaluated once per call
- *                   and then read by every Gaussian's sum
- * The sums run in FP32 in a fixed order (each of four quarters of the grid
- * in direction order, the quarters added in order): bitwise reproducible.
+ *                   n_phi) bytes, 16-byte aligned (16 bytes per grid
+ *                   direction with the columns padded to a multiple of 16,
+ *                   plus the row and column sines and cosines): the probe's
+ *                   weighted radiance and weight on the grid, evaluated once
+ *                   per call and then read by every Gaussian's sum.
+ *                   DGSM_EINVAL if ws is not 16-byte aligned.
+ * The sums run in FP32 in a fixed order, bitwise reproducible: the grid is
+ * cut into eight parts; within a part, of every 16 directions 12 go to two
+ * matrix-core partial sums (alternating) and 4 to a vector partial sum, each
+ * in direction order; the three are added, then the parts in order.
  */
 size_t sh_transfer_workspace_size(int32_t n_theta, int32_t n_phi);
 dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_t* gaussians,

@@ -88,7 +88,9 @@ int main(int argc, char** argv) {
                        nullptr) == DGSM_EINVAL);
     EXPECT(sh_transfer(ff, 9, &G, nullptr, &sp, static_cast<float*>(fake), nullptr, nullptr, fake, 16, nullptr) ==
            DGSM_EWORKSPACE);
-    EXPECT(sh_transfer_workspace_size(32, 64) == 32 * 64 * 32 && sh_transfer_workspace_size(0, 64) == 0);
+    EXPECT(sh_transfer(ff, 9, &G, nullptr, &sp, static_cast<float*>(fake), nullptr, nullptr,
+                       static_cast<char*>(fake) + 8, 1 << 20, nullptr) == DGSM_EINVAL);
+    EXPECT(sh_transfer_workspace_size(32, 64) == 32 * 64 * 16 + 256 + 256 + 256 && sh_transfer_workspace_size(0, 64) == 0);
     EXPECT(dgsm_probe_fit_workspace_size(3) == 0);
     EXPECT(dgsm_mlp_workspace_size(33) == 0);
     EXPECT(dgsm_mlp_check_grid_workspace_size(&d, -1) == 0);

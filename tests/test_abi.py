@@ -137,6 +137,22 @@ def test_null_pointers_and_small_workspace_are_rejected(lib):
     assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, 1, 1, ws, None) == 1
     assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, None, 1, 64, None) == 2
     assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, None, None, ws, None) == 2
+    # the probe table is written with 16-byte stores: a misaligned workspace is refused
+    assert lib.sh_transfer(1, 16, ctypes.byref(gs), None, ctypes.byref(prm), 1, None, None, 8, ws, None) == 1
+
+
+def test_sh_workspace_covers_the_padded_grid(lib):
+    """16 bytes per direction of the grid with its columns padded to a
+    multiple of 16, then the cosines and sines of the 16 columns of a group,
+    of the groups' first edges (at least two) and of the rows, each part
+    256-byte aligned."""
+    up = lambda b: (b + 255) // 256 * 256
+    for nt, nph in ((32, 64), (7, 13), (1, 1), (48, 100), (4, 2048)):
+        p16 = (nph + 15) // 16 * 16
+        want = up(nt * p16 * 16) + up(16 * 8) + up(max(2, p16 // 16) * 8) + up(nt * 8)
+        assert lib.sh_transfer_workspace_size(nt, nph) == want
+    assert lib.sh_transfer_workspace_size(0, 64) == 0
+    assert lib.sh_transfer_workspace_size(1 << 12, 1 << 13) == 0
 
 
 @fake_pointers

@@ -384,6 +384,22 @@ def test_cfg3_frame0_full_size_sampled(dtype, tol):
 
 @pytest.mark.parametrize("kp,q", [(16, 1.0), (9, 1.0), (4, 3.5), (1, 1.0), (16, 8.0)])
 def test_sh_transfer_matches_oracle(kp, q):
+    _check_sh_transfer(kp, q, 32, 64)
+
+
+# grids whose columns are padded to 16 (13, 100, 1, 40), whose waves'
+# direction ranges cross rows (48 x 100: 7 groups of 16 per row, 42 groups per
+# wave) or start inside a row (17 x 40), with fewer direction groups than
+# waves (3 x 16, 1 x 1), and with long rows (4 x 2048: 128 groups per row, the
+# column angle of each group carried by 63 rotation steps from the wave's
+# first group)
+@pytest.mark.parametrize("kp,q,n_theta,n_phi", [(9, 1.0, 7, 13), (16, 1.0, 48, 100), (4, 3.5, 3, 16),
+                                                 (1, 1.0, 1, 1), (16, 2.0, 17, 40), (16, 1.0, 4, 2048)])
+def test_sh_transfer_on_other_grids(kp, q, n_theta, n_phi):
+    _check_sh_transfer(kp, q, n_theta, n_phi)
+
+
+def _check_sh_transfer(kp, q, n_theta, n_phi):
     import paper_2601_01660_amd as P
     c = synth.cfg2(n_scene=10, n_avatar=3000)
     av = c["avatar"]
@@ -394,22 +410,24 @@ def test_sh_transfer_matches_oracle(kp, q):
     cen_gpu = P.dgsm_alpha_centroid(gs)
     cen = osh.alpha_centroid(av.mean, av.opacity)
     assert np.abs(cen_gpu.cpu().numpy() - cen).max() <= 1e-6
-    s, fo, rgb = P.sh_transfer(torch.from_numpy(probe), gs, torch.from_numpy(f), cen_gpu, q=q)
+    s, fo, rgb = P.sh_transfer(torch.from_numpy(probe), gs, torch.from_numpy(f), cen_gpu, q=q, n_theta=n_theta,
+                               n_phi=n_phi)
     torch.cuda.synchronize()
-    s_ref, f_ref, rgb_ref = osh.relight(probe, av, f, centroid=cen_gpu.cpu().numpy().astype(np.float64), q=q)
+    s_ref, f_ref, rgb_ref = osh.relight(probe, av, f, centroid=cen_gpu.cpu().numpy().astype(np.float64), q=q,
+                                        n_theta=n_theta, n_phi=n_phi)
     s = s.cpu().numpy()
     # normals that sit on the centroid plane may legitimately flip: accept either side there
     n = osh.normals(av.rot, av.scale, av.mean, cen_gpu.cpu().numpy().astype(np.float64))
     side = np.abs(np.einsum("ni,ni->n", n, av.mean - cen_gpu.cpu().numpy()))
     amb = side < 1e-5
-    s_flip = osh.transfer_scale(probe, -n[amb], q=q) if amb.any() else None
+    s_flip = osh.transfer_scale(probe, -n[amb], n_theta, n_phi, q=q) if amb.any() else None
     # relative 1e-4, with an absolute floor of 5e-6 where s is near zero (a 2048-term
     # FP32 sum of mixed-sign radiance carries ~1e-7 absolute rounding)
     rel = np.abs(s - s_ref) / np.maximum(np.abs(s_ref), 0.05)
     if amb.any():
         rel_f = np.abs(s[amb] - s_flip) / np.maximum(np.abs(s_flip), 0.05)
         rel[amb] = np.minimum(rel[amb], rel_f)
-    print(f"[parity] sh kp={kp} q={q}: max rel = {rel.max():.3e}", flush=True)
+    print(f"[parity] sh kp={kp} q={q} grid {n_theta}x{n_phi}: max rel = {rel.max():.3e}", flush=True)
     assert rel.max() <= 1e-4
     ok = ~amb
     assert np.abs(fo.cpu().numpy()[ok] - f_ref[ok]).max() <= 1e-4 * max(1.0, np.abs(f_ref).max())
