@@ -156,9 +156,24 @@ constexpr int kDefaultSplitUnits = 32768;
 // Enqueue the per-tile accumulation of all lights into atlas [L][K][H][W].
 dgsm_status enqueue_accumulate(const Geom& g, const BuildLayout& L, unsigned char* ws, int n_lights,
                                float pair_eps, void* atlas, const AccumOpts& o, hipStream_t st);
-// T [L][P] (light-major), or [P][L] (point-major) with point_major.
+// T [L][P] (light-major, row stride ld or P), or [P][L] (point-major) with point_major.
 hipError_t launch_query(const Geom& g, const float* lights, int L, const void* atlas, const float* points,
                         int64_t P, float* T, hipStream_t st, bool tiled = false,
-                        const int* out_index = nullptr, bool point_major = false);
+                        const int* out_index = nullptr, bool point_major = false, int64_t ld = 0);
+// Points that never move indexed by the tiles their lookups read (tiled
+// atlas).  With offs == nullptr: counts[l][tile] += entries; else idx[offs[b]
+// + counts[b]++] = point for every (light, tile) bucket b of every point
+// (counts zeroed before each pass).
+hipError_t launch_point_buckets(const Geom& g, const float* lights, int L, const float* points, int64_t P,
+                                int* counts, const int* offs, int* idx, hipStream_t st);
+// For every tile with a nonzero count in hits (light l's int array at hits0 +
+// l * hits_stride bytes): the lookups of its bucket's points in the tiled
+// atlas into T[l][out_col[p]] (row stride ld), each point once.  chunks:
+// {bucket, first entry} of every 256-entry piece of every bucket.
+hipError_t launch_patch(const Geom& g, const float* lights, int L, const void* atlas, const float* points,
+                        const unsigned char* hits0, size_t hits_stride, const int* offs, const int2* chunks,
+                        int64_t nchunks, const int* idx, const int* out_col, float* T, int64_t ld, hipStream_t st);
+// dst[r][i] = src[r][i] for r < rows, i < n (dst row stride ld)
+hipError_t launch_copy_rows(const float* src, int64_t n, int rows, float* dst, int64_t ld, hipStream_t st);
 
 }  // namespace dgsm

@@ -26,6 +26,7 @@
 #include "dgsm_device.hpp"
 #include "dgsm_host.hpp"
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <new>
@@ -267,6 +268,11 @@ struct dgsm_plan_s {
     int* in_pos;          // [ns + nd] plan position of each caller column
     float* tq;            // [ns + nd][L] one frame's query results in plan order (point-major)
     float* tau_static;    // [L][K][H][W] (cache mode)
+    float* ts;            // [L][ns] cache mode: T of the static points in the static-only atlas (caller order)
+    int* boffs;           // [L ntiles + 1] cache mode: static points per (light, tile) bucket, offsets
+    int* bidx;            // cache mode: static points (plan order) of each bucket
+    int2* bchunk;         // cache mode: {bucket, first entry} of every 256-entry piece of a bucket
+    int64_t nchunks;
     void* atlas;          // [L][K][plane] of desc.dtype (tile-major planes)
     void* atlas_static;   // cache mode: T of the static set alone (the per-frame baseline)
     unsigned char* ws_a;  // workspace for the static (cache) or full (no cache) set
@@ -302,7 +308,7 @@ void plan_free(dgsm_plan p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     void* bufs[] = {p->lights,     p->mean,  p->scale,        p->rot,  p->opacity, p->out_index,
                     p->tau_static, p->atlas, p->atlas_static, p->ws_a, p->ws_b,    p->in_pos,
-                    p->tq,         p->group};
+                    p->tq,         p->group, p->ts,           p->boffs, p->bidx,    p->bchunk};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     for (int c = 1; c < kMaxChains; ++c) {
@@ -341,7 +347,13 @@ dgsm_status enqueue_static(dgsm_plan p, int tile_waves, int split_units, hipStre
         for (int c = 0; c < p->chains; ++c) a.a[c] = static_cast<float*>(p->catlas[c]);
         static_finish_kernel<float><<<grid, kWave, 0, st>>>(p->g, p->tau_static, a, static_cast<float*>(p->atlas_static));
     }
-    return hipGetLastError() == hipSuccess ? DGSM_OK : DGSM_EHIP;
+    if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    // T of the static points (they never move) in the static-only atlas, in
+    // the caller's columns: every frame starts from these
+    return launch_query(p->g, p->lights, p->L, p->atlas_static, p->mean, p->ns, p->ts, st, true, p->out_index,
+                        false) == hipSuccess
+               ? DGSM_OK
+               : DGSM_EHIP;
 }
 
 // One frame on chain c (its stream st): dynamic means, build (on top of the
@@ -408,15 +420,30 @@ dgsm_status enqueue_frame(dgsm_plan p, int f, int c, const dgsm_gaussians_t* dyn
     }
     if (s != DGSM_OK) return s;
     mark(2);
-    // Query in plan (spatial) order with coalesced point-major writes, then one
-    // gather into the caller's order: writing straight to the caller's columns
-    // scatters 4-byte stores over the whole output.
-    if (launch_query(p->g, p->lights, p->L, atlas, mean, p->np, p->ctq[c], st, true, nullptr, true) != hipSuccess)
-        return DGSM_EHIP;
-    if (p->np > 0) {
-        unstage_kernel<<<(unsigned)((p->np + 255) / 256), 256, 0, st>>>(p->ctq[c], p->in_pos, p->np, p->L,
-                                                                        T_out + (size_t)f * p->L * p->np);
-        if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+    float* Tf = T_out + (size_t)f * p->L * p->np;
+    if (p->cache) {
+        // A tile the dynamic set did not reach holds the static baseline, so a
+        // static point whose footprint lies in such tiles has its once-per-run
+        // static value: the frame starts from those and looks up again only
+        // the static points listed under reached tiles, then the dynamic
+        // points (whose plan order is the caller's).
+        const BuildLayout& Lb = p->lay_b;
+        if (launch_copy_rows(p->ts, p->ns, p->L, Tf, p->np, st) != hipSuccess ||
+            launch_patch(p->g, p->lights, p->L, atlas, mean, ws_b + Lb.light0 + Lb.hits, Lb.light_stride, p->boffs,
+                         p->bchunk, p->nchunks, p->bidx, p->out_index, Tf, p->np, st) != hipSuccess ||
+            launch_query(p->g, p->lights, p->L, atlas, mean + 3 * p->ns, p->nd, Tf + p->ns, st, true, nullptr,
+                         false, p->np) != hipSuccess)
+            return DGSM_EHIP;
+    } else {
+        // Query in plan (spatial) order with coalesced point-major writes, then
+        // one gather into the caller's order: writing straight to the caller's
+        // columns scatters 4-byte stores over the whole output.
+        if (launch_query(p->g, p->lights, p->L, atlas, mean, p->np, p->ctq[c], st, true, nullptr, true) != hipSuccess)
+            return DGSM_EHIP;
+        if (p->np > 0) {
+            unstage_kernel<<<(unsigned)((p->np + 255) / 256), 256, 0, st>>>(p->ctq[c], p->in_pos, p->np, p->L, Tf);
+            if (hipGetLastError() != hipSuccess) return DGSM_EHIP;
+        }
     }
     mark(3);
     if (p->cache) {
@@ -622,6 +649,42 @@ dgsm_status sort_static(dgsm_plan p, const dgsm_gaussians_t& src) {
     return ok ? DGSM_OK : DGSM_EHIP;
 }
 
+// Static points per (light, tile) bucket of the tiles their lookups read
+// (once, at plan creation: the points and lights never change).
+dgsm_status bucket_static(dgsm_plan p) {
+    const size_t nb = (size_t)p->L * p->g.ntiles;
+    int* counts = nullptr;
+    if (dalloc(&p->boffs, 4 * (nb + 1)) != hipSuccess || dalloc(&counts, 4 * nb) != hipSuccess) {
+        if (counts) (void)hipFree(counts);
+        return DGSM_EHIP;
+    }
+    std::vector<int> h(nb + 1, 0);
+    bool ok = hipMemset(counts, 0, 4 * nb) == hipSuccess &&
+              launch_point_buckets(p->g, p->lights, p->L, p->mean, p->ns, counts, nullptr, nullptr, nullptr) ==
+                  hipSuccess &&
+              hipMemcpy(h.data() + 1, counts, 4 * nb, hipMemcpyDeviceToHost) == hipSuccess;
+    int64_t total = 0;
+    for (size_t b = 0; ok && b < nb; ++b) {
+        total += h[b + 1];
+        h[b + 1] = (int)total;
+    }
+    std::vector<int2> chunks;
+    for (size_t b = 0; ok && b < nb; ++b)
+        for (int q = h[b]; q < h[b + 1]; q += 256) chunks.push_back(make_int2((int)b, q));
+    p->nchunks = (int64_t)chunks.size();
+    ok = ok && total < INT32_MAX && hipMemcpy(p->boffs, h.data(), 4 * (nb + 1), hipMemcpyHostToDevice) == hipSuccess &&
+         dalloc(&p->bchunk, sizeof(int2) * std::max<size_t>(chunks.size(), 1)) == hipSuccess &&
+         (chunks.empty() ||
+          hipMemcpy(p->bchunk, chunks.data(), sizeof(int2) * chunks.size(), hipMemcpyHostToDevice) == hipSuccess) &&
+         dalloc(&p->bidx, 4 * (size_t)std::max<int64_t>(total, 1)) == hipSuccess &&
+         hipMemset(counts, 0, 4 * nb) == hipSuccess &&
+         launch_point_buckets(p->g, p->lights, p->L, p->mean, p->ns, counts, p->boffs, p->bidx, nullptr) ==
+             hipSuccess &&
+         hipDeviceSynchronize() == hipSuccess;
+    (void)hipFree(counts);
+    return ok ? DGSM_OK : DGSM_EHIP;
+}
+
 // List entries the static set (in plan order) needs per light, the maximum
 // over lights; a binning on a temporary minimal workspace; synchronous.
 dgsm_status count_static_entries(dgsm_plan p, int64_t& entries) {
@@ -699,6 +762,7 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
               dalloc(&p->atlas, table * elem) == hipSuccess &&
               (!p->cache || (dalloc(&p->tau_static, table * 4) == hipSuccess &&
                              dalloc(&p->atlas_static, table * elem) == hipSuccess &&
+                             dalloc(&p->ts, 4 * (size_t)std::max<int64_t>(p->ns, 1) * p->L) == hipSuccess &&
                              dalloc(&p->ws_b, p->ws_b_bytes) == hipSuccess));
     if (ok && groups > 1) {
         ok = dalloc(&p->group, 2 * (size_t)p->nd) == hipSuccess;
@@ -714,9 +778,9 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     p->ctq[0] = p->tq;
     p->catlas[0] = p->atlas;
     p->cws[0] = p->ws_b;
+    // chains beyond the first exist in cache mode only, whose query needs no staging
     for (int c = 1; c < p->chains && ok; ++c)
         ok = dalloc(&p->cmean[c], 12 * (size_t)np) == hipSuccess &&
-             dalloc(&p->ctq[c], 4 * (size_t)np * p->L) == hipSuccess &&
              dalloc(&p->catlas[c], table * elem) == hipSuccess && dalloc(&p->cws[c], p->ws_b_bytes) == hipSuccess &&
              hipStreamCreateWithFlags(&p->cstream[c], hipStreamNonBlocking) == hipSuccess &&
              hipEventCreateWithFlags(&p->ev_join[c], hipEventDisableTiming) == hipSuccess;
@@ -725,6 +789,7 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     ok = ok && hipMemcpy(p->lights, lights->pos, 12 * (size_t)p->L, hipMemcpyDeviceToDevice) == hipSuccess;
     ok = ok && hipDeviceSynchronize() == hipSuccess;
     if (ok && n > 0) ok = sort_static(p, *static_set) == DGSM_OK;
+    if (ok && p->cache) ok = bucket_static(p) == DGSM_OK;
     // The static set never changes, so its list entries are counted once here
     // and its workspace holds exactly them (the worst case, every Gaussian in
     // every supertile list, is far larger).  Without the cache the lists hold

@@ -254,3 +254,33 @@ def test_autotune_cache_serves_a_second_plan_of_the_same_workload(scene):
     print(f"[batched] tuned knobs {knobs} served from the cache to a second plan", flush=True)
     for p in (a, b, c):
         p.close()
+
+
+def test_cached_plan_reuses_static_results_only_outside_the_dynamic_footprint(scene):
+    """In cache mode a frame's query takes the once-per-run static result for
+    a static point whose footprint tiles the dynamic set did not reach.  The
+    scene has both kinds of static points in every frame (some shadowed by
+    the dynamic set, most not); the plan matches plain per-frame builds on
+    each kind, at the FP32 tolerance of the plain comparison."""
+    import paper_2601_01660_amd as P
+    atlas = P.Atlas(64, 64, 24, dtype="f32")
+    lights = torch.from_numpy(scene["lights"]).cuda()
+    ref = _plain_frames(P, scene, atlas)
+    gs_static = P.GaussianSet.from_host(scene["static"])
+    T0 = P.dgsm_build(lights, gs_static, atlas)
+    alone = P.dgsm_query(lights, atlas, T0, gs_static.mean).cpu().numpy()
+    ns = scene["static"].n
+    plan = P.Plan(lights, atlas, gs_static, scene["dyn"].n, scene["traj"].shape[0], static_cache=True,
+                  autotune=False, tile_waves=4, chains=2)
+    out = plan.run(P.GaussianSet.from_host(scene["dyn"]), torch.from_numpy(scene["traj"]).cuda(), use_graph=False)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    plan.close()
+    for f in range(ref.shape[0]):
+        shadowed = np.abs(ref[f][:, :ns] - alone) > 1e-3
+        assert shadowed.any() and (~shadowed).sum() > shadowed.sum()
+        err_in = np.abs(out[f][:, :ns][shadowed] - ref[f][:, :ns][shadowed]).max()
+        err_out = np.abs(out[f][:, :ns][~shadowed] - ref[f][:, :ns][~shadowed]).max()
+        print(f"[batched] frame {f}: {int(shadowed.sum())} shadowed static (point, light) pairs, "
+              f"max|dT| {err_in:.2e} there, {err_out:.2e} elsewhere", flush=True)
+        assert err_in <= 2e-6 and err_out <= 2e-6
