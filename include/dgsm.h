@@ -432,7 +432,13 @@ dgsm_status sh_transfer(const float* probe_sh, int32_t Kp, const dgsm_gaussians_
  * Memory: the static set's supertile lists are counted once at creation (a
  * binning of the static set, synchronous) and its workspace holds exactly
  * those entries; the dynamic set's workspaces hold its worst case (n_dynamic
- * times the supertile count per light), since it moves.
+ * times the supertile count per light), since it moves.  In cache mode the
+ * static points are also indexed at creation by the atlas tiles their
+ * lookups read (per light and tile; about 1.3 four-byte entries per point
+ * and light), and each run queries them once in the static-only atlas: a
+ * frame then looks up again only the static points under tiles the dynamic
+ * set reaches and copies the others' run-wide values (the tiles it does not
+ * reach hold the static-only atlas, so those values are the lookups' own).
  *
  * dgsm_plan_create allocates all device memory the plan needs (the only
  * allocating entry points are create and destroy) and synchronises the device;
