@@ -1,5 +1,8 @@
 // DGSM sampling on gfx950 (Sec. 3.3): trilinear lookup of the octahedral x
-// radial atlas at world points, one thread per (point, light).
+// radial atlas at world points, one thread per (point, light); footprint
+// sampling; and, for the batched plan, points that never move indexed by the
+// atlas tiles their lookups read, so that a frame looks up again only the
+// points under the tiles it changed.
 
 #include <climits>
 

@@ -186,8 +186,8 @@ __global__ __launch_bounds__(kShThreads) void sh_transfer_kernel(ShArgs a) {
         const ShConst16 btv = (ShConst16)(const void*)a.bt;   // four directions per entry
         const ShConst2 cgv = (ShConst2)(const void*)a.cg;
         const ShConst2 rtv = (ShConst2)(const void*)a.rt;
-        // (cos, sin) of the 16 columns of a group relative to its first edge,
-        // held in scalar registers for the whole sweep
+        // (cos, sin) of the 16 columns of a group relative to its first edge:
+        // the same 32 values for every group of the sweep
         const shv16 c0s = csv[0], c1s = csv[1];
         float c0[16], c1[16];
 #pragma unroll
