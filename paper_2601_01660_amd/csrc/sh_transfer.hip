@@ -128,11 +128,13 @@ __global__ __launch_bounds__(256) void probe_table_kernel(const float* __restric
 // operand, lane j + 4b of block b), so the accumulator of lane l collects its
 // own Gaussian's four sums in its four registers.  The other 16 - kShMfma
 // directions are summed with four vector multiply-adds each, from table
-// entries read with scalar loads one group ahead.  Measured on the 150k
-// avatar, one such product costs the wave about as much issue time as the
-// four multiply-adds it replaces (the two do not overlap on a SIMD); 12 of 16
-// on the matrix cores ran fastest (0.069 ms per call; 16: 0.074, 8: 0.073,
-// 4: 0.073, all on the vector units as before: 0.104).
+// entries read with scalar loads one group ahead.  One such product keeps the
+// matrix pipe busy for 32 cycles (the FP32 4x4 shape runs at a quarter of the
+// matrix cores' FP32 rate), about as long as the four multiply-adds it
+// replaces take on the vector unit, and the two pipes overlap only in part
+// (counters on the 150k avatar: matrix pipe busy 73% and vector unit 67% of
+// the kernel); 12 of 16 on the matrix cores ran fastest (0.069 ms per call;
+// 16: 0.074, 8: 0.073, 4: 0.073, all on the vector units as before: 0.104).
 typedef float shv4 __attribute__((ext_vector_type(4)));
 typedef float shv16 __attribute__((ext_vector_type(16)));
 typedef const __attribute__((address_space(4))) shv16* ShConst16;
