@@ -247,6 +247,19 @@ def test_binding_rejects_buffers_of_the_wrong_shape(cfg1):
     torch.cuda.synchronize()
     assert out.shape == (3, L, g.n)
     plan.close()
+    # no dynamic Gaussians: every frame is the static set's own query (the
+    # frame query copies the once-per-run static results, no tile reached)
+    ref = P.dgsm_query(lt, atlas, T, gs.mean).cpu()
+    for f in range(3):
+        assert (out[f].cpu() - ref).abs().max().item() <= 2e-6
+    # no static Gaussians: every frame is the dynamic set's own build and query
+    plan = P.Plan(lt, atlas, empty, g.n, 2, static_cache=True, autotune=False)
+    out = plan.run(gs, torch.zeros((2, 3), device="cuda"), use_graph=False)
+    torch.cuda.synchronize()
+    assert out.shape == (2, L, g.n)
+    for f in range(2):
+        assert (out[f].cpu() - ref).abs().max().item() <= 2e-6
+    plan.close()
 
 
 def test_monotone_bounded_and_deterministic(cfg1):
