@@ -265,8 +265,8 @@ struct dgsm_plan_s {
     float* rot;           // [ns + nd][4]
     float* opacity;       // [ns + nd]
     int* out_index;       // [ns + nd] caller column of each plan point (static part in spatial order)
-    int* in_pos;          // [ns + nd] plan position of each caller column
-    float* tq;            // [ns + nd][L] one frame's query results in plan order (point-major)
+    int* in_pos;          // [ns + nd] plan position of each caller column (without the cache)
+    float* tq;            // [ns + nd][L] one frame's query results in plan order (point-major; without the cache)
     float* tau_static;    // [L][K][H][W] (cache mode)
     float* ts;            // [L][ns] cache mode: T of the static points in the static-only atlas (caller order)
     int* boffs;           // [L ntiles + 1] cache mode: static points per (light, tile) bucket, offsets
@@ -757,8 +757,9 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
     bool ok = dalloc(&p->lights, 12 * (size_t)p->L) == hipSuccess && dalloc(&p->mean, 12 * (size_t)np) == hipSuccess &&
               dalloc(&p->scale, 12 * (size_t)np) == hipSuccess && dalloc(&p->rot, 16 * (size_t)np) == hipSuccess &&
               dalloc(&p->opacity, 4 * (size_t)np) == hipSuccess && dalloc(&p->out_index, 4 * (size_t)np) == hipSuccess &&
-              dalloc(&p->in_pos, 4 * (size_t)np) == hipSuccess &&
-              dalloc(&p->tq, 4 * (size_t)np * p->L) == hipSuccess &&
+              // the query staging and its gather index serve the uncached frame query only
+              (p->cache || (dalloc(&p->in_pos, 4 * (size_t)np) == hipSuccess &&
+                            dalloc(&p->tq, 4 * (size_t)np * p->L) == hipSuccess)) &&
               dalloc(&p->atlas, table * elem) == hipSuccess &&
               (!p->cache || (dalloc(&p->tau_static, table * 4) == hipSuccess &&
                              dalloc(&p->atlas_static, table * elem) == hipSuccess &&
@@ -816,7 +817,7 @@ extern "C" dgsm_status dgsm_plan_create(const dgsm_lights_t* lights, const dgsm_
         iota_kernel<<<(unsigned)((p->nd + 255) / 256), 256>>>(p->out_index, p->ns, p->np);
         ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
     }
-    if (ok && np > 0) {
+    if (ok && np > 0 && !p->cache) {
         invert_kernel<<<(unsigned)((np + 255) / 256), 256>>>(p->out_index, np, p->in_pos);
         ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
     }
